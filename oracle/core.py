@@ -1,0 +1,280 @@
+"""Python side of the oracle -- TEST INFRASTRUCTURE ONLY.
+
+ctypes wrapper around ``liboracle.so`` (oracle.c) plus the plain numpy
+bookkeeping of the subdivision loop: building a box CSF from a set of grid
+indices, the exclusion test and the bisection.  Only tests, the smoke check
+and the benchmark's CPU-baseline leg use this module.
+
+Paper: G. Moroz, arXiv 2406.09857.
+  * CSF of a set of grid indices: Sec. 2.1 (labelled tree; the children of a
+    depth-l node are the projections pi_t(E)); Remark 1 (N_i = number of
+    depth-i nodes).
+  * Algorithm 2 (EvaluationCSF) and Theorem 1: ``eval_csf``.
+  * Algorithm 3 (subdivision) restricted to the exclusion criterion C0 and a
+    fixed depth: ``subdivide``.  C0(F, B) is "0 not in []F(B)" (Sec. 3.2); a
+    system is excluded when any of its polynomials excludes 0.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SRC_PATH = os.path.join(HERE, "oracle.c")
+
+OUTWARD = 0
+NEAREST = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with a strict floating-point model (clang)."""
+    if not force and os.path.exists(LIB_PATH) and os.path.getmtime(LIB_PATH) >= os.path.getmtime(SRC_PATH):
+        return LIB_PATH
+    clang = "/opt/rocm/llvm/bin/clang"
+    if not os.path.exists(clang):
+        clang = "clang"
+    cmd = [clang, "-O2", "-ffp-model=strict", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-o", LIB_PATH + ".tmp", SRC_PATH, "-lm", "-Wl,-rpath,/opt/rocm/llvm/lib"]
+    subprocess.check_call(cmd)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        i64p = C.POINTER(C.c_int64)
+        L.orc_iv_add.argtypes = [dp, dp, C.c_int, dp]
+        L.orc_iv_mul.argtypes = [dp, dp, C.c_int, dp]
+        L.orc_box.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int64, dp]
+        L.orc_box_table.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int64, dp]
+        L.orc_eval_box.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, C.c_int, dp, i64p]
+        L.orc_eval_box.restype = C.c_int
+        L.orc_eval_csf.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, i64p,
+                                   C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.POINTER(C.c_int32)),
+                                   C.POINTER(dp), i64p, C.c_int, C.c_int, dp, dp, i64p]
+        L.orc_eval_csf.restype = C.c_int
+        L.orc_eval_points.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int64, dp]
+        L.orc_eval_points.restype = C.c_int
+        L.orc_max_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+# ---------------------------------------------------------------------------
+# Primitive operations
+# ---------------------------------------------------------------------------
+
+def iv_add(x, y, mode=OUTWARD):
+    a = np.array(x, np.float64); b = np.array(y, np.float64); r = np.zeros(2)
+    lib().orc_iv_add(_dp(a), _dp(b), mode, _dp(r))
+    return float(r[0]), float(r[1])
+
+
+def iv_mul(x, y, mode=OUTWARD):
+    a = np.array(x, np.float64); b = np.array(y, np.float64); r = np.zeros(2)
+    lib().orc_iv_mul(_dp(a), _dp(b), mode, _dp(r))
+    return float(r[0]), float(r[1])
+
+
+def box(dlo: float, dhi: float, level: int, label: int):
+    r = np.zeros(2)
+    lib().orc_box(dlo, dhi, level, label, _dp(r))
+    return float(r[0]), float(r[1])
+
+
+def box_table(dlo: float, dhi: float, level: int, n: int | None = None) -> np.ndarray:
+    """(n, 2) enclosures of the cells 0..n-1 of the 2^level grid on [dlo, dhi]."""
+    n = (1 << level) if n is None else n
+    out = np.zeros((n, 2))
+    lib().orc_box_table(dlo, dhi, level, n, _dp(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Evaluation
+# ---------------------------------------------------------------------------
+
+def _coef(poly):
+    """(clo, chi, k, cube) from a cube or a (lo_cube, hi_cube) pair."""
+    if isinstance(poly, tuple):
+        lo = np.ascontiguousarray(poly[0], np.float64); hi = np.ascontiguousarray(poly[1], np.float64)
+    else:
+        lo = np.ascontiguousarray(poly, np.float64); hi = lo
+    return lo, hi, lo.ndim, lo.shape[0]
+
+
+def eval_box(poly, d: int, boxiv: np.ndarray, mode=OUTWARD):
+    """Brute-force nested Horner on one box ((k,2) array). Returns (lo, hi, steps)."""
+    lo, hi, k, cube = _coef(poly)
+    b = np.ascontiguousarray(boxiv, np.float64).reshape(-1)
+    r = np.zeros(2); st = C.c_int64(0)
+    rc = lib().orc_eval_box(k, d, cube, _dp(lo), _dp(hi), _dp(b), mode, _dp(r), C.byref(st))
+    if rc:
+        raise ValueError("orc_eval_box failed")
+    return float(r[0]), float(r[1]), int(st.value)
+
+
+def eval_points(poly: np.ndarray, d: int, x: np.ndarray) -> np.ndarray:
+    """Round-to-nearest point values by the same nested Horner order."""
+    c = np.ascontiguousarray(poly, np.float64)
+    k = c.ndim
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, k)
+    f = np.zeros(x.shape[0])
+    if lib().orc_eval_points(k, d, c.shape[0], _dp(c), _dp(x), x.shape[0], _dp(f)):
+        raise ValueError("orc_eval_points failed")
+    return f
+
+
+def eval_csf(poly, d: int, csf: dict, tables: list, mode=OUTWARD, nthreads: int = 1):
+    """Algorithm 2 on a box CSF.
+
+    ``tables[l]`` is an (m_l, 2) array: the interval of each label on axis l.
+    Returns (lo, hi, steps) with lo/hi in CSF leaf order and steps[l] the
+    number of interval Horner steps spent at CSF depth l+1.
+    """
+    lo, hi, k, cube = _coef(poly)
+    assert csf["k"] == k
+    n = np.array([len(a) for a in csf["idx"]], np.int64)
+    idx = [np.ascontiguousarray(a, np.int32) for a in csf["idx"]]
+    ptr = [np.ascontiguousarray(a, np.int32) for a in csf["ptr"]] + [np.zeros(1, np.int32)] * (k - len(csf["ptr"]))
+    tabs = [np.ascontiguousarray(t, np.float64) for t in tables]
+    xn = np.array([t.shape[0] for t in tabs], np.int64)
+    I32P = C.POINTER(C.c_int32)
+    idx_arr = (I32P * k)(*[a.ctypes.data_as(I32P) for a in idx])
+    ptr_arr = (I32P * k)(*[a.ctypes.data_as(I32P) for a in ptr])
+    tab_arr = (C.POINTER(C.c_double) * k)(*[_dp(t) for t in tabs])
+    nl = int(n[-1])
+    olo = np.zeros(nl); ohi = np.zeros(nl); steps = np.zeros(k, np.int64)
+    i64p = C.POINTER(C.c_int64)
+    rc = lib().orc_eval_csf(k, d, cube, _dp(lo), _dp(hi), n.ctypes.data_as(i64p), idx_arr, ptr_arr,
+                            tab_arr, xn.ctypes.data_as(i64p), mode, nthreads, _dp(olo), _dp(ohi),
+                            steps.ctypes.data_as(i64p))
+    if rc:
+        raise ValueError("orc_eval_csf failed (bad arguments or labels outside the tables)")
+    return olo, ohi, steps
+
+
+# ---------------------------------------------------------------------------
+# CSF of a set of grid indices (Sec. 2.1)
+# ---------------------------------------------------------------------------
+
+def csf_from_boxes(boxes: np.ndarray, level: int = 0) -> dict:
+    """Canonical CSF of a set of index tuples (duplicates allowed, any order).
+
+    Depth-l nodes are the distinct prefixes of length l+1, in lexicographic
+    order; idx[l] holds their last coordinate and ptr[l][j] the position of
+    the first child of node j among the depth-(l+1) nodes (ptr[l][-1] = N_{l+2}).
+    """
+    b = np.asarray(boxes, dtype=np.int64)
+    k = b.shape[1]
+    if b.shape[0]:
+        b = np.unique(b, axis=0)  # lexicographic order of whole tuples
+    idx, starts = [], []
+    for l in range(k):
+        if b.shape[0] == 0:
+            flag = np.zeros(0, bool)
+        else:
+            flag = np.ones(b.shape[0], bool)
+            flag[1:] = np.any(b[1:, : l + 1] != b[:-1, : l + 1], axis=1)
+        st = np.flatnonzero(flag)
+        starts.append(st)
+        idx.append(b[st, l].astype(np.int32))
+    ptr = []
+    for l in range(k - 1):
+        p = np.searchsorted(starts[l + 1], starts[l]).astype(np.int64)
+        ptr.append(np.concatenate([p, [len(starts[l + 1])]]).astype(np.int32))
+    return {"k": k, "level": level, "idx": idx, "ptr": ptr, "boxes": b.astype(np.int32)}
+
+
+def csf_sizes(csf: dict) -> list:
+    """N_1(S), ..., N_k(S) (Remark 1: number of nodes at each depth)."""
+    return [len(a) for a in csf["idx"]]
+
+
+def children_of(boxes: np.ndarray) -> np.ndarray:
+    """All 2^k children 2*B + b of each box (bisection G_n -> G_2n, Sec. 3.2)."""
+    b = np.asarray(boxes, np.int64)
+    k = b.shape[1]
+    bits = np.array(np.meshgrid(*([[0, 1]] * k), indexing="ij")).reshape(k, -1).T
+    return (2 * b[:, None, :] + bits[None, :, :]).reshape(-1, k)
+
+
+def level_tables(dom: np.ndarray, k: int, level: int) -> list:
+    dom = np.asarray(dom, np.float64).reshape(k, 2)
+    return [box_table(float(dom[j, 0]), float(dom[j, 1]), level) for j in range(k)]
+
+
+def keep_mask(lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """C0 over a system: keep a box unless some polynomial's enclosure excludes 0.
+
+    lo/hi are (npolys, n).  A NaN endpoint never excludes (the comparison is
+    false), so undefined enclosures keep their box.
+    """
+    excl = np.any((lo > 0) | (hi < 0), axis=0)
+    return ~excl
+
+
+def poly_degree(poly) -> int:
+    c = poly[0] if isinstance(poly, tuple) else poly
+    return c.shape[0] - 1
+
+
+def eval_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1, mode=OUTWARD, degrees=None):
+    """Enclosures of every polynomial on every leaf of the level's CSF."""
+    k = csf["k"]
+    tabs = level_tables(dom, k, csf["level"])
+    los, his, steps = [], [], []
+    for j, p in enumerate(polys):
+        d = poly_degree(p) if degrees is None else degrees[j]
+        lo, hi, st = eval_csf(p, d, csf, tabs, mode, nthreads)
+        los.append(lo); his.append(hi); steps.append(st)
+    return np.array(los).reshape(len(polys), -1), np.array(his).reshape(len(polys), -1), np.array(steps)
+
+
+def subdivide(polys, k: int, depth: int, dom=None, nthreads: int = 1, start_level: int = 0,
+              start_boxes=None, degrees=None):
+    """Algorithm 3 with C0 only, stopped after `depth` (levels start_level..depth).
+
+    Returns one record per level: the CSF S_l, the enclosures, the keep mask,
+    the kept boxes K_l and the step counts.  S_{l+1} is the set of children of
+    K_l.
+    """
+    dom = np.array([-1.0, 1.0] * k) if dom is None else np.asarray(dom, np.float64)
+    boxes = np.zeros((1, k), np.int64) if start_boxes is None else np.asarray(start_boxes)
+    out = []
+    for level in range(start_level, depth + 1):
+        S = csf_from_boxes(boxes, level)
+        lo, hi, steps = eval_level(polys, S, dom, nthreads, degrees=degrees)
+        keep = keep_mask(lo, hi)
+        K = S["boxes"][keep]
+        out.append({"level": level, "S": S, "lo": lo, "hi": hi, "keep": keep, "kept": K, "steps": steps})
+        if level < depth:
+            boxes = children_of(K)
+    return out
+
+
+def theorem1_steps(k: int, d: int, sizes: list) -> list:
+    """Steps at each CSF depth: (Nt_{k-l} - Nt_{k-l-1}) * N_{l+1}(S) for a dense
+    total-degree simplex, where Nt_m = C(d+m, m) counts the trailing m-tuples."""
+    nt = [math.comb(d + m, m) for m in range(k + 1)]
+    return [(nt[k - l] - nt[k - l - 1]) * sizes[l] for l in range(k)]

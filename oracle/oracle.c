@@ -1,0 +1,353 @@
+/*
+ * oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow CPU reference for the interval-subdivision hot path of
+ * G. Moroz, "Sparse Tensors and Subdivision Methods for Finding the Zero Set
+ * of Polynomial Equations" (arXiv 2406.09857).  Only the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark load this library; the
+ * product library never links, calls or includes anything from here, and this
+ * file includes nothing from the product.
+ *
+ * What is computed (and where the paper defines it):
+ *   - interval addition [a,b]+[c,d] = [a+c, b+d]  (Sec. 3.2, "Exclusion
+ *     Criterion"), with every endpoint rounded outward (lower endpoints toward
+ *     -inf, upper endpoints toward +inf) so that {F(x) : x in B} is contained
+ *     in the result;
+ *   - interval product [a,b]*[c,d] = [min P, max P], P = {ac, ad, bc, bd}, the
+ *     textbook rule (the paper names interval arithmetic but does not spell the
+ *     product out), with the min rounded down and the max rounded up;
+ *   - Horner's rule on an interval (Algorithm 1): J <- a_l; J <- J*I + a_j for
+ *     descending exponents (consecutive exponents, so I^(e_{j+1}-e_j) = I);
+ *   - EvaluationCSF (Algorithm 2): for every x1 node i of the box CSF, the
+ *     partial evaluation F(I_i, x2, ..., xk) and a recursive call on the
+ *     subtree of i; a univariate F is evaluated directly on each child.
+ *   - a per-box brute force that evaluates one box by nested Horner without
+ *     sharing anything between boxes (the left-hand side of Theorem 1's
+ *     comparison), used to pin the amortized routine.
+ *
+ * Rounding is set with fesetround() around each batch of endpoint
+ * computations; the file is compiled with clang -ffp-model=strict so that the
+ * compiler neither folds nor reorders floating-point operations across the
+ * mode changes (FENV_ACCESS ON below).
+ *
+ * Polynomials are dense coefficient cubes of side `cube` in k variables,
+ * c[e1][e2]...[ek] in C order, restricted to the total-degree simplex
+ * e1+...+ek <= d (entries outside are never read).  Coefficients are
+ * intervals [clo, chi]; point coefficients pass the same array twice.
+ */
+#include <fenv.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#pragma STDC FENV_ACCESS ON
+
+#define ORC_KMAX 4
+
+/* Rounding modes of the oracle: OUTWARD is interval arithmetic proper;
+ * NEAREST evaluates every endpoint in round-to-nearest (used to compare
+ * degenerate boxes against an ordinary floating-point Horner evaluation). */
+enum { ORC_OUTWARD = 0, ORC_NEAREST = 1 };
+
+typedef struct { double lo, hi; } ivl;
+
+static void round_down(int mode) { fesetround(mode == ORC_NEAREST ? FE_TONEAREST : FE_DOWNWARD); }
+static void round_up(int mode) { fesetround(mode == ORC_NEAREST ? FE_TONEAREST : FE_UPWARD); }
+static void round_restore(void) { fesetround(FE_TONEAREST); }
+
+static double min4(double a, double b, double c, double d) { return fmin(fmin(a, b), fmin(c, d)); }
+static double max4(double a, double b, double c, double d) { return fmax(fmax(a, b), fmax(c, d)); }
+
+/* ------------------------------------------------------------------ */
+/* Scalar interval operations (one rounding-mode switch per endpoint). */
+/* ------------------------------------------------------------------ */
+
+static ivl iv_add(ivl x, ivl y, int mode) {
+  ivl r;
+  round_down(mode); r.lo = x.lo + y.lo;
+  round_up(mode);   r.hi = x.hi + y.hi;
+  round_restore();
+  return r;
+}
+
+static ivl iv_mul(ivl x, ivl y, int mode) {
+  ivl r;
+  round_down(mode); r.lo = min4(x.lo * y.lo, x.lo * y.hi, x.hi * y.lo, x.hi * y.hi);
+  round_up(mode);   r.hi = max4(x.lo * y.lo, x.lo * y.hi, x.hi * y.lo, x.hi * y.hi);
+  round_restore();
+  return r;
+}
+
+void orc_iv_add(const double* x, const double* y, int mode, double* r) {
+  ivl a = {x[0], x[1]}, b = {y[0], y[1]};
+  ivl s = iv_add(a, b, mode);
+  r[0] = s.lo; r[1] = s.hi;
+}
+
+void orc_iv_mul(const double* x, const double* y, int mode, double* r) {
+  ivl a = {x[0], x[1]}, b = {y[0], y[1]};
+  ivl p = iv_mul(a, b, mode);
+  r[0] = p.lo; r[1] = p.hi;
+}
+
+/* ------------------------------------------------------------------ */
+/* Box intervals of the uniform grid G_n (Sec. 2.1, "Representing a Set */
+/* of Boxes"), on a domain [dlo, dhi] split into n = 2^level cells.      */
+/* Cell i is [dlo + i*w, dlo + (i+1)*w], w = (dhi-dlo)/2^level; its      */
+/* enclosure rounds each endpoint outward.  On dyadic domains such as   */
+/* [-1,1] every endpoint is exact.                                       */
+/* ------------------------------------------------------------------ */
+
+void orc_box(double dlo, double dhi, int level, int64_t label, double* r) {
+  round_down(ORC_OUTWARD);
+  double wd = dhi - dlo;
+  double lo = dlo + ldexp((double)label * wd, -level);
+  round_up(ORC_OUTWARD);
+  double wu = dhi - dlo;
+  double hi = dlo + ldexp((double)(label + 1) * wu, -level);
+  round_restore();
+  r[0] = lo; r[1] = hi;
+}
+
+void orc_box_table(double dlo, double dhi, int level, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; i++) orc_box(dlo, dhi, level, i, out + 2 * i);
+}
+
+/* ------------------------------------------------------------------ */
+/* Tuple bookkeeping for dense cubes restricted to the simplex.         */
+/* ------------------------------------------------------------------ */
+
+static int64_t ipow(int64_t b, int e) { int64_t r = 1; while (e-- > 0) r *= b; return r; }
+
+/* Total degree |t| of every flat index of an m-dimensional cube of side s. */
+static int* degrees_of_cube(int m, int s) {
+  int64_t n = ipow(s, m);
+  int* deg = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  for (int64_t f = 0; f < n; f++) {
+    int64_t q = f; int g = 0;
+    for (int j = 0; j < m; j++) { g += (int)(q % s); q /= s; }
+    deg[f] = g;
+  }
+  return deg;
+}
+
+/* Flat indices of the m-dim cube with |t| <= d, listed by increasing |t|
+ * (ties by flat index), and first[g] = number of tuples with |t| < g. */
+typedef struct { int m, s, d; int64_t n; int64_t* flat; int64_t* first; int* deg; } graded;
+
+static graded graded_make(int m, int s, int d) {
+  graded G; G.m = m; G.s = s; G.d = d;
+  int64_t cube = ipow(s, m);
+  G.deg = degrees_of_cube(m, s);
+  G.first = (int64_t*)calloc((size_t)d + 2, sizeof(int64_t));
+  for (int64_t f = 0; f < cube; f++) if (G.deg[f] <= d) G.first[G.deg[f] + 1]++;
+  for (int g = 0; g <= d; g++) G.first[g + 1] += G.first[g];
+  G.n = G.first[d + 1];
+  G.flat = (int64_t*)malloc(sizeof(int64_t) * (size_t)(G.n > 0 ? G.n : 1));
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)d + 1));
+  for (int g = 0; g <= d; g++) fill[g] = G.first[g];
+  for (int64_t f = 0; f < cube; f++) if (G.deg[f] <= d) G.flat[fill[G.deg[f]]++] = f;
+  free(fill);
+  return G;
+}
+
+static void graded_free(graded* G) { free(G->flat); free(G->first); free(G->deg); }
+
+/* ------------------------------------------------------------------ */
+/* Partial evaluation F(I, x_{s+1}, ..., x_k) of an m-variate interval  */
+/* polynomial C (cube of side S over (e_s, t)) at the interval I: for    */
+/* every trailing tuple t with |t| <= d, Horner in e_s from d-|t| down   */
+/* to 0.  All chains sharing I advance together, one exponent at a time, */
+/* so the rounding mode is switched twice per exponent, not per step.    */
+/* Each chain performs exactly the operations of Algorithm 1.            */
+/* Out: cube of side S over t (m-1 dims), only |t| <= d written.         */
+/* Returns the number of interval steps (one multiply + one add).        */
+/* ------------------------------------------------------------------ */
+
+static int64_t partial_eval(const ivl* C, int m, int S, int d, const graded* T, ivl I, int mode,
+                            ivl* out, double* tmp) {
+  int64_t tcube = ipow(S, m - 1), steps = 0;
+  for (int e = d; e >= 0; e--) {
+    /* chains with |t| < d-e continue, chains with |t| == d-e start at e. */
+    int64_t nact = T->first[d - e];       /* tuples with |t| <= d-e-1 */
+    int64_t nnew_end = T->first[d - e + 1];
+    round_down(mode);
+    for (int64_t j = 0; j < nact; j++) {
+      int64_t f = T->flat[j];
+      ivl J = out[f], c = C[(int64_t)e * tcube + f];
+      tmp[j] = min4(J.lo * I.lo, J.lo * I.hi, J.hi * I.lo, J.hi * I.hi) + c.lo;
+    }
+    round_up(mode);
+    for (int64_t j = 0; j < nact; j++) {
+      int64_t f = T->flat[j];
+      ivl J = out[f], c = C[(int64_t)e * tcube + f];
+      out[f].hi = max4(J.lo * I.lo, J.lo * I.hi, J.hi * I.lo, J.hi * I.hi) + c.hi;
+      out[f].lo = tmp[j];
+    }
+    round_restore();
+    for (int64_t j = nact; j < nnew_end; j++) {
+      int64_t f = T->flat[j];
+      out[f] = C[(int64_t)e * tcube + f];
+    }
+    steps += nact;
+  }
+  return steps;
+}
+
+/* ------------------------------------------------------------------ */
+/* Algorithm 2 (EvaluationCSF), recursive, on a box CSF.                 */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  int k, d, S, mode;
+  const int64_t* n;           /* n[l] nodes at CSF depth l+1 */
+  const int32_t* const* idx;  /* labels per depth */
+  const int32_t* const* ptr;  /* child offsets per depth */
+  const double* const* X;     /* X[l][2*label], X[l][2*label+1]: interval of that label on axis l */
+  const int64_t* xn;          /* table sizes (labels must be < xn[l]) */
+  graded T[ORC_KMAX];         /* T[l]: trailing tuples for stage l (dimension k-l-1) */
+  double* lo; double* hi;     /* leaf outputs, CSF leaf order */
+} csf_job;
+
+typedef struct { ivl* buf[ORC_KMAX]; double* tmp; int64_t steps[ORC_KMAX]; int err; } csf_scratch;
+
+/* Evaluate F (m = k - l variables, cube side S) on the nodes [b, e) of depth l. */
+static void eval_rec(const csf_job* J, csf_scratch* W, const ivl* F, int l, int64_t b, int64_t e) {
+  int m = J->k - l;
+  for (int64_t q = b; q < e; q++) {
+    int32_t lab = J->idx[l][q];
+    if (lab < 0 || (int64_t)lab >= J->xn[l]) { W->err = 1; return; }
+    ivl I = { J->X[l][2 * (int64_t)lab], J->X[l][2 * (int64_t)lab + 1] };
+    ivl* FI = W->buf[l];
+    W->steps[l] += partial_eval(F, m, J->S, J->d, &J->T[l], I, J->mode, FI, W->tmp);
+    if (m == 1) {
+      J->lo[q] = FI[0].lo; J->hi[q] = FI[0].hi;
+    } else {
+      eval_rec(J, W, FI, l + 1, J->ptr[l][q], J->ptr[l][q + 1]);
+      if (W->err) return;
+    }
+  }
+}
+
+/*
+ * Evaluate the polynomial (clo/chi: dense cube, side `cube`, degree d, k vars)
+ * on every leaf of the box CSF (n, idx, ptr) whose axis-l labels index the
+ * interval tables X[l] (2*xn[l] doubles).  Writes lo/hi in CSF leaf order and,
+ * if steps != NULL, steps[l] = number of interval Horner steps spent at depth
+ * l (for Theorem 1).  nthreads > 1 splits the x1 loop over OpenMP threads; the
+ * result does not depend on it (every chain is sequential).
+ * Returns 0, or -1 on bad arguments / out-of-table labels.
+ */
+int orc_eval_csf(int k, int d, int cube, const double* clo, const double* chi,
+                 const int64_t* n, const int32_t* const* idx, const int32_t* const* ptr,
+                 const double* const* X, const int64_t* xn, int mode, int nthreads,
+                 double* lo, double* hi, int64_t* steps) {
+  if (k < 1 || k > ORC_KMAX || d < 0 || cube < d + 1) return -1;
+  csf_job J; memset(&J, 0, sizeof J);
+  J.k = k; J.d = d; J.S = cube; J.mode = mode; J.n = n; J.idx = idx; J.ptr = ptr; J.X = X; J.xn = xn;
+  J.lo = lo; J.hi = hi;
+  for (int l = 0; l < k; l++) J.T[l] = graded_make(k - l - 1, cube, d);
+  int64_t total = ipow(cube, k);
+  ivl* F = (ivl*)malloc(sizeof(ivl) * (size_t)total);
+  for (int64_t f = 0; f < total; f++) { F[f].lo = clo[f]; F[f].hi = chi ? chi[f] : clo[f]; }
+  int64_t st[ORC_KMAX] = {0, 0, 0, 0};
+  int err = 0;
+  if (nthreads < 1) nthreads = 1;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nthreads) reduction(+ : err)
+#endif
+  {
+    csf_scratch W; memset(&W, 0, sizeof W);
+    for (int l = 0; l < k; l++) W.buf[l] = (ivl*)calloc((size_t)ipow(cube, k - l - 1), sizeof(ivl));
+    W.tmp = (double*)malloc(sizeof(double) * (size_t)(J.T[0].n + 1));
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+    for (int64_t q = 0; q < n[0]; q++) {
+      if (!W.err) eval_rec(&J, &W, F, 0, q, q + 1);
+    }
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+    { for (int l = 0; l < k; l++) st[l] += W.steps[l]; }
+    err += W.err;
+    for (int l = 0; l < k; l++) free(W.buf[l]);
+    free(W.tmp);
+  }
+  round_restore();
+  if (steps) for (int l = 0; l < k; l++) steps[l] = st[l];
+  for (int l = 0; l < k; l++) graded_free(&J.T[l]);
+  free(F);
+  return err ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Per-box brute force: nested Horner on one box, nothing shared.        */
+/* value(s, rem, suffix) is the polynomial in x_1..x_s (suffix exponents */
+/* e_{s+1..k} fixed, |e_1..e_s| <= rem) evaluated on I_1..I_s; the      */
+/* outermost call is value(k, d, {}).  Every chain is Algorithm 1.      */
+/* ------------------------------------------------------------------ */
+
+typedef struct { int k, d, S, mode; const double* clo; const double* chi; const ivl* B; int64_t steps; } box_job;
+
+static ivl box_value(box_job* J, int s, int rem, int* e) {
+  /* e[0..k-1]: exponents; entries s..k-1 (0-based) are fixed by the caller. */
+  ivl acc = {0.0, 0.0};
+  for (int es = rem; es >= 0; es--) {
+    e[s - 1] = es;
+    ivl coef;
+    if (s == 1) {
+      int64_t f = 0;
+      for (int j = 0; j < J->k; j++) f = f * J->S + e[j];
+      coef.lo = J->clo[f]; coef.hi = J->chi ? J->chi[f] : J->clo[f];
+    } else {
+      coef = box_value(J, s - 1, rem - es, e);
+    }
+    if (es == rem) {
+      acc = coef;
+    } else {
+      acc = iv_add(iv_mul(acc, J->B[s - 1], J->mode), coef, J->mode);
+      J->steps++;
+    }
+  }
+  return acc;
+}
+
+/* Evaluate one box B (2k doubles: lo_1, hi_1, ..., lo_k, hi_k). */
+int orc_eval_box(int k, int d, int cube, const double* clo, const double* chi, const double* box,
+                 int mode, double* r, int64_t* steps) {
+  if (k < 1 || k > ORC_KMAX || d < 0 || cube < d + 1) return -1;
+  ivl B[ORC_KMAX];
+  for (int j = 0; j < k; j++) { B[j].lo = box[2 * j]; B[j].hi = box[2 * j + 1]; }
+  box_job J = {k, d, cube, mode, clo, chi, B, 0};
+  int e[ORC_KMAX] = {0, 0, 0, 0};
+  ivl v = box_value(&J, k, d, e);
+  r[0] = v.lo; r[1] = v.hi;
+  if (steps) *steps = J.steps;
+  return 0;
+}
+
+/* Point evaluation in round-to-nearest by the same nested Horner order
+ * (degenerate boxes); used by the derivative checks. */
+int orc_eval_points(int k, int d, int cube, const double* c, const double* x, int64_t npts, double* f) {
+  if (k < 1 || k > ORC_KMAX) return -1;
+  for (int64_t p = 0; p < npts; p++) {
+    double box[2 * ORC_KMAX], r[2];
+    for (int j = 0; j < k; j++) { box[2 * j] = x[p * k + j]; box[2 * j + 1] = x[p * k + j]; }
+    if (orc_eval_box(k, d, cube, c, NULL, box, ORC_NEAREST, r, NULL)) return -1;
+    f[p] = r[0];
+  }
+  return 0;
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
