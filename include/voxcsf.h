@@ -1,0 +1,183 @@
+/*
+ * voxcsf.h -- C ABI of libvoxcsf.so: amortized interval subdivision of
+ * polynomial systems on MI355X (gfx950).
+ *
+ * Method: G. Moroz, "Sparse Tensors and Subdivision Methods for Finding the
+ * Zero Set of Polynomial Equations", arXiv 2406.09857.
+ *   - Sec. 2.1: Compressed Sparse Fiber (CSF) trees; a set of grid boxes is
+ *     stored by the indices of its boxes (a tree without leaves values).
+ *   - Algorithm 1: Horner's rule on an interval.
+ *   - Algorithm 2 (EvaluationCSF) and Theorem 1: evaluation of F on every box
+ *     of a CSF by partial evaluation, one variable per tree depth.
+ *   - Sec. 3.2, Algorithm 3: subdivision with the exclusion criterion
+ *     C0(F, B) = "0 is not in the interval evaluation of F on B"; a system is
+ *     excluded on B when any of its polynomials is.
+ *
+ * Conventions shared by every entry point
+ *   - Device pointers are HIP device addresses (e.g. torch CUDA tensors'
+ *     data_ptr()); "host" marks host memory.  All device buffers are owned by
+ *     the caller; the library keeps no device allocation between calls.
+ *   - `stream` is a hipStream_t (NULL = default stream).  Calls enqueue work
+ *     on it and return without waiting unless stated otherwise.
+ *   - Scratch memory is the caller's `ws` (device, 256-byte aligned) of
+ *     `ws_bytes`; vx_workspace_bytes() gives the size a call needs.
+ *   - Return value: VX_OK or a negative VX_E* code; vx_last_error() then
+ *     describes the failure (per host thread).  Argument errors are detected
+ *     before anything is enqueued.
+ *   - Arithmetic: FP64 intervals, every endpoint rounded outward (lower
+ *     endpoints toward -inf, upper toward +inf), no fused multiply-add, so
+ *     {F(x) : x in B} is contained in [lo, hi] for every box B.  Results are
+ *     bit-for-bit reproducible (up to the sign of zero endpoints).
+ *   - The domain is a box [dom[2j], dom[2j+1]] per axis j (host array of 2k
+ *     finite doubles, dom[2j] < dom[2j+1]).  At level L, axis j is cut into
+ *     2^L cells; cell i is enclosed by
+ *       [RD(dlo + RD(i * RD(dhi - dlo)) / 2^L), RU(dlo + RU((i+1) * RU(dhi - dlo)) / 2^L)]
+ *     which is exact on dyadic domains such as [-1, 1].
+ */
+#ifndef VOXCSF_H
+#define VOXCSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VX_KMAX 4
+
+enum {
+  VX_OK = 0,
+  VX_EINVAL = -1,        /* bad argument (null pointer, size, k, degree, domain) */
+  VX_ECAPACITY = -2,     /* a caller buffer or the workspace is too small */
+  VX_EHIP = -3,          /* a HIP runtime call or kernel launch failed */
+  VX_EOVERFLOW = -4,     /* a count or label does not fit in int32 */
+  VX_EUNSUPPORTED = -5   /* valid request this build does not implement */
+};
+
+/* A polynomial in k variables of total degree <= degree, given as a dense
+ * coefficient cube c[e1][e2]...[ek] (C order, side `side` >= degree+1) whose
+ * entries with e1+...+ek > degree are ignored.  Coefficients are intervals
+ * [c_lo, c_hi]; c_hi == NULL means point coefficients (c_hi = c_lo).  The
+ * polynomial CSF of Sec. 2.1 is the simplex support of this cube. */
+typedef struct vx_poly {
+  int32_t k;
+  int32_t degree;
+  int32_t side;
+  int32_t reserved;
+  const double* c_lo;    /* device, side^k doubles */
+  const double* c_hi;    /* device, side^k doubles, or NULL */
+} vx_poly;
+
+/* A set of boxes of the 2^level grid as a CSF tree (Sec. 2.1).  Depth l+1
+ * (l = 0..k-1) holds n[l] nodes; idx[l][q] is the grid index, on axis l, of
+ * node q; the children of node q of depth l+1 are the nodes
+ * ptr[l][q] .. ptr[l][q+1]-1 of depth l+2 (l < k-1), with strictly ascending
+ * labels.  Nodes of one depth are in lexicographic order of their paths, so
+ * the depth-k nodes (the boxes, "leaves") are the boxes in lexicographic order.
+ * n[l] = N_{l+1}(S) of Definition 1 / Remark 1. */
+typedef struct vx_csf {
+  int32_t k;
+  int32_t level;
+  int64_t n[VX_KMAX];    /* host: node counts per depth */
+  int64_t cap[VX_KMAX];  /* host: capacity (entries) of idx[l]; ptr[l] holds cap[l]+1 */
+  int32_t* idx[VX_KMAX]; /* device labels */
+  int32_t* ptr[VX_KMAX]; /* device child offsets, l < k-1 */
+} vx_csf;
+
+/* Message describing the last failure on this host thread ("" if none). */
+const char* vx_last_error(void);
+
+/* Workspace sizes.  `which` selects the call; arguments not used by that call
+ * may be NULL/0.  Returns 0 on invalid arguments. */
+enum { VX_WS_EVAL = 0, VX_WS_FILTER = 1, VX_WS_BUILD = 2, VX_WS_GRAD = 3 };
+size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_csf* S, int64_t n);
+
+/*
+ * csf_build -- CSF of an arbitrary list of boxes (Sec. 2.1).
+ *   boxes : device int32, n x k row-major grid indices in [0, 2^level), any
+ *           order, duplicates allowed (they are merged).
+ *   out   : caller CSF with k, level set and idx/ptr of capacity >= n at every
+ *           depth; on return out->n[] holds the node counts (this call waits
+ *           for the stream to read them back).
+ * Errors: VX_EINVAL (k, level, negative n, labels outside the grid are
+ * reported as VX_EINVAL after the build), VX_ECAPACITY (out->cap < n, ws).
+ */
+int csf_build(int32_t k, int32_t level, const int32_t* boxes, int64_t n, vx_csf* out, void* ws, size_t ws_bytes,
+              void* stream);
+
+/*
+ * interval_eval_level -- Algorithm 2 on one level: enclosures of np
+ * polynomials (one system: same k) on every box of S.
+ *   lo, hi : device double, np x S->n[k-1], row p = polynomial p, boxes in
+ *            CSF leaf order.
+ *   keep   : device uint8, S->n[k-1], or NULL: keep[b] = 1 unless some
+ *            polynomial's enclosure on box b excludes 0 (lo > 0 or hi < 0);
+ *            NaN endpoints never exclude.  This is criterion C0 over the
+ *            system.
+ * The amortization follows Theorem 1: the polynomial is partially evaluated
+ * at each depth-1 interval once, the result at each depth-2 interval once,
+ * and so on; the work is sum_l (Nt_{k-l} - Nt_{k-l-1}) N_{l+1}(S) interval
+ * Horner steps per polynomial (Nt_m = C(d+m, m)).
+ * Errors: VX_EINVAL (k mismatch, degree/side, null pointers, domain),
+ * VX_ECAPACITY (ws smaller than vx_workspace_bytes(VX_WS_EVAL, ...)).
+ */
+int interval_eval_level(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo, double* hi,
+                        uint8_t* keep, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * filter_subdivide -- exclusion filter and bisection (Algorithm 3): prune S
+ * to the kept boxes K (keep[b] != 0, internal nodes without kept descendants
+ * removed) and build the CSF of their 2^k children at level+1, child c of box
+ * B being 2B + c, c in {0,1}^k (bisection of G_n into G_2n, Sec. 3.2).
+ *   keep     : device uint8, S->n[k-1].
+ *   kept     : caller CSF, cap[l] >= S->n[l]; may be NULL (not written).
+ *   next     : caller CSF, cap[l] >= 2^(l+1) S->n[l]; may be NULL.
+ *   d_counts : device int64[2k]: K's n[0..k-1] then next's n[0..k-1].
+ * The host-side n[] of kept/next are not updated (the counts are on the
+ * device); copy d_counts back before using them.
+ * Errors: VX_EINVAL, VX_ECAPACITY (caps below the bounds above, ws).
+ */
+int filter_subdivide(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Per-level record of run_subdivision. */
+typedef struct vx_level_stat {
+  int32_t level;
+  int32_t reserved;
+  int64_t n[VX_KMAX];     /* N_l of the evaluated set S_level */
+  int64_t kept[VX_KMAX];  /* N_l of the kept set K_level */
+  int64_t steps;          /* interval Horner steps, all polynomials (Theorem 1 count) */
+  double eval_ms;         /* interval_eval_level time (HIP events) */
+  double filter_ms;       /* filter_subdivide time (HIP events) */
+} vx_level_stat;
+
+/* Called after each level with device pointers valid until it returns; a
+ * nonzero return stops the run (VX_OK is still returned). */
+typedef int (*vx_level_cb)(void* user, int32_t level, const vx_csf* S, const double* lo, const double* hi,
+                           const uint8_t* keep, const vx_csf* kept);
+
+/*
+ * run_subdivision -- Algorithm 3 with C0 only, from the whole domain (level
+ * 0) to level `depth`: evaluate, filter, bisect, repeat.  The boxes kept at
+ * the last level are the enclosure of the zero set.
+ *   stats : host array of depth+1 records (may be NULL).
+ *   cb    : optional per-level callback.
+ *   ws    : one device workspace carved into all level buffers; if it is too
+ *           small the call returns VX_ECAPACITY and *ws_needed (if not NULL)
+ *           receives a sufficient size for the level that did not fit.
+ * The call synchronizes the stream once per level (to read the counts).
+ */
+int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t depth, void* ws, size_t ws_bytes,
+                    size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user, void* stream);
+
+/* Copy `bytes` between host and device or device and device on `stream` and
+ * wait for it (helper for callbacks). kind: 0 = device->host, 1 = host->device,
+ * 2 = device->device. */
+int vx_copy(void* dst, const void* src, size_t bytes, int32_t kind, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VOXCSF_H */

@@ -1,0 +1,326 @@
+"""Thin Python binding of libvoxcsf.so (ctypes; argument marshalling only).
+
+Every computation runs in the library's HIP kernels; torch provides device
+memory and the current stream.  Function names follow the C ABI
+(include/voxcsf.h): ``interval_eval_level``, ``filter_subdivide``,
+``run_subdivision``, ``csf_build``.
+
+A box set is a :class:`CSF`: per depth l (0-based) an int32 label tensor
+``idx[l]`` and, for l < k-1, an int32 offset tensor ``ptr[l]``, plus the
+host-side node counts ``n``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvoxcsf.so")
+KMAX = 4
+
+VX_OK, VX_EINVAL, VX_ECAPACITY, VX_EHIP, VX_EOVERFLOW, VX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD = 0, 1, 2, 3
+
+
+class VxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"voxcsf error {code}: {msg}")
+        self.code = code
+
+
+class vx_poly(C.Structure):
+    _fields_ = [("k", C.c_int32), ("degree", C.c_int32), ("side", C.c_int32), ("reserved", C.c_int32),
+                ("c_lo", C.c_void_p), ("c_hi", C.c_void_p)]
+
+
+class vx_csf(C.Structure):
+    _fields_ = [("k", C.c_int32), ("level", C.c_int32), ("n", C.c_int64 * KMAX), ("cap", C.c_int64 * KMAX),
+                ("idx", C.c_void_p * KMAX), ("ptr", C.c_void_p * KMAX)]
+
+
+class vx_level_stat(C.Structure):
+    _fields_ = [("level", C.c_int32), ("reserved", C.c_int32), ("n", C.c_int64 * KMAX),
+                ("kept", C.c_int64 * KMAX), ("steps", C.c_int64), ("eval_ms", C.c_double),
+                ("filter_ms", C.c_double)]
+
+
+LEVEL_CB = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.POINTER(vx_csf), C.c_void_p, C.c_void_p, C.c_void_p,
+                       C.POINTER(vx_csf))
+
+_lib = None
+
+
+def lib():
+    """Load libvoxcsf.so; fails loudly when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2406_09857_amd.build` "
+                               "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.vx_last_error.restype = C.c_char_p
+        L.vx_workspace_bytes.argtypes = [C.c_int32, C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.c_int64]
+        L.vx_workspace_bytes.restype = C.c_size_t
+        L.interval_eval_level.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.POINTER(C.c_double),
+                                          vp, vp, vp, vp, C.c_size_t, vp]
+        L.filter_subdivide.argtypes = [C.POINTER(vx_csf), vp, C.POINTER(vx_csf), C.POINTER(vx_csf), vp, vp,
+                                       C.c_size_t, vp]
+        L.run_subdivision.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(C.c_double), C.c_int32, vp,
+                                      C.c_size_t, C.POINTER(C.c_size_t), C.POINTER(vx_level_stat), LEVEL_CB, vp, vp]
+        L.csf_build.argtypes = [C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(vx_csf), vp, C.c_size_t, vp]
+        L.vx_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
+        for f in ("interval_eval_level", "filter_subdivide", "run_subdivision", "csf_build", "vx_copy"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != VX_OK:
+        raise VxError(rc, lib().vx_last_error().decode())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(device=None):
+    return torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+
+
+# ---------------------------------------------------------------------------
+# Data holders
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Poly:
+    """A polynomial as a dense coefficient cube on the device (float64)."""
+    c_lo: torch.Tensor
+    c_hi: torch.Tensor | None = None
+    degree: int | None = None
+
+    def __post_init__(self):
+        self.c_lo = self.c_lo.contiguous()
+        if self.c_hi is not None:
+            self.c_hi = self.c_hi.contiguous()
+        if self.degree is None:
+            self.degree = self.c_lo.shape[0] - 1
+
+    @property
+    def k(self) -> int:
+        return self.c_lo.dim()
+
+    def struct(self) -> vx_poly:
+        return vx_poly(self.k, self.degree, self.c_lo.shape[0], 0, self.c_lo.data_ptr(),
+                       self.c_hi.data_ptr() if self.c_hi is not None else None)
+
+
+def as_polys(polys, device=None) -> list:
+    out = []
+    for p in polys:
+        if isinstance(p, Poly):
+            out.append(p)
+        elif isinstance(p, tuple):
+            out.append(Poly(torch.as_tensor(p[0], dtype=torch.float64, device=_dev(device)),
+                            torch.as_tensor(p[1], dtype=torch.float64, device=_dev(device))))
+        else:
+            out.append(Poly(torch.as_tensor(np.asarray(p), dtype=torch.float64, device=_dev(device))))
+    return out
+
+
+def _poly_array(polys):
+    arr = (vx_poly * len(polys))(*[p.struct() for p in polys])
+    return arr
+
+
+@dataclass
+class CSF:
+    """A box set of the 2^level grid as a CSF tree on the device."""
+    k: int
+    level: int
+    idx: list
+    ptr: list
+    n: list = field(default_factory=list)
+
+    def struct(self) -> vx_csf:
+        s = vx_csf()
+        s.k = self.k
+        s.level = self.level
+        for l in range(self.k):
+            s.n[l] = int(self.n[l])
+            s.cap[l] = int(self.idx[l].numel())
+            s.idx[l] = self.idx[l].data_ptr()
+            if l + 1 < self.k:
+                s.ptr[l] = self.ptr[l].data_ptr()
+        return s
+
+    @staticmethod
+    def empty(k: int, level: int, cap: list, device=None) -> "CSF":
+        dev = _dev(device)
+        idx = [torch.empty(max(1, int(c)), dtype=torch.int32, device=dev) for c in cap]
+        ptr = [torch.empty(max(1, int(c)) + 1, dtype=torch.int32, device=dev) for c in cap[:-1]]
+        return CSF(k, level, idx, ptr, [0] * k)
+
+    @staticmethod
+    def from_arrays(k: int, level: int, idx: list, ptr: list, device=None) -> "CSF":
+        dev = _dev(device)
+        ti = [torch.as_tensor(np.asarray(a, np.int32), device=dev) for a in idx]
+        tp = [torch.as_tensor(np.asarray(a, np.int32), device=dev) for a in ptr]
+        return CSF(k, level, ti, tp, [len(a) for a in idx])
+
+    def trimmed(self) -> "CSF":
+        return CSF(self.k, self.level, [self.idx[l][: self.n[l]] for l in range(self.k)],
+                   [self.ptr[l][: self.n[l] + 1] for l in range(self.k - 1)], list(self.n))
+
+    def to_numpy(self) -> dict:
+        return {"k": self.k, "level": self.level,
+                "idx": [self.idx[l][: self.n[l]].cpu().numpy() for l in range(self.k)],
+                "ptr": [self.ptr[l][: self.n[l] + 1].cpu().numpy() for l in range(self.k - 1)]}
+
+    @property
+    def nboxes(self) -> int:
+        return int(self.n[self.k - 1])
+
+
+def _ws(nbytes: int, device=None) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=_dev(device))
+
+
+# ---------------------------------------------------------------------------
+# Entry points
+# ---------------------------------------------------------------------------
+
+def workspace_bytes(which: int, polys=None, csf: CSF | None = None, n: int = 0) -> int:
+    parr = _poly_array(polys) if polys else None
+    s = csf.struct() if csf is not None else None
+    return int(lib().vx_workspace_bytes(which, parr, len(polys) if polys else 0, C.byref(s) if s else None, n))
+
+
+def interval_eval_level(polys, csf: CSF, dom, out=None, keep: bool = True, ws=None, stream=None):
+    """Enclosures (lo, hi: (np, nboxes) float64) and keep flags (uint8) of a
+    polynomial system on every box of the CSF, in CSF leaf order."""
+    polys = as_polys(polys)
+    dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
+    nb = csf.nboxes
+    dev = csf.idx[0].device
+    if out is None:
+        lo = torch.empty((len(polys), nb), dtype=torch.float64, device=dev)
+        hi = torch.empty((len(polys), nb), dtype=torch.float64, device=dev)
+        kp = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev) if keep else None
+    else:
+        lo, hi, kp = out
+    parr = _poly_array(polys)
+    s = csf.struct()
+    need = int(lib().vx_workspace_bytes(VX_WS_EVAL, parr, len(polys), C.byref(s), 0))
+    if need == 0:
+        _check(VX_EINVAL)
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    _check(lib().interval_eval_level(parr, len(polys), C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)),
+                                     lo.data_ptr(), hi.data_ptr(), kp.data_ptr() if kp is not None else None,
+                                     ws.data_ptr(), ws.numel(), _stream(stream)))
+    return lo, hi, (kp[:nb] if kp is not None else None)
+
+
+def filter_subdivide(csf: CSF, keep: torch.Tensor, want_kept: bool = True, want_next: bool = True, ws=None,
+                     stream=None):
+    """(kept CSF, next CSF) with host counts filled (synchronizes)."""
+    k = csf.k
+    dev = csf.idx[0].device
+    kept = CSF.empty(k, csf.level, [csf.n[l] for l in range(k)], dev) if want_kept else None
+    nxt = CSF.empty(k, csf.level + 1, [csf.n[l] << (l + 1) for l in range(k)], dev) if want_next else None
+    d_counts = torch.zeros(2 * k, dtype=torch.int64, device=dev)
+    s = csf.struct()
+    need = int(lib().vx_workspace_bytes(VX_WS_FILTER, None, 0, C.byref(s), 0))
+    if ws is None or ws.numel() < need:
+        ws = _ws(need, dev)
+    ks = kept.struct() if kept else None
+    ns = nxt.struct() if nxt else None
+    _check(lib().filter_subdivide(C.byref(s), keep.data_ptr(), C.byref(ks) if ks else None,
+                                  C.byref(ns) if ns else None, d_counts.data_ptr(), ws.data_ptr(), ws.numel(),
+                                  _stream(stream)))
+    counts = d_counts.cpu().tolist()
+    if kept:
+        kept.n = counts[:k]
+    if nxt:
+        nxt.n = counts[k:]
+    return kept, nxt
+
+
+def root_csf(k: int, device=None) -> CSF:
+    """The level-0 box set {(0, ..., 0)}."""
+    return CSF.from_arrays(k, 0, [[0]] * k, [[0, 1]] * (k - 1), device)
+
+
+def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None):
+    """Algorithm 3 with C0 to `depth`.  Returns (stats, kept) where stats is a
+    list of per-level dicts and kept the final level's kept CSF (host numpy).
+
+    ``record(level, S, lo, hi, keep, K)`` is called with device-side views
+    (numpy copies) when given; it may return True to stop.
+    """
+    polys = as_polys(polys)
+    k = polys[0].k
+    dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
+    parr = _poly_array(polys)
+    stats = (vx_level_stat * (depth + 1))()
+    need = C.c_size_t(0)
+    final = {}
+
+    def _copy_csf(cs) -> dict:
+        out = {"k": k, "level": cs.level, "idx": [], "ptr": []}
+        for l in range(k):
+            a = np.empty(cs.n[l], np.int32)
+            if cs.n[l]:
+                _check(lib().vx_copy(a.ctypes.data, cs.idx[l], a.nbytes, 0, _stream(stream)))
+            out["idx"].append(a)
+            if l + 1 < k:
+                b = np.empty(cs.n[l] + 1, np.int32)
+                _check(lib().vx_copy(b.ctypes.data, cs.ptr[l], b.nbytes, 0, _stream(stream)))
+                out["ptr"].append(b)
+        return out
+
+    def _cb(user, level, S, lo, hi, keep, K):
+        try:
+            if level == depth:
+                final["kept"] = _copy_csf(K.contents)
+            if record is not None:
+                Sd = _copy_csf(S.contents)
+                nb = S.contents.n[k - 1]
+                lo_h = np.empty((len(polys), nb)); hi_h = np.empty((len(polys), nb)); kp = np.empty(nb, np.uint8)
+                if nb:
+                    _check(lib().vx_copy(lo_h.ctypes.data, lo, lo_h.nbytes, 0, _stream(stream)))
+                    _check(lib().vx_copy(hi_h.ctypes.data, hi, hi_h.nbytes, 0, _stream(stream)))
+                    _check(lib().vx_copy(kp.ctypes.data, keep, kp.nbytes, 0, _stream(stream)))
+                stop = record(level, Sd, lo_h, hi_h, kp, _copy_csf(K.contents))
+                return 1 if stop else 0
+            return 0
+        except Exception as e:  # never let an exception cross the C boundary
+            final["error"] = e
+            return 1
+
+    cb = LEVEL_CB(_cb)
+    size = ws_bytes if ws_bytes is not None else 4 << 30
+    for _ in range(8):
+        ws = _ws(size)
+        rc = lib().run_subdivision(parr, len(polys), dom.ctypes.data_as(C.POINTER(C.c_double)), depth,
+                                   ws.data_ptr(), ws.numel(), C.byref(need), stats, cb, None, _stream(stream))
+        if rc == VX_ECAPACITY and need.value > size:
+            size = int(need.value * 1.25)
+            del ws
+            continue
+        _check(rc)
+        break
+    if "error" in final:
+        raise final["error"]
+    out = []
+    for r in stats:
+        out.append({"level": r.level, "n": list(r.n)[:k], "kept": list(r.kept)[:k], "steps": r.steps,
+                    "eval_ms": r.eval_ms, "filter_ms": r.filter_ms})
+    return out, final.get("kept")

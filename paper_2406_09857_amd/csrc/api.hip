@@ -1,0 +1,322 @@
+// C ABI of libvoxcsf.so: argument checking, dispatch, and the level loop of
+// Algorithm 3 (Moroz, arXiv 2406.09857).
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "eval.hpp"
+
+namespace vx {
+
+static thread_local std::string g_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+}
+
+const char* get_error() { return g_error.c_str(); }
+
+static int check_poly(const vx_poly* P, int np, int k) {
+  if (!P || np < 1) VX_FAIL(VX_EINVAL, "need at least one polynomial");
+  for (int p = 0; p < np; p++) {
+    if (P[p].k != k) VX_FAIL(VX_EINVAL, "polynomial %d has k=%d, the box set has k=%d", p, P[p].k, k);
+    if (P[p].degree < 0 || P[p].degree > 400) VX_FAIL(VX_EINVAL, "polynomial %d: degree %d outside [0, 400]", p, P[p].degree);
+    if (P[p].side < P[p].degree + 1) VX_FAIL(VX_EINVAL, "polynomial %d: side %d < degree+1", p, P[p].side);
+    if (!P[p].c_lo) VX_FAIL(VX_EINVAL, "polynomial %d: null coefficients", p);
+    int64_t cube = 1;
+    for (int i = 0; i < k; i++) cube *= P[p].side;
+    if (cube > (int64_t)1 << 31) VX_FAIL(VX_EOVERFLOW, "polynomial %d: coefficient cube too large", p);
+  }
+  return VX_OK;
+}
+
+static int check_csf(const vx_csf* S, bool need_arrays) {
+  if (!S) VX_FAIL(VX_EINVAL, "null CSF");
+  if (S->k < 1 || S->k > VX_KMAX) VX_FAIL(VX_EINVAL, "k=%d outside [1, %d]", S->k, VX_KMAX);
+  if (S->level < 0 || S->level > 29) VX_FAIL(VX_EINVAL, "level %d outside [0, 29]", S->level);
+  for (int l = 0; l < S->k; l++) {
+    if (S->n[l] < 0) VX_FAIL(VX_EINVAL, "negative node count at depth %d", l + 1);
+    if (S->n[l] >= ((int64_t)1 << 31) - 1) VX_FAIL(VX_EOVERFLOW, "depth %d has %lld nodes (int32 limit)", l + 1, (long long)S->n[l]);
+    if (l > 0 && S->n[l] < S->n[l - 1]) VX_FAIL(VX_EINVAL, "depth %d has fewer nodes than depth %d", l + 1, l);
+    if (need_arrays && S->n[l] > 0 && !S->idx[l]) VX_FAIL(VX_EINVAL, "null labels at depth %d", l + 1);
+    if (need_arrays && l + 1 < S->k && S->n[l] > 0 && !S->ptr[l]) VX_FAIL(VX_EINVAL, "null offsets at depth %d", l + 1);
+  }
+  return VX_OK;
+}
+
+static int check_dom(const double* dom, int k) {
+  if (!dom) VX_FAIL(VX_EINVAL, "null domain");
+  for (int j = 0; j < k; j++) {
+    const double a = dom[2 * j], b = dom[2 * j + 1];
+    if (!(a < b) || a != a || b != b || a - a != 0.0 || b - b != 0.0)
+      VX_FAIL(VX_EINVAL, "axis %d: domain [%g, %g] is not a finite nonempty interval", j, a, b);
+  }
+  return VX_OK;
+}
+
+static int64_t theorem1_steps(const vx_poly* P, int np, const vx_csf* S) {
+  int64_t total = 0;
+  for (int p = 0; p < np; p++) {
+    const int d = P[p].degree, k = S->k;
+    for (int l = 0; l < k; l++) total += (ntup(k - l, d) - ntup(k - l - 1, d)) * S->n[l];
+  }
+  return total;
+}
+
+}  // namespace vx
+
+// ---------------------------------------------------------------------------
+// run_subdivision: the level loop.  The workspace is used from both ends:
+// S_level sits at one end and the next level's CSF is built at the other, so
+// the two swap ends every level without copies; everything else (enclosures,
+// keep flags, K, scratch) lives in between.
+// ---------------------------------------------------------------------------
+namespace vx {
+
+static size_t csf_bytes(int k, const int64_t* cap) {
+  size_t b = 0;
+  for (int l = 0; l < k; l++) {
+    b += ((size_t)cap[l] * 4 + 255) / 256 * 256;
+    if (l + 1 < k) b += ((size_t)(cap[l] + 1) * 4 + 255) / 256 * 256;
+  }
+  return b;
+}
+
+static void csf_place(vx_csf* S, int k, int level, const int64_t* cap, char* base) {
+  memset(S, 0, sizeof *S);
+  S->k = k;
+  S->level = level;
+  size_t off = 0;
+  for (int l = 0; l < k; l++) {
+    S->cap[l] = cap[l];
+    S->idx[l] = reinterpret_cast<int32_t*>(base + off);
+    off += ((size_t)cap[l] * 4 + 255) / 256 * 256;
+    if (l + 1 < k) {
+      S->ptr[l] = reinterpret_cast<int32_t*>(base + off);
+      off += ((size_t)(cap[l] + 1) * 4 + 255) / 256 * 256;
+    }
+  }
+}
+
+}  // namespace vx
+
+using namespace vx;
+
+extern "C" {
+
+const char* vx_last_error(void) { return get_error(); }
+
+size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_csf* S, int64_t n) {
+  switch (which) {
+    case VX_WS_EVAL:
+      if (check_csf(S, false) || check_poly(P, np, S->k)) return 0;
+      return eval_workspace_bytes(P, np, S);
+    case VX_WS_FILTER:
+      if (check_csf(S, false)) return 0;
+      return filter_workspace_bytes(S);
+    case VX_WS_BUILD:
+      if (!S || S->k < 1 || S->k > VX_KMAX || n < 0) return 0;
+      return build_workspace_bytes(S->k, n);
+    default:
+      return 0;
+  }
+}
+
+int interval_eval_level(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo, double* hi,
+                        uint8_t* keep, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_csf(S, true))) return rc;
+  if ((rc = check_poly(P, np, S->k))) return rc;
+  if ((rc = check_dom(dom, S->k))) return rc;
+  if (S->n[S->k - 1] > 0 && (!lo || !hi)) VX_FAIL(VX_EINVAL, "null output arrays");
+  return eval_level_impl(P, np, S, dom, lo, hi, keep, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int filter_subdivide(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
+                     size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_csf(S, true))) return rc;
+  const int k = S->k;
+  if (S->n[k - 1] > 0 && !keep) VX_FAIL(VX_EINVAL, "null keep flags");
+  if (S->level >= 29 && next) VX_FAIL(VX_EOVERFLOW, "level %d cannot be bisected (labels are int32)", S->level);
+  for (int l = 0; l < k; l++) {
+    if (kept && (kept->k != k || kept->cap[l] < S->n[l] || !kept->idx[l] || (l + 1 < k && !kept->ptr[l])))
+      VX_FAIL(VX_ECAPACITY, "kept CSF: depth %d needs capacity %lld", l + 1, (long long)S->n[l]);
+    const int64_t bound = S->n[l] << (l + 1);
+    if (bound >= ((int64_t)1 << 31) - 1) VX_FAIL(VX_EOVERFLOW, "next level may exceed int32 at depth %d", l + 1);
+    if (next && (next->k != k || next->cap[l] < bound || !next->idx[l] || (l + 1 < k && !next->ptr[l])))
+      VX_FAIL(VX_ECAPACITY, "next CSF: depth %d needs capacity %lld", l + 1, (long long)bound);
+  }
+  if (kept) kept->level = S->level;
+  if (next) next->level = S->level + 1;
+  return filter_impl(S, keep, kept, next, d_counts, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int vx_copy(void* dst, const void* src, size_t bytes, int32_t kind, void* stream) {
+  if (bytes == 0) return VX_OK;
+  if (!dst || !src) VX_FAIL(VX_EINVAL, "null pointer");
+  hipMemcpyKind mk = kind == 0 ? hipMemcpyDeviceToHost : kind == 1 ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  VX_HIP(hipMemcpyAsync(dst, src, bytes, mk, (hipStream_t)stream));
+  VX_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return VX_OK;
+}
+
+
+int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t depth, void* ws, size_t ws_bytes,
+                    size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user, void* stream) {
+  if (!P || np < 1) VX_FAIL(VX_EINVAL, "need at least one polynomial");
+  const int k = P[0].k;
+  int rc;
+  if (k < 1 || k > VX_KMAX) VX_FAIL(VX_EINVAL, "k=%d outside [1, %d]", k, VX_KMAX);
+  if ((rc = check_poly(P, np, k))) return rc;
+  if ((rc = check_dom(dom, k))) return rc;
+  if (depth < 0 || depth > 28) VX_FAIL(VX_EINVAL, "depth %d outside [0, 28]", depth);
+  if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
+  hipStream_t st = (hipStream_t)stream;
+  char* base = reinterpret_cast<char*>(ws);
+  const size_t total = ws_bytes / 256 * 256;
+
+  hipEvent_t ev[3];
+  for (int i = 0; i < 3; i++) VX_HIP(hipEventCreate(&ev[i]));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 3; i++) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+
+  // S_0 at the low end.
+  int64_t cap[VX_KMAX] = {1, 1, 1, 1};
+  vx_csf S;
+  size_t s_bytes = csf_bytes(k, cap);
+  bool s_low = true;
+  if (s_bytes > total) {
+    if (ws_needed) *ws_needed = s_bytes + 256;
+    VX_FAIL(VX_ECAPACITY, "workspace too small");
+  }
+  csf_place(&S, k, 0, cap, base);
+  if ((rc = init_root_impl(&S, st))) return rc;
+
+  std::vector<int64_t> counts(2 * k);
+  for (int level = 0; level <= depth; level++) {
+    S.level = level;
+    const int64_t nleaf = S.n[k - 1];
+    const bool last = level == depth;
+    // next CSF capacity bound
+    int64_t ncap[VX_KMAX] = {0, 0, 0, 0};
+    for (int l = 0; l < k; l++) ncap[l] = (S.n[l] << (l + 1)) > 0 ? (S.n[l] << (l + 1)) : 1;
+    const size_t n_bytes = last ? 0 : csf_bytes(k, ncap);
+    // middle region (offsets relative to its start)
+    size_t moff = 0;
+    auto carve = [&](size_t bytes) {
+      const size_t o = moff;
+      moff += (bytes + 255) / 256 * 256;
+      return o;
+    };
+    const size_t o_lo = carve(sizeof(double) * (size_t)np * nleaf);
+    const size_t o_hi = carve(sizeof(double) * (size_t)np * nleaf);
+    const size_t o_keep = carve(nleaf > 0 ? (size_t)nleaf : 1);
+    const size_t o_cnt = carve(sizeof(int64_t) * 2 * VX_KMAX);
+    int64_t kcap[VX_KMAX] = {1, 1, 1, 1};
+    for (int l = 0; l < k; l++) kcap[l] = S.n[l] > 0 ? S.n[l] : 1;
+    const size_t o_k = carve(csf_bytes(k, kcap));
+    const size_t ews = eval_workspace_bytes(P, np, &S);
+    const size_t fws = filter_workspace_bytes(&S);
+    const size_t scratch_bytes = ews > fws ? ews : fws;
+    const size_t o_scr = carve(scratch_bytes);
+    const size_t mid_bytes = moff;
+    const size_t need = s_bytes + n_bytes + mid_bytes;
+    if (need > total) {
+      if (ws_needed) *ws_needed = need + 256;
+      VX_FAIL(VX_ECAPACITY, "run_subdivision: level %d needs a %zu-byte workspace (%zu given)", level, need + 256,
+              ws_bytes);
+    }
+    // place: S at one end, next at the other, the middle right after S's end.
+    char* mid_base;
+    char* next_base;
+    if (s_low) {
+      mid_base = base + s_bytes;
+      next_base = base + total - n_bytes;
+    } else {
+      mid_base = base + n_bytes;
+      next_base = base;
+    }
+    double* lo = reinterpret_cast<double*>(mid_base + o_lo);
+    double* hi = reinterpret_cast<double*>(mid_base + o_hi);
+    uint8_t* keep = reinterpret_cast<uint8_t*>(mid_base + o_keep);
+    int64_t* d_counts = reinterpret_cast<int64_t*>(mid_base + o_cnt);
+    vx_csf K;
+    csf_place(&K, k, level, kcap, mid_base + o_k);
+    char* scratch = mid_base + o_scr;
+    vx_csf N;
+    if (!last) csf_place(&N, k, level + 1, ncap, next_base);
+
+    VX_HIP(hipEventRecord(ev[0], st));
+    if ((rc = eval_level_impl(P, np, &S, dom, lo, hi, keep, scratch, scratch_bytes, st))) return rc;
+    VX_HIP(hipEventRecord(ev[1], st));
+    if ((rc = filter_impl(&S, keep, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st))) return rc;
+    VX_HIP(hipEventRecord(ev[2], st));
+    VX_HIP(hipMemcpyAsync(counts.data(), d_counts, sizeof(int64_t) * 2 * k, hipMemcpyDeviceToHost, st));
+    VX_HIP(hipStreamSynchronize(st));
+    for (int l = 0; l < k; l++) K.n[l] = counts[l];
+    if (stats) {
+      vx_level_stat& r = stats[level];
+      memset(&r, 0, sizeof r);
+      r.level = level;
+      for (int l = 0; l < k; l++) {
+        r.n[l] = S.n[l];
+        r.kept[l] = K.n[l];
+      }
+      r.steps = theorem1_steps(P, np, &S);
+      float ms = 0;
+      VX_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      r.eval_ms = ms;
+      VX_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+      r.filter_ms = ms;
+    }
+    if (cb && cb(user, level, &S, lo, hi, keep, &K)) break;
+    if (last) break;
+    // next becomes S (at the other end)
+    for (int l = 0; l < k; l++) N.n[l] = counts[k + l];
+    S = N;
+    for (int l = 0; l < k; l++) S.cap[l] = ncap[l];
+    s_bytes = n_bytes;
+    s_low = !s_low;
+    if (S.n[k - 1] == 0) {
+      // nothing left: record empty levels
+      for (int lv = level + 1; lv <= depth; lv++) {
+        if (stats) {
+          memset(&stats[lv], 0, sizeof stats[lv]);
+          stats[lv].level = lv;
+        }
+      }
+      break;
+    }
+  }
+  return VX_OK;
+}
+
+int csf_build(int32_t k, int32_t level, const int32_t* boxes, int64_t n, vx_csf* out, void* ws, size_t ws_bytes,
+              void* stream) {
+  if (k < 1 || k > VX_KMAX) VX_FAIL(VX_EINVAL, "k=%d outside [1, %d]", k, VX_KMAX);
+  if (level < 0 || level > 29) VX_FAIL(VX_EINVAL, "level %d outside [0, 29]", level);
+  if (n < 0 || (n > 0 && !boxes)) VX_FAIL(VX_EINVAL, "bad box list");
+  if (!out || out->k != k) VX_FAIL(VX_EINVAL, "output CSF must have k=%d", k);
+  if (n >= ((int64_t)1 << 31) - 1) VX_FAIL(VX_EOVERFLOW, "too many boxes");
+  for (int l = 0; l < k; l++)
+    if (out->cap[l] < n || !out->idx[l] || (l + 1 < k && !out->ptr[l]))
+      VX_FAIL(VX_ECAPACITY, "output CSF depth %d needs capacity %lld", l + 1, (long long)n);
+  out->level = level;
+  return build_impl(k, level, boxes, n, out, nullptr, ws, ws_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

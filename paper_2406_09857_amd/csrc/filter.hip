@@ -1,0 +1,240 @@
+// Exclusion filter, bisection and CSF compaction (Algorithm 3 of Moroz,
+// arXiv 2406.09857; bisection of G_n into G_2n, Sec. 3.2).
+//
+// Given a level's CSF S and a keep flag per box:
+//   K    = S restricted to the kept boxes; an internal node survives when at
+//          least one descendant box does.  Depth by depth from the leaves:
+//          newpos_l = exclusive scan of the survival flags, and a node's flag
+//          is newpos_{l+1}[ptr[q+1]] > newpos_{l+1}[ptr[q]].
+//   next = CSF of the children 2B + c, c in {0,1}^k, of every kept box B.  A
+//          depth-(l+1) node of K with label i becomes 2^(l+1) nodes; the
+//          children of a copy of node y are the labels 2 i' + b of y's
+//          children i' (b = 0, 1), so N_l(next) = 2^l N_l(K) and labels stay
+//          ascending under each parent.  Offsets come from a scan of the
+//          child counts; every output entry finds its parent by binary search.
+// All passes are scans and gathers with one thread per element; nothing
+// depends on scheduling order, so the output is deterministic.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "eval.hpp"
+#include "scan.hpp"
+
+namespace vx {
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile_sums(int64_t* tile_sum, const int64_t* n_dev,
+                                                                  int64_t nmax, int64_t* total_out) {
+  (void)n_dev;
+  const int64_t nt = scan_tiles(nmax);
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nt; base += SCAN_THREADS) {
+    const int64_t i = base + threadIdx.x;
+    const int64_t v = i < nt ? tile_sum[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_exclusive_scan(v, tot);
+    if (i < nt) tile_sum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
+struct KeepLoader {
+  const uint8_t* keep;
+  __device__ int64_t operator()(int64_t i) const { return keep[i] != 0; }
+};
+
+struct AnyChildLoader {
+  const int32_t* ptr;
+  const int32_t* child_pos;
+  __device__ int64_t operator()(int64_t i) const { return child_pos[ptr[i + 1]] > child_pos[ptr[i]]; }
+};
+
+struct ChildCountLoader {
+  const int32_t* src;
+  const int32_t* kptr;
+  __device__ int64_t operator()(int64_t i) const {
+    const int32_t y = src[i];
+    return 2 * (int64_t)(kptr[y + 1] - kptr[y]);
+  }
+};
+
+// Write the kept nodes of one depth.
+__global__ void k_compact_level(int64_t n, const int32_t* __restrict__ newpos, const int32_t* __restrict__ idx,
+                                const int32_t* __restrict__ ptr, const int32_t* __restrict__ child_newpos,
+                                int32_t* __restrict__ kidx, int32_t* __restrict__ kptr,
+                                const int64_t* __restrict__ total_child) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && newpos[i + 1] > newpos[i]) {
+    const int32_t o = newpos[i];
+    kidx[o] = idx[i];
+    if (kptr) kptr[o] = child_newpos[ptr[i]];
+  }
+  if (i == 0 && kptr) kptr[newpos[n]] = (int32_t)*total_child;
+}
+
+__global__ void k_next_counts(int k, const int64_t* __restrict__ kcnt, int64_t* __restrict__ ncnt,
+                              int64_t* __restrict__ d_counts) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int l = 0; l < k; l++) {
+      ncnt[l] = kcnt[l] << (l + 1);
+      if (d_counts) {
+        d_counts[l] = kcnt[l];
+        d_counts[k + l] = ncnt[l];
+      }
+    }
+  }
+}
+
+// Depth-1 nodes of next: 2i, 2i+1 for every depth-1 label i of K.
+__global__ void k_next_first(const int64_t* __restrict__ ncnt, const int32_t* __restrict__ kidx,
+                             int32_t* __restrict__ nidx, int32_t* __restrict__ src) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= ncnt[0]) return;
+  const int64_t j = o >> 1;
+  nidx[o] = 2 * kidx[j] + (int32_t)(o & 1);
+  if (src) src[o] = (int32_t)j;
+}
+
+// Depth l+1 >= 2 of next: entry o under parent P (binary search in nptr).
+__global__ void k_next_fill(const int64_t* __restrict__ ncnt_parent, const int64_t* __restrict__ ncnt,
+                            const int32_t* __restrict__ nptr, const int32_t* __restrict__ src_parent,
+                            const int32_t* __restrict__ kptr, const int32_t* __restrict__ kidx,
+                            int32_t* __restrict__ nidx, int32_t* __restrict__ src) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= *ncnt) return;
+  int64_t lo = 0, hi = *ncnt_parent;  // last P with nptr[P] <= o
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (nptr[mid] <= o) lo = mid; else hi = mid;
+  }
+  const int64_t rel = o - nptr[lo];
+  const int32_t y = src_parent[lo];
+  const int32_t child = kptr[y] + (int32_t)(rel >> 1);
+  nidx[o] = 2 * kidx[child] + (int32_t)(rel & 1);
+  if (src) src[o] = child;
+}
+
+struct FilterPlan {
+  int32_t* newpos[VX_KMAX] = {};
+  int64_t* kcnt = nullptr;
+  int64_t* ncnt = nullptr;
+  int64_t* tiles = nullptr;
+  int32_t* kidx[VX_KMAX] = {};
+  int32_t* kptr[VX_KMAX] = {};
+  int32_t* src[VX_KMAX] = {};
+};
+
+static void plan_filter(Arena& A, FilterPlan& F, const vx_csf* S, bool own_kept, bool want_next) {
+  const int k = S->k;
+  int64_t maxn = 1;
+  for (int l = 0; l < k; l++) {
+    F.newpos[l] = A.take<int32_t>(S->n[l] + 1);
+    const int64_t nb = S->n[l] << (l + 1);
+    maxn = maxn > nb ? maxn : nb;
+  }
+  F.kcnt = A.take<int64_t>(VX_KMAX);
+  F.ncnt = A.take<int64_t>(VX_KMAX);
+  F.tiles = A.take<int64_t>(scan_tiles(maxn));
+  if (own_kept)
+    for (int l = 0; l < k; l++) {
+      F.kidx[l] = A.take<int32_t>(S->n[l] > 0 ? S->n[l] : 1);
+      if (l + 1 < k) F.kptr[l] = A.take<int32_t>(S->n[l] + 1);
+    }
+  if (want_next)
+    for (int l = 0; l + 1 < k; l++) F.src[l] = A.take<int32_t>((S->n[l] << (l + 1)) + 1);
+}
+
+size_t filter_workspace_bytes(const vx_csf* S) {
+  Arena A;
+  FilterPlan F;
+  plan_filter(A, F, S, true, true);
+  return A.off + 256;
+}
+
+int filter_impl(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
+                size_t ws_bytes, hipStream_t st) {
+  const int k = S->k;
+  Arena A;
+  A.base = reinterpret_cast<char*>(ws);
+  A.size = ws_bytes;
+  FilterPlan F;
+  plan_filter(A, F, S, kept == nullptr, next != nullptr);
+  if (A.overflow)
+    VX_FAIL(VX_ECAPACITY, "filter_subdivide: workspace of %zu bytes is too small (%zu needed)", ws_bytes, A.off + 256);
+  int32_t* const* kidx = kept ? kept->idx : F.kidx;
+  int32_t* const* kptr = kept ? kept->ptr : F.kptr;
+
+  // Survival scans, leaves first.
+  scan_exclusive(KeepLoader{keep}, (const int64_t*)nullptr, S->n[k - 1], F.newpos[k - 1], F.kcnt + (k - 1), F.tiles,
+                 st);
+  VX_CHECK_LAUNCH("keep scan");
+  for (int l = k - 2; l >= 0; l--) {
+    scan_exclusive(AnyChildLoader{S->ptr[l], F.newpos[l + 1]}, (const int64_t*)nullptr, S->n[l], F.newpos[l],
+                   F.kcnt + l, F.tiles, st);
+    VX_CHECK_LAUNCH("survival scan");
+  }
+  // Compacted K.
+  for (int l = 0; l < k; l++) {
+    const int64_t n = S->n[l];
+    const bool inner = l + 1 < k;
+    hipLaunchKernelGGL(k_compact_level, dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)), dim3(256), 0,
+                       st, n, (const int32_t*)F.newpos[l], (const int32_t*)S->idx[l],
+                       inner ? (const int32_t*)S->ptr[l] : nullptr, inner ? (const int32_t*)F.newpos[l + 1] : nullptr,
+                       kidx[l], inner ? kptr[l] : nullptr, inner ? (const int64_t*)(F.kcnt + l + 1) : nullptr);
+    VX_CHECK_LAUNCH("k_compact_level");
+  }
+  hipLaunchKernelGGL(k_next_counts, dim3(1), dim3(64), 0, st, k, (const int64_t*)F.kcnt, F.ncnt, d_counts);
+  VX_CHECK_LAUNCH("k_next_counts");
+  if (!next) return VX_OK;
+
+  // Children CSF.
+  {
+    const int64_t bound = S->n[0] << 1;
+    hipLaunchKernelGGL(k_next_first, dim3((unsigned)((bound + 255) / 256 > 0 ? (bound + 255) / 256 : 1)), dim3(256),
+                       0, st, (const int64_t*)F.ncnt, (const int32_t*)kidx[0], next->idx[0],
+                       k > 1 ? F.src[0] : nullptr);
+    VX_CHECK_LAUNCH("k_next_first");
+  }
+  for (int l = 1; l < k; l++) {
+    const int64_t pbound = S->n[l - 1] << l;       // next depth-l count bound
+    const int64_t bound = S->n[l] << (l + 1);      // next depth-(l+1) count bound
+    scan_exclusive(ChildCountLoader{F.src[l - 1], kptr[l - 1]}, (const int64_t*)(F.ncnt + l - 1), pbound,
+                   next->ptr[l - 1], (int64_t*)nullptr, F.tiles, st);
+    VX_CHECK_LAUNCH("child count scan");
+    hipLaunchKernelGGL(k_next_fill, dim3((unsigned)((bound + 255) / 256 > 0 ? (bound + 255) / 256 : 1)), dim3(256),
+                       0, st, (const int64_t*)(F.ncnt + l - 1), (const int64_t*)(F.ncnt + l),
+                       (const int32_t*)next->ptr[l - 1], (const int32_t*)F.src[l - 1], (const int32_t*)kptr[l - 1],
+                       (const int32_t*)kidx[l], next->idx[l], l + 1 < k ? F.src[l] : nullptr);
+    VX_CHECK_LAUNCH("k_next_fill");
+  }
+  return VX_OK;
+}
+
+}  // namespace vx
+
+namespace vx {
+
+// The level-0 CSF of Algorithm 3: the single box (0, ..., 0).
+__global__ void k_init_root(int k, int32_t* i0, int32_t* i1, int32_t* i2, int32_t* i3, int32_t* p0, int32_t* p1,
+                            int32_t* p2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int32_t* idx[4] = {i0, i1, i2, i3};
+  int32_t* ptr[3] = {p0, p1, p2};
+  for (int l = 0; l < k; l++) {
+    idx[l][0] = 0;
+    if (l + 1 < k) {
+      ptr[l][0] = 0;
+      ptr[l][1] = 1;
+    }
+  }
+}
+
+int init_root_impl(vx_csf* S, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_root, dim3(1), dim3(64), 0, st, S->k, S->idx[0], S->idx[1], S->idx[2], S->idx[3],
+                     S->ptr[0], S->ptr[1], S->ptr[2]);
+  VX_CHECK_LAUNCH("k_init_root");
+  for (int l = 0; l < S->k; l++) S->n[l] = 1;
+  return VX_OK;
+}
+
+}  // namespace vx
