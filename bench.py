@@ -1,0 +1,155 @@
+#!/usr/bin/env python
+"""Benchmark of the amortized interval subdivision path on one MI355X.
+
+One step = one full run of Algorithm 3 with the interval exclusion criterion
+(Moroz, arXiv 2406.09857) on the two-surface curve workload: two random
+trivariate polynomials of total degree 100 (N(0,1) coefficients, seed 3),
+domain [-1,1]^3, levels 0..10.  Every level evaluates both polynomials on the
+level's CSF (interval_eval_level), filters and bisects (filter_subdivide).
+The inputs are resident in HBM before the timed region.
+
+Prints one JSON line: throughput in interval box evaluations per second
+(sum over levels and polynomials of |S_level|, divided by the step time),
+the FP64 roofline of the dominant kernel (HIP events around each kernel
+launch in the timed region), and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "interval box-evals/sec per level + % FP64-VALU peak; batched & adjoint vs plain"
+# MI355X: 256 CUs x 64 FP64 lanes x 2.4 GHz = 39.3e12 FP64 VALU operations/s
+# without fused multiply-add (the published 78.6 TFLOP/s counts an FMA as two).
+FP64_NOFMA_PEAK = 256 * 64 * 2.4e9
+OPS_PER_STEP = 4      # lower/upper product and lower/upper sum of one interval Horner step
+VALU_PER_STEP = 8     # FP64 instructions per step in the sign-specialized kernels
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="curve", choices=["curve", "surface", "tiny"])
+    ap.add_argument("--cpu-depth", type=int, default=8, help="oracle sample: levels 0..cpu-depth of the workload")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_2406_09857_amd import synth
+    if name == "curve":
+        return synth.curve(), "two trivariate polynomials, total degree 100, N(0,1) coefficients, domain [-1,1]^3, levels 0..10"
+    if name == "surface":
+        return synth.surface(), "one trivariate polynomial, total degree 40, N(0,1) coefficients, domain [-1,1]^3, levels 0..9"
+    return synth.tiny(), "one bivariate polynomial, total degree 20, integer coefficients in [-100,100], domain [-1,1]^2, levels 0..8"
+
+
+def cpu_baseline(w, depth):
+    from oracle import core as orc
+    nth = orc.max_threads()
+    t0 = time.perf_counter()
+    recs = orc.subdivide(w.polys, w.k, depth, dom=w.domain(), nthreads=nth)
+    dt = time.perf_counter() - t0
+    evals = sum(len(w.polys) * len(r["S"]["boxes"]) for r in recs)
+    return {"value": evals / dt, "unit": "box-evals/s", "cores": nth, "kind": "oracle",
+            "sample": f"oracle subdivision of the same workload, levels 0..{depth} ({evals} box evaluations, "
+                      f"{dt:.2f} s, OpenMP over x1 fibres)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2406_09857_amd import binding as vx
+
+    w, desc = workload(args.workload)
+    polys = vx.as_polys(w.polys)
+    dom = w.domain()
+    ws = torch.empty(6 << 30, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    stats = None
+    for _ in range(args.warmup):
+        stats, _ = vx.run_subdivision(polys, dom, w.depth, ws=ws, want_kept=False)
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        vx.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats, _ = vx.run_subdivision(polys, dom, w.depth, ws=ws, want_kept=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = vx.profile_end() if not args.no_profile else {}
+    ms_step = (t1 - t0) * 1e3 / args.steps
+
+    evals = sum(len(polys) * s["n"][w.k - 1] for s in stats)
+    steps_total = sum(s["steps"] for s in stats)
+    eval_ms = sum(s["eval_ms"] for s in stats)
+    levels = [{"level": s["level"], "boxes": s["n"][w.k - 1], "N": s["n"], "kept": s["kept"][w.k - 1],
+               "eval_ms": round(s["eval_ms"], 4), "filter_ms": round(s["filter_ms"], 4),
+               "box_evals_per_s": (len(polys) * s["n"][w.k - 1] / (s["eval_ms"] * 1e-3)) if s["eval_ms"] > 0 else None,
+               "fp64_valu_frac": (VALU_PER_STEP * s["steps"] / (s["eval_ms"] * 1e-3) / FP64_NOFMA_PEAK)
+               if s["eval_ms"] > 0 else None}
+              for s in stats]
+
+    roof = None
+    kernels = {}
+    for name, r in prof.items():
+        if r["ms"] <= 0:
+            continue
+        kernels[name] = {"launches": r["launches"], "avg_ms": r["ms"] / r["launches"], "total_ms": r["ms"] / args.steps,
+                         "units_per_launch": r["units"] / r["launches"]}
+    evk = {n: r for n, r in prof.items() if n.startswith("k_") and r["ms"] > 0}
+    if evk:
+        dom_name = max(evk, key=lambda n: evk[n]["ms"])
+        r = evk[dom_name]
+        avg_s = r["ms"] * 1e-3 / r["launches"]
+        ops_per_launch = OPS_PER_STEP * r["units"] / r["launches"]
+        achieved = ops_per_launch / avg_s / 1e12
+        roof = {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": FP64_NOFMA_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / (FP64_NOFMA_PEAK / 1e12), "traffic": None,
+                "avg_launch_ms": avg_s * 1e3, "ops_per_launch": ops_per_launch,
+                "valu_inst_frac": VALU_PER_STEP * r["units"] / r["launches"] / avg_s / FP64_NOFMA_PEAK}
+
+    out = {
+        "metric": METRIC,
+        "value": evals / (ms_step * 1e-3),
+        "unit": "box-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {desc}", "polynomials": len(polys), "depth": w.depth,
+                   "box_evals_per_step": evals, "interval_steps_per_step": steps_total},
+        "eval_only": {"box_evals_per_s": evals / (eval_ms * 1e-3) if eval_ms > 0 else None,
+                      "fp64_valu_frac": VALU_PER_STEP * steps_total / (eval_ms * 1e-3) / FP64_NOFMA_PEAK
+                      if eval_ms > 0 else None,
+                      "ms": eval_ms},
+        "roofline": roof,
+        "kernels": kernels,
+        "levels": levels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_depth, w.depth))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

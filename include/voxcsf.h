@@ -176,6 +176,22 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
  * 2 = device->device. */
 int vx_copy(void* dst, const void* src, size_t bytes, int32_t kind, void* stream);
 
+/* Per-kernel timing.  vx_profile_begin() starts recording HIP events around
+ * every evaluation and filter kernel launched afterwards from any host thread;
+ * vx_profile_end() waits for the recorded events, fills up to `max` records
+ * (one per kernel name: launches, total milliseconds, and the algorithmic
+ * work units of those launches -- interval Horner steps for the evaluation
+ * kernels, elements for the filter kernels), stores the number of names in
+ * *count and stops recording. */
+typedef struct vx_kernel_stat {
+  char name[32];
+  int64_t launches;
+  double ms;
+  double units;
+} vx_kernel_stat;
+int vx_profile_begin(void);
+int vx_profile_end(vx_kernel_stat* out, int32_t max, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -48,6 +48,10 @@ class vx_level_stat(C.Structure):
                 ("filter_ms", C.c_double)]
 
 
+class vx_kernel_stat(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double), ("units", C.c_double)]
+
+
 LEVEL_CB = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.POINTER(vx_csf), C.c_void_p, C.c_void_p, C.c_void_p,
                        C.POINTER(vx_csf))
 
@@ -74,7 +78,9 @@ def lib():
                                       C.c_size_t, C.POINTER(C.c_size_t), C.POINTER(vx_level_stat), LEVEL_CB, vp, vp]
         L.csf_build.argtypes = [C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(vx_csf), vp, C.c_size_t, vp]
         L.vx_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
-        for f in ("interval_eval_level", "filter_subdivide", "run_subdivision", "csf_build", "vx_copy"):
+        L.vx_profile_end.argtypes = [C.POINTER(vx_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
+        for f in ("interval_eval_level", "filter_subdivide", "run_subdivision", "csf_build", "vx_copy",
+                  "vx_profile_begin", "vx_profile_end"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -258,7 +264,8 @@ def root_csf(k: int, device=None) -> CSF:
     return CSF.from_arrays(k, 0, [[0]] * k, [[0, 1]] * (k - 1), device)
 
 
-def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None):
+def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None,
+                    ws: torch.Tensor | None = None, want_kept: bool = True):
     """Algorithm 3 with C0 to `depth`.  Returns (stats, kept) where stats is a
     list of per-level dicts and kept the final level's kept CSF (host numpy).
 
@@ -305,15 +312,16 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
             final["error"] = e
             return 1
 
-    cb = LEVEL_CB(_cb)
-    size = ws_bytes if ws_bytes is not None else 4 << 30
+    cb = LEVEL_CB(_cb) if (record is not None or want_kept) else LEVEL_CB()
+    size = ws_bytes if ws_bytes is not None else (ws.numel() if ws is not None else 4 << 30)
     for _ in range(8):
-        ws = _ws(size)
+        if ws is None or ws.numel() < size:
+            ws = _ws(size)
         rc = lib().run_subdivision(parr, len(polys), dom.ctypes.data_as(C.POINTER(C.c_double)), depth,
                                    ws.data_ptr(), ws.numel(), C.byref(need), stats, cb, None, _stream(stream))
         if rc == VX_ECAPACITY and need.value > size:
             size = int(need.value * 1.25)
-            del ws
+            ws = None
             continue
         _check(rc)
         break
@@ -324,3 +332,17 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
         out.append({"level": r.level, "n": list(r.n)[:k], "kept": list(r.kept)[:k], "steps": r.steps,
                     "eval_ms": r.eval_ms, "filter_ms": r.filter_ms})
     return out, final.get("kept")
+
+
+def profile_begin():
+    """Start per-kernel HIP-event timing inside the library."""
+    _check(lib().vx_profile_begin())
+
+
+def profile_end() -> dict:
+    """Stop timing; {kernel name: {launches, ms, units}} (waits for the events)."""
+    arr = (vx_kernel_stat * 64)()
+    cnt = C.c_int32(0)
+    _check(lib().vx_profile_end(arr, 64, C.byref(cnt)))
+    return {arr[i].name.decode(): {"launches": int(arr[i].launches), "ms": float(arr[i].ms),
+                                   "units": float(arr[i].units)} for i in range(min(cnt.value, 64))}

@@ -320,3 +320,93 @@ int csf_build(int32_t k, int32_t level, const int32_t* boxes, int64_t n, vx_csf*
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Per-kernel event timing.
+// ---------------------------------------------------------------------------
+#include <mutex>
+
+#include "profile.hpp"
+
+namespace vx {
+namespace {
+struct ProfRec {
+  const char* name;
+  double units;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+}  // namespace
+
+bool profiling() { return g_prof_on; }
+
+int prof_start(const char* name, double units, hipStream_t st) {
+  if (!g_prof_on) return -1;
+  ProfRec r{name, units, nullptr, nullptr};
+  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
+  if (hipEventRecord(r.a, st) != hipSuccess) return -1;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof.push_back(r);
+  return (int)g_prof.size() - 1;
+}
+
+void prof_stop(int slot, hipStream_t st) {
+  if (slot < 0) return;
+  hipEvent_t b;
+  {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    if (slot >= (int)g_prof.size()) return;
+    b = g_prof[slot].b;
+  }
+  (void)hipEventRecord(b, st);
+}
+
+}  // namespace vx
+
+extern "C" {
+
+int vx_profile_begin(void) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  for (auto& r : g_prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  g_prof_on = true;
+  return VX_OK;
+}
+
+int vx_profile_end(vx_kernel_stat* out, int32_t max, int32_t* count) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = false;
+  std::vector<vx_kernel_stat> acc;
+  int rc = VX_OK;
+  for (auto& r : g_prof) {
+    float ms = 0;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      set_error("profile: event timing failed");
+      rc = VX_EHIP;
+    }
+    size_t j = 0;
+    while (j < acc.size() && strncmp(acc[j].name, r.name, sizeof acc[j].name) != 0) j++;
+    if (j == acc.size()) {
+      vx_kernel_stat s;
+      memset(&s, 0, sizeof s);
+      snprintf(s.name, sizeof s.name, "%s", r.name);
+      acc.push_back(s);
+    }
+    acc[j].launches++;
+    acc[j].ms += ms;
+    acc[j].units += r.units;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  if (count) *count = (int32_t)acc.size();
+  for (size_t j = 0; j < acc.size() && (int32_t)j < max; j++) out[j] = acc[j];
+  return rc;
+}
+
+}  // extern "C"

@@ -36,6 +36,7 @@
 #include "common.hpp"
 #include "eval.hpp"
 #include "interval.hpp"
+#include "profile.hpp"
 #include "scan.hpp"
 
 namespace vx {
@@ -513,10 +514,12 @@ int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom
                        P[p].c_hi, E.packed, E.ttab, E.lens2, E.lens1);
     VX_CHECK_LAUNCH("k_tables");
     if (k == 1) {
+      const int ps = prof_start("k_leaf", (double)d * (double)nleaf, st);
       hipLaunchKernelGGL(k_leaf, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st, (const double*)E.packed,
                          (int64_t)0, (const int32_t*)nullptr, S->idx[0], nleaf, d, gleaf, lo + p * nleaf,
                          hi + p * nleaf, keep, p == 0 ? 1 : 0);
       VX_CHECK_LAUNCH("k_leaf");
+      prof_stop(ps, st);
       continue;
     }
     // stage 1
@@ -527,10 +530,12 @@ int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom
       const int64_t stride = nt * width;
       const SegPlan& sp = E.seg[0];
       dim3 grid((unsigned)sp.maxseg, (unsigned)((nt + 63) / 64));
+      const int ps = prof_start("k_stage1", (double)(ntup(k, d) - nt) * (double)S->n[0], st);
       hipLaunchKernelGGL(k_stage1<STAGE1_R>, grid, dim3(64), 0, st, (const double2*)E.packed,
                          (const int2*)E.ttab, (int)nt, d, m, S->idx[0], (const int4*)sp.seg,
                          (const int64_t*)sp.nseg, make_grid(dom, 0, S->level), E.rows[0], stride, width);
       VX_CHECK_LAUNCH("k_stage1");
+      prof_stop(ps, st);
     }
     // middle stages
     for (int l = 1; l + 1 < k; l++) {
@@ -540,16 +545,20 @@ int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom
       const int width = (l == k - 2) ? 3 : 2;
       const SegPlan& sp = E.seg[l];
       const int32_t* lens = (m_out == 2) ? E.lens2 : E.lens1;
+      const int ps = prof_start("k_narrow", (double)(ntup(m_in, d) - nch) * (double)S->n[l], st);
       hipLaunchKernelGGL(k_narrow, dim3((unsigned)sp.maxseg), dim3(64), 0, st, (const double*)E.rows[l - 1],
                          (int64_t)(ntup(m_in, d) * 2), lens, (int)nch, S->idx[l], (const int4*)sp.seg,
                          (const int64_t*)sp.nseg, make_grid(dom, l, S->level), E.rows[l], nch * width, width);
       VX_CHECK_LAUNCH("k_narrow");
+      prof_stop(ps, st);
     }
     // leaves
+    const int ps = prof_start("k_leaf", (double)d * (double)nleaf, st);
     hipLaunchKernelGGL(k_leaf, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st,
                        (const double*)E.rows[k - 2], (int64_t)(3 * (d + 1)), (const int32_t*)E.parent,
                        S->idx[k - 1], nleaf, d, gleaf, lo + p * nleaf, hi + p * nleaf, keep, p == 0 ? 1 : 0);
     VX_CHECK_LAUNCH("k_leaf");
+    prof_stop(ps, st);
   }
   return VX_OK;
 }

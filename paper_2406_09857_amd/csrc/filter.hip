@@ -18,6 +18,7 @@
 
 #include "common.hpp"
 #include "eval.hpp"
+#include "profile.hpp"
 #include "scan.hpp"
 
 namespace vx {
@@ -151,8 +152,19 @@ size_t filter_workspace_bytes(const vx_csf* S) {
   return A.off + 256;
 }
 
+static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts,
+                       void* ws, size_t ws_bytes, hipStream_t st);
+
 int filter_impl(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
                 size_t ws_bytes, hipStream_t st) {
+  const int ps = prof_start("filter_subdivide", (double)S->n[S->k - 1], st);
+  const int rc = filter_body(S, keep, kept, next, d_counts, ws, ws_bytes, st);
+  prof_stop(ps, st);
+  return rc;
+}
+
+static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts,
+                       void* ws, size_t ws_bytes, hipStream_t st) {
   const int k = S->k;
   Arena A;
   A.base = reinterpret_cast<char*>(ws);
