@@ -27,6 +27,7 @@ const char* get_error() { return g_error.c_str(); }
 
 static int check_poly(const vx_poly* P, int np, int k) {
   if (!P || np < 1) VX_FAIL(VX_EINVAL, "need at least one polynomial");
+  if (np > VX_MAXPOLY) VX_FAIL(VX_EINVAL, "at most %d polynomials per system", VX_MAXPOLY);
   for (int p = 0; p < np; p++) {
     if (P[p].k != k) VX_FAIL(VX_EINVAL, "polynomial %d has k=%d, the box set has k=%d", p, P[p].k, k);
     if (P[p].degree < 0 || P[p].degree > 400) VX_FAIL(VX_EINVAL, "polynomial %d: degree %d outside [0, 400]", p, P[p].degree);
@@ -182,8 +183,16 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
   if (depth < 0 || depth > 28) VX_FAIL(VX_EINVAL, "depth %d outside [0, 28]", depth);
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
   hipStream_t st = (hipStream_t)stream;
-  char* base = reinterpret_cast<char*>(ws);
-  const size_t total = ws_bytes / 256 * 256;
+  // coefficient tables once for the whole run, at the start of the workspace
+  const size_t qbytes = (prepared_bytes(P, np) + 255) / 256 * 256;
+  if (qbytes > ws_bytes) {
+    if (ws_needed) *ws_needed = qbytes + (1 << 20);
+    VX_FAIL(VX_ECAPACITY, "workspace too small");
+  }
+  Prepared Q;
+  if ((rc = prepare_polys(P, np, ws, qbytes, &Q, st))) return rc;
+  char* base = reinterpret_cast<char*>(ws) + qbytes;
+  const size_t total = (ws_bytes - qbytes) / 256 * 256;
 
   hipEvent_t ev[3];
   for (int i = 0; i < 3; i++) VX_HIP(hipEventCreate(&ev[i]));
@@ -229,16 +238,16 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
     int64_t kcap[VX_KMAX] = {1, 1, 1, 1};
     for (int l = 0; l < k; l++) kcap[l] = S.n[l] > 0 ? S.n[l] : 1;
     const size_t o_k = carve(csf_bytes(k, kcap));
-    const size_t ews = eval_workspace_bytes(P, np, &S);
+    const size_t ews = eval_level_bytes(P, np, &S);
     const size_t fws = filter_workspace_bytes(&S);
     const size_t scratch_bytes = ews > fws ? ews : fws;
     const size_t o_scr = carve(scratch_bytes);
     const size_t mid_bytes = moff;
     const size_t need = s_bytes + n_bytes + mid_bytes;
     if (need > total) {
-      if (ws_needed) *ws_needed = need + 256;
-      VX_FAIL(VX_ECAPACITY, "run_subdivision: level %d needs a %zu-byte workspace (%zu given)", level, need + 256,
-              ws_bytes);
+      if (ws_needed) *ws_needed = need + qbytes + 256;
+      VX_FAIL(VX_ECAPACITY, "run_subdivision: level %d needs a %zu-byte workspace (%zu given)", level,
+              need + qbytes + 256, ws_bytes);
     }
     // place: S at one end, next at the other, the middle right after S's end.
     char* mid_base;
@@ -261,7 +270,7 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
     if (!last) csf_place(&N, k, level + 1, ncap, next_base);
 
     VX_HIP(hipEventRecord(ev[0], st));
-    if ((rc = eval_level_impl(P, np, &S, dom, lo, hi, keep, scratch, scratch_bytes, st))) return rc;
+    if ((rc = eval_level_prepared(Q, &S, dom, lo, hi, keep, scratch, scratch_bytes, st, P))) return rc;
     VX_HIP(hipEventRecord(ev[1], st));
     if ((rc = filter_impl(&S, keep, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st))) return rc;
     VX_HIP(hipEventRecord(ev[2], st));

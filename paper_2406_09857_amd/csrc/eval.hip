@@ -33,6 +33,10 @@
 //   bytes (see k_leaf).
 #include <hip/hip_runtime.h>
 
+#include <string.h>
+
+#include <vector>
+
 #include "common.hpp"
 #include "eval.hpp"
 #include "interval.hpp"
@@ -180,50 +184,60 @@ __device__ __forceinline__ double wave_uniform(double x) {
   return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
 
+// Rows are read two ahead of their use so the load latency overlaps the R
+// interval steps of the current row.
 template <int R, int CLS>
 __device__ __forceinline__ void stage1_chain(const double2* __restrict__ P, int m, int d, int r0, int gdeg,
                                              int64_t gidx, const double (&u)[R], const double (&v)[R],
                                              const CellOps (&ops)[R], double (&nl)[R], double (&hh)[R]) {
-  int64_t rowoff = dbinom(r0 + m, m + 1), rowcnt = dbinom(r0 + m, m);
+  const double2 zero = make_double2(0.0, 0.0);
+  const int64_t off0 = dbinom(r0 + m, m + 1), cnt0 = dbinom(r0 + m, m);
+  const int64_t off1 = off0 + cnt0, cnt1 = cnt0 * (r0 + m + 1) / (r0 + 1);
+  int64_t off2 = off1 + cnt1, cnt2 = cnt1 * (r0 + m + 2) / (r0 + 2);
+  double2 c0 = (gdeg <= r0) ? P[off0 + gidx] : zero;
+  double2 c1 = (r0 + 1 <= d && gdeg <= r0 + 1) ? P[off1 + gidx] : zero;
   for (int r = r0; r <= d; r++) {
-    double cn = 0.0, ch = 0.0;
-    if (gdeg <= r) {
-      const double2 c = P[rowoff + gidx];
-      cn = c.x;
-      ch = c.y;
-    }
+    const double2 c = c0;
+    c0 = c1;
+    c1 = (r + 2 <= d && gdeg <= r + 2) ? P[off2 + gidx] : zero;
+    off2 += cnt2;
+    cnt2 = cnt2 * (r + m + 3) / (r + 3);
 #pragma unroll
     for (int j = 0; j < R; j++) {
-      if (CLS == CLS_POS) step_pos(nl[j], hh[j], u[j], v[j], cn, ch);
-      else if (CLS == CLS_NEG) step_neg(nl[j], hh[j], u[j], v[j], cn, ch);
-      else step_gen(nl[j], hh[j], ops[j], cn, ch);
+      if (CLS == CLS_POS) step_pos(nl[j], hh[j], u[j], v[j], c.x, c.y);
+      else if (CLS == CLS_NEG) step_neg(nl[j], hh[j], u[j], v[j], c.x, c.y);
+      else step_gen(nl[j], hh[j], ops[j], c.x, c.y);
     }
-    rowoff += rowcnt;
-    rowcnt = rowcnt * (r + m + 1) / (r + 1);
   }
 }
 
-template <int R>
-__global__ __launch_bounds__(64) void k_stage1(const double2* __restrict__ P, const int2* __restrict__ ttab,
-                                               int nt, int d, int m, const int32_t* __restrict__ labels0,
-                                               const int4* __restrict__ seg, const int64_t* __restrict__ nseg,
-                                               AxisGrid g, double* __restrict__ out, int64_t out_stride,
-                                               int out_width) {
-  round_up_mode();
-  if ((int64_t)blockIdx.x >= *nseg) return;
-  const int4 sg = seg[blockIdx.x];
-  const int begin = sg.y, cnt = sg.z, cls = sg.w;
-  const int lane = threadIdx.x;
-  const int64_t gidx = (int64_t)blockIdx.y * 64 + lane;
-  const bool active = gidx < nt;
-  int gdeg = d + 1, opos = 0;
-  if (active) {
-    const int2 tt = ttab[gidx];
-    gdeg = tt.x;
-    opos = tt.y;
-  }
-  const int r0 = __builtin_amdgcn_readfirstlane(gdeg);  // lane 0 holds the wave's smallest |t|
+// Per-polynomial tables and stage outputs, passed by value; blockIdx.z (or a
+// loop in the leaf kernel) selects the polynomial.
+constexpr int PMAX = 8;
 
+struct PolyTab {
+  const double2* packed;  // stage-1 coefficients (k >= 2) or the leaf row (k == 1)
+  const int2* ttab;       // graded tuple -> (|t|, O position)
+  const int32_t* lens2;   // O_2 chain lengths (k == 4)
+  int d;
+  int nt;                 // trailing tuples of stage 1: C(d+k-1, k-1)
+};
+
+struct RowSet {
+  double* rows[PMAX];
+  int64_t stride[PMAX];   // doubles per node row
+};
+
+struct PolySet {
+  int np;
+  PolyTab p[PMAX];
+};
+
+template <int R, int CLS>
+__device__ __forceinline__ void stage1_body(const PolyTab& pt, int m, const int32_t* __restrict__ labels0, int begin,
+                                            int cnt, const AxisGrid& g, int64_t gidx, bool active, int gdeg,
+                                            int opos, int r0, double* __restrict__ base, int64_t stride,
+                                            int out_width) {
   double u[R], v[R], nl[R], hh[R];
   CellOps ops[R];
 #pragma unroll
@@ -231,25 +245,24 @@ __global__ __launch_bounds__(64) void k_stage1(const double2* __restrict__ P, co
     const int32_t lab = labels0[begin + (j < cnt ? j : 0)];
     double cnl, chi;
     cell(g, lab, cnl, chi);
-    ops[j] = cell_ops(cnl, chi, cls);
+    ops[j] = cell_ops(cnl, chi, CLS);
     ops[j].u = wave_uniform(ops[j].u);
     ops[j].v = wave_uniform(ops[j].v);
-    ops[j].nu = wave_uniform(ops[j].nu);
-    ops[j].nv = wave_uniform(ops[j].nv);
+    if (CLS == CLS_STRADDLE) {
+      ops[j].nu = wave_uniform(ops[j].nu);
+      ops[j].nv = wave_uniform(ops[j].nv);
+    }
     u[j] = ops[j].u;
     v[j] = ops[j].v;
     nl[j] = 0.0;
     hh[j] = 0.0;
   }
-  if (cls == CLS_POS) stage1_chain<R, CLS_POS>(P, m, d, r0, gdeg, gidx, u, v, ops, nl, hh);
-  else if (cls == CLS_NEG) stage1_chain<R, CLS_NEG>(P, m, d, r0, gdeg, gidx, u, v, ops, nl, hh);
-  else stage1_chain<R, CLS_STRADDLE>(P, m, d, r0, gdeg, gidx, u, v, ops, nl, hh);
-
+  stage1_chain<R, CLS>(pt.packed, m, pt.d, r0, gdeg, gidx, u, v, ops, nl, hh);
   if (!active) return;
 #pragma unroll
   for (int j = 0; j < R; j++) {
     if (j < cnt) {
-      double* o = out + (int64_t)(begin + j) * out_stride + (int64_t)opos * out_width;
+      double* o = base + (int64_t)(begin + j) * stride + (int64_t)opos * out_width;
       o[0] = nl[j];
       o[1] = hh[j];
       if (out_width == 3) o[2] = nl[j];
@@ -257,41 +270,160 @@ __global__ __launch_bounds__(64) void k_stage1(const double2* __restrict__ P, co
   }
 }
 
+template <int R>
+__global__ __launch_bounds__(64) void k_stage1(PolySet ps, int m, const int32_t* __restrict__ labels0,
+                                               const int4* __restrict__ seg, const int64_t* __restrict__ nseg,
+                                               AxisGrid g, RowSet out, int out_width) {
+  round_up_mode();
+  if ((int64_t)blockIdx.x >= *nseg) return;
+  const PolyTab& pt = ps.p[blockIdx.z];
+  const int nt = pt.nt, d = pt.d;
+  if ((int64_t)blockIdx.y * 64 >= nt) return;
+  const int4 sg = seg[blockIdx.x];
+  const int begin = sg.y, cnt = sg.z, cls = sg.w;
+  const int lane = threadIdx.x;
+  const int64_t gidx = (int64_t)blockIdx.y * 64 + lane;
+  const bool active = gidx < nt;
+  int gdeg = d + 1, opos = 0;
+  if (active) {
+    const int2 tt = pt.ttab[gidx];
+    gdeg = tt.x;
+    opos = tt.y;
+  }
+  const int r0 = __builtin_amdgcn_readfirstlane(gdeg);  // lane 0 holds the wave's smallest |t|
+  double* base = out.rows[blockIdx.z];
+  const int64_t stride = out.stride[blockIdx.z];
+  if (cls == CLS_POS)
+    stage1_body<R, CLS_POS>(pt, m, labels0, begin, cnt, g, gidx, active, gdeg, opos, r0, base, stride, out_width);
+  else if (cls == CLS_NEG)
+    stage1_body<R, CLS_NEG>(pt, m, labels0, begin, cnt, g, gidx, active, gdeg, opos, r0, base, stride, out_width);
+  else  // cells containing 0 in their interior: rare, one node at a time
+    for (int j = 0; j < cnt; j++)
+      stage1_body<1, CLS_STRADDLE>(pt, m, labels0, begin + j, 1, g, gidx, active, gdeg, opos, r0, base, stride,
+                                   out_width);
+}
+
 // ---------------------------------------------------------------------------
 // Narrow stage.
 // ---------------------------------------------------------------------------
-template <int CLS>
-__device__ __forceinline__ void narrow_chains(const double2* __restrict__ C, const int32_t* __restrict__ lens,
-                                              int nchains, const CellOps& o, bool valid, double* __restrict__ out,
-                                              int out_width) {
-  int64_t pos = 0;
-  for (int j = 0; j < nchains; j++) {
-    const int L = lens[j];
-    double2 c = C[pos];
-    double nl = c.x, hh = c.y;
-    for (int i = 1; i <= L; i++) {
-      c = C[pos + i];
-      if (CLS == CLS_POS) step_pos(nl, hh, o.u, o.v, c.x, c.y);
-      else if (CLS == CLS_NEG) step_neg(nl, hh, o.u, o.v, c.x, c.y);
-      else step_gen(nl, hh, o, c.x, c.y);
+// The parent row is consumed chain by chain in groups of NARROW_GROUP
+// entries read with scalar loads.  A chain of n entries takes ceil(n/G)
+// groups; its first group starts G*ceil(n/G) - n entries early (inside the
+// previous chain, or in the slack before the first row) and those leading
+// entries are replaced by zeros in scalar registers.  Every chain starts from
+// J = 0, so each entry is one uniform interval step (0*I + c = c exactly, up
+// to the sign of a zero) and the only per-chain work is one store.  The next
+// group's loads are issued after the current group has arrived (a data
+// dependency through `after`), so they overlap the current group's steps;
+// scalar loads complete out of order, and waiting for the current group must
+// not also wait for the next one.
+constexpr int NARROW_GROUP = 8;
+
+constexpr int SPLIT_MAX = 16;
+
+struct ChainSplit {
+  int n;
+  int j0[SPLIT_MAX + 1];      // first chain of group g (j0[n] = number of chains)
+  int64_t p0[SPLIT_MAX + 1];  // first row entry of group g
+};
+
+// Zero that the compiler can only produce once `x` is available.
+__device__ __forceinline__ int64_t after(double x) {
+  int64_t z;
+  asm volatile("s_mov_b64 %0, 0" : "=s"(z) : "s"(x));
+  return z;
+}
+
+template <bool ORDER1>
+__device__ __forceinline__ int chain_len(const int32_t* __restrict__ lens, int j) {
+  return ORDER1 ? j : lens[j];
+}
+
+// Rows read by a narrow stage are never written during the launch; the
+// constant address space lets the compiler fetch the wave-uniform stream with
+// scalar loads.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(4))) const dvec2 crow_t;
+
+template <int CLS, bool ORDER1>
+__device__ __forceinline__ void narrow_run(const crow_t* __restrict__ C, const int32_t* __restrict__ lens, int j,
+                                           const int jend, int64_t cpos, const CellOps& o, bool valid,
+                                           double* __restrict__ out, int out_width) {
+  constexpr int G = NARROW_GROUP;
+  if (j >= jend) return;
+  int n = chain_len<ORDER1>(lens, j) + 1;  // entries of chain j
+  int ng = (n + G - 1) / G;                // its groups
+  int g = 0;                               // current group within the chain
+  int64_t gpos = cpos - (G * ng - n);      // first entry of the current group
+  dvec2 A[G];
+#pragma unroll
+  for (int e = 0; e < G; e++) A[e] = C[gpos + e];
+  double nl = 0.0, hh = 0.0;
+  while (true) {
+    // next group coordinates
+    int jn = j, gn = g + 1, nn = n, ngn = ng;
+    int64_t cposn = cpos, gposn = gpos + G;
+    if (gn == ng) {
+      jn = j + 1;
+      cposn = cpos + n;
+      gn = 0;
+      if (jn < jend) {
+        nn = chain_len<ORDER1>(lens, jn) + 1;
+        ngn = (nn + G - 1) / G;
+        gposn = cposn - (G * ngn - nn);
+      }
     }
-    pos += L + 1;
-    if (valid) {
-      double* w = out + (int64_t)j * out_width;
-      w[0] = nl;
-      w[1] = hh;
-      if (out_width == 3) w[2] = nl;
+    const bool more = jn < jend;
+    const int64_t z = after(A[0].x);
+    dvec2 B[G];
+    if (more) {
+#pragma unroll
+      for (int e = 0; e < G; e++) B[e] = C[gposn + z + e];
     }
+    if (g == 0) {
+      const int pad = G * ng - n;
+#pragma unroll
+      for (int e = 0; e < G; e++)
+        if (e < pad) A[e] = dvec2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int e = 0; e < G; e++) {
+      if (CLS == CLS_POS) step_pos(nl, hh, o.u, o.v, A[e].x, A[e].y);
+      else if (CLS == CLS_NEG) step_neg(nl, hh, o.u, o.v, A[e].x, A[e].y);
+      else step_gen(nl, hh, o, A[e].x, A[e].y);
+    }
+    if (g == ng - 1) {
+      if (valid) {
+        double* w = out + (int64_t)j * out_width;
+        w[0] = nl;
+        w[1] = hh;
+        if (out_width == 3) w[2] = nl;
+      }
+      nl = 0.0;
+      hh = 0.0;
+    }
+    if (!more) break;
+#pragma unroll
+    for (int e = 0; e < G; e++) A[e] = B[e];
+    j = jn; g = gn; n = nn; ng = ngn; cpos = cposn; gpos = gposn;
   }
 }
 
-__global__ __launch_bounds__(64) void k_narrow(const double* __restrict__ in_rows, int64_t in_stride,
-                                               const int32_t* __restrict__ lens, int nchains,
+struct SplitSet {
+  ChainSplit s[PMAX];
+};
+
+template <bool ORDER1>
+__global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet splits,
                                                const int32_t* __restrict__ labels, const int4* __restrict__ seg,
-                                               const int64_t* __restrict__ nseg, AxisGrid g,
-                                               double* __restrict__ out, int64_t out_stride, int out_width) {
+                                               const int64_t* __restrict__ nseg, AxisGrid g, RowSet out,
+                                               int out_width) {
   round_up_mode();
   if ((int64_t)blockIdx.x >= *nseg) return;
+  const int pz = blockIdx.z;
+  const ChainSplit& split = splits.s[pz];
+  const int gi = blockIdx.y;
+  if (gi >= split.n) return;
   const int4 sg = seg[blockIdx.x];
   const int parent = sg.x, begin = sg.y, cnt = sg.z, cls = sg.w;
   const int lane = threadIdx.x;
@@ -300,11 +432,14 @@ __global__ __launch_bounds__(64) void k_narrow(const double* __restrict__ in_row
   double cnl, chi;
   cell(g, labels[node], cnl, chi);
   const CellOps o = cell_ops(cnl, chi, cls);
-  const double2* C = reinterpret_cast<const double2*>(in_rows + (int64_t)parent * in_stride);
-  double* w = out + node * out_stride;
-  if (cls == CLS_POS) narrow_chains<CLS_POS>(C, lens, nchains, o, valid, w, out_width);
-  else if (cls == CLS_NEG) narrow_chains<CLS_NEG>(C, lens, nchains, o, valid, w, out_width);
-  else narrow_chains<CLS_STRADDLE>(C, lens, nchains, o, valid, w, out_width);
+  const crow_t* C = (const crow_t*)(in.rows[pz] + (int64_t)parent * in.stride[pz]);
+  double* w = out.rows[pz] + node * out.stride[pz];
+  const int32_t* lens = ps.p[pz].lens2;
+  const int j0 = split.j0[gi], j1 = split.j0[gi + 1];
+  const int64_t p0 = split.p0[gi];
+  if (cls == CLS_POS) narrow_run<CLS_POS, ORDER1>(C, lens, j0, j1, p0, o, valid, w, out_width);
+  else if (cls == CLS_NEG) narrow_run<CLS_NEG, ORDER1>(C, lens, j0, j1, p0, o, valid, w, out_width);
+  else narrow_run<CLS_STRADDLE, ORDER1>(C, lens, j0, j1, p0, o, valid, w, out_width);
 }
 
 // ---------------------------------------------------------------------------
@@ -319,46 +454,67 @@ __global__ __launch_bounds__(64) void k_narrow(const double* __restrict__ in_row
 // ---------------------------------------------------------------------------
 typedef double dpair_a8 __attribute__((ext_vector_type(2), aligned(8)));
 
-__global__ __launch_bounds__(256) void k_leaf(const double* __restrict__ rows, int64_t row_stride,
-                                              const int32_t* __restrict__ parent_of,
-                                              const int32_t* __restrict__ labels, int64_t nleaf, int d,
-                                              AxisGrid g, double* __restrict__ lo_out, double* __restrict__ hi_out,
+// One polynomial's leaf chain for one box; returns (nlo, hi).
+__device__ __forceinline__ void leaf_chain(const double* __restrict__ R, int d, int cls, double cnl, double chi,
+                                           double& nl, double& hh) {
+  const CellOps o = cell_ops(cnl, chi, cls);
+  if (cls == CLS_STRADDLE) {
+    nl = R[0];
+    hh = R[1];
+    for (int j = 1; j <= d; j++) step_gen(nl, hh, o, R[3 * j], R[3 * j + 1]);
+    return;
+  }
+  const int sh = cls == CLS_NEG ? 1 : 0;
+  // Entry j (exponent d - j) is read at R + 3j, one double later when the
+  // lane is mirrored and d - j is odd.  pe serves even j, po odd j.
+  const double* pe = R + ((d & 1) ? sh : 0);
+  const double* po = R + 3 + (((d - 1) & 1) ? sh : 0);
+  auto at = [&](int j) -> dpair_a8 {
+    return (j & 1) ? *reinterpret_cast<const dpair_a8*>(po + 3 * (j - 1))
+                   : *reinterpret_cast<const dpair_a8*>(pe + 3 * j);
+  };
+  dpair_a8 c = at(0);
+  nl = c.x;
+  hh = c.y;
+  // four entries in flight (rows are padded so reads past entry d stay in bounds)
+  dpair_a8 q0 = at(1), q1 = at(2), q2 = at(3), q3 = at(4);
+  int j = 1;
+  for (; j + 3 <= d; j += 4) {
+    step_pos(nl, hh, o.u, o.v, q0.x, q0.y);
+    q0 = *reinterpret_cast<const dpair_a8*>(po + 3 * (j + 3));  // entry j+4 (odd)
+    step_pos(nl, hh, o.u, o.v, q1.x, q1.y);
+    q1 = *reinterpret_cast<const dpair_a8*>(pe + 3 * (j + 5));  // entry j+5 (even)
+    step_pos(nl, hh, o.u, o.v, q2.x, q2.y);
+    q2 = *reinterpret_cast<const dpair_a8*>(po + 3 * (j + 5));  // entry j+6 (odd)
+    step_pos(nl, hh, o.u, o.v, q3.x, q3.y);
+    q3 = *reinterpret_cast<const dpair_a8*>(pe + 3 * (j + 7));  // entry j+7 (even)
+  }
+  if (j <= d) step_pos(nl, hh, o.u, o.v, q0.x, q0.y);
+  if (j + 1 <= d) step_pos(nl, hh, o.u, o.v, q1.x, q1.y);
+  if (j + 2 <= d) step_pos(nl, hh, o.u, o.v, q2.x, q2.y);
+}
+
+__global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int32_t* __restrict__ parent_of,
+                                              const int32_t* __restrict__ labels, int64_t nleaf, AxisGrid g,
+                                              double* __restrict__ lo_out, double* __restrict__ hi_out,
                                               uint8_t* __restrict__ keep, int first) {
   round_up_mode();
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nleaf) return;
-  const int64_t p = parent_of ? parent_of[b] : 0;
+  const int64_t par = parent_of ? parent_of[b] : 0;
   double cnl, chi;
   cell(g, labels[b], cnl, chi);
   const int cls = cell_class(cnl, chi);
-  const double* R = rows + p * row_stride;
-  double nl, hh;
-  if (cls == CLS_STRADDLE) {
-    const CellOps o = cell_ops(cnl, chi, cls);
-    nl = R[0];
-    hh = R[1];
-    for (int j = 1; j <= d; j++) step_gen(nl, hh, o, R[3 * j], R[3 * j + 1]);
-  } else {
-    const CellOps o = cell_ops(cnl, chi, cls);
-    const int sh = cls == CLS_NEG ? 1 : 0;
-    // entry j holds exponent e = d - j; mirrored lanes read odd exponents swapped.
-    dpair_a8 c = *reinterpret_cast<const dpair_a8*>(R + (((d & 1) ? sh : 0)));
-    nl = c.x;
-    hh = c.y;
-    for (int j = 1; j <= d; j++) {
-      const int off = 3 * j + (((d - j) & 1) ? sh : 0);
-      c = *reinterpret_cast<const dpair_a8*>(R + off);
-      step_pos(nl, hh, o.u, o.v, c.x, c.y);
-    }
+  bool excl = false;
+  for (int p = 0; p < ps.np; p++) {
+    double nl, hh;
+    leaf_chain(rows.rows[p] + par * rows.stride[p], ps.p[p].d, cls, cnl, chi, nl, hh);
+    const double lo = -opaque(nl);
+    lo_out[p * nleaf + b] = lo;
+    hi_out[p * nleaf + b] = hh;
+    excl = excl || (lo > 0.0) || (hh < 0.0);
   }
-  const double lo = -opaque(nl);
-  lo_out[b] = lo;
-  hi_out[b] = hh;
-  if (keep) {
-    const bool excl = (lo > 0.0) || (hh < 0.0);
-    const uint8_t kp = excl ? 0 : 1;
-    keep[b] = first ? kp : (uint8_t)(keep[b] & kp);
-  }
+  if (keep) keep[b] = first ? (excl ? 0 : 1) : (excl ? 0 : keep[b]);
 }
 
 // Parent (depth k-1 node) of every leaf: binary search in ptr.
@@ -392,6 +548,8 @@ static AxisGrid make_grid(const double* dom, int axis, int level) {
   return g;
 }
 
+constexpr int64_t ROW_PAD = 16;  // entries of slack before and after every rows buffer
+
 struct SegPlan {
   int4* seg = nullptr;
   int64_t* nseg = nullptr;
@@ -419,10 +577,6 @@ static void plan_segments(Arena& A, SegPlan& sp, int64_t nparent, int64_t nchild
 static int build_segments(SegPlan& sp, const int32_t* ptr, const int32_t* labels, const AxisGrid& g,
                           hipStream_t st) {
   const int64_t np = sp.nparent;
-  if (np == 0) {
-    VX_HIP(hipMemsetAsync(sp.nseg, 0, sizeof(int64_t), st));
-    return VX_OK;
-  }
   const unsigned blocks = (unsigned)((np + 255) / 256);
   hipLaunchKernelGGL(k_seg_count, dim3(blocks), dim3(256), 0, st, ptr, np, sp.nchild, labels, g, sp.Z, sp.cnt,
                      sp.bounds);
@@ -435,40 +589,110 @@ static int build_segments(SegPlan& sp, const int32_t* ptr, const int32_t* labels
   return VX_OK;
 }
 
-constexpr int STAGE1_R = 8;
+constexpr int64_t NARROW_TARGET_WAVES = 8192;
+
+// Chain lengths of O_m (m = 1 or 2) in order, host side.
+static std::vector<int> o_lengths(int m, int d) {
+  std::vector<int> L;
+  if (m == 1) {
+    for (int j = 0; j <= d; j++) L.push_back(j);
+  } else {
+    // O_2 = for e_k = d..0: for e = d - e_k .. 0: (e, e_k); length d - e - e_k
+    for (int ek = d; ek >= 0; ek--)
+      for (int e = d - ek; e >= 0; e--) L.push_back(d - e - ek);
+  }
+  return L;
+}
+
+// Split the chains of O_m into at most `groups` contiguous runs of about
+// equal row entries (entries of chain j = length + 1).
+static ChainSplit chain_split(int m, int d, int groups) {
+  const std::vector<int> L = o_lengths(m, d);
+  int64_t total = 0;
+  for (int v : L) total += v + 1;
+  ChainSplit cs;
+  memset(&cs, 0, sizeof cs);
+  int64_t acc = 0;
+  int g = 1;
+  for (size_t j = 0; j < L.size() && g < groups; j++) {
+    acc += L[j] + 1;
+    if (acc * groups >= total * g && j + 1 < L.size()) {
+      cs.j0[g] = (int)j + 1;
+      cs.p0[g] = acc;
+      g++;
+    }
+  }
+  cs.n = g;
+  cs.j0[g] = (int)L.size();
+  cs.p0[g] = total;
+  return cs;
+}
+
+static void plan_prepared(Arena& A, Prepared& Q, const vx_poly* P, int np) {
+  const int k = P[0].k;
+  Q.k = k;
+  Q.np = np;
+  for (int p = 0; p < np; p++) {
+    const int d = P[p].degree;
+    Q.d[p] = d;
+    Q.dmax = d > Q.dmax ? d : Q.dmax;
+    Q.packed[p] = A.take<double>((k == 1 ? 3 * (int64_t)(d + 1) : 2 * ntup(k, d)) + 2 * ROW_PAD * 3);
+    Q.ttab[p] = A.take<int2>(k >= 2 ? ntup(k - 1, d) : 1);
+    Q.lens2[p] = A.take<int32_t>(k == 4 ? ntup(2, d) : 1);
+    Q.lens1[p] = A.take<int32_t>(d + 1);
+  }
+}
+
+size_t prepared_bytes(const vx_poly* P, int np) {
+  Arena A;
+  Prepared Q;
+  plan_prepared(A, Q, P, np);
+  return A.off + 256;
+}
+
+int prepare_polys(const vx_poly* P, int np, void* ws, size_t ws_bytes, Prepared* out, hipStream_t st) {
+  Arena A;
+  A.base = reinterpret_cast<char*>(ws);
+  A.size = ws_bytes;
+  plan_prepared(A, *out, P, np);
+  if (A.overflow) VX_FAIL(VX_ECAPACITY, "workspace too small for the coefficient tables");
+  const int k = P[0].k;
+  for (int p = 0; p < np; p++) {
+    int64_t cube = 1;
+    for (int i = 0; i < k; i++) cube *= P[p].side;
+    hipLaunchKernelGGL(k_tables, dim3((unsigned)((cube + 255) / 256)), dim3(256), 0, st, k, P[p].degree, P[p].side,
+                       P[p].c_lo, P[p].c_hi, out->packed[p], out->ttab[p], out->lens2[p], out->lens1[p]);
+    VX_CHECK_LAUNCH("k_tables");
+  }
+  return VX_OK;
+}
 
 struct EvalPlan {
-  int k = 0, dmax = 0;
-  double* packed = nullptr;
-  int2* ttab = nullptr;
-  int32_t* lens2 = nullptr;
-  int32_t* lens1 = nullptr;
-  double* rows[VX_KMAX] = {nullptr, nullptr, nullptr, nullptr};  // output rows of stage l (l = 0..k-2)
+  int k = 0;
+  double* rows[VX_KMAX][VX_MAXPOLY] = {};  // output rows of stage l for polynomial p
   int32_t* parent = nullptr;
   SegPlan seg[VX_KMAX];
+  int R = 8;
 };
 
-// Workspace layout of one interval_eval_level call (measure with A.base == nullptr).
+static int stage1_blocking(int64_t n0) { return n0 <= 4 ? 1 : n0 <= 16 ? 2 : n0 <= 64 ? 4 : 8; }
+
+// Level workspace (measure with A.base == nullptr).
 static void plan_eval(Arena& A, EvalPlan& E, const vx_poly* P, int np, const vx_csf* S) {
   const int k = S->k;
-  int dmax = 0;
-  for (int p = 0; p < np; p++) dmax = P[p].degree > dmax ? P[p].degree : dmax;
   E.k = k;
-  E.dmax = dmax;
-  const int64_t nt_k = ntup(k, dmax);
-  E.packed = A.take<double>(k == 1 ? 3 * (int64_t)(dmax + 1) : 2 * nt_k);
-  E.ttab = A.take<int2>(k >= 2 ? ntup(k - 1, dmax) : 1);
-  E.lens2 = A.take<int32_t>(k == 4 ? ntup(2, dmax) : 1);
-  E.lens1 = A.take<int32_t>(dmax + 1);
   for (int l = 0; l + 1 < k; l++) {
     const int m = k - l - 1;  // dimension of the trailing tuples left after depth l+1
     const int width = (l == k - 2) ? 3 : 2;
-    E.rows[l] = A.take<double>((size_t)S->n[l] * ntup(m, dmax) * width);
+    for (int p = 0; p < np; p++)
+      E.rows[l][p] = A.take<double>((size_t)S->n[l] * ntup(m, P[p].degree) * width + 4 * ROW_PAD * width) +
+                     2 * ROW_PAD * width;
   }
   if (k >= 2) E.parent = A.take<int32_t>(S->n[k - 1] > 0 ? S->n[k - 1] : 1);
+  E.R = stage1_blocking(S->n[0]);
   for (int l = 0; l + 1 < k; l++) {
     const int64_t nparent = l == 0 ? 1 : S->n[l - 1];
-    plan_segments(A, E.seg[l], nparent, S->n[l], l == 0 ? STAGE1_R : 64);
+    plan_segments(A, E.seg[l], nparent, S->n[l], l == 0 ? E.R : 64);
   }
 }
 
@@ -476,11 +700,128 @@ size_t eval_workspace_bytes(const vx_poly* P, int np, const vx_csf* S) {
   Arena A;
   EvalPlan E;
   plan_eval(A, E, P, np, S);
+  return A.off + prepared_bytes(P, np) + 512;
+}
+
+size_t eval_level_bytes(const vx_poly* P, int np, const vx_csf* S) {
+  Arena A;
+  EvalPlan E;
+  plan_eval(A, E, P, np, S);
   return A.off + 256;
 }
 
-int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi,
-                    uint8_t* keep, void* ws, size_t ws_bytes, hipStream_t st) {
+static int launch_stage1(const Prepared& Q, int p0, int pn, const vx_csf* S, const double* dom, EvalPlan& E,
+                         hipStream_t st) {
+  const int k = S->k, m = k - 1;
+  PolySet ps;
+  memset(&ps, 0, sizeof ps);
+  RowSet rs;
+  memset(&rs, 0, sizeof rs);
+  ps.np = pn;
+  int nt_max = 0;
+  double units = 0;
+  const int width = (k == 2) ? 3 : 2;
+  for (int i = 0; i < pn; i++) {
+    const int p = p0 + i, d = Q.d[p];
+    ps.p[i].packed = reinterpret_cast<const double2*>(Q.packed[p]);
+    ps.p[i].ttab = Q.ttab[p];
+    ps.p[i].lens2 = Q.lens2[p];
+    ps.p[i].d = d;
+    ps.p[i].nt = (int)ntup(m, d);
+    nt_max = ps.p[i].nt > nt_max ? ps.p[i].nt : nt_max;
+    rs.rows[i] = E.rows[0][p];
+    rs.stride[i] = ntup(m, d) * width;
+    units += (double)(ntup(k, d) - ntup(m, d)) * (double)S->n[0];
+  }
+  const SegPlan& sp = E.seg[0];
+  dim3 grid((unsigned)sp.maxseg, (unsigned)((nt_max + 63) / 64), (unsigned)pn);
+  const AxisGrid g = make_grid(dom, 0, S->level);
+  const int pr = prof_start("k_stage1", units, st);
+  switch (E.R) {
+    case 1: hipLaunchKernelGGL(k_stage1<1>, grid, dim3(64), 0, st, ps, m, S->idx[0], (const int4*)sp.seg, (const int64_t*)sp.nseg, g, rs, width); break;
+    case 2: hipLaunchKernelGGL(k_stage1<2>, grid, dim3(64), 0, st, ps, m, S->idx[0], (const int4*)sp.seg, (const int64_t*)sp.nseg, g, rs, width); break;
+    case 4: hipLaunchKernelGGL(k_stage1<4>, grid, dim3(64), 0, st, ps, m, S->idx[0], (const int4*)sp.seg, (const int64_t*)sp.nseg, g, rs, width); break;
+    default: hipLaunchKernelGGL(k_stage1<8>, grid, dim3(64), 0, st, ps, m, S->idx[0], (const int4*)sp.seg, (const int64_t*)sp.nseg, g, rs, width); break;
+  }
+  VX_CHECK_LAUNCH("k_stage1");
+  prof_stop(pr, st);
+  return VX_OK;
+}
+
+static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf* S, const double* dom, EvalPlan& E,
+                         hipStream_t st) {
+  const int k = S->k;
+  const int m_in = k - l, m_out = k - l - 1;
+  const int width = (l == k - 2) ? 3 : 2;
+  PolySet ps;
+  memset(&ps, 0, sizeof ps);
+  RowSet in, out;
+  memset(&in, 0, sizeof in);
+  memset(&out, 0, sizeof out);
+  SplitSet ss;
+  memset(&ss, 0, sizeof ss);
+  const int64_t est_waves = (S->n[l] + 63) / 64 + S->n[l - 1];
+  int groups = (int)((NARROW_TARGET_WAVES + est_waves - 1) / est_waves);
+  groups = groups < 1 ? 1 : (groups > SPLIT_MAX ? SPLIT_MAX : groups);
+  int gmax = 1;
+  double units = 0;
+  ps.np = pn;
+  for (int i = 0; i < pn; i++) {
+    const int p = p0 + i, d = Q.d[p];
+    ps.p[i].lens2 = Q.lens2[p];
+    ps.p[i].d = d;
+    in.rows[i] = E.rows[l - 1][p];
+    in.stride[i] = ntup(m_in, d) * 2;
+    out.rows[i] = E.rows[l][p];
+    out.stride[i] = ntup(m_out, d) * width;
+    ss.s[i] = chain_split(m_out, d, groups);
+    gmax = ss.s[i].n > gmax ? ss.s[i].n : gmax;
+    units += (double)(ntup(m_in, d) - ntup(m_out, d)) * (double)S->n[l];
+  }
+  const SegPlan& sp = E.seg[l];
+  dim3 grid((unsigned)sp.maxseg, (unsigned)gmax, (unsigned)pn);
+  const AxisGrid g = make_grid(dom, l, S->level);
+  const int pr = prof_start("k_narrow", units, st);
+  if (m_out == 1)
+    hipLaunchKernelGGL(k_narrow<true>, grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
+                       (const int64_t*)sp.nseg, g, out, width);
+  else
+    hipLaunchKernelGGL(k_narrow<false>, grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
+                       (const int64_t*)sp.nseg, g, out, width);
+  VX_CHECK_LAUNCH("k_narrow");
+  prof_stop(pr, st);
+  return VX_OK;
+}
+
+static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const double* dom, EvalPlan& E,
+                       double* lo, double* hi, uint8_t* keep, hipStream_t st) {
+  const int k = S->k;
+  const int64_t nleaf = S->n[k - 1];
+  PolySet ps;
+  memset(&ps, 0, sizeof ps);
+  RowSet rs;
+  memset(&rs, 0, sizeof rs);
+  ps.np = pn;
+  double units = 0;
+  for (int i = 0; i < pn; i++) {
+    const int p = p0 + i, d = Q.d[p];
+    ps.p[i].d = d;
+    rs.rows[i] = k == 1 ? Q.packed[p] : E.rows[k - 2][p];
+    rs.stride[i] = k == 1 ? 0 : 3 * (int64_t)(d + 1);
+    units += (double)d * (double)nleaf;
+  }
+  const int pr = prof_start("k_leaf", units, st);
+  hipLaunchKernelGGL(k_leaf, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st, ps, rs,
+                     k == 1 ? (const int32_t*)nullptr : (const int32_t*)E.parent, S->idx[k - 1], nleaf,
+                     make_grid(dom, k - 1, S->level), lo + (int64_t)p0 * nleaf, hi + (int64_t)p0 * nleaf, keep,
+                     p0 == 0 ? 1 : 0);
+  VX_CHECK_LAUNCH("k_leaf");
+  prof_stop(pr, st);
+  return VX_OK;
+}
+
+int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
+                        void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P) {
   const int k = S->k;
   const int64_t nleaf = S->n[k - 1];
   if (nleaf == 0) return VX_OK;
@@ -488,79 +829,39 @@ int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom
   A.base = reinterpret_cast<char*>(ws);
   A.size = ws_bytes;
   EvalPlan E;
-  plan_eval(A, E, P, np, S);
+  plan_eval(A, E, P, Q.np, S);
   if (A.overflow)
     VX_FAIL(VX_ECAPACITY, "interval_eval_level: workspace of %zu bytes is too small (%zu needed)", ws_bytes,
             A.off + 256);
-
-  // Segments (depend on the CSF only).
+  int rc;
   for (int l = 0; l + 1 < k; l++) {
     const AxisGrid g = make_grid(dom, l, S->level);
-    int rc = build_segments(E.seg[l], l == 0 ? nullptr : S->ptr[l - 1], S->idx[l], g, st);
-    if (rc) return rc;
+    if ((rc = build_segments(E.seg[l], l == 0 ? nullptr : S->ptr[l - 1], S->idx[l], g, st))) return rc;
   }
   if (k >= 2) {
     hipLaunchKernelGGL(k_parent_of, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st, S->ptr[k - 2],
                        S->n[k - 2], nleaf, E.parent);
     VX_CHECK_LAUNCH("k_parent_of");
   }
-  const AxisGrid gleaf = make_grid(dom, k - 1, S->level);
-
-  for (int p = 0; p < np; p++) {
-    const int d = P[p].degree, side = P[p].side;
-    int64_t cube = 1;
-    for (int i = 0; i < k; i++) cube *= side;
-    hipLaunchKernelGGL(k_tables, dim3((unsigned)((cube + 255) / 256)), dim3(256), 0, st, k, d, side, P[p].c_lo,
-                       P[p].c_hi, E.packed, E.ttab, E.lens2, E.lens1);
-    VX_CHECK_LAUNCH("k_tables");
-    if (k == 1) {
-      const int ps = prof_start("k_leaf", (double)d * (double)nleaf, st);
-      hipLaunchKernelGGL(k_leaf, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st, (const double*)E.packed,
-                         (int64_t)0, (const int32_t*)nullptr, S->idx[0], nleaf, d, gleaf, lo + p * nleaf,
-                         hi + p * nleaf, keep, p == 0 ? 1 : 0);
-      VX_CHECK_LAUNCH("k_leaf");
-      prof_stop(ps, st);
-      continue;
-    }
-    // stage 1
-    {
-      const int m = k - 1;
-      const int64_t nt = ntup(m, d);
-      const int width = (k == 2) ? 3 : 2;
-      const int64_t stride = nt * width;
-      const SegPlan& sp = E.seg[0];
-      dim3 grid((unsigned)sp.maxseg, (unsigned)((nt + 63) / 64));
-      const int ps = prof_start("k_stage1", (double)(ntup(k, d) - nt) * (double)S->n[0], st);
-      hipLaunchKernelGGL(k_stage1<STAGE1_R>, grid, dim3(64), 0, st, (const double2*)E.packed,
-                         (const int2*)E.ttab, (int)nt, d, m, S->idx[0], (const int4*)sp.seg,
-                         (const int64_t*)sp.nseg, make_grid(dom, 0, S->level), E.rows[0], stride, width);
-      VX_CHECK_LAUNCH("k_stage1");
-      prof_stop(ps, st);
-    }
-    // middle stages
-    for (int l = 1; l + 1 < k; l++) {
-      const int m_in = k - l;        // tuple dimension of the parent rows
-      const int m_out = k - l - 1;   // chains of this stage
-      const int64_t nch = ntup(m_out, d);
-      const int width = (l == k - 2) ? 3 : 2;
-      const SegPlan& sp = E.seg[l];
-      const int32_t* lens = (m_out == 2) ? E.lens2 : E.lens1;
-      const int ps = prof_start("k_narrow", (double)(ntup(m_in, d) - nch) * (double)S->n[l], st);
-      hipLaunchKernelGGL(k_narrow, dim3((unsigned)sp.maxseg), dim3(64), 0, st, (const double*)E.rows[l - 1],
-                         (int64_t)(ntup(m_in, d) * 2), lens, (int)nch, S->idx[l], (const int4*)sp.seg,
-                         (const int64_t*)sp.nseg, make_grid(dom, l, S->level), E.rows[l], nch * width, width);
-      VX_CHECK_LAUNCH("k_narrow");
-      prof_stop(ps, st);
-    }
-    // leaves
-    const int ps = prof_start("k_leaf", (double)d * (double)nleaf, st);
-    hipLaunchKernelGGL(k_leaf, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st,
-                       (const double*)E.rows[k - 2], (int64_t)(3 * (d + 1)), (const int32_t*)E.parent,
-                       S->idx[k - 1], nleaf, d, gleaf, lo + p * nleaf, hi + p * nleaf, keep, p == 0 ? 1 : 0);
-    VX_CHECK_LAUNCH("k_leaf");
-    prof_stop(ps, st);
+  for (int p0 = 0; p0 < Q.np; p0 += PMAX) {
+    const int pn = Q.np - p0 < PMAX ? Q.np - p0 : PMAX;
+    if (k >= 2 && (rc = launch_stage1(Q, p0, pn, S, dom, E, st))) return rc;
+    for (int l = 1; l + 1 < k; l++)
+      if ((rc = launch_narrow(Q, p0, pn, l, S, dom, E, st))) return rc;
+    if ((rc = launch_leaf(Q, p0, pn, S, dom, E, lo, hi, keep, st))) return rc;
   }
   return VX_OK;
+}
+
+int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi,
+                    uint8_t* keep, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (S->n[S->k - 1] == 0) return VX_OK;
+  const size_t qb = prepared_bytes(P, np);
+  if (qb > ws_bytes) VX_FAIL(VX_ECAPACITY, "interval_eval_level: workspace too small");
+  Prepared Q;
+  int rc;
+  if ((rc = prepare_polys(P, np, ws, qb, &Q, st))) return rc;
+  return eval_level_prepared(Q, S, dom, lo, hi, keep, reinterpret_cast<char*>(ws) + qb, ws_bytes - qb, st, P);
 }
 
 }  // namespace vx
