@@ -73,12 +73,29 @@ __device__ inline int64_t o_pos(const int* t, int m, int d) {
   return pos;
 }
 
+// Padded O_2 layout (k = 3, input rows of the middle stage): chain j of O_1
+// (exponent e3 = d - j, j+1 entries) is preceded by zero entries up to a
+// multiple of 8 entries, so it occupies the 8-entry groups [c(j), c(j+1)),
+// c(j) = sum_{i=1..j} ceil(i/8).  Entry (e2, e3) sits at 8 c(j+1) - 1 - e2.
+constexpr int PADG = 8;
+
+__host__ __device__ inline int64_t padded_groups(int64_t j) {
+  const int64_t q = j / PADG, r = j % PADG;
+  return (PADG / 2) * q * (q + 1) + (q + 1) * r;
+}
+
+__host__ __device__ inline int64_t padded_entries(int d) { return PADG * padded_groups(d + 1); }
+
+__host__ __device__ inline int64_t padded_npad(int d) {
+  return padded_entries(d) - (int64_t)(d + 1) * (d + 2) / 2;
+}
+
 // ---------------------------------------------------------------------------
 // Tables and coefficient packing (one thread per cube entry).
 // ---------------------------------------------------------------------------
 __global__ void k_tables(int k, int d, int side, const double* __restrict__ clo, const double* __restrict__ chi,
                          double* __restrict__ packed, int2* __restrict__ ttab, int32_t* __restrict__ lens2,
-                         int32_t* __restrict__ lens1) {
+                         int32_t* __restrict__ lens1, int32_t* __restrict__ padlist) {
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t total = 1;
   for (int i = 0; i < k; i++) total *= side;
@@ -105,7 +122,20 @@ __global__ void k_tables(int k, int d, int side, const double* __restrict__ clo,
   const int64_t at = dbinom(r + m, m + 1) + g;
   packed[2 * at + 0] = -lo;
   packed[2 * at + 1] = hi;
-  if (e[0] == 0) ttab[g] = make_int2(tdeg, (int)o_pos(t, m, d));
+  if (e[0] == 0) {
+    if (k == 3) {
+      const int j = d - e[2];
+      ttab[g] = make_int2(tdeg, (int)(PADG * padded_groups(j + 1) - 1 - e[1]));
+      if (e[1] == 0) {  // one thread per chain lists the chain's padding slots
+        const int64_t start = PADG * padded_groups(j);
+        const int64_t pad = PADG * padded_groups(j + 1) - start - (j + 1);
+        const int64_t at0 = start - (int64_t)j * (j + 1) / 2;
+        for (int64_t q2 = 0; q2 < pad; q2++) padlist[at0 + q2] = (int32_t)(start + q2);
+      }
+    } else {
+      ttab[g] = make_int2(tdeg, (int)o_pos(t, m, d));
+    }
+  }
   // chain-length tables of the narrow stages: O_2 (k = 4, stage 2) and O_1.
   if (k == 4 && e[0] == 0 && e[1] == 0) lens2[o_pos(e + 2, 2, d)] = d - (e[2] + e[3]);
   if (k >= 3) {
@@ -216,11 +246,13 @@ __device__ __forceinline__ void stage1_chain(const double2* __restrict__ P, int 
 constexpr int PMAX = 8;
 
 struct PolyTab {
-  const double2* packed;  // stage-1 coefficients (k >= 2) or the leaf row (k == 1)
-  const int2* ttab;       // graded tuple -> (|t|, O position)
-  const int32_t* lens2;   // O_2 chain lengths (k == 4)
+  const double2* packed;   // stage-1 coefficients (k >= 2) or the leaf row (k == 1)
+  const int2* ttab;        // graded tuple -> (|t|, output position)
+  const int32_t* lens2;    // O_2 chain lengths (k == 4)
+  const int32_t* padlist;  // zero slots of the padded stage-1 rows (k == 3)
   int d;
-  int nt;                 // trailing tuples of stage 1: C(d+k-1, k-1)
+  int nt;                  // trailing tuples of stage 1: C(d+k-1, k-1)
+  int npad;
 };
 
 struct RowSet {
@@ -278,7 +310,21 @@ __global__ __launch_bounds__(64) void k_stage1(PolySet ps, int m, const int32_t*
   if ((int64_t)blockIdx.x >= *nseg) return;
   const PolyTab& pt = ps.p[blockIdx.z];
   const int nt = pt.nt, d = pt.d;
-  if ((int64_t)blockIdx.y * 64 >= nt) return;
+  const int ntw = (nt + 63) / 64;
+  if ((int)blockIdx.y > ntw) return;
+  if ((int)blockIdx.y == ntw) {  // zero the padding slots of this segment's rows
+    if (pt.npad == 0) return;
+    const int4 sg = seg[blockIdx.x];
+    double* base = out.rows[blockIdx.z];
+    const int64_t stride = out.stride[blockIdx.z];
+    for (int j = 0; j < sg.z; j++)
+      for (int i = threadIdx.x; i < pt.npad; i += 64) {
+        double* o = base + (int64_t)(sg.y + j) * stride + (int64_t)pt.padlist[i] * out_width;
+        o[0] = 0.0;
+        o[1] = 0.0;
+      }
+    return;
+  }
   const int4 sg = seg[blockIdx.x];
   const int begin = sg.y, cnt = sg.z, cls = sg.w;
   const int lane = threadIdx.x;
@@ -409,11 +455,76 @@ __device__ __forceinline__ void narrow_run(const crow_t* __restrict__ C, const i
   }
 }
 
+// Middle stage on padded rows (k = 3): every group of 8 entries belongs to one
+// chain, chains end on group boundaries, and the leading zeros replace the
+// masking; two register buffers alternate so no copies are needed.
+template <int CLS>
+__device__ __forceinline__ void narrow_padded(const crow_t* __restrict__ C, int j, const int jend, const CellOps& o,
+                                              bool valid, double* __restrict__ out, int out_width) {
+  constexpr int G = PADG;
+  if (j >= jend) return;
+  // 32-bit group counters: the scalar unit compares 32-bit values only
+  int g = (int)padded_groups(j);
+  int gend = (int)padded_groups(j + 1);
+  const int glast = (int)padded_groups(jend);
+  dvec2 A[G], B[G];
+#pragma unroll
+  for (int e = 0; e < G; e++) A[e] = C[(int64_t)g * G + e];
+  double nl = 0.0, hh = 0.0;
+  auto steps = [&](const dvec2 (&X)[G]) {
+#pragma unroll
+    for (int e = 0; e < G; e++) {
+      if (CLS == CLS_POS) step_pos(nl, hh, o.u, o.v, X[e].x, X[e].y);
+      else if (CLS == CLS_NEG) step_neg(nl, hh, o.u, o.v, X[e].x, X[e].y);
+      else step_gen(nl, hh, o, X[e].x, X[e].y);
+    }
+  };
+  auto finish = [&]() {
+    g++;
+    if (g == gend) {
+      if (valid) {
+        double* w = out + (int64_t)j * out_width;
+        w[0] = nl;
+        w[1] = hh;
+        if (out_width == 3) w[2] = nl;
+      }
+      nl = 0.0;
+      hh = 0.0;
+      j++;
+      gend = (int)padded_groups(j + 1);
+    }
+  };
+  while (true) {
+    {
+      const int64_t z = after(A[0].x);
+      const bool more = g + 1 < glast;
+      if (more) {
+#pragma unroll
+        for (int e = 0; e < G; e++) B[e] = C[(int64_t)(g + 1) * G + z + e];
+      }
+      steps(A);
+      finish();
+      if (!more) break;
+    }
+    {
+      const int64_t z = after(B[0].x);
+      const bool more = g + 1 < glast;
+      if (more) {
+#pragma unroll
+        for (int e = 0; e < G; e++) A[e] = C[(int64_t)(g + 1) * G + z + e];
+      }
+      steps(B);
+      finish();
+      if (!more) break;
+    }
+  }
+}
+
 struct SplitSet {
   ChainSplit s[PMAX];
 };
 
-template <bool ORDER1>
+template <bool ORDER1, bool PADDED>
 __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet splits,
                                                const int32_t* __restrict__ labels, const int4* __restrict__ seg,
                                                const int64_t* __restrict__ nseg, AxisGrid g, RowSet out,
@@ -435,7 +546,14 @@ __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet s
   const crow_t* C = (const crow_t*)(in.rows[pz] + (int64_t)parent * in.stride[pz]);
   double* w = out.rows[pz] + node * out.stride[pz];
   const int32_t* lens = ps.p[pz].lens2;
-  const int j0 = split.j0[gi], j1 = split.j0[gi + 1];
+  const int j0 = __builtin_amdgcn_readfirstlane(split.j0[gi]);
+  const int j1 = __builtin_amdgcn_readfirstlane(split.j0[gi + 1]);
+  if (PADDED) {
+    if (cls == CLS_POS) narrow_padded<CLS_POS>(C, j0, j1, o, valid, w, out_width);
+    else if (cls == CLS_NEG) narrow_padded<CLS_NEG>(C, j0, j1, o, valid, w, out_width);
+    else narrow_padded<CLS_STRADDLE>(C, j0, j1, o, valid, w, out_width);
+    return;
+  }
   const int64_t p0 = split.p0[gi];
   if (cls == CLS_POS) narrow_run<CLS_POS, ORDER1>(C, lens, j0, j1, p0, o, valid, w, out_width);
   else if (cls == CLS_NEG) narrow_run<CLS_NEG, ORDER1>(C, lens, j0, j1, p0, o, valid, w, out_width);
@@ -454,67 +572,112 @@ __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet s
 // ---------------------------------------------------------------------------
 typedef double dpair_a8 __attribute__((ext_vector_type(2), aligned(8)));
 
-// One polynomial's leaf chain for one box; returns (nlo, hi).
-__device__ __forceinline__ void leaf_chain(const double* __restrict__ R, int d, int cls, double cnl, double chi,
-                                           double& nl, double& hh) {
-  const CellOps o = cell_ops(cnl, chi, cls);
-  if (cls == CLS_STRADDLE) {
-    nl = R[0];
-    hh = R[1];
-    for (int j = 1; j <= d; j++) step_gen(nl, hh, o, R[3 * j], R[3 * j + 1]);
-    return;
-  }
-  const int sh = cls == CLS_NEG ? 1 : 0;
-  // Entry j (exponent d - j) is read at R + 3j, one double later when the
-  // lane is mirrored and d - j is odd.  pe serves even j, po odd j.
+// General (straddling) leaf chain for one box.
+__device__ __forceinline__ void leaf_chain_gen(const double* __restrict__ R, int d, double cnl, double chi,
+                                               double& nl, double& hh) {
+  const CellOps o = cell_ops(cnl, chi, CLS_STRADDLE);
+  nl = R[0];
+  hh = R[1];
+  for (int j = 1; j <= d; j++) step_gen(nl, hh, o, R[3 * j], R[3 * j + 1]);
+}
+
+// Up to LR boxes of one column and one sign class (POS or NEG) share every
+// coefficient load.  Entry j (exponent d - j) is read at R + 3j, one double
+// later when the boxes are mirrored (NEG) and d - j is odd; pe serves even j,
+// po odd j.  Four entries are in flight; rows are padded so reads past entry
+// d stay inside the buffer.
+template <int LR>
+__device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int d, int sh, const double (&u)[LR],
+                                            const double (&v)[LR], double (&nl)[LR], double (&hh)[LR]) {
   const double* pe = R + ((d & 1) ? sh : 0);
   const double* po = R + 3 + (((d - 1) & 1) ? sh : 0);
   auto at = [&](int j) -> dpair_a8 {
     return (j & 1) ? *reinterpret_cast<const dpair_a8*>(po + 3 * (j - 1))
                    : *reinterpret_cast<const dpair_a8*>(pe + 3 * j);
   };
-  dpair_a8 c = at(0);
-  nl = c.x;
-  hh = c.y;
-  // four entries in flight (rows are padded so reads past entry d stay in bounds)
+  const dpair_a8 c = at(0);
+#pragma unroll
+  for (int i = 0; i < LR; i++) {
+    nl[i] = c.x;
+    hh[i] = c.y;
+  }
   dpair_a8 q0 = at(1), q1 = at(2), q2 = at(3), q3 = at(4);
+  auto steps = [&](const dpair_a8& q) {
+#pragma unroll
+    for (int i = 0; i < LR; i++) step_pos(nl[i], hh[i], u[i], v[i], q.x, q.y);
+  };
   int j = 1;
   for (; j + 3 <= d; j += 4) {
-    step_pos(nl, hh, o.u, o.v, q0.x, q0.y);
+    steps(q0);
     q0 = *reinterpret_cast<const dpair_a8*>(po + 3 * (j + 3));  // entry j+4 (odd)
-    step_pos(nl, hh, o.u, o.v, q1.x, q1.y);
+    steps(q1);
     q1 = *reinterpret_cast<const dpair_a8*>(pe + 3 * (j + 5));  // entry j+5 (even)
-    step_pos(nl, hh, o.u, o.v, q2.x, q2.y);
+    steps(q2);
     q2 = *reinterpret_cast<const dpair_a8*>(po + 3 * (j + 5));  // entry j+6 (odd)
-    step_pos(nl, hh, o.u, o.v, q3.x, q3.y);
+    steps(q3);
     q3 = *reinterpret_cast<const dpair_a8*>(pe + 3 * (j + 7));  // entry j+7 (even)
   }
-  if (j <= d) step_pos(nl, hh, o.u, o.v, q0.x, q0.y);
-  if (j + 1 <= d) step_pos(nl, hh, o.u, o.v, q1.x, q1.y);
-  if (j + 2 <= d) step_pos(nl, hh, o.u, o.v, q2.x, q2.y);
+  if (j <= d) steps(q0);
+  if (j + 1 <= d) steps(q1);
+  if (j + 2 <= d) steps(q2);
 }
 
-__global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int32_t* __restrict__ parent_of,
-                                              const int32_t* __restrict__ labels, int64_t nleaf, AxisGrid g,
-                                              double* __restrict__ lo_out, double* __restrict__ hi_out,
-                                              uint8_t* __restrict__ keep, int first) {
+// One lane per leaf segment (<= LEAF_R boxes of one parent and one class).
+constexpr int LEAF_R = 4;
+
+__global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int4* __restrict__ seg,
+                                              const int64_t* __restrict__ nseg, const int32_t* __restrict__ labels,
+                                              int64_t nleaf, AxisGrid g, double* __restrict__ lo_out,
+                                              double* __restrict__ hi_out, uint8_t* __restrict__ keep, int first) {
   round_up_mode();
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nleaf) return;
-  const int64_t par = parent_of ? parent_of[b] : 0;
-  double cnl, chi;
-  cell(g, labels[b], cnl, chi);
-  const int cls = cell_class(cnl, chi);
-  bool excl = false;
-  for (int p = 0; p < ps.np; p++) {
-    double nl, hh;
-    leaf_chain(rows.rows[p] + par * rows.stride[p], ps.p[p].d, cls, cnl, chi, nl, hh);
-    const double lo = -opaque(nl);
-    lo_out[p * nleaf + b] = lo;
-    hi_out[p * nleaf + b] = hh;
-    excl = excl || (lo > 0.0) || (hh < 0.0);
+  const int64_t sid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sid >= *nseg) return;
+  const int4 sg = seg[sid];
+  const int64_t par = sg.x, begin = sg.y;
+  const int cnt = sg.z, cls = sg.w;
+  double u[LEAF_R], v[LEAF_R];
+#pragma unroll
+  for (int i = 0; i < LEAF_R; i++) {
+    double cnl, chi;
+    cell(g, labels[begin + (i < cnt ? i : 0)], cnl, chi);
+    const CellOps o = cell_ops(cnl, chi, cls == CLS_STRADDLE ? CLS_POS : cls);
+    u[i] = o.u;
+    v[i] = o.v;
   }
-  if (keep) keep[b] = first ? (excl ? 0 : 1) : (excl ? 0 : keep[b]);
+  bool excl[LEAF_R] = {};
+  for (int p = 0; p < ps.np; p++) {
+    const double* R = rows.rows[p] + par * rows.stride[p];
+    const int d = ps.p[p].d;
+    double nl[LEAF_R], hh[LEAF_R];
+    if (cls == CLS_STRADDLE) {
+#pragma unroll
+      for (int i = 0; i < LEAF_R; i++) {
+        nl[i] = 0.0;
+        hh[i] = 0.0;
+        if (i < cnt) {
+          double cnl, chi;
+          cell(g, labels[begin + i], cnl, chi);
+          leaf_chain_gen(R, d, cnl, chi, nl[i], hh[i]);
+        }
+      }
+    } else {
+      leaf_chains<LEAF_R>(R, d, cls == CLS_NEG ? 1 : 0, u, v, nl, hh);
+    }
+#pragma unroll
+    for (int i = 0; i < LEAF_R; i++) {
+      if (i < cnt) {
+        const double lo = -opaque(nl[i]);
+        lo_out[p * nleaf + begin + i] = lo;
+        hi_out[p * nleaf + begin + i] = hh[i];
+        excl[i] = excl[i] || (lo > 0.0) || (hh[i] < 0.0);
+      }
+    }
+  }
+  if (keep) {
+#pragma unroll
+    for (int i = 0; i < LEAF_R; i++)
+      if (i < cnt) keep[begin + i] = first ? (excl[i] ? 0 : 1) : (excl[i] ? 0 : keep[begin + i]);
+  }
 }
 
 // Parent (depth k-1 node) of every leaf: binary search in ptr.
@@ -640,6 +803,7 @@ static void plan_prepared(Arena& A, Prepared& Q, const vx_poly* P, int np) {
     Q.ttab[p] = A.take<int2>(k >= 2 ? ntup(k - 1, d) : 1);
     Q.lens2[p] = A.take<int32_t>(k == 4 ? ntup(2, d) : 1);
     Q.lens1[p] = A.take<int32_t>(d + 1);
+    Q.padlist[p] = A.take<int32_t>(k == 3 ? padded_npad(d) + 1 : 1);
   }
 }
 
@@ -661,7 +825,8 @@ int prepare_polys(const vx_poly* P, int np, void* ws, size_t ws_bytes, Prepared*
     int64_t cube = 1;
     for (int i = 0; i < k; i++) cube *= P[p].side;
     hipLaunchKernelGGL(k_tables, dim3((unsigned)((cube + 255) / 256)), dim3(256), 0, st, k, P[p].degree, P[p].side,
-                       P[p].c_lo, P[p].c_hi, out->packed[p], out->ttab[p], out->lens2[p], out->lens1[p]);
+                       P[p].c_lo, P[p].c_hi, out->packed[p], out->ttab[p], out->lens2[p], out->lens1[p],
+                       out->padlist[p]);
     VX_CHECK_LAUNCH("k_tables");
   }
   return VX_OK;
@@ -670,7 +835,6 @@ int prepare_polys(const vx_poly* P, int np, void* ws, size_t ws_bytes, Prepared*
 struct EvalPlan {
   int k = 0;
   double* rows[VX_KMAX][VX_MAXPOLY] = {};  // output rows of stage l for polynomial p
-  int32_t* parent = nullptr;
   SegPlan seg[VX_KMAX];
   int R = 8;
 };
@@ -684,15 +848,16 @@ static void plan_eval(Arena& A, EvalPlan& E, const vx_poly* P, int np, const vx_
   for (int l = 0; l + 1 < k; l++) {
     const int m = k - l - 1;  // dimension of the trailing tuples left after depth l+1
     const int width = (l == k - 2) ? 3 : 2;
-    for (int p = 0; p < np; p++)
-      E.rows[l][p] = A.take<double>((size_t)S->n[l] * ntup(m, P[p].degree) * width + 4 * ROW_PAD * width) +
-                     2 * ROW_PAD * width;
+    for (int p = 0; p < np; p++) {
+      const int64_t row = (k == 3 && l == 0) ? padded_entries(P[p].degree) : ntup(m, P[p].degree);
+      E.rows[l][p] = A.take<double>((size_t)S->n[l] * row * width + 4 * ROW_PAD * width) + 2 * ROW_PAD * width;
+    }
   }
-  if (k >= 2) E.parent = A.take<int32_t>(S->n[k - 1] > 0 ? S->n[k - 1] : 1);
   E.R = stage1_blocking(S->n[0]);
-  for (int l = 0; l + 1 < k; l++) {
+  for (int l = 0; l < k; l++) {
     const int64_t nparent = l == 0 ? 1 : S->n[l - 1];
-    plan_segments(A, E.seg[l], nparent, S->n[l], l == 0 ? E.R : 64);
+    const int Z = l == k - 1 ? LEAF_R : (l == 0 ? E.R : 64);
+    plan_segments(A, E.seg[l], nparent, S->n[l], Z);
   }
 }
 
@@ -726,15 +891,17 @@ static int launch_stage1(const Prepared& Q, int p0, int pn, const vx_csf* S, con
     ps.p[i].packed = reinterpret_cast<const double2*>(Q.packed[p]);
     ps.p[i].ttab = Q.ttab[p];
     ps.p[i].lens2 = Q.lens2[p];
+    ps.p[i].padlist = Q.padlist[p];
+    ps.p[i].npad = k == 3 ? (int)padded_npad(d) : 0;
     ps.p[i].d = d;
     ps.p[i].nt = (int)ntup(m, d);
     nt_max = ps.p[i].nt > nt_max ? ps.p[i].nt : nt_max;
     rs.rows[i] = E.rows[0][p];
-    rs.stride[i] = ntup(m, d) * width;
+    rs.stride[i] = (k == 3 ? padded_entries(d) : ntup(m, d)) * width;
     units += (double)(ntup(k, d) - ntup(m, d)) * (double)S->n[0];
   }
   const SegPlan& sp = E.seg[0];
-  dim3 grid((unsigned)sp.maxseg, (unsigned)((nt_max + 63) / 64), (unsigned)pn);
+  dim3 grid((unsigned)sp.maxseg, (unsigned)((nt_max + 63) / 64 + 1), (unsigned)pn);
   const AxisGrid g = make_grid(dom, 0, S->level);
   const int pr = prof_start("k_stage1", units, st);
   switch (E.R) {
@@ -771,7 +938,7 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
     ps.p[i].lens2 = Q.lens2[p];
     ps.p[i].d = d;
     in.rows[i] = E.rows[l - 1][p];
-    in.stride[i] = ntup(m_in, d) * 2;
+    in.stride[i] = (k == 3 ? padded_entries(d) : ntup(m_in, d)) * 2;
     out.rows[i] = E.rows[l][p];
     out.stride[i] = ntup(m_out, d) * width;
     ss.s[i] = chain_split(m_out, d, groups);
@@ -782,11 +949,14 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
   dim3 grid((unsigned)sp.maxseg, (unsigned)gmax, (unsigned)pn);
   const AxisGrid g = make_grid(dom, l, S->level);
   const int pr = prof_start("k_narrow", units, st);
-  if (m_out == 1)
-    hipLaunchKernelGGL(k_narrow<true>, grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
+  if (k == 3)
+    hipLaunchKernelGGL((k_narrow<true, true>), grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
+                       (const int64_t*)sp.nseg, g, out, width);
+  else if (m_out == 1)
+    hipLaunchKernelGGL((k_narrow<true, false>), grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
                        (const int64_t*)sp.nseg, g, out, width);
   else
-    hipLaunchKernelGGL(k_narrow<false>, grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
+    hipLaunchKernelGGL((k_narrow<false, false>), grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
                        (const int64_t*)sp.nseg, g, out, width);
   VX_CHECK_LAUNCH("k_narrow");
   prof_stop(pr, st);
@@ -810,9 +980,10 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
     rs.stride[i] = k == 1 ? 0 : 3 * (int64_t)(d + 1);
     units += (double)d * (double)nleaf;
   }
+  const SegPlan& sp = E.seg[k - 1];
   const int pr = prof_start("k_leaf", units, st);
-  hipLaunchKernelGGL(k_leaf, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st, ps, rs,
-                     k == 1 ? (const int32_t*)nullptr : (const int32_t*)E.parent, S->idx[k - 1], nleaf,
+  hipLaunchKernelGGL(k_leaf, dim3((unsigned)((sp.maxseg + 255) / 256)), dim3(256), 0, st, ps, rs,
+                     (const int4*)sp.seg, (const int64_t*)sp.nseg, S->idx[k - 1], nleaf,
                      make_grid(dom, k - 1, S->level), lo + (int64_t)p0 * nleaf, hi + (int64_t)p0 * nleaf, keep,
                      p0 == 0 ? 1 : 0);
   VX_CHECK_LAUNCH("k_leaf");
@@ -834,14 +1005,9 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
     VX_FAIL(VX_ECAPACITY, "interval_eval_level: workspace of %zu bytes is too small (%zu needed)", ws_bytes,
             A.off + 256);
   int rc;
-  for (int l = 0; l + 1 < k; l++) {
+  for (int l = 0; l < k; l++) {
     const AxisGrid g = make_grid(dom, l, S->level);
     if ((rc = build_segments(E.seg[l], l == 0 ? nullptr : S->ptr[l - 1], S->idx[l], g, st))) return rc;
-  }
-  if (k >= 2) {
-    hipLaunchKernelGGL(k_parent_of, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st, S->ptr[k - 2],
-                       S->n[k - 2], nleaf, E.parent);
-    VX_CHECK_LAUNCH("k_parent_of");
   }
   for (int p0 = 0; p0 < Q.np; p0 += PMAX) {
     const int pn = Q.np - p0 < PMAX ? Q.np - p0 : PMAX;

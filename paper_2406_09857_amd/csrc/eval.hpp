@@ -17,6 +17,7 @@ struct Prepared {
   int2* ttab[VX_MAXPOLY] = {};
   int32_t* lens2[VX_MAXPOLY] = {};
   int32_t* lens1[VX_MAXPOLY] = {};
+  int32_t* padlist[VX_MAXPOLY] = {};
   int d[VX_MAXPOLY] = {};
 };
 size_t prepared_bytes(const vx_poly* P, int np);

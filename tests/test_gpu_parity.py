@@ -125,3 +125,28 @@ def test_curve_low_levels_full_parity(vx):
     for r in recs:
         keep = _check_level(vx, w.polys, r["S"], w.domain(), "curve")
         _check_filter(vx, r["S"], keep, f"curve level {r['level']}")
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_mixed_degrees_one_system(vx, k):
+    """Polynomials of different degrees in one system (one launch per stage
+    serves all of them); degrees cross the 8-entry group boundaries of the
+    padded middle-stage rows."""
+    rng = np.random.default_rng(700 + k)
+    degs = [1, 7, 8, 9, 15, 16, 17, 23] if k == 3 else [0, 1, 5, 9, 16, 31]
+    polys = [synth.small_random(k, dg, seed=800 + dg)[0] for dg in degs]
+    level = 5
+    boxes = rng.integers(0, 1 << level, size=(3000, k))
+    S = orc.csf_from_boxes(boxes, level)
+    for dom in (np.array([-1.0, 1.0] * k), np.array([-0.6, 1.1] * k)):
+        keep = _check_level(vx, polys, S, dom, f"mixed k={k}")
+        _check_filter(vx, S, keep, f"mixed k={k}")
+
+
+def test_more_than_eight_polynomials(vx):
+    """Systems larger than one launch's polynomial set are evaluated in chunks;
+    the keep flag is the conjunction over all of them."""
+    rng = np.random.default_rng(901)
+    polys = [synth.small_random(3, 4 + (i % 5), seed=900 + i)[0] for i in range(11)]
+    S = orc.csf_from_boxes(rng.integers(0, 16, size=(500, 3)), 4)
+    _check_level(vx, polys, S, np.array([-1.0, 1.0] * 3), "eleven polynomials")
