@@ -346,3 +346,21 @@ def profile_end() -> dict:
     _check(lib().vx_profile_end(arr, 64, C.byref(cnt)))
     return {arr[i].name.decode(): {"launches": int(arr[i].launches), "ms": float(arr[i].ms),
                                    "units": float(arr[i].units)} for i in range(min(cnt.value, 64))}
+
+
+def csf_build(boxes: torch.Tensor, level: int, stream=None) -> CSF:
+    """CSF of an (n, k) int32 device tensor of grid indices (any order,
+    duplicates merged).  Synchronizes to read the node counts."""
+    boxes = boxes.to(torch.int32).contiguous()
+    n, k = int(boxes.shape[0]), int(boxes.shape[1])
+    dev = boxes.device
+    out = CSF.empty(k, level, [max(n, 1)] * k, dev)
+    s = out.struct()
+    probe = vx_csf()
+    probe.k = k
+    need = int(lib().vx_workspace_bytes(VX_WS_BUILD, None, 0, C.byref(probe), n))
+    ws = _ws(need, dev)
+    _check(lib().csf_build(k, level, boxes.data_ptr() if n else None, n, C.byref(s), ws.data_ptr(), ws.numel(),
+                           _stream(stream)))
+    out.n = [int(s.n[l]) for l in range(k)]
+    return out
