@@ -176,6 +176,50 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
  * 2 = device->device. */
 int vx_copy(void* dst, const void* src, size_t bytes, int32_t kind, void* stream);
 
+/*
+ * eval_grad -- point values and gradients of a polynomial system, and the
+ * gradient of sum_{p,i} gbar[p][i] F_p(x_i) with respect to the coefficients
+ * (the adjoint of the evaluation).  Round-to-nearest FP64, no fused
+ * multiply-add, nested Horner in the order of the interval path (x1
+ * innermost), so f is bit-identical to that plain evaluation; derivatives are
+ * carried forward along the same chains.  Sec. 3.2 uses the gradients for
+ * Newton steps in the span of the gradients and for Taylor forms.
+ *   P, np  : point coefficients (c_hi must be NULL), np <= 4, same k.
+ *   x      : device, n x k points (row-major).
+ *   f      : device, np x n values, or NULL.
+ *   jac    : device, n x np x k partial derivatives dF_p/dx_j, or NULL.
+ *   gbar   : device, np x n weights, or NULL.
+ *   xbar   : device, n x k, or NULL: sum_p gbar[p][i] dF_p/dx_j (x_i), the
+ *            gradient of the weighted sum with respect to the points.
+ *   dcoef  : device, np dense cubes (side^k each, zeros outside the simplex)
+ *            receiving sum_i gbar[p][i] x_i^e; requires `grid`.
+ *   grid, dom : when the points are the centres of the leaves of a CSF (as
+ *            written by csf_centres), the coefficient gradient is the
+ *            transpose of the amortized evaluation, one CSF depth at a time
+ *            (Algorithm 2 run backwards); NULL for arbitrary points.
+ * Errors: VX_EINVAL, VX_EUNSUPPORTED (dcoef without grid; degree > 200 for
+ * dcoef), VX_ECAPACITY (workspace: vx_workspace_bytes(VX_WS_GRAD, P, np,
+ * grid, n)).
+ */
+int eval_grad(const vx_poly* P, int32_t np, const double* x, int64_t n, double* f, double* jac, const double* gbar,
+              double* xbar, double* dcoef, const vx_csf* grid, const double* dom, void* ws, size_t ws_bytes,
+              void* stream);
+
+/* csf_centres -- centres of the cells of the leaves of S on the domain (host
+ * dom[2k]), device output n[k-1] x k, leaf order; round-to-nearest (exact on
+ * dyadic domains). */
+int csf_centres(const vx_csf* S, const double* dom, double* x, void* stream);
+
+/*
+ * newton_project -- `steps` Newton steps x <- x - J^T (J J^T)^{-1} F(x) on
+ * every point (the minimum-norm step in the span of the gradients, Sec. 3.2,
+ * for systems with fewer equations than unknowns; J is np x k).  Points whose
+ * J J^T is singular are left in place.  x (device, n x k) is updated in
+ * place; f (device np x n, or NULL) receives F at the final points.
+ */
+int newton_project(const vx_poly* P, int32_t np, double* x, int64_t n, int32_t steps, double* f, void* ws,
+                   size_t ws_bytes, void* stream);
+
 /* Per-kernel timing.  vx_profile_begin() starts recording HIP events around
  * every evaluation and filter kernel launched afterwards from any host thread;
  * vx_profile_end() waits for the recorded events, fills up to `max` records

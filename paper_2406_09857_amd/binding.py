@@ -364,3 +364,116 @@ def csf_build(boxes: torch.Tensor, level: int, stream=None) -> CSF:
                            _stream(stream)))
     out.n = [int(s.n[l]) for l in range(k)]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Point evaluation, adjoint, Newton projection
+# ---------------------------------------------------------------------------
+
+def _grad_lib():
+    L = lib()
+    if not getattr(L, "_grad_ready", False):
+        vp = C.c_void_p
+        L.eval_grad.argtypes = [C.POINTER(vx_poly), C.c_int32, vp, C.c_int64, vp, vp, vp, vp, vp,
+                                C.POINTER(vx_csf), C.POINTER(C.c_double), vp, C.c_size_t, vp]
+        L.eval_grad.restype = C.c_int
+        L.csf_centres.argtypes = [C.POINTER(vx_csf), C.POINTER(C.c_double), vp, vp]
+        L.csf_centres.restype = C.c_int
+        L.newton_project.argtypes = [C.POINTER(vx_poly), C.c_int32, vp, C.c_int64, C.c_int32, vp, vp, C.c_size_t,
+                                     vp]
+        L.newton_project.restype = C.c_int
+        L._grad_ready = True
+    return L
+
+
+def csf_centres(csf: CSF, dom, stream=None) -> torch.Tensor:
+    """(n, k) float64 centres of the leaf cells of a CSF."""
+    dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
+    x = torch.empty((max(csf.nboxes, 1), csf.k), dtype=torch.float64, device=csf.idx[0].device)
+    s = csf.struct()
+    _check(_grad_lib().csf_centres(C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)), x.data_ptr(),
+                                   _stream(stream)))
+    return x[: csf.nboxes]
+
+
+def eval_grad(polys, x: torch.Tensor, want_jac: bool = True, gbar: torch.Tensor | None = None,
+              want_xbar: bool = False, want_dcoef: bool = False, grid: CSF | None = None, dom=None, stream=None):
+    """Point values f (np, n), Jacobian (n, np, k), and with gbar (np, n) the
+    adjoints xbar (n, k) and dcoef (np, side^k cubes; needs `grid`, the CSF
+    whose leaf centres are x)."""
+    polys = as_polys(polys)
+    x = x.to(torch.float64).contiguous()
+    n, k = int(x.shape[0]), polys[0].k
+    dev = x.device
+    npl = len(polys)
+    f = torch.empty((npl, max(n, 1)), dtype=torch.float64, device=dev)
+    jac = torch.empty((max(n, 1), npl, k), dtype=torch.float64, device=dev) if want_jac else None
+    xbar = torch.empty((max(n, 1), k), dtype=torch.float64, device=dev) if want_xbar else None
+    dcoef = None
+    if want_dcoef:
+        dcoef = torch.zeros((npl,) + tuple(polys[0].c_lo.shape), dtype=torch.float64, device=dev)
+    if gbar is not None:
+        gbar = gbar.to(torch.float64).contiguous()
+    parr = _poly_array(polys)
+    gs = grid.struct() if grid is not None else None
+    need = int(_grad_lib().vx_workspace_bytes(VX_WS_GRAD, parr, npl, C.byref(gs) if gs else None, n))
+    if need == 0:
+        _check(VX_EINVAL)
+    ws = _ws(need, dev)
+    domarr = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1)) if dom is not None else None
+    _check(_grad_lib().eval_grad(parr, npl, x.data_ptr() if n else None, n, f.data_ptr(),
+                                 jac.data_ptr() if jac is not None else None,
+                                 gbar.data_ptr() if gbar is not None else None,
+                                 xbar.data_ptr() if xbar is not None else None,
+                                 dcoef.data_ptr() if dcoef is not None else None,
+                                 C.byref(gs) if gs else None,
+                                 domarr.ctypes.data_as(C.POINTER(C.c_double)) if domarr is not None else None,
+                                 ws.data_ptr(), ws.numel(), _stream(stream)))
+    return (f[:, :n], jac[:n] if jac is not None else None, xbar[:n] if xbar is not None else None, dcoef)
+
+
+def newton_project(polys, x: torch.Tensor, steps: int = 3, stream=None):
+    """`steps` minimum-norm Newton steps on every point (in place); returns
+    (x, F at the final points)."""
+    polys = as_polys(polys)
+    n = int(x.shape[0])
+    f = torch.empty((len(polys), max(n, 1)), dtype=torch.float64, device=x.device)
+    parr = _poly_array(polys)
+    need = int(_grad_lib().vx_workspace_bytes(VX_WS_GRAD, parr, len(polys), None, n))
+    ws = _ws(need, x.device)
+    _check(_grad_lib().newton_project(parr, len(polys), x.data_ptr(), n, steps, f.data_ptr(), ws.data_ptr(),
+                                      ws.numel(), _stream(stream)))
+    return x, f[:, :n]
+
+
+class PolyEval(torch.autograd.Function):
+    """F(x) for a polynomial system as a torch autograd function.
+
+    forward(x, *coefs): x (n, k) float64 points, coefs one dense cube per
+    polynomial (point coefficients); returns (np, n).  The backward is the
+    library's adjoint: dL/dx from the forward-mode Jacobian contracted with the
+    incoming gradient, dL/dcoef from the transposed amortized evaluation when a
+    CSF grid is attached with ``PolyEval.grid = (csf, dom)`` (x must then be
+    that grid's centres); otherwise coefficient gradients are not provided.
+    """
+    grid = None
+
+    @staticmethod
+    def forward(ctx, x, *coefs):
+        polys = [Poly(c.detach().to(torch.float64)) for c in coefs]
+        f, _, _, _ = eval_grad(polys, x.detach(), want_jac=False)
+        ctx.save_for_backward(x, *coefs)
+        ctx.grid = PolyEval.grid
+        return f
+
+    @staticmethod
+    def backward(ctx, gf):
+        x, *coefs = ctx.saved_tensors
+        polys = [Poly(c.detach().to(torch.float64)) for c in coefs]
+        want_dc = any(ctx.needs_input_grad[1:]) and ctx.grid is not None
+        grid, dom = ctx.grid if ctx.grid is not None else (None, None)
+        _, _, xbar, dcoef = eval_grad(polys, x.detach(), want_jac=False, gbar=gf.contiguous(),
+                                      want_xbar=ctx.needs_input_grad[0], want_dcoef=want_dc, grid=grid, dom=dom)
+        gx = xbar if ctx.needs_input_grad[0] else None
+        gcs = [dcoef[i] if (want_dc and ctx.needs_input_grad[1 + i]) else None for i in range(len(coefs))]
+        return (gx, *gcs)

@@ -9,6 +9,7 @@
 
 #include "common.hpp"
 #include "eval.hpp"
+#include "grad.hpp"
 
 namespace vx {
 
@@ -127,6 +128,10 @@ size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_
     case VX_WS_BUILD:
       if (!S || S->k < 1 || S->k > VX_KMAX || n < 0) return 0;
       return build_workspace_bytes(S->k, n);
+    case VX_WS_GRAD:
+      if (!P || np < 1 || np > PMAX_GRAD || check_poly(P, np, P[0].k)) return 0;
+      if (S && check_csf(S, false)) return 0;
+      return grad_workspace_bytes(P, np, S, n);
     default:
       return 0;
   }
@@ -160,6 +165,54 @@ int filter_subdivide(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf*
   if (kept) kept->level = S->level;
   if (next) next->level = S->level + 1;
   return filter_impl(S, keep, kept, next, d_counts, ws, ws_bytes, (hipStream_t)stream);
+}
+
+static int check_point_polys(const vx_poly* P, int np) {
+  if (!P || np < 1 || np > PMAX_GRAD) VX_FAIL(VX_EINVAL, "point evaluation takes 1..%d polynomials", PMAX_GRAD);
+  int rc;
+  if ((rc = check_poly(P, np, P[0].k))) return rc;
+  for (int p = 0; p < np; p++)
+    if (P[p].c_hi && P[p].c_hi != P[p].c_lo)
+      VX_FAIL(VX_EINVAL, "point evaluation needs point coefficients (c_hi == NULL)");
+  return VX_OK;
+}
+
+int eval_grad(const vx_poly* P, int32_t np, const double* x, int64_t n, double* f, double* jac, const double* gbar,
+              double* xbar, double* dcoef, const vx_csf* grid, const double* dom, void* ws, size_t ws_bytes,
+              void* stream) {
+  int rc;
+  if ((rc = check_point_polys(P, np))) return rc;
+  const int k = P[0].k;
+  if (n < 0 || (n > 0 && (f || jac || xbar) && !x)) VX_FAIL(VX_EINVAL, "bad point list");
+  if (xbar && !gbar) VX_FAIL(VX_EINVAL, "xbar needs gbar");
+  if (dcoef) {
+    if (!gbar) VX_FAIL(VX_EINVAL, "dcoef needs gbar");
+    if (!grid) VX_FAIL(VX_EUNSUPPORTED, "coefficient gradients need the points as a CSF grid of centres");
+    if ((rc = check_csf(grid, true))) return rc;
+    if (grid->k != k) VX_FAIL(VX_EINVAL, "grid has k=%d, polynomials k=%d", grid->k, k);
+    if (grid->n[k - 1] != n) VX_FAIL(VX_EINVAL, "grid has %lld leaves, n=%lld", (long long)grid->n[k - 1], (long long)n);
+    if ((rc = check_dom(dom, k))) return rc;
+    for (int p = 0; p < np; p++)
+      if (P[p].degree > MAXDEG_ADJ) VX_FAIL(VX_EUNSUPPORTED, "coefficient gradient limited to degree %d", MAXDEG_ADJ);
+  }
+  return grad_impl(P, np, x, n, f, jac, gbar, xbar, dcoef, dcoef ? grid : nullptr, dom, ws, ws_bytes,
+                   (hipStream_t)stream);
+}
+
+int csf_centres(const vx_csf* S, const double* dom, double* x, void* stream) {
+  int rc;
+  if ((rc = check_csf(S, true))) return rc;
+  if ((rc = check_dom(dom, S->k))) return rc;
+  if (S->n[S->k - 1] > 0 && !x) VX_FAIL(VX_EINVAL, "null output");
+  return centres_impl(S, dom, x, (hipStream_t)stream);
+}
+
+int newton_project(const vx_poly* P, int32_t np, double* x, int64_t n, int32_t steps, double* f, void* ws,
+                   size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_point_polys(P, np))) return rc;
+  if (n < 0 || (n > 0 && !x) || steps < 0 || steps > 100) VX_FAIL(VX_EINVAL, "bad arguments");
+  return newton_impl(P, np, x, n, steps, f, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int vx_copy(void* dst, const void* src, size_t bytes, int32_t kind, void* stream) {

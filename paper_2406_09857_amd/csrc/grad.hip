@@ -1,0 +1,626 @@
+// Point evaluation with gradients, the coefficient adjoint on a CSF grid of
+// cell centres, and Newton projection (Moroz, arXiv 2406.09857, Sec. 3.2:
+// Newton steps in the span of the gradients when a system has fewer equations
+// than unknowns; the Taylor/mean-value form uses the gradient on a box).
+//
+// Arithmetic is ordinary round-to-nearest FP64 with no fused multiply-add.
+// Values follow the same nested Horner order as the interval path (x1
+// innermost, descending exponents), so F(x) is bit-identical to a plain
+// nested Horner evaluation; derivatives are carried forward-mode along the
+// same chains (d(v*x + c)/dx = (dv/dx)*x + v).
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include "common.hpp"
+#include "eval.hpp"
+#include "grad.hpp"
+#include "scan.hpp"
+
+namespace vx {
+
+__host__ __device__ inline int64_t gbinom(int n, int r) {
+  if (r < 0 || n < r) return 0;
+  int64_t v = 1;
+  for (int i = 1; i <= r; i++) v = v * (n - r + i) / i;
+  return v;
+}
+
+// O_m position (consumption order: for t' in O_{m-1}: for e desc).
+__device__ inline int64_t g_opos(const int* t, int m, int d) {
+  int64_t pos = 0;
+  int sigma = 0;
+  for (int j = m; j >= 1; j--) {
+    sigma += t[j - 1];
+    pos += gbinom(d - sigma + j - 1, j);
+  }
+  return pos;
+}
+
+// Graded order of m-tuples: by total degree, then lexicographic (t0, t1, ...).
+__device__ inline int64_t g_rank(const int* t, int m) {
+  if (m == 0) return 0;
+  int g = 0;
+  for (int i = 0; i < m; i++) g += t[i];
+  int64_t r = gbinom(g + m - 1, m);
+  int pre = 0;
+  for (int i = 0; i + 1 < m; i++) {
+    for (int v = 0; v < t[i]; v++) r += gbinom(g - pre - v + (m - 1 - i) - 1, (m - 1 - i) - 1);
+    pre += t[i];
+  }
+  return r;
+}
+
+__device__ inline void g_unrank(int64_t r, int m, int* t) {
+  if (m == 0) return;
+  int g = 0;
+  while (gbinom(g + 1 + m - 1, m) <= r) g++;
+  r -= gbinom(g + m - 1, m);
+  int pre = 0;
+  for (int i = 0; i + 1 < m; i++) {
+    int v = 0;
+    while (true) {
+      const int64_t c = gbinom(g - pre - v + (m - 1 - i) - 1, (m - 1 - i) - 1);
+      if (r < c) break;
+      r -= c;
+      v++;
+    }
+    t[i] = v;
+    pre += v;
+  }
+  t[m - 1] = g - pre;
+}
+
+// Cell centre of `label` at `level` on [dlo, dhi], round to nearest (exact
+// on dyadic domains).
+__device__ __forceinline__ double centre(double dlo, double dhi, int level, int32_t label) {
+  return dlo + ldexp((double)(2 * (int64_t)label + 1) * (dhi - dlo), -(level + 1));
+}
+
+// ---------------------------------------------------------------------------
+// Nested coefficient stream: chains in O_{k-1} order of their trailing tuple,
+// each chain c[e1 = d-|t| .. 0, t] front-padded with zeros to a multiple of
+// SG entries.
+// ---------------------------------------------------------------------------
+constexpr int SG = 8;
+
+__global__ void k_stream_len(int k, int d, int side, int64_t* __restrict__ plen) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = 1;
+  for (int i = 1; i < k; i++) total *= side;
+  if (f >= total) return;  // enumerate trailing tuples t (k-1 coordinates)
+  int t[VX_KMAX] = {0, 0, 0, 0};
+  int64_t q = f;
+  for (int i = k - 2; i >= 0; i--) { t[i] = (int)(q % side); q /= side; }
+  int deg = 0;
+  for (int i = 0; i + 1 < k; i++) deg += t[i];
+  if (deg > d) return;
+  const int64_t L = d - deg + 1;
+  plen[k >= 2 ? g_opos(t, k - 1, d) : 0] = (L + SG - 1) / SG * SG;
+}
+
+__global__ void k_stream_fill(int k, int d, int side, const double* __restrict__ c, const int64_t* __restrict__ start,
+                              double* __restrict__ stream) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t total = 1;
+  for (int i = 0; i < k; i++) total *= side;
+  if (f >= total) return;
+  int e[VX_KMAX] = {0, 0, 0, 0};
+  int64_t q = f;
+  for (int i = k - 1; i >= 0; i--) { e[i] = (int)(q % side); q /= side; }
+  int deg = 0;
+  for (int i = 0; i < k; i++) deg += e[i];
+  if (deg > d) return;
+  const int tdeg = deg - e[0];
+  const int64_t ch = k >= 2 ? g_opos(e + 1, k - 1, d) : 0;
+  const int64_t L = d - tdeg + 1;
+  const int64_t pad = (L + SG - 1) / SG * SG - L;
+  stream[start[ch] + pad + (d - tdeg - e[0])] = c[f];
+}
+
+struct I64Load {
+  const int64_t* a;
+  __device__ int64_t operator()(int64_t i) const { return a[i]; }
+};
+
+// ---------------------------------------------------------------------------
+// Per-point evaluation: lanes are points, the stream is wave-uniform.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(4))) const double cdbl_t;
+
+__device__ __forceinline__ int64_t after_d(double x) {
+  int64_t z;
+  asm volatile("s_mov_b64 %0, 0" : "=s"(z) : "s"(x));
+  return z;
+}
+
+// Value and gradient of one polynomial at the lane's point.  `grad` may be
+// skipped (GRAD = false) for value-only evaluation.
+template <int K, bool GRAD>
+__device__ void point_eval(const cdbl_t* __restrict__ S, int d, const double (&x)[VX_KMAX], double& val,
+                           double (&grad)[VX_KMAX]) {
+  // acc[s]: Horner accumulator of depth s (s = 0 is the x1 chain);
+  // der[s][j]: its derivative with respect to x_j (j <= s).
+  double acc[K], der[K][K];
+#pragma unroll
+  for (int s = 0; s < K; s++) {
+    acc[s] = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; j++) der[s][j] = 0.0;
+  }
+  double A[SG];
+  int64_t g = 0;
+#pragma unroll
+  for (int e = 0; e < SG; e++) A[e] = S[e];
+  // loops over the trailing tuple in O_{K-1} order (outermost variable first)
+  int t[VX_KMAX] = {0, 0, 0, 0};
+  auto chain = [&](int L) {  // one x1 chain of L entries, padded
+    const int ng = (L + SG - 1) / SG;
+    acc[0] = 0.0;
+    if (GRAD) der[0][0] = 0.0;
+    for (int gg = 0; gg < ng; gg++) {
+      const int64_t z = after_d(A[0]);
+      double B[SG];
+#pragma unroll
+      for (int e = 0; e < SG; e++) B[e] = S[(g + 1) * SG + z + e];
+#pragma unroll
+      for (int e = 0; e < SG; e++) {
+        if (GRAD) der[0][0] = der[0][0] * x[0] + acc[0];
+        acc[0] = acc[0] * x[0] + A[e];
+      }
+#pragma unroll
+      for (int e = 0; e < SG; e++) A[e] = B[e];
+      g++;
+    }
+  };
+  // fold accumulator s-1 into s (Horner step in x_s)
+  auto fold = [&](int s) {
+    if (GRAD) {
+#pragma unroll
+      for (int j = 0; j < K; j++) {
+        if (j < s) der[s][j] = der[s][j] * x[s] + der[s - 1][j];
+        else if (j == s) der[s][j] = der[s][j] * x[s] + acc[s];
+      }
+    }
+    acc[s] = acc[s] * x[s] + acc[s - 1];
+  };
+  auto reset = [&](int s) {
+    acc[s] = 0.0;
+    if (GRAD) {
+#pragma unroll
+      for (int j = 0; j < K; j++) der[s][j] = 0.0;
+    }
+  };
+  if (K == 1) {
+    chain(d + 1);
+  } else if (K == 2) {
+    for (t[0] = d; t[0] >= 0; t[0]--) {
+      chain(d - t[0] + 1);
+      fold(1);
+    }
+  } else if (K == 3) {
+    for (int e3 = d; e3 >= 0; e3--) {
+      reset(1);
+      for (int e2 = d - e3; e2 >= 0; e2--) {
+        chain(d - e2 - e3 + 1);
+        fold(1);
+      }
+      fold(2);
+    }
+  } else {
+    for (int e4 = d; e4 >= 0; e4--) {
+      reset(2);
+      for (int e3 = d - e4; e3 >= 0; e3--) {
+        reset(1);
+        for (int e2 = d - e3 - e4; e2 >= 0; e2--) {
+          chain(d - e2 - e3 - e4 + 1);
+          fold(1);
+        }
+        fold(2);
+      }
+      fold(3);
+    }
+  }
+  val = acc[K - 1];
+  if (GRAD) {
+#pragma unroll
+    for (int j = 0; j < K; j++) grad[j] = der[K - 1][j];
+  }
+}
+
+struct StreamSet {
+  const double* s[PMAX_GRAD];
+  int d[PMAX_GRAD];
+};
+
+template <int K, bool GRAD>
+__global__ __launch_bounds__(64) void k_point_eval(StreamSet ss, int np, const double* __restrict__ x, int64_t n,
+                                                   double* __restrict__ f, double* __restrict__ jac) {
+  const int p = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const bool valid = i < n;
+  double xi[VX_KMAX] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < K; j++) xi[j] = valid ? x[i * K + j] : 0.0;
+  double v, gr[VX_KMAX];
+  point_eval<K, GRAD>((const cdbl_t*)ss.s[p], ss.d[p], xi, v, gr);
+  if (!valid) return;
+  f[p * n + i] = v;
+  if (GRAD && jac) {
+#pragma unroll
+    for (int j = 0; j < K; j++) jac[(i * np + p) * K + j] = gr[j];
+  }
+}
+
+// Newton projection: x <- x - J^T (J J^T)^{-1} F, J the np x K Jacobian
+// (minimum-norm step in the span of the gradients).
+template <int K>
+__global__ __launch_bounds__(64) void k_newton(StreamSet ss, int np, double* __restrict__ x, int64_t n, int steps,
+                                               double* __restrict__ f_out) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const bool valid = i < n;
+  double xi[VX_KMAX] = {0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < K; j++) xi[j] = valid ? x[i * K + j] : 0.0;
+  double F[PMAX_GRAD], J[PMAX_GRAD][VX_KMAX];
+  for (int it = 0; it <= steps; it++) {
+    for (int p = 0; p < np; p++) {
+      double gr[VX_KMAX];
+      point_eval<K, true>((const cdbl_t*)ss.s[p], ss.d[p], xi, F[p], gr);
+#pragma unroll
+      for (int j = 0; j < K; j++) J[p][j] = gr[j];
+    }
+    if (it == steps) break;
+    // M = J J^T (np x np), solve M y = F by elimination with partial pivoting
+    double M[PMAX_GRAD][PMAX_GRAD + 1];
+    for (int a = 0; a < np; a++) {
+      for (int b = 0; b < np; b++) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < K; j++) s += J[a][j] * J[b][j];
+        M[a][b] = s;
+      }
+      M[a][np] = F[a];
+    }
+    bool ok = true;
+    for (int c = 0; c < np && ok; c++) {
+      int piv = c;
+      for (int r = c + 1; r < np; r++)
+        if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+      if (!(fabs(M[piv][c]) > 1e-300)) { ok = false; break; }
+      if (piv != c)
+        for (int q = 0; q <= np; q++) {
+          const double tmp = M[c][q];
+          M[c][q] = M[piv][q];
+          M[piv][q] = tmp;
+        }
+      for (int r = c + 1; r < np; r++) {
+        const double fct = M[r][c] / M[c][c];
+        for (int q = c; q <= np; q++) M[r][q] -= fct * M[c][q];
+      }
+    }
+    if (ok) {
+      double y[PMAX_GRAD];
+      for (int r = np - 1; r >= 0; r--) {
+        double s = M[r][np];
+        for (int q = r + 1; q < np; q++) s -= M[r][q] * y[q];
+        y[r] = s / M[r][r];
+      }
+#pragma unroll
+      for (int j = 0; j < K; j++) {
+        double s = 0.0;
+        for (int p = 0; p < np; p++) s += J[p][j] * y[p];
+        xi[j] -= s;
+      }
+    }
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int j = 0; j < K; j++) x[i * K + j] = xi[j];
+  if (f_out)
+    for (int p = 0; p < np; p++) f_out[p * n + i] = F[p];
+}
+
+// Centres of the leaves of a CSF (n x k, RN).
+__global__ void k_csf_centres(int k, int level, const int32_t* i0, const int32_t* i1, const int32_t* i2,
+                              const int32_t* i3, const int32_t* p0, const int32_t* p1, const int32_t* p2,
+                              int64_t n0, int64_t n1, int64_t n2, int64_t nleaf, AxisDom dom,
+                              double* __restrict__ x) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  const int32_t* idx[4] = {i0, i1, i2, i3};
+  const int32_t* ptr[3] = {p0, p1, p2};
+  const int64_t nn[3] = {n0, n1, n2};
+  int64_t node = b;
+  for (int l = k - 1; l >= 0; l--) {
+    x[b * k + l] = centre(dom.lo[l], dom.hi[l], level, idx[l][node]);
+    if (l > 0) {  // parent: last q with ptr[l-1][q] <= node
+      int64_t lo = 0, hi = nn[l - 1];
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ptr[l - 1][mid] <= node) lo = mid; else hi = mid;
+      }
+      node = lo;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coefficient adjoint on a CSF grid of centres: the transpose of the
+// amortized evaluation.  Depth by depth from the leaves, every parent row is
+//   out[(e, t)] = sum_{children q} x(q)^e * in_q[t]
+// (graded order of tuples); the leaf input is gbar.  Each output entry is one
+// lane summing over the children in order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int ADJ_CHUNK = 32;
+
+__global__ __launch_bounds__(256) void k_adjoint_level(int d, int m_in, const int32_t* __restrict__ ptr,
+                                                       int64_t nroot_children, const int32_t* __restrict__ labels,
+                                                       double dlo, double dhi, int level,
+                                                       const double* __restrict__ in, int64_t in_stride,
+                                                       double* __restrict__ out, int64_t out_stride,
+                                                       int64_t nout) {
+  __shared__ double pw[ADJ_CHUNK][MAXDEG_ADJ + 1];
+  __shared__ double xs[ADJ_CHUNK];
+  const int64_t parent = blockIdx.x;
+  const int64_t o = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  const bool act = o < nout;
+  int tt[VX_KMAX] = {0, 0, 0, 0};
+  if (act) g_unrank(o, m_in + 1, tt);
+  const int e = tt[0];
+  const int64_t tin = act ? g_rank(tt + 1, m_in) : 0;
+  const int64_t b = ptr ? ptr[parent] : 0, en = ptr ? ptr[parent + 1] : nroot_children;
+  double acc = 0.0;
+  for (int64_t c0 = b; c0 < en; c0 += ADJ_CHUNK) {
+    const int cn = (int)(en - c0 < ADJ_CHUNK ? en - c0 : ADJ_CHUNK);
+    __syncthreads();
+    if (threadIdx.x < cn) xs[threadIdx.x] = centre(dlo, dhi, level, labels[c0 + threadIdx.x]);
+    __syncthreads();
+    // powers x^0..x^d of every child in the chunk, by repeated multiplication
+    for (int q = threadIdx.x; q < cn; q += blockDim.x) {
+      double p = 1.0;
+      for (int j = 0; j <= d; j++) {
+        pw[q][j] = p;
+        p = p * xs[q];
+      }
+    }
+    __syncthreads();
+    if (act)
+      for (int q = 0; q < cn; q++) acc += pw[q][e] * in[(c0 + q) * in_stride + tin];
+  }
+  if (act) out[parent * out_stride + o] = acc;
+}
+
+// Scatter the root row (graded order, dimension k) into the dense cube.
+__global__ void k_adjoint_scatter(int k, int d, int side, const double* __restrict__ row, int64_t nrow,
+                                  double* __restrict__ cube) {
+  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nrow) return;
+  int t[VX_KMAX] = {0, 0, 0, 0};
+  g_unrank(o, k, t);
+  int64_t f = 0;
+  for (int i = 0; i < k; i++) f = f * side + t[i];
+  cube[f] = row[o];
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+// ---------------------------------------------------------------------------
+struct GradPlan {
+  double* stream[PMAX_GRAD] = {};
+  int64_t* plen[PMAX_GRAD] = {};
+  int64_t* start[PMAX_GRAD] = {};
+  int64_t* tiles = nullptr;
+  int64_t slen[PMAX_GRAD] = {};
+};
+
+static int64_t stream_chains(int k, int d) { return k >= 2 ? gbinom(d + k - 1, k - 1) : 1; }
+
+static int64_t stream_len_host(int k, int d) {
+  // sum over trailing tuples of SG*ceil((d-|t|+1)/SG): tuples of degree g: C(g+k-2, k-2)
+  int64_t s = 0;
+  for (int g = 0; g <= d; g++) {
+    const int64_t cnt = k >= 2 ? gbinom(g + k - 2, k - 2) : (g == 0 ? 1 : 0);
+    s += cnt * ((int64_t)(d - g + 1 + SG - 1) / SG * SG);
+  }
+  return s;
+}
+
+static void plan_grad(Arena& A, GradPlan& G, const vx_poly* P, int np) {
+  int64_t maxch = 1;
+  for (int p = 0; p < np; p++) {
+    const int k = P[p].k, d = P[p].degree;
+    G.slen[p] = stream_len_host(k, d);
+    G.stream[p] = A.take<double>(G.slen[p] + 2 * SG);
+    const int64_t nch = stream_chains(k, d);
+    G.plen[p] = A.take<int64_t>(nch + 1);
+    G.start[p] = A.take<int64_t>(nch + 1);
+    maxch = nch > maxch ? nch : maxch;
+  }
+  G.tiles = A.take<int64_t>(scan_tiles(maxch));
+}
+
+static int build_streams(GradPlan& G, const vx_poly* P, int np, hipStream_t st) {
+  for (int p = 0; p < np; p++) {
+    const int k = P[p].k, d = P[p].degree, side = P[p].side;
+    const int64_t nch = stream_chains(k, d);
+    int64_t tcube = 1;
+    for (int i = 1; i < k; i++) tcube *= side;
+    hipLaunchKernelGGL(k_stream_len, dim3((unsigned)((tcube + 255) / 256)), dim3(256), 0, st, k, d, side, G.plen[p]);
+    VX_CHECK_LAUNCH("k_stream_len");
+    scan_exclusive(I64Load{G.plen[p]}, (const int64_t*)nullptr, nch, G.start[p], (int64_t*)nullptr, G.tiles, st);
+    VX_CHECK_LAUNCH("stream scan");
+    VX_HIP(hipMemsetAsync(G.stream[p], 0, sizeof(double) * (G.slen[p] + 2 * SG), st));
+    int64_t cube = tcube * side;
+    hipLaunchKernelGGL(k_stream_fill, dim3((unsigned)((cube + 255) / 256)), dim3(256), 0, st, k, d, side, P[p].c_lo,
+                       (const int64_t*)G.start[p], G.stream[p]);
+    VX_CHECK_LAUNCH("k_stream_fill");
+  }
+  return VX_OK;
+}
+
+size_t grad_workspace_bytes(const vx_poly* P, int np, const vx_csf* grid, int64_t n) {
+  Arena A;
+  GradPlan G;
+  plan_grad(A, G, P, np);
+  A.take<double>((size_t)n * np * VX_KMAX + 1);
+  A.take<double>((size_t)n * np + 1);
+  if (grid) {
+    const int k = grid->k;
+    int dmax = 0;
+    for (int p = 0; p < np; p++) dmax = P[p].degree > dmax ? P[p].degree : dmax;
+    // adjoint rows: depth l nodes hold rows of dimension k - l
+    for (int l = 0; l < k; l++) A.take<double>((size_t)grid->n[l] * gbinom(dmax + k - l - 1, k - l - 1) + 1);
+    A.take<double>(gbinom(dmax + k, k) + 1);
+  }
+  return A.off + 256;
+}
+
+static StreamSet stream_set(const GradPlan& G, const vx_poly* P, int np) {
+  StreamSet ss;
+  memset(&ss, 0, sizeof ss);
+  for (int p = 0; p < np; p++) {
+    ss.s[p] = G.stream[p];
+    ss.d[p] = P[p].degree;
+  }
+  return ss;
+}
+
+// xbar[i][j] = sum_p gbar[p][i] jac[i][p][j]
+__global__ void k_contract_xbar(int np, int k, int64_t n, const double* __restrict__ gbar,
+                                const double* __restrict__ jac, double* __restrict__ xbar) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int j = 0; j < k; j++) {
+    double s = 0.0;
+    for (int p = 0; p < np; p++) s += gbar[p * n + i] * jac[(i * np + p) * k + j];
+    xbar[i * k + j] = s;
+  }
+}
+
+int grad_impl(const vx_poly* P, int np, const double* x, int64_t n, double* f, double* jac, const double* gbar,
+              double* xbar, double* dcoef, const vx_csf* grid, const double* dom, void* ws, size_t ws_bytes,
+              hipStream_t st) {
+  const int k = P[0].k;
+  Arena A;
+  A.base = reinterpret_cast<char*>(ws);
+  A.size = ws_bytes;
+  GradPlan G;
+  plan_grad(A, G, P, np);
+  double* rows[VX_KMAX] = {};
+  double* root = nullptr;
+  int dmax = 0;
+  for (int p = 0; p < np; p++) dmax = P[p].degree > dmax ? P[p].degree : dmax;
+  if (grid && dcoef) {
+    for (int l = 0; l < k; l++) rows[l] = A.take<double>((size_t)grid->n[l] * gbinom(dmax + k - l - 1, k - l - 1) + 1);
+    root = A.take<double>(gbinom(dmax + k, k) + 1);
+  }
+  double* jac_tmp = nullptr;
+  if (xbar && !jac) jac_tmp = A.take<double>((size_t)n * np * k + 1);
+  if (A.overflow) VX_FAIL(VX_ECAPACITY, "eval_grad: workspace of %zu bytes is too small (%zu needed)", ws_bytes, A.off + 256);
+  int rc;
+  if ((rc = build_streams(G, P, np, st))) return rc;
+  const StreamSet ss = stream_set(G, P, np);
+  if (jac_tmp) jac = jac_tmp;
+  double* f_tmp = nullptr;
+  if (n > 0 && (f || jac)) {
+    if (!f) {
+      f_tmp = A.take<double>((size_t)n * np + 1);
+      if (A.overflow) VX_FAIL(VX_ECAPACITY, "eval_grad: workspace too small");
+      f = f_tmp;
+    }
+    dim3 grid3((unsigned)((n + 63) / 64), (unsigned)np);
+    const bool gradf = jac != nullptr;
+#define VX_PE(KK)                                                                                       \
+  if (gradf)                                                                                            \
+    hipLaunchKernelGGL((k_point_eval<KK, true>), grid3, dim3(64), 0, st, ss, np, x, n, f, jac);         \
+  else                                                                                                  \
+    hipLaunchKernelGGL((k_point_eval<KK, false>), grid3, dim3(64), 0, st, ss, np, x, n, f, jac);
+    switch (k) {
+      case 1: VX_PE(1) break;
+      case 2: VX_PE(2) break;
+      case 3: VX_PE(3) break;
+      default: VX_PE(4) break;
+    }
+#undef VX_PE
+    VX_CHECK_LAUNCH("k_point_eval");
+  }
+  if (xbar && n > 0) {
+    hipLaunchKernelGGL(k_contract_xbar, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, np, k, n, gbar,
+                       (const double*)jac, xbar);
+    VX_CHECK_LAUNCH("k_contract_xbar");
+  }
+  if (dcoef && gbar) {
+    if (!grid) VX_FAIL(VX_EUNSUPPORTED, "eval_grad: coefficient gradients need points given as a CSF grid");
+    for (int p = 0; p < np; p++) {
+      const int d = P[p].degree;
+      // leaves -> depth k-1 rows (dimension 1) -> ... -> root row (dimension k)
+      const double* in = gbar + (int64_t)p * grid->n[k - 1];
+      int64_t in_stride = 1;
+      for (int l = k - 1; l >= 0; l--) {
+        const int m_in = k - 1 - l;
+        const int64_t nout = gbinom(d + m_in + 1, m_in + 1);
+        const int64_t nparent = l == 0 ? 1 : grid->n[l - 1];
+        double* out = l == 0 ? root : rows[l - 1];
+        dim3 g2((unsigned)nparent, (unsigned)((nout + 255) / 256));
+        hipLaunchKernelGGL(k_adjoint_level, g2, dim3(256), 0, st, d, m_in, l == 0 ? nullptr : grid->ptr[l - 1],
+                           grid->n[0], grid->idx[l], dom[2 * l], dom[2 * l + 1], grid->level, in, in_stride, out,
+                           nout, nout);
+        VX_CHECK_LAUNCH("k_adjoint_level");
+        in = out;
+        in_stride = nout;
+      }
+      int64_t cube = 1;
+      for (int i = 0; i < k; i++) cube *= P[p].side;
+      double* dc = dcoef + (int64_t)p * cube;
+      VX_HIP(hipMemsetAsync(dc, 0, sizeof(double) * cube, st));
+      const int64_t nrow = gbinom(d + k, k);
+      hipLaunchKernelGGL(k_adjoint_scatter, dim3((unsigned)((nrow + 255) / 256)), dim3(256), 0, st, k, d, P[p].side,
+                         (const double*)root, nrow, dc);
+      VX_CHECK_LAUNCH("k_adjoint_scatter");
+    }
+  }
+  return VX_OK;
+}
+
+int newton_impl(const vx_poly* P, int np, double* x, int64_t n, int steps, double* f, void* ws, size_t ws_bytes,
+                hipStream_t st) {
+  const int k = P[0].k;
+  Arena A;
+  A.base = reinterpret_cast<char*>(ws);
+  A.size = ws_bytes;
+  GradPlan G;
+  plan_grad(A, G, P, np);
+  if (A.overflow) VX_FAIL(VX_ECAPACITY, "newton_project: workspace too small (%zu needed)", A.off + 256);
+  int rc;
+  if ((rc = build_streams(G, P, np, st))) return rc;
+  const StreamSet ss = stream_set(G, P, np);
+  if (n == 0) return VX_OK;
+  dim3 g1((unsigned)((n + 63) / 64));
+  switch (k) {
+    case 1: hipLaunchKernelGGL(k_newton<1>, g1, dim3(64), 0, st, ss, np, x, n, steps, f); break;
+    case 2: hipLaunchKernelGGL(k_newton<2>, g1, dim3(64), 0, st, ss, np, x, n, steps, f); break;
+    case 3: hipLaunchKernelGGL(k_newton<3>, g1, dim3(64), 0, st, ss, np, x, n, steps, f); break;
+    default: hipLaunchKernelGGL(k_newton<4>, g1, dim3(64), 0, st, ss, np, x, n, steps, f); break;
+  }
+  VX_CHECK_LAUNCH("k_newton");
+  return VX_OK;
+}
+
+int centres_impl(const vx_csf* S, const double* dom, double* x, hipStream_t st) {
+  const int k = S->k;
+  const int64_t n = S->n[k - 1];
+  if (n == 0) return VX_OK;
+  AxisDom ad;
+  memset(&ad, 0, sizeof ad);
+  for (int j = 0; j < k; j++) {
+    ad.lo[j] = dom[2 * j];
+    ad.hi[j] = dom[2 * j + 1];
+  }
+  hipLaunchKernelGGL(k_csf_centres, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, S->level, S->idx[0],
+                     S->idx[1], S->idx[2], S->idx[3], S->ptr[0], S->ptr[1], S->ptr[2], S->n[0], S->n[1], S->n[2], n,
+                     ad, x);
+  VX_CHECK_LAUNCH("k_csf_centres");
+  return VX_OK;
+}
+
+}  // namespace vx

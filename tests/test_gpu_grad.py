@@ -1,0 +1,204 @@
+"""Point evaluation, adjoint and Newton projection on the GPU.
+
+* values: bit-identical to the oracle's round-to-nearest nested Horner;
+* Jacobian: the oracle's derivative polynomials (coefficients e_j c_e),
+  within the Horner error bound, and central finite differences;
+* coefficient adjoint on a CSF grid of centres: exact rational sums;
+* Newton projection onto sphere ∩ plane converges to the exact circle;
+* the torch.autograd.Function passes gradcheck.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import core as orc
+from paper_2406_09857_amd import synth
+from tests.helpers import bits_equal
+
+pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def vx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_09857_amd import binding
+    binding.lib()
+    return binding
+
+
+def deriv_cube(c, j):
+    """Coefficients of dF/dx_j: e_j c_e moved to exponent e - u_j (rounded to nearest)."""
+    k = c.ndim
+    e = np.indices(c.shape)[j].astype(np.float64)
+    d = c * e
+    sl = [slice(None)] * k
+    sl[j] = slice(1, None)
+    out = np.zeros_like(c)
+    osl = [slice(None)] * k
+    osl[j] = slice(0, c.shape[j] - 1)
+    out[tuple(osl)] = d[tuple(sl)]
+    return out
+
+
+def horner_bound(c, dgr, x):
+    """gamma_{4d} * |P|(|x|): error bound of a nested Horner evaluation."""
+    absv = orc.eval_points(np.abs(c), dgr, np.abs(x))
+    return 4 * (4 * dgr + 8) * EPS * absv
+
+
+@pytest.mark.parametrize("k,d", [(1, 30), (2, 20), (3, 12), (4, 6), (3, 100)])
+def test_values_bitexact_and_jacobian(vx, k, d):
+    import torch
+    print(f"[grad] k={k} d={d}", flush=True)
+    rng = np.random.default_rng(1000 + k * 10 + d)
+    polys = synth.small_random(k, d, seed=1100 + d, npolys=2)
+    x = rng.uniform(-1, 1, size=(777 if d < 100 else 200, k))
+    f, jac, _, _ = vx.eval_grad(polys, torch.as_tensor(x, device="cuda"))
+    f = f.cpu().numpy(); jac = jac.cpu().numpy()
+    for p, c in enumerate(polys):
+        ref = orc.eval_points(c, d, x)
+        assert bits_equal(f[p], ref)
+        for j in range(k):
+            dc = deriv_cube(c, j)
+            dref = orc.eval_points(dc, d, x)
+            tol = horner_bound(dc, d, x) + horner_bound(c, d, x) * d
+            assert np.all(np.abs(jac[:, p, j] - dref) <= tol + 1e-300), (p, j)
+
+
+def test_jacobian_central_differences(vx):
+    import torch
+    rng = np.random.default_rng(5)
+    w = synth.tiny()
+    c = w.polys[0] / 100.0
+    x = rng.uniform(-0.8, 0.8, size=(500, 2))
+    h = 1e-6
+    _, jac, _, _ = vx.eval_grad([c], torch.as_tensor(x, device="cuda"))
+    jac = jac.cpu().numpy()[:, 0, :]
+    for j in range(2):
+        xp = x.copy(); xp[:, j] += h
+        xm = x.copy(); xm[:, j] -= h
+        fp = vx.eval_grad([c], torch.as_tensor(xp, device="cuda"), want_jac=False)[0].cpu().numpy()[0]
+        fm = vx.eval_grad([c], torch.as_tensor(xm, device="cuda"), want_jac=False)[0].cpu().numpy()[0]
+        fd = (fp - fm) / (2 * h)
+        rel = np.abs(fd - jac[:, j]) / np.maximum(np.abs(jac).max(axis=1), 1e-30)
+        assert np.max(rel) <= 1e-7, np.max(rel)
+
+
+def _grid(level, k, n, seed):
+    rng = np.random.default_rng(seed)
+    return orc.csf_from_boxes(rng.integers(0, 1 << level, size=(n, k)), level)
+
+
+def test_coefficient_adjoint_exact(vx):
+    import torch
+    k, d, level = 3, 5, 3
+    S = _grid(level, k, 150, 11)
+    c = synth.small_random(k, d, seed=12)[0]
+    dom = np.array([-1.0, 1.0] * k)
+    csf = vx.CSF.from_arrays(k, level, S["idx"], S["ptr"])
+    x = vx.csf_centres(csf, dom)
+    xs = x.cpu().numpy()
+    # centres are exact dyadics
+    want = -1.0 + (2 * S["boxes"] + 1) / (1 << level)
+    assert np.array_equal(xs, want)
+    rng = np.random.default_rng(13)
+    gbar = rng.standard_normal((1, xs.shape[0]))
+    _, _, xbar, dcoef = vx.eval_grad([c], x, want_jac=True, gbar=torch.as_tensor(gbar, device="cuda"),
+                                     want_xbar=True, want_dcoef=True, grid=csf, dom=dom)
+    dcoef = dcoef.cpu().numpy()[0]
+    fx = [[Fraction(float(v)) for v in row] for row in xs]
+    fg = [Fraction(float(v)) for v in gbar[0]]
+    for e in np.argwhere(synth.simplex_mask(k, d)):
+        ex = sum(g * fx_i[0] ** int(e[0]) * fx_i[1] ** int(e[1]) * fx_i[2] ** int(e[2]) for g, fx_i in zip(fg, fx))
+        bound = sum(abs(g) * abs(fx_i[0]) ** int(e[0]) * abs(fx_i[1]) ** int(e[1]) * abs(fx_i[2]) ** int(e[2])
+                    for g, fx_i in zip(fg, fx))
+        tol = (len(fg) + 3 * d + 4) * EPS * float(bound)
+        assert abs(float(Fraction(float(dcoef[tuple(e)])) - ex)) <= tol + 1e-300, tuple(e)
+    outside = ~synth.simplex_mask(k, d)
+    assert np.all(dcoef[outside] == 0.0)
+    # xbar = gbar * dF/dx
+    _, jac, _, _ = vx.eval_grad([c], x)
+    assert np.allclose(xbar.cpu().numpy(), gbar[0][:, None] * jac.cpu().numpy()[:, 0, :], rtol=0, atol=0)
+
+
+def test_coefficient_adjoint_curve_sample(vx):
+    """Degree-100 curve polynomials on the kept centres of level 6 (oracle
+    subdivision): sampled coefficients against long-double sums with bounds."""
+    import torch
+    w = synth.curve()
+    rec = orc.subdivide(w.polys, 3, 6, nthreads=orc.max_threads())[-1]
+    K = orc.csf_from_boxes(rec["kept"], 6)
+    csf = vx.CSF.from_arrays(3, 6, K["idx"], K["ptr"])
+    dom = w.domain()
+    x = vx.csf_centres(csf, dom)
+    rng = np.random.default_rng(21)
+    gbar = rng.standard_normal((2, x.shape[0]))
+    _, _, _, dcoef = vx.eval_grad(w.polys, x, want_jac=False, gbar=torch.as_tensor(gbar, device="cuda"),
+                                  want_dcoef=True, grid=csf, dom=dom)
+    dcoef = dcoef.cpu().numpy()
+    xs = x.cpu().numpy().astype(np.longdouble)
+    es = np.argwhere(synth.simplex_mask(3, 100))
+    for e in es[rng.choice(len(es), 60, replace=False)]:
+        mono = xs[:, 0] ** int(e[0]) * xs[:, 1] ** int(e[1]) * xs[:, 2] ** int(e[2])
+        for p in range(2):
+            ref = np.sum(gbar[p].astype(np.longdouble) * mono)
+            bound = np.sum(np.abs(gbar[p]) * np.abs(mono))
+            tol = (x.shape[0] + 310) * EPS * float(bound)
+            assert abs(float(dcoef[p][tuple(e)]) - float(ref)) <= tol + 1e-300
+
+
+def test_newton_projects_onto_sphere_plane_circle(vx):
+    import torch
+    polys = [synth.sphere(), synth.plane_x3()]
+    recs = orc.subdivide(polys, 3, 5)
+    K = orc.csf_from_boxes(recs[-1]["kept"], 5)
+    csf = vx.CSF.from_arrays(3, 5, K["idx"], K["ptr"])
+    x = vx.csf_centres(csf, np.array([-1.0, 1.0] * 3))
+    f0 = vx.eval_grad(polys, x, want_jac=False)[0].abs().max().item()
+    x, f = vx.newton_project(polys, x, steps=3)
+    assert f0 > 1e-3 and f.abs().max().item() < 1e-9  # quadratic convergence from cells of width 1/16
+    x, f = vx.newton_project(polys, x, steps=3)
+    xs = x.cpu().numpy()
+    assert f.abs().max().item() < 1e-14
+    assert np.all(np.abs(xs[:, 2] - 1.0 / 3.0) < 1e-14)
+    assert np.all(np.abs(xs[:, 0] ** 2 + xs[:, 1] ** 2 - (0.5 - (1.0 / 3.0) ** 2)) < 1e-14)
+
+
+def test_newton_reduces_residual_on_curve(vx):
+    import torch
+    w = synth.curve()
+    rec = orc.subdivide(w.polys, 3, 5, nthreads=orc.max_threads())[-1]
+    K = orc.csf_from_boxes(rec["kept"], 5)
+    csf = vx.CSF.from_arrays(3, 5, K["idx"], K["ptr"])
+    x = vx.csf_centres(csf, w.domain())
+    f0 = vx.eval_grad(w.polys, x, want_jac=False)[0].abs().amax(dim=0)
+    x, f = vx.newton_project(w.polys, x, steps=3)
+    f1 = f.abs().amax(dim=0)
+    assert torch.median(f1).item() < 1e-6 * torch.median(f0).item()
+
+
+def test_polyeval_gradcheck(vx):
+    import torch
+    from torch.autograd import gradcheck
+    c1, c2 = (torch.as_tensor(c, device="cuda") for c in synth.small_random(3, 4, seed=31, npolys=2))
+    rng = np.random.default_rng(32)
+    x = torch.as_tensor(rng.uniform(-0.9, 0.9, size=(20, 3)), device="cuda").requires_grad_(True)
+    vx.PolyEval.grid = None
+    assert gradcheck(lambda xx: vx.PolyEval.apply(xx, c1, c2), (x,), eps=1e-6, atol=1e-7, rtol=1e-6)
+    # coefficient gradients on a grid of centres
+    S = _grid(3, 3, 30, 33)
+    csf = vx.CSF.from_arrays(3, 3, S["idx"], S["ptr"])
+    dom = np.array([-1.0, 1.0] * 3)
+    xg = vx.csf_centres(csf, dom)
+    vx.PolyEval.grid = (csf, dom)
+    a = c1.clone().requires_grad_(True)
+    b = c2.clone().requires_grad_(True)
+    try:
+        assert gradcheck(lambda p, q: vx.PolyEval.apply(xg, p, q), (a, b), eps=1e-6, atol=1e-7, rtol=1e-6)
+    finally:
+        vx.PolyEval.grid = None
