@@ -220,6 +220,78 @@ int csf_centres(const vx_csf* S, const double* dom, double* x, void* stream);
 int newton_project(const vx_poly* P, int32_t np, double* x, int64_t n, int32_t steps, double* f, void* ws,
                    size_t ws_bytes, void* stream);
 
+/*
+ * Batched subdivision -- many independent systems run through Algorithm 3 in
+ * lockstep (all levels 0..depth), for workloads of many small problems where
+ * one system cannot fill the GPU.  Sec. 3.2 runs independent subdivisions in
+ * parallel on CPU threads; here every kernel covers all systems at once.
+ *
+ * The box sets of all systems form one CSF with an extra top depth: depth 0
+ * holds one node per live system (label = system index), depths 1..k hold the
+ * grid indices as in vx_csf.  Every count stays on the device and every
+ * kernel is a fixed-shape persistent grid-stride loop, so one run is a fixed
+ * launch sequence that can be captured once as a HIP graph and replayed.
+ * Each system's boxes, enclosures and keep flags are bit-identical to
+ * run_subdivision on that system alone (same arithmetic in the same order).
+ *
+ * Scope: k = 3 and one polynomial per system (C0 on a single equation),
+ * 1 <= nsys <= 64, one domain for all systems.
+ *
+ *   cap   : host int64[k+1], node capacity per depth of the batched CSF
+ *           (cap[0] >= nsys).  A run that would exceed it stops growing,
+ *           finishes with empty levels, and vx_batch_result reports
+ *           VX_ECAPACITY together with the counts it needed.
+ *   tune  : host array of depth+1 launch configurations (one per level), or
+ *           NULL for defaults: r1 = depth-1 nodes per stage-1 wave (1, 2, 4
+ *           or 8), groups = chain groups per middle-stage segment (1..64),
+ *           grid = workgroups of the evaluation kernels (64..65536).
+ *           The configuration changes the work distribution only, never a
+ *           result.
+ *   flags : VX_BATCH_GRAPH = capture the run as a HIP graph on the first
+ *           vx_batch_run and replay it afterwards (captured on a private
+ *           stream, launched on the caller's).
+ *   ws    : device workspace of vx_batch_workspace_bytes(P, nsys, depth, cap)
+ *           bytes, owned by the caller, used by the handle until
+ *           vx_batch_destroy.  The coefficient buffers of P are read by every
+ *           run (the tables are rebuilt at the start of each run).
+ * The handle holds host state only (configuration, graph); it is not
+ * thread-safe, and runs of one handle must not overlap.
+ */
+typedef struct vx_batch vx_batch;
+typedef struct vx_batch_tune {
+  int32_t r1;
+  int32_t groups;
+  int32_t grid;
+  int32_t reserved;
+} vx_batch_tune;
+enum { VX_BATCH_GRAPH = 1 };
+
+size_t vx_batch_workspace_bytes(const vx_poly* P, int32_t nsys, int32_t depth, const int64_t* cap);
+int vx_batch_create(const vx_poly* P, int32_t nsys, const double* dom, int32_t depth, const int64_t* cap,
+                    const vx_batch_tune* tune, int32_t flags, void* ws, size_t ws_bytes, void* stream,
+                    vx_batch** out);
+/* Enqueue one whole run (levels 0..depth) on `stream`; does not wait. */
+int vx_batch_run(vx_batch* b, void* stream);
+/* Wait for the stream, then report the last run:
+ *   stats : host int64[(depth+1) * 2 * VX_KMAX] or NULL; per level, the node
+ *           counts of the evaluated set (depths 0..k) then of the kept set,
+ *           summed over systems.
+ *   need  : host int64[k+1] or NULL: the largest node counts per depth the
+ *           run reached (a sufficient `cap` after VX_ECAPACITY, as far as the
+ *           run got).
+ *   last  : batched CSF (k+1 depths, caps >= counts) receiving the evaluated
+ *           set of the last level, or NULL; lo/hi/keep: device arrays of its
+ *           leaves' enclosures and keep flags, or NULL.
+ *   kept  : batched CSF receiving the kept set of the last level, or NULL. */
+int vx_batch_result(vx_batch* b, int64_t* stats, int64_t* need, vx_csf* last, double* lo, double* hi, uint8_t* keep,
+                    vx_csf* kept, void* stream);
+/* Autotuner: run every candidate configuration `reps` times eagerly, and
+ * keep per level the fastest (written to chosen[depth+1] and its time to
+ * level_ms[depth+1], either may be NULL).  Waits for the stream. */
+int vx_batch_autotune(vx_batch* b, const vx_batch_tune* cand, int32_t ncand, int32_t reps, vx_batch_tune* chosen,
+                      float* level_ms, void* stream);
+void vx_batch_destroy(vx_batch* b);
+
 /* Per-kernel timing.  vx_profile_begin() starts recording HIP events around
  * every evaluation and filter kernel launched afterwards from any host thread;
  * vx_profile_end() waits for the recorded events, fills up to `max` records

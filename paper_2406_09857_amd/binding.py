@@ -477,3 +477,194 @@ class PolyEval(torch.autograd.Function):
         gx = xbar if ctx.needs_input_grad[0] else None
         gcs = [dcoef[i] if (want_dc and ctx.needs_input_grad[1 + i]) else None for i in range(len(coefs))]
         return (gx, *gcs)
+
+
+# ---------------------------------------------------------------------------
+# Batched subdivision of many independent systems
+# ---------------------------------------------------------------------------
+
+class vx_batch_tune(C.Structure):
+    _fields_ = [("r1", C.c_int32), ("groups", C.c_int32), ("grid", C.c_int32), ("reserved", C.c_int32)]
+
+
+VX_BATCH_GRAPH = 1
+
+
+def _batch_lib():
+    L = lib()
+    if not getattr(L, "_batch_ready", False):
+        vp = C.c_void_p
+        i64p = C.POINTER(C.c_int64)
+        L.vx_batch_workspace_bytes.argtypes = [C.POINTER(vx_poly), C.c_int32, C.c_int32, i64p]
+        L.vx_batch_workspace_bytes.restype = C.c_size_t
+        L.vx_batch_create.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(C.c_double), C.c_int32, i64p,
+                                      C.POINTER(vx_batch_tune), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.vx_batch_run.argtypes = [vp, vp]
+        L.vx_batch_result.argtypes = [vp, i64p, i64p, C.POINTER(vx_csf), vp, vp, vp, C.POINTER(vx_csf), vp]
+        L.vx_batch_autotune.argtypes = [vp, C.POINTER(vx_batch_tune), C.c_int32, C.c_int32,
+                                        C.POINTER(vx_batch_tune), C.POINTER(C.c_float), vp]
+        L.vx_batch_destroy.argtypes = [vp]
+        L.vx_batch_destroy.restype = None
+        for f in ("vx_batch_create", "vx_batch_run", "vx_batch_result", "vx_batch_autotune"):
+            getattr(L, f).restype = C.c_int
+        L._batch_ready = True
+    return L
+
+
+def _system_poly(s):
+    """One polynomial per system: a cube, a Poly, or a one-element list."""
+    if isinstance(s, list):
+        if len(s) != 1:
+            raise ValueError("the batched path takes one polynomial per system")
+        s = s[0]
+    return as_polys([s])[0]
+
+
+def batch_caps_guess(nsys: int, depth: int) -> list:
+    """Starting node capacities of a batched trivariate run: exact at depths 0
+    and 1 (systems, x1 cells), a surface-sized guess below."""
+    c2 = max(nsys * (4 ** depth) // 8, 4096)
+    return [nsys, nsys << depth, c2, 4 * c2]
+
+
+class Batch:
+    """A batched run of independent systems (``vx_batch_*``): create once,
+    ``run()`` many times (a HIP graph replay when ``graph``), ``result()``."""
+
+    def __init__(self, systems, dom, depth: int, cap=None, tune=None, graph: bool = True, stream=None):
+        L = _batch_lib()
+        self.polys = [_system_poly(s) for s in systems]
+        self.nsys = len(self.polys)
+        self.k = self.polys[0].k
+        self.depth = depth
+        self.dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
+        self._parr = _poly_array(self.polys)
+        self.cap = [int(c) for c in (cap if cap is not None else batch_caps_guess(self.nsys, depth))]
+        capa = (C.c_int64 * KMAX)(*(self.cap + [0] * (KMAX - len(self.cap))))
+        need = int(L.vx_batch_workspace_bytes(self._parr, self.nsys, depth, capa))
+        if need == 0:
+            _check(VX_EINVAL)
+        self.ws = _ws(need)
+        tarr = None
+        if tune is not None:
+            tarr = (vx_batch_tune * (depth + 1))(*[vx_batch_tune(*t, 0) for t in tune])
+        h = C.c_void_p()
+        _check(L.vx_batch_create(self._parr, self.nsys, self.dom.ctypes.data_as(C.POINTER(C.c_double)), depth, capa,
+                                 tarr, VX_BATCH_GRAPH if graph else 0, self.ws.data_ptr(), self.ws.numel(),
+                                 _stream(stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _batch_lib().vx_batch_destroy(self._h)
+            self._h = None
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, stream=None):
+        _check(_batch_lib().vx_batch_run(self._h, _stream(stream)))
+
+    def autotune(self, candidates=None, reps: int = 2, stream=None):
+        """Per-level fastest of the candidates [(r1, groups, grid), ...];
+        returns (chosen configs, per-level ms)."""
+        if candidates is None:
+            candidates = [(r, g, grid) for r in (4, 8) for g in (1, 2, 4) for grid in (2048, 8192)]
+        ca = (vx_batch_tune * len(candidates))(*[vx_batch_tune(*c, 0) for c in candidates])
+        ch = (vx_batch_tune * (self.depth + 1))()
+        ms = (C.c_float * (self.depth + 1))()
+        _check(_batch_lib().vx_batch_autotune(self._h, ca, len(candidates), reps, ch, ms, _stream(stream)))
+        return [(c.r1, c.groups, c.grid) for c in ch], list(ms)
+
+    def result(self, want_last: bool = True, want_kept: bool = True, stream=None) -> dict:
+        """Waits; per-level counts, high-water marks, the last level's
+        evaluated set with enclosures and keep flags, and its kept set
+        (outputs sized from the counts of a first, counts-only call)."""
+        L = _batch_lib()
+        nl = self.depth + 1
+        kk = self.k + 1
+        stats = (C.c_int64 * (nl * 2 * KMAX))()
+        need = (C.c_int64 * KMAX)()
+        rc = L.vx_batch_result(self._h, stats, need, None, None, None, None, None, _stream(stream))
+        st = np.array(stats[:], dtype=np.int64).reshape(nl, 2, KMAX)
+        out = {"stats": st, "need": list(need)[:kk], "rc": rc}
+        if rc != VX_OK:
+            out["error"] = lib().vx_last_error().decode()
+            return out
+        if not (want_last or want_kept):
+            return out
+        nS, nK = [int(v) for v in st[self.depth, 0, :kk]], [int(v) for v in st[self.depth, 1, :kk]]
+        dev = _dev()
+        last = CSF.empty(kk, self.depth, nS, dev) if want_last else None
+        kept = CSF.empty(kk, self.depth, nK, dev) if want_kept else None
+        nb = max(1, nS[self.k])
+        lo = torch.empty(nb, dtype=torch.float64, device=dev) if want_last else None
+        hi = torch.empty(nb, dtype=torch.float64, device=dev) if want_last else None
+        kp = torch.empty(nb, dtype=torch.uint8, device=dev) if want_last else None
+        ls = last.struct() if last else None
+        ks = kept.struct() if kept else None
+        _check(L.vx_batch_result(self._h, None, None, C.byref(ls) if ls else None,
+                                 lo.data_ptr() if lo is not None else None, hi.data_ptr() if hi is not None else None,
+                                 kp.data_ptr() if kp is not None else None, C.byref(ks) if ks else None,
+                                 _stream(stream)))
+        if last:
+            last.n = [int(ls.n[l]) for l in range(kk)]
+            out.update(last=last, lo=lo[: nS[self.k]], hi=hi[: nS[self.k]], keep=kp[: nS[self.k]])
+        if kept:
+            kept.n = [int(ks.n[l]) for l in range(kk)]
+            out["kept"] = kept
+        return out
+
+
+def split_systems(csf_np: dict, nsys: int) -> list:
+    """Per-system leaf boxes ((n, k) int64, lexicographic) of a batched CSF
+    given as numpy arrays (``CSF.to_numpy()``), plus each system's leaf
+    range in the batched leaf order."""
+    idx, ptr = csf_np["idx"], csf_np["ptr"]
+    kk = len(idx)
+    # parent of every node at each depth
+    owner = [np.arange(len(idx[0]))]
+    for l in range(1, kk):
+        owner.append(np.repeat(np.arange(len(idx[l - 1])), np.diff(ptr[l - 1])))
+    cols = []
+    node = np.arange(len(idx[kk - 1]))
+    for l in range(kk - 1, 0, -1):
+        cols.append(idx[l][node])
+        node = owner[l][node]
+    sys_of_leaf = idx[0][node]
+    boxes = np.stack(cols[::-1], axis=1).astype(np.int64) if cols else np.zeros((len(node), 0), np.int64)
+    out = []
+    for s in range(nsys):
+        sel = np.nonzero(sys_of_leaf == s)[0]
+        out.append({"boxes": boxes[sel], "leaves": sel})
+    return out
+
+
+def run_subdivision_batch(systems, dom, depth: int, graph: bool = True, autotune: bool = False, cap=None,
+                          stream=None, max_tries: int = 6):
+    """Batched Algorithm 3 (C0) on independent systems.  Grows the node
+    capacities and retries when a run outgrows them.  Returns (Batch, result)."""
+    cap = list(cap) if cap is not None else None
+    for _ in range(max_tries):
+        b = Batch(systems, dom, depth, cap=cap, graph=graph, stream=stream)
+        b.run(stream)
+        r = b.result(stream=stream)
+        if r["rc"] == VX_ECAPACITY:
+            cap = [max(int(n), 2 * c) if n >= c else c for n, c in zip(r["need"], b.cap)]
+            b.close()
+            del b
+            continue
+        if r["rc"] != VX_OK:
+            raise VxError(r["rc"], r.get("error", ""))
+        if autotune:
+            b.autotune(stream=stream)
+            b.run(stream)
+            r = b.result(stream=stream)
+            if r["rc"] != VX_OK:
+                raise VxError(r["rc"], r.get("error", ""))
+        return b, r
+    raise VxError(VX_ECAPACITY, "batched run still outgrows its capacities")

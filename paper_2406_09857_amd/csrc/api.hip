@@ -367,6 +367,71 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
   return VX_OK;
 }
 
+static int check_batch(const vx_poly* P, int32_t nsys, int32_t depth, const int64_t* cap) {
+  if (!P || nsys < 1 || nsys > VX_MAXPOLY) VX_FAIL(VX_EINVAL, "batch: 1..%d systems", VX_MAXPOLY);
+  if (P[0].k != 3) VX_FAIL(VX_EUNSUPPORTED, "batch: implemented for k = 3 (got k = %d)", P[0].k);
+  int rc;
+  if ((rc = check_poly(P, nsys, 3))) return rc;
+  if (depth < 0 || depth > 28) VX_FAIL(VX_EINVAL, "batch: depth %d outside [0, 28]", depth);
+  if (!cap) VX_FAIL(VX_EINVAL, "batch: null capacities");
+  if (cap[0] < nsys) VX_FAIL(VX_EINVAL, "batch: cap[0] = %lld < %d systems", (long long)cap[0], nsys);
+  for (int l = 0; l <= 3; l++)
+    if (cap[l] < 1 || cap[l] >= ((int64_t)1 << 31) - 2)
+      VX_FAIL(VX_EINVAL, "batch: cap[%d] = %lld outside [1, 2^31 - 3]", l, (long long)cap[l]);
+  return VX_OK;
+}
+
+static int check_tune(const vx_batch_tune* t, int n) {
+  for (int i = 0; i < n; i++) {
+    const int r = t[i].r1;
+    if (r != 1 && r != 2 && r != 4 && r != 8) VX_FAIL(VX_EINVAL, "batch tune %d: r1 = %d not in {1, 2, 4, 8}", i, r);
+    if (t[i].groups < 1 || t[i].groups > 64) VX_FAIL(VX_EINVAL, "batch tune %d: groups = %d", i, t[i].groups);
+    if (t[i].grid < 64 || t[i].grid > 65536) VX_FAIL(VX_EINVAL, "batch tune %d: grid = %d", i, t[i].grid);
+  }
+  return VX_OK;
+}
+
+size_t vx_batch_workspace_bytes(const vx_poly* P, int32_t nsys, int32_t depth, const int64_t* cap) {
+  if (check_batch(P, nsys, depth, cap)) return 0;
+  return batch_workspace_bytes(P, nsys, depth, cap);
+}
+
+int vx_batch_create(const vx_poly* P, int32_t nsys, const double* dom, int32_t depth, const int64_t* cap,
+                    const vx_batch_tune* tune, int32_t flags, void* ws, size_t ws_bytes, void* stream,
+                    vx_batch** out) {
+  int rc;
+  if (!out) VX_FAIL(VX_EINVAL, "batch: null handle output");
+  *out = nullptr;
+  if ((rc = check_batch(P, nsys, depth, cap))) return rc;
+  if ((rc = check_dom(dom, 3))) return rc;
+  if (tune && (rc = check_tune(tune, depth + 1))) return rc;
+  if (flags & ~VX_BATCH_GRAPH) VX_FAIL(VX_EINVAL, "batch: unknown flags 0x%x", flags);
+  if (!ws) VX_FAIL(VX_EINVAL, "batch: null workspace");
+  return batch_create_impl(P, nsys, dom, depth, cap, tune, flags, ws, ws_bytes, (hipStream_t)stream, out);
+}
+
+int vx_batch_run(vx_batch* b, void* stream) {
+  if (!b) VX_FAIL(VX_EINVAL, "batch: null handle");
+  return batch_run_impl(b, (hipStream_t)stream);
+}
+
+int vx_batch_result(vx_batch* b, int64_t* stats, int64_t* need, vx_csf* last, double* lo, double* hi, uint8_t* keep,
+                    vx_csf* kept, void* stream) {
+  if (!b) VX_FAIL(VX_EINVAL, "batch: null handle");
+  return batch_result_impl(b, stats, need, last, lo, hi, keep, kept, (hipStream_t)stream);
+}
+
+int vx_batch_autotune(vx_batch* b, const vx_batch_tune* cand, int32_t ncand, int32_t reps, vx_batch_tune* chosen,
+                      float* level_ms, void* stream) {
+  int rc;
+  if (!b) VX_FAIL(VX_EINVAL, "batch: null handle");
+  if (!cand || ncand < 1 || ncand > 256 || reps < 1 || reps > 16) VX_FAIL(VX_EINVAL, "batch autotune: bad candidates");
+  if ((rc = check_tune(cand, ncand))) return rc;
+  return batch_autotune_impl(b, cand, ncand, reps, chosen, level_ms, (hipStream_t)stream);
+}
+
+void vx_batch_destroy(vx_batch* b) { batch_destroy_impl(b); }
+
 int csf_build(int32_t k, int32_t level, const int32_t* boxes, int64_t n, vx_csf* out, void* ws, size_t ws_bytes,
               void* stream) {
   if (k < 1 || k > VX_KMAX) VX_FAIL(VX_EINVAL, "k=%d outside [1, %d]", k, VX_KMAX);

@@ -93,10 +93,10 @@ __host__ __device__ inline int64_t padded_npad(int d) {
 // ---------------------------------------------------------------------------
 // Tables and coefficient packing (one thread per cube entry).
 // ---------------------------------------------------------------------------
-__global__ void k_tables(int k, int d, int side, const double* __restrict__ clo, const double* __restrict__ chi,
-                         double* __restrict__ packed, int2* __restrict__ ttab, int32_t* __restrict__ lens2,
-                         int32_t* __restrict__ lens1, int32_t* __restrict__ padlist) {
-  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void tables_entry(int64_t f, int k, int d, int side, const double* __restrict__ clo,
+                                    const double* __restrict__ chi, double* __restrict__ packed,
+                                    int2* __restrict__ ttab, int32_t* __restrict__ lens2,
+                                    int32_t* __restrict__ lens1, int32_t* __restrict__ padlist) {
   int64_t total = 1;
   for (int i = 0; i < k; i++) total *= side;
   if (f >= total) return;
@@ -143,6 +143,13 @@ __global__ void k_tables(int k, int d, int side, const double* __restrict__ clo,
     for (int i = 0; i < k - 1; i++) lead_zero = lead_zero && e[i] == 0;
     if (lead_zero) lens1[d - e[k - 1]] = d - e[k - 1];
   }
+}
+
+__global__ void k_tables(int k, int d, int side, const double* __restrict__ clo, const double* __restrict__ chi,
+                         double* __restrict__ packed, int2* __restrict__ ttab, int32_t* __restrict__ lens2,
+                         int32_t* __restrict__ lens1, int32_t* __restrict__ padlist) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  tables_entry(f, k, d, side, clo, chi, packed, ttab, lens2, lens1, padlist);
 }
 
 // ---------------------------------------------------------------------------
@@ -1029,5 +1036,9 @@ int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom
   if ((rc = prepare_polys(P, np, ws, qb, &Q, st))) return rc;
   return eval_level_prepared(Q, S, dom, lo, hi, keep, reinterpret_cast<char*>(ws) + qb, ws_bytes - qb, st, P);
 }
+
+// Batched persistent subdivision of many systems (same translation unit: it
+// reuses the device functions above).
+#include "batch.inc"
 
 }  // namespace vx
