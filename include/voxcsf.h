@@ -272,10 +272,20 @@ int vx_batch_create(const vx_poly* P, int32_t nsys, const double* dom, int32_t d
                     vx_batch** out);
 /* Enqueue one whole run (levels 0..depth) on `stream`; does not wait. */
 int vx_batch_run(vx_batch* b, void* stream);
+/* Per-level record of a batched run, summed over systems: node counts of
+ * the evaluated and of the kept set per batched depth (0 = live systems,
+ * l = 1..k as in vx_csf), and the interval Horner steps of Theorem 1, per
+ * CSF depth of the systems (steps_depth[l], l = 0..k-1) and in total. */
+typedef struct vx_batch_stat {
+  int32_t level;
+  int32_t reserved;
+  int64_t n[VX_KMAX];
+  int64_t kept[VX_KMAX];
+  int64_t steps;
+  int64_t steps_depth[VX_KMAX];
+} vx_batch_stat;
 /* Wait for the stream, then report the last run:
- *   stats : host int64[(depth+1) * 2 * VX_KMAX] or NULL; per level, the node
- *           counts of the evaluated set (depths 0..k) then of the kept set,
- *           summed over systems.
+ *   stats : host array of depth+1 records, or NULL.
  *   need  : host int64[k+1] or NULL: the largest node counts per depth the
  *           run reached (a sufficient `cap` after VX_ECAPACITY, as far as the
  *           run got).
@@ -283,7 +293,7 @@ int vx_batch_run(vx_batch* b, void* stream);
  *           set of the last level, or NULL; lo/hi/keep: device arrays of its
  *           leaves' enclosures and keep flags, or NULL.
  *   kept  : batched CSF receiving the kept set of the last level, or NULL. */
-int vx_batch_result(vx_batch* b, int64_t* stats, int64_t* need, vx_csf* last, double* lo, double* hi, uint8_t* keep,
+int vx_batch_result(vx_batch* b, vx_batch_stat* stats, int64_t* need, vx_csf* last, double* lo, double* hi, uint8_t* keep,
                     vx_csf* kept, void* stream);
 /* Autotuner: run every candidate configuration `reps` times eagerly, and
  * keep per level the fastest (written to chosen[depth+1] and its time to

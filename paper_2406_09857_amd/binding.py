@@ -487,6 +487,11 @@ class vx_batch_tune(C.Structure):
     _fields_ = [("r1", C.c_int32), ("groups", C.c_int32), ("grid", C.c_int32), ("reserved", C.c_int32)]
 
 
+class vx_batch_stat(C.Structure):
+    _fields_ = [("level", C.c_int32), ("reserved", C.c_int32), ("n", C.c_int64 * KMAX),
+                ("kept", C.c_int64 * KMAX), ("steps", C.c_int64), ("steps_depth", C.c_int64 * KMAX)]
+
+
 VX_BATCH_GRAPH = 1
 
 
@@ -500,7 +505,8 @@ def _batch_lib():
         L.vx_batch_create.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(C.c_double), C.c_int32, i64p,
                                       C.POINTER(vx_batch_tune), C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
         L.vx_batch_run.argtypes = [vp, vp]
-        L.vx_batch_result.argtypes = [vp, i64p, i64p, C.POINTER(vx_csf), vp, vp, vp, C.POINTER(vx_csf), vp]
+        L.vx_batch_result.argtypes = [vp, C.POINTER(vx_batch_stat), i64p, C.POINTER(vx_csf), vp, vp, vp,
+                                      C.POINTER(vx_csf), vp]
         L.vx_batch_autotune.argtypes = [vp, C.POINTER(vx_batch_tune), C.c_int32, C.c_int32,
                                         C.POINTER(vx_batch_tune), C.POINTER(C.c_float), vp]
         L.vx_batch_destroy.argtypes = [vp]
@@ -573,7 +579,7 @@ class Batch:
         """Per-level fastest of the candidates [(r1, groups, grid), ...];
         returns (chosen configs, per-level ms)."""
         if candidates is None:
-            candidates = [(r, g, grid) for r in (4, 8) for g in (1, 2, 4) for grid in (2048, 8192)]
+            candidates = [(r, g, grid) for r in (1, 4, 8) for g in (1, 2, 4, 8, 16) for grid in (2048, 8192)]
         ca = (vx_batch_tune * len(candidates))(*[vx_batch_tune(*c, 0) for c in candidates])
         ch = (vx_batch_tune * (self.depth + 1))()
         ms = (C.c_float * (self.depth + 1))()
@@ -587,11 +593,13 @@ class Batch:
         L = _batch_lib()
         nl = self.depth + 1
         kk = self.k + 1
-        stats = (C.c_int64 * (nl * 2 * KMAX))()
+        stats = (vx_batch_stat * nl)()
         need = (C.c_int64 * KMAX)()
         rc = L.vx_batch_result(self._h, stats, need, None, None, None, None, None, _stream(stream))
-        st = np.array(stats[:], dtype=np.int64).reshape(nl, 2, KMAX)
-        out = {"stats": st, "need": list(need)[:kk], "rc": rc}
+        st = np.array([[list(r.n), list(r.kept)] for r in stats], dtype=np.int64).reshape(nl, 2, KMAX)
+        out = {"stats": st, "steps": [int(r.steps) for r in stats],
+               "steps_depth": np.array([list(r.steps_depth)[: self.k] for r in stats], dtype=np.int64),
+               "need": list(need)[:kk], "rc": rc}
         if rc != VX_OK:
             out["error"] = lib().vx_last_error().decode()
             return out

@@ -415,7 +415,7 @@ int vx_batch_run(vx_batch* b, void* stream) {
   return batch_run_impl(b, (hipStream_t)stream);
 }
 
-int vx_batch_result(vx_batch* b, int64_t* stats, int64_t* need, vx_csf* last, double* lo, double* hi, uint8_t* keep,
+int vx_batch_result(vx_batch* b, vx_batch_stat* stats, int64_t* need, vx_csf* last, double* lo, double* hi, uint8_t* keep,
                     vx_csf* kept, void* stream) {
   if (!b) VX_FAIL(VX_EINVAL, "batch: null handle");
   return batch_result_impl(b, stats, need, last, lo, hi, keep, kept, (hipStream_t)stream);

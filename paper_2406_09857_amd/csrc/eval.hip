@@ -39,6 +39,7 @@
 
 #include "common.hpp"
 #include "eval.hpp"
+#include "fill.hpp"
 #include "interval.hpp"
 #include "profile.hpp"
 #include "scan.hpp"
@@ -262,9 +263,16 @@ struct PolyTab {
   int npad;
 };
 
+// Node q's entry j sits at rows + q * stride + j * estride (doubles).  Rows
+// written by stage 1 are node-major (estride = entry width); the leaf input
+// written by a middle stage is entry-major (stride = 3, estride = 3 * nodes),
+// so the 64 lanes of a middle-stage wave, which are 64 consecutive nodes,
+// store each entry contiguously, and leaf lanes of neighbouring columns read
+// neighbouring addresses.
 struct RowSet {
   double* rows[PMAX];
-  int64_t stride[PMAX];   // doubles per node row
+  int64_t stride[PMAX];
+  int64_t estride[PMAX];
 };
 
 struct PolySet {
@@ -401,7 +409,7 @@ typedef __attribute__((address_space(4))) const dvec2 crow_t;
 template <int CLS, bool ORDER1>
 __device__ __forceinline__ void narrow_run(const crow_t* __restrict__ C, const int32_t* __restrict__ lens, int j,
                                            const int jend, int64_t cpos, const CellOps& o, bool valid,
-                                           double* __restrict__ out, int out_width) {
+                                           double* __restrict__ out, int64_t es, int out_width) {
   constexpr int G = NARROW_GROUP;
   if (j >= jend) return;
   int n = chain_len<ORDER1>(lens, j) + 1;  // entries of chain j
@@ -447,7 +455,7 @@ __device__ __forceinline__ void narrow_run(const crow_t* __restrict__ C, const i
     }
     if (g == ng - 1) {
       if (valid) {
-        double* w = out + (int64_t)j * out_width;
+        double* w = out + (int64_t)j * es;
         w[0] = nl;
         w[1] = hh;
         if (out_width == 3) w[2] = nl;
@@ -467,7 +475,7 @@ __device__ __forceinline__ void narrow_run(const crow_t* __restrict__ C, const i
 // masking; two register buffers alternate so no copies are needed.
 template <int CLS>
 __device__ __forceinline__ void narrow_padded(const crow_t* __restrict__ C, int j, const int jend, const CellOps& o,
-                                              bool valid, double* __restrict__ out, int out_width) {
+                                              bool valid, double* __restrict__ out, int64_t es, int out_width) {
   constexpr int G = PADG;
   if (j >= jend) return;
   // 32-bit group counters: the scalar unit compares 32-bit values only
@@ -490,7 +498,7 @@ __device__ __forceinline__ void narrow_padded(const crow_t* __restrict__ C, int 
     g++;
     if (g == gend) {
       if (valid) {
-        double* w = out + (int64_t)j * out_width;
+        double* w = out + (int64_t)j * es;
         w[0] = nl;
         w[1] = hh;
         if (out_width == 3) w[2] = nl;
@@ -552,19 +560,20 @@ __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet s
   const CellOps o = cell_ops(cnl, chi, cls);
   const crow_t* C = (const crow_t*)(in.rows[pz] + (int64_t)parent * in.stride[pz]);
   double* w = out.rows[pz] + node * out.stride[pz];
+  const int64_t es = out.estride[pz];
   const int32_t* lens = ps.p[pz].lens2;
   const int j0 = __builtin_amdgcn_readfirstlane(split.j0[gi]);
   const int j1 = __builtin_amdgcn_readfirstlane(split.j0[gi + 1]);
   if (PADDED) {
-    if (cls == CLS_POS) narrow_padded<CLS_POS>(C, j0, j1, o, valid, w, out_width);
-    else if (cls == CLS_NEG) narrow_padded<CLS_NEG>(C, j0, j1, o, valid, w, out_width);
-    else narrow_padded<CLS_STRADDLE>(C, j0, j1, o, valid, w, out_width);
+    if (cls == CLS_POS) narrow_padded<CLS_POS>(C, j0, j1, o, valid, w, es, out_width);
+    else if (cls == CLS_NEG) narrow_padded<CLS_NEG>(C, j0, j1, o, valid, w, es, out_width);
+    else narrow_padded<CLS_STRADDLE>(C, j0, j1, o, valid, w, es, out_width);
     return;
   }
   const int64_t p0 = split.p0[gi];
-  if (cls == CLS_POS) narrow_run<CLS_POS, ORDER1>(C, lens, j0, j1, p0, o, valid, w, out_width);
-  else if (cls == CLS_NEG) narrow_run<CLS_NEG, ORDER1>(C, lens, j0, j1, p0, o, valid, w, out_width);
-  else narrow_run<CLS_STRADDLE, ORDER1>(C, lens, j0, j1, p0, o, valid, w, out_width);
+  if (cls == CLS_POS) narrow_run<CLS_POS, ORDER1>(C, lens, j0, j1, p0, o, valid, w, es, out_width);
+  else if (cls == CLS_NEG) narrow_run<CLS_NEG, ORDER1>(C, lens, j0, j1, p0, o, valid, w, es, out_width);
+  else narrow_run<CLS_STRADDLE, ORDER1>(C, lens, j0, j1, p0, o, valid, w, es, out_width);
 }
 
 // ---------------------------------------------------------------------------
@@ -579,28 +588,29 @@ __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet s
 // ---------------------------------------------------------------------------
 typedef double dpair_a8 __attribute__((ext_vector_type(2), aligned(8)));
 
-// General (straddling) leaf chain for one box.
-__device__ __forceinline__ void leaf_chain_gen(const double* __restrict__ R, int d, double cnl, double chi,
-                                               double& nl, double& hh) {
+// General (straddling) leaf chain for one box; entry j at R + es * j.
+__device__ __forceinline__ void leaf_chain_gen(const double* __restrict__ R, int64_t es, int d, double cnl,
+                                               double chi, double& nl, double& hh) {
   const CellOps o = cell_ops(cnl, chi, CLS_STRADDLE);
   nl = R[0];
   hh = R[1];
-  for (int j = 1; j <= d; j++) step_gen(nl, hh, o, R[3 * j], R[3 * j + 1]);
+  for (int j = 1; j <= d; j++) step_gen(nl, hh, o, R[es * j], R[es * j + 1]);
 }
 
 // Up to LR boxes of one column and one sign class (POS or NEG) share every
-// coefficient load.  Entry j (exponent d - j) is read at R + 3j, one double
+// coefficient load.  Entry j (exponent d - j) is read at R + es * j, one double
 // later when the boxes are mirrored (NEG) and d - j is odd; pe serves even j,
-// po odd j.  Four entries are in flight; rows are padded so reads past entry
-// d stay inside the buffer.
+// po odd j.  Four entries are in flight, so entries up to max(4, d + 4) are
+// read (the buffers are sized for it); those past d are never used.
 template <int LR>
-__device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int d, int sh, const double (&u)[LR],
-                                            const double (&v)[LR], double (&nl)[LR], double (&hh)[LR]) {
+__device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int64_t es, int d, int sh,
+                                            const double (&u)[LR], const double (&v)[LR], double (&nl)[LR],
+                                            double (&hh)[LR]) {
   const double* pe = R + ((d & 1) ? sh : 0);
-  const double* po = R + 3 + (((d - 1) & 1) ? sh : 0);
+  const double* po = R + es + (((d - 1) & 1) ? sh : 0);
   auto at = [&](int j) -> dpair_a8 {
-    return (j & 1) ? *reinterpret_cast<const dpair_a8*>(po + 3 * (j - 1))
-                   : *reinterpret_cast<const dpair_a8*>(pe + 3 * j);
+    return (j & 1) ? *reinterpret_cast<const dpair_a8*>(po + es * (j - 1))
+                   : *reinterpret_cast<const dpair_a8*>(pe + es * j);
   };
   const dpair_a8 c = at(0);
 #pragma unroll
@@ -616,13 +626,13 @@ __device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int d,
   int j = 1;
   for (; j + 3 <= d; j += 4) {
     steps(q0);
-    q0 = *reinterpret_cast<const dpair_a8*>(po + 3 * (j + 3));  // entry j+4 (odd)
+    q0 = *reinterpret_cast<const dpair_a8*>(po + es * (j + 3));  // entry j+4 (odd)
     steps(q1);
-    q1 = *reinterpret_cast<const dpair_a8*>(pe + 3 * (j + 5));  // entry j+5 (even)
+    q1 = *reinterpret_cast<const dpair_a8*>(pe + es * (j + 5));  // entry j+5 (even)
     steps(q2);
-    q2 = *reinterpret_cast<const dpair_a8*>(po + 3 * (j + 5));  // entry j+6 (odd)
+    q2 = *reinterpret_cast<const dpair_a8*>(po + es * (j + 5));  // entry j+6 (odd)
     steps(q3);
-    q3 = *reinterpret_cast<const dpair_a8*>(pe + 3 * (j + 7));  // entry j+7 (even)
+    q3 = *reinterpret_cast<const dpair_a8*>(pe + es * (j + 7));  // entry j+7 (even)
   }
   if (j <= d) steps(q0);
   if (j + 1 <= d) steps(q1);
@@ -654,6 +664,7 @@ __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int
   bool excl[LEAF_R] = {};
   for (int p = 0; p < ps.np; p++) {
     const double* R = rows.rows[p] + par * rows.stride[p];
+    const int64_t es = rows.estride[p];
     const int d = ps.p[p].d;
     double nl[LEAF_R], hh[LEAF_R];
     if (cls == CLS_STRADDLE) {
@@ -664,11 +675,11 @@ __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int
         if (i < cnt) {
           double cnl, chi;
           cell(g, labels[begin + i], cnl, chi);
-          leaf_chain_gen(R, d, cnl, chi, nl[i], hh[i]);
+          leaf_chain_gen(R, es, d, cnl, chi, nl[i], hh[i]);
         }
       }
     } else {
-      leaf_chains<LEAF_R>(R, d, cls == CLS_NEG ? 1 : 0, u, v, nl, hh);
+      leaf_chains<LEAF_R>(R, es, d, cls == CLS_NEG ? 1 : 0, u, v, nl, hh);
     }
 #pragma unroll
     for (int i = 0; i < LEAF_R; i++) {
@@ -856,7 +867,11 @@ static void plan_eval(Arena& A, EvalPlan& E, const vx_poly* P, int np, const vx_
     const int m = k - l - 1;  // dimension of the trailing tuples left after depth l+1
     const int width = (l == k - 2) ? 3 : 2;
     for (int p = 0; p < np; p++) {
-      const int64_t row = (k == 3 && l == 0) ? padded_entries(P[p].degree) : ntup(m, P[p].degree);
+      // leaf input written by a middle stage: entry-major, d + 5 entry planes
+      // (the leaf reads up to entry d + 4)
+      const int64_t row = (k >= 3 && l == k - 2) ? P[p].degree + 5
+                          : (k == 3 && l == 0)   ? padded_entries(P[p].degree)
+                                                 : ntup(m, P[p].degree);
       E.rows[l][p] = A.take<double>((size_t)S->n[l] * row * width + 4 * ROW_PAD * width) + 2 * ROW_PAD * width;
     }
   }
@@ -905,6 +920,7 @@ static int launch_stage1(const Prepared& Q, int p0, int pn, const vx_csf* S, con
     nt_max = ps.p[i].nt > nt_max ? ps.p[i].nt : nt_max;
     rs.rows[i] = E.rows[0][p];
     rs.stride[i] = (k == 3 ? padded_entries(d) : ntup(m, d)) * width;
+    rs.estride[i] = width;
     units += (double)(ntup(k, d) - ntup(m, d)) * (double)S->n[0];
   }
   const SegPlan& sp = E.seg[0];
@@ -947,7 +963,9 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
     in.rows[i] = E.rows[l - 1][p];
     in.stride[i] = (k == 3 ? padded_entries(d) : ntup(m_in, d)) * 2;
     out.rows[i] = E.rows[l][p];
-    out.stride[i] = ntup(m_out, d) * width;
+    const bool to_leaf = l == k - 2;
+    out.stride[i] = to_leaf ? 3 : ntup(m_out, d) * width;
+    out.estride[i] = to_leaf ? 3 * S->n[l] : width;
     ss.s[i] = chain_split(m_out, d, groups);
     gmax = ss.s[i].n > gmax ? ss.s[i].n : gmax;
     units += (double)(ntup(m_in, d) - ntup(m_out, d)) * (double)S->n[l];
@@ -984,7 +1002,8 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
     const int p = p0 + i, d = Q.d[p];
     ps.p[i].d = d;
     rs.rows[i] = k == 1 ? Q.packed[p] : E.rows[k - 2][p];
-    rs.stride[i] = k == 1 ? 0 : 3 * (int64_t)(d + 1);
+    rs.stride[i] = k == 1 ? 0 : (k == 2 ? 3 * (int64_t)(d + 1) : 3);
+    rs.estride[i] = k >= 3 ? 3 * S->n[k - 2] : 3;
     units += (double)d * (double)nleaf;
   }
   const SegPlan& sp = E.seg[k - 1];

@@ -45,7 +45,7 @@ int batch_create_impl(const vx_poly* P, int nsys, const double* dom, int depth, 
                       const vx_batch_tune* tune, int flags, void* ws, size_t ws_bytes, hipStream_t st,
                       vx_batch** out);
 int batch_run_impl(vx_batch* H, hipStream_t st);
-int batch_result_impl(vx_batch* H, int64_t* stats, int64_t* need, vx_csf* last, double* lo, double* hi,
+int batch_result_impl(vx_batch* H, vx_batch_stat* stats, int64_t* need, vx_csf* last, double* lo, double* hi,
                       uint8_t* keep, vx_csf* kept, hipStream_t st);
 int batch_autotune_impl(vx_batch* H, const vx_batch_tune* cand, int ncand, int reps, vx_batch_tune* chosen,
                         float* level_ms, hipStream_t st);

@@ -11,13 +11,15 @@
 //          children of a copy of node y are the labels 2 i' + b of y's
 //          children i' (b = 0, 1), so N_l(next) = 2^l N_l(K) and labels stay
 //          ascending under each parent.  Offsets come from a scan of the
-//          child counts; every output entry finds its parent by binary search.
+//          child counts; every output entry finds its parent by a search
+//          staged through LDS, one tile of outputs per workgroup.
 // All passes are scans and gathers with one thread per element; nothing
 // depends on scheduling order, so the output is deterministic.
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
 #include "eval.hpp"
+#include "fill.hpp"
 #include "profile.hpp"
 #include "scan.hpp"
 
@@ -26,17 +28,7 @@ namespace vx {
 __global__ __launch_bounds__(SCAN_THREADS) void k_scan_tile_sums(int64_t* tile_sum, const int64_t* n_dev,
                                                                   int64_t nmax, int64_t* total_out) {
   (void)n_dev;
-  const int64_t nt = scan_tiles(nmax);
-  int64_t carry = 0;
-  for (int64_t base = 0; base < nt; base += SCAN_THREADS) {
-    const int64_t i = base + threadIdx.x;
-    const int64_t v = i < nt ? tile_sum[i] : 0;
-    int64_t tot;
-    const int64_t ex = block_exclusive_scan(v, tot);
-    if (i < nt) tile_sum[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0 && total_out) *total_out = carry;
+  scan_tile_sums_body(tile_sum, scan_tiles(nmax), total_out);
 }
 
 struct KeepLoader {
@@ -96,23 +88,26 @@ __global__ void k_next_first(const int64_t* __restrict__ ncnt, const int32_t* __
   if (src) src[o] = (int32_t)j;
 }
 
-// Depth l+1 >= 2 of next: entry o under parent P (binary search in nptr).
-__global__ void k_next_fill(const int64_t* __restrict__ ncnt_parent, const int64_t* __restrict__ ncnt,
-                            const int32_t* __restrict__ nptr, const int32_t* __restrict__ src_parent,
-                            const int32_t* __restrict__ kptr, const int32_t* __restrict__ kidx,
-                            int32_t* __restrict__ nidx, int32_t* __restrict__ src) {
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= *ncnt) return;
-  int64_t lo = 0, hi = *ncnt_parent;  // last P with nptr[P] <= o
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (nptr[mid] <= o) lo = mid; else hi = mid;
-  }
-  const int64_t rel = o - nptr[lo];
-  const int32_t y = src_parent[lo];
-  const int32_t child = kptr[y] + (int32_t)(rel >> 1);
-  nidx[o] = 2 * kidx[child] + (int32_t)(rel & 1);
-  if (src) src[o] = child;
+// Depth l+1 >= 2 of next: the parent of each tile's first output, then one
+// tile of outputs per workgroup.
+__global__ void k_fill_partition(const int64_t* __restrict__ ncnt_parent, const int64_t* __restrict__ ncnt,
+                                 const int32_t* __restrict__ nptr, int32_t* __restrict__ part) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ntile = (*ncnt + FILL_TILE - 1) / FILL_TILE;
+  if (t <= ntile) fill_partition_at(t, ntile, *ncnt_parent, nptr, part);
+}
+
+__global__ __launch_bounds__(FILL_THREADS) void k_next_fill(const int64_t* __restrict__ ncnt_parent,
+                                                           const int64_t* __restrict__ ncnt,
+                                                           const int32_t* __restrict__ part,
+                                                           const int32_t* __restrict__ nptr,
+                                                           const int32_t* __restrict__ src_parent,
+                                                           const int32_t* __restrict__ kptr,
+                                                           const int32_t* __restrict__ kidx,
+                                                           int32_t* __restrict__ nidx, int32_t* __restrict__ src) {
+  const int64_t n = *ncnt;
+  if ((int64_t)blockIdx.x * FILL_TILE >= n) return;
+  next_fill_tile(blockIdx.x, n, *ncnt_parent, part, nptr, src_parent, kptr, kidx, nidx, src);
 }
 
 struct FilterPlan {
@@ -123,6 +118,7 @@ struct FilterPlan {
   int32_t* kidx[VX_KMAX] = {};
   int32_t* kptr[VX_KMAX] = {};
   int32_t* src[VX_KMAX] = {};
+  int32_t* part = nullptr;
 };
 
 static void plan_filter(Arena& A, FilterPlan& F, const vx_csf* S, bool own_kept, bool want_next) {
@@ -141,8 +137,10 @@ static void plan_filter(Arena& A, FilterPlan& F, const vx_csf* S, bool own_kept,
       F.kidx[l] = A.take<int32_t>(S->n[l] > 0 ? S->n[l] : 1);
       if (l + 1 < k) F.kptr[l] = A.take<int32_t>(S->n[l] + 1);
     }
-  if (want_next)
+  if (want_next) {
     for (int l = 0; l + 1 < k; l++) F.src[l] = A.take<int32_t>((S->n[l] << (l + 1)) + 1);
+    F.part = A.take<int32_t>(maxn / FILL_TILE + 2);
+  }
 }
 
 size_t filter_workspace_bytes(const vx_csf* S) {
@@ -213,8 +211,13 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
     scan_exclusive(ChildCountLoader{F.src[l - 1], kptr[l - 1]}, (const int64_t*)(F.ncnt + l - 1), pbound,
                    next->ptr[l - 1], (int64_t*)nullptr, F.tiles, st);
     VX_CHECK_LAUNCH("child count scan");
-    hipLaunchKernelGGL(k_next_fill, dim3((unsigned)((bound + 255) / 256 > 0 ? (bound + 255) / 256 : 1)), dim3(256),
-                       0, st, (const int64_t*)(F.ncnt + l - 1), (const int64_t*)(F.ncnt + l),
+    const int64_t tiles = (bound + FILL_TILE - 1) / FILL_TILE;
+    hipLaunchKernelGGL(k_fill_partition, dim3((unsigned)((tiles + 1 + 255) / 256)), dim3(256), 0, st,
+                       (const int64_t*)(F.ncnt + l - 1), (const int64_t*)(F.ncnt + l),
+                       (const int32_t*)next->ptr[l - 1], F.part);
+    VX_CHECK_LAUNCH("k_fill_partition");
+    hipLaunchKernelGGL(k_next_fill, dim3((unsigned)(tiles > 0 ? tiles : 1)), dim3(FILL_THREADS), 0, st,
+                       (const int64_t*)(F.ncnt + l - 1), (const int64_t*)(F.ncnt + l), (const int32_t*)F.part,
                        (const int32_t*)next->ptr[l - 1], (const int32_t*)F.src[l - 1], (const int32_t*)kptr[l - 1],
                        (const int32_t*)kidx[l], next->idx[l], l + 1 < k ? F.src[l] : nullptr);
     VX_CHECK_LAUNCH("k_next_fill");

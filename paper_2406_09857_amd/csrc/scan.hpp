@@ -51,6 +51,31 @@ __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t& tota
 
 __host__ __device__ inline int64_t scan_tiles(int64_t nmax);
 
+// Pass 2 body: exclusive scan, in place, of nt tile sums by one workgroup,
+// SCAN_ITEMS consecutive sums per thread per round; total to *total_out.
+__device__ __forceinline__ void scan_tile_sums_body(int64_t* tile_sum, int64_t nt, int64_t* total_out) {
+  int64_t carry = 0;
+  for (int64_t base = 0; base < nt; base += SCAN_TILE) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+      v[j] = i0 + j < nt ? tile_sum[i0 + j] : 0;
+      s += v[j];
+    }
+    int64_t tot;
+    int64_t run = carry + block_exclusive_scan(s, tot);
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+      if (i0 + j < nt) tile_sum[i0 + j] = run;
+      run += v[j];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
+}
+
 __device__ __forceinline__ int64_t load_n(const int64_t* n_dev, int64_t nmax) {
   if (!n_dev) return nmax;
   const int64_t n = *n_dev;

@@ -35,7 +35,8 @@ def vx():
 def _host(r):
     """Host copies of a batch result's last level and kept set."""
     return {"last": r["last"].to_numpy(), "kept": r["kept"].to_numpy(), "lo": r["lo"].cpu().numpy(),
-            "hi": r["hi"].cpu().numpy(), "keep": r["keep"].cpu().numpy().astype(bool), "stats": r["stats"]}
+            "hi": r["hi"].cpu().numpy(), "keep": r["keep"].cpu().numpy().astype(bool), "stats": r["stats"],
+            "steps": r["steps"]}
 
 
 def _sub(csf, s):
@@ -81,9 +82,11 @@ def _empty_csf():
 def _compare_to_oracle(vx, systems, depth, r, tag):
     h = _host(r)
     tot = np.zeros((depth + 1, 2, 4), np.int64)
+    steps = np.zeros(depth + 1, np.int64)
     for s, sysp in enumerate(systems):
         recs = orc.subdivide(sysp, 3, depth, nthreads=orc.max_threads())
         for rec in recs:
+            steps[rec["level"]] += int(np.sum(rec["steps"]))
             sz = orc.csf_sizes(rec["S"])
             K = orc.csf_from_boxes(rec["kept"], rec["level"]) if len(rec["kept"]) else None
             ksz = orc.csf_sizes(K) if K is not None else [0, 0, 0]
@@ -94,6 +97,7 @@ def _compare_to_oracle(vx, systems, depth, r, tag):
         K = orc.csf_from_boxes(last["kept"], depth) if len(last["kept"]) else _empty_csf()
         _check_system(h, s, S, last["lo"][0], last["hi"][0], last["keep"], K, tag)
     assert np.array_equal(h["stats"], tot), (tag, "per-level counts")
+    assert r["steps"] == steps.tolist(), (tag, "Theorem 1 steps")
 
 
 def _same_result(a, b):
@@ -144,6 +148,7 @@ def test_batch64_depth8_matches_plain_runs(vx):
     b.close()
     del r
     tot = np.zeros((depth + 1, 2, 4), np.int64)
+    steps = np.zeros(depth + 1, np.int64)
     for s, sysp in enumerate(w.systems):
         grab = {}
 
@@ -157,11 +162,13 @@ def test_batch64_depth8_matches_plain_runs(vx):
             lv = st["level"]
             tot[lv, 0] += [1 if st["n"][2] > 0 else 0] + st["n"]
             tot[lv, 1] += [1 if st["kept"][2] > 0 else 0] + st["kept"]
+            steps[lv] += st["steps"]
         if not grab:
             grab = dict(S=_empty_csf(), lo=np.zeros(0), hi=np.zeros(0), keep=np.zeros(0, bool), K=_empty_csf())
         _check_system(h, s, grab["S"], grab["lo"], grab["hi"], grab["keep"], grab["K"], "batch64")
     _say(f"[batch] per-level totals {tot[:, 0, 3].tolist()}")
     assert np.array_equal(h["stats"], tot)
+    assert h["steps"] == steps.tolist()
 
 
 def test_batch_eager_graph_replays_and_autotune_identical(vx):
