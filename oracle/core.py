@@ -68,6 +68,11 @@ def lib():
         L.orc_eval_points.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int64, dp]
         L.orc_eval_points.restype = C.c_int
         L.orc_max_threads.restype = C.c_int
+        L.orc_centre_table.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int64, dp]
+        L.orc_deriv.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, dp, dp]
+        L.orc_deriv.restype = C.c_int
+        L.orc_mean_value.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp]
+        L.orc_mean_value.restype = C.c_int
         _lib = L
     return _lib
 
@@ -278,3 +283,74 @@ def theorem1_steps(k: int, d: int, sizes: list) -> list:
     total-degree simplex, where Nt_m = C(d+m, m) counts the trailing m-tuples."""
     nt = [math.comb(d + m, m) for m in range(k + 1)]
     return [(nt[k - l] - nt[k - l - 1]) * sizes[l] for l in range(k)]
+
+
+# ---------------------------------------------------------------------------
+# Mean-value exclusion (order-1 Taylor form, Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+def centre_table(dlo: float, dhi: float, level: int, n: int | None = None) -> np.ndarray:
+    """(n, 2) enclosures of the centres of cells 0..n-1 of the 2^level grid."""
+    n = (1 << level) if n is None else n
+    out = np.zeros((n, 2))
+    lib().orc_centre_table(dlo, dhi, level, n, _dp(out))
+    return out
+
+
+def deriv(poly, d: int, axis: int):
+    """Outward-rounded coefficient cubes (lo, hi) of dF/dx_axis (same side)."""
+    lo, hi, k, cube = _coef(poly)
+    olo = np.zeros_like(lo); ohi = np.zeros_like(lo)
+    if lib().orc_deriv(k, d, cube, _dp(lo), _dp(hi), axis, _dp(olo), _dp(ohi)):
+        raise ValueError("orc_deriv failed")
+    return olo, ohi
+
+
+def mean_value_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1, degrees=None):
+    """Mean-value enclosures (lo, hi: (npolys, n)) on every leaf of the CSF:
+    F(c) at the centre enclosures, each dF/dx_i on the boxes (Algorithm 2 on
+    the same CSF), combined by ``orc_mean_value``."""
+    k, level = csf["k"], csf["level"]
+    dom = np.asarray(dom, np.float64).reshape(k, 2)
+    btabs = level_tables(dom, k, level)
+    ctabs = [centre_table(float(dom[j, 0]), float(dom[j, 1]), level) for j in range(k)]
+    boxes = np.asarray(csf["boxes"], np.int64)
+    nb = boxes.shape[0]
+    bx = np.stack([btabs[j][boxes[:, j]] for j in range(k)], axis=1) if nb else np.zeros((0, k, 2))
+    cx = np.stack([ctabs[j][boxes[:, j]] for j in range(k)], axis=1) if nb else np.zeros((0, k, 2))
+    bx = np.ascontiguousarray(bx); cx = np.ascontiguousarray(cx)
+    los, his = [], []
+    for jp, p in enumerate(polys):
+        d = poly_degree(p) if degrees is None else degrees[jp]
+        fl, fh, _ = eval_csf(p, d, csf, ctabs, OUTWARD, nthreads)
+        D = np.zeros((k, nb, 2))
+        for i in range(k):
+            if d == 0:
+                continue
+            dl, dh, _ = eval_csf(deriv(p, d, i), d - 1, csf, btabs, OUTWARD, nthreads)
+            D[i, :, 0] = dl; D[i, :, 1] = dh
+        fc = np.ascontiguousarray(np.stack([fl, fh], axis=1))
+        out = np.zeros((nb, 2))
+        if nb and lib().orc_mean_value(k, nb, _dp(fc), _dp(D), _dp(bx), _dp(cx), _dp(out)):
+            raise ValueError("orc_mean_value failed")
+        los.append(out[:, 0]); his.append(out[:, 1])
+    return np.array(los).reshape(len(polys), -1), np.array(his).reshape(len(polys), -1)
+
+
+def subdivide_mv(polys, k: int, depth: int, dom=None, nthreads: int = 1):
+    """Algorithm 3 with the exclusion C0 and the mean-value test together: a
+    box is dropped when, for some polynomial, either enclosure excludes 0."""
+    dom = np.array([-1.0, 1.0] * k) if dom is None else np.asarray(dom, np.float64)
+    boxes = np.zeros((1, k), np.int64)
+    out = []
+    for level in range(depth + 1):
+        S = csf_from_boxes(boxes, level)
+        lo, hi, steps = eval_level(polys, S, dom, nthreads)
+        mlo, mhi = mean_value_level(polys, S, dom, nthreads)
+        keep = keep_mask(lo, hi) & keep_mask(mlo, mhi)
+        K = S["boxes"][keep]
+        out.append({"level": level, "S": S, "lo": lo, "hi": hi, "mv_lo": mlo, "mv_hi": mhi, "keep": keep,
+                    "kept": K})
+        if level < depth:
+            boxes = children_of(K)
+    return out

@@ -23,7 +23,9 @@
  *     subtree of i; a univariate F is evaluated directly on each child.
  *   - a per-box brute force that evaluates one box by nested Horner without
  *     sharing anything between boxes (the left-hand side of Theorem 1's
- *     comparison), used to pin the amortized routine.
+ *     comparison), used to pin the amortized routine;
+ *   - the mean-value (order-1 Taylor form) enclosure of Sec. 3.2: centre
+ *     enclosures, derivative coefficients and the final combination.
  *
  * Rounding is set with fesetround() around each batch of endpoint
  * computations; the file is compiled with clang -ffp-model=strict so that the
@@ -340,6 +342,77 @@ int orc_eval_points(int k, int d, int cube, const double* c, const double* x, in
     for (int j = 0; j < k; j++) { box[2 * j] = x[p * k + j]; box[2 * j + 1] = x[p * k + j]; }
     if (orc_eval_box(k, d, cube, c, NULL, box, ORC_NEAREST, r, NULL)) return -1;
     f[p] = r[0];
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Mean-value exclusion: the Taylor form of order 1 (Sec. 3.2, Taylor    */
+/* form definition with m = 1):  T(F, B) = F(c) + sum_i dF/dx_i(B) *     */
+/* (B_i - c_i), c the centre of B.  Every part is an outward-rounded     */
+/* enclosure: F(c) is the interval evaluation at the degenerate box of   */
+/* the centre enclosures, dF/dx_i(B) the interval evaluation of the      */
+/* derivative polynomial on B, B_i - c_i = [RD(lo_i - chi_i),            */
+/* RU(hi_i - clo_i)], and the sum runs left to right over i.             */
+/* ------------------------------------------------------------------ */
+
+/* Enclosure of the centre of cell `label` at `level`: it is the common
+ * endpoint of cells 2*label and 2*label+1 at level+1, so its lower bound is
+ * the lower end of cell 2*label+1 and its upper bound the upper end of cell
+ * 2*label (both exact on dyadic domains). */
+void orc_centre(double dlo, double dhi, int level, int64_t label, double* r) {
+  double a[2], b[2];
+  orc_box(dlo, dhi, level + 1, 2 * label + 1, a);
+  orc_box(dlo, dhi, level + 1, 2 * label, b);
+  r[0] = a[0]; r[1] = b[1];
+}
+
+void orc_centre_table(double dlo, double dhi, int level, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; i++) orc_centre(dlo, dhi, level, i, out + 2 * i);
+}
+
+/* Coefficients of dF/dx_axis: entry e is (e_axis + 1) * c_{e + u_axis},
+ * rounded outward (the factor is positive, so the bounds scale separately).
+ * Output cube of the same side; entries with |e| > d - 1 are zero. */
+int orc_deriv(int k, int d, int cube, const double* clo, const double* chi, int axis, double* olo, double* ohi) {
+  if (k < 1 || k > ORC_KMAX || axis < 0 || axis >= k || cube < d + 1) return -1;
+  int64_t total = ipow(cube, k), stride = ipow(cube, k - 1 - axis);
+  for (int64_t f = 0; f < total; f++) {
+    int64_t q = f; int deg = 0, ea = 0;
+    for (int j = k - 1; j >= 0; j--) {
+      int e = (int)(q % cube); q /= cube;
+      deg += e;
+      if (j == axis) ea = e;
+    }
+    olo[f] = 0.0; ohi[f] = 0.0;
+    if (deg + 1 > d || ea + 1 >= cube) continue;
+    double n = (double)(ea + 1);
+    int64_t src = f + stride;
+    round_down(ORC_OUTWARD); olo[f] = n * clo[src];
+    round_up(ORC_OUTWARD);   ohi[f] = n * (chi ? chi[src] : clo[src]);
+    round_restore();
+  }
+  return 0;
+}
+
+/* Combine per box b: fc[b] (2), D[i][b] (2, axis i), box[b][i] and
+ * centre[b][i] (2 each); out[b] = fc + D_0 W_0 + ... + D_{k-1} W_{k-1}. */
+int orc_mean_value(int k, int64_t nbox, const double* fc, const double* D, const double* box,
+                   const double* centre, double* out) {
+  if (k < 1 || k > ORC_KMAX) return -1;
+  for (int64_t b = 0; b < nbox; b++) {
+    ivl acc = {fc[2 * b], fc[2 * b + 1]};
+    for (int i = 0; i < k; i++) {
+      const double* I = box + (b * k + i) * 2;
+      const double* c = centre + (b * k + i) * 2;
+      ivl W;
+      round_down(ORC_OUTWARD); W.lo = I[0] - c[1];
+      round_up(ORC_OUTWARD);   W.hi = I[1] - c[0];
+      round_restore();
+      ivl Di = {D[((int64_t)i * nbox + b) * 2], D[((int64_t)i * nbox + b) * 2 + 1]};
+      acc = iv_add(acc, iv_mul(Di, W, ORC_OUTWARD), ORC_OUTWARD);
+    }
+    out[2 * b] = acc.lo; out[2 * b + 1] = acc.hi;
   }
   return 0;
 }

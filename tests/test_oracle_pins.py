@@ -402,3 +402,109 @@ def test_openmp_threads_do_not_change_bits():
     a = orc.eval_csf(w.polys[0], 40, rec["S"], tabs, nthreads=1)
     b = orc.eval_csf(w.polys[0], 40, rec["S"], tabs, nthreads=4)
     assert bits_equal(a[0], b[0]) and bits_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+# ---------------------------------------------------------------------------
+# Mean-value exclusion (order-1 Taylor form, Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+def test_centre_table_closed_form():
+    for level in (0, 1, 3, 7):
+        t = orc.centre_table(-1.0, 1.0, level)
+        want = -1.0 + (2 * np.arange(1 << level) + 1) / float(1 << level)
+        assert np.array_equal(t[:, 0], want) and np.array_equal(t[:, 1], want)
+    # non-dyadic domain: a true enclosure of the exact centre, at most one ulp wide per side
+    t = orc.centre_table(-0.3, 0.7, 5)
+    for i in range(32):
+        c = ex.F(-0.3) + (ex.F(0.7) - ex.F(-0.3)) * Fraction(2 * i + 1, 64)
+        assert ex.F(t[i, 0]) <= c <= ex.F(t[i, 1])
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_derivative_coefficients_match_numpy_polyder(k):
+    """Integer coefficients: e * c is exact, so the outward-rounded derivative
+    equals numpy's polyder along the axis (a library routine)."""
+    d = 6
+    rng = np.random.default_rng(70 + k)
+    c = synth.random_poly(k, d, rng, "int100")
+    for axis in range(k):
+        lo, hi = orc.deriv(c, d, axis)
+        assert np.array_equal(lo, hi)
+        ref = np.polynomial.polynomial.polyder(c, axis=axis)
+        pad = [(0, 0)] * k
+        pad[axis] = (0, 1)
+        ref = np.pad(ref, pad)
+        ref[np.indices(c.shape).sum(axis=0) > d - 1] = 0.0
+        assert np.array_equal(lo, ref), axis
+    # non-integer coefficients: [RD(e c), RU(e c)] brackets the exact product tightly
+    c = synth.random_poly(2, 5, rng, "normal")
+    lo, hi = orc.deriv(c, 5, 0)
+    for e1 in range(5):
+        for e2 in range(5 - e1):
+            exact = (e1 + 1) * ex.F(c[e1 + 1, e2])
+            assert ex.is_round_down(lo[e1, e2], exact) and ex.is_round_up(hi[e1, e2], exact)
+
+
+def test_mean_value_of_a_plane_is_its_exact_range():
+    """For F affine the Taylor form is exact: F(c) +- sum |a_i| h equals the
+    range of F over the box (dyadic coefficients, so nothing rounds)."""
+    k = 3
+    a = [0.375, -1.5, 0.25, 2.0]  # F = a0 + a1 x1 + a2 x2 + a3 x3
+    cube = synth.monomial_poly(k, 1, {(0, 0, 0): a[0], (1, 0, 0): a[1], (0, 1, 0): a[2], (0, 0, 1): a[3]})
+    S = orc.csf_from_boxes(np.array([[0, 3, 5], [2, 2, 2], [7, 0, 6]]), 3)
+    lo, hi = orc.mean_value_level([cube], S, np.array([-1.0, 1.0] * k))
+    h = Fraction(1, 8)
+    for q, b in enumerate(S["boxes"]):
+        c = [Fraction(-1) + (2 * int(b[j]) + 1) * h for j in range(k)]
+        fc = ex.F(a[0]) + sum(ex.F(a[j + 1]) * c[j] for j in range(k))
+        r = sum(abs(ex.F(a[j + 1])) * h for j in range(k))
+        assert ex.F(lo[0, q]) == fc - r and ex.F(hi[0, q]) == fc + r
+
+
+def test_mean_value_of_the_sphere_closed_form():
+    """F = sum x_i^2 - 1/2: dF/dx_i = 2 x_i, so on a box T = F(c) + sum
+    [2 lo_i, 2 hi_i] * [-h, h] = F(c) +- sum 2 max(|lo_i|, |hi_i|) h, exact in
+    rationals for dyadic boxes."""
+    k = 3
+    S = orc.csf_from_boxes(np.array([[0, 1, 2], [3, 3, 3], [1, 0, 3], [2, 2, 1]]), 2)
+    lo, hi = orc.mean_value_level([synth.sphere()], S, np.array([-1.0, 1.0] * k))
+    h = Fraction(1, 4)
+    for q, b in enumerate(S["boxes"]):
+        blo = [Fraction(-1) + int(b[j]) * 2 * h for j in range(k)]
+        bhi = [x + 2 * h for x in blo]
+        c = [(x + y) / 2 for x, y in zip(blo, bhi)]
+        fc = sum(x * x for x in c) - Fraction(1, 2)
+        r = sum(2 * max(abs(x), abs(y)) * h for x, y in zip(blo, bhi))
+        assert ex.F(lo[0, q]) == fc - r and ex.F(hi[0, q]) == fc + r
+
+
+@pytest.mark.parametrize("k,d,level", [(2, 6, 4), (3, 4, 3)])
+def test_mean_value_contains_exact_values(k, d, level):
+    """Enclosure property of the Taylor form: exact F at the corners, the
+    centre and random dyadic points of each box lies in the mean-value
+    enclosure (random interval-free coefficients)."""
+    rng = np.random.default_rng(90 + k)
+    poly = synth.small_random(k, d, seed=91 + k)[0]
+    boxes = rng.integers(0, 1 << level, size=(25, k))
+    S = orc.csf_from_boxes(boxes, level)
+    lo, hi = orc.mean_value_level([poly], S, np.array([-1.0, 1.0] * k))
+    tabs = orc.level_tables(np.array([-1.0, 1.0] * k), k, level)
+    for q, b in enumerate(S["boxes"]):
+        box = [tuple(tabs[j][b[j]]) for j in range(k)]
+        corners = [list(c) for c in np.array(np.meshgrid(*box, indexing="ij")).reshape(k, -1).T]
+        centre = [(ex.F(u) + ex.F(v)) / 2 for u, v in box]
+        for x in corners + [centre] + _dyadic_points(rng, box, 4):
+            val = ex.exact_point_value(poly, d, x)
+            assert ex.F(lo[0, q]) <= val <= ex.F(hi[0, q])
+
+
+def test_mean_value_prunes_more_on_the_surface():
+    """Near the zero set the Taylor form is tighter than plain interval
+    evaluation: the combined test keeps a subset of C0's boxes, strictly
+    smaller at level 5 of the degree-40 surface."""
+    w = synth.surface()
+    plain = orc.subdivide(w.polys, 3, 5, nthreads=orc.max_threads())
+    mv = orc.subdivide_mv(w.polys, 3, 5, nthreads=orc.max_threads())
+    for r0, r1 in zip(plain, mv):
+        assert len(r1["kept"]) <= len(r0["kept"])
+    assert len(mv[-1]["kept"]) < len(plain[-1]["kept"])
