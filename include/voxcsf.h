@@ -90,7 +90,7 @@ const char* vx_last_error(void);
 
 /* Workspace sizes.  `which` selects the call; arguments not used by that call
  * may be NULL/0.  Returns 0 on invalid arguments. */
-enum { VX_WS_EVAL = 0, VX_WS_FILTER = 1, VX_WS_BUILD = 2, VX_WS_GRAD = 3 };
+enum { VX_WS_EVAL = 0, VX_WS_FILTER = 1, VX_WS_BUILD = 2, VX_WS_GRAD = 3, VX_WS_MEANVALUE = 4 };
 size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_csf* S, int64_t n);
 
 /*
@@ -124,6 +124,25 @@ int csf_build(int32_t k, int32_t level, const int32_t* boxes, int64_t n, vx_csf*
  */
 int interval_eval_level(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo, double* hi,
                         uint8_t* keep, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * mean_value_exclusion -- the Taylor form of order 1 (Sec. 3.2, Taylor form
+ * definition with m = 1) as an exclusion test on every box of S:
+ *   T(F_p, B) = F_p(c) + sum_i dF_p/dx_i(B) * (B_i - c_i),  c the centre of B,
+ * each part an outward-rounded enclosure computed by Algorithm 2 on S: F_p at
+ * the degenerate boxes of the centre enclosures (the centre of cell i at
+ * level L is the common endpoint of cells 2i, 2i+1 at level L+1), the
+ * derivative polynomials (coefficients (e_i+1) c_{e+u_i}, rounded outward) on
+ * the boxes, B_i - c_i = [RD(lo_i - chi_i), RU(hi_i - clo_i)], and the sum
+ * left to right over i.  {F_p(x) : x in B} is contained in T(F_p, B).
+ *   lo, hi : device double, np x S->n[k-1], the mean-value enclosures.
+ *   keep   : device uint8 or NULL; if given, keep[b] is cleared when some
+ *            T(F_p, B) excludes 0 (AND with the caller's flags, e.g. C0's).
+ * Limits: np * k <= 64.  Errors as interval_eval_level; workspace
+ * vx_workspace_bytes(VX_WS_MEANVALUE, P, np, S, 0).
+ */
+int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo, double* hi,
+                         uint8_t* keep, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * filter_subdivide -- exclusion filter and bisection (Algorithm 3): prune S
@@ -170,6 +189,15 @@ typedef int (*vx_level_cb)(void* user, int32_t level, const vx_csf* S, const dou
  */
 int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t depth, void* ws, size_t ws_bytes,
                     size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user, void* stream);
+
+/* run_subdivision with options.  flags: VX_RUN_MEAN_VALUE adds the
+ * mean-value test (mean_value_exclusion) to C0 at every level: a box is kept
+ * only when both tests keep it (eval_ms then includes both; the callback
+ * still receives the C0 enclosures and the combined keep flags). */
+enum { VX_RUN_MEAN_VALUE = 1 };
+int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
+                       size_t ws_bytes, size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user,
+                       void* stream);
 
 /* Copy `bytes` between host and device or device and device on `stream` and
  * wait for it (helper for callbacks). kind: 0 = device->host, 1 = host->device,

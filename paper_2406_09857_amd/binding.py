@@ -23,7 +23,8 @@ LIB_PATH = os.path.join(HERE, "libvoxcsf.so")
 KMAX = 4
 
 VX_OK, VX_EINVAL, VX_ECAPACITY, VX_EHIP, VX_EOVERFLOW, VX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD = 0, 1, 2, 3
+VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD, VX_WS_MEANVALUE = 0, 1, 2, 3, 4
+VX_RUN_MEAN_VALUE = 1
 
 
 class VxError(RuntimeError):
@@ -76,11 +77,16 @@ def lib():
                                        C.c_size_t, vp]
         L.run_subdivision.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(C.c_double), C.c_int32, vp,
                                       C.c_size_t, C.POINTER(C.c_size_t), C.POINTER(vx_level_stat), LEVEL_CB, vp, vp]
+        L.run_subdivision_ex.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(C.c_double), C.c_int32, C.c_int32,
+                                         vp, C.c_size_t, C.POINTER(C.c_size_t), C.POINTER(vx_level_stat), LEVEL_CB,
+                                         vp, vp]
+        L.mean_value_exclusion.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.POINTER(C.c_double),
+                                           vp, vp, vp, vp, C.c_size_t, vp]
         L.csf_build.argtypes = [C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(vx_csf), vp, C.c_size_t, vp]
         L.vx_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
         L.vx_profile_end.argtypes = [C.POINTER(vx_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
-        for f in ("interval_eval_level", "filter_subdivide", "run_subdivision", "csf_build", "vx_copy",
-                  "vx_profile_begin", "vx_profile_end"):
+        for f in ("interval_eval_level", "filter_subdivide", "run_subdivision", "run_subdivision_ex", "csf_build",
+                  "vx_copy", "vx_profile_begin", "vx_profile_end", "mean_value_exclusion"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -234,6 +240,28 @@ def interval_eval_level(polys, csf: CSF, dom, out=None, keep: bool = True, ws=No
     return lo, hi, (kp[:nb] if kp is not None else None)
 
 
+def mean_value_exclusion(polys, csf: CSF, dom, keep: torch.Tensor | None = None, stream=None):
+    """Mean-value (order-1 Taylor form) enclosures (lo, hi: (np, nboxes)) on
+    every box; ``keep`` (uint8, nboxes), if given, is cleared in place where
+    some enclosure excludes 0."""
+    polys = as_polys(polys)
+    dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
+    nb = csf.nboxes
+    dev = csf.idx[0].device
+    lo = torch.empty((len(polys), max(nb, 1)), dtype=torch.float64, device=dev)
+    hi = torch.empty((len(polys), max(nb, 1)), dtype=torch.float64, device=dev)
+    parr = _poly_array(polys)
+    s = csf.struct()
+    need = int(lib().vx_workspace_bytes(VX_WS_MEANVALUE, parr, len(polys), C.byref(s), 0))
+    if need == 0:
+        _check(VX_EINVAL)
+    ws = _ws(need, dev)
+    _check(lib().mean_value_exclusion(parr, len(polys), C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)),
+                                      lo.data_ptr(), hi.data_ptr(), keep.data_ptr() if keep is not None else None,
+                                      ws.data_ptr(), ws.numel(), _stream(stream)))
+    return lo[:, :nb], hi[:, :nb]
+
+
 def filter_subdivide(csf: CSF, keep: torch.Tensor, want_kept: bool = True, want_next: bool = True, ws=None,
                      stream=None):
     """(kept CSF, next CSF) with host counts filled (synchronizes)."""
@@ -265,7 +293,7 @@ def root_csf(k: int, device=None) -> CSF:
 
 
 def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None,
-                    ws: torch.Tensor | None = None, want_kept: bool = True):
+                    ws: torch.Tensor | None = None, want_kept: bool = True, mean_value: bool = False):
     """Algorithm 3 with C0 to `depth`.  Returns (stats, kept) where stats is a
     list of per-level dicts and kept the final level's kept CSF (host numpy).
 
@@ -317,8 +345,9 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
     for _ in range(8):
         if ws is None or ws.numel() < size:
             ws = _ws(size)
-        rc = lib().run_subdivision(parr, len(polys), dom.ctypes.data_as(C.POINTER(C.c_double)), depth,
-                                   ws.data_ptr(), ws.numel(), C.byref(need), stats, cb, None, _stream(stream))
+        rc = lib().run_subdivision_ex(parr, len(polys), dom.ctypes.data_as(C.POINTER(C.c_double)), depth,
+                                      VX_RUN_MEAN_VALUE if mean_value else 0, ws.data_ptr(), ws.numel(),
+                                      C.byref(need), stats, cb, None, _stream(stream))
         if rc == VX_ECAPACITY and need.value > size:
             size = int(need.value * 1.25)
             ws = None

@@ -128,6 +128,9 @@ size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_
     case VX_WS_BUILD:
       if (!S || S->k < 1 || S->k > VX_KMAX || n < 0) return 0;
       return build_workspace_bytes(S->k, n);
+    case VX_WS_MEANVALUE:
+      if (check_csf(S, false) || check_poly(P, np, S->k) || np * S->k > VX_MAXPOLY) return 0;
+      return mv_workspace_bytes(P, np, S);
     case VX_WS_GRAD:
       if (!P || np < 1 || np > PMAX_GRAD || check_poly(P, np, P[0].k)) return 0;
       if (S && check_csf(S, false)) return 0;
@@ -145,6 +148,18 @@ int interval_eval_level(const vx_poly* P, int32_t np, const vx_csf* S, const dou
   if ((rc = check_dom(dom, S->k))) return rc;
   if (S->n[S->k - 1] > 0 && (!lo || !hi)) VX_FAIL(VX_EINVAL, "null output arrays");
   return eval_level_impl(P, np, S, dom, lo, hi, keep, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo, double* hi,
+                         uint8_t* keep, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_csf(S, true))) return rc;
+  if ((rc = check_poly(P, np, S->k))) return rc;
+  if (np * S->k > VX_MAXPOLY) VX_FAIL(VX_EINVAL, "mean-value test: np * k = %d exceeds %d", np * S->k, VX_MAXPOLY);
+  if ((rc = check_dom(dom, S->k))) return rc;
+  if (S->n[S->k - 1] > 0 && (!lo || !hi)) VX_FAIL(VX_EINVAL, "null output arrays");
+  if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
+  return mv_impl(P, np, S, dom, lo, hi, keep, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int filter_subdivide(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
@@ -227,6 +242,12 @@ int vx_copy(void* dst, const void* src, size_t bytes, int32_t kind, void* stream
 
 int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t depth, void* ws, size_t ws_bytes,
                     size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user, void* stream) {
+  return run_subdivision_ex(P, np, dom, depth, 0, ws, ws_bytes, ws_needed, stats, cb, user, stream);
+}
+
+int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
+                       size_t ws_bytes, size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user,
+                       void* stream) {
   if (!P || np < 1) VX_FAIL(VX_EINVAL, "need at least one polynomial");
   const int k = P[0].k;
   int rc;
@@ -235,15 +256,31 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
   if ((rc = check_dom(dom, k))) return rc;
   if (depth < 0 || depth > 28) VX_FAIL(VX_EINVAL, "depth %d outside [0, 28]", depth);
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
+  if (flags & ~VX_RUN_MEAN_VALUE) VX_FAIL(VX_EINVAL, "unknown flags 0x%x", flags);
+  const bool mv = (flags & VX_RUN_MEAN_VALUE) != 0;
+  if (mv && np * k > VX_MAXPOLY) VX_FAIL(VX_EINVAL, "mean-value test: np * k = %d exceeds %d", np * k, VX_MAXPOLY);
   hipStream_t st = (hipStream_t)stream;
   // coefficient tables once for the whole run, at the start of the workspace
-  const size_t qbytes = (prepared_bytes(P, np) + 255) / 256 * 256;
+  // (followed by the mean-value test's derivative tables when requested)
+  const size_t qbytes = (prepared_bytes(P, np) + 255) / 256 * 256 + (mv ? mv_run_workspace(P, np) : 0);
   if (qbytes > ws_bytes) {
     if (ws_needed) *ws_needed = qbytes + (1 << 20);
     VX_FAIL(VX_ECAPACITY, "workspace too small");
   }
   Prepared Q;
-  if ((rc = prepare_polys(P, np, ws, qbytes, &Q, st))) return rc;
+  const size_t qf = (prepared_bytes(P, np) + 255) / 256 * 256;
+  if ((rc = prepare_polys(P, np, ws, qf, &Q, st))) return rc;
+  void* mvh = nullptr;
+  if (mv) {
+    mvh = mv_run_begin(P, np, reinterpret_cast<char*>(ws) + qf, qbytes - qf, st, &rc);
+    if (rc) return rc;
+  }
+  struct MvGuard {
+    void* h;
+    ~MvGuard() {
+      if (h) mv_run_end(h);
+    }
+  } mv_guard{mvh};
   char* base = reinterpret_cast<char*>(ws) + qbytes;
   const size_t total = (ws_bytes - qbytes) / 256 * 256;
 
@@ -291,9 +328,13 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
     int64_t kcap[VX_KMAX] = {1, 1, 1, 1};
     for (int l = 0; l < k; l++) kcap[l] = S.n[l] > 0 ? S.n[l] : 1;
     const size_t o_k = carve(csf_bytes(k, kcap));
+    const size_t o_mlo = mv ? carve(sizeof(double) * (size_t)np * nleaf) : 0;
+    const size_t o_mhi = mv ? carve(sizeof(double) * (size_t)np * nleaf) : 0;
     const size_t ews = eval_level_bytes(P, np, &S);
     const size_t fws = filter_workspace_bytes(&S);
-    const size_t scratch_bytes = ews > fws ? ews : fws;
+    const size_t mws = mv ? mv_level_workspace(P, np, &S) : 0;
+    size_t scratch_bytes = ews > fws ? ews : fws;
+    scratch_bytes = scratch_bytes > mws ? scratch_bytes : mws;
     const size_t o_scr = carve(scratch_bytes);
     const size_t mid_bytes = moff;
     const size_t need = s_bytes + n_bytes + mid_bytes;
@@ -324,6 +365,11 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
 
     VX_HIP(hipEventRecord(ev[0], st));
     if ((rc = eval_level_prepared(Q, &S, dom, lo, hi, keep, scratch, scratch_bytes, st, P))) return rc;
+    if (mv && nleaf > 0) {
+      double* mlo = reinterpret_cast<double*>(mid_base + o_mlo);
+      double* mhi = reinterpret_cast<double*>(mid_base + o_mhi);
+      if ((rc = mv_run_level(mvh, P, np, &S, dom, mlo, mhi, keep, scratch, scratch_bytes, st))) return rc;
+    }
     VX_HIP(hipEventRecord(ev[1], st));
     if ((rc = filter_impl(&S, keep, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st))) return rc;
     VX_HIP(hipEventRecord(ev[2], st));

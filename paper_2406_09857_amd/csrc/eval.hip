@@ -719,13 +719,14 @@ struct I64Loader {
   __device__ int64_t operator()(int64_t i) const { return a[i]; }
 };
 
-static AxisGrid make_grid(const double* dom, int axis, int level) {
+static AxisGrid make_grid(const double* dom, int axis, int level, int centre = 0) {
   AxisGrid g;
   g.dlo = dom[2 * axis];
   g.dhi = dom[2 * axis + 1];
   g.ndlo = -g.dlo;
   g.ndhi = -g.dhi;
   g.level = level;
+  g.centre = centre;
   return g;
 }
 
@@ -855,6 +856,7 @@ struct EvalPlan {
   double* rows[VX_KMAX][VX_MAXPOLY] = {};  // output rows of stage l for polynomial p
   SegPlan seg[VX_KMAX];
   int R = 8;
+  int centre = 0;  // evaluate at the cell centres (degenerate boxes)
 };
 
 static int stage1_blocking(int64_t n0) { return n0 <= 4 ? 1 : n0 <= 16 ? 2 : n0 <= 64 ? 4 : 8; }
@@ -925,7 +927,7 @@ static int launch_stage1(const Prepared& Q, int p0, int pn, const vx_csf* S, con
   }
   const SegPlan& sp = E.seg[0];
   dim3 grid((unsigned)sp.maxseg, (unsigned)((nt_max + 63) / 64 + 1), (unsigned)pn);
-  const AxisGrid g = make_grid(dom, 0, S->level);
+  const AxisGrid g = make_grid(dom, 0, S->level, E.centre);
   const int pr = prof_start("k_stage1", units, st);
   switch (E.R) {
     case 1: hipLaunchKernelGGL(k_stage1<1>, grid, dim3(64), 0, st, ps, m, S->idx[0], (const int4*)sp.seg, (const int64_t*)sp.nseg, g, rs, width); break;
@@ -972,7 +974,7 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
   }
   const SegPlan& sp = E.seg[l];
   dim3 grid((unsigned)sp.maxseg, (unsigned)gmax, (unsigned)pn);
-  const AxisGrid g = make_grid(dom, l, S->level);
+  const AxisGrid g = make_grid(dom, l, S->level, E.centre);
   const int pr = prof_start("k_narrow", units, st);
   if (k == 3)
     hipLaunchKernelGGL((k_narrow<true, true>), grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
@@ -1010,7 +1012,7 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
   const int pr = prof_start("k_leaf", units, st);
   hipLaunchKernelGGL(k_leaf, dim3((unsigned)((sp.maxseg + 255) / 256)), dim3(256), 0, st, ps, rs,
                      (const int4*)sp.seg, (const int64_t*)sp.nseg, S->idx[k - 1], nleaf,
-                     make_grid(dom, k - 1, S->level), lo + (int64_t)p0 * nleaf, hi + (int64_t)p0 * nleaf, keep,
+                     make_grid(dom, k - 1, S->level, E.centre), lo + (int64_t)p0 * nleaf, hi + (int64_t)p0 * nleaf, keep,
                      p0 == 0 ? 1 : 0);
   VX_CHECK_LAUNCH("k_leaf");
   prof_stop(pr, st);
@@ -1018,7 +1020,7 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
 }
 
 int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
-                        void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P) {
+                        void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P, int centre) {
   const int k = S->k;
   const int64_t nleaf = S->n[k - 1];
   if (nleaf == 0) return VX_OK;
@@ -1027,12 +1029,13 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
   A.size = ws_bytes;
   EvalPlan E;
   plan_eval(A, E, P, Q.np, S);
+  E.centre = centre;
   if (A.overflow)
     VX_FAIL(VX_ECAPACITY, "interval_eval_level: workspace of %zu bytes is too small (%zu needed)", ws_bytes,
             A.off + 256);
   int rc;
   for (int l = 0; l < k; l++) {
-    const AxisGrid g = make_grid(dom, l, S->level);
+    const AxisGrid g = make_grid(dom, l, S->level, centre);
     if ((rc = build_segments(E.seg[l], l == 0 ? nullptr : S->ptr[l - 1], S->idx[l], g, st))) return rc;
   }
   for (int p0 = 0; p0 < Q.np; p0 += PMAX) {
@@ -1046,14 +1049,15 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
 }
 
 int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi,
-                    uint8_t* keep, void* ws, size_t ws_bytes, hipStream_t st) {
+                    uint8_t* keep, void* ws, size_t ws_bytes, hipStream_t st, int centre) {
   if (S->n[S->k - 1] == 0) return VX_OK;
   const size_t qb = prepared_bytes(P, np);
   if (qb > ws_bytes) VX_FAIL(VX_ECAPACITY, "interval_eval_level: workspace too small");
   Prepared Q;
   int rc;
   if ((rc = prepare_polys(P, np, ws, qb, &Q, st))) return rc;
-  return eval_level_prepared(Q, S, dom, lo, hi, keep, reinterpret_cast<char*>(ws) + qb, ws_bytes - qb, st, P);
+  return eval_level_prepared(Q, S, dom, lo, hi, keep, reinterpret_cast<char*>(ws) + qb, ws_bytes - qb, st, P,
+                             centre);
 }
 
 // Batched persistent subdivision of many systems (same translation unit: it

@@ -23,12 +23,13 @@ struct Prepared {
 size_t prepared_bytes(const vx_poly* P, int np);
 int prepare_polys(const vx_poly* P, int np, void* ws, size_t ws_bytes, Prepared* out, hipStream_t st);
 size_t eval_level_bytes(const vx_poly* P, int np, const vx_csf* S);
+// centre = 1 evaluates at the cell centres (degenerate boxes) instead of the cells.
 int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
-                        void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P);
+                        void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P, int centre = 0);
 
 size_t eval_workspace_bytes(const vx_poly* P, int np, const vx_csf* S);
 int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi,
-                    uint8_t* keep, void* ws, size_t ws_bytes, hipStream_t st);
+                    uint8_t* keep, void* ws, size_t ws_bytes, hipStream_t st, int centre = 0);
 
 size_t filter_workspace_bytes(const vx_csf* S);
 int filter_impl(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
@@ -39,6 +40,17 @@ int init_root_impl(vx_csf* S, hipStream_t st);
 size_t build_workspace_bytes(int k, int64_t n);
 int build_impl(int k, int level, const int32_t* boxes, int64_t n, vx_csf* out, int64_t* d_counts, void* ws,
                size_t ws_bytes, hipStream_t st);
+
+// Mean-value (order-1 Taylor form) exclusion test (meanvalue.hip).
+size_t mv_workspace_bytes(const vx_poly* P, int np, const vx_csf* S);
+int mv_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
+            void* ws, size_t ws_bytes, hipStream_t st);
+size_t mv_run_workspace(const vx_poly* P, int np);
+size_t mv_level_workspace(const vx_poly* P, int np, const vx_csf* S);
+void* mv_run_begin(const vx_poly* P, int np, void* ws, size_t bytes, hipStream_t st, int* rc);
+int mv_run_level(void* handle, const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi,
+                 uint8_t* keep, void* ws, size_t bytes, hipStream_t st);
+void mv_run_end(void* handle);
 
 size_t batch_workspace_bytes(const vx_poly* P, int nsys, int depth, const int64_t* cap);
 int batch_create_impl(const vx_poly* P, int nsys, const double* dom, int depth, const int64_t* cap,

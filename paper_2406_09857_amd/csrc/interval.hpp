@@ -52,16 +52,22 @@ enum : int { CLS_POS = 0, CLS_NEG = 1, CLS_STRADDLE = 2 };
 // Cell `label` of the 2^level grid on [dlo, dhi] is
 //   [RD(dlo + RD(label * RD(dhi-dlo)) 2^-level), RU(dlo + RU((label+1) * RU(dhi-dlo)) 2^-level)].
 // Returned as nlo = -lo and hi.  On dyadic domains such as [-1,1] both are exact.
+// With centre = 1 the "cell" is the degenerate box of the cell's centre, the
+// common endpoint of cells 2*label and 2*label+1 at level+1: its lower bound is
+// the lower end of cell 2*label+1, its upper bound the upper end of cell
+// 2*label (the centre enclosures of the mean-value form).
 struct AxisGrid {
   double dlo, ndlo, dhi, ndhi;  // domain endpoints and their negations (host-negated)
   int level;
+  int centre;                   // 0: cells, 1: cell centres
 };
 
 __device__ __forceinline__ void cell(const AxisGrid& g, int32_t label, double& nlo, double& hi) {
   const double wu = g.dhi + g.ndlo;   // RU(dhi - dlo)
   const double nw = g.dlo + g.ndhi;   // RU(dlo - dhi) = -RD(dhi - dlo)
-  nlo = g.ndlo + ldexp((double)label * nw, -g.level);
-  hi = g.dlo + ldexp((double)(label + 1) * wu, -g.level);
+  const int64_t base = (int64_t)label << g.centre;
+  nlo = g.ndlo + ldexp((double)(base + g.centre) * nw, -(g.level + g.centre));
+  hi = g.dlo + ldexp((double)(base + 1) * wu, -(g.level + g.centre));
 }
 
 __device__ __forceinline__ int cell_class(double nlo, double hi) {
