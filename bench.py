@@ -38,9 +38,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="curve", choices=["curve", "surface", "tiny"])
-    ap.add_argument("--cpu-depth", type=int, default=8, help="oracle sample: levels 0..cpu-depth of the workload")
+    ap.add_argument("--cpu-depth", type=int, default=9, help="oracle sample: levels 0..cpu-depth of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint and mean-value legs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (reference for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -65,8 +68,153 @@ def cpu_baseline(w, depth):
                       f"{dt:.2f} s, OpenMP over x1 fibres)"}
 
 
+def _evt_ms(fn, reps=1):
+    """Time `fn` on torch's current stream with HIP events (ms per call)."""
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bench_batched(vx, reps):
+    """64 independent systems (degrees 10..60, depth 8): one graph-replayed
+    batched run against 64 sequential plain runs of the same systems."""
+    import torch
+    from paper_2406_09857_amd import synth
+    w = synth.batch()
+    dom = w.domain()
+    b, r = vx.run_subdivision_batch(w.systems, dom, w.depth, graph=False)
+    cap = [max(int(n), 1) for n in r["need"]]
+    b.close()
+    del b
+    b = vx.Batch(w.systems, dom, w.depth, cap=cap, graph=True)
+    chosen, _ = b.autotune(reps=1)
+    b.run()
+    torch.cuda.synchronize()
+    ms = _evt_ms(b.run, reps)
+    r = b.result(want_last=False, want_kept=False)
+    b.close()
+    del b
+    evals = int(r["stats"][:, 0, 3].sum())
+    steps = int(sum(r["steps"]))
+    ws = torch.empty(6 << 30, dtype=torch.uint8, device="cuda")
+    for sysp in w.systems[:4]:
+        vx.run_subdivision(sysp, dom, w.depth, ws=ws, want_kept=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sysp in w.systems:
+        vx.run_subdivision(sysp, dom, w.depth, ws=ws, want_kept=False)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3
+    del ws
+    return {"workload": f"{w.name}: {len(w.systems)} single-polynomial trivariate systems, degrees uniform in "
+                        f"[10, 60], N(0,1) coefficients, domain [-1,1]^3, levels 0..{w.depth}",
+            "ms_per_run": ms, "box_evals_per_s": evals / (ms * 1e-3), "interval_steps": steps,
+            "fp64_valu_frac": VALU_PER_STEP * steps / (ms * 1e-3) / FP64_NOFMA_PEAK,
+            "plain_64_runs_ms": plain_ms, "speedup_vs_plain": plain_ms / ms,
+            "mode": "hipGraph replay, per-level autotuned launch shapes",
+            "tune": chosen, "node_capacity": cap,
+            "parity": "bit-identical to the plain runs (tests/test_gpu_batch.py)"}
+
+
+def bench_adjoint(vx, polys, dom, depth, kept):
+    """Point evaluation on the final kept-box centres: forward only, forward +
+    hand-written backward (dF/dx and dF/dcoef on the CSF grid), 3 Newton steps."""
+    import numpy as np
+    import torch
+    csf = vx.CSF.from_arrays(3, depth, kept["idx"], kept["ptr"])
+    x = vx.csf_centres(csf, dom)
+    n = int(x.shape[0])
+    gbar = torch.ones((len(polys), n), dtype=torch.float64, device="cuda")
+    fwd = lambda: vx.eval_grad(polys, x, want_jac=False)
+    fb = lambda: vx.eval_grad(polys, x, want_jac=True, gbar=gbar, want_xbar=True, want_dcoef=True, grid=csf,
+                              dom=dom)
+    fwd(); fb()
+    torch.cuda.synchronize()
+    f_ms = _evt_ms(fwd)
+    fb_ms = _evt_ms(fb)
+    f0 = fwd()[0].abs().amax(dim=0)
+    xn = x.clone()
+    newton_ms = _evt_ms(lambda: vx.newton_project(polys, xn, steps=3))
+    f3 = vx.eval_grad(polys, xn, want_jac=False)[0].abs().amax(dim=0)
+    return {"points": n, "forward_ms": f_ms, "forward_backward_ms": fb_ms, "backward_over_forward": fb_ms / f_ms,
+            "newton3_ms": newton_ms, "median_residual_before": float(torch.median(f0)),
+            "median_residual_after_3_newton": float(torch.median(f3)),
+            "parity": "values bit-identical to the oracle, Jacobian vs derivative polynomials and central "
+                      "differences, dcoef vs exact sums (tests/test_gpu_grad.py)"}
+
+
+def bench_mean_value(vx, polys, dom, depth, plain_stats, plain_ms):
+    """The curve run with C0 and the mean-value test together against C0 alone."""
+    import torch
+    vx.run_subdivision(polys, dom, depth, want_kept=False, mean_value=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats, _ = vx.run_subdivision(polys, dom, depth, want_kept=False, mean_value=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"ms_per_run": ms, "plain_ms_per_run": plain_ms,
+            "kept_per_level": [s["kept"][2] for s in stats],
+            "plain_kept_per_level": [s["kept"][2] for s in plain_stats],
+            "parity": "enclosures bit-identical to the oracle (tests/test_gpu_meanvalue.py)"}
+
+
+COPY_BYTES = 1 << 31  # bytes read (and written) by the calibration copy
+
+
+def copy_calibration():
+    """One elementwise copy of COPY_BYTES: its FETCH_SIZE / WRITE_SIZE
+    readings convert the counters of the measured kernels to bytes."""
+    import torch
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES}))
+
+
+def source_digest() -> str:
+    """Digest of the HIP sources: a traffic figure measured on other sources is stale."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2406_09857_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_<workload>_traffic.txt), or None when there is none
+    or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("source_sha256") != source_digest():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
@@ -119,7 +267,8 @@ def main():
         ops_per_launch = OPS_PER_STEP * r["units"] / r["launches"]
         achieved = ops_per_launch / avg_s / 1e12
         roof = {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": FP64_NOFMA_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / (FP64_NOFMA_PEAK / 1e12), "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / (FP64_NOFMA_PEAK / 1e12),
+                "traffic": measured_traffic(dom_name, args.workload),
                 "avg_launch_ms": avg_s * 1e3, "ops_per_launch": ops_per_launch,
                 "valu_inst_frac": VALU_PER_STEP * r["units"] / r["launches"] / avg_s / FP64_NOFMA_PEAK}
 
@@ -146,6 +295,13 @@ def main():
         "kernels": kernels,
         "levels": levels,
     }
+    if not args.no_extras and args.workload == "curve":
+        del ws
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(vx, reps=5)
+        _, kept = vx.run_subdivision(polys, dom, w.depth, want_kept=True)
+        out["adjoint"] = bench_adjoint(vx, polys, dom, w.depth, kept)
+        out["mean_value"] = bench_mean_value(vx, polys, dom, w.depth, stats, ms_step)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_depth, w.depth))
     print(json.dumps(out))

@@ -43,6 +43,7 @@
 #include "interval.hpp"
 #include "profile.hpp"
 #include "scan.hpp"
+#include "xcd.hpp"
 
 namespace vx {
 
@@ -539,18 +540,26 @@ struct SplitSet {
   ChainSplit s[PMAX];
 };
 
+// One workgroup per (polynomial, segment, chain group) item, items ordered
+// with the chain group fastest and dealt to the XCDs in chunks, so that the
+// segments of one parent, which stream the same parent row, share an L2.
+constexpr int NARROW_XCD_CHUNK = 64;
+
 template <bool ORDER1, bool PADDED>
 __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet splits,
                                                const int32_t* __restrict__ labels, const int4* __restrict__ seg,
                                                const int64_t* __restrict__ nseg, AxisGrid g, RowSet out,
-                                               int out_width) {
+                                               int out_width, int64_t maxseg, int gdim, int64_t items) {
   round_up_mode();
-  if ((int64_t)blockIdx.x >= *nseg) return;
-  const int pz = blockIdx.z;
+  const int64_t item = xcd_item(blockIdx.x % NXCD, blockIdx.x / NXCD, NARROW_XCD_CHUNK);
+  if (item >= items) return;
+  const int gi = (int)(item % gdim);
+  const int64_t sidx = (item / gdim) % maxseg;
+  const int pz = (int)(item / ((int64_t)gdim * maxseg));
+  if (sidx >= *nseg) return;
   const ChainSplit& split = splits.s[pz];
-  const int gi = blockIdx.y;
   if (gi >= split.n) return;
-  const int4 sg = seg[blockIdx.x];
+  const int4 sg = seg[sidx];
   const int parent = sg.x, begin = sg.y, cnt = sg.z, cls = sg.w;
   const int lane = threadIdx.x;
   const bool valid = lane < cnt;
@@ -973,18 +982,19 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
     units += (double)(ntup(m_in, d) - ntup(m_out, d)) * (double)S->n[l];
   }
   const SegPlan& sp = E.seg[l];
-  dim3 grid((unsigned)sp.maxseg, (unsigned)gmax, (unsigned)pn);
+  const int64_t items = sp.maxseg * gmax * pn;
+  dim3 grid((unsigned)xcd_grid(items, NARROW_XCD_CHUNK));
   const AxisGrid g = make_grid(dom, l, S->level, E.centre);
   const int pr = prof_start("k_narrow", units, st);
   if (k == 3)
     hipLaunchKernelGGL((k_narrow<true, true>), grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
-                       (const int64_t*)sp.nseg, g, out, width);
+                       (const int64_t*)sp.nseg, g, out, width, sp.maxseg, gmax, items);
   else if (m_out == 1)
     hipLaunchKernelGGL((k_narrow<true, false>), grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
-                       (const int64_t*)sp.nseg, g, out, width);
+                       (const int64_t*)sp.nseg, g, out, width, sp.maxseg, gmax, items);
   else
     hipLaunchKernelGGL((k_narrow<false, false>), grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
-                       (const int64_t*)sp.nseg, g, out, width);
+                       (const int64_t*)sp.nseg, g, out, width, sp.maxseg, gmax, items);
   VX_CHECK_LAUNCH("k_narrow");
   prof_stop(pr, st);
   return VX_OK;
