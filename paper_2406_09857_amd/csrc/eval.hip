@@ -112,6 +112,10 @@ __device__ inline void tables_entry(int64_t f, int k, int d, int side, const dou
   const int m = k - 1;
   const int* t = e + 1;
   const int tdeg = deg - e[0];
+  if (f == 0 && k >= 2) {  // zero entry after the last row (read by chains not yet started)
+    packed[2 * dbinom(d + k, k) + 0] = 0.0;
+    packed[2 * dbinom(d + k, k) + 1] = 0.0;
+  }
   if (k == 1) {
     const int64_t j = d - e[0];
     packed[3 * j + 0] = -lo;
@@ -223,31 +227,81 @@ __device__ __forceinline__ double wave_uniform(double x) {
   return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
 
-// Rows are read two ahead of their use so the load latency overlaps the R
-// interval steps of the current row.
+// The packed rows are read from global memory (a generic pointer would make
+// every load a flat load, which also counts against the scalar-load counter).
+typedef double gvec2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const gvec2 gdouble2;
+
+// Row r of the packed table starts at C(r+m, m+1) and holds C(r+m, m)
+// tuples; the walk uses additions only: c_j = C(r+j, j) obeys
+// c_j(r+1) = c_j(r) + c_{j-1}(r+1) (Pascal), so no division runs per row.
+// Four rows are in flight in four register buffers that rotate in place (no
+// copies, so waiting for one row never waits for the others).  Lanes whose chain has
+// not started (|t| > r), and rows past d, read the zero entry the table keeps
+// after its last row, so every load is unconditional.
 template <int R, int CLS>
-__device__ __forceinline__ void stage1_chain(const double2* __restrict__ P, int m, int d, int r0, int gdeg,
+__device__ __forceinline__ void stage1_steps(const double2 c, const double (&u)[R], const double (&v)[R],
+                                             const CellOps (&ops)[R], double (&nl)[R], double (&hh)[R]) {
+#pragma unroll
+  for (int j = 0; j < R; j++) {
+    if (CLS == CLS_POS) step_pos(nl[j], hh[j], u[j], v[j], c.x, c.y);
+    else if (CLS == CLS_NEG) step_neg(nl[j], hh[j], u[j], v[j], c.x, c.y);
+    else step_gen(nl[j], hh[j], ops[j], c.x, c.y);
+  }
+}
+
+// Advance the row walk by one row: returns the index to read for row `rl`
+// (the zero entry for lanes whose chain has not started, or past the table).
+template <int M>
+__device__ __forceinline__ int64_t stage1_next(int64_t& off, int64_t& c1, int64_t& c2, int64_t& c3, int& rl,
+                                               int d, int gdeg, int64_t gidx, int64_t zidx) {
+  const int64_t at = (rl <= d && gdeg <= rl) ? off + gidx : zidx;
+  off += M == 1 ? c1 : (M == 2 ? c2 : c3);
+  c1 += 1;
+  c2 += c1;
+  c3 += c2;
+  rl++;
+  return at;
+}
+
+template <int R, int CLS, int M>
+__device__ __forceinline__ void stage1_chain_m(const double2* __restrict__ Pg, int d, int r0, int gdeg, int64_t gidx,
+                                               const double (&u)[R], const double (&v)[R], const CellOps (&ops)[R],
+                                               double (&nl)[R], double (&hh)[R]) {
+  constexpr int m = M;
+  const gdouble2* P = (const gdouble2*)Pg;
+  const int64_t zidx = dbinom(d + 1 + m, m + 1);  // zero entry after the last row
+  int64_t c1 = r0 + 1, c2 = dbinom(r0 + 2, 2), c3 = dbinom(r0 + 3, 3);
+  int64_t off = dbinom(r0 + m, m + 1);  // start of the next row to load
+  int rl = r0;                          // that row's index
+  // four rows in flight; rows past d read the zero entry and are never used
+  gvec2 q0 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+  gvec2 q1 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+  gvec2 q2 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+  gvec2 q3 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+  int r = r0;
+  for (; r + 3 <= d; r += 4) {
+    stage1_steps<R, CLS>(make_double2(q0.x, q0.y), u, v, ops, nl, hh);
+    q0 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+    stage1_steps<R, CLS>(make_double2(q1.x, q1.y), u, v, ops, nl, hh);
+    q1 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+    stage1_steps<R, CLS>(make_double2(q2.x, q2.y), u, v, ops, nl, hh);
+    q2 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+    stage1_steps<R, CLS>(make_double2(q3.x, q3.y), u, v, ops, nl, hh);
+    q3 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+  }
+  if (r <= d) stage1_steps<R, CLS>(make_double2(q0.x, q0.y), u, v, ops, nl, hh);
+  if (r + 1 <= d) stage1_steps<R, CLS>(make_double2(q1.x, q1.y), u, v, ops, nl, hh);
+  if (r + 2 <= d) stage1_steps<R, CLS>(make_double2(q2.x, q2.y), u, v, ops, nl, hh);
+}
+
+template <int R, int CLS>
+__device__ __forceinline__ void stage1_chain(const double2* __restrict__ Pg, int m, int d, int r0, int gdeg,
                                              int64_t gidx, const double (&u)[R], const double (&v)[R],
                                              const CellOps (&ops)[R], double (&nl)[R], double (&hh)[R]) {
-  const double2 zero = make_double2(0.0, 0.0);
-  const int64_t off0 = dbinom(r0 + m, m + 1), cnt0 = dbinom(r0 + m, m);
-  const int64_t off1 = off0 + cnt0, cnt1 = cnt0 * (r0 + m + 1) / (r0 + 1);
-  int64_t off2 = off1 + cnt1, cnt2 = cnt1 * (r0 + m + 2) / (r0 + 2);
-  double2 c0 = (gdeg <= r0) ? P[off0 + gidx] : zero;
-  double2 c1 = (r0 + 1 <= d && gdeg <= r0 + 1) ? P[off1 + gidx] : zero;
-  for (int r = r0; r <= d; r++) {
-    const double2 c = c0;
-    c0 = c1;
-    c1 = (r + 2 <= d && gdeg <= r + 2) ? P[off2 + gidx] : zero;
-    off2 += cnt2;
-    cnt2 = cnt2 * (r + m + 3) / (r + 3);
-#pragma unroll
-    for (int j = 0; j < R; j++) {
-      if (CLS == CLS_POS) step_pos(nl[j], hh[j], u[j], v[j], c.x, c.y);
-      else if (CLS == CLS_NEG) step_neg(nl[j], hh[j], u[j], v[j], c.x, c.y);
-      else step_gen(nl[j], hh[j], ops[j], c.x, c.y);
-    }
-  }
+  if (m == 1) stage1_chain_m<R, CLS, 1>(Pg, d, r0, gdeg, gidx, u, v, ops, nl, hh);
+  else if (m == 2) stage1_chain_m<R, CLS, 2>(Pg, d, r0, gdeg, gidx, u, v, ops, nl, hh);
+  else stage1_chain_m<R, CLS, 3>(Pg, d, r0, gdeg, gidx, u, v, ops, nl, hh);
 }
 
 // Per-polynomial tables and stage outputs, passed by value; blockIdx.z (or a
@@ -780,6 +834,75 @@ static int build_segments(SegPlan& sp, const int32_t* ptr, const int32_t* labels
   return VX_OK;
 }
 
+// Small levels: one workgroup builds the segments of every depth in a single
+// launch (count, scan, write per depth), instead of five launches per depth.
+// Same segments as build_segments.
+constexpr int64_t SMALL_LEVEL_NODES = 32768;  // largest depth count for the one-workgroup paths
+
+struct SegJob {
+  const int32_t* ptr[VX_KMAX];
+  const int32_t* labels[VX_KMAX];
+  AxisGrid g[VX_KMAX];
+  int Z[VX_KMAX];
+  int64_t nparent[VX_KMAX], nchild[VX_KMAX];
+  int64_t* cnt[VX_KMAX];
+  int64_t* bounds[VX_KMAX];
+  int64_t* off[VX_KMAX];
+  int4* seg[VX_KMAX];
+  int64_t* nseg[VX_KMAX];
+};
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_segments_small(int k, SegJob J) {
+  round_up_mode();
+  for (int l = 0; l < k; l++) {
+    const int64_t np = J.nparent[l];
+    const int32_t* ptr = J.ptr[l];
+    const int Z = J.Z[l];
+    for (int64_t p = threadIdx.x; p < np; p += SCAN_THREADS) {
+      const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : J.nchild[l];
+      int64_t ne, pb;
+      class_bounds(J.labels[l], b, e, J.g[l], ne, pb);
+      J.bounds[l][2 * p] = ne;
+      J.bounds[l][2 * p + 1] = pb;
+      J.cnt[l][p] = cdiv(ne - b, Z) + cdiv(pb - ne, Z) + cdiv(e - pb, Z);
+    }
+    __syncthreads();
+    int64_t carry = 0;
+    for (int64_t base = 0; base < np; base += SCAN_TILE) {
+      const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+      int64_t v[SCAN_ITEMS];
+      int64_t sum = 0;
+#pragma unroll
+      for (int j = 0; j < SCAN_ITEMS; j++) {
+        v[j] = i0 + j < np ? J.cnt[l][i0 + j] : 0;
+        sum += v[j];
+      }
+      int64_t tot;
+      int64_t run = carry + block_exclusive_scan(sum, tot);
+#pragma unroll
+      for (int j = 0; j < SCAN_ITEMS; j++) {
+        if (i0 + j < np) J.off[l][i0 + j] = run;
+        run += v[j];
+      }
+      carry += tot;
+    }
+    if (threadIdx.x == 0) *J.nseg[l] = carry;
+    __syncthreads();
+    const int cls[3] = {CLS_NEG, CLS_STRADDLE, CLS_POS};
+    for (int64_t p = threadIdx.x; p < np; p += SCAN_THREADS) {
+      const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : J.nchild[l];
+      const int64_t cuts[4] = {b, J.bounds[l][2 * p], J.bounds[l][2 * p + 1], e};
+      int64_t o = J.off[l][p];
+      for (int c = 0; c < 3; c++)
+        for (int64_t q = cuts[c]; q < cuts[c + 1]; q += Z) {
+          const int64_t cnt = cuts[c + 1] - q < Z ? cuts[c + 1] - q : Z;
+          J.seg[l][o++] = make_int4((int)p, (int)q, (int)cnt, cls[c]);
+        }
+    }
+    __syncthreads();
+  }
+}
+
 constexpr int64_t NARROW_TARGET_WAVES = 8192;
 
 // Chain lengths of O_m (m = 1 or 2) in order, host side.
@@ -1044,9 +1167,32 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
     VX_FAIL(VX_ECAPACITY, "interval_eval_level: workspace of %zu bytes is too small (%zu needed)", ws_bytes,
             A.off + 256);
   int rc;
-  for (int l = 0; l < k; l++) {
-    const AxisGrid g = make_grid(dom, l, S->level, centre);
-    if ((rc = build_segments(E.seg[l], l == 0 ? nullptr : S->ptr[l - 1], S->idx[l], g, st))) return rc;
+  int64_t nmax = 0;
+  for (int l = 0; l < k; l++) nmax = S->n[l] > nmax ? S->n[l] : nmax;
+  if (nmax <= SMALL_LEVEL_NODES) {
+    SegJob J;
+    memset(&J, 0, sizeof J);
+    for (int l = 0; l < k; l++) {
+      const SegPlan& sp = E.seg[l];
+      J.ptr[l] = l == 0 ? nullptr : S->ptr[l - 1];
+      J.labels[l] = S->idx[l];
+      J.g[l] = make_grid(dom, l, S->level, centre);
+      J.Z[l] = sp.Z;
+      J.nparent[l] = sp.nparent;
+      J.nchild[l] = sp.nchild;
+      J.cnt[l] = sp.cnt;
+      J.bounds[l] = sp.bounds;
+      J.off[l] = sp.off;
+      J.seg[l] = sp.seg;
+      J.nseg[l] = sp.nseg;
+    }
+    hipLaunchKernelGGL(k_segments_small, dim3(1), dim3(SCAN_THREADS), 0, st, k, J);
+    VX_CHECK_LAUNCH("k_segments_small");
+  } else {
+    for (int l = 0; l < k; l++) {
+      const AxisGrid g = make_grid(dom, l, S->level, centre);
+      if ((rc = build_segments(E.seg[l], l == 0 ? nullptr : S->ptr[l - 1], S->idx[l], g, st))) return rc;
+    }
   }
   for (int p0 = 0; p0 < Q.np; p0 += PMAX) {
     const int pn = Q.np - p0 < PMAX ? Q.np - p0 : PMAX;

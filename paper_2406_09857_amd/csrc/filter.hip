@@ -16,6 +16,7 @@
 // All passes are scans and gathers with one thread per element; nothing
 // depends on scheduling order, so the output is deterministic.
 #include <hip/hip_runtime.h>
+#include <string.h>
 
 #include "common.hpp"
 #include "eval.hpp"
@@ -110,6 +111,105 @@ __global__ __launch_bounds__(FILL_THREADS) void k_next_fill(const int64_t* __res
   next_fill_tile(blockIdx.x, n, *ncnt_parent, part, nptr, src_parent, kptr, kidx, nidx, src);
 }
 
+// ---------------------------------------------------------------------------
+// Small levels: the whole filter in one workgroup (survival scans, compaction,
+// counts, next CSF), the same outputs as the multi-launch path below.
+// ---------------------------------------------------------------------------
+constexpr int64_t SMALL_FILTER_NODES = 4096;
+
+struct SmallFilterJob {
+  const int32_t* idx[VX_KMAX];
+  const int32_t* ptr[VX_KMAX];
+  int64_t n[VX_KMAX];
+  int32_t* newpos[VX_KMAX];
+  int32_t* kidx[VX_KMAX];
+  int32_t* kptr[VX_KMAX];
+  int32_t* nidx[VX_KMAX];
+  int32_t* nptr[VX_KMAX];
+  int32_t* src[VX_KMAX];
+  int64_t* kcnt;
+  int64_t* ncnt;
+  int64_t* d_counts;
+};
+
+// out[0..n] = exclusive prefix sums of ld(0..n-1); returns the total (all threads).
+template <class Loader>
+__device__ int64_t block_scan_to(Loader ld, int64_t n, int32_t* out) {
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += SCAN_TILE) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+    int64_t v[SCAN_ITEMS];
+    int64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+      v[j] = i0 + j < n ? ld(i0 + j) : 0;
+      sum += v[j];
+    }
+    int64_t tot;
+    int64_t run = carry + block_exclusive_scan(sum, tot);
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) {
+      if (i0 + j < n) out[i0 + j] = (int32_t)run;
+      run += v[j];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n] = (int32_t)carry;
+  __syncthreads();
+  return carry;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_filter_small(int k, const uint8_t* __restrict__ keep,
+                                                               SmallFilterJob J, int want_next) {
+  int64_t kc[VX_KMAX] = {0, 0, 0, 0};
+  kc[k - 1] = block_scan_to(KeepLoader{keep}, J.n[k - 1], J.newpos[k - 1]);
+  for (int l = k - 2; l >= 0; l--)
+    kc[l] = block_scan_to(AnyChildLoader{J.ptr[l], J.newpos[l + 1]}, J.n[l], J.newpos[l]);
+  for (int l = 0; l < k; l++) {
+    const bool inner = l + 1 < k;
+    for (int64_t i = threadIdx.x; i < J.n[l]; i += SCAN_THREADS)
+      if (J.newpos[l][i + 1] > J.newpos[l][i]) {
+        const int32_t o = J.newpos[l][i];
+        J.kidx[l][o] = J.idx[l][i];
+        if (inner) J.kptr[l][o] = J.newpos[l + 1][J.ptr[l][i]];
+      }
+    if (inner && threadIdx.x == 0) J.kptr[l][kc[l]] = (int32_t)kc[l + 1];
+  }
+  int64_t nc[VX_KMAX] = {0, 0, 0, 0};
+  for (int l = 0; l < k; l++) nc[l] = kc[l] << (l + 1);
+  if (threadIdx.x == 0)
+    for (int l = 0; l < k; l++) {
+      J.kcnt[l] = kc[l];
+      J.ncnt[l] = nc[l];
+      if (J.d_counts) {
+        J.d_counts[l] = kc[l];
+        J.d_counts[k + l] = nc[l];
+      }
+    }
+  if (!want_next) return;
+  __syncthreads();
+  for (int64_t o = threadIdx.x; o < nc[0]; o += SCAN_THREADS) {
+    J.nidx[0][o] = 2 * J.kidx[0][o >> 1] + (int32_t)(o & 1);
+    if (k > 1) J.src[0][o] = (int32_t)(o >> 1);
+  }
+  __syncthreads();
+  for (int l = 1; l < k; l++) {
+    block_scan_to(ChildCountLoader{J.src[l - 1], J.kptr[l - 1]}, nc[l - 1], J.nptr[l - 1]);
+    // one thread per new parent writes its children (2 per kept child)
+    for (int64_t P = threadIdx.x; P < nc[l - 1]; P += SCAN_THREADS) {
+      const int32_t y = J.src[l - 1][P];
+      const int32_t c0 = J.kptr[l - 1][y], c1 = J.kptr[l - 1][y + 1];
+      int64_t o = J.nptr[l - 1][P];
+      for (int32_t c = c0; c < c1; c++)
+        for (int b = 0; b < 2; b++, o++) {
+          J.nidx[l][o] = 2 * J.kidx[l][c] + b;
+          if (l + 1 < k) J.src[l][o] = c;
+        }
+    }
+    __syncthreads();
+  }
+}
+
 struct FilterPlan {
   int32_t* newpos[VX_KMAX] = {};
   int64_t* kcnt = nullptr;
@@ -173,6 +273,30 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
     VX_FAIL(VX_ECAPACITY, "filter_subdivide: workspace of %zu bytes is too small (%zu needed)", ws_bytes, A.off + 256);
   int32_t* const* kidx = kept ? kept->idx : F.kidx;
   int32_t* const* kptr = kept ? kept->ptr : F.kptr;
+
+  int64_t nmax = 0;
+  for (int l = 0; l < k; l++) nmax = S->n[l] > nmax ? S->n[l] : nmax;
+  if (nmax <= SMALL_FILTER_NODES) {
+    SmallFilterJob J;
+    memset(&J, 0, sizeof J);
+    for (int l = 0; l < k; l++) {
+      J.idx[l] = S->idx[l];
+      J.ptr[l] = l + 1 < k ? S->ptr[l] : nullptr;
+      J.n[l] = S->n[l];
+      J.newpos[l] = F.newpos[l];
+      J.kidx[l] = kidx[l];
+      J.kptr[l] = l + 1 < k ? kptr[l] : nullptr;
+      J.nidx[l] = next ? next->idx[l] : nullptr;
+      J.nptr[l] = (next && l + 1 < k) ? next->ptr[l] : nullptr;
+      J.src[l] = F.src[l];
+    }
+    J.kcnt = F.kcnt;
+    J.ncnt = F.ncnt;
+    J.d_counts = d_counts;
+    hipLaunchKernelGGL(k_filter_small, dim3(1), dim3(SCAN_THREADS), 0, st, k, keep, J, next ? 1 : 0);
+    VX_CHECK_LAUNCH("k_filter_small");
+    return VX_OK;
+  }
 
   // Survival scans, leaves first.
   scan_exclusive(KeepLoader{keep}, (const int64_t*)nullptr, S->n[k - 1], F.newpos[k - 1], F.kcnt + (k - 1), F.tiles,
