@@ -305,7 +305,16 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   csf_place(&S, k, 0, cap, base);
   if ((rc = init_root_impl(&S, st))) return rc;
 
-  std::vector<int64_t> counts(2 * k);
+  // Per-level counts come back through a mapped pinned host buffer written by
+  // the filter's last kernel: no copy launch, only the stream wait.
+  int64_t* counts = nullptr;
+  int64_t* counts_dev = nullptr;
+  VX_HIP(hipHostMalloc((void**)&counts, sizeof(int64_t) * 2 * VX_KMAX, hipHostMallocMapped | hipHostMallocCoherent));
+  struct PinGuard {
+    int64_t* p;
+    ~PinGuard() { (void)hipHostFree(p); }
+  } pin_guard{counts};
+  VX_HIP(hipHostGetDevicePointer((void**)&counts_dev, counts, 0));
   for (int level = 0; level <= depth; level++) {
     S.level = level;
     const int64_t nleaf = S.n[k - 1];
@@ -356,7 +365,8 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     double* lo = reinterpret_cast<double*>(mid_base + o_lo);
     double* hi = reinterpret_cast<double*>(mid_base + o_hi);
     uint8_t* keep = reinterpret_cast<uint8_t*>(mid_base + o_keep);
-    int64_t* d_counts = reinterpret_cast<int64_t*>(mid_base + o_cnt);
+    int64_t* d_counts = counts_dev;
+    (void)o_cnt;
     vx_csf K;
     csf_place(&K, k, level, kcap, mid_base + o_k);
     char* scratch = mid_base + o_scr;
@@ -373,7 +383,6 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     VX_HIP(hipEventRecord(ev[1], st));
     if ((rc = filter_impl(&S, keep, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st))) return rc;
     VX_HIP(hipEventRecord(ev[2], st));
-    VX_HIP(hipMemcpyAsync(counts.data(), d_counts, sizeof(int64_t) * 2 * k, hipMemcpyDeviceToHost, st));
     VX_HIP(hipStreamSynchronize(st));
     for (int l = 0; l < k; l++) K.n[l] = counts[l];
     if (stats) {
