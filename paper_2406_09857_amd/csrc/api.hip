@@ -84,6 +84,34 @@ static int64_t theorem1_steps(const vx_poly* P, int np, const vx_csf* S) {
 // ---------------------------------------------------------------------------
 namespace vx {
 
+// End-of-level signal: written after the filter's kernels (stream order), so
+// the counts they wrote to the same mapped host buffer are already there.
+__global__ void k_signal(int64_t* flag, int64_t value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    __threadfence_system();
+    *reinterpret_cast<volatile int64_t*>(flag) = value;
+  }
+}
+
+// Spin on the mapped flag instead of a stream wait (lower latency per level).
+// The stream is queried now and then so that a failed or idle stream ends the
+// wait with an error instead of spinning forever.
+static int wait_for_flag(const int64_t* flag, int64_t value, hipStream_t st) {
+  const volatile int64_t* f = flag;
+  for (uint64_t spin = 0;; spin++) {
+    if (*f == value) return VX_OK;
+    if ((spin & 1023) == 1023) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {  // stream drained: the flag must be visible after a full wait
+        VX_HIP(hipStreamSynchronize(st));
+        if (*f == value) return VX_OK;
+        VX_FAIL(VX_EHIP, "run_subdivision: the stream drained without signalling the level");
+      }
+      if (e != hipErrorNotReady) VX_FAIL(VX_EHIP, "run_subdivision: %s", hipGetErrorString(e));
+    }
+  }
+}
+
 static size_t csf_bytes(int k, const int64_t* cap) {
   size_t b = 0;
   for (int l = 0; l < k; l++) {
@@ -309,7 +337,8 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   // the filter's last kernel: no copy launch, only the stream wait.
   int64_t* counts = nullptr;
   int64_t* counts_dev = nullptr;
-  VX_HIP(hipHostMalloc((void**)&counts, sizeof(int64_t) * 2 * VX_KMAX, hipHostMallocMapped | hipHostMallocCoherent));
+  VX_HIP(hipHostMalloc((void**)&counts, sizeof(int64_t) * (2 * VX_KMAX + 1), hipHostMallocMapped | hipHostMallocCoherent));
+  counts[2 * VX_KMAX] = 0;  // level-done flag
   struct PinGuard {
     int64_t* p;
     ~PinGuard() { (void)hipHostFree(p); }
@@ -383,9 +412,12 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     VX_HIP(hipEventRecord(ev[1], st));
     if ((rc = filter_impl(&S, keep, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st))) return rc;
     VX_HIP(hipEventRecord(ev[2], st));
-    VX_HIP(hipStreamSynchronize(st));
+    hipLaunchKernelGGL(k_signal, dim3(1), dim3(64), 0, st, counts_dev + 2 * VX_KMAX, (int64_t)level + 1);
+    VX_CHECK_LAUNCH("k_signal");
+    if ((rc = wait_for_flag(counts + 2 * VX_KMAX, (int64_t)level + 1, st))) return rc;
     for (int l = 0; l < k; l++) K.n[l] = counts[l];
     if (stats) {
+      VX_HIP(hipEventSynchronize(ev[2]));
       vx_level_stat& r = stats[level];
       memset(&r, 0, sizeof r);
       r.level = level;
