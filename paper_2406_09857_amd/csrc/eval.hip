@@ -903,6 +903,91 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_segments_small(int k, SegJob J
   }
 }
 
+// Large levels: the segments of every depth in five launches in total (count,
+// three scan passes, write), blockIdx.y selecting the depth; the depths are
+// independent, so their work overlaps.
+__global__ void k_seg_count_all(int k, SegJob J) {
+  round_up_mode();
+  const int l = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= k || p >= J.nparent[l]) return;
+  const int32_t* ptr = J.ptr[l];
+  const int Z = J.Z[l];
+  const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : J.nchild[l];
+  int64_t ne, pb;
+  class_bounds(J.labels[l], b, e, J.g[l], ne, pb);
+  J.bounds[l][2 * p] = ne;
+  J.bounds[l][2 * p + 1] = pb;
+  J.cnt[l][p] = cdiv(ne - b, Z) + cdiv(pb - ne, Z) + cdiv(e - pb, Z);
+}
+
+struct MultiScan {
+  const int64_t* in[VX_KMAX];
+  int64_t* out[VX_KMAX];
+  int64_t* total[VX_KMAX];
+  int64_t* tiles[VX_KMAX];
+  int64_t n[VX_KMAX];
+};
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_mscan_tiles(MultiScan M) {
+  const int a = blockIdx.y;
+  const int64_t n = M.n[a];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  if (base > n) return;  // tiles [0, n / SCAN_TILE] exist for every array
+  const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int64_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++)
+    if (i0 + j < n) sum += M.in[a][i0 + j];
+  int64_t tot;
+  block_exclusive_scan(sum, tot);
+  if (threadIdx.x == 0) M.tiles[a][blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_mscan_sums(MultiScan M) {
+  const int a = blockIdx.y;
+  scan_tile_sums_body(M.tiles[a], M.n[a] / SCAN_TILE + 1, M.total[a]);
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_mscan_write(MultiScan M) {
+  const int a = blockIdx.y;
+  const int64_t n = M.n[a];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  if (base > n) return;
+  const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int64_t v[SCAN_ITEMS];
+  int64_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++) {
+    v[j] = i0 + j < n ? M.in[a][i0 + j] : 0;
+    sum += v[j];
+  }
+  int64_t tot;
+  int64_t run = block_exclusive_scan(sum, tot) + M.tiles[a][blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++) {
+    if (i0 + j <= n) M.out[a][i0 + j] = run;
+    run += v[j];
+  }
+}
+
+__global__ void k_seg_write_all(int k, SegJob J) {
+  const int l = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= k || p >= J.nparent[l]) return;
+  const int32_t* ptr = J.ptr[l];
+  const int Z = J.Z[l];
+  const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : J.nchild[l];
+  const int64_t cuts[4] = {b, J.bounds[l][2 * p], J.bounds[l][2 * p + 1], e};
+  const int cls[3] = {CLS_NEG, CLS_STRADDLE, CLS_POS};
+  int64_t o = J.off[l][p];
+  for (int c = 0; c < 3; c++)
+    for (int64_t q = cuts[c]; q < cuts[c + 1]; q += Z) {
+      const int64_t cnt = cuts[c + 1] - q < Z ? cuts[c + 1] - q : Z;
+      J.seg[l][o++] = make_int4((int)p, (int)q, (int)cnt, cls[c]);
+    }
+}
+
 constexpr int64_t NARROW_TARGET_WAVES = 8192;
 
 // Chain lengths of O_m (m = 1 or 2) in order, host side.
@@ -1169,30 +1254,47 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
   int rc;
   int64_t nmax = 0;
   for (int l = 0; l < k; l++) nmax = S->n[l] > nmax ? S->n[l] : nmax;
+  SegJob J;
+  memset(&J, 0, sizeof J);
+  int64_t pmax = 1;
+  for (int l = 0; l < k; l++) {
+    const SegPlan& sp = E.seg[l];
+    J.ptr[l] = l == 0 ? nullptr : S->ptr[l - 1];
+    J.labels[l] = S->idx[l];
+    J.g[l] = make_grid(dom, l, S->level, centre);
+    J.Z[l] = sp.Z;
+    J.nparent[l] = sp.nparent;
+    J.nchild[l] = sp.nchild;
+    J.cnt[l] = sp.cnt;
+    J.bounds[l] = sp.bounds;
+    J.off[l] = sp.off;
+    J.seg[l] = sp.seg;
+    J.nseg[l] = sp.nseg;
+    pmax = sp.nparent > pmax ? sp.nparent : pmax;
+  }
   if (nmax <= SMALL_LEVEL_NODES) {
-    SegJob J;
-    memset(&J, 0, sizeof J);
-    for (int l = 0; l < k; l++) {
-      const SegPlan& sp = E.seg[l];
-      J.ptr[l] = l == 0 ? nullptr : S->ptr[l - 1];
-      J.labels[l] = S->idx[l];
-      J.g[l] = make_grid(dom, l, S->level, centre);
-      J.Z[l] = sp.Z;
-      J.nparent[l] = sp.nparent;
-      J.nchild[l] = sp.nchild;
-      J.cnt[l] = sp.cnt;
-      J.bounds[l] = sp.bounds;
-      J.off[l] = sp.off;
-      J.seg[l] = sp.seg;
-      J.nseg[l] = sp.nseg;
-    }
     hipLaunchKernelGGL(k_segments_small, dim3(1), dim3(SCAN_THREADS), 0, st, k, J);
     VX_CHECK_LAUNCH("k_segments_small");
   } else {
+    const dim3 grid((unsigned)((pmax + 255) / 256), (unsigned)k);
+    hipLaunchKernelGGL(k_seg_count_all, grid, dim3(256), 0, st, k, J);
+    VX_CHECK_LAUNCH("k_seg_count_all");
+    MultiScan M;
+    memset(&M, 0, sizeof M);
     for (int l = 0; l < k; l++) {
-      const AxisGrid g = make_grid(dom, l, S->level, centre);
-      if ((rc = build_segments(E.seg[l], l == 0 ? nullptr : S->ptr[l - 1], S->idx[l], g, st))) return rc;
+      M.in[l] = E.seg[l].cnt;
+      M.out[l] = E.seg[l].off;
+      M.total[l] = E.seg[l].nseg;
+      M.tiles[l] = E.seg[l].tiles;
+      M.n[l] = E.seg[l].nparent;
     }
+    const dim3 sgrid((unsigned)(pmax / SCAN_TILE + 1), (unsigned)k);
+    hipLaunchKernelGGL(k_mscan_tiles, sgrid, dim3(SCAN_THREADS), 0, st, M);
+    hipLaunchKernelGGL(k_mscan_sums, dim3(1, k), dim3(SCAN_THREADS), 0, st, M);
+    hipLaunchKernelGGL(k_mscan_write, sgrid, dim3(SCAN_THREADS), 0, st, M);
+    VX_CHECK_LAUNCH("segment scans");
+    hipLaunchKernelGGL(k_seg_write_all, grid, dim3(256), 0, st, k, J);
+    VX_CHECK_LAUNCH("k_seg_write_all");
   }
   for (int p0 = 0; p0 < Q.np; p0 += PMAX) {
     const int pn = Q.np - p0 < PMAX ? Q.np - p0 : PMAX;

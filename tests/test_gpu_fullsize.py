@@ -1,0 +1,128 @@
+"""Full-size parity through run_subdivision, the entry point and launch
+configuration that the throughput measurement times.
+
+* The surface (one trivariate degree-40 polynomial, depth 9, 11.4M boxes at
+  the last level) and the curve (two trivariate degree-100 polynomials,
+  depth 10, 9.3M boxes at the last level): at every level the input CSF, the
+  enclosure bits of every box and polynomial, the keep flags, the kept CSF
+  and the Theorem-1 step count against the oracle, level by level, the
+  oracle's next level built from its own kept boxes.
+* The curve with the mean-value test on (Sec. 3.2, C0 and C1): at every
+  level a seeded sample of boxes is re-evaluated by the oracle on a CSF of
+  the sample alone (a box's enclosures depend on its own cells only), and
+  the combined keep flags must match; every level's CSF must be the children
+  of the previous level's kept boxes, and the kept CSF the boxes whose flag
+  is set.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import core as orc
+from paper_2406_09857_amd import synth
+from tests.helpers import bits_equal, csf_equal, first_mismatch
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_09857_amd import binding
+    binding.lib()
+    return binding
+
+
+def _gpu_run(vx, w, mean_value=False):
+    got = {}
+
+    def rec(level, S, lo, hi, keep, K):
+        got[level] = (S, lo, hi, keep.astype(bool), K)
+        return False
+
+    t = time.time()
+    stats, _ = vx.run_subdivision(w.polys, w.domain(), w.depth, record=rec, mean_value=mean_value)
+    _say(f"[full] {w.name} mean_value={mean_value}: GPU run with per-level copies {time.time() - t:.1f} s")
+    return stats, got
+
+
+def _boxes_of(S):
+    """Leaf boxes (level labels, one row per leaf) of a host CSF, in leaf order."""
+    k = S["k"]
+    cols = [np.asarray(S["idx"][k - 1], np.int64)]
+    up = np.arange(len(cols[0]))
+    for l in range(k - 2, -1, -1):
+        ptr = np.asarray(S["ptr"][l], np.int64)
+        up = np.searchsorted(ptr, up, side="right") - 1
+        cols.append(np.asarray(S["idx"][l], np.int64)[up])
+    return np.stack(cols[::-1], axis=1) if len(cols[0]) else np.zeros((0, k), np.int64)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["surface", "curve"])
+def test_full_size_every_level_bit_exact(vx, name):
+    w = getattr(synth, name)()
+    dom = w.domain()
+    stats, got = _gpu_run(vx, w)
+    boxes = np.zeros((1, w.k), np.int64)
+    for level in range(w.depth + 1):
+        t = time.time()
+        S_o = orc.csf_from_boxes(boxes, level)
+        lo_o, hi_o, steps = orc.eval_level(w.polys, S_o, dom, nthreads=orc.max_threads())
+        keep_o = orc.keep_mask(lo_o, hi_o)
+        K_o = orc.csf_from_boxes(S_o["boxes"][keep_o], level)
+        S, lo, hi, keep, K = got.pop(level)
+        tag = f"{w.name} level {level}"
+        assert csf_equal(S, S_o) and [len(a) for a in S["idx"]] == orc.csf_sizes(S_o), tag
+        assert bits_equal(lo, lo_o), (tag, "lo", first_mismatch(lo, lo_o))
+        assert bits_equal(hi, hi_o), (tag, "hi", first_mismatch(hi, hi_o))
+        assert np.array_equal(keep, keep_o), tag
+        assert csf_equal(K, K_o) and [len(a) for a in K["idx"]] == orc.csf_sizes(K_o), tag
+        assert stats[level]["n"] == orc.csf_sizes(S_o), tag
+        assert stats[level]["kept"] == orc.csf_sizes(K_o), tag
+        assert stats[level]["steps"] == int(steps.sum()), tag
+        _say(f"[full] {tag}: {orc.csf_sizes(S_o)} boxes, {int(keep_o.sum())} kept, oracle {time.time() - t:.1f} s")
+        boxes = orc.children_of(S_o["boxes"][keep_o])
+    assert not got
+
+
+@pytest.mark.timeout(900)
+def test_curve_mean_value_sampled_every_level(vx):
+    w = synth.curve()
+    dom = w.domain()
+    stats, got = _gpu_run(vx, w, mean_value=True)
+    rng = np.random.default_rng(2406)
+    prev_children = np.zeros((1, w.k), np.int64)
+    for level in range(w.depth + 1):
+        S, lo, hi, keep, K = got.pop(level)
+        tag = f"curve mean-value level {level}"
+        B = _boxes_of(S)
+        # structure: S is the children of the previous kept set, K its flagged boxes
+        assert csf_equal(S, orc.csf_from_boxes(prev_children, level)), tag
+        assert csf_equal(K, orc.csf_from_boxes(B[keep], level)), tag
+        assert stats[level]["n"] == [len(a) for a in S["idx"]], tag
+        # enclosures and flags on a sample
+        n = len(B)
+        pick = np.sort(rng.choice(n, size=min(n, 384), replace=False))
+        T = orc.csf_from_boxes(B[pick], level)
+        assert np.array_equal(T["boxes"], B[pick]), tag  # the sample's leaf order is its sorted order
+        t = time.time()
+        lo_o, hi_o, _ = orc.eval_level(w.polys, T, dom, nthreads=orc.max_threads())
+        mlo, mhi = orc.mean_value_level(w.polys, T, dom, nthreads=orc.max_threads())
+        keep_o = orc.keep_mask(lo_o, hi_o) & orc.keep_mask(mlo, mhi)
+        assert bits_equal(lo[:, pick], lo_o), (tag, "lo", first_mismatch(lo[:, pick], lo_o))
+        assert bits_equal(hi[:, pick], hi_o), (tag, "hi", first_mismatch(hi[:, pick], hi_o))
+        assert np.array_equal(keep[pick], keep_o), tag
+        _say(f"[full] {tag}: {n} boxes, {int(keep.sum())} kept, sample {len(pick)} "
+             f"({int(keep_o.sum())} kept), oracle {time.time() - t:.1f} s")
+        prev_children = orc.children_of(B[keep])
+    assert not got
