@@ -921,56 +921,6 @@ __global__ void k_seg_count_all(int k, SegJob J) {
   J.cnt[l][p] = cdiv(ne - b, Z) + cdiv(pb - ne, Z) + cdiv(e - pb, Z);
 }
 
-struct MultiScan {
-  const int64_t* in[VX_KMAX];
-  int64_t* out[VX_KMAX];
-  int64_t* total[VX_KMAX];
-  int64_t* tiles[VX_KMAX];
-  int64_t n[VX_KMAX];
-};
-
-__global__ __launch_bounds__(SCAN_THREADS) void k_mscan_tiles(MultiScan M) {
-  const int a = blockIdx.y;
-  const int64_t n = M.n[a];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-  if (base > n) return;  // tiles [0, n / SCAN_TILE] exist for every array
-  const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
-  int64_t sum = 0;
-#pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; j++)
-    if (i0 + j < n) sum += M.in[a][i0 + j];
-  int64_t tot;
-  block_exclusive_scan(sum, tot);
-  if (threadIdx.x == 0) M.tiles[a][blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(SCAN_THREADS) void k_mscan_sums(MultiScan M) {
-  const int a = blockIdx.y;
-  scan_tile_sums_body(M.tiles[a], M.n[a] / SCAN_TILE + 1, M.total[a]);
-}
-
-__global__ __launch_bounds__(SCAN_THREADS) void k_mscan_write(MultiScan M) {
-  const int a = blockIdx.y;
-  const int64_t n = M.n[a];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-  if (base > n) return;
-  const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
-  int64_t v[SCAN_ITEMS];
-  int64_t sum = 0;
-#pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; j++) {
-    v[j] = i0 + j < n ? M.in[a][i0 + j] : 0;
-    sum += v[j];
-  }
-  int64_t tot;
-  int64_t run = block_exclusive_scan(sum, tot) + M.tiles[a][blockIdx.x];
-#pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; j++) {
-    if (i0 + j <= n) M.out[a][i0 + j] = run;
-    run += v[j];
-  }
-}
-
 __global__ void k_seg_write_all(int k, SegJob J) {
   const int l = blockIdx.y;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1279,7 +1229,7 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
     const dim3 grid((unsigned)((pmax + 255) / 256), (unsigned)k);
     hipLaunchKernelGGL(k_seg_count_all, grid, dim3(256), 0, st, k, J);
     VX_CHECK_LAUNCH("k_seg_count_all");
-    MultiScan M;
+    MultiScan<int64_t, int64_t> M;
     memset(&M, 0, sizeof M);
     for (int l = 0; l < k; l++) {
       M.in[l] = E.seg[l].cnt;
@@ -1288,10 +1238,7 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
       M.tiles[l] = E.seg[l].tiles;
       M.n[l] = E.seg[l].nparent;
     }
-    const dim3 sgrid((unsigned)(pmax / SCAN_TILE + 1), (unsigned)k);
-    hipLaunchKernelGGL(k_mscan_tiles, sgrid, dim3(SCAN_THREADS), 0, st, M);
-    hipLaunchKernelGGL(k_mscan_sums, dim3(1, k), dim3(SCAN_THREADS), 0, st, M);
-    hipLaunchKernelGGL(k_mscan_write, sgrid, dim3(SCAN_THREADS), 0, st, M);
+    multi_scan(M, k, pmax, st);
     VX_CHECK_LAUNCH("segment scans");
     hipLaunchKernelGGL(k_seg_write_all, grid, dim3(256), 0, st, k, J);
     VX_CHECK_LAUNCH("k_seg_write_all");

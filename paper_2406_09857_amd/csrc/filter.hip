@@ -7,20 +7,26 @@
 //          newpos_l = exclusive scan of the survival flags, and a node's flag
 //          is newpos_{l+1}[ptr[q+1]] > newpos_{l+1}[ptr[q]].
 //   next = CSF of the children 2B + c, c in {0,1}^k, of every kept box B.  A
-//          depth-(l+1) node of K with label i becomes 2^(l+1) nodes; the
-//          children of a copy of node y are the labels 2 i' + b of y's
-//          children i' (b = 0, 1), so N_l(next) = 2^l N_l(K) and labels stay
-//          ascending under each parent.  Offsets come from a scan of the
-//          child counts; every output entry finds its parent by a search
-//          staged through LDS, one tile of outputs per workgroup.
-// All passes are scans and gathers with one thread per element; nothing
-// depends on scheduling order, so the output is deterministic.
+//          depth-l node z of K with label i (ancestors a_0 .. a_l = z) becomes
+//          the 2^(l+1) nodes (bits b_0 .. b_l) with labels 2 i + b_l, so
+//          N_l(next) = 2^(l+1) N_l(K).  Next's nodes are ordered by
+//          (a_0, b_0, a_1, b_1, ...), so with F_l(x) = index of the first
+//          depth-l descendant in K of node x (at depth i: kptr chained l - i
+//          times) the position of the copy is
+//            sum_i 2^(l-i+1) (F_l(a_i) - F_l(a_(i-1))) + b_i 2^(l-i) (F_l(a_i + 1) - F_l(a_i)),
+//          F_l(a_(-1)) = 0, and its child offset is the position of the copy
+//          (b_0 .. b_l, 0) of z's first kept child.  Every node of next is
+//          written by the thread of its K node, without scans or searches.
+// Large levels take seven launches: survival flags of the inner depths
+// (leaves up), one multi-array scan of every depth's flags, compaction of
+// every depth (which also records each kept node's parent), and the next CSF.
+// All passes have one thread per element and no atomics; nothing depends on
+// scheduling order, so the output is deterministic.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
 #include "common.hpp"
 #include "eval.hpp"
-#include "fill.hpp"
 #include "profile.hpp"
 #include "scan.hpp"
 
@@ -52,63 +58,143 @@ struct ChildCountLoader {
   }
 };
 
-// Write the kept nodes of one depth.
-__global__ void k_compact_level(int64_t n, const int32_t* __restrict__ newpos, const int32_t* __restrict__ idx,
-                                const int32_t* __restrict__ ptr, const int32_t* __restrict__ child_newpos,
-                                int32_t* __restrict__ kidx, int32_t* __restrict__ kptr,
-                                const int64_t* __restrict__ total_child) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && newpos[i + 1] > newpos[i]) {
-    const int32_t o = newpos[i];
-    kidx[o] = idx[i];
-    if (kptr) kptr[o] = child_newpos[ptr[i]];
-  }
-  if (i == 0 && kptr) kptr[newpos[n]] = (int32_t)*total_child;
+static_assert(MSCAN_MAX >= VX_KMAX, "one scan array per depth");
+
+// Survival flag of every depth-l node (l < k-1): some child survives.
+__global__ void k_alive(int64_t n, const int32_t* __restrict__ ptr, const uint8_t* __restrict__ child_alive,
+                        uint8_t* __restrict__ alive) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  uint8_t a = 0;
+  for (int32_t c = ptr[p], e = ptr[p + 1]; c < e && !a; c++) a = child_alive[c] != 0;
+  alive[p] = a;
 }
 
-__global__ void k_next_counts(int k, const int64_t* __restrict__ kcnt, int64_t* __restrict__ ncnt,
-                              int64_t* __restrict__ d_counts) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    for (int l = 0; l < k; l++) {
-      ncnt[l] = kcnt[l] << (l + 1);
-      if (d_counts) {
-        d_counts[l] = kcnt[l];
-        d_counts[k + l] = ncnt[l];
+struct CompactJob {
+  const int32_t* idx[VX_KMAX];
+  const int32_t* ptr[VX_KMAX];
+  const int32_t* newpos[VX_KMAX];
+  int32_t* kidx[VX_KMAX];
+  int32_t* kptr[VX_KMAX];
+  int32_t* kpar[VX_KMAX];  // kpar[l][j] = parent (depth l-1 index in K) of kept node j; null: not wanted
+  int64_t n[VX_KMAX];
+  const int64_t* kcnt;
+  int64_t* ncnt;
+  int64_t* d_counts;
+};
+
+// Kept nodes of every depth (blockIdx.y = depth).  A surviving node p lands
+// at newpos[p]; its kept children are the contiguous range newpos'[ptr[p]] ..
+// newpos'[ptr[p+1]] of the next depth.
+__global__ void k_compact_all(int k, CompactJob J) {
+  const int l = blockIdx.y;
+  const bool inner = l + 1 < k;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (inner) J.kptr[l][J.kcnt[l]] = (int32_t)J.kcnt[l + 1];
+    if (l == 0)
+      for (int m = 0; m < k; m++) {
+        J.ncnt[m] = J.kcnt[m] << (m + 1);
+        if (J.d_counts) {
+          J.d_counts[m] = J.kcnt[m];
+          J.d_counts[k + m] = J.ncnt[m];
+        }
       }
+  }
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= J.n[l]) return;
+  const int32_t q = J.newpos[l][p];
+  if (J.newpos[l][p + 1] == q) return;
+  J.kidx[l][q] = J.idx[l][p];
+  if (inner) {
+    const int32_t c0 = J.newpos[l + 1][J.ptr[l][p]], c1 = J.newpos[l + 1][J.ptr[l][p + 1]];
+    J.kptr[l][q] = c0;
+    if (J.kpar[l + 1])
+      for (int32_t c = c0; c < c1; c++) J.kpar[l + 1][c] = q;
+  }
+}
+
+struct GenJob {
+  const int32_t* kidx[VX_KMAX];
+  const int32_t* kptr[VX_KMAX];
+  const int32_t* kpar[VX_KMAX];
+  int32_t* nidx[VX_KMAX];
+  int32_t* nptr[VX_KMAX];
+  const int64_t* kcnt;
+  const int64_t* ncnt;
+};
+
+// Index of the first depth-L descendant in K of the depth-i node x (x may be
+// one past the last node of its depth).
+template <int L>
+__device__ __forceinline__ int64_t first_desc(const GenJob& J, int i, int64_t x) {
+#pragma unroll
+  for (int m = 0; m < L; m++)
+    if (m >= i) x = J.kptr[m][x];
+  return x;
+}
+
+// Position terms of the copies at depth L of the node with ancestors a[0..L]:
+// position(bits) = base + sum over set bits i of w[i] (bit i = b_i).
+template <int L>
+__device__ __forceinline__ void copy_terms(const GenJob& J, const int64_t* a, int64_t& base, int64_t* w) {
+  base = 0;
+  int64_t prev = 0;
+#pragma unroll
+  for (int i = 0; i <= L; i++) {
+    const int64_t f0 = first_desc<L>(J, i, a[i]);
+    const int64_t f1 = first_desc<L>(J, i, a[i] + 1);
+    base += (f0 - prev) << (L - i + 1);
+    w[i] = (f1 - f0) << (L - i);
+    prev = f0;
+  }
+}
+
+// The 2^(L+1) copies in next of kept depth-L node z, with their labels and
+// (inner depths) child offsets.
+template <int L>
+__device__ __forceinline__ void next_copies(const GenJob& J, int64_t z, bool inner) {
+  int64_t a[L + 2];
+  a[L] = z;
+#pragma unroll
+  for (int i = L; i > 0; i--) a[i - 1] = J.kpar[i][a[i]];
+  int64_t base, w[L + 1];
+  copy_terms<L>(J, a, base, w);
+  int64_t cbase = 0, cw[L + 2];
+  if (inner) {
+    a[L + 1] = J.kptr[L][z];
+    copy_terms<L + 1>(J, a, cbase, cw);
+  }
+  const int32_t lab = 2 * J.kidx[L][z];
+  for (unsigned hi = 0; hi < (1u << L); hi++) {  // b_0 .. b_(L-1)
+    int64_t o = base, c = cbase;
+#pragma unroll
+    for (int i = 0; i < L; i++)
+      if ((hi >> i) & 1) {
+        o += w[i];
+        c += inner ? cw[i] : 0;
+      }
+#pragma unroll
+    for (int b = 0; b < 2; b++) {  // b_L
+      const int64_t ob = o + (b ? w[L] : 0);
+      J.nidx[L][ob] = lab + b;
+      if (inner) J.nptr[L][ob] = (int32_t)(c + (b ? cw[L] : 0));
     }
   }
 }
 
-// Depth-1 nodes of next: 2i, 2i+1 for every depth-1 label i of K.
-__global__ void k_next_first(const int64_t* __restrict__ ncnt, const int32_t* __restrict__ kidx,
-                             int32_t* __restrict__ nidx, int32_t* __restrict__ src) {
-  const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= ncnt[0]) return;
-  const int64_t j = o >> 1;
-  nidx[o] = 2 * kidx[j] + (int32_t)(o & 1);
-  if (src) src[o] = (int32_t)j;
-}
-
-// Depth l+1 >= 2 of next: the parent of each tile's first output, then one
-// tile of outputs per workgroup.
-__global__ void k_fill_partition(const int64_t* __restrict__ ncnt_parent, const int64_t* __restrict__ ncnt,
-                                 const int32_t* __restrict__ nptr, int32_t* __restrict__ part) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t ntile = (*ncnt + FILL_TILE - 1) / FILL_TILE;
-  if (t <= ntile) fill_partition_at(t, ntile, *ncnt_parent, nptr, part);
-}
-
-__global__ __launch_bounds__(FILL_THREADS) void k_next_fill(const int64_t* __restrict__ ncnt_parent,
-                                                           const int64_t* __restrict__ ncnt,
-                                                           const int32_t* __restrict__ part,
-                                                           const int32_t* __restrict__ nptr,
-                                                           const int32_t* __restrict__ src_parent,
-                                                           const int32_t* __restrict__ kptr,
-                                                           const int32_t* __restrict__ kidx,
-                                                           int32_t* __restrict__ nidx, int32_t* __restrict__ src) {
-  const int64_t n = *ncnt;
-  if ((int64_t)blockIdx.x * FILL_TILE >= n) return;
-  next_fill_tile(blockIdx.x, n, *ncnt_parent, part, nptr, src_parent, kptr, kidx, nidx, src);
+// Next CSF, every depth (blockIdx.y = depth), one thread per kept node.
+__global__ void k_next_gen(int k, GenJob J) {
+  const int l = blockIdx.y;
+  const bool inner = l + 1 < k;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && inner) J.nptr[l][J.ncnt[l]] = (int32_t)J.ncnt[l + 1];
+  const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= J.kcnt[l]) return;
+  switch (l) {
+    case 0: next_copies<0>(J, z, inner); break;
+    case 1: next_copies<1>(J, z, inner); break;
+    case 2: next_copies<2>(J, z, inner); break;
+    default: next_copies<3>(J, z, inner); break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -212,34 +298,37 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_filter_small(int k, const uint
 
 struct FilterPlan {
   int32_t* newpos[VX_KMAX] = {};
+  uint8_t* alive[VX_KMAX] = {};
   int64_t* kcnt = nullptr;
   int64_t* ncnt = nullptr;
-  int64_t* tiles = nullptr;
+  int64_t* tiles[VX_KMAX] = {};
   int32_t* kidx[VX_KMAX] = {};
   int32_t* kptr[VX_KMAX] = {};
+  int32_t* kpar[VX_KMAX] = {};
   int32_t* src[VX_KMAX] = {};
-  int32_t* part = nullptr;
 };
 
 static void plan_filter(Arena& A, FilterPlan& F, const vx_csf* S, bool own_kept, bool want_next) {
   const int k = S->k;
-  int64_t maxn = 1;
+  int64_t nmax = 1;
   for (int l = 0; l < k; l++) {
     F.newpos[l] = A.take<int32_t>(S->n[l] + 1);
-    const int64_t nb = S->n[l] << (l + 1);
-    maxn = maxn > nb ? maxn : nb;
+    F.tiles[l] = A.take<int64_t>(scan_tiles(S->n[l]));
+    if (l + 1 < k) F.alive[l] = A.take<uint8_t>(S->n[l] > 0 ? S->n[l] : 1);
+    nmax = nmax > S->n[l] ? nmax : S->n[l];
   }
   F.kcnt = A.take<int64_t>(VX_KMAX);
   F.ncnt = A.take<int64_t>(VX_KMAX);
-  F.tiles = A.take<int64_t>(scan_tiles(maxn));
   if (own_kept)
     for (int l = 0; l < k; l++) {
       F.kidx[l] = A.take<int32_t>(S->n[l] > 0 ? S->n[l] : 1);
       if (l + 1 < k) F.kptr[l] = A.take<int32_t>(S->n[l] + 1);
     }
   if (want_next) {
-    for (int l = 0; l + 1 < k; l++) F.src[l] = A.take<int32_t>((S->n[l] << (l + 1)) + 1);
-    F.part = A.take<int32_t>(maxn / FILL_TILE + 2);
+    if (nmax <= SMALL_FILTER_NODES)
+      for (int l = 0; l + 1 < k; l++) F.src[l] = A.take<int32_t>((S->n[l] << (l + 1)) + 1);
+    else
+      for (int l = 1; l < k; l++) F.kpar[l] = A.take<int32_t>(S->n[l] > 0 ? S->n[l] : 1);
   }
 }
 
@@ -298,54 +387,57 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
     return VX_OK;
   }
 
-  // Survival scans, leaves first.
-  scan_exclusive(KeepLoader{keep}, (const int64_t*)nullptr, S->n[k - 1], F.newpos[k - 1], F.kcnt + (k - 1), F.tiles,
-                 st);
-  VX_CHECK_LAUNCH("keep scan");
+  // Survival flags of the inner depths, leaves up; then every depth's scan.
   for (int l = k - 2; l >= 0; l--) {
-    scan_exclusive(AnyChildLoader{S->ptr[l], F.newpos[l + 1]}, (const int64_t*)nullptr, S->n[l], F.newpos[l],
-                   F.kcnt + l, F.tiles, st);
-    VX_CHECK_LAUNCH("survival scan");
-  }
-  // Compacted K.
-  for (int l = 0; l < k; l++) {
     const int64_t n = S->n[l];
-    const bool inner = l + 1 < k;
-    hipLaunchKernelGGL(k_compact_level, dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)), dim3(256), 0,
-                       st, n, (const int32_t*)F.newpos[l], (const int32_t*)S->idx[l],
-                       inner ? (const int32_t*)S->ptr[l] : nullptr, inner ? (const int32_t*)F.newpos[l + 1] : nullptr,
-                       kidx[l], inner ? kptr[l] : nullptr, inner ? (const int64_t*)(F.kcnt + l + 1) : nullptr);
-    VX_CHECK_LAUNCH("k_compact_level");
+    hipLaunchKernelGGL(k_alive, dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)), dim3(256), 0, st, n,
+                       (const int32_t*)S->ptr[l], l + 2 < k ? (const uint8_t*)F.alive[l + 1] : keep, F.alive[l]);
+    VX_CHECK_LAUNCH("k_alive");
   }
-  hipLaunchKernelGGL(k_next_counts, dim3(1), dim3(64), 0, st, k, (const int64_t*)F.kcnt, F.ncnt, d_counts);
-  VX_CHECK_LAUNCH("k_next_counts");
+  MultiScan<uint8_t, int32_t> M;
+  memset(&M, 0, sizeof M);
+  for (int l = 0; l < k; l++) {
+    M.in[l] = l + 1 < k ? F.alive[l] : keep;
+    M.out[l] = F.newpos[l];
+    M.total[l] = F.kcnt + l;
+    M.tiles[l] = F.tiles[l];
+    M.n[l] = S->n[l];
+  }
+  multi_scan(M, k, nmax, st);
+  VX_CHECK_LAUNCH("survival scans");
+  // Compacted K (and each kept node's parent when next is wanted).
+  CompactJob C;
+  memset(&C, 0, sizeof C);
+  for (int l = 0; l < k; l++) {
+    C.idx[l] = S->idx[l];
+    C.ptr[l] = l + 1 < k ? S->ptr[l] : nullptr;
+    C.newpos[l] = F.newpos[l];
+    C.kidx[l] = kidx[l];
+    C.kptr[l] = l + 1 < k ? kptr[l] : nullptr;
+    C.kpar[l] = next ? F.kpar[l] : nullptr;
+    C.n[l] = S->n[l];
+  }
+  C.kcnt = F.kcnt;
+  C.ncnt = F.ncnt;
+  C.d_counts = d_counts;
+  const unsigned blocks = (unsigned)((nmax + 255) / 256);
+  hipLaunchKernelGGL(k_compact_all, dim3(blocks, k), dim3(256), 0, st, k, C);
+  VX_CHECK_LAUNCH("k_compact_all");
   if (!next) return VX_OK;
-
   // Children CSF.
-  {
-    const int64_t bound = S->n[0] << 1;
-    hipLaunchKernelGGL(k_next_first, dim3((unsigned)((bound + 255) / 256 > 0 ? (bound + 255) / 256 : 1)), dim3(256),
-                       0, st, (const int64_t*)F.ncnt, (const int32_t*)kidx[0], next->idx[0],
-                       k > 1 ? F.src[0] : nullptr);
-    VX_CHECK_LAUNCH("k_next_first");
+  GenJob G;
+  memset(&G, 0, sizeof G);
+  for (int l = 0; l < k; l++) {
+    G.kidx[l] = kidx[l];
+    G.kptr[l] = l + 1 < k ? kptr[l] : nullptr;
+    G.kpar[l] = F.kpar[l];
+    G.nidx[l] = next->idx[l];
+    G.nptr[l] = l + 1 < k ? next->ptr[l] : nullptr;
   }
-  for (int l = 1; l < k; l++) {
-    const int64_t pbound = S->n[l - 1] << l;       // next depth-l count bound
-    const int64_t bound = S->n[l] << (l + 1);      // next depth-(l+1) count bound
-    scan_exclusive(ChildCountLoader{F.src[l - 1], kptr[l - 1]}, (const int64_t*)(F.ncnt + l - 1), pbound,
-                   next->ptr[l - 1], (int64_t*)nullptr, F.tiles, st);
-    VX_CHECK_LAUNCH("child count scan");
-    const int64_t tiles = (bound + FILL_TILE - 1) / FILL_TILE;
-    hipLaunchKernelGGL(k_fill_partition, dim3((unsigned)((tiles + 1 + 255) / 256)), dim3(256), 0, st,
-                       (const int64_t*)(F.ncnt + l - 1), (const int64_t*)(F.ncnt + l),
-                       (const int32_t*)next->ptr[l - 1], F.part);
-    VX_CHECK_LAUNCH("k_fill_partition");
-    hipLaunchKernelGGL(k_next_fill, dim3((unsigned)(tiles > 0 ? tiles : 1)), dim3(FILL_THREADS), 0, st,
-                       (const int64_t*)(F.ncnt + l - 1), (const int64_t*)(F.ncnt + l), (const int32_t*)F.part,
-                       (const int32_t*)next->ptr[l - 1], (const int32_t*)F.src[l - 1], (const int32_t*)kptr[l - 1],
-                       (const int32_t*)kidx[l], next->idx[l], l + 1 < k ? F.src[l] : nullptr);
-    VX_CHECK_LAUNCH("k_next_fill");
-  }
+  G.kcnt = F.kcnt;
+  G.ncnt = F.ncnt;
+  hipLaunchKernelGGL(k_next_gen, dim3(blocks, k), dim3(256), 0, st, k, G);
+  VX_CHECK_LAUNCH("k_next_gen");
   return VX_OK;
 }
 

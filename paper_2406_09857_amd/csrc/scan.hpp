@@ -142,4 +142,76 @@ void scan_exclusive(Loader ld, const int64_t* n_dev, int64_t nmax, OutT* out, in
                      (const int64_t*)tile_buf, out);
 }
 
+// Several independent exclusive scans in three launches, blockIdx.y picking
+// the array: out_a[0..n_a] = exclusive prefix sums of in_a, out_a[n_a] =
+// total_a = *total[a].  Inputs are 0/1 flags (uint8, nonzero counts as 1) or
+// int64 counts; tiles[a] needs scan_tiles(n_a) int64s.
+constexpr int MSCAN_MAX = 4;
+
+__device__ __forceinline__ int64_t mscan_value(uint8_t v) { return v != 0; }
+__device__ __forceinline__ int64_t mscan_value(int64_t v) { return v; }
+
+template <class In, class Out>
+struct MultiScan {
+  const In* in[MSCAN_MAX];
+  Out* out[MSCAN_MAX];
+  int64_t* total[MSCAN_MAX];
+  int64_t* tiles[MSCAN_MAX];
+  int64_t n[MSCAN_MAX];
+};
+
+template <class In, class Out>
+__global__ __launch_bounds__(SCAN_THREADS) void k_mscan_tiles(MultiScan<In, Out> M) {
+  const int a = blockIdx.y;
+  const int64_t n = M.n[a];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  if (base > n) return;  // tiles 0 .. n / SCAN_TILE exist for every array
+  const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int64_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++)
+    if (i0 + j < n) sum += mscan_value(M.in[a][i0 + j]);
+  int64_t tot;
+  block_exclusive_scan(sum, tot);
+  if (threadIdx.x == 0) M.tiles[a][blockIdx.x] = tot;
+}
+
+template <class In, class Out>
+__global__ __launch_bounds__(SCAN_THREADS) void k_mscan_sums(MultiScan<In, Out> M) {
+  const int a = blockIdx.y;
+  scan_tile_sums_body(M.tiles[a], M.n[a] / SCAN_TILE + 1, M.total[a]);
+}
+
+template <class In, class Out>
+__global__ __launch_bounds__(SCAN_THREADS) void k_mscan_write(MultiScan<In, Out> M) {
+  const int a = blockIdx.y;
+  const int64_t n = M.n[a];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  if (base > n) return;
+  const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int64_t v[SCAN_ITEMS];
+  int64_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++) {
+    v[j] = i0 + j < n ? mscan_value(M.in[a][i0 + j]) : 0;
+    sum += v[j];
+  }
+  int64_t tot;
+  int64_t run = block_exclusive_scan(sum, tot) + M.tiles[a][blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++) {
+    if (i0 + j <= n) M.out[a][i0 + j] = (Out)run;
+    run += v[j];
+  }
+}
+
+// count arrays (count <= MSCAN_MAX), nmax = the largest n.
+template <class In, class Out>
+void multi_scan(const MultiScan<In, Out>& M, int count, int64_t nmax, hipStream_t st) {
+  const dim3 grid((unsigned)(nmax / SCAN_TILE + 1), (unsigned)count);
+  hipLaunchKernelGGL((k_mscan_tiles<In, Out>), grid, dim3(SCAN_THREADS), 0, st, M);
+  hipLaunchKernelGGL((k_mscan_sums<In, Out>), dim3(1, count), dim3(SCAN_THREADS), 0, st, M);
+  hipLaunchKernelGGL((k_mscan_write<In, Out>), grid, dim3(SCAN_THREADS), 0, st, M);
+}
+
 }  // namespace vx
