@@ -904,13 +904,14 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_segments_small(int k, SegJob J
 }
 
 // Large levels: the segments of every depth in five launches in total (count,
-// three scan passes, write), blockIdx.y selecting the depth; the depths are
+// three scan passes, write), the depths sharing one 1-D grid; they are
 // independent, so their work overlaps.
-__global__ void k_seg_count_all(int k, SegJob J) {
+__global__ void k_seg_count_all(DepthBlocks D, SegJob J) {
   round_up_mode();
-  const int l = blockIdx.y;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= k || p >= J.nparent[l]) return;
+  int64_t t;
+  const int l = D.find(blockIdx.x, t);
+  const int64_t p = t * blockDim.x + threadIdx.x;
+  if (p >= J.nparent[l]) return;
   const int32_t* ptr = J.ptr[l];
   const int Z = J.Z[l];
   const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : J.nchild[l];
@@ -921,10 +922,11 @@ __global__ void k_seg_count_all(int k, SegJob J) {
   J.cnt[l][p] = cdiv(ne - b, Z) + cdiv(pb - ne, Z) + cdiv(e - pb, Z);
 }
 
-__global__ void k_seg_write_all(int k, SegJob J) {
-  const int l = blockIdx.y;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= k || p >= J.nparent[l]) return;
+__global__ void k_seg_write_all(DepthBlocks D, SegJob J) {
+  int64_t t;
+  const int l = D.find(blockIdx.x, t);
+  const int64_t p = t * blockDim.x + threadIdx.x;
+  if (p >= J.nparent[l]) return;
   const int32_t* ptr = J.ptr[l];
   const int Z = J.Z[l];
   const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : J.nchild[l];
@@ -1206,7 +1208,6 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
   for (int l = 0; l < k; l++) nmax = S->n[l] > nmax ? S->n[l] : nmax;
   SegJob J;
   memset(&J, 0, sizeof J);
-  int64_t pmax = 1;
   for (int l = 0; l < k; l++) {
     const SegPlan& sp = E.seg[l];
     J.ptr[l] = l == 0 ? nullptr : S->ptr[l - 1];
@@ -1220,14 +1221,14 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
     J.off[l] = sp.off;
     J.seg[l] = sp.seg;
     J.nseg[l] = sp.nseg;
-    pmax = sp.nparent > pmax ? sp.nparent : pmax;
   }
   if (nmax <= SMALL_LEVEL_NODES) {
     hipLaunchKernelGGL(k_segments_small, dim3(1), dim3(SCAN_THREADS), 0, st, k, J);
     VX_CHECK_LAUNCH("k_segments_small");
   } else {
-    const dim3 grid((unsigned)((pmax + 255) / 256), (unsigned)k);
-    hipLaunchKernelGGL(k_seg_count_all, grid, dim3(256), 0, st, k, J);
+    const DepthBlocks D = depth_blocks(J.nparent, k, 256);
+    const dim3 grid(D.blocks());
+    hipLaunchKernelGGL(k_seg_count_all, grid, dim3(256), 0, st, D, J);
     VX_CHECK_LAUNCH("k_seg_count_all");
     MultiScan<int64_t, int64_t> M;
     memset(&M, 0, sizeof M);
@@ -1238,9 +1239,9 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
       M.tiles[l] = E.seg[l].tiles;
       M.n[l] = E.seg[l].nparent;
     }
-    multi_scan(M, k, pmax, st);
+    multi_scan(M, k, st);
     VX_CHECK_LAUNCH("segment scans");
-    hipLaunchKernelGGL(k_seg_write_all, grid, dim3(256), 0, st, k, J);
+    hipLaunchKernelGGL(k_seg_write_all, grid, dim3(256), 0, st, D, J);
     VX_CHECK_LAUNCH("k_seg_write_all");
   }
   for (int p0 = 0; p0 < Q.np; p0 += PMAX) {

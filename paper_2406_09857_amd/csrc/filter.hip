@@ -60,13 +60,47 @@ struct ChildCountLoader {
 
 static_assert(MSCAN_MAX >= VX_KMAX, "one scan array per depth");
 
-// Survival flag of every depth-l node (l < k-1): some child survives.
+// Survival flag of every depth-l node (l < k-1): some child survives.  One
+// thread per node reads its children's flags eight bytes at a time, eight
+// words in flight, and stops at the first batch holding a survivor.  Bytes of
+// a word outside the node's range are masked; the word holding the array's
+// last byte, and every word of a flag array that is not 8-byte aligned, are
+// read bytewise so that nothing past the array is touched.
+constexpr int ALIVE_BATCH = 8;
+
+__device__ __forceinline__ uint64_t flag_word(const uint8_t* __restrict__ f, int64_t wi, int64_t nf, bool aligned) {
+  if (aligned && (wi + 1) * 8 <= nf) return reinterpret_cast<const uint64_t*>(f)[wi];
+  uint64_t v = 0;
+  for (int j = 0; j < 8; j++) {
+    const int64_t c = wi * 8 + j;
+    if (c >= 0 && c < nf) v |= (uint64_t)f[c] << (8 * j);
+  }
+  return v;
+}
+
 __global__ void k_alive(int64_t n, const int32_t* __restrict__ ptr, const uint8_t* __restrict__ child_alive,
-                        uint8_t* __restrict__ alive) {
+                        int64_t nchild, uint8_t* __restrict__ alive) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  uint8_t a = 0;
-  for (int32_t c = ptr[p], e = ptr[p + 1]; c < e && !a; c++) a = child_alive[c] != 0;
+  const bool aligned = ((uintptr_t)child_alive & 7) == 0;
+  const int64_t b = ptr[p], e = ptr[p + 1];
+  const int64_t we = (e + 7) >> 3;  // one past the last word
+  bool a = false;
+  for (int64_t wb = b >> 3; wb < we && !a; wb += ALIVE_BATCH) {
+    uint64_t acc = 0;
+#pragma unroll
+    for (int u = 0; u < ALIVE_BATCH; u++) {
+      const int64_t wi = wb + u;
+      if (wi < we) {
+        uint64_t v = flag_word(child_alive, wi, nchild, aligned);
+        const int64_t lo = b - wi * 8, hi = e - wi * 8;  // the node's bytes within this word
+        if (lo > 0) v &= ~0ull << (8 * lo);
+        if (hi < 8) v &= ~0ull >> (8 * (8 - hi));
+        acc |= v;
+      }
+    }
+    a = acc != 0;
+  }
   alive[p] = a;
 }
 
@@ -83,13 +117,14 @@ struct CompactJob {
   int64_t* d_counts;
 };
 
-// Kept nodes of every depth (blockIdx.y = depth).  A surviving node p lands
-// at newpos[p]; its kept children are the contiguous range newpos'[ptr[p]] ..
-// newpos'[ptr[p+1]] of the next depth.
-__global__ void k_compact_all(int k, CompactJob J) {
-  const int l = blockIdx.y;
+// Kept nodes of every depth (one 1-D grid over the depths).  A surviving
+// node p lands at newpos[p]; its kept children are the contiguous range
+// newpos'[ptr[p]] .. newpos'[ptr[p+1]] of the next depth.
+__global__ void k_compact_all(int k, DepthBlocks D, CompactJob J) {
+  int64_t t;
+  const int l = D.find(blockIdx.x, t);
   const bool inner = l + 1 < k;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (t == 0 && threadIdx.x == 0) {
     if (inner) J.kptr[l][J.kcnt[l]] = (int32_t)J.kcnt[l + 1];
     if (l == 0)
       for (int m = 0; m < k; m++) {
@@ -100,7 +135,7 @@ __global__ void k_compact_all(int k, CompactJob J) {
         }
       }
   }
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t p = t * blockDim.x + threadIdx.x;
   if (p >= J.n[l]) return;
   const int32_t q = J.newpos[l][p];
   if (J.newpos[l][p + 1] == q) return;
@@ -182,12 +217,13 @@ __device__ __forceinline__ void next_copies(const GenJob& J, int64_t z, bool inn
   }
 }
 
-// Next CSF, every depth (blockIdx.y = depth), one thread per kept node.
-__global__ void k_next_gen(int k, GenJob J) {
-  const int l = blockIdx.y;
+// Next CSF, every depth (one 1-D grid over the depths), one thread per kept node.
+__global__ void k_next_gen(int k, DepthBlocks D, GenJob J) {
+  int64_t t;
+  const int l = D.find(blockIdx.x, t);
   const bool inner = l + 1 < k;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && inner) J.nptr[l][J.ncnt[l]] = (int32_t)J.ncnt[l + 1];
-  const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0 && threadIdx.x == 0 && inner) J.nptr[l][J.ncnt[l]] = (int32_t)J.ncnt[l + 1];
+  const int64_t z = t * blockDim.x + threadIdx.x;
   if (z >= J.kcnt[l]) return;
   switch (l) {
     case 0: next_copies<0>(J, z, inner); break;
@@ -391,7 +427,8 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
   for (int l = k - 2; l >= 0; l--) {
     const int64_t n = S->n[l];
     hipLaunchKernelGGL(k_alive, dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)), dim3(256), 0, st, n,
-                       (const int32_t*)S->ptr[l], l + 2 < k ? (const uint8_t*)F.alive[l + 1] : keep, F.alive[l]);
+                       (const int32_t*)S->ptr[l], l + 2 < k ? (const uint8_t*)F.alive[l + 1] : keep, S->n[l + 1],
+                       F.alive[l]);
     VX_CHECK_LAUNCH("k_alive");
   }
   MultiScan<uint8_t, int32_t> M;
@@ -403,7 +440,7 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
     M.tiles[l] = F.tiles[l];
     M.n[l] = S->n[l];
   }
-  multi_scan(M, k, nmax, st);
+  multi_scan(M, k, st);
   VX_CHECK_LAUNCH("survival scans");
   // Compacted K (and each kept node's parent when next is wanted).
   CompactJob C;
@@ -420,8 +457,8 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
   C.kcnt = F.kcnt;
   C.ncnt = F.ncnt;
   C.d_counts = d_counts;
-  const unsigned blocks = (unsigned)((nmax + 255) / 256);
-  hipLaunchKernelGGL(k_compact_all, dim3(blocks, k), dim3(256), 0, st, k, C);
+  const DepthBlocks D = depth_blocks(S->n, k, 256);
+  hipLaunchKernelGGL(k_compact_all, dim3(D.blocks()), dim3(256), 0, st, k, D, C);
   VX_CHECK_LAUNCH("k_compact_all");
   if (!next) return VX_OK;
   // Children CSF.
@@ -436,7 +473,7 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
   }
   G.kcnt = F.kcnt;
   G.ncnt = F.ncnt;
-  hipLaunchKernelGGL(k_next_gen, dim3(blocks, k), dim3(256), 0, st, k, G);
+  hipLaunchKernelGGL(k_next_gen, dim3(D.blocks()), dim3(256), 0, st, k, D, G);
   VX_CHECK_LAUNCH("k_next_gen");
   return VX_OK;
 }

@@ -142,14 +142,37 @@ void scan_exclusive(Loader ld, const int64_t* n_dev, int64_t nmax, OutT* out, in
                      (const int64_t*)tile_buf, out);
 }
 
-// Several independent exclusive scans in three launches, blockIdx.y picking
-// the array: out_a[0..n_a] = exclusive prefix sums of in_a, out_a[n_a] =
-// total_a = *total[a].  Inputs are 0/1 flags (uint8, nonzero counts as 1) or
-// int64 counts; tiles[a] needs scan_tiles(n_a) int64s.
+// Several independent exclusive scans in three launches: out_a[0..n_a] =
+// exclusive prefix sums of in_a, out_a[n_a] = total_a = *total[a].  Inputs
+// are 0/1 flags (uint8, nonzero counts as 1) or int64 counts; tiles[a] needs
+// scan_tiles(n_a) int64s.  The tiles of all arrays share one 1-D grid, so
+// no workgroup is launched idle.
 constexpr int MSCAN_MAX = 4;
 
-__device__ __forceinline__ int64_t mscan_value(uint8_t v) { return v != 0; }
-__device__ __forceinline__ int64_t mscan_value(int64_t v) { return v; }
+// One 1-D grid over several arrays: array a owns blocks off[a] .. off[a+1]-1,
+// n[a] / per_block + 1 of them (at least one, covering elements 0 .. n[a]).
+struct DepthBlocks {
+  int64_t off[MSCAN_MAX + 1];
+  int count;
+  // Array of block b and the block's index within it.
+  __device__ __forceinline__ int find(int64_t b, int64_t& t) const {
+    int a = 0;
+#pragma unroll
+    for (int i = 1; i < MSCAN_MAX; i++)
+      if (i < count && b >= off[i]) a = i;
+    t = b - off[a];
+    return a;
+  }
+  unsigned blocks() const { return (unsigned)off[count]; }
+};
+
+inline DepthBlocks depth_blocks(const int64_t* n, int count, int64_t per_block) {
+  DepthBlocks D;
+  D.count = count;
+  D.off[0] = 0;
+  for (int a = 0; a < MSCAN_MAX; a++) D.off[a + 1] = D.off[a] + (a < count ? n[a] / per_block + 1 : 0);
+  return D;
+}
 
 template <class In, class Out>
 struct MultiScan {
@@ -158,60 +181,99 @@ struct MultiScan {
   int64_t* total[MSCAN_MAX];
   int64_t* tiles[MSCAN_MAX];
   int64_t n[MSCAN_MAX];
+  DepthBlocks D;
 };
+
+// The SCAN_ITEMS inputs of one thread (consecutive, i0 .. i0+7), 0 past n.
+__device__ __forceinline__ void mscan_load(const uint8_t* in, int64_t i0, int64_t n, int64_t* v) {
+  if (i0 + SCAN_ITEMS <= n && ((uintptr_t)(in + i0) & 7) == 0) {
+    const uint64_t w = *reinterpret_cast<const uint64_t*>(in + i0);
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) v[j] = ((w >> (8 * j)) & 0xff) != 0;
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++) v[j] = i0 + j < n ? in[i0 + j] != 0 : 0;
+  }
+}
+
+__device__ __forceinline__ void mscan_load(const int64_t* in, int64_t i0, int64_t n, int64_t* v) {
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++) v[j] = i0 + j < n ? in[i0 + j] : 0;
+}
+
+// out[i0 + j] = r[j] for i0 + j <= n.
+__device__ __forceinline__ void mscan_store(int32_t* out, int64_t i0, int64_t n, const int64_t* r) {
+  if (i0 + SCAN_ITEMS <= n + 1 && ((uintptr_t)(out + i0) & 31) == 0) {
+    int4* o = reinterpret_cast<int4*>(out + i0);
+    o[0] = make_int4((int)r[0], (int)r[1], (int)r[2], (int)r[3]);
+    o[1] = make_int4((int)r[4], (int)r[5], (int)r[6], (int)r[7]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; j++)
+      if (i0 + j <= n) out[i0 + j] = (int32_t)r[j];
+  }
+}
+
+__device__ __forceinline__ void mscan_store(int64_t* out, int64_t i0, int64_t n, const int64_t* r) {
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; j++)
+    if (i0 + j <= n) out[i0 + j] = r[j];
+}
+
+static_assert(SCAN_ITEMS == 8, "the vector paths of mscan_load / mscan_store move 8 items");
 
 template <class In, class Out>
 __global__ __launch_bounds__(SCAN_THREADS) void k_mscan_tiles(MultiScan<In, Out> M) {
-  const int a = blockIdx.y;
+  int64_t t;
+  const int a = M.D.find(blockIdx.x, t);
   const int64_t n = M.n[a];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-  if (base > n) return;  // tiles 0 .. n / SCAN_TILE exist for every array
-  const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+  const int64_t i0 = t * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int64_t v[SCAN_ITEMS];
+  mscan_load(M.in[a], i0, n, v);
   int64_t sum = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; j++)
-    if (i0 + j < n) sum += mscan_value(M.in[a][i0 + j]);
+  for (int j = 0; j < SCAN_ITEMS; j++) sum += v[j];
   int64_t tot;
   block_exclusive_scan(sum, tot);
-  if (threadIdx.x == 0) M.tiles[a][blockIdx.x] = tot;
+  if (threadIdx.x == 0) M.tiles[a][t] = tot;
 }
 
 template <class In, class Out>
 __global__ __launch_bounds__(SCAN_THREADS) void k_mscan_sums(MultiScan<In, Out> M) {
-  const int a = blockIdx.y;
+  const int a = blockIdx.x;
   scan_tile_sums_body(M.tiles[a], M.n[a] / SCAN_TILE + 1, M.total[a]);
 }
 
 template <class In, class Out>
 __global__ __launch_bounds__(SCAN_THREADS) void k_mscan_write(MultiScan<In, Out> M) {
-  const int a = blockIdx.y;
+  int64_t t;
+  const int a = M.D.find(blockIdx.x, t);
   const int64_t n = M.n[a];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-  if (base > n) return;
-  const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
+  const int64_t i0 = t * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int64_t v[SCAN_ITEMS];
+  mscan_load(M.in[a], i0, n, v);
   int64_t sum = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; j++) {
-    v[j] = i0 + j < n ? mscan_value(M.in[a][i0 + j]) : 0;
-    sum += v[j];
-  }
+  for (int j = 0; j < SCAN_ITEMS; j++) sum += v[j];
   int64_t tot;
-  int64_t run = block_exclusive_scan(sum, tot) + M.tiles[a][blockIdx.x];
+  int64_t run = block_exclusive_scan(sum, tot) + M.tiles[a][t];
+  int64_t r[SCAN_ITEMS];
 #pragma unroll
   for (int j = 0; j < SCAN_ITEMS; j++) {
-    if (i0 + j <= n) M.out[a][i0 + j] = (Out)run;
+    r[j] = run;
     run += v[j];
   }
+  mscan_store(M.out[a], i0, n, r);
 }
 
-// count arrays (count <= MSCAN_MAX), nmax = the largest n.
+// Sets M.D for `count` arrays (count <= MSCAN_MAX) and launches.
 template <class In, class Out>
-void multi_scan(const MultiScan<In, Out>& M, int count, int64_t nmax, hipStream_t st) {
-  const dim3 grid((unsigned)(nmax / SCAN_TILE + 1), (unsigned)count);
-  hipLaunchKernelGGL((k_mscan_tiles<In, Out>), grid, dim3(SCAN_THREADS), 0, st, M);
-  hipLaunchKernelGGL((k_mscan_sums<In, Out>), dim3(1, count), dim3(SCAN_THREADS), 0, st, M);
-  hipLaunchKernelGGL((k_mscan_write<In, Out>), grid, dim3(SCAN_THREADS), 0, st, M);
+void multi_scan(MultiScan<In, Out>& M, int count, hipStream_t st) {
+  M.D = depth_blocks(M.n, count, SCAN_TILE);
+  const unsigned blocks = M.D.blocks();
+  hipLaunchKernelGGL((k_mscan_tiles<In, Out>), dim3(blocks), dim3(SCAN_THREADS), 0, st, M);
+  hipLaunchKernelGGL((k_mscan_sums<In, Out>), dim3(count), dim3(SCAN_THREADS), 0, st, M);
+  hipLaunchKernelGGL((k_mscan_write<In, Out>), dim3(blocks), dim3(SCAN_THREADS), 0, st, M);
 }
 
 }  // namespace vx
