@@ -232,14 +232,25 @@ def main():
     for _ in range(args.warmup):
         stats, _ = vx.run_subdivision(polys, dom, w.depth, ws=ws, want_kept=False)
     torch.cuda.synchronize()
+    # Every kernel timed over one untimed step (event records between all
+    # launches slow the level loop down); it picks the dominant kernel, whose
+    # launches alone are then timed with events inside the timed region.
+    prof_all, dom_name = {}, None
     if not args.no_profile:
         vx.profile_begin()
+        vx.run_subdivision(polys, dom, w.depth, ws=ws, want_kept=False)
+        prof_all = vx.profile_end()
+        evk = {n: r for n, r in prof_all.items() if n.startswith("k_") and r["ms"] > 0}
+        dom_name = max(evk, key=lambda n: evk[n]["ms"]) if evk else None
+    torch.cuda.synchronize()
+    if dom_name:
+        vx.profile_begin(only=dom_name)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         stats, _ = vx.run_subdivision(polys, dom, w.depth, ws=ws, want_kept=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = vx.profile_end() if not args.no_profile else {}
+    prof = vx.profile_end() if dom_name else {}
     ms_step = (t1 - t0) * 1e3 / args.steps
 
     evals = sum(len(polys) * s["n"][w.k - 1] for s in stats)
@@ -254,15 +265,13 @@ def main():
 
     roof = None
     kernels = {}
-    for name, r in prof.items():
+    for name, r in prof_all.items():
         if r["ms"] <= 0:
             continue
-        kernels[name] = {"launches": r["launches"], "avg_ms": r["ms"] / r["launches"], "total_ms": r["ms"] / args.steps,
+        kernels[name] = {"launches": r["launches"], "avg_ms": r["ms"] / r["launches"], "total_ms": r["ms"],
                          "units_per_launch": r["units"] / r["launches"]}
-    evk = {n: r for n, r in prof.items() if n.startswith("k_") and r["ms"] > 0}
-    if evk:
-        dom_name = max(evk, key=lambda n: evk[n]["ms"])
-        r = evk[dom_name]
+    if dom_name and prof.get(dom_name, {}).get("ms", 0) > 0:
+        r = prof[dom_name]
         avg_s = r["ms"] * 1e-3 / r["launches"]
         ops_per_launch = OPS_PER_STEP * r["units"] / r["launches"]
         achieved = ops_per_launch / avg_s / 1e12
@@ -292,6 +301,7 @@ def main():
                       if eval_ms > 0 else None,
                       "ms": eval_ms},
         "roofline": roof,
+        "kernels_note": "every kernel, HIP-event timed over one untimed step before the timed region",
         "kernels": kernels,
         "levels": levels,
     }

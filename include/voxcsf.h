@@ -345,6 +345,11 @@ typedef struct vx_kernel_stat {
 } vx_kernel_stat;
 int vx_profile_begin(void);
 int vx_profile_end(vx_kernel_stat* out, int32_t max, int32_t* count);
+/* Restrict later recording to the launches of one kernel name (NULL or ""
+ * records every kernel again), so that a timed run pays for two event
+ * records per launch of that kernel only.  VX_EINVAL for names of 32 or more
+ * characters. */
+int vx_profile_select(const char* name);
 
 #ifdef __cplusplus
 }

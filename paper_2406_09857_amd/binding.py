@@ -85,8 +85,9 @@ def lib():
         L.csf_build.argtypes = [C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(vx_csf), vp, C.c_size_t, vp]
         L.vx_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
         L.vx_profile_end.argtypes = [C.POINTER(vx_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
+        L.vx_profile_select.argtypes = [C.c_char_p]
         for f in ("interval_eval_level", "filter_subdivide", "run_subdivision", "run_subdivision_ex", "csf_build",
-                  "vx_copy", "vx_profile_begin", "vx_profile_end", "mean_value_exclusion"):
+                  "vx_copy", "vx_profile_begin", "vx_profile_end", "vx_profile_select", "mean_value_exclusion"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -363,9 +364,12 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
     return out, final.get("kept")
 
 
-def profile_begin():
-    """Start per-kernel HIP-event timing inside the library."""
-    _check(lib().vx_profile_begin())
+def profile_begin(only: str | None = None):
+    """Start per-kernel HIP-event timing inside the library (of the kernel
+    named `only`, or of every kernel)."""
+    L = lib()
+    _check(L.vx_profile_select(only.encode() if only else None))
+    _check(L.vx_profile_begin())
 
 
 def profile_end() -> dict:

@@ -313,7 +313,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   const size_t total = (ws_bytes - qbytes) / 256 * 256;
 
   hipEvent_t ev[3];
-  for (int i = 0; i < 3; i++) VX_HIP(hipEventCreate(&ev[i]));
+  for (int i = 0; i < 3; i++) VX_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableSystemFence));  // timing only
   struct EvGuard {
     hipEvent_t* e;
     ~EvGuard() {
@@ -552,16 +552,30 @@ struct ProfRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
+// Events are kept and reused across profiling sessions: creating two events
+// per timed launch would add host time between launches.
+std::vector<hipEvent_t> g_ev_pool;
+size_t g_ev_used = 0;
+char g_prof_only[32] = "";  // record only regions of this name ("" = all)
+
+hipEvent_t pool_event() {
+  if (g_ev_used == g_ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;  // timing only
+    g_ev_pool.push_back(e);
+  }
+  return g_ev_pool[g_ev_used++];
+}
 }  // namespace
 
 bool profiling() { return g_prof_on; }
 
 int prof_start(const char* name, double units, hipStream_t st) {
   if (!g_prof_on) return -1;
-  ProfRec r{name, units, nullptr, nullptr};
-  if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return -1;
-  if (hipEventRecord(r.a, st) != hipSuccess) return -1;
   std::lock_guard<std::mutex> g(g_prof_mu);
+  if (g_prof_only[0] && strncmp(g_prof_only, name, sizeof g_prof_only) != 0) return -1;
+  ProfRec r{name, units, pool_event(), pool_event()};
+  if (!r.a || !r.b || hipEventRecord(r.a, st) != hipSuccess) return -1;
   g_prof.push_back(r);
   return (int)g_prof.size() - 1;
 }
@@ -581,13 +595,21 @@ void prof_stop(int slot, hipStream_t st) {
 
 extern "C" {
 
+int vx_profile_select(const char* name) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  if (name && strlen(name) >= sizeof g_prof_only) VX_FAIL(VX_EINVAL, "profile: kernel name too long");
+  snprintf(g_prof_only, sizeof g_prof_only, "%s", name ? name : "");
+  return VX_OK;
+}
+
 int vx_profile_begin(void) {
   std::lock_guard<std::mutex> g(g_prof_mu);
-  for (auto& r : g_prof) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
+  for (auto& r : g_prof) {  // a session that was never ended: wait for its events before reuse
+    (void)hipEventSynchronize(r.a);
+    (void)hipEventSynchronize(r.b);
   }
   g_prof.clear();
+  g_ev_used = 0;
   g_prof_on = true;
   return VX_OK;
 }
@@ -614,10 +636,9 @@ int vx_profile_end(vx_kernel_stat* out, int32_t max, int32_t* count) {
     acc[j].launches++;
     acc[j].ms += ms;
     acc[j].units += r.units;
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
   }
   g_prof.clear();
+  g_ev_used = 0;
   if (count) *count = (int32_t)acc.size();
   for (size_t j = 0; j < acc.size() && (int32_t)j < max; j++) out[j] = acc[j];
   return rc;

@@ -373,20 +373,30 @@ __device__ __forceinline__ void stage1_body(const PolyTab& pt, int m, const int3
 }
 
 template <int R>
+// One workgroup per (polynomial z, tuple wave y, segment x) item, x fastest.
+// Items are dealt to the XCDs in chunks of whole tuple waves (all segments of
+// one (z, y)), so an XCD streams only its share of the coefficient tensor,
+// which stays in its L2 while every segment reads it.
 __global__ __launch_bounds__(64) void k_stage1(PolySet ps, int m, const int32_t* __restrict__ labels0,
                                                const int4* __restrict__ seg, const int64_t* __restrict__ nseg,
-                                               AxisGrid g, RowSet out, int out_width) {
+                                               AxisGrid g, RowSet out, int out_width, int64_t maxseg, int ny,
+                                               int64_t chunk, int64_t items) {
   round_up_mode();
-  if ((int64_t)blockIdx.x >= *nseg) return;
-  const PolyTab& pt = ps.p[blockIdx.z];
+  const int64_t item = xcd_item(blockIdx.x % NXCD, blockIdx.x / NXCD, chunk);
+  if (item >= items) return;
+  const int64_t sx = item % maxseg;
+  const int wy = (int)((item / maxseg) % ny);
+  const int pz = (int)(item / (maxseg * ny));
+  if (sx >= *nseg) return;
+  const PolyTab& pt = ps.p[pz];
   const int nt = pt.nt, d = pt.d;
   const int ntw = (nt + 63) / 64;
-  if ((int)blockIdx.y > ntw) return;
-  if ((int)blockIdx.y == ntw) {  // zero the padding slots of this segment's rows
+  if (wy > ntw) return;
+  if (wy == ntw) {  // zero the padding slots of this segment's rows
     if (pt.npad == 0) return;
-    const int4 sg = seg[blockIdx.x];
-    double* base = out.rows[blockIdx.z];
-    const int64_t stride = out.stride[blockIdx.z];
+    const int4 sg = seg[sx];
+    double* base = out.rows[pz];
+    const int64_t stride = out.stride[pz];
     for (int j = 0; j < sg.z; j++)
       for (int i = threadIdx.x; i < pt.npad; i += 64) {
         double* o = base + (int64_t)(sg.y + j) * stride + (int64_t)pt.padlist[i] * out_width;
@@ -395,10 +405,10 @@ __global__ __launch_bounds__(64) void k_stage1(PolySet ps, int m, const int32_t*
       }
     return;
   }
-  const int4 sg = seg[blockIdx.x];
+  const int4 sg = seg[sx];
   const int begin = sg.y, cnt = sg.z, cls = sg.w;
   const int lane = threadIdx.x;
-  const int64_t gidx = (int64_t)blockIdx.y * 64 + lane;
+  const int64_t gidx = (int64_t)wy * 64 + lane;
   const bool active = gidx < nt;
   int gdeg = d + 1, opos = 0;
   if (active) {
@@ -407,8 +417,8 @@ __global__ __launch_bounds__(64) void k_stage1(PolySet ps, int m, const int32_t*
     opos = tt.y;
   }
   const int r0 = __builtin_amdgcn_readfirstlane(gdeg);  // lane 0 holds the wave's smallest |t|
-  double* base = out.rows[blockIdx.z];
-  const int64_t stride = out.stride[blockIdx.z];
+  double* base = out.rows[pz];
+  const int64_t stride = out.stride[pz];
   if (cls == CLS_POS)
     stage1_body<R, CLS_POS>(pt, m, labels0, begin, cnt, g, gidx, active, gdeg, opos, r0, base, stride, out_width);
   else if (cls == CLS_NEG)
@@ -590,6 +600,20 @@ __device__ __forceinline__ void narrow_padded(const crow_t* __restrict__ C, int 
   }
 }
 
+// Padded rows (k = 3): split g of n splits the chains 0..d into runs of about
+// equal group counts; its first chain is the first j with padded_groups(j) >=
+// padded_groups(d + 1) * g / n (split n ends at d + 1).  Wave-uniform.
+__device__ __forceinline__ int padded_split(int d, int g, int n) {
+  if (g >= n) return d + 1;
+  const int64_t target = (padded_groups(d + 1) * g + n - 1) / n;
+  int lo = 0, hi = d + 1;  // padded_groups(hi) >= target
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (padded_groups(mid) >= target) hi = mid; else lo = mid + 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
 struct SplitSet {
   ChainSplit s[PMAX];
 };
@@ -612,7 +636,7 @@ __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet s
   const int pz = (int)(item / ((int64_t)gdim * maxseg));
   if (sidx >= *nseg) return;
   const ChainSplit& split = splits.s[pz];
-  if (gi >= split.n) return;
+  if (!PADDED && gi >= split.n) return;
   const int4 sg = seg[sidx];
   const int parent = sg.x, begin = sg.y, cnt = sg.z, cls = sg.w;
   const int lane = threadIdx.x;
@@ -625,14 +649,16 @@ __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet s
   double* w = out.rows[pz] + node * out.stride[pz];
   const int64_t es = out.estride[pz];
   const int32_t* lens = ps.p[pz].lens2;
-  const int j0 = __builtin_amdgcn_readfirstlane(split.j0[gi]);
-  const int j1 = __builtin_amdgcn_readfirstlane(split.j0[gi + 1]);
   if (PADDED) {
+    const int d = ps.p[pz].d;
+    const int j0 = padded_split(d, gi, gdim), j1 = padded_split(d, gi + 1, gdim);
     if (cls == CLS_POS) narrow_padded<CLS_POS>(C, j0, j1, o, valid, w, es, out_width);
     else if (cls == CLS_NEG) narrow_padded<CLS_NEG>(C, j0, j1, o, valid, w, es, out_width);
     else narrow_padded<CLS_STRADDLE>(C, j0, j1, o, valid, w, es, out_width);
     return;
   }
+  const int j0 = __builtin_amdgcn_readfirstlane(split.j0[gi]);
+  const int j1 = __builtin_amdgcn_readfirstlane(split.j0[gi + 1]);
   const int64_t p0 = split.p0[gi];
   if (cls == CLS_POS) narrow_run<CLS_POS, ORDER1>(C, lens, j0, j1, p0, o, valid, w, es, out_width);
   else if (cls == CLS_NEG) narrow_run<CLS_NEG, ORDER1>(C, lens, j0, j1, p0, o, valid, w, es, out_width);
@@ -663,14 +689,18 @@ __device__ __forceinline__ void leaf_chain_gen(const double* __restrict__ R, int
 // Up to LR boxes of one column and one sign class (POS or NEG) share every
 // coefficient load.  Entry j (exponent d - j) is read at R + es * j, one double
 // later when the boxes are mirrored (NEG) and d - j is odd; pe serves even j,
-// po odd j.  Four entries are in flight, so entries up to max(4, d + 4) are
-// read (the buffers are sized for it); those past d are never used.
-template <int LR>
+// po odd j.  PF entries are in flight, so entries up to max(PF, d + PF) are
+// read (the buffers are sized for LEAF_PF_MAX); those past d are never used.
+constexpr int LEAF_PF_MAX = 8;
+
+template <int LR, int PF>
 __device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int64_t es, int d, int sh,
                                             const double (&u)[LR], const double (&v)[LR], double (&nl)[LR],
                                             double (&hh)[LR]) {
+  static_assert(PF % 2 == 0 && PF <= LEAF_PF_MAX, "even prefetch depth within the row slack");
   const double* pe = R + ((d & 1) ? sh : 0);
   const double* po = R + es + (((d - 1) & 1) ? sh : 0);
+  // entry j; every call site has j = 1 + (even) + i with i known, so the parity is static
   auto at = [&](int j) -> dpair_a8 {
     return (j & 1) ? *reinterpret_cast<const dpair_a8*>(po + es * (j - 1))
                    : *reinterpret_cast<const dpair_a8*>(pe + es * j);
@@ -681,37 +711,46 @@ __device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int64_
     nl[i] = c.x;
     hh[i] = c.y;
   }
-  dpair_a8 q0 = at(1), q1 = at(2), q2 = at(3), q3 = at(4);
-  auto steps = [&](const dpair_a8& q) {
+  dpair_a8 q[PF];
 #pragma unroll
-    for (int i = 0; i < LR; i++) step_pos(nl[i], hh[i], u[i], v[i], q.x, q.y);
+  for (int i = 0; i < PF; i++) q[i] = at(1 + i);
+  auto steps = [&](const dpair_a8& x) {
+#pragma unroll
+    for (int i = 0; i < LR; i++) step_pos(nl[i], hh[i], u[i], v[i], x.x, x.y);
   };
   int j = 1;
-  for (; j + 3 <= d; j += 4) {
-    steps(q0);
-    q0 = *reinterpret_cast<const dpair_a8*>(po + es * (j + 3));  // entry j+4 (odd)
-    steps(q1);
-    q1 = *reinterpret_cast<const dpair_a8*>(pe + es * (j + 5));  // entry j+5 (even)
-    steps(q2);
-    q2 = *reinterpret_cast<const dpair_a8*>(po + es * (j + 5));  // entry j+6 (odd)
-    steps(q3);
-    q3 = *reinterpret_cast<const dpair_a8*>(pe + es * (j + 7));  // entry j+7 (even)
+  for (; j + PF - 1 <= d; j += PF) {
+#pragma unroll
+    for (int i = 0; i < PF; i++) {
+      steps(q[i]);
+      // entry j + PF + i: odd when i is even (j is odd)
+      q[i] = (i & 1) ? *reinterpret_cast<const dpair_a8*>(pe + es * (j + PF + i))
+                     : *reinterpret_cast<const dpair_a8*>(po + es * (j + PF + i - 1));
+    }
   }
-  if (j <= d) steps(q0);
-  if (j + 1 <= d) steps(q1);
-  if (j + 2 <= d) steps(q2);
+#pragma unroll
+  for (int i = 0; i < PF - 1; i++)
+    if (j + i <= d) steps(q[i]);
 }
 
 // One lane per leaf segment (<= LEAF_R boxes of one parent and one class).
+// SPLITP: the polynomials of a segment run on P2 adjacent lanes (P2 = the
+// power of two >= np), one each, and the lanes OR their exclusion flags with
+// cross-lane shuffles; small levels use it to halve (or better) the serial
+// chain of each lane.
 constexpr int LEAF_R = 4;
 
+template <bool SPLITP, int PF>
 __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int4* __restrict__ seg,
                                               const int64_t* __restrict__ nseg, const int32_t* __restrict__ labels,
                                               int64_t nleaf, AxisGrid g, double* __restrict__ lo_out,
-                                              double* __restrict__ hi_out, uint8_t* __restrict__ keep, int first) {
+                                              double* __restrict__ hi_out, uint8_t* __restrict__ keep, int first,
+                                              int p2) {
   round_up_mode();
-  const int64_t sid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (sid >= *nseg) return;
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t sid = SPLITP ? q / p2 : q;
+  const int pl = SPLITP ? (int)(q % p2) : 0;
+  if (sid >= *nseg) return;  // all p2 lanes of a segment leave together
   const int4 sg = seg[sid];
   const int64_t par = sg.x, begin = sg.y;
   const int cnt = sg.z, cls = sg.w;
@@ -724,8 +763,9 @@ __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int
     u[i] = o.u;
     v[i] = o.v;
   }
-  bool excl[LEAF_R] = {};
-  for (int p = 0; p < ps.np; p++) {
+  int excl = 0;  // bit i: box i excluded by some polynomial
+  const int pbeg = SPLITP ? pl : 0, pend = SPLITP ? (pl < ps.np ? pl + 1 : pl) : ps.np;
+  for (int p = pbeg; p < pend; p++) {
     const double* R = rows.rows[p] + par * rows.stride[p];
     const int64_t es = rows.estride[p];
     const int d = ps.p[p].d;
@@ -742,7 +782,7 @@ __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int
         }
       }
     } else {
-      leaf_chains<LEAF_R>(R, es, d, cls == CLS_NEG ? 1 : 0, u, v, nl, hh);
+      leaf_chains<LEAF_R, PF>(R, es, d, cls == CLS_NEG ? 1 : 0, u, v, nl, hh);
     }
 #pragma unroll
     for (int i = 0; i < LEAF_R; i++) {
@@ -750,16 +790,25 @@ __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int
         const double lo = -opaque(nl[i]);
         lo_out[p * nleaf + begin + i] = lo;
         hi_out[p * nleaf + begin + i] = hh[i];
-        excl[i] = excl[i] || (lo > 0.0) || (hh[i] < 0.0);
+        if ((lo > 0.0) || (hh[i] < 0.0)) excl |= 1 << i;
       }
     }
   }
+  if (SPLITP) {
+    for (int off = 1; off < p2; off <<= 1) excl |= __shfl_xor(excl, off);
+    if (pl != 0) return;
+  }
   if (keep) {
 #pragma unroll
-    for (int i = 0; i < LEAF_R; i++)
-      if (i < cnt) keep[begin + i] = first ? (excl[i] ? 0 : 1) : (excl[i] ? 0 : keep[begin + i]);
+    for (int i = 0; i < LEAF_R; i++) {
+      const bool ex = (excl >> i) & 1;
+      if (i < cnt) keep[begin + i] = first ? (ex ? 0 : 1) : (ex ? 0 : keep[begin + i]);
+    }
   }
 }
+
+// Largest leaf count for the one-polynomial-per-lane leaf launch.
+constexpr int64_t LEAF_SPLIT_NODES = 1536 * 1024;
 
 // Parent (depth k-1 node) of every leaf: binary search in ptr.
 __global__ void k_parent_of(const int32_t* __restrict__ ptr, int64_t nparent, int64_t nleaf,
@@ -1038,9 +1087,9 @@ static void plan_eval(Arena& A, EvalPlan& E, const vx_poly* P, int np, const vx_
     const int m = k - l - 1;  // dimension of the trailing tuples left after depth l+1
     const int width = (l == k - 2) ? 3 : 2;
     for (int p = 0; p < np; p++) {
-      // leaf input written by a middle stage: entry-major, d + 5 entry planes
-      // (the leaf reads up to entry d + 4)
-      const int64_t row = (k >= 3 && l == k - 2) ? P[p].degree + 5
+      // leaf input written by a middle stage: entry-major, d + 1 + LEAF_PF_MAX
+      // entry planes (the leaf reads up to entry d + LEAF_PF_MAX)
+      const int64_t row = (k >= 3 && l == k - 2) ? P[p].degree + 1 + LEAF_PF_MAX
                           : (k == 3 && l == 0)   ? padded_entries(P[p].degree)
                                                  : ntup(m, P[p].degree);
       E.rows[l][p] = A.take<double>((size_t)S->n[l] * row * width + 4 * ROW_PAD * width) + 2 * ROW_PAD * width;
@@ -1095,14 +1144,19 @@ static int launch_stage1(const Prepared& Q, int p0, int pn, const vx_csf* S, con
     units += (double)(ntup(k, d) - ntup(m, d)) * (double)S->n[0];
   }
   const SegPlan& sp = E.seg[0];
-  dim3 grid((unsigned)sp.maxseg, (unsigned)((nt_max + 63) / 64 + 1), (unsigned)pn);
+  const int ny = (nt_max + 63) / 64 + 1;
+  const int64_t maxseg = sp.maxseg > 0 ? sp.maxseg : 1;
+  const int64_t items = maxseg * ny * pn, chunk = maxseg;
+  const dim3 grid((unsigned)xcd_grid(items, chunk));
   const AxisGrid g = make_grid(dom, 0, S->level, E.centre);
+  const int4* sg = (const int4*)sp.seg;
+  const int64_t* ns = (const int64_t*)sp.nseg;
   const int pr = prof_start("k_stage1", units, st);
   switch (E.R) {
-    case 1: hipLaunchKernelGGL(k_stage1<1>, grid, dim3(64), 0, st, ps, m, S->idx[0], (const int4*)sp.seg, (const int64_t*)sp.nseg, g, rs, width); break;
-    case 2: hipLaunchKernelGGL(k_stage1<2>, grid, dim3(64), 0, st, ps, m, S->idx[0], (const int4*)sp.seg, (const int64_t*)sp.nseg, g, rs, width); break;
-    case 4: hipLaunchKernelGGL(k_stage1<4>, grid, dim3(64), 0, st, ps, m, S->idx[0], (const int4*)sp.seg, (const int64_t*)sp.nseg, g, rs, width); break;
-    default: hipLaunchKernelGGL(k_stage1<8>, grid, dim3(64), 0, st, ps, m, S->idx[0], (const int4*)sp.seg, (const int64_t*)sp.nseg, g, rs, width); break;
+    case 1: hipLaunchKernelGGL(k_stage1<1>, grid, dim3(64), 0, st, ps, m, S->idx[0], sg, ns, g, rs, width, maxseg, ny, chunk, items); break;
+    case 2: hipLaunchKernelGGL(k_stage1<2>, grid, dim3(64), 0, st, ps, m, S->idx[0], sg, ns, g, rs, width, maxseg, ny, chunk, items); break;
+    case 4: hipLaunchKernelGGL(k_stage1<4>, grid, dim3(64), 0, st, ps, m, S->idx[0], sg, ns, g, rs, width, maxseg, ny, chunk, items); break;
+    default: hipLaunchKernelGGL(k_stage1<8>, grid, dim3(64), 0, st, ps, m, S->idx[0], sg, ns, g, rs, width, maxseg, ny, chunk, items); break;
   }
   VX_CHECK_LAUNCH("k_stage1");
   prof_stop(pr, st);
@@ -1123,7 +1177,10 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
   memset(&ss, 0, sizeof ss);
   const int64_t est_waves = (S->n[l] + 63) / 64 + S->n[l - 1];
   int groups = (int)((NARROW_TARGET_WAVES + est_waves - 1) / est_waves);
-  groups = groups < 1 ? 1 : (groups > SPLIT_MAX ? SPLIT_MAX : groups);
+  // padded rows (k = 3) split in the kernel, down to one chain per split;
+  // the other layouts take a table of at most SPLIT_MAX splits
+  const int gcap = k == 3 ? Q.dmax + 1 : SPLIT_MAX;
+  groups = groups < 1 ? 1 : (groups > gcap ? gcap : groups);
   int gmax = 1;
   double units = 0;
   ps.np = pn;
@@ -1137,8 +1194,12 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
     const bool to_leaf = l == k - 2;
     out.stride[i] = to_leaf ? 3 : ntup(m_out, d) * width;
     out.estride[i] = to_leaf ? 3 * S->n[l] : width;
-    ss.s[i] = chain_split(m_out, d, groups);
-    gmax = ss.s[i].n > gmax ? ss.s[i].n : gmax;
+    if (k == 3) {
+      gmax = groups;
+    } else {
+      ss.s[i] = chain_split(m_out, d, groups);
+      gmax = ss.s[i].n > gmax ? ss.s[i].n : gmax;
+    }
     units += (double)(ntup(m_in, d) - ntup(m_out, d)) * (double)S->n[l];
   }
   const SegPlan& sp = E.seg[l];
@@ -1179,11 +1240,26 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
     units += (double)d * (double)nleaf;
   }
   const SegPlan& sp = E.seg[k - 1];
+  const AxisGrid g = make_grid(dom, k - 1, S->level, E.centre);
+  double* lo_p = lo + (int64_t)p0 * nleaf;
+  double* hi_p = hi + (int64_t)p0 * nleaf;
+  const int4* sg = (const int4*)sp.seg;
+  const int64_t* ns = (const int64_t*)sp.nseg;
+  const int first = p0 == 0 ? 1 : 0;
   const int pr = prof_start("k_leaf", units, st);
-  hipLaunchKernelGGL(k_leaf, dim3((unsigned)((sp.maxseg + 255) / 256)), dim3(256), 0, st, ps, rs,
-                     (const int4*)sp.seg, (const int64_t*)sp.nseg, S->idx[k - 1], nleaf,
-                     make_grid(dom, k - 1, S->level, E.centre), lo + (int64_t)p0 * nleaf, hi + (int64_t)p0 * nleaf, keep,
-                     p0 == 0 ? 1 : 0);
+  if (nleaf <= LEAF_SPLIT_NODES && pn > 1) {
+    int p2 = 1;
+    while (p2 < pn) p2 <<= 1;
+    const int64_t threads = sp.maxseg * p2;
+    hipLaunchKernelGGL((k_leaf<true, 8>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, ps, rs, sg, ns,
+                       S->idx[k - 1], nleaf, g, lo_p, hi_p, keep, first, p2);
+  } else if (nleaf <= LEAF_SPLIT_NODES) {
+    hipLaunchKernelGGL((k_leaf<false, 8>), dim3((unsigned)((sp.maxseg + 255) / 256)), dim3(256), 0, st, ps, rs, sg,
+                       ns, S->idx[k - 1], nleaf, g, lo_p, hi_p, keep, first, 1);
+  } else {
+    hipLaunchKernelGGL((k_leaf<false, 4>), dim3((unsigned)((sp.maxseg + 255) / 256)), dim3(256), 0, st, ps, rs, sg,
+                       ns, S->idx[k - 1], nleaf, g, lo_p, hi_p, keep, first, 1);
+  }
   VX_CHECK_LAUNCH("k_leaf");
   prof_stop(pr, st);
   return VX_OK;

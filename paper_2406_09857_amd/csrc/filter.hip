@@ -237,7 +237,7 @@ __global__ void k_next_gen(int k, DepthBlocks D, GenJob J) {
 // Small levels: the whole filter in one workgroup (survival scans, compaction,
 // counts, next CSF), the same outputs as the multi-launch path below.
 // ---------------------------------------------------------------------------
-constexpr int64_t SMALL_FILTER_NODES = 4096;
+constexpr int64_t SMALL_FILTER_NODES = 1024;
 
 struct SmallFilterJob {
   const int32_t* idx[VX_KMAX];
