@@ -901,23 +901,40 @@ struct SegJob {
   int64_t* nseg[VX_KMAX];
 };
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_segments_small(int k, SegJob J) {
+constexpr int SMALL_THREADS = 1024;
+
+// Item i of the (depth, parent) items of every depth, depth-major.
+__device__ __forceinline__ int seg_item(const SegJob& J, int k, int64_t i, int64_t& p) {
+  int l = 0;
+  while (l + 1 < k && i >= J.nparent[l]) i -= J.nparent[l++];
+  p = i;
+  return l;
+}
+
+// Three phases over all depths at once: class bounds and segment counts of
+// every (depth, parent) item, the per-depth scans, the segment records.
+__global__ __launch_bounds__(SMALL_THREADS) void k_segments_small(int k, SegJob J) {
   round_up_mode();
-  for (int l = 0; l < k; l++) {
-    const int64_t np = J.nparent[l];
+  int64_t items = 0;
+  for (int l = 0; l < k; l++) items += J.nparent[l];
+  for (int64_t i = threadIdx.x; i < items; i += SMALL_THREADS) {
+    int64_t p;
+    const int l = seg_item(J, k, i, p);
     const int32_t* ptr = J.ptr[l];
     const int Z = J.Z[l];
-    for (int64_t p = threadIdx.x; p < np; p += SCAN_THREADS) {
-      const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : J.nchild[l];
-      int64_t ne, pb;
-      class_bounds(J.labels[l], b, e, J.g[l], ne, pb);
-      J.bounds[l][2 * p] = ne;
-      J.bounds[l][2 * p + 1] = pb;
-      J.cnt[l][p] = cdiv(ne - b, Z) + cdiv(pb - ne, Z) + cdiv(e - pb, Z);
-    }
-    __syncthreads();
+    const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : J.nchild[l];
+    int64_t ne, pb;
+    class_bounds(J.labels[l], b, e, J.g[l], ne, pb);
+    J.bounds[l][2 * p] = ne;
+    J.bounds[l][2 * p + 1] = pb;
+    J.cnt[l][p] = cdiv(ne - b, Z) + cdiv(pb - ne, Z) + cdiv(e - pb, Z);
+  }
+  __syncthreads();
+  constexpr int64_t TILE = (int64_t)SMALL_THREADS * SCAN_ITEMS;
+  for (int l = 0; l < k; l++) {
+    const int64_t np = J.nparent[l];
     int64_t carry = 0;
-    for (int64_t base = 0; base < np; base += SCAN_TILE) {
+    for (int64_t base = 0; base < np; base += TILE) {
       const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
       int64_t v[SCAN_ITEMS];
       int64_t sum = 0;
@@ -927,7 +944,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_segments_small(int k, SegJob J
         sum += v[j];
       }
       int64_t tot;
-      int64_t run = carry + block_exclusive_scan(sum, tot);
+      int64_t run = carry + block_exclusive_scan<SMALL_THREADS>(sum, tot);
 #pragma unroll
       for (int j = 0; j < SCAN_ITEMS; j++) {
         if (i0 + j < np) J.off[l][i0 + j] = run;
@@ -936,19 +953,22 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_segments_small(int k, SegJob J
       carry += tot;
     }
     if (threadIdx.x == 0) *J.nseg[l] = carry;
-    __syncthreads();
-    const int cls[3] = {CLS_NEG, CLS_STRADDLE, CLS_POS};
-    for (int64_t p = threadIdx.x; p < np; p += SCAN_THREADS) {
-      const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : J.nchild[l];
-      const int64_t cuts[4] = {b, J.bounds[l][2 * p], J.bounds[l][2 * p + 1], e};
-      int64_t o = J.off[l][p];
-      for (int c = 0; c < 3; c++)
-        for (int64_t q = cuts[c]; q < cuts[c + 1]; q += Z) {
-          const int64_t cnt = cuts[c + 1] - q < Z ? cuts[c + 1] - q : Z;
-          J.seg[l][o++] = make_int4((int)p, (int)q, (int)cnt, cls[c]);
-        }
-    }
-    __syncthreads();
+  }
+  __syncthreads();
+  const int cls[3] = {CLS_NEG, CLS_STRADDLE, CLS_POS};
+  for (int64_t i = threadIdx.x; i < items; i += SMALL_THREADS) {
+    int64_t p;
+    const int l = seg_item(J, k, i, p);
+    const int32_t* ptr = J.ptr[l];
+    const int Z = J.Z[l];
+    const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : J.nchild[l];
+    const int64_t cuts[4] = {b, J.bounds[l][2 * p], J.bounds[l][2 * p + 1], e};
+    int64_t o = J.off[l][p];
+    for (int c = 0; c < 3; c++)
+      for (int64_t q = cuts[c]; q < cuts[c + 1]; q += Z) {
+        const int64_t cnt = cuts[c + 1] - q < Z ? cuts[c + 1] - q : Z;
+        J.seg[l][o++] = make_int4((int)p, (int)q, (int)cnt, cls[c]);
+      }
   }
 }
 
@@ -1299,7 +1319,7 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
     J.nseg[l] = sp.nseg;
   }
   if (nmax <= SMALL_LEVEL_NODES) {
-    hipLaunchKernelGGL(k_segments_small, dim3(1), dim3(SCAN_THREADS), 0, st, k, J);
+    hipLaunchKernelGGL(k_segments_small, dim3(1), dim3(SMALL_THREADS), 0, st, k, J);
     VX_CHECK_LAUNCH("k_segments_small");
   } else {
     const DepthBlocks D = depth_blocks(J.nparent, k, 256);

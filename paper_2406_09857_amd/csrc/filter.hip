@@ -49,15 +49,6 @@ struct AnyChildLoader {
   __device__ int64_t operator()(int64_t i) const { return child_pos[ptr[i + 1]] > child_pos[ptr[i]]; }
 };
 
-struct ChildCountLoader {
-  const int32_t* src;
-  const int32_t* kptr;
-  __device__ int64_t operator()(int64_t i) const {
-    const int32_t y = src[i];
-    return 2 * (int64_t)(kptr[y + 1] - kptr[y]);
-  }
-};
-
 static_assert(MSCAN_MAX >= VX_KMAX, "one scan array per depth");
 
 // Survival flag of every depth-l node (l < k-1): some child survives.  One
@@ -234,10 +225,13 @@ __global__ void k_next_gen(int k, DepthBlocks D, GenJob J) {
 }
 
 // ---------------------------------------------------------------------------
-// Small levels: the whole filter in one workgroup (survival scans, compaction,
-// counts, next CSF), the same outputs as the multi-launch path below.
+// Small levels: the whole filter in one workgroup of SMALL_FILTER_THREADS
+// (survival scans leaves up, compaction of every depth in one pass with the
+// kept nodes' parents, the next CSF of every depth in one pass in closed
+// form), the same outputs as the multi-launch path.
 // ---------------------------------------------------------------------------
 constexpr int64_t SMALL_FILTER_NODES = 1024;
+constexpr int SMALL_FILTER_THREADS = 1024;
 
 struct SmallFilterJob {
   const int32_t* idx[VX_KMAX];
@@ -246,9 +240,9 @@ struct SmallFilterJob {
   int32_t* newpos[VX_KMAX];
   int32_t* kidx[VX_KMAX];
   int32_t* kptr[VX_KMAX];
+  int32_t* kpar[VX_KMAX];
   int32_t* nidx[VX_KMAX];
   int32_t* nptr[VX_KMAX];
-  int32_t* src[VX_KMAX];
   int64_t* kcnt;
   int64_t* ncnt;
   int64_t* d_counts;
@@ -257,8 +251,9 @@ struct SmallFilterJob {
 // out[0..n] = exclusive prefix sums of ld(0..n-1); returns the total (all threads).
 template <class Loader>
 __device__ int64_t block_scan_to(Loader ld, int64_t n, int32_t* out) {
+  constexpr int64_t TILE = (int64_t)SMALL_FILTER_THREADS * SCAN_ITEMS;
   int64_t carry = 0;
-  for (int64_t base = 0; base < n; base += SCAN_TILE) {
+  for (int64_t base = 0; base < n; base += TILE) {
     const int64_t i0 = base + (int64_t)threadIdx.x * SCAN_ITEMS;
     int64_t v[SCAN_ITEMS];
     int64_t sum = 0;
@@ -268,7 +263,7 @@ __device__ int64_t block_scan_to(Loader ld, int64_t n, int32_t* out) {
       sum += v[j];
     }
     int64_t tot;
-    int64_t run = carry + block_exclusive_scan(sum, tot);
+    int64_t run = carry + block_exclusive_scan<SMALL_FILTER_THREADS>(sum, tot);
 #pragma unroll
     for (int j = 0; j < SCAN_ITEMS; j++) {
       if (i0 + j < n) out[i0 + j] = (int32_t)run;
@@ -281,54 +276,64 @@ __device__ int64_t block_scan_to(Loader ld, int64_t n, int32_t* out) {
   return carry;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_filter_small(int k, const uint8_t* __restrict__ keep,
-                                                               SmallFilterJob J, int want_next) {
+__global__ __launch_bounds__(SMALL_FILTER_THREADS) void k_filter_small(int k, const uint8_t* __restrict__ keep,
+                                                                       SmallFilterJob J, int want_next) {
   int64_t kc[VX_KMAX] = {0, 0, 0, 0};
   kc[k - 1] = block_scan_to(KeepLoader{keep}, J.n[k - 1], J.newpos[k - 1]);
   for (int l = k - 2; l >= 0; l--)
     kc[l] = block_scan_to(AnyChildLoader{J.ptr[l], J.newpos[l + 1]}, J.n[l], J.newpos[l]);
-  for (int l = 0; l < k; l++) {
-    const bool inner = l + 1 < k;
-    for (int64_t i = threadIdx.x; i < J.n[l]; i += SCAN_THREADS)
-      if (J.newpos[l][i + 1] > J.newpos[l][i]) {
-        const int32_t o = J.newpos[l][i];
-        J.kidx[l][o] = J.idx[l][i];
-        if (inner) J.kptr[l][o] = J.newpos[l + 1][J.ptr[l][i]];
-      }
-    if (inner && threadIdx.x == 0) J.kptr[l][kc[l]] = (int32_t)kc[l + 1];
+  int64_t items = 0;
+  for (int l = 0; l < k; l++) items += J.n[l];
+  for (int64_t i = threadIdx.x; i < items; i += SMALL_FILTER_THREADS) {
+    int64_t p = i;
+    int l = 0;
+    while (l + 1 < k && p >= J.n[l]) p -= J.n[l++];
+    const int32_t q = J.newpos[l][p];
+    if (J.newpos[l][p + 1] == q) continue;
+    J.kidx[l][q] = J.idx[l][p];
+    if (l + 1 < k) {
+      const int32_t c0 = J.newpos[l + 1][J.ptr[l][p]], c1 = J.newpos[l + 1][J.ptr[l][p + 1]];
+      J.kptr[l][q] = c0;
+      if (want_next)
+        for (int32_t c = c0; c < c1; c++) J.kpar[l + 1][c] = q;
+    }
   }
-  int64_t nc[VX_KMAX] = {0, 0, 0, 0};
-  for (int l = 0; l < k; l++) nc[l] = kc[l] << (l + 1);
   if (threadIdx.x == 0)
     for (int l = 0; l < k; l++) {
+      if (l + 1 < k) J.kptr[l][kc[l]] = (int32_t)kc[l + 1];
       J.kcnt[l] = kc[l];
-      J.ncnt[l] = nc[l];
+      J.ncnt[l] = kc[l] << (l + 1);
       if (J.d_counts) {
         J.d_counts[l] = kc[l];
-        J.d_counts[k + l] = nc[l];
+        J.d_counts[k + l] = kc[l] << (l + 1);
       }
+      if (want_next && l + 1 < k) J.nptr[l][kc[l] << (l + 1)] = (int32_t)(kc[l + 1] << (l + 2));
     }
   if (!want_next) return;
   __syncthreads();
-  for (int64_t o = threadIdx.x; o < nc[0]; o += SCAN_THREADS) {
-    J.nidx[0][o] = 2 * J.kidx[0][o >> 1] + (int32_t)(o & 1);
-    if (k > 1) J.src[0][o] = (int32_t)(o >> 1);
+  GenJob G;
+  for (int l = 0; l < VX_KMAX; l++) {
+    G.kidx[l] = J.kidx[l];
+    G.kptr[l] = J.kptr[l];
+    G.kpar[l] = J.kpar[l];
+    G.nidx[l] = J.nidx[l];
+    G.nptr[l] = J.nptr[l];
   }
-  __syncthreads();
-  for (int l = 1; l < k; l++) {
-    block_scan_to(ChildCountLoader{J.src[l - 1], J.kptr[l - 1]}, nc[l - 1], J.nptr[l - 1]);
-    // one thread per new parent writes its children (2 per kept child)
-    for (int64_t P = threadIdx.x; P < nc[l - 1]; P += SCAN_THREADS) {
-      const int32_t y = J.src[l - 1][P];
-      const int32_t c0 = J.kptr[l - 1][y], c1 = J.kptr[l - 1][y + 1];
-      int64_t o = J.nptr[l - 1][P];
-      for (int32_t c = c0; c < c1; c++)
-        for (int b = 0; b < 2; b++, o++) {
-          J.nidx[l][o] = 2 * J.kidx[l][c] + b;
-          if (l + 1 < k) J.src[l][o] = c;
-        }
+  G.kcnt = J.kcnt;
+  G.ncnt = J.ncnt;
+  int64_t kitems = 0;
+  for (int l = 0; l < k; l++) kitems += kc[l];
+  for (int64_t i = threadIdx.x; i < kitems; i += SMALL_FILTER_THREADS) {
+    int64_t z = i;
+    int l = 0;
+    while (l + 1 < k && z >= kc[l]) z -= kc[l++];
+    const bool inner = l + 1 < k;
+    switch (l) {
+      case 0: next_copies<0>(G, z, inner); break;
+      case 1: next_copies<1>(G, z, inner); break;
+      case 2: next_copies<2>(G, z, inner); break;
+      default: next_copies<3>(G, z, inner); break;
     }
-    __syncthreads();
   }
 }
 
@@ -341,17 +346,14 @@ struct FilterPlan {
   int32_t* kidx[VX_KMAX] = {};
   int32_t* kptr[VX_KMAX] = {};
   int32_t* kpar[VX_KMAX] = {};
-  int32_t* src[VX_KMAX] = {};
 };
 
 static void plan_filter(Arena& A, FilterPlan& F, const vx_csf* S, bool own_kept, bool want_next) {
   const int k = S->k;
-  int64_t nmax = 1;
   for (int l = 0; l < k; l++) {
     F.newpos[l] = A.take<int32_t>(S->n[l] + 1);
     F.tiles[l] = A.take<int64_t>(scan_tiles(S->n[l]));
     if (l + 1 < k) F.alive[l] = A.take<uint8_t>(S->n[l] > 0 ? S->n[l] : 1);
-    nmax = nmax > S->n[l] ? nmax : S->n[l];
   }
   F.kcnt = A.take<int64_t>(VX_KMAX);
   F.ncnt = A.take<int64_t>(VX_KMAX);
@@ -360,12 +362,8 @@ static void plan_filter(Arena& A, FilterPlan& F, const vx_csf* S, bool own_kept,
       F.kidx[l] = A.take<int32_t>(S->n[l] > 0 ? S->n[l] : 1);
       if (l + 1 < k) F.kptr[l] = A.take<int32_t>(S->n[l] + 1);
     }
-  if (want_next) {
-    if (nmax <= SMALL_FILTER_NODES)
-      for (int l = 0; l + 1 < k; l++) F.src[l] = A.take<int32_t>((S->n[l] << (l + 1)) + 1);
-    else
-      for (int l = 1; l < k; l++) F.kpar[l] = A.take<int32_t>(S->n[l] > 0 ? S->n[l] : 1);
-  }
+  if (want_next)
+    for (int l = 1; l < k; l++) F.kpar[l] = A.take<int32_t>(S->n[l] > 0 ? S->n[l] : 1);
 }
 
 size_t filter_workspace_bytes(const vx_csf* S) {
@@ -413,12 +411,12 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
       J.kptr[l] = l + 1 < k ? kptr[l] : nullptr;
       J.nidx[l] = next ? next->idx[l] : nullptr;
       J.nptr[l] = (next && l + 1 < k) ? next->ptr[l] : nullptr;
-      J.src[l] = F.src[l];
+      J.kpar[l] = F.kpar[l];
     }
     J.kcnt = F.kcnt;
     J.ncnt = F.ncnt;
     J.d_counts = d_counts;
-    hipLaunchKernelGGL(k_filter_small, dim3(1), dim3(SCAN_THREADS), 0, st, k, keep, J, next ? 1 : 0);
+    hipLaunchKernelGGL(k_filter_small, dim3(1), dim3(SMALL_FILTER_THREADS), 0, st, k, keep, J, next ? 1 : 0);
     VX_CHECK_LAUNCH("k_filter_small");
     return VX_OK;
   }

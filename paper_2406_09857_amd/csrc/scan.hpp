@@ -29,17 +29,19 @@ __device__ __forceinline__ int64_t wave_inclusive_scan(int64_t v) {
   return v;
 }
 
-// Exclusive scan of one value per thread across the workgroup; returns the
-// thread's exclusive prefix and writes the workgroup total to `total`.
+// Exclusive scan of one value per thread across a workgroup of NT threads;
+// returns the thread's exclusive prefix and writes the workgroup total to
+// `total`.
+template <int NT = SCAN_THREADS>
 __device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t& total) {
-  __shared__ int64_t wsum[SCAN_THREADS / 64];
+  __shared__ int64_t wsum[NT / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   int64_t inc = wave_inclusive_scan(v);
   if (lane == 63) wsum[wid] = inc;
   __syncthreads();
   int64_t base = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < SCAN_THREADS / 64; w++) {
+  for (int w = 0; w < NT / 64; w++) {
     const int64_t s = wsum[w];
     if (w < wid) base += s;
     tot += s;
