@@ -264,6 +264,8 @@ __device__ __forceinline__ int64_t stage1_next(int64_t& off, int64_t& c1, int64_
   return at;
 }
 
+constexpr int STAGE1_PF = 8;
+
 template <int R, int CLS, int M>
 __device__ __forceinline__ void stage1_chain_m(const double2* __restrict__ Pg, int d, int r0, int gdeg, int64_t gidx,
                                                const double (&u)[R], const double (&v)[R], const CellOps (&ops)[R],
@@ -274,25 +276,22 @@ __device__ __forceinline__ void stage1_chain_m(const double2* __restrict__ Pg, i
   int64_t c1 = r0 + 1, c2 = dbinom(r0 + 2, 2), c3 = dbinom(r0 + 3, 3);
   int64_t off = dbinom(r0 + m, m + 1);  // start of the next row to load
   int rl = r0;                          // that row's index
-  // four rows in flight; rows past d read the zero entry and are never used
-  gvec2 q0 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
-  gvec2 q1 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
-  gvec2 q2 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
-  gvec2 q3 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+  // STAGE1_PF rows in flight; rows past d read the zero entry and are never used
+  constexpr int PF = STAGE1_PF;
+  gvec2 q[PF];
+#pragma unroll
+  for (int i = 0; i < PF; i++) q[i] = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
   int r = r0;
-  for (; r + 3 <= d; r += 4) {
-    stage1_steps<R, CLS>(make_double2(q0.x, q0.y), u, v, ops, nl, hh);
-    q0 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
-    stage1_steps<R, CLS>(make_double2(q1.x, q1.y), u, v, ops, nl, hh);
-    q1 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
-    stage1_steps<R, CLS>(make_double2(q2.x, q2.y), u, v, ops, nl, hh);
-    q2 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
-    stage1_steps<R, CLS>(make_double2(q3.x, q3.y), u, v, ops, nl, hh);
-    q3 = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+  for (; r + PF - 1 <= d; r += PF) {
+#pragma unroll
+    for (int i = 0; i < PF; i++) {
+      stage1_steps<R, CLS>(make_double2(q[i].x, q[i].y), u, v, ops, nl, hh);
+      q[i] = P[stage1_next<M>(off, c1, c2, c3, rl, d, gdeg, gidx, zidx)];
+    }
   }
-  if (r <= d) stage1_steps<R, CLS>(make_double2(q0.x, q0.y), u, v, ops, nl, hh);
-  if (r + 1 <= d) stage1_steps<R, CLS>(make_double2(q1.x, q1.y), u, v, ops, nl, hh);
-  if (r + 2 <= d) stage1_steps<R, CLS>(make_double2(q2.x, q2.y), u, v, ops, nl, hh);
+#pragma unroll
+  for (int i = 0; i < PF - 1; i++)
+    if (r + i <= d) stage1_steps<R, CLS>(make_double2(q[i].x, q[i].y), u, v, ops, nl, hh);
 }
 
 template <int R, int CLS>
@@ -372,11 +371,11 @@ __device__ __forceinline__ void stage1_body(const PolyTab& pt, int m, const int3
   }
 }
 
-template <int R>
 // One workgroup per (polynomial z, tuple wave y, segment x) item, x fastest.
 // Items are dealt to the XCDs in chunks of whole tuple waves (all segments of
 // one (z, y)), so an XCD streams only its share of the coefficient tensor,
 // which stays in its L2 while every segment reads it.
+template <int R>
 __global__ __launch_bounds__(64) void k_stage1(PolySet ps, int m, const int32_t* __restrict__ labels0,
                                                const int4* __restrict__ seg, const int64_t* __restrict__ nseg,
                                                AxisGrid g, RowSet out, int out_width, int64_t maxseg, int ny,
@@ -538,15 +537,24 @@ __device__ __forceinline__ void narrow_run(const crow_t* __restrict__ C, const i
 // Middle stage on padded rows (k = 3): every group of 8 entries belongs to one
 // chain, chains end on group boundaries, and the leading zeros replace the
 // masking; two register buffers alternate so no copies are needed.
-template <int CLS>
-__device__ __forceinline__ void narrow_padded(const crow_t* __restrict__ C, int j, const int jend, const CellOps& o,
+typedef __attribute__((address_space(1))) const dvec2 vrow_t;
+
+// ROW = crow_t: the row is wave-uniform (scalar loads, the next group issued
+// once the current one has arrived); ROW = vrow_t: every lane reads its own
+// parent's row with vector loads.
+template <int CLS, class ROW>
+__device__ __forceinline__ void narrow_padded(ROW* __restrict__ C, int j, const int jend, const CellOps& o,
                                               bool valid, double* __restrict__ out, int64_t es, int out_width) {
-  constexpr int G = PADG;
+  constexpr bool SCALAR = __is_same(ROW, crow_t);
+  // vector rows move half groups (chains still end on whole PADG groups), so
+  // that the two register buffers cost 32 VGPRs, not 64
+  constexpr int G = SCALAR ? PADG : PADG / 2;
+  constexpr int GM = PADG / G;
   if (j >= jend) return;
   // 32-bit group counters: the scalar unit compares 32-bit values only
-  int g = (int)padded_groups(j);
-  int gend = (int)padded_groups(j + 1);
-  const int glast = (int)padded_groups(jend);
+  int g = (int)padded_groups(j) * GM;
+  int gend = (int)padded_groups(j + 1) * GM;
+  const int glast = (int)padded_groups(jend) * GM;
   dvec2 A[G], B[G];
 #pragma unroll
   for (int e = 0; e < G; e++) A[e] = C[(int64_t)g * G + e];
@@ -571,12 +579,12 @@ __device__ __forceinline__ void narrow_padded(const crow_t* __restrict__ C, int 
       nl = 0.0;
       hh = 0.0;
       j++;
-      gend = (int)padded_groups(j + 1);
+      gend = (int)padded_groups(j + 1) * GM;
     }
   };
   while (true) {
     {
-      const int64_t z = after(A[0].x);
+      const int64_t z = SCALAR ? after(A[0].x) : 0;
       const bool more = g + 1 < glast;
       if (more) {
 #pragma unroll
@@ -587,7 +595,7 @@ __device__ __forceinline__ void narrow_padded(const crow_t* __restrict__ C, int 
       if (!more) break;
     }
     {
-      const int64_t z = after(B[0].x);
+      const int64_t z = SCALAR ? after(B[0].x) : 0;
       const bool more = g + 1 < glast;
       if (more) {
 #pragma unroll
@@ -652,9 +660,9 @@ __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet s
   if (PADDED) {
     const int d = ps.p[pz].d;
     const int j0 = padded_split(d, gi, gdim), j1 = padded_split(d, gi + 1, gdim);
-    if (cls == CLS_POS) narrow_padded<CLS_POS>(C, j0, j1, o, valid, w, es, out_width);
-    else if (cls == CLS_NEG) narrow_padded<CLS_NEG>(C, j0, j1, o, valid, w, es, out_width);
-    else narrow_padded<CLS_STRADDLE>(C, j0, j1, o, valid, w, es, out_width);
+    if (cls == CLS_POS) narrow_padded<CLS_POS, crow_t>(C, j0, j1, o, valid, w, es, out_width);
+    else if (cls == CLS_NEG) narrow_padded<CLS_NEG, crow_t>(C, j0, j1, o, valid, w, es, out_width);
+    else narrow_padded<CLS_STRADDLE, crow_t>(C, j0, j1, o, valid, w, es, out_width);
     return;
   }
   const int j0 = __builtin_amdgcn_readfirstlane(split.j0[gi]);
@@ -663,6 +671,78 @@ __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet s
   if (cls == CLS_POS) narrow_run<CLS_POS, ORDER1>(C, lens, j0, j1, p0, o, valid, w, es, out_width);
   else if (cls == CLS_NEG) narrow_run<CLS_NEG, ORDER1>(C, lens, j0, j1, p0, o, valid, w, es, out_width);
   else narrow_run<CLS_STRADDLE, ORDER1>(C, lens, j0, j1, p0, o, valid, w, es, out_width);
+}
+
+// Packed middle-stage waves (k = 3): the 64 lanes take consecutive entries of
+// one sign class's tail list, so a wave holds nodes of several parents and
+// every lane streams its own parent's row with vector loads (the rows of
+// consecutive tails are neighbours, so a load instruction touches a few
+// cache lines).
+struct TailLists {
+  const int32_t* node[2];  // NEG, POS
+  const int32_t* par[2];
+};
+
+__device__ __forceinline__ void narrow_packed_item(const PolySet& ps, const RowSet& in, const int32_t* labels,
+                                                   const int4& sg, const TailLists& tl, const AxisGrid& g,
+                                                   const RowSet& out, int out_width, int pz, int gi, int gdim) {
+  const int cnt = sg.z, cls = sg.w;
+  const int lane = threadIdx.x;
+  const bool valid = lane < cnt;
+  const int64_t ti = sg.x + (valid ? lane : 0);
+  const int c = cls == CLS_NEG ? 0 : 1;
+  const int64_t node = tl.node[c][ti], parent = tl.par[c][ti];
+  double cnl, chi;
+  cell(g, labels[node], cnl, chi);
+  const CellOps o = cell_ops(cnl, chi, cls);
+  vrow_t* C = (vrow_t*)(in.rows[pz] + parent * in.stride[pz]);
+  double* w = out.rows[pz] + node * out.stride[pz];
+  const int64_t es = out.estride[pz];
+  const int d = ps.p[pz].d;
+  const int j0 = padded_split(d, gi, gdim), j1 = padded_split(d, gi + 1, gdim);
+  if (cls == CLS_NEG) narrow_padded<CLS_NEG, vrow_t>(C, j0, j1, o, valid, w, es, out_width);
+  else narrow_padded<CLS_POS, vrow_t>(C, j0, j1, o, valid, w, es, out_width);
+}
+
+// k = 3 with packed tails: one launch over the nfull parent-uniform segments
+// and the packed ones, the packed spread evenly among the others (position t
+// of the nseg is packed when floor((t+1) P / T) > floor(t P / T), P packed of
+// T), so that the vector-load waves share every CU with scalar-load waves.
+__global__ __launch_bounds__(64) void k_narrow_mixed(PolySet ps, RowSet in, const int32_t* __restrict__ labels,
+                                                     const int4* __restrict__ seg, const int64_t* __restrict__ nfull,
+                                                     const int64_t* __restrict__ nseg, TailLists tl, AxisGrid g,
+                                                     RowSet out, int out_width, int64_t maxseg, int gdim,
+                                                     int64_t items) {
+  round_up_mode();
+  const int64_t item = xcd_item(blockIdx.x % NXCD, blockIdx.x / NXCD, NARROW_XCD_CHUNK);
+  if (item >= items) return;
+  const int gi = (int)(item % gdim);
+  const int64_t t = (item / gdim) % maxseg;
+  const int pz = (int)(item / ((int64_t)gdim * maxseg));
+  const int64_t T = *nseg, nf = *nfull;
+  if (t >= T) return;
+  const int64_t P = T - nf;
+  const int64_t before = t * P / T;  // packed segments at positions < t
+  if ((t + 1) * P / T > before) {
+    narrow_packed_item(ps, in, labels, seg[nf + before], tl, g, out, out_width, pz, gi, gdim);
+    return;
+  }
+  const int4 sg = seg[t - before];
+  const int parent = sg.x, begin = sg.y, cnt = sg.z, cls = sg.w;
+  const int lane = threadIdx.x;
+  const bool valid = lane < cnt;
+  const int64_t node = begin + (valid ? lane : 0);
+  double cnl, chi;
+  cell(g, labels[node], cnl, chi);
+  const CellOps o = cell_ops(cnl, chi, cls);
+  const crow_t* C = (const crow_t*)(in.rows[pz] + (int64_t)parent * in.stride[pz]);
+  double* w = out.rows[pz] + node * out.stride[pz];
+  const int64_t es = out.estride[pz];
+  const int d = ps.p[pz].d;
+  const int j0 = padded_split(d, gi, gdim), j1 = padded_split(d, gi + 1, gdim);
+  if (cls == CLS_POS) narrow_padded<CLS_POS, crow_t>(C, j0, j1, o, valid, w, es, out_width);
+  else if (cls == CLS_NEG) narrow_padded<CLS_NEG, crow_t>(C, j0, j1, o, valid, w, es, out_width);
+  else narrow_padded<CLS_STRADDLE, crow_t>(C, j0, j1, o, valid, w, es, out_width);
 }
 
 // ---------------------------------------------------------------------------
@@ -844,6 +924,12 @@ static AxisGrid make_grid(const double* dom, int axis, int level, int centre = 0
 
 constexpr int64_t ROW_PAD = 16;  // entries of slack before and after every rows buffer
 
+// Segments of one depth: runs of at most Z children of one parent and one
+// sign class.  With `pack` (the middle stage of k = 3 on large levels), a
+// class run of c children gives floor(c / Z) full segments and its c mod Z
+// tail children go to a per-class tail list; the tails of all parents are
+// then cut into "packed" segments of Z children of several parents each,
+// stored after the nfull parent-uniform ones (seg[nfull .. nseg)).
 struct SegPlan {
   int4* seg = nullptr;
   int64_t* nseg = nullptr;
@@ -853,19 +939,41 @@ struct SegPlan {
   int64_t* tiles = nullptr;
   int64_t nparent = 0, nchild = 0, maxseg = 0;
   int Z = 64;
+  int pack = 0;
+  int64_t* nfull = nullptr;                    // parent-uniform segments (pack)
+  int64_t* tcnt[2] = {};                       // tail children per parent, NEG / POS
+  int64_t* toff[2] = {};                       // their exclusive scans
+  int64_t* ttot[2] = {};                       // tail list lengths
+  int64_t* ttiles[2] = {};
+  int32_t* tnode[2] = {};                      // tail lists: node, parent
+  int32_t* tpar[2] = {};
+  int64_t maxpacked = 0;
 };
 
-static void plan_segments(Arena& A, SegPlan& sp, int64_t nparent, int64_t nchild, int Z) {
+static void plan_segments(Arena& A, SegPlan& sp, int64_t nparent, int64_t nchild, int Z, int pack = 0) {
   sp.nparent = nparent;
   sp.nchild = nchild;
   sp.Z = Z;
-  sp.maxseg = (nchild + Z - 1) / Z + 3 * nparent;
+  sp.pack = pack;
+  sp.maxseg = (nchild + Z - 1) / Z + 3 * nparent + 2;
   sp.seg = A.take<int4>(sp.maxseg > 0 ? sp.maxseg : 1);
   sp.nseg = A.take<int64_t>(1);
   sp.cnt = A.take<int64_t>(nparent + 1);
   sp.off = A.take<int64_t>(nparent + 1);
   sp.bounds = A.take<int64_t>(2 * nparent + 2);
   sp.tiles = A.take<int64_t>(scan_tiles(nparent));
+  if (pack) {
+    sp.nfull = A.take<int64_t>(1);
+    sp.maxpacked = (nchild + Z - 1) / Z + 2;
+    for (int c = 0; c < 2; c++) {
+      sp.tcnt[c] = A.take<int64_t>(nparent + 1);
+      sp.toff[c] = A.take<int64_t>(nparent + 1);
+      sp.ttot[c] = A.take<int64_t>(1);
+      sp.ttiles[c] = A.take<int64_t>(scan_tiles(nparent));
+      sp.tnode[c] = A.take<int32_t>(nchild > 0 ? nchild : 1);
+      sp.tpar[c] = A.take<int32_t>(nchild > 0 ? nchild : 1);
+    }
+  }
 }
 
 static int build_segments(SegPlan& sp, const int32_t* ptr, const int32_t* labels, const AxisGrid& g,
@@ -899,6 +1007,13 @@ struct SegJob {
   int64_t* off[VX_KMAX];
   int4* seg[VX_KMAX];
   int64_t* nseg[VX_KMAX];
+  int pl;  // the packed depth, -1 for none (large-level path only)
+  int64_t* nfull;
+  int64_t* tcnt[2];
+  int64_t* toff[2];
+  int64_t* ttot[2];
+  int32_t* tnode[2];
+  int32_t* tpar[2];
 };
 
 constexpr int SMALL_THREADS = 1024;
@@ -988,7 +1103,13 @@ __global__ void k_seg_count_all(DepthBlocks D, SegJob J) {
   class_bounds(J.labels[l], b, e, J.g[l], ne, pb);
   J.bounds[l][2 * p] = ne;
   J.bounds[l][2 * p + 1] = pb;
-  J.cnt[l][p] = cdiv(ne - b, Z) + cdiv(pb - ne, Z) + cdiv(e - pb, Z);
+  if (l == J.pl) {
+    J.cnt[l][p] = (ne - b) / Z + cdiv(pb - ne, Z) + (e - pb) / Z;
+    J.tcnt[0][p] = (ne - b) % Z;
+    J.tcnt[1][p] = (e - pb) % Z;
+  } else {
+    J.cnt[l][p] = cdiv(ne - b, Z) + cdiv(pb - ne, Z) + cdiv(e - pb, Z);
+  }
 }
 
 __global__ void k_seg_write_all(DepthBlocks D, SegJob J) {
@@ -1002,11 +1123,39 @@ __global__ void k_seg_write_all(DepthBlocks D, SegJob J) {
   const int64_t cuts[4] = {b, J.bounds[l][2 * p], J.bounds[l][2 * p + 1], e};
   const int cls[3] = {CLS_NEG, CLS_STRADDLE, CLS_POS};
   int64_t o = J.off[l][p];
-  for (int c = 0; c < 3; c++)
-    for (int64_t q = cuts[c]; q < cuts[c + 1]; q += Z) {
-      const int64_t cnt = cuts[c + 1] - q < Z ? cuts[c + 1] - q : Z;
+  if (l != J.pl) {
+    for (int c = 0; c < 3; c++)
+      for (int64_t q = cuts[c]; q < cuts[c + 1]; q += Z) {
+        const int64_t cnt = cuts[c + 1] - q < Z ? cuts[c + 1] - q : Z;
+        J.seg[l][o++] = make_int4((int)p, (int)q, (int)cnt, cls[c]);
+      }
+    return;
+  }
+  // packed depth: full runs of Z, then this parent's tails into the class lists
+  for (int c = 0; c < 3; c++) {
+    const int64_t full_end = c == 1 ? cuts[2] : cuts[c] + (cuts[c + 1] - cuts[c]) / Z * Z;
+    for (int64_t q = cuts[c]; q < full_end; q += Z) {
+      const int64_t cnt = full_end - q < Z ? full_end - q : Z;
       J.seg[l][o++] = make_int4((int)p, (int)q, (int)cnt, cls[c]);
     }
+    if (c != 1) {
+      const int tl = c == 0 ? 0 : 1;
+      int64_t w = J.toff[tl][p];
+      for (int64_t q = full_end; q < cuts[c + 1]; q++, w++) {
+        J.tnode[tl][w] = (int32_t)q;
+        J.tpar[tl][w] = (int32_t)p;
+      }
+    }
+  }
+  // packed segments (x = offset in the class's tail list)
+  const int64_t nf = *J.nfull, tn = *J.ttot[0], tp = *J.ttot[1];
+  const int64_t wn = cdiv(tn, Z), wp = cdiv(tp, Z);
+  for (int64_t w = p; w < wn + wp; w += J.nparent[l]) {
+    const bool neg = w < wn;
+    const int64_t s = (neg ? w : w - wn) * Z, tot = neg ? tn : tp;
+    J.seg[l][nf + w] = make_int4((int)s, 0, (int)(tot - s < Z ? tot - s : Z), neg ? CLS_NEG : CLS_POS);
+  }
+  if (p == 0) *J.nseg[l] = nf + wn + wp;
 }
 
 constexpr int64_t NARROW_TARGET_WAVES = 8192;
@@ -1089,6 +1238,9 @@ int prepare_polys(const vx_poly* P, int np, void* ws, size_t ws_bytes, Prepared*
   return VX_OK;
 }
 
+// Middle-stage node count from which tails are packed into full waves.
+constexpr int64_t PACK_MIN_NODES = 8192;
+
 struct EvalPlan {
   int k = 0;
   double* rows[VX_KMAX][VX_MAXPOLY] = {};  // output rows of stage l for polynomial p
@@ -1116,10 +1268,13 @@ static void plan_eval(Arena& A, EvalPlan& E, const vx_poly* P, int np, const vx_
     }
   }
   E.R = stage1_blocking(S->n[0]);
+  int64_t nmax = 0;
+  for (int l = 0; l < k; l++) nmax = S->n[l] > nmax ? S->n[l] : nmax;
   for (int l = 0; l < k; l++) {
     const int64_t nparent = l == 0 ? 1 : S->n[l - 1];
     const int Z = l == k - 1 ? LEAF_R : (l == 0 ? E.R : 64);
-    plan_segments(A, E.seg[l], nparent, S->n[l], Z);
+    const int pack = k == 3 && l == 1 && S->n[1] >= PACK_MIN_NODES && nmax > SMALL_LEVEL_NODES;
+    plan_segments(A, E.seg[l], nparent, S->n[l], Z, pack);
   }
 }
 
@@ -1227,9 +1382,18 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
   dim3 grid((unsigned)xcd_grid(items, NARROW_XCD_CHUNK));
   const AxisGrid g = make_grid(dom, l, S->level, E.centre);
   const int pr = prof_start("k_narrow", units, st);
-  if (k == 3)
+  if (k == 3 && sp.pack) {
+    TailLists tl;
+    for (int c = 0; c < 2; c++) {
+      tl.node[c] = sp.tnode[c];
+      tl.par[c] = sp.tpar[c];
+    }
+    hipLaunchKernelGGL(k_narrow_mixed, grid, dim3(64), 0, st, ps, in, S->idx[l], (const int4*)sp.seg,
+                       (const int64_t*)sp.nfull, (const int64_t*)sp.nseg, tl, g, out, width, sp.maxseg, gmax, items);
+  } else if (k == 3) {
     hipLaunchKernelGGL((k_narrow<true, true>), grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
                        (const int64_t*)sp.nseg, g, out, width, sp.maxseg, gmax, items);
+  }
   else if (m_out == 1)
     hipLaunchKernelGGL((k_narrow<true, false>), grid, dim3(64), 0, st, ps, in, ss, S->idx[l], (const int4*)sp.seg,
                        (const int64_t*)sp.nseg, g, out, width, sp.maxseg, gmax, items);
@@ -1318,7 +1482,21 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
     J.seg[l] = sp.seg;
     J.nseg[l] = sp.nseg;
   }
-  if (nmax <= SMALL_LEVEL_NODES) {
+  J.pl = -1;
+  for (int l = 0; l < k; l++)
+    if (E.seg[l].pack) {
+      const SegPlan& sp = E.seg[l];
+      J.pl = l;
+      J.nfull = sp.nfull;
+      for (int c = 0; c < 2; c++) {
+        J.tcnt[c] = sp.tcnt[c];
+        J.toff[c] = sp.toff[c];
+        J.ttot[c] = sp.ttot[c];
+        J.tnode[c] = sp.tnode[c];
+        J.tpar[c] = sp.tpar[c];
+      }
+    }
+  if (nmax <= SMALL_LEVEL_NODES && J.pl < 0) {
     hipLaunchKernelGGL(k_segments_small, dim3(1), dim3(SMALL_THREADS), 0, st, k, J);
     VX_CHECK_LAUNCH("k_segments_small");
   } else {
@@ -1328,14 +1506,24 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
     VX_CHECK_LAUNCH("k_seg_count_all");
     MultiScan<int64_t, int64_t> M;
     memset(&M, 0, sizeof M);
-    for (int l = 0; l < k; l++) {
-      M.in[l] = E.seg[l].cnt;
-      M.out[l] = E.seg[l].off;
-      M.total[l] = E.seg[l].nseg;
-      M.tiles[l] = E.seg[l].tiles;
-      M.n[l] = E.seg[l].nparent;
+    int na = 0;
+    for (int l = 0; l < k; l++, na++) {
+      M.in[na] = E.seg[l].cnt;
+      M.out[na] = E.seg[l].off;
+      M.total[na] = E.seg[l].pack ? E.seg[l].nfull : E.seg[l].nseg;
+      M.tiles[na] = E.seg[l].tiles;
+      M.n[na] = E.seg[l].nparent;
     }
-    multi_scan(M, k, st);
+    if (J.pl >= 0)
+      for (int c = 0; c < 2; c++, na++) {
+        const SegPlan& sp = E.seg[J.pl];
+        M.in[na] = sp.tcnt[c];
+        M.out[na] = sp.toff[c];
+        M.total[na] = sp.ttot[c];
+        M.tiles[na] = sp.ttiles[c];
+        M.n[na] = sp.nparent;
+      }
+    multi_scan(M, na, st);
     VX_CHECK_LAUNCH("segment scans");
     hipLaunchKernelGGL(k_seg_write_all, grid, dim3(256), 0, st, D, J);
     VX_CHECK_LAUNCH("k_seg_write_all");

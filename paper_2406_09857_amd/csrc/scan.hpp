@@ -149,7 +149,7 @@ void scan_exclusive(Loader ld, const int64_t* n_dev, int64_t nmax, OutT* out, in
 // are 0/1 flags (uint8, nonzero counts as 1) or int64 counts; tiles[a] needs
 // scan_tiles(n_a) int64s.  The tiles of all arrays share one 1-D grid, so
 // no workgroup is launched idle.
-constexpr int MSCAN_MAX = 4;
+constexpr int MSCAN_MAX = 8;
 
 // One 1-D grid over several arrays: array a owns blocks off[a] .. off[a+1]-1,
 // n[a] / per_block + 1 of them (at least one, covering elements 0 .. n[a]).
