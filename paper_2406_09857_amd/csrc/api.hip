@@ -84,15 +84,6 @@ static int64_t theorem1_steps(const vx_poly* P, int np, const vx_csf* S) {
 // ---------------------------------------------------------------------------
 namespace vx {
 
-// End-of-level signal: written after the filter's kernels (stream order), so
-// the counts they wrote to the same mapped host buffer are already there.
-__global__ void k_signal(int64_t* flag, int64_t value) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    __threadfence_system();
-    *reinterpret_cast<volatile int64_t*>(flag) = value;
-  }
-}
-
 // Spin on the mapped flag instead of a stream wait (lower latency per level).
 // The stream is queried now and then so that a failed or idle stream ends the
 // wait with an error instead of spinning forever.
@@ -312,14 +303,29 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   char* base = reinterpret_cast<char*>(ws) + qbytes;
   const size_t total = (ws_bytes - qbytes) / 256 * 256;
 
-  hipEvent_t ev[3];
-  for (int i = 0; i < 3; i++) VX_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableSystemFence));  // timing only
+  // Timing events of two consecutive levels: a level's times are read once
+  // the next level is queued, so reading them never idles the GPU.
+  hipEvent_t evs[6] = {};
+  for (int i = 0; i < 6; i++) VX_HIP(hipEventCreateWithFlags(&evs[i], hipEventDisableSystemFence));  // timing only
   struct EvGuard {
     hipEvent_t* e;
     ~EvGuard() {
-      for (int i = 0; i < 3; i++) (void)hipEventDestroy(e[i]);
+      for (int i = 0; i < 6; i++) (void)hipEventDestroy(e[i]);
     }
-  } guard{ev};
+  } guard{evs};
+  int pending = -1;  // level whose event times are still to be read
+  auto finish_times = [&]() -> int {
+    if (pending < 0 || !stats) return VX_OK;
+    hipEvent_t* e = evs + 3 * (pending & 1);
+    VX_HIP(hipEventSynchronize(e[2]));
+    float ms = 0;
+    VX_HIP(hipEventElapsedTime(&ms, e[0], e[1]));
+    stats[pending].eval_ms = ms;
+    VX_HIP(hipEventElapsedTime(&ms, e[1], e[2]));
+    stats[pending].filter_ms = ms;
+    pending = -1;
+    return VX_OK;
+  };
 
   // S_0 at the low end.
   int64_t cap[VX_KMAX] = {1, 1, 1, 1};
@@ -402,6 +408,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     vx_csf N;
     if (!last) csf_place(&N, k, level + 1, ncap, next_base);
 
+    hipEvent_t* ev = evs + 3 * (level & 1);
     VX_HIP(hipEventRecord(ev[0], st));
     if ((rc = eval_level_prepared(Q, &S, dom, lo, hi, keep, scratch, scratch_bytes, st, P))) return rc;
     if (mv && nleaf > 0) {
@@ -410,14 +417,15 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
       if ((rc = mv_run_level(mvh, P, np, &S, dom, mlo, mhi, keep, scratch, scratch_bytes, st))) return rc;
     }
     VX_HIP(hipEventRecord(ev[1], st));
-    if ((rc = filter_impl(&S, keep, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st))) return rc;
+    // the filter publishes its counts (and the flag) as soon as they are known
+    if ((rc = filter_impl(&S, keep, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st,
+                          counts_dev + 2 * VX_KMAX, (int64_t)level + 1)))
+      return rc;
     VX_HIP(hipEventRecord(ev[2], st));
-    hipLaunchKernelGGL(k_signal, dim3(1), dim3(64), 0, st, counts_dev + 2 * VX_KMAX, (int64_t)level + 1);
-    VX_CHECK_LAUNCH("k_signal");
+    if ((rc = finish_times())) return rc;  // the previous level's times
     if ((rc = wait_for_flag(counts + 2 * VX_KMAX, (int64_t)level + 1, st))) return rc;
     for (int l = 0; l < k; l++) K.n[l] = counts[l];
     if (stats) {
-      VX_HIP(hipEventSynchronize(ev[2]));
       vx_level_stat& r = stats[level];
       memset(&r, 0, sizeof r);
       r.level = level;
@@ -426,13 +434,14 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
         r.kept[l] = K.n[l];
       }
       r.steps = theorem1_steps(P, np, &S);
-      float ms = 0;
-      VX_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
-      r.eval_ms = ms;
-      VX_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
-      r.filter_ms = ms;
+      pending = level;
     }
-    if (cb && cb(user, level, &S, lo, hi, keep, &K)) break;
+    if (cb) {
+      // the callback reads this level's buffers: let the filter finish first
+      if ((rc = finish_times())) return rc;
+      VX_HIP(hipStreamSynchronize(st));
+      if (cb(user, level, &S, lo, hi, keep, &K)) break;
+    }
     if (last) break;
     // next becomes S (at the other end)
     for (int l = 0; l < k; l++) N.n[l] = counts[k + l];
@@ -451,6 +460,9 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
       break;
     }
   }
+  if ((rc = finish_times())) return rc;
+  // the last filter may still be writing after it published its counts
+  VX_HIP(hipStreamSynchronize(st));
   return VX_OK;
 }
 

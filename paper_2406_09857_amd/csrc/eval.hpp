@@ -32,8 +32,12 @@ int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom
                     uint8_t* keep, void* ws, size_t ws_bytes, hipStream_t st, int centre = 0);
 
 size_t filter_workspace_bytes(const vx_csf* S);
+// d_counts (device-visible, may be null): the kept counts then the next
+// counts, written as soon as they are known; then, when flag is not null,
+// *flag = flag_value after a system-scope fence (the host may spin on it
+// while the rest of the filter still runs).
 int filter_impl(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
-                size_t ws_bytes, hipStream_t st);
+                size_t ws_bytes, hipStream_t st, int64_t* flag = nullptr, int64_t flag_value = 0);
 
 int init_root_impl(vx_csf* S, hipStream_t st);
 

@@ -51,6 +51,15 @@ struct AnyChildLoader {
 
 static_assert(MSCAN_MAX >= VX_KMAX, "one scan array per depth");
 
+// Publish the counts: *flag = value once the counts written before by this
+// thread are visible to the host.
+__device__ __forceinline__ void publish_counts(int64_t* flag, int64_t value) {
+  if (!flag) return;
+  __threadfence_system();
+  *reinterpret_cast<volatile int64_t*>(flag) = value;
+}
+
+
 // Survival flag of every depth-l node (l < k-1): some child survives.  One
 // thread per node reads its children's flags eight bytes at a time, eight
 // words in flight, and stops at the first batch holding a survivor.  Bytes of
@@ -106,6 +115,8 @@ struct CompactJob {
   const int64_t* kcnt;
   int64_t* ncnt;
   int64_t* d_counts;
+  int64_t* flag;
+  int64_t flag_value;
 };
 
 // Kept nodes of every depth (one 1-D grid over the depths).  A surviving
@@ -117,7 +128,7 @@ __global__ void k_compact_all(int k, DepthBlocks D, CompactJob J) {
   const bool inner = l + 1 < k;
   if (t == 0 && threadIdx.x == 0) {
     if (inner) J.kptr[l][J.kcnt[l]] = (int32_t)J.kcnt[l + 1];
-    if (l == 0)
+    if (l == 0) {
       for (int m = 0; m < k; m++) {
         J.ncnt[m] = J.kcnt[m] << (m + 1);
         if (J.d_counts) {
@@ -125,6 +136,8 @@ __global__ void k_compact_all(int k, DepthBlocks D, CompactJob J) {
           J.d_counts[k + m] = J.ncnt[m];
         }
       }
+      publish_counts(J.flag, J.flag_value);
+    }
   }
   const int64_t p = t * blockDim.x + threadIdx.x;
   if (p >= J.n[l]) return;
@@ -246,6 +259,8 @@ struct SmallFilterJob {
   int64_t* kcnt;
   int64_t* ncnt;
   int64_t* d_counts;
+  int64_t* flag;
+  int64_t flag_value;
 };
 
 // out[0..n] = exclusive prefix sums of ld(0..n-1); returns the total (all threads).
@@ -309,6 +324,7 @@ __global__ __launch_bounds__(SMALL_FILTER_THREADS) void k_filter_small(int k, co
       }
       if (want_next && l + 1 < k) J.nptr[l][kc[l] << (l + 1)] = (int32_t)(kc[l + 1] << (l + 2));
     }
+  if (threadIdx.x == 0) publish_counts(J.flag, J.flag_value);
   if (!want_next) return;
   __syncthreads();
   GenJob G;
@@ -374,18 +390,18 @@ size_t filter_workspace_bytes(const vx_csf* S) {
 }
 
 static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts,
-                       void* ws, size_t ws_bytes, hipStream_t st);
+                       void* ws, size_t ws_bytes, hipStream_t st, int64_t* flag, int64_t flag_value);
 
 int filter_impl(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
-                size_t ws_bytes, hipStream_t st) {
+                size_t ws_bytes, hipStream_t st, int64_t* flag, int64_t flag_value) {
   const int ps = prof_start("filter_subdivide", (double)S->n[S->k - 1], st);
-  const int rc = filter_body(S, keep, kept, next, d_counts, ws, ws_bytes, st);
+  const int rc = filter_body(S, keep, kept, next, d_counts, ws, ws_bytes, st, flag, flag_value);
   prof_stop(ps, st);
   return rc;
 }
 
 static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts,
-                       void* ws, size_t ws_bytes, hipStream_t st) {
+                       void* ws, size_t ws_bytes, hipStream_t st, int64_t* flag, int64_t flag_value) {
   const int k = S->k;
   Arena A;
   A.base = reinterpret_cast<char*>(ws);
@@ -416,6 +432,8 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
     J.kcnt = F.kcnt;
     J.ncnt = F.ncnt;
     J.d_counts = d_counts;
+    J.flag = flag;
+    J.flag_value = flag_value;
     hipLaunchKernelGGL(k_filter_small, dim3(1), dim3(SMALL_FILTER_THREADS), 0, st, k, keep, J, next ? 1 : 0);
     VX_CHECK_LAUNCH("k_filter_small");
     return VX_OK;
@@ -455,6 +473,8 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
   C.kcnt = F.kcnt;
   C.ncnt = F.ncnt;
   C.d_counts = d_counts;
+  C.flag = flag;
+  C.flag_value = flag_value;
   const DepthBlocks D = depth_blocks(S->n, k, 256);
   hipLaunchKernelGGL(k_compact_all, dim3(D.blocks()), dim3(256), 0, st, k, D, C);
   VX_CHECK_LAUNCH("k_compact_all");
