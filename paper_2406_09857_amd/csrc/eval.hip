@@ -80,6 +80,7 @@ __device__ inline int64_t o_pos(const int* t, int m, int d) {
 // multiple of 8 entries, so it occupies the 8-entry groups [c(j), c(j+1)),
 // c(j) = sum_{i=1..j} ceil(i/8).  Entry (e2, e3) sits at 8 c(j+1) - 1 - e2.
 constexpr int PADG = 8;
+constexpr int SEG_PACKED = 4;  // segment class | this flag: a packed middle-stage segment
 
 __host__ __device__ inline int64_t padded_groups(int64_t j) {
   const int64_t q = j / PADG, r = j % PADG;
@@ -704,10 +705,9 @@ __device__ __forceinline__ void narrow_packed_item(const PolySet& ps, const RowS
   else narrow_padded<CLS_POS, vrow_t>(C, j0, j1, o, valid, w, es, out_width);
 }
 
-// k = 3 with packed tails: one launch over the nfull parent-uniform segments
-// and the packed ones, the packed spread evenly among the others (position t
-// of the nseg is packed when floor((t+1) P / T) > floor(t P / T), P packed of
-// T), so that the vector-load waves share every CU with scalar-load waves.
+// k = 3 with packed tails: one launch over the parent-uniform segments and
+// the packed ones (flagged), so that vector-load waves share the CUs with
+// scalar-load waves and run next to the segments that read the same rows.
 __global__ __launch_bounds__(64) void k_narrow_mixed(PolySet ps, RowSet in, const int32_t* __restrict__ labels,
                                                      const int4* __restrict__ seg, const int64_t* __restrict__ nfull,
                                                      const int64_t* __restrict__ nseg, TailLists tl, AxisGrid g,
@@ -719,15 +719,14 @@ __global__ __launch_bounds__(64) void k_narrow_mixed(PolySet ps, RowSet in, cons
   const int gi = (int)(item % gdim);
   const int64_t t = (item / gdim) % maxseg;
   const int pz = (int)(item / ((int64_t)gdim * maxseg));
-  const int64_t T = *nseg, nf = *nfull;
-  if (t >= T) return;
-  const int64_t P = T - nf;
-  const int64_t before = t * P / T;  // packed segments at positions < t
-  if ((t + 1) * P / T > before) {
-    narrow_packed_item(ps, in, labels, seg[nf + before], tl, g, out, out_width, pz, gi, gdim);
+  (void)nfull;
+  if (t >= *nseg) return;
+  const int4 sg = seg[t];
+  if (sg.w & SEG_PACKED) {
+    narrow_packed_item(ps, in, labels, make_int4(sg.x, sg.y, sg.z, sg.w & ~SEG_PACKED), tl, g, out, out_width, pz,
+                       gi, gdim);
     return;
   }
-  const int4 sg = seg[t - before];
   const int parent = sg.x, begin = sg.y, cnt = sg.z, cls = sg.w;
   const int lane = threadIdx.x;
   const bool valid = lane < cnt;
@@ -928,8 +927,9 @@ constexpr int64_t ROW_PAD = 16;  // entries of slack before and after every rows
 // sign class.  With `pack` (the middle stage of k = 3 on large levels), a
 // class run of c children gives floor(c / Z) full segments and its c mod Z
 // tail children go to a per-class tail list; the tails of all parents are
-// then cut into "packed" segments of Z children of several parents each,
-// stored after the nfull parent-uniform ones (seg[nfull .. nseg)).
+// then cut into "packed" segments of Z children of several parents each
+// (class | SEG_PACKED), stored in parent order among the nfull
+// parent-uniform ones.
 struct SegPlan {
   int4* seg = nullptr;
   int64_t* nseg = nullptr;
@@ -1131,7 +1131,14 @@ __global__ void k_seg_write_all(DepthBlocks D, SegJob J) {
       }
     return;
   }
-  // packed depth: full runs of Z, then this parent's tails into the class lists
+  // Packed depth, in parent order: this parent's full runs of Z, then the
+  // packed segments whose first tail child is one of this parent's (so a
+  // packed wave runs next to the full segments that read the same rows).  A
+  // class's packed segment w starts at tail-list offset Z w; the packed
+  // segments starting before this parent's tails number ceil(toff / Z).
+  const int64_t cN = cdiv(J.toff[0][p], Z), cP = cdiv(J.toff[1][p], Z);
+  const int64_t cN1 = cdiv(J.toff[0][p + 1], Z), cP1 = cdiv(J.toff[1][p + 1], Z);
+  o += cN + cP;
   for (int c = 0; c < 3; c++) {
     const int64_t full_end = c == 1 ? cuts[2] : cuts[c] + (cuts[c + 1] - cuts[c]) / Z * Z;
     for (int64_t q = cuts[c]; q < full_end; q += Z) {
@@ -1147,15 +1154,13 @@ __global__ void k_seg_write_all(DepthBlocks D, SegJob J) {
       }
     }
   }
-  // packed segments (x = offset in the class's tail list)
-  const int64_t nf = *J.nfull, tn = *J.ttot[0], tp = *J.ttot[1];
-  const int64_t wn = cdiv(tn, Z), wp = cdiv(tp, Z);
-  for (int64_t w = p; w < wn + wp; w += J.nparent[l]) {
-    const bool neg = w < wn;
-    const int64_t s = (neg ? w : w - wn) * Z, tot = neg ? tn : tp;
-    J.seg[l][nf + w] = make_int4((int)s, 0, (int)(tot - s < Z ? tot - s : Z), neg ? CLS_NEG : CLS_POS);
-  }
-  if (p == 0) *J.nseg[l] = nf + wn + wp;
+  // packed records (x = offset in the class's tail list)
+  const int64_t tn = *J.ttot[0], tp = *J.ttot[1];
+  for (int64_t w = cN; w < cN1; w++)
+    J.seg[l][o++] = make_int4((int)(w * Z), 0, (int)(tn - w * Z < Z ? tn - w * Z : Z), CLS_NEG | SEG_PACKED);
+  for (int64_t w = cP; w < cP1; w++)
+    J.seg[l][o++] = make_int4((int)(w * Z), 0, (int)(tp - w * Z < Z ? tp - w * Z : Z), CLS_POS | SEG_PACKED);
+  if (p == 0) *J.nseg[l] = *J.nfull + cdiv(tn, Z) + cdiv(tp, Z);
 }
 
 constexpr int64_t NARROW_TARGET_WAVES = 8192;
