@@ -812,14 +812,16 @@ __device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int64_
     if (j + i <= d) steps(q[i]);
 }
 
-// One lane per leaf segment (<= LEAF_R boxes of one parent and one class).
+// One lane per leaf segment (<= LR boxes of one parent and one class; LR =
+// LEAF_R, or 1 on the smallest levels, where the lanes are plentiful and
+// each lane's serial chain is the latency).
 // SPLITP: the polynomials of a segment run on P2 adjacent lanes (P2 = the
 // power of two >= np), one each, and the lanes OR their exclusion flags with
 // cross-lane shuffles; small levels use it to halve (or better) the serial
 // chain of each lane.
 constexpr int LEAF_R = 4;
 
-template <bool SPLITP, int PF>
+template <bool SPLITP, int PF, int LR>
 __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int4* __restrict__ seg,
                                               const int64_t* __restrict__ nseg, const int32_t* __restrict__ labels,
                                               int64_t nleaf, AxisGrid g, double* __restrict__ lo_out,
@@ -833,9 +835,9 @@ __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int
   const int4 sg = seg[sid];
   const int64_t par = sg.x, begin = sg.y;
   const int cnt = sg.z, cls = sg.w;
-  double u[LEAF_R], v[LEAF_R];
+  double u[LR], v[LR];
 #pragma unroll
-  for (int i = 0; i < LEAF_R; i++) {
+  for (int i = 0; i < LR; i++) {
     double cnl, chi;
     cell(g, labels[begin + (i < cnt ? i : 0)], cnl, chi);
     const CellOps o = cell_ops(cnl, chi, cls == CLS_STRADDLE ? CLS_POS : cls);
@@ -848,10 +850,10 @@ __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int
     const double* R = rows.rows[p] + par * rows.stride[p];
     const int64_t es = rows.estride[p];
     const int d = ps.p[p].d;
-    double nl[LEAF_R], hh[LEAF_R];
+    double nl[LR], hh[LR];
     if (cls == CLS_STRADDLE) {
 #pragma unroll
-      for (int i = 0; i < LEAF_R; i++) {
+      for (int i = 0; i < LR; i++) {
         nl[i] = 0.0;
         hh[i] = 0.0;
         if (i < cnt) {
@@ -861,10 +863,10 @@ __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int
         }
       }
     } else {
-      leaf_chains<LEAF_R, PF>(R, es, d, cls == CLS_NEG ? 1 : 0, u, v, nl, hh);
+      leaf_chains<LR, PF>(R, es, d, cls == CLS_NEG ? 1 : 0, u, v, nl, hh);
     }
 #pragma unroll
-    for (int i = 0; i < LEAF_R; i++) {
+    for (int i = 0; i < LR; i++) {
       if (i < cnt) {
         const double lo = -opaque(nl[i]);
         lo_out[p * nleaf + begin + i] = lo;
@@ -879,15 +881,17 @@ __global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int
   }
   if (keep) {
 #pragma unroll
-    for (int i = 0; i < LEAF_R; i++) {
+    for (int i = 0; i < LR; i++) {
       const bool ex = (excl >> i) & 1;
       if (i < cnt) keep[begin + i] = first ? (ex ? 0 : 1) : (ex ? 0 : keep[begin + i]);
     }
   }
 }
 
-// Largest leaf count for the one-polynomial-per-lane leaf launch.
+// Largest leaf count for the one-polynomial-per-lane leaf launch, and for
+// one box per lane.
 constexpr int64_t LEAF_SPLIT_NODES = 1536 * 1024;
+constexpr int64_t LEAF_ONE_NODES = 16384;
 
 // Parent (depth k-1 node) of every leaf: binary search in ptr.
 __global__ void k_parent_of(const int32_t* __restrict__ ptr, int64_t nparent, int64_t nleaf,
@@ -1277,7 +1281,7 @@ static void plan_eval(Arena& A, EvalPlan& E, const vx_poly* P, int np, const vx_
   for (int l = 0; l < k; l++) nmax = S->n[l] > nmax ? S->n[l] : nmax;
   for (int l = 0; l < k; l++) {
     const int64_t nparent = l == 0 ? 1 : S->n[l - 1];
-    const int Z = l == k - 1 ? LEAF_R : (l == 0 ? E.R : 64);
+    const int Z = l == k - 1 ? (S->n[k - 1] <= LEAF_ONE_NODES ? 1 : LEAF_R) : (l == 0 ? E.R : 64);
     const int pack = k == 3 && l == 1 && S->n[1] >= PACK_MIN_NODES && nmax > SMALL_LEVEL_NODES;
     plan_segments(A, E.seg[l], nparent, S->n[l], Z, pack);
   }
@@ -1436,18 +1440,25 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
   const int64_t* ns = (const int64_t*)sp.nseg;
   const int first = p0 == 0 ? 1 : 0;
   const int pr = prof_start("k_leaf", units, st);
-  if (nleaf <= LEAF_SPLIT_NODES && pn > 1) {
+  const dim3 grid1((unsigned)((sp.maxseg + 255) / 256));
+  if (sp.Z == 1) {  // one box per lane (the segments were built with Z = 1)
+    int p2 = 1;
+    while (p2 < pn) p2 <<= 1;
+    const dim3 grid((unsigned)((sp.maxseg * p2 + 255) / 256));
+    hipLaunchKernelGGL((k_leaf<true, 8, 1>), grid, dim3(256), 0, st, ps, rs, sg, ns, S->idx[k - 1], nleaf, g, lo_p,
+                       hi_p, keep, first, p2);
+  } else if (nleaf <= LEAF_SPLIT_NODES && pn > 1) {
     int p2 = 1;
     while (p2 < pn) p2 <<= 1;
     const int64_t threads = sp.maxseg * p2;
-    hipLaunchKernelGGL((k_leaf<true, 8>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, ps, rs, sg, ns,
-                       S->idx[k - 1], nleaf, g, lo_p, hi_p, keep, first, p2);
+    hipLaunchKernelGGL((k_leaf<true, 8, LEAF_R>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, ps, rs,
+                       sg, ns, S->idx[k - 1], nleaf, g, lo_p, hi_p, keep, first, p2);
   } else if (nleaf <= LEAF_SPLIT_NODES) {
-    hipLaunchKernelGGL((k_leaf<false, 8>), dim3((unsigned)((sp.maxseg + 255) / 256)), dim3(256), 0, st, ps, rs, sg,
-                       ns, S->idx[k - 1], nleaf, g, lo_p, hi_p, keep, first, 1);
+    hipLaunchKernelGGL((k_leaf<false, 8, LEAF_R>), grid1, dim3(256), 0, st, ps, rs, sg, ns, S->idx[k - 1], nleaf, g,
+                       lo_p, hi_p, keep, first, 1);
   } else {
-    hipLaunchKernelGGL((k_leaf<false, 4>), dim3((unsigned)((sp.maxseg + 255) / 256)), dim3(256), 0, st, ps, rs, sg,
-                       ns, S->idx[k - 1], nleaf, g, lo_p, hi_p, keep, first, 1);
+    hipLaunchKernelGGL((k_leaf<false, 4, LEAF_R>), grid1, dim3(256), 0, st, ps, rs, sg, ns, S->idx[k - 1], nleaf, g,
+                       lo_p, hi_p, keep, first, 1);
   }
   VX_CHECK_LAUNCH("k_leaf");
   prof_stop(pr, st);
