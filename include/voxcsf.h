@@ -19,8 +19,9 @@
  *     the caller; the library keeps no device allocation between calls.
  *   - `stream` is a hipStream_t (NULL = default stream).  Calls enqueue work
  *     on it and return without waiting unless stated otherwise.
- *   - Scratch memory is the caller's `ws` (device, 256-byte aligned) of
- *     `ws_bytes`; vx_workspace_bytes() gives the size a call needs.
+ *   - Scratch memory is the caller's `ws` (device, 256-byte aligned: any
+ *     other address is VX_EINVAL) of `ws_bytes`; vx_workspace_bytes() gives
+ *     the size a call needs.
  *   - Return value: VX_OK or a negative VX_E* code; vx_last_error() then
  *     describes the failure (per host thread).  Argument errors are detected
  *     before anything is enqueued.

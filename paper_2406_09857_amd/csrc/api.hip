@@ -65,6 +65,15 @@ static int check_dom(const double* dom, int k) {
   return VX_OK;
 }
 
+// The workspace contract: 256-byte aligned (every buffer carved from it is
+// aligned to 256 bytes relative to its start, and kernels rely on 16-byte
+// alignment of their rows).
+static int check_ws(const void* ws) {
+  if (ws && (reinterpret_cast<uintptr_t>(ws) & 255))
+    VX_FAIL(VX_EINVAL, "workspace %p is not 256-byte aligned", ws);
+  return VX_OK;
+}
+
 static int64_t theorem1_steps(const vx_poly* P, int np, const vx_csf* S) {
   int64_t total = 0;
   for (int p = 0; p < np; p++) {
@@ -166,6 +175,7 @@ int interval_eval_level(const vx_poly* P, int32_t np, const vx_csf* S, const dou
   if ((rc = check_poly(P, np, S->k))) return rc;
   if ((rc = check_dom(dom, S->k))) return rc;
   if (S->n[S->k - 1] > 0 && (!lo || !hi)) VX_FAIL(VX_EINVAL, "null output arrays");
+  if ((rc = check_ws(ws))) return rc;
   return eval_level_impl(P, np, S, dom, lo, hi, keep, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -178,6 +188,7 @@ int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const do
   if ((rc = check_dom(dom, S->k))) return rc;
   if (S->n[S->k - 1] > 0 && (!lo || !hi)) VX_FAIL(VX_EINVAL, "null output arrays");
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
+  if ((rc = check_ws(ws))) return rc;
   return mv_impl(P, np, S, dom, lo, hi, keep, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -196,6 +207,7 @@ int filter_subdivide(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf*
     if (next && (next->k != k || next->cap[l] < bound || !next->idx[l] || (l + 1 < k && !next->ptr[l])))
       VX_FAIL(VX_ECAPACITY, "next CSF: depth %d needs capacity %lld", l + 1, (long long)bound);
   }
+  if ((rc = check_ws(ws))) return rc;
   if (kept) kept->level = S->level;
   if (next) next->level = S->level + 1;
   return filter_impl(S, keep, kept, next, d_counts, ws, ws_bytes, (hipStream_t)stream);
@@ -229,6 +241,7 @@ int eval_grad(const vx_poly* P, int32_t np, const double* x, int64_t n, double* 
     for (int p = 0; p < np; p++)
       if (P[p].degree > MAXDEG_ADJ) VX_FAIL(VX_EUNSUPPORTED, "coefficient gradient limited to degree %d", MAXDEG_ADJ);
   }
+  if ((rc = check_ws(ws))) return rc;
   return grad_impl(P, np, x, n, f, jac, gbar, xbar, dcoef, dcoef ? grid : nullptr, dom, ws, ws_bytes,
                    (hipStream_t)stream);
 }
@@ -246,6 +259,7 @@ int newton_project(const vx_poly* P, int32_t np, double* x, int64_t n, int32_t s
   int rc;
   if ((rc = check_point_polys(P, np))) return rc;
   if (n < 0 || (n > 0 && !x) || steps < 0 || steps > 100) VX_FAIL(VX_EINVAL, "bad arguments");
+  if ((rc = check_ws(ws))) return rc;
   return newton_impl(P, np, x, n, steps, f, ws, ws_bytes, (hipStream_t)stream);
 }
 
@@ -275,6 +289,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   if ((rc = check_dom(dom, k))) return rc;
   if (depth < 0 || depth > 28) VX_FAIL(VX_EINVAL, "depth %d outside [0, 28]", depth);
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
+  if ((rc = check_ws(ws))) return rc;
   if (flags & ~VX_RUN_MEAN_VALUE) VX_FAIL(VX_EINVAL, "unknown flags 0x%x", flags);
   const bool mv = (flags & VX_RUN_MEAN_VALUE) != 0;
   if (mv && np * k > VX_MAXPOLY) VX_FAIL(VX_EINVAL, "mean-value test: np * k = %d exceeds %d", np * k, VX_MAXPOLY);
@@ -506,6 +521,7 @@ int vx_batch_create(const vx_poly* P, int32_t nsys, const double* dom, int32_t d
   if (tune && (rc = check_tune(tune, depth + 1))) return rc;
   if (flags & ~VX_BATCH_GRAPH) VX_FAIL(VX_EINVAL, "batch: unknown flags 0x%x", flags);
   if (!ws) VX_FAIL(VX_EINVAL, "batch: null workspace");
+  if (reinterpret_cast<uintptr_t>(ws) & 255) VX_FAIL(VX_EINVAL, "batch: workspace not 256-byte aligned");
   return batch_create_impl(P, nsys, dom, depth, cap, tune, flags, ws, ws_bytes, (hipStream_t)stream, out);
 }
 
@@ -541,6 +557,8 @@ int csf_build(int32_t k, int32_t level, const int32_t* boxes, int64_t n, vx_csf*
   for (int l = 0; l < k; l++)
     if (out->cap[l] < n || !out->idx[l] || (l + 1 < k && !out->ptr[l]))
       VX_FAIL(VX_ECAPACITY, "output CSF depth %d needs capacity %lld", l + 1, (long long)n);
+  int rc;
+  if ((rc = check_ws(ws))) return rc;
   out->level = level;
   return build_impl(k, level, boxes, n, out, nullptr, ws, ws_bytes, (hipStream_t)stream);
 }

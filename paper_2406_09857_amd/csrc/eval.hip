@@ -365,9 +365,13 @@ __device__ __forceinline__ void stage1_body(const PolyTab& pt, int m, const int3
   for (int j = 0; j < R; j++) {
     if (j < cnt) {
       double* o = base + (int64_t)(begin + j) * stride + (int64_t)opos * out_width;
-      o[0] = nl[j];
-      o[1] = hh[j];
-      if (out_width == 3) o[2] = nl[j];
+      if (out_width == 2) {  // 16-byte aligned (rows, strides and entries are): one store
+        *reinterpret_cast<double2*>(o) = make_double2(nl[j], hh[j]);
+      } else {
+        o[0] = nl[j];
+        o[1] = hh[j];
+        o[2] = nl[j];
+      }
     }
   }
 }

@@ -297,6 +297,20 @@ __global__ __launch_bounds__(SMALL_FILTER_THREADS) void k_filter_small(int k, co
   kc[k - 1] = block_scan_to(KeepLoader{keep}, J.n[k - 1], J.newpos[k - 1]);
   for (int l = k - 2; l >= 0; l--)
     kc[l] = block_scan_to(AnyChildLoader{J.ptr[l], J.newpos[l + 1]}, J.n[l], J.newpos[l]);
+  // the counts are final: publish them before the compaction and the next CSF
+  if (threadIdx.x == 0) {
+    for (int l = 0; l < k; l++) {
+      if (l + 1 < k) J.kptr[l][kc[l]] = (int32_t)kc[l + 1];
+      J.kcnt[l] = kc[l];
+      J.ncnt[l] = kc[l] << (l + 1);
+      if (J.d_counts) {
+        J.d_counts[l] = kc[l];
+        J.d_counts[k + l] = kc[l] << (l + 1);
+      }
+      if (want_next && l + 1 < k) J.nptr[l][kc[l] << (l + 1)] = (int32_t)(kc[l + 1] << (l + 2));
+    }
+    publish_counts(J.flag, J.flag_value);
+  }
   int64_t items = 0;
   for (int l = 0; l < k; l++) items += J.n[l];
   for (int64_t i = threadIdx.x; i < items; i += SMALL_FILTER_THREADS) {
@@ -313,18 +327,6 @@ __global__ __launch_bounds__(SMALL_FILTER_THREADS) void k_filter_small(int k, co
         for (int32_t c = c0; c < c1; c++) J.kpar[l + 1][c] = q;
     }
   }
-  if (threadIdx.x == 0)
-    for (int l = 0; l < k; l++) {
-      if (l + 1 < k) J.kptr[l][kc[l]] = (int32_t)kc[l + 1];
-      J.kcnt[l] = kc[l];
-      J.ncnt[l] = kc[l] << (l + 1);
-      if (J.d_counts) {
-        J.d_counts[l] = kc[l];
-        J.d_counts[k + l] = kc[l] << (l + 1);
-      }
-      if (want_next && l + 1 < k) J.nptr[l][kc[l] << (l + 1)] = (int32_t)(kc[l + 1] << (l + 2));
-    }
-  if (threadIdx.x == 0) publish_counts(J.flag, J.flag_value);
   if (!want_next) return;
   __syncthreads();
   GenJob G;

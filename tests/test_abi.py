@@ -49,3 +49,22 @@ def test_error_path_without_gpu_work():
     rc = L.filter_subdivide(C.byref(s), None, None, None, None, None, 0, None)
     assert rc == b.VX_EINVAL
     assert b"k=7" in L.vx_last_error()
+
+
+def test_misaligned_workspace_is_rejected_before_any_work():
+    """The workspace contract (256-byte aligned) is checked on the host."""
+    import ctypes as C
+    from paper_2406_09857_amd import binding as b
+    L = b.lib()
+    s = b.vx_csf()
+    s.k = 1
+    s.level = 0
+    s.n[0] = 0
+    s.cap[0] = 1
+    s.idx[0] = 256  # never dereferenced: no boxes
+    parr = (b.vx_poly * 1)()
+    parr[0].k, parr[0].degree, parr[0].side = 1, 1, 2
+    parr[0].c_lo = 4096  # a device address in a real call; never dereferenced here
+    dom = (C.c_double * 2)(-1.0, 1.0)
+    rc = L.interval_eval_level(parr, 1, C.byref(s), dom, None, None, None, C.c_void_p(4096 + 8), 1 << 20, None)
+    assert rc == b.VX_EINVAL and b"aligned" in L.vx_last_error()
