@@ -688,6 +688,61 @@ struct TailLists {
   const int32_t* par[2];
 };
 
+// Packed waves with at most PK_SLOTS distinct parents (the usual case) stage
+// every group of 8 entries of those parents' rows in LDS: lanes 0 .. 8P-1
+// load one entry each (issued a group ahead, written to LDS after the
+// current group's steps), and every lane reads its parent's entries from
+// LDS.  One wave per workgroup, so the in-order LDS queue of the wave orders
+// the writes before the next group's reads.
+constexpr int PK_SLOTS = 8;
+
+template <int CLS>
+__device__ __forceinline__ void narrow_packed_lds(const double* __restrict__ rows, int64_t stride, int slot, int nslot,
+                                                  const int32_t* __restrict__ spar, int j, const int jend,
+                                                  const CellOps& o, bool valid, double* __restrict__ out, int64_t es,
+                                                  int out_width) {
+  constexpr int G = PADG;
+  __shared__ dvec2 buf[2][PK_SLOTS][G];
+  if (j >= jend) return;
+  const int lane = threadIdx.x;
+  const bool loader = lane < G * nslot;
+  const int ls = loader ? lane / G : 0, le = lane % G;
+  const vrow_t* src = (const vrow_t*)(rows + (int64_t)spar[ls] * stride) + le;
+  int g = (int)padded_groups(j);
+  int gend = (int)padded_groups(j + 1);
+  const int glast = (int)padded_groups(jend);
+  if (loader) buf[0][ls][le] = src[(int64_t)g * G];
+  int b = 0;
+  double nl = 0.0, hh = 0.0;
+  while (true) {
+    const bool more = g + 1 < glast;
+    dvec2 nxt = dvec2{0.0, 0.0};
+    if (more && loader) nxt = src[(int64_t)(g + 1) * G];
+#pragma unroll
+    for (int e = 0; e < G; e++) {
+      const dvec2 x = buf[b][slot][e];
+      if (CLS == CLS_POS) step_pos(nl, hh, o.u, o.v, x.x, x.y);
+      else step_neg(nl, hh, o.u, o.v, x.x, x.y);
+    }
+    g++;
+    if (g == gend) {
+      if (valid) {
+        double* w = out + (int64_t)j * es;
+        w[0] = nl;
+        w[1] = hh;
+        if (out_width == 3) w[2] = nl;
+      }
+      nl = 0.0;
+      hh = 0.0;
+      j++;
+      gend = (int)padded_groups(j + 1);
+    }
+    if (!more) break;
+    b ^= 1;
+    if (loader) buf[b][ls][le] = nxt;
+  }
+}
+
 __device__ __forceinline__ void narrow_packed_item(const PolySet& ps, const RowSet& in, const int32_t* labels,
                                                    const int4& sg, const TailLists& tl, const AxisGrid& g,
                                                    const RowSet& out, int out_width, int pz, int gi, int gdim) {
@@ -700,11 +755,26 @@ __device__ __forceinline__ void narrow_packed_item(const PolySet& ps, const RowS
   double cnl, chi;
   cell(g, labels[node], cnl, chi);
   const CellOps o = cell_ops(cnl, chi, cls);
-  vrow_t* C = (vrow_t*)(in.rows[pz] + parent * in.stride[pz]);
   double* w = out.rows[pz] + node * out.stride[pz];
   const int64_t es = out.estride[pz];
   const int d = ps.p[pz].d;
   const int j0 = padded_split(d, gi, gdim), j1 = padded_split(d, gi + 1, gdim);
+  // parent slots: the parents of a packed segment ascend with the lane
+  const int64_t prev = __shfl_up(parent, 1);
+  const bool first = lane == 0 || parent != prev;
+  const uint64_t fm = __ballot(first);
+  const int nslot = __popcll(fm);
+  if (nslot <= PK_SLOTS) {
+    __shared__ int32_t spar[PK_SLOTS];
+    const int slot = __popcll(fm & ((2ull << lane) - 1)) - 1;
+    if (first) spar[slot] = (int32_t)parent;
+    if (cls == CLS_NEG)
+      narrow_packed_lds<CLS_NEG>(in.rows[pz], in.stride[pz], slot, nslot, spar, j0, j1, o, valid, w, es, out_width);
+    else
+      narrow_packed_lds<CLS_POS>(in.rows[pz], in.stride[pz], slot, nslot, spar, j0, j1, o, valid, w, es, out_width);
+    return;
+  }
+  vrow_t* C = (vrow_t*)(in.rows[pz] + parent * in.stride[pz]);
   if (cls == CLS_NEG) narrow_padded<CLS_NEG, vrow_t>(C, j0, j1, o, valid, w, es, out_width);
   else narrow_padded<CLS_POS, vrow_t>(C, j0, j1, o, valid, w, es, out_width);
 }
