@@ -895,8 +895,10 @@ __device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int64_
 // chain of each lane.
 constexpr int LEAF_R = 4;
 
+// The large-level form (PF = 4) is held to 80 VGPRs (6 waves per SIMD
+// instead of 4; it fits without spilling); the others keep their registers.
 template <bool SPLITP, int PF, int LR>
-__global__ __launch_bounds__(256) void k_leaf(PolySet ps, RowSet rows, const int4* __restrict__ seg,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF == 4 ? 6 : 1, 8))) void k_leaf(PolySet ps, RowSet rows, const int4* __restrict__ seg,
                                               const int64_t* __restrict__ nseg, const int32_t* __restrict__ labels,
                                               int64_t nleaf, AxisGrid g, double* __restrict__ lo_out,
                                               double* __restrict__ hi_out, uint8_t* __restrict__ keep, int first,
