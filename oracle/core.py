@@ -13,6 +13,9 @@ Paper: G. Moroz, arXiv 2406.09857.
   * Algorithm 3 (subdivision) restricted to the exclusion criterion C0 and a
     fixed depth: ``subdivide``.  C0(F, B) is "0 not in []F(B)" (Sec. 3.2); a
     system is excluded when any of its polynomials excludes 0.
+  * The Taylor form of Sec. 3.2 as an exclusion test: order 1 (the mean-value
+    form, ``mean_value_level``, ``subdivide_mv``) and order 2
+    (``taylor2_level``, ``subdivide_t2``).
 """
 from __future__ import annotations
 
@@ -73,6 +76,10 @@ def lib():
         L.orc_deriv.restype = C.c_int
         L.orc_mean_value.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp]
         L.orc_mean_value.restype = C.c_int
+        L.orc_deriv2.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, C.c_int, dp, dp]
+        L.orc_deriv2.restype = C.c_int
+        L.orc_taylor2.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp, dp]
+        L.orc_taylor2.restype = C.c_int
         _lib = L
     return _lib
 
@@ -350,6 +357,81 @@ def subdivide_mv(polys, k: int, depth: int, dom=None, nthreads: int = 1):
         keep = keep_mask(lo, hi) & keep_mask(mlo, mhi)
         K = S["boxes"][keep]
         out.append({"level": level, "S": S, "lo": lo, "hi": hi, "mv_lo": mlo, "mv_hi": mhi, "keep": keep,
+                    "kept": K})
+        if level < depth:
+            boxes = children_of(K)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Order-2 Taylor form (Sec. 3.2, Taylor form definition with m = 2)
+# ---------------------------------------------------------------------------
+
+def taylor_pairs(k: int) -> list:
+    """The pairs (i, j), i <= j, in lexicographic order (the order of the
+    second-order terms and of the H_ij polynomials)."""
+    return [(i, j) for i in range(k) for j in range(i, k)]
+
+
+def deriv2(poly, d: int, i: int, j: int):
+    """Outward-rounded coefficient cubes (lo, hi) of H_ij: (1/2) d2F/dx_i^2
+    when i == j, d2F/dx_i dx_j when i < j (same side)."""
+    lo, hi, k, cube = _coef(poly)
+    olo = np.zeros_like(lo); ohi = np.zeros_like(lo)
+    if lib().orc_deriv2(k, d, cube, _dp(lo), _dp(hi), i, j, _dp(olo), _dp(ohi)):
+        raise ValueError("orc_deriv2 failed")
+    return olo, ohi
+
+
+def taylor2_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1, degrees=None):
+    """Order-2 Taylor enclosures (lo, hi: (npolys, n)) on every leaf of the CSF:
+    F(c) and every dF/dx_i(c) at the centre enclosures, every H_ij on the
+    boxes (Algorithm 2 on the same CSF), combined by ``orc_taylor2``."""
+    k, level = csf["k"], csf["level"]
+    dom = np.asarray(dom, np.float64).reshape(k, 2)
+    btabs = level_tables(dom, k, level)
+    ctabs = [centre_table(float(dom[j, 0]), float(dom[j, 1]), level) for j in range(k)]
+    boxes = np.asarray(csf["boxes"], np.int64)
+    nb = boxes.shape[0]
+    bx = np.stack([btabs[j][boxes[:, j]] for j in range(k)], axis=1) if nb else np.zeros((0, k, 2))
+    cx = np.stack([ctabs[j][boxes[:, j]] for j in range(k)], axis=1) if nb else np.zeros((0, k, 2))
+    bx = np.ascontiguousarray(bx); cx = np.ascontiguousarray(cx)
+    pairs = taylor_pairs(k)
+    los, his = [], []
+    for jp, p in enumerate(polys):
+        d = poly_degree(p) if degrees is None else degrees[jp]
+        fl, fh, _ = eval_csf(p, d, csf, ctabs, OUTWARD, nthreads)
+        D = np.zeros((k, nb, 2))
+        for i in range(k):
+            if d >= 1:
+                dl, dh, _ = eval_csf(deriv(p, d, i), d - 1, csf, ctabs, OUTWARD, nthreads)
+                D[i, :, 0] = dl; D[i, :, 1] = dh
+        H = np.zeros((len(pairs), nb, 2))
+        for t, (i, j) in enumerate(pairs):
+            if d >= 2:
+                hl, hh, _ = eval_csf(deriv2(p, d, i, j), d - 2, csf, btabs, OUTWARD, nthreads)
+                H[t, :, 0] = hl; H[t, :, 1] = hh
+        fc = np.ascontiguousarray(np.stack([fl, fh], axis=1))
+        out = np.zeros((nb, 2))
+        if nb and lib().orc_taylor2(k, nb, _dp(fc), _dp(D), _dp(H), _dp(bx), _dp(cx), _dp(out)):
+            raise ValueError("orc_taylor2 failed")
+        los.append(out[:, 0]); his.append(out[:, 1])
+    return np.array(los).reshape(len(polys), -1), np.array(his).reshape(len(polys), -1)
+
+
+def subdivide_t2(polys, k: int, depth: int, dom=None, nthreads: int = 1):
+    """Algorithm 3 with the exclusion C0 and the order-2 Taylor test together:
+    a box is dropped when, for some polynomial, either enclosure excludes 0."""
+    dom = np.array([-1.0, 1.0] * k) if dom is None else np.asarray(dom, np.float64)
+    boxes = np.zeros((1, k), np.int64)
+    out = []
+    for level in range(depth + 1):
+        S = csf_from_boxes(boxes, level)
+        lo, hi, steps = eval_level(polys, S, dom, nthreads)
+        tlo, thi = taylor2_level(polys, S, dom, nthreads)
+        keep = keep_mask(lo, hi) & keep_mask(tlo, thi)
+        K = S["boxes"][keep]
+        out.append({"level": level, "S": S, "lo": lo, "hi": hi, "t2_lo": tlo, "t2_hi": thi, "keep": keep,
                     "kept": K})
         if level < depth:
             boxes = children_of(K)

@@ -25,7 +25,11 @@
  *     sharing anything between boxes (the left-hand side of Theorem 1's
  *     comparison), used to pin the amortized routine;
  *   - the mean-value (order-1 Taylor form) enclosure of Sec. 3.2: centre
- *     enclosures, derivative coefficients and the final combination.
+ *     enclosures, derivative coefficients and the final combination;
+ *   - the order-2 Taylor form of Sec. 3.2 (Taylor form definition, m = 2):
+ *     second-derivative coefficients (halved on the diagonal) and the
+ *     combination F(c) + sum_i dF/dx_i(c) W_i + sum_{i<=j} H_ij(B) W_i W_j,
+ *     W_i = B_i - c_i, with the diagonal products taken as interval squares.
  *
  * Rounding is set with fesetround() around each batch of endpoint
  * computations; the file is compiled with clang -ffp-model=strict so that the
@@ -412,6 +416,88 @@ int orc_mean_value(int k, int64_t nbox, const double* fc, const double* D, const
       ivl Di = {D[((int64_t)i * nbox + b) * 2], D[((int64_t)i * nbox + b) * 2 + 1]};
       acc = iv_add(acc, iv_mul(Di, W, ORC_OUTWARD), ORC_OUTWARD);
     }
+    out[2 * b] = acc.lo; out[2 * b + 1] = acc.hi;
+  }
+  return 0;
+}
+
+/* Coefficients of H_ij, the order-2 Taylor coefficient polynomial of the
+ * pair i <= j: (1/2) d2F/dx_i^2 for i == j, d2F/dx_i dx_j for i < j.  Entry e
+ * is m * c_{e + u_i + u_j} with the integer m = (e_i+1)(e_i+2)/2 (i == j) or
+ * (e_i+1)(e_j+1) (i < j), exact in double, times the coefficient rounded
+ * outward once (m > 0, so the bounds scale separately).  Output cube of the
+ * same side; entries with |e| > d - 2 are zero. */
+int orc_deriv2(int k, int d, int cube, const double* clo, const double* chi, int i, int j, double* olo,
+               double* ohi) {
+  if (k < 1 || k > ORC_KMAX || i < 0 || j < i || j >= k || cube < d + 1) return -1;
+  int64_t total = ipow(cube, k);
+  int64_t shift = ipow(cube, k - 1 - i) + ipow(cube, k - 1 - j);
+  for (int64_t f = 0; f < total; f++) {
+    int64_t q = f; int deg = 0, ei = 0, ej = 0;
+    for (int a = k - 1; a >= 0; a--) {
+      int e = (int)(q % cube); q /= cube;
+      deg += e;
+      if (a == i) ei = e;
+      if (a == j) ej = e;
+    }
+    olo[f] = 0.0; ohi[f] = 0.0;
+    if (deg + 2 > d) continue;
+    double m = i == j ? (double)((ei + 1) * (ei + 2) / 2) : (double)((ei + 1) * (ej + 1));
+    int64_t src = f + shift;
+    round_down(ORC_OUTWARD); olo[f] = m * clo[src];
+    round_up(ORC_OUTWARD);   ohi[f] = m * (chi ? chi[src] : clo[src]);
+    round_restore();
+  }
+  return 0;
+}
+
+/* Interval square: the range of x^2 over X (not X*X, which forgets that both
+ * factors are the same variable). */
+static ivl iv_sqr(ivl x) {
+  ivl r;
+  if (x.lo >= 0.0) {
+    round_down(ORC_OUTWARD); r.lo = x.lo * x.lo;
+    round_up(ORC_OUTWARD);   r.hi = x.hi * x.hi;
+  } else if (x.hi <= 0.0) {
+    round_down(ORC_OUTWARD); r.lo = x.hi * x.hi;
+    round_up(ORC_OUTWARD);   r.hi = x.lo * x.lo;
+  } else {
+    r.lo = 0.0;
+    round_up(ORC_OUTWARD); r.hi = fmax(x.lo * x.lo, x.hi * x.hi);
+  }
+  round_restore();
+  return r;
+}
+
+/* Order-2 Taylor form per box b: fc[b] (2) = F(c), Dc[i][b] (2) = dF/dx_i(c),
+ * H[t][b] (2) = H_ij(B) for the pairs t = (i, j), i <= j, in lexicographic
+ * order, box[b][i] and centre[b][i] (2 each).  With W_i = B_i - c_i,
+ *   out[b] = fc + Dc_0 W_0 + ... + Dc_{k-1} W_{k-1} + sum_t H_t X_t,
+ * X_t = W_i^2 (i == j) or W_i W_j, summed left to right in that order. */
+int orc_taylor2(int k, int64_t nbox, const double* fc, const double* Dc, const double* H, const double* box,
+                const double* centre, double* out) {
+  if (k < 1 || k > ORC_KMAX) return -1;
+  for (int64_t b = 0; b < nbox; b++) {
+    ivl W[ORC_KMAX];
+    for (int i = 0; i < k; i++) {
+      const double* I = box + (b * k + i) * 2;
+      const double* c = centre + (b * k + i) * 2;
+      round_down(ORC_OUTWARD); W[i].lo = I[0] - c[1];
+      round_up(ORC_OUTWARD);   W[i].hi = I[1] - c[0];
+      round_restore();
+    }
+    ivl acc = {fc[2 * b], fc[2 * b + 1]};
+    for (int i = 0; i < k; i++) {
+      ivl Di = {Dc[((int64_t)i * nbox + b) * 2], Dc[((int64_t)i * nbox + b) * 2 + 1]};
+      acc = iv_add(acc, iv_mul(Di, W[i], ORC_OUTWARD), ORC_OUTWARD);
+    }
+    int t = 0;
+    for (int i = 0; i < k; i++)
+      for (int j = i; j < k; j++, t++) {
+        ivl X = i == j ? iv_sqr(W[i]) : iv_mul(W[i], W[j], ORC_OUTWARD);
+        ivl Ht = {H[((int64_t)t * nbox + b) * 2], H[((int64_t)t * nbox + b) * 2 + 1]};
+        acc = iv_add(acc, iv_mul(Ht, X, ORC_OUTWARD), ORC_OUTWARD);
+      }
     out[2 * b] = acc.lo; out[2 * b + 1] = acc.hi;
   }
   return 0;

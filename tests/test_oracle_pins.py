@@ -508,3 +508,177 @@ def test_mean_value_prunes_more_on_the_surface():
     for r0, r1 in zip(plain, mv):
         assert len(r1["kept"]) <= len(r0["kept"])
     assert len(mv[-1]["kept"]) < len(plain[-1]["kept"])
+
+
+# ---------------------------------------------------------------------------
+# Order-2 Taylor form (Sec. 3.2, Taylor form definition with m = 2)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_second_derivative_coefficients_match_numpy_polyder(k):
+    """Integer coefficients: every multiplier times c is exact, so H_ij equals
+    numpy's polyder taken along i and then j (a library routine), halved on
+    the diagonal."""
+    d = 6
+    rng = np.random.default_rng(170 + k)
+    c = synth.random_poly(k, d, rng, "int100")
+    for i, j in orc.taylor_pairs(k):
+        lo, hi = orc.deriv2(c, d, i, j)
+        assert np.array_equal(lo, hi)
+        ref = np.polynomial.polynomial.polyder(np.polynomial.polynomial.polyder(c, axis=i), axis=j)
+        if i == j:
+            ref = ref / 2.0
+        pad = [(0, 0)] * k
+        pad[i] = (0, pad[i][1] + 1)
+        pad[j] = (0, pad[j][1] + 1)
+        ref = np.pad(ref, pad)
+        ref[np.indices(c.shape).sum(axis=0) > d - 2] = 0.0
+        assert np.array_equal(lo, ref), (i, j)
+    # non-integer coefficients: [RD(m c), RU(m c)] brackets the exact product tightly
+    if k == 2:
+        c = synth.random_poly(2, 5, rng, "normal")
+        for (i, j) in [(0, 0), (0, 1), (1, 1)]:
+            lo, hi = orc.deriv2(c, 5, i, j)
+            for e1 in range(4):
+                for e2 in range(4 - e1):
+                    e = [e1, e2]
+                    src = list(e)
+                    src[i] += 1
+                    src[j] += 1
+                    m = (e[i] + 1) * (e[i] + 2) // 2 if i == j else (e[i] + 1) * (e[j] + 1)
+                    exact = m * ex.F(c[tuple(src)])
+                    assert ex.is_round_down(lo[e1, e2], exact) and ex.is_round_up(hi[e1, e2], exact)
+
+
+def test_taylor2_of_a_quadratic_closed_form():
+    """For F of degree 2 the second derivatives are constants and the order-2
+    form is F(c) + sum_i g_i [-h, h] + sum_i a_ii [0, h^2] + sum_{i<j} a_ij
+    [-h^2, h^2] (g = grad F(c), a_ii the x_i^2 coefficients, a_ij the x_i x_j
+    ones): exact in rationals for dyadic data, so the bits must match."""
+    k = 3
+    terms = {(2, 0, 0): 1.5, (0, 2, 0): -0.75, (0, 0, 2): 0.25, (1, 1, 0): -2.0, (1, 0, 1): 0.5,
+             (0, 1, 1): 1.25, (1, 0, 0): 0.375, (0, 1, 0): -1.0, (0, 0, 1): 0.125, (0, 0, 0): -0.3125}
+    cube = synth.monomial_poly(k, 2, terms)
+    S = orc.csf_from_boxes(np.array([[0, 3, 5], [2, 2, 2], [7, 0, 6], [4, 5, 1]]), 3)
+    lo, hi = orc.taylor2_level([cube], S, np.array([-1.0, 1.0] * k))
+    h = Fraction(1, 8)
+    T = {e: ex.F(v) for e, v in terms.items()}
+    for q, b in enumerate(S["boxes"]):
+        c = [Fraction(-1) + (2 * int(b[j]) + 1) * h for j in range(k)]
+        fc = ex.exact_point_value(cube, 2, c)
+        g = [2 * T[tuple(2 if a == i else 0 for a in range(k))] * c[i]
+             + sum(T[tuple(1 if a in (i, j) else 0 for a in range(k))] * c[j] for j in range(k) if j != i)
+             + T[tuple(1 if a == i else 0 for a in range(k))] for i in range(k)]
+        tl = fc - sum(abs(x) for x in g) * h
+        th = fc + sum(abs(x) for x in g) * h
+        for i, j in orc.taylor_pairs(k):
+            a = T[tuple((2 if i == j else 1) if x in (i, j) else 0 for x in range(k))]
+            if i == j:
+                tl += min(Fraction(0), a * h * h)
+                th += max(Fraction(0), a * h * h)
+            else:
+                tl -= abs(a) * h * h
+                th += abs(a) * h * h
+        assert ex.F(lo[0, q]) == tl and ex.F(hi[0, q]) == th, q
+
+
+def test_taylor2_of_an_affine_polynomial_is_the_mean_value_form():
+    """Degree 1: every H_ij is zero and the gradient is constant, so the
+    order-2 form and the mean-value form are the same sum (bit for bit)."""
+    k = 3
+    rng = np.random.default_rng(177)
+    cube = synth.random_poly(k, 1, rng, "normal")
+    boxes = rng.integers(0, 32, size=(40, k))
+    S = orc.csf_from_boxes(boxes, 5)
+    dom = np.array([-0.7, 1.3, -1.0, 0.9, -2.0, 2.0])
+    lo2, hi2 = orc.taylor2_level([cube], S, dom)
+    lo1, hi1 = orc.mean_value_level([cube], S, dom)
+    assert bits_equal(lo2, lo1) and bits_equal(hi2, hi1)
+
+
+def _exact_deriv_cube(cube, d, i, j=None):
+    """Exact rational coefficient cube of dF/dx_i (j None) or of H_ij."""
+    k = cube.ndim
+    out = np.empty(cube.shape, dtype=object)
+    for e in np.ndindex(*cube.shape):
+        out[e] = Fraction(0)
+        if sum(e) > d - (1 if j is None else 2):
+            continue
+        src = list(e)
+        src[i] += 1
+        if j is None:
+            m = e[i] + 1
+        else:
+            src[j] += 1
+            m = (e[i] + 1) * (e[i] + 2) // 2 if i == j else (e[i] + 1) * (e[j] + 1)
+        out[e] = m * ex.F(cube[tuple(src)])
+    return out
+
+
+@pytest.mark.parametrize("k,d,level", [(2, 6, 3), (3, 4, 2)])
+def test_taylor2_within_rounding_of_the_exact_rational_form(k, d, level):
+    """The order-2 form computed in exact rationals (exact derivative
+    coefficients, exact interval Horner, exact squares and products) lies
+    inside the oracle's enclosure, and each endpoint is within a few units in
+    the last place of the exact one: a dropped, extra or mis-weighted term, or
+    a product where the square belongs, moves an endpoint far more."""
+    rng = np.random.default_rng(180 + k)
+    poly = synth.small_random(k, d, seed=181 + k)[0]
+    boxes = rng.integers(0, 1 << level, size=(12, k))
+    S = orc.csf_from_boxes(boxes, level)
+    lo, hi = orc.taylor2_level([poly], S, np.array([-1.0, 1.0] * k))
+    tabs = orc.level_tables(np.array([-1.0, 1.0] * k), k, level)
+    Dq = [_exact_deriv_cube(poly, d, i) for i in range(k)]
+    Hq = [_exact_deriv_cube(poly, d, i, j) for i, j in orc.taylor_pairs(k)]
+    for q, b in enumerate(S["boxes"]):
+        B = [(ex.F(tabs[j][b[j]][0]), ex.F(tabs[j][b[j]][1])) for j in range(k)]
+        c = [(u + v) / 2 for u, v in B]
+        W = [(u - cj, v - cj) for (u, v), cj in zip(B, c)]
+        fc = ex.exact_point_value(poly, d, c)
+        acc = (fc, fc)
+        for i in range(k):
+            g = ex.exact_point_value(Dq[i], d - 1, c)
+            acc = ex._qadd(acc, ex._qmul((g, g), W[i]))
+        for t, (i, j) in enumerate(orc.taylor_pairs(k)):
+            hb = ex.exact_interval_eval(Hq[t], d - 2, B)
+            if i == j:
+                u, v = W[i]
+                X = (Fraction(0) if u <= 0 <= v else min(u * u, v * v), max(u * u, v * v))
+            else:
+                X = ex._qmul(W[i], W[j])
+            acc = ex._qadd(acc, ex._qmul(hb, X))
+        L, H = ex.F(lo[0, q]), ex.F(hi[0, q])
+        assert L <= acc[0] and acc[1] <= H, q
+        scale = 1 + abs(acc[0]) + abs(acc[1])
+        assert acc[0] - L <= scale * Fraction(1, 2 ** 45) and H - acc[1] <= scale * Fraction(1, 2 ** 45), q
+
+
+@pytest.mark.parametrize("k,d,level", [(2, 6, 4), (3, 4, 3)])
+def test_taylor2_contains_exact_values(k, d, level):
+    """Enclosure property: exact F at the corners, the centre and random
+    dyadic points of each box lies in the order-2 enclosure."""
+    rng = np.random.default_rng(190 + k)
+    poly = synth.small_random(k, d, seed=191 + k)[0]
+    boxes = rng.integers(0, 1 << level, size=(25, k))
+    S = orc.csf_from_boxes(boxes, level)
+    lo, hi = orc.taylor2_level([poly], S, np.array([-1.0, 1.0] * k))
+    tabs = orc.level_tables(np.array([-1.0, 1.0] * k), k, level)
+    for q, b in enumerate(S["boxes"]):
+        box = [tuple(tabs[j][b[j]]) for j in range(k)]
+        corners = [list(c) for c in np.array(np.meshgrid(*box, indexing="ij")).reshape(k, -1).T]
+        centre = [(ex.F(u) + ex.F(v)) / 2 for u, v in box]
+        for x in corners + [centre] + _dyadic_points(rng, box, 4):
+            val = ex.exact_point_value(poly, d, x)
+            assert ex.F(lo[0, q]) <= val <= ex.F(hi[0, q])
+
+
+def test_taylor2_prunes_more_on_the_surface():
+    """With the order-2 test the kept sets are subsets of C0's, strictly
+    smaller at level 5 of the degree-40 surface."""
+    w = synth.surface()
+    plain = orc.subdivide(w.polys, 3, 5, nthreads=orc.max_threads())
+    t2 = orc.subdivide_t2(w.polys, 3, 5, nthreads=orc.max_threads())
+    for r0, r1 in zip(plain, t2):
+        k0 = {tuple(x) for x in r0["kept"]}
+        assert all(tuple(x) in k0 for x in r1["kept"])
+    assert len(t2[-1]["kept"]) < len(plain[-1]["kept"])
