@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--cpu-depth", type=int, default=9, help="oracle sample: levels 0..cpu-depth of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint and mean-value legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, mean-value and order-2 Taylor legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -162,6 +162,25 @@ def bench_mean_value(vx, polys, dom, depth, plain_stats, plain_ms):
             "kept_per_level": [s["kept"][2] for s in stats],
             "plain_kept_per_level": [s["kept"][2] for s in plain_stats],
             "parity": "enclosures bit-identical to the oracle (tests/test_gpu_meanvalue.py)"}
+
+
+def bench_taylor2(vx, polys, dom, depth, plain_stats, plain_ms, mv_stats):
+    """The curve run with C0 and the order-2 Taylor test together, against C0
+    alone and against C0 with the mean-value test."""
+    import torch
+    vx.run_subdivision(polys, dom, depth, want_kept=False, taylor2=True)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        stats, _ = vx.run_subdivision(polys, dom, depth, want_kept=False, taylor2=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"ms_per_run": ms, "plain_ms_per_run": plain_ms,
+            "kept_per_level": [s["kept"][2] for s in stats],
+            "mean_value_kept_per_level": mv_stats,
+            "plain_kept_per_level": [s["kept"][2] for s in plain_stats],
+            "parity": "enclosures bit-identical to the oracle (tests/test_gpu_taylor2.py)"}
 
 
 COPY_BYTES = 1 << 31  # bytes read (and written) by the calibration copy
@@ -312,6 +331,8 @@ def main():
         _, kept = vx.run_subdivision(polys, dom, w.depth, want_kept=True)
         out["adjoint"] = bench_adjoint(vx, polys, dom, w.depth, kept)
         out["mean_value"] = bench_mean_value(vx, polys, dom, w.depth, stats, ms_step)
+        out["taylor2"] = bench_taylor2(vx, polys, dom, w.depth, stats, ms_step,
+                                       out["mean_value"]["kept_per_level"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_depth, w.depth))
     print(json.dumps(out))

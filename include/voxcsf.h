@@ -91,7 +91,7 @@ const char* vx_last_error(void);
 
 /* Workspace sizes.  `which` selects the call; arguments not used by that call
  * may be NULL/0.  Returns 0 on invalid arguments. */
-enum { VX_WS_EVAL = 0, VX_WS_FILTER = 1, VX_WS_BUILD = 2, VX_WS_GRAD = 3, VX_WS_MEANVALUE = 4 };
+enum { VX_WS_EVAL = 0, VX_WS_FILTER = 1, VX_WS_BUILD = 2, VX_WS_GRAD = 3, VX_WS_MEANVALUE = 4, VX_WS_TAYLOR2 = 5 };
 size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_csf* S, int64_t n);
 
 /*
@@ -146,6 +146,30 @@ int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const do
                          uint8_t* keep, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * taylor_exclusion -- the Taylor form of order `order` (1 or 2; Sec. 3.2,
+ * Taylor form definition) as an exclusion test on every box of S.  Order 1
+ * is mean_value_exclusion.  Order 2:
+ *   T2(F_p, B) = F_p(c) + sum_i dF_p/dx_i(c) W_i + sum_{i<=j} H_ij(B) X_ij,
+ * W_i = B_i - c_i = [RD(lo_i - chi_i), RU(hi_i - clo_i)] (c's enclosure as in
+ * mean_value_exclusion), H_ii = (1/2) d2F_p/dx_i^2 and H_ij = d2F_p/dx_i dx_j
+ * (i < j), whose coefficients m c_{e+u_i+u_j} (m = (e_i+1)(e_i+2)/2 or
+ * (e_i+1)(e_j+1), an exact integer) are rounded outward once, X_ii the range
+ * of the square ([0, RU(max(a^2, b^2))] for W_i = [a, b] holding 0) and
+ * X_ij = W_i W_j.  F_p and its gradient are evaluated at the centre
+ * enclosures and the H_ij on the boxes, each by Algorithm 2 on S; the terms
+ * are added left to right, gradient terms first, then the pairs in
+ * lexicographic order.  {F_p(x) : x in B} is contained in T2(F_p, B).
+ *   lo, hi : device double, np x S->n[k-1], the order-`order` enclosures.
+ *   keep   : device uint8 or NULL; if given, keep[b] is cleared when some
+ *            enclosure excludes 0 (AND with the caller's flags).
+ * Limits: np * k <= 64 (order 1), np * k(k+1)/2 <= 64 (order 2).  Errors as
+ * interval_eval_level, VX_EINVAL for another order; workspace
+ * vx_workspace_bytes(VX_WS_MEANVALUE or VX_WS_TAYLOR2, P, np, S, 0).
+ */
+int taylor_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, int32_t order, double* lo,
+                     double* hi, uint8_t* keep, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * filter_subdivide -- exclusion filter and bisection (Algorithm 3): prune S
  * to the kept boxes K (keep[b] != 0, internal nodes without kept descendants
  * removed) and build the CSF of their 2^k children at level+1, child c of box
@@ -194,8 +218,10 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
 /* run_subdivision with options.  flags: VX_RUN_MEAN_VALUE adds the
  * mean-value test (mean_value_exclusion) to C0 at every level: a box is kept
  * only when both tests keep it (eval_ms then includes both; the callback
- * still receives the C0 enclosures and the combined keep flags). */
-enum { VX_RUN_MEAN_VALUE = 1 };
+ * still receives the C0 enclosures and the combined keep flags).
+ * VX_RUN_TAYLOR2 adds the order-2 Taylor test (taylor_exclusion, order 2) in
+ * the same way; the two flags are exclusive (VX_EINVAL). */
+enum { VX_RUN_MEAN_VALUE = 1, VX_RUN_TAYLOR2 = 2 };
 int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
                        size_t ws_bytes, size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user,
                        void* stream);

@@ -23,8 +23,8 @@ LIB_PATH = os.path.join(HERE, "libvoxcsf.so")
 KMAX = 4
 
 VX_OK, VX_EINVAL, VX_ECAPACITY, VX_EHIP, VX_EOVERFLOW, VX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD, VX_WS_MEANVALUE = 0, 1, 2, 3, 4
-VX_RUN_MEAN_VALUE = 1
+VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD, VX_WS_MEANVALUE, VX_WS_TAYLOR2 = 0, 1, 2, 3, 4, 5
+VX_RUN_MEAN_VALUE, VX_RUN_TAYLOR2 = 1, 2
 
 
 class VxError(RuntimeError):
@@ -82,12 +82,15 @@ def lib():
                                          vp, vp]
         L.mean_value_exclusion.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.POINTER(C.c_double),
                                            vp, vp, vp, vp, C.c_size_t, vp]
+        L.taylor_exclusion.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.POINTER(C.c_double),
+                                       C.c_int32, vp, vp, vp, vp, C.c_size_t, vp]
         L.csf_build.argtypes = [C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(vx_csf), vp, C.c_size_t, vp]
         L.vx_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
         L.vx_profile_end.argtypes = [C.POINTER(vx_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
         L.vx_profile_select.argtypes = [C.c_char_p]
         for f in ("interval_eval_level", "filter_subdivide", "run_subdivision", "run_subdivision_ex", "csf_build",
-                  "vx_copy", "vx_profile_begin", "vx_profile_end", "vx_profile_select", "mean_value_exclusion"):
+                  "vx_copy", "vx_profile_begin", "vx_profile_end", "vx_profile_select", "mean_value_exclusion",
+                  "taylor_exclusion"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -245,6 +248,13 @@ def mean_value_exclusion(polys, csf: CSF, dom, keep: torch.Tensor | None = None,
     """Mean-value (order-1 Taylor form) enclosures (lo, hi: (np, nboxes)) on
     every box; ``keep`` (uint8, nboxes), if given, is cleared in place where
     some enclosure excludes 0."""
+    return taylor_exclusion(polys, csf, dom, 1, keep, stream)
+
+
+def taylor_exclusion(polys, csf: CSF, dom, order: int, keep: torch.Tensor | None = None, stream=None):
+    """Taylor-form enclosures of order 1 or 2 (lo, hi: (np, nboxes)) on every
+    box; ``keep`` (uint8, nboxes), if given, is cleared in place where some
+    enclosure excludes 0."""
     polys = as_polys(polys)
     dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
     nb = csf.nboxes
@@ -253,13 +263,14 @@ def mean_value_exclusion(polys, csf: CSF, dom, keep: torch.Tensor | None = None,
     hi = torch.empty((len(polys), max(nb, 1)), dtype=torch.float64, device=dev)
     parr = _poly_array(polys)
     s = csf.struct()
-    need = int(lib().vx_workspace_bytes(VX_WS_MEANVALUE, parr, len(polys), C.byref(s), 0))
+    need = int(lib().vx_workspace_bytes(VX_WS_TAYLOR2 if order == 2 else VX_WS_MEANVALUE, parr, len(polys),
+                                        C.byref(s), 0))
     if need == 0:
         _check(VX_EINVAL)
     ws = _ws(need, dev)
-    _check(lib().mean_value_exclusion(parr, len(polys), C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)),
-                                      lo.data_ptr(), hi.data_ptr(), keep.data_ptr() if keep is not None else None,
-                                      ws.data_ptr(), ws.numel(), _stream(stream)))
+    _check(lib().taylor_exclusion(parr, len(polys), C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)), order,
+                                  lo.data_ptr(), hi.data_ptr(), keep.data_ptr() if keep is not None else None,
+                                  ws.data_ptr(), ws.numel(), _stream(stream)))
     return lo[:, :nb], hi[:, :nb]
 
 
@@ -294,9 +305,11 @@ def root_csf(k: int, device=None) -> CSF:
 
 
 def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None,
-                    ws: torch.Tensor | None = None, want_kept: bool = True, mean_value: bool = False):
+                    ws: torch.Tensor | None = None, want_kept: bool = True, mean_value: bool = False,
+                    taylor2: bool = False):
     """Algorithm 3 with C0 to `depth`.  Returns (stats, kept) where stats is a
     list of per-level dicts and kept the final level's kept CSF (host numpy).
+    ``mean_value`` / ``taylor2`` add the Taylor test of order 1 / 2 to C0.
 
     ``record(level, S, lo, hi, keep, K)`` is called with device-side views
     (numpy copies) when given; it may return True to stop.
@@ -347,7 +360,8 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
         if ws is None or ws.numel() < size:
             ws = _ws(size)
         rc = lib().run_subdivision_ex(parr, len(polys), dom.ctypes.data_as(C.POINTER(C.c_double)), depth,
-                                      VX_RUN_MEAN_VALUE if mean_value else 0, ws.data_ptr(), ws.numel(),
+                                      (VX_RUN_MEAN_VALUE if mean_value else 0) | (VX_RUN_TAYLOR2 if taylor2 else 0),
+                                      ws.data_ptr(), ws.numel(),
                                       C.byref(need), stats, cb, None, _stream(stream))
         if rc == VX_ECAPACITY and need.value > size:
             size = int(need.value * 1.25)

@@ -93,6 +93,21 @@ static int64_t theorem1_steps(const vx_poly* P, int np, const vx_csf* S) {
 // ---------------------------------------------------------------------------
 namespace vx {
 
+// Largest derivative table set per polynomial of a Taylor test: its k first
+// derivatives (order 1), or its k(k+1)/2 second-order polynomials (order 2,
+// which also has the k first derivatives: fewer).  Each set is one system of
+// at most VX_MAXPOLY polynomials.
+static int taylor_tables(int k, int order) { return order == 0 ? 0 : order == 1 ? k : k * (k + 1) / 2; }
+
+static int check_taylor_polys(int np, int k, int order) {
+  if (order == 0) return VX_OK;
+  const int per = taylor_tables(k, order);
+  if (np * per > VX_MAXPOLY)
+    VX_FAIL(VX_EINVAL, "Taylor test of order %d: %d polynomials x %d derivative tables exceeds %d", order, np, per,
+            VX_MAXPOLY);
+  return VX_OK;
+}
+
 // Spin on the mapped flag instead of a stream wait (lower latency per level).
 // The stream is queried now and then so that a failed or idle stream ends the
 // wait with an error instead of spinning forever.
@@ -157,8 +172,11 @@ size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_
       if (!S || S->k < 1 || S->k > VX_KMAX || n < 0) return 0;
       return build_workspace_bytes(S->k, n);
     case VX_WS_MEANVALUE:
-      if (check_csf(S, false) || check_poly(P, np, S->k) || np * S->k > VX_MAXPOLY) return 0;
-      return mv_workspace_bytes(P, np, S);
+    case VX_WS_TAYLOR2: {
+      const int order = which == VX_WS_TAYLOR2 ? 2 : 1;
+      if (check_csf(S, false) || check_poly(P, np, S->k) || np * taylor_tables(S->k, order) > VX_MAXPOLY) return 0;
+      return mv_workspace_bytes(P, np, S, order);
+    }
     case VX_WS_GRAD:
       if (!P || np < 1 || np > PMAX_GRAD || check_poly(P, np, P[0].k)) return 0;
       if (S && check_csf(S, false)) return 0;
@@ -179,17 +197,23 @@ int interval_eval_level(const vx_poly* P, int32_t np, const vx_csf* S, const dou
   return eval_level_impl(P, np, S, dom, lo, hi, keep, ws, ws_bytes, (hipStream_t)stream);
 }
 
-int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo, double* hi,
-                         uint8_t* keep, void* ws, size_t ws_bytes, void* stream) {
+int taylor_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, int32_t order, double* lo,
+                     double* hi, uint8_t* keep, void* ws, size_t ws_bytes, void* stream) {
   int rc;
+  if (order != 1 && order != 2) VX_FAIL(VX_EINVAL, "Taylor order %d is not 1 or 2", order);
   if ((rc = check_csf(S, true))) return rc;
   if ((rc = check_poly(P, np, S->k))) return rc;
-  if (np * S->k > VX_MAXPOLY) VX_FAIL(VX_EINVAL, "mean-value test: np * k = %d exceeds %d", np * S->k, VX_MAXPOLY);
+  if ((rc = check_taylor_polys(np, S->k, order))) return rc;
   if ((rc = check_dom(dom, S->k))) return rc;
   if (S->n[S->k - 1] > 0 && (!lo || !hi)) VX_FAIL(VX_EINVAL, "null output arrays");
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
   if ((rc = check_ws(ws))) return rc;
-  return mv_impl(P, np, S, dom, lo, hi, keep, ws, ws_bytes, (hipStream_t)stream);
+  return mv_impl(P, np, S, dom, lo, hi, keep, ws, ws_bytes, (hipStream_t)stream, order);
+}
+
+int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo, double* hi,
+                         uint8_t* keep, void* ws, size_t ws_bytes, void* stream) {
+  return taylor_exclusion(P, np, S, dom, 1, lo, hi, keep, ws, ws_bytes, stream);
 }
 
 int filter_subdivide(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
@@ -290,13 +314,16 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   if (depth < 0 || depth > 28) VX_FAIL(VX_EINVAL, "depth %d outside [0, 28]", depth);
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
   if ((rc = check_ws(ws))) return rc;
-  if (flags & ~VX_RUN_MEAN_VALUE) VX_FAIL(VX_EINVAL, "unknown flags 0x%x", flags);
-  const bool mv = (flags & VX_RUN_MEAN_VALUE) != 0;
-  if (mv && np * k > VX_MAXPOLY) VX_FAIL(VX_EINVAL, "mean-value test: np * k = %d exceeds %d", np * k, VX_MAXPOLY);
+  if (flags & ~(VX_RUN_MEAN_VALUE | VX_RUN_TAYLOR2)) VX_FAIL(VX_EINVAL, "unknown flags 0x%x", flags);
+  if ((flags & VX_RUN_MEAN_VALUE) && (flags & VX_RUN_TAYLOR2))
+    VX_FAIL(VX_EINVAL, "VX_RUN_MEAN_VALUE and VX_RUN_TAYLOR2 are exclusive");
+  const int order = (flags & VX_RUN_TAYLOR2) ? 2 : (flags & VX_RUN_MEAN_VALUE) ? 1 : 0;
+  const bool mv = order > 0;
+  if ((rc = check_taylor_polys(np, k, order))) return rc;
   hipStream_t st = (hipStream_t)stream;
   // coefficient tables once for the whole run, at the start of the workspace
   // (followed by the mean-value test's derivative tables when requested)
-  const size_t qbytes = (prepared_bytes(P, np) + 255) / 256 * 256 + (mv ? mv_run_workspace(P, np) : 0);
+  const size_t qbytes = (prepared_bytes(P, np) + 255) / 256 * 256 + (mv ? mv_run_workspace(P, np, order) : 0);
   if (qbytes > ws_bytes) {
     if (ws_needed) *ws_needed = qbytes + (1 << 20);
     VX_FAIL(VX_ECAPACITY, "workspace too small");
@@ -306,7 +333,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   if ((rc = prepare_polys(P, np, ws, qf, &Q, st))) return rc;
   void* mvh = nullptr;
   if (mv) {
-    mvh = mv_run_begin(P, np, reinterpret_cast<char*>(ws) + qf, qbytes - qf, st, &rc);
+    mvh = mv_run_begin(P, np, reinterpret_cast<char*>(ws) + qf, qbytes - qf, st, &rc, order);
     if (rc) return rc;
   }
   struct MvGuard {
@@ -391,7 +418,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     const size_t o_mhi = mv ? carve(sizeof(double) * (size_t)np * nleaf) : 0;
     const size_t ews = eval_level_bytes(P, np, &S);
     const size_t fws = filter_workspace_bytes(&S);
-    const size_t mws = mv ? mv_level_workspace(P, np, &S) : 0;
+    const size_t mws = mv ? mv_level_workspace(P, np, &S, order) : 0;
     size_t scratch_bytes = ews > fws ? ews : fws;
     scratch_bytes = scratch_bytes > mws ? scratch_bytes : mws;
     const size_t o_scr = carve(scratch_bytes);

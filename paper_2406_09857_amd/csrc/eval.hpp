@@ -45,13 +45,13 @@ size_t build_workspace_bytes(int k, int64_t n);
 int build_impl(int k, int level, const int32_t* boxes, int64_t n, vx_csf* out, int64_t* d_counts, void* ws,
                size_t ws_bytes, hipStream_t st);
 
-// Mean-value (order-1 Taylor form) exclusion test (meanvalue.hip).
-size_t mv_workspace_bytes(const vx_poly* P, int np, const vx_csf* S);
+// Taylor-form exclusion tests of order 1 (mean value) and 2 (meanvalue.hip).
+size_t mv_workspace_bytes(const vx_poly* P, int np, const vx_csf* S, int order);
 int mv_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
-            void* ws, size_t ws_bytes, hipStream_t st);
-size_t mv_run_workspace(const vx_poly* P, int np);
-size_t mv_level_workspace(const vx_poly* P, int np, const vx_csf* S);
-void* mv_run_begin(const vx_poly* P, int np, void* ws, size_t bytes, hipStream_t st, int* rc);
+            void* ws, size_t ws_bytes, hipStream_t st, int order);
+size_t mv_run_workspace(const vx_poly* P, int np, int order);
+size_t mv_level_workspace(const vx_poly* P, int np, const vx_csf* S, int order);
+void* mv_run_begin(const vx_poly* P, int np, void* ws, size_t bytes, hipStream_t st, int* rc, int order);
 int mv_run_level(void* handle, const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi,
                  uint8_t* keep, void* ws, size_t bytes, hipStream_t st);
 void mv_run_end(void* handle);

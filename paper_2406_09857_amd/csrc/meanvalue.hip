@@ -12,6 +12,14 @@
 //     centre enclosures, and the sum taken left to right over i.
 // A box is dropped when, for some polynomial, 0 lies outside T(F, B); the
 // test is combined with C0 by AND-ing keep flags.
+//
+// Order 2 (the same definition with m = 2):
+//   T2(F, B) = F(c) + sum_i dF/dx_i(c) W_i + sum_{i<=j} H_ij(B) X_ij,
+// W_i = B_i - c_i, H_ii = (1/2) d2F/dx_i^2, H_ij = d2F/dx_i dx_j (i < j),
+// X_ii = W_i^2 (the range of a square, [0, max(a^2, b^2)] when W_i holds 0),
+// X_ij = W_i W_j; the gradient is evaluated at the centre enclosures and the
+// H_ij on the boxes, all by Algorithm 2 on the level's CSF, and the terms are
+// added left to right, the pairs in lexicographic order.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -68,6 +76,58 @@ __global__ void k_deriv(DerivArgs a, int k, int64_t cube_max, double* __restrict
   const double ch = a.chi[p] ? a.chi[p][src] : cl;
   lo[f] = -opaque(n * opaque(-cl));  // RD(n * cl) = -RU(n * -cl)
   hi[f] = n * ch;
+}
+
+// Second-derivative coefficient cubes, one thread per (polynomial, pair,
+// entry); the pairs (i, j), i <= j, in lexicographic order.  Entry e of H_ij
+// is [RD(m clo), RU(m chi)] of source entry e + u_i + u_j with the integer
+// m = (e_i+1)(e_i+2)/2 (i == j) or (e_i+1)(e_j+1), exact in double; zero
+// outside the simplex of degree d - 2.
+struct PairTab {
+  int8_t i[VX_KMAX * (VX_KMAX + 1) / 2];
+  int8_t j[VX_KMAX * (VX_KMAX + 1) / 2];
+  int n;
+};
+
+__global__ void k_deriv2(DerivArgs a, int k, PairTab pt, int64_t cube_max, double* __restrict__ olo,
+                         double* __restrict__ ohi) {
+  round_up_mode();
+  const int p = blockIdx.y / pt.n, t = blockIdx.y % pt.n;
+  const int ai = pt.i[t], aj = pt.j[t];
+  const int side = a.side[p], d = a.d[p];
+  int64_t total = 1;
+  for (int j = 0; j < k; j++) total *= side;
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= total) return;
+  int64_t q = f, stride = 1, shift = 0;
+  int deg = 0, ei = 0, ej = 0;
+  for (int j = k - 1; j >= 0; j--) {
+    const int e = (int)(q % side);
+    q /= side;
+    deg += e;
+    if (j == ai) {
+      ei = e;
+      shift += stride;
+    }
+    if (j == aj) {
+      ej = e;
+      shift += stride;
+    }
+    stride *= side;
+  }
+  double* lo = olo + (int64_t)blockIdx.y * cube_max;
+  double* hi = ohi + (int64_t)blockIdx.y * cube_max;
+  if (deg + 2 > d || ei + (ai == aj ? 2 : 1) >= side || ej + 1 >= side) {
+    lo[f] = 0.0;
+    hi[f] = 0.0;
+    return;
+  }
+  const double m = ai == aj ? (double)((ei + 1) * (ei + 2) / 2) : (double)((ei + 1) * (ej + 1));
+  const int64_t src = f + shift;
+  const double cl = a.clo[p][src];
+  const double ch = a.chi[p] ? a.chi[p][src] : cl;
+  lo[f] = -opaque(m * opaque(-cl));  // RD(m * cl) = -RU(m * -cl)
+  hi[f] = m * ch;
 }
 
 // Labels of every leaf on every axis: walk up the CSF by binary search.
@@ -142,16 +202,99 @@ __global__ void k_mv_combine(int k, int np, int64_t nleaf, GridSet gs, const int
   if (keep && excl) keep[b] = 0;
 }
 
+// Range of x^2 over X = [lo, hi] held as (nlo, hi): [RD(lo^2), RU(hi^2)] when
+// lo >= 0, [RD(hi^2), RU(lo^2)] when hi <= 0, else [0, RU(max(lo^2, hi^2))].
+__device__ __forceinline__ void interval_square(double xnl, double xh, double& snl, double& sh) {
+  if (xnl <= 0.0) {         // lo >= 0
+    snl = xnl * opaque(-xnl);  // RU(-lo^2)
+    sh = xh * xh;
+  } else if (xh <= 0.0) {
+    snl = xh * opaque(-xh);    // RU(-hi^2)
+    sh = xnl * xnl;            // RU(lo^2)
+  } else {
+    snl = 0.0;
+    sh = fmax(xnl * xnl, xh * xh);
+  }
+}
+
+// T2(F_p, B) for every leaf and polynomial; keep (if given) is AND-ed with
+// "0 in T2(F_p, B) for every p" (NaN endpoints never exclude).  Layouts:
+// fc (np x nleaf), dc ((p, i) x nleaf), h ((p, pair) x nleaf).
+__global__ void k_t2_combine(int k, int np, int64_t nleaf, GridSet gs, const int32_t* __restrict__ labels,
+                             const double* __restrict__ fc_lo, const double* __restrict__ fc_hi,
+                             const double* __restrict__ dc_lo, const double* __restrict__ dc_hi,
+                             const double* __restrict__ h_lo, const double* __restrict__ h_hi,
+                             double* __restrict__ lo, double* __restrict__ hi, uint8_t* __restrict__ keep) {
+  round_up_mode();
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  double wnl[VX_KMAX], wh[VX_KMAX];
+  CellOps W[VX_KMAX];
+  for (int i = 0; i < k; i++) {
+    double inl, ih, cnl, ch;
+    const int32_t lab = labels[b * k + i];
+    cell(gs.cell[i], lab, inl, ih);
+    cell(gs.centre[i], lab, cnl, ch);
+    wnl[i] = ch + inl;  // -RD(lo_i - chi_i) = RU(chi_i - lo_i)
+    wh[i] = ih + cnl;   // RU(hi_i - clo_i)
+    W[i] = cell_ops(wnl[i], wh[i], CLS_STRADDLE);
+  }
+  const int npair = k * (k + 1) / 2;
+  bool excl = false;
+  for (int p = 0; p < np; p++) {
+    double anl = -opaque(fc_lo[(int64_t)p * nleaf + b]);
+    double ah = fc_hi[(int64_t)p * nleaf + b];
+    for (int i = 0; i < k; i++) {
+      const int64_t di = ((int64_t)p * k + i) * nleaf + b;
+      double dnl = -opaque(dc_lo[di]);
+      double dh = dc_hi[di];
+      step_gen(dnl, dh, W[i], anl, ah);  // Dc_i * W_i + acc
+      anl = dnl;
+      ah = dh;
+    }
+    int t = 0;
+    for (int i = 0; i < k; i++)
+      for (int j = i; j < k; j++, t++) {
+        double xnl, xh;
+        if (i == j) {
+          interval_square(wnl[i], wh[i], xnl, xh);
+        } else {
+          xnl = wnl[i];
+          xh = wh[i];
+          step_gen(xnl, xh, W[j], 0.0, 0.0);  // W_i * W_j (+ 0: exact)
+        }
+        const CellOps X = cell_ops(xnl, xh, CLS_STRADDLE);
+        const int64_t hi_ = ((int64_t)p * npair + t) * nleaf + b;
+        double hnl = -opaque(h_lo[hi_]);
+        double hh = h_hi[hi_];
+        step_gen(hnl, hh, X, anl, ah);  // H_t * X_t + acc
+        anl = hnl;
+        ah = hh;
+      }
+    const double l = -opaque(anl);
+    lo[(int64_t)p * nleaf + b] = l;
+    hi[(int64_t)p * nleaf + b] = ah;
+    excl = excl || (l > 0.0) || (ah < 0.0);
+  }
+  if (keep && excl) keep[b] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 struct MvPolys {
-  std::vector<vx_poly> dp;  // derivative polynomials, (p, axis) order
+  int order = 1;
+  std::vector<vx_poly> dp;  // first-derivative polynomials, (p, axis) order
+  std::vector<vx_poly> hp;  // order 2: H_ij polynomials, (p, pair) order
   int64_t cube_max = 1;
 };
 
-static MvPolys mv_polys(const vx_poly* P, int np, double* dlo, double* dhi) {
+static int npairs(int k) { return k * (k + 1) / 2; }
+
+// Coefficient cube pointers are null when only sizes are wanted.
+static MvPolys mv_polys(const vx_poly* P, int np, int order, double* dlo, double* dhi, double* hlo, double* hhi) {
   MvPolys M;
+  M.order = order;
   const int k = P[0].k;
   for (int p = 0; p < np; p++) {
     int64_t cube = 1;
@@ -170,11 +313,23 @@ static MvPolys mv_polys(const vx_poly* P, int np, double* dlo, double* dhi) {
       q.c_hi = dhi ? dhi + slot * M.cube_max : nullptr;
       M.dp.push_back(q);
     }
+  if (order == 2)
+    for (int p = 0; p < np; p++)
+      for (int t = 0; t < npairs(k); t++) {
+        vx_poly q;
+        memset(&q, 0, sizeof q);
+        q.k = k;
+        q.degree = P[p].degree > 1 ? P[p].degree - 2 : 0;
+        q.side = P[p].side;
+        const int64_t slot = (int64_t)p * npairs(k) + t;
+        q.c_lo = hlo ? hlo + slot * M.cube_max : nullptr;
+        q.c_hi = hhi ? hhi + slot * M.cube_max : nullptr;
+        M.hp.push_back(q);
+      }
   return M;
 }
 
-static int launch_deriv(const vx_poly* P, int np, const MvPolys& M, double* dlo, double* dhi, hipStream_t st) {
-  const int k = P[0].k;
+static DerivArgs deriv_args(const vx_poly* P, int np) {
   DerivArgs a;
   memset(&a, 0, sizeof a);
   for (int p = 0; p < np; p++) {
@@ -183,60 +338,107 @@ static int launch_deriv(const vx_poly* P, int np, const MvPolys& M, double* dlo,
     a.d[p] = P[p].degree;
     a.side[p] = P[p].side;
   }
-  hipLaunchKernelGGL(k_deriv, dim3((unsigned)((M.cube_max + 255) / 256), (unsigned)(np * k)), dim3(256), 0, st, a,
-                     k, M.cube_max, dlo, dhi);
+  return a;
+}
+
+static int launch_deriv(const vx_poly* P, int np, const MvPolys& M, double* dlo, double* dhi, hipStream_t st) {
+  const int k = P[0].k;
+  hipLaunchKernelGGL(k_deriv, dim3((unsigned)((M.cube_max + 255) / 256), (unsigned)(np * k)), dim3(256), 0, st,
+                     deriv_args(P, np), k, M.cube_max, dlo, dhi);
   VX_CHECK_LAUNCH("k_deriv");
   return VX_OK;
 }
 
-// Per-run state of the mean-value test: derivative coefficient cubes and the
+static int launch_deriv2(const vx_poly* P, int np, const MvPolys& M, double* hlo, double* hhi, hipStream_t st) {
+  const int k = P[0].k;
+  PairTab pt;
+  memset(&pt, 0, sizeof pt);
+  for (int i = 0; i < k; i++)
+    for (int j = i; j < k; j++, pt.n++) {
+      pt.i[pt.n] = (int8_t)i;
+      pt.j[pt.n] = (int8_t)j;
+    }
+  hipLaunchKernelGGL(k_deriv2, dim3((unsigned)((M.cube_max + 255) / 256), (unsigned)(np * pt.n)), dim3(256), 0,
+                     st, deriv_args(P, np), k, pt, M.cube_max, hlo, hhi);
+  VX_CHECK_LAUNCH("k_deriv2");
+  return VX_OK;
+}
+
+// Per-run state of a Taylor test: derivative coefficient cubes and the
 // prepared tables of F and of its derivatives (built once).
 struct MvRun {
   MvPolys M;
-  Prepared QF, QD;
+  Prepared QF, QD, QH;
   double* dlo = nullptr;
   double* dhi = nullptr;
+  double* hlo = nullptr;
+  double* hhi = nullptr;
 };
 
-static size_t mv_run_bytes(const vx_poly* P, int np) {
-  MvPolys M = mv_polys(P, np, nullptr, nullptr);
-  const size_t cubes = ((sizeof(double) * (size_t)M.cube_max * np * P[0].k + 255) / 256 * 256) * 2;
-  return cubes + prepared_bytes(P, np) + prepared_bytes(M.dp.data(), (int)M.dp.size()) + 1024;
+static size_t cubes_bytes(const MvPolys& M, int64_t count) {
+  return (sizeof(double) * (size_t)M.cube_max * count + 255) / 256 * 256;
 }
 
-static int mv_run_prepare(const vx_poly* P, int np, char* ws, size_t bytes, MvRun& R, hipStream_t st) {
+static size_t mv_run_bytes(const vx_poly* P, int np, int order) {
+  MvPolys M = mv_polys(P, np, order, nullptr, nullptr, nullptr, nullptr);
   const int k = P[0].k;
-  MvPolys M0 = mv_polys(P, np, nullptr, nullptr);
-  const size_t cube_bytes = (sizeof(double) * (size_t)M0.cube_max * np * k + 255) / 256 * 256;
+  size_t b = cubes_bytes(M, (int64_t)np * k) * 2 + prepared_bytes(P, np) + prepared_bytes(M.dp.data(), (int)M.dp.size());
+  if (order == 2) b += cubes_bytes(M, (int64_t)np * npairs(k)) * 2 + prepared_bytes(M.hp.data(), (int)M.hp.size());
+  return b + 2048;
+}
+
+static int mv_run_prepare(const vx_poly* P, int np, int order, char* ws, size_t bytes, MvRun& R, hipStream_t st) {
+  const int k = P[0].k;
+  MvPolys M0 = mv_polys(P, np, order, nullptr, nullptr, nullptr, nullptr);
+  const size_t cd = cubes_bytes(M0, (int64_t)np * k);
+  const size_t ch = order == 2 ? cubes_bytes(M0, (int64_t)np * npairs(k)) : 0;
   R.dlo = reinterpret_cast<double*>(ws);
-  R.dhi = reinterpret_cast<double*>(ws + cube_bytes);
-  R.M = mv_polys(P, np, R.dlo, R.dhi);
-  char* at = ws + 2 * cube_bytes;
+  R.dhi = reinterpret_cast<double*>(ws + cd);
+  R.hlo = order == 2 ? reinterpret_cast<double*>(ws + 2 * cd) : nullptr;
+  R.hhi = order == 2 ? reinterpret_cast<double*>(ws + 2 * cd + ch) : nullptr;
+  R.M = mv_polys(P, np, order, R.dlo, R.dhi, R.hlo, R.hhi);
+  char* at = ws + 2 * cd + 2 * ch;
   const size_t qf = (prepared_bytes(P, np) + 255) / 256 * 256;
   const size_t qd = (prepared_bytes(R.M.dp.data(), (int)R.M.dp.size()) + 255) / 256 * 256;
-  if (2 * cube_bytes + qf + qd > bytes) VX_FAIL(VX_ECAPACITY, "mean-value test: workspace too small");
+  const size_t qh = order == 2 ? (prepared_bytes(R.M.hp.data(), (int)R.M.hp.size()) + 255) / 256 * 256 : 0;
+  if (2 * cd + 2 * ch + qf + qd + qh > bytes) VX_FAIL(VX_ECAPACITY, "Taylor test: workspace too small");
   int rc;
   if ((rc = launch_deriv(P, np, R.M, R.dlo, R.dhi, st))) return rc;
+  if (order == 2 && (rc = launch_deriv2(P, np, R.M, R.hlo, R.hhi, st))) return rc;
   if ((rc = prepare_polys(P, np, at, qf, &R.QF, st))) return rc;
   if ((rc = prepare_polys(R.M.dp.data(), (int)R.M.dp.size(), at + qf, qd, &R.QD, st))) return rc;
+  if (order == 2 && (rc = prepare_polys(R.M.hp.data(), (int)R.M.hp.size(), at + qf + qd, qh, &R.QH, st))) return rc;
   return VX_OK;
+}
+
+static size_t mv_scratch_bytes(const vx_poly* P, int np, const MvPolys& M, const vx_csf* S) {
+  size_t e = eval_level_bytes(P, np, S);
+  const size_t ed = eval_level_bytes(M.dp.data(), (int)M.dp.size(), S);
+  e = ed > e ? ed : e;
+  if (M.order == 2) {
+    const size_t eh = eval_level_bytes(M.hp.data(), (int)M.hp.size(), S);
+    e = eh > e ? eh : e;
+  }
+  return e;
 }
 
 static size_t mv_level_bytes(const vx_poly* P, int np, const MvPolys& M, const vx_csf* S) {
   const int k = S->k;
   const int64_t nl = S->n[k - 1];
   auto r = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t ef = eval_level_bytes(P, np, S), ed = eval_level_bytes(M.dp.data(), (int)M.dp.size(), S);
-  return r(sizeof(double) * np * nl) * 2 + r(sizeof(double) * np * k * nl) * 2 + r(sizeof(int32_t) * k * nl) +
-         (ef > ed ? ef : ed) + 256;
+  size_t b = r(sizeof(double) * np * nl) * 2 + r(sizeof(double) * np * k * nl) * 2 + r(sizeof(int32_t) * k * nl) +
+             mv_scratch_bytes(P, np, M, S) + 256;
+  if (M.order == 2) b += r(sizeof(double) * np * npairs(k) * nl) * 2;
+  return b;
 }
 
-// One level: mean-value enclosures lo/hi (np x nleaf) and keep AND-ed.
+// One level: Taylor enclosures lo/hi (np x nleaf) and keep AND-ed.
 static int mv_level(const vx_poly* P, int np, const MvRun& R, const vx_csf* S, const double* dom, double* lo,
                     double* hi, uint8_t* keep, char* ws, size_t bytes, hipStream_t st) {
   const int k = S->k;
   const int64_t nl = S->n[k - 1];
   if (nl == 0) return VX_OK;
+  const bool t2 = R.M.order == 2;
   Arena A;
   A.base = ws;
   A.size = bytes;
@@ -244,15 +446,20 @@ static int mv_level(const vx_poly* P, int np, const MvRun& R, const vx_csf* S, c
   double* fch = A.take<double>((size_t)np * nl);
   double* dl = A.take<double>((size_t)np * k * nl);
   double* dh = A.take<double>((size_t)np * k * nl);
+  double* hl = t2 ? A.take<double>((size_t)np * npairs(k) * nl) : nullptr;
+  double* hh = t2 ? A.take<double>((size_t)np * npairs(k) * nl) : nullptr;
   int32_t* labels = A.take<int32_t>((size_t)k * nl);
-  const size_t ef = eval_level_bytes(P, np, S), ed = eval_level_bytes(R.M.dp.data(), (int)R.M.dp.size(), S);
-  char* scratch = A.take<char>(ef > ed ? ef : ed);
-  if (A.overflow) VX_FAIL(VX_ECAPACITY, "mean-value test: workspace of %zu bytes is too small", bytes);
-  const size_t sb = ef > ed ? ef : ed;
-  const int pr = prof_start("mean_value", (double)nl, st);
+  const size_t sb = mv_scratch_bytes(P, np, R.M, S);
+  char* scratch = A.take<char>(sb);
+  if (A.overflow) VX_FAIL(VX_ECAPACITY, "Taylor test: workspace of %zu bytes is too small", bytes);
+  const int pr = prof_start(t2 ? "taylor2" : "mean_value", (double)nl, st);
   int rc;
+  // F at the centres; the gradient on the boxes (order 1) or at the centres
+  // (order 2); the second-order coefficient polynomials on the boxes
   if ((rc = eval_level_prepared(R.QF, S, dom, fcl, fch, nullptr, scratch, sb, st, P, 1))) return rc;
-  if ((rc = eval_level_prepared(R.QD, S, dom, dl, dh, nullptr, scratch, sb, st, R.M.dp.data(), 0))) return rc;
+  if ((rc = eval_level_prepared(R.QD, S, dom, dl, dh, nullptr, scratch, sb, st, R.M.dp.data(), t2 ? 1 : 0)))
+    return rc;
+  if (t2 && (rc = eval_level_prepared(R.QH, S, dom, hl, hh, nullptr, scratch, sb, st, R.M.hp.data(), 0))) return rc;
   CsfView cv;
   memset(&cv, 0, sizeof cv);
   for (int l = 0; l < k; l++) {
@@ -277,34 +484,43 @@ static int mv_level(const vx_poly* P, int np, const MvRun& R, const vx_csf* S, c
     g.centre = 1;
     gs.centre[i] = g;
   }
-  hipLaunchKernelGGL(k_mv_combine, dim3(nb), dim3(256), 0, st, k, np, nl, gs, (const int32_t*)labels,
-                     (const double*)fcl, (const double*)fch, (const double*)dl, (const double*)dh, lo, hi, keep);
-  VX_CHECK_LAUNCH("k_mv_combine");
+  if (t2) {
+    hipLaunchKernelGGL(k_t2_combine, dim3(nb), dim3(256), 0, st, k, np, nl, gs, (const int32_t*)labels,
+                       (const double*)fcl, (const double*)fch, (const double*)dl, (const double*)dh,
+                       (const double*)hl, (const double*)hh, lo, hi, keep);
+    VX_CHECK_LAUNCH("k_t2_combine");
+  } else {
+    hipLaunchKernelGGL(k_mv_combine, dim3(nb), dim3(256), 0, st, k, np, nl, gs, (const int32_t*)labels,
+                       (const double*)fcl, (const double*)fch, (const double*)dl, (const double*)dh, lo, hi, keep);
+    VX_CHECK_LAUNCH("k_mv_combine");
+  }
   prof_stop(pr, st);
   return VX_OK;
 }
 
-size_t mv_workspace_bytes(const vx_poly* P, int np, const vx_csf* S) {
-  MvPolys M = mv_polys(P, np, nullptr, nullptr);
-  return mv_run_bytes(P, np) + mv_level_bytes(P, np, M, S) + 512;
+size_t mv_workspace_bytes(const vx_poly* P, int np, const vx_csf* S, int order) {
+  MvPolys M = mv_polys(P, np, order, nullptr, nullptr, nullptr, nullptr);
+  return mv_run_bytes(P, np, order) + mv_level_bytes(P, np, M, S) + 512;
 }
 
 int mv_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
-            void* ws, size_t ws_bytes, hipStream_t st) {
+            void* ws, size_t ws_bytes, hipStream_t st, int order) {
   if (S->n[S->k - 1] == 0) return VX_OK;
-  const size_t rb = (mv_run_bytes(P, np) + 255) / 256 * 256;
-  if (rb > ws_bytes) VX_FAIL(VX_ECAPACITY, "mean_value_exclusion: workspace too small");
+  const size_t rb = (mv_run_bytes(P, np, order) + 255) / 256 * 256;
+  if (rb > ws_bytes) VX_FAIL(VX_ECAPACITY, "Taylor test: workspace too small");
   MvRun R;
   int rc;
-  if ((rc = mv_run_prepare(P, np, reinterpret_cast<char*>(ws), rb, R, st))) return rc;
+  if ((rc = mv_run_prepare(P, np, order, reinterpret_cast<char*>(ws), rb, R, st))) return rc;
   return mv_level(P, np, R, S, dom, lo, hi, keep, reinterpret_cast<char*>(ws) + rb, ws_bytes - rb, st);
 }
 
 // Run-level interface for run_subdivision: the tables are built once.
-size_t mv_run_workspace(const vx_poly* P, int np) { return (mv_run_bytes(P, np) + 255) / 256 * 256; }
+size_t mv_run_workspace(const vx_poly* P, int np, int order) {
+  return (mv_run_bytes(P, np, order) + 255) / 256 * 256;
+}
 
-size_t mv_level_workspace(const vx_poly* P, int np, const vx_csf* S) {
-  MvPolys M = mv_polys(P, np, nullptr, nullptr);
+size_t mv_level_workspace(const vx_poly* P, int np, const vx_csf* S, int order) {
+  MvPolys M = mv_polys(P, np, order, nullptr, nullptr, nullptr, nullptr);
   return mv_level_bytes(P, np, M, S);
 }
 
@@ -312,9 +528,9 @@ struct MvRunHandle {
   MvRun R;
 };
 
-void* mv_run_begin(const vx_poly* P, int np, void* ws, size_t bytes, hipStream_t st, int* rc) {
+void* mv_run_begin(const vx_poly* P, int np, void* ws, size_t bytes, hipStream_t st, int* rc, int order) {
   MvRunHandle* h = new MvRunHandle;
-  *rc = mv_run_prepare(P, np, reinterpret_cast<char*>(ws), bytes, h->R, st);
+  *rc = mv_run_prepare(P, np, order, reinterpret_cast<char*>(ws), bytes, h->R, st);
   if (*rc) {
     delete h;
     return nullptr;

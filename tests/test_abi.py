@@ -68,3 +68,26 @@ def test_misaligned_workspace_is_rejected_before_any_work():
     dom = (C.c_double * 2)(-1.0, 1.0)
     rc = L.interval_eval_level(parr, 1, C.byref(s), dom, None, None, None, C.c_void_p(4096 + 8), 1 << 20, None)
     assert rc == b.VX_EINVAL and b"aligned" in L.vx_last_error()
+
+
+def test_taylor_arguments_are_checked_before_any_work():
+    """Order outside {1, 2} and the two exclusive run flags are VX_EINVAL."""
+    import ctypes as C
+    from paper_2406_09857_amd import binding as b
+    L = b.lib()
+    s = b.vx_csf()
+    s.k = 1
+    s.level = 0
+    s.n[0] = 0
+    s.cap[0] = 1
+    s.idx[0] = 256  # never dereferenced
+    parr = (b.vx_poly * 1)()
+    parr[0].k, parr[0].degree, parr[0].side = 1, 1, 2
+    parr[0].c_lo = 4096  # never dereferenced
+    dom = (C.c_double * 2)(-1.0, 1.0)
+    rc = L.taylor_exclusion(parr, 1, C.byref(s), dom, 3, None, None, None, C.c_void_p(4096), 1 << 20, None)
+    assert rc == b.VX_EINVAL and b"order 3" in L.vx_last_error()
+    rc = L.run_subdivision_ex(parr, 1, dom, 2, b.VX_RUN_MEAN_VALUE | b.VX_RUN_TAYLOR2, C.c_void_p(4096), 1 << 20,
+                              None, None, b.LEVEL_CB(), None, None)
+    assert rc == b.VX_EINVAL and b"exclusive" in L.vx_last_error()
+    assert b.workspace_bytes(b.VX_WS_TAYLOR2) == 0  # invalid arguments give 0

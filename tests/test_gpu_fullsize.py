@@ -126,3 +126,47 @@ def test_curve_mean_value_sampled_every_level(vx):
              f"({int(keep_o.sum())} kept), oracle {time.time() - t:.1f} s")
         prev_children = orc.children_of(B[keep])
     assert not got
+
+
+@pytest.mark.timeout(900)
+def test_curve_taylor2_sampled_every_level(vx):
+    """The curve with the order-2 Taylor test on (Sec. 3.2, Taylor form with
+    m = 2, AND-ed with C0): every level's CSF is the children of the previous
+    kept set, the kept CSF the flagged boxes, and a seeded sample of boxes per
+    level is re-evaluated by the oracle (C0 and order-2 enclosures, combined
+    flag) on a CSF of the sample alone."""
+    w = synth.curve()
+    dom = w.domain()
+    got = {}
+
+    def rec(level, S, lo, hi, keep, K):
+        got[level] = (S, lo, hi, keep.astype(bool), K)
+        return False
+
+    t = time.time()
+    stats, _ = vx.run_subdivision(w.polys, dom, w.depth, record=rec, taylor2=True)
+    _say(f"[full] curve taylor2: GPU run with per-level copies {time.time() - t:.1f} s")
+    rng = np.random.default_rng(2407)
+    prev_children = np.zeros((1, w.k), np.int64)
+    for level in range(w.depth + 1):
+        S, lo, hi, keep, K = got.pop(level)
+        tag = f"curve taylor2 level {level}"
+        B = _boxes_of(S)
+        assert csf_equal(S, orc.csf_from_boxes(prev_children, level)), tag
+        assert csf_equal(K, orc.csf_from_boxes(B[keep], level)), tag
+        assert stats[level]["n"] == [len(a) for a in S["idx"]], tag
+        n = len(B)
+        pick = np.sort(rng.choice(n, size=min(n, 192), replace=False))
+        T = orc.csf_from_boxes(B[pick], level)
+        assert np.array_equal(T["boxes"], B[pick]), tag
+        t = time.time()
+        lo_o, hi_o, _ = orc.eval_level(w.polys, T, dom, nthreads=orc.max_threads())
+        tlo, thi = orc.taylor2_level(w.polys, T, dom, nthreads=orc.max_threads())
+        keep_o = orc.keep_mask(lo_o, hi_o) & orc.keep_mask(tlo, thi)
+        assert bits_equal(lo[:, pick], lo_o), (tag, "lo", first_mismatch(lo[:, pick], lo_o))
+        assert bits_equal(hi[:, pick], hi_o), (tag, "hi", first_mismatch(hi[:, pick], hi_o))
+        assert np.array_equal(keep[pick], keep_o), tag
+        _say(f"[full] {tag}: {n} boxes, {int(keep.sum())} kept, sample {len(pick)} "
+             f"({int(keep_o.sum())} kept), oracle {time.time() - t:.1f} s")
+        prev_children = orc.children_of(B[keep])
+    assert not got
