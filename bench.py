@@ -247,9 +247,8 @@ def main():
     ws = torch.empty(6 << 30, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
 
-    stats = None
     for _ in range(args.warmup):
-        stats, _ = vx.run_subdivision(polys, dom, w.depth, ws=ws, want_kept=False)
+        vx.run_subdivision(polys, dom, w.depth, ws=ws, want_kept=False, level_times=False)
     torch.cuda.synchronize()
     # Every kernel timed over one untimed step (event records between all
     # launches slow the level loop down); it picks the dominant kernel, whose
@@ -264,13 +263,18 @@ def main():
     torch.cuda.synchronize()
     if dom_name:
         vx.profile_begin(only=dom_name)
+    # The timed steps record no per-level events (each one is a packet the
+    # stream passes between kernels); one more run, untimed, records them for
+    # the per-level table.
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        stats, _ = vx.run_subdivision(polys, dom, w.depth, ws=ws, want_kept=False)
+        vx.run_subdivision(polys, dom, w.depth, ws=ws, want_kept=False, level_times=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = vx.profile_end() if dom_name else {}
     ms_step = (t1 - t0) * 1e3 / args.steps
+    stats, _ = vx.run_subdivision(polys, dom, w.depth, ws=ws, want_kept=False)
+    torch.cuda.synchronize()
 
     evals = sum(len(polys) * s["n"][w.k - 1] for s in stats)
     steps_total = sum(s["steps"] for s in stats)
@@ -322,6 +326,8 @@ def main():
         "roofline": roof,
         "kernels_note": "every kernel, HIP-event timed over one untimed step before the timed region",
         "kernels": kernels,
+        "levels_note": "per-level eval/filter times from one untimed run with level timing events; "
+                       "the timed steps record none",
         "levels": levels,
     }
     if not args.no_extras and args.workload == "curve":

@@ -220,8 +220,10 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
  * only when both tests keep it (eval_ms then includes both; the callback
  * still receives the C0 enclosures and the combined keep flags).
  * VX_RUN_TAYLOR2 adds the order-2 Taylor test (taylor_exclusion, order 2) in
- * the same way; the two flags are exclusive (VX_EINVAL). */
-enum { VX_RUN_MEAN_VALUE = 1, VX_RUN_TAYLOR2 = 2 };
+ * the same way; the two flags are exclusive (VX_EINVAL).  VX_RUN_NO_TIMES
+ * records no per-level timing events (stats eval_ms and filter_ms are 0):
+ * each event is a packet the stream must pass between the level's kernels. */
+enum { VX_RUN_MEAN_VALUE = 1, VX_RUN_TAYLOR2 = 2, VX_RUN_NO_TIMES = 4 };
 int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
                        size_t ws_bytes, size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user,
                        void* stream);

@@ -24,7 +24,7 @@ KMAX = 4
 
 VX_OK, VX_EINVAL, VX_ECAPACITY, VX_EHIP, VX_EOVERFLOW, VX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD, VX_WS_MEANVALUE, VX_WS_TAYLOR2 = 0, 1, 2, 3, 4, 5
-VX_RUN_MEAN_VALUE, VX_RUN_TAYLOR2 = 1, 2
+VX_RUN_MEAN_VALUE, VX_RUN_TAYLOR2, VX_RUN_NO_TIMES = 1, 2, 4
 
 
 class VxError(RuntimeError):
@@ -306,10 +306,12 @@ def root_csf(k: int, device=None) -> CSF:
 
 def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None,
                     ws: torch.Tensor | None = None, want_kept: bool = True, mean_value: bool = False,
-                    taylor2: bool = False):
+                    taylor2: bool = False, level_times: bool = True):
     """Algorithm 3 with C0 to `depth`.  Returns (stats, kept) where stats is a
     list of per-level dicts and kept the final level's kept CSF (host numpy).
-    ``mean_value`` / ``taylor2`` add the Taylor test of order 1 / 2 to C0.
+    ``mean_value`` / ``taylor2`` add the Taylor test of order 1 / 2 to C0;
+    ``level_times=False`` records no per-level timing events (eval_ms and
+    filter_ms are then 0).
 
     ``record(level, S, lo, hi, keep, K)`` is called with device-side views
     (numpy copies) when given; it may return True to stop.
@@ -360,7 +362,8 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
         if ws is None or ws.numel() < size:
             ws = _ws(size)
         rc = lib().run_subdivision_ex(parr, len(polys), dom.ctypes.data_as(C.POINTER(C.c_double)), depth,
-                                      (VX_RUN_MEAN_VALUE if mean_value else 0) | (VX_RUN_TAYLOR2 if taylor2 else 0),
+                                      (VX_RUN_MEAN_VALUE if mean_value else 0) | (VX_RUN_TAYLOR2 if taylor2 else 0)
+                                      | (0 if level_times else VX_RUN_NO_TIMES),
                                       ws.data_ptr(), ws.numel(),
                                       C.byref(need), stats, cb, None, _stream(stream))
         if rc == VX_ECAPACITY and need.value > size:

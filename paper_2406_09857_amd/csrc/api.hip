@@ -314,7 +314,8 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   if (depth < 0 || depth > 28) VX_FAIL(VX_EINVAL, "depth %d outside [0, 28]", depth);
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
   if ((rc = check_ws(ws))) return rc;
-  if (flags & ~(VX_RUN_MEAN_VALUE | VX_RUN_TAYLOR2)) VX_FAIL(VX_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(VX_RUN_MEAN_VALUE | VX_RUN_TAYLOR2 | VX_RUN_NO_TIMES)) VX_FAIL(VX_EINVAL, "unknown flags 0x%x", flags);
+  const bool times = stats && !(flags & VX_RUN_NO_TIMES);
   if ((flags & VX_RUN_MEAN_VALUE) && (flags & VX_RUN_TAYLOR2))
     VX_FAIL(VX_EINVAL, "VX_RUN_MEAN_VALUE and VX_RUN_TAYLOR2 are exclusive");
   const int order = (flags & VX_RUN_TAYLOR2) ? 2 : (flags & VX_RUN_MEAN_VALUE) ? 1 : 0;
@@ -348,16 +349,18 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   // Timing events of two consecutive levels: a level's times are read once
   // the next level is queued, so reading them never idles the GPU.
   hipEvent_t evs[6] = {};
-  for (int i = 0; i < 6; i++) VX_HIP(hipEventCreateWithFlags(&evs[i], hipEventDisableSystemFence));  // timing only
+  if (times)
+    for (int i = 0; i < 6; i++) VX_HIP(hipEventCreateWithFlags(&evs[i], hipEventDisableSystemFence));  // timing only
   struct EvGuard {
     hipEvent_t* e;
     ~EvGuard() {
-      for (int i = 0; i < 6; i++) (void)hipEventDestroy(e[i]);
+      for (int i = 0; i < 6; i++)
+        if (e[i]) (void)hipEventDestroy(e[i]);
     }
   } guard{evs};
   int pending = -1;  // level whose event times are still to be read
   auto finish_times = [&]() -> int {
-    if (pending < 0 || !stats) return VX_OK;
+    if (pending < 0 || !times) return VX_OK;
     hipEvent_t* e = evs + 3 * (pending & 1);
     VX_HIP(hipEventSynchronize(e[2]));
     float ms = 0;
@@ -451,19 +454,19 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     if (!last) csf_place(&N, k, level + 1, ncap, next_base);
 
     hipEvent_t* ev = evs + 3 * (level & 1);
-    VX_HIP(hipEventRecord(ev[0], st));
+    if (times) VX_HIP(hipEventRecord(ev[0], st));
     if ((rc = eval_level_prepared(Q, &S, dom, lo, hi, keep, scratch, scratch_bytes, st, P))) return rc;
     if (mv && nleaf > 0) {
       double* mlo = reinterpret_cast<double*>(mid_base + o_mlo);
       double* mhi = reinterpret_cast<double*>(mid_base + o_mhi);
       if ((rc = mv_run_level(mvh, P, np, &S, dom, mlo, mhi, keep, scratch, scratch_bytes, st))) return rc;
     }
-    VX_HIP(hipEventRecord(ev[1], st));
+    if (times) VX_HIP(hipEventRecord(ev[1], st));
     // the filter publishes its counts (and the flag) as soon as they are known
     if ((rc = filter_impl(&S, keep, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st,
                           counts_dev + 2 * VX_KMAX, (int64_t)level + 1)))
       return rc;
-    VX_HIP(hipEventRecord(ev[2], st));
+    if (times) VX_HIP(hipEventRecord(ev[2], st));
     if ((rc = finish_times())) return rc;  // the previous level's times
     if ((rc = wait_for_flag(counts + 2 * VX_KMAX, (int64_t)level + 1, st))) return rc;
     for (int l = 0; l < k; l++) K.n[l] = counts[l];
