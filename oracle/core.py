@@ -16,6 +16,9 @@ Paper: G. Moroz, arXiv 2406.09857.
   * The Taylor form of Sec. 3.2 as an exclusion test: order 1 (the mean-value
     form, ``mean_value_level``, ``subdivide_mv``) and order 2
     (``taylor2_level``, ``subdivide_t2``).
+  * The inclusion criterion C1 of Sec. 3.2 (sign change over the vertices of
+    a box, the vertices evaluated by Algorithm 2 on their grid):
+    ``inclusion_level``.
 """
 from __future__ import annotations
 
@@ -76,6 +79,8 @@ def lib():
         L.orc_deriv.restype = C.c_int
         L.orc_mean_value.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp]
         L.orc_mean_value.restype = C.c_int
+        L.orc_vertex_table.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int64, dp]
+        L.orc_vertex_table.restype = None
         L.orc_deriv2.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, C.c_int, dp, dp]
         L.orc_deriv2.restype = C.c_int
         L.orc_taylor2.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp, dp]
@@ -435,4 +440,55 @@ def subdivide_t2(polys, k: int, depth: int, dom=None, nthreads: int = 1):
                     "kept": K})
         if level < depth:
             boxes = children_of(K)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Inclusion criterion C1 (Sec. 3.2): sign change over the vertices of a box
+# ---------------------------------------------------------------------------
+
+def vertex_table(dlo: float, dhi: float, level: int, n: int | None = None) -> np.ndarray:
+    """(n, 2) enclosures of the grid vertices 0..n-1 (n = 2^level + 1)."""
+    n = (1 << level) + 1 if n is None else n
+    out = np.zeros((n, 2))
+    lib().orc_vertex_table(dlo, dhi, level, n, _dp(out))
+    return out
+
+
+def box_vertices(boxes: np.ndarray) -> np.ndarray:
+    """(n, 2^k, k) vertex indices of each box: i + b for b in {0, 1}^k, b in
+    binary order with the first axis most significant."""
+    boxes = np.asarray(boxes, np.int64)
+    n, k = boxes.shape
+    bits = np.array([[(m >> (k - 1 - j)) & 1 for j in range(k)] for m in range(1 << k)], np.int64)
+    return boxes[:, None, :] + bits[None, :, :]
+
+
+def inclusion_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1, degrees=None):
+    """C1 for every polynomial and box of the CSF: (np, n) booleans, true when
+    some vertex's enclosure is > 0 and another's < 0 (so F vanishes in the box
+    by the intermediate value theorem).  The vertices of all boxes form a set
+    of grid points, evaluated once each by Algorithm 2 on its own CSF."""
+    k, level = csf["k"], csf["level"]
+    dom = np.asarray(dom, np.float64).reshape(k, 2)
+    boxes = np.asarray(csf["boxes"], np.int64)
+    nb = boxes.shape[0]
+    out = np.zeros((len(polys), nb), bool)
+    if nb == 0:
+        return out
+    vt = box_vertices(boxes).reshape(-1, k)
+    V = csf_from_boxes(vt, level + 1)  # vertex labels run to 2^level
+    vtabs = [vertex_table(float(dom[j, 0]), float(dom[j, 1]), level) for j in range(k)]
+    keys = np.zeros(len(V["boxes"]), np.int64)
+    q = np.zeros(len(vt), np.int64)
+    for j in range(k):
+        keys = keys * ((1 << level) + 1) + V["boxes"][:, j]
+        q = q * ((1 << level) + 1) + vt[:, j]
+    where = np.searchsorted(keys, q).reshape(nb, 1 << k)
+    for jp, p in enumerate(polys):
+        d = poly_degree(p) if degrees is None else degrees[jp]
+        vl, vh, _ = eval_csf(p, d, V, vtabs, OUTWARD, nthreads)
+        pos = (vl > 0.0)[where].any(axis=1)
+        neg = (vh < 0.0)[where].any(axis=1)
+        out[jp] = pos & neg
     return out

@@ -26,6 +26,7 @@
  *     comparison), used to pin the amortized routine;
  *   - the mean-value (order-1 Taylor form) enclosure of Sec. 3.2: centre
  *     enclosures, derivative coefficients and the final combination;
+ *   - the grid-vertex enclosures of the inclusion criterion C1 (Sec. 3.2);
  *   - the order-2 Taylor form of Sec. 3.2 (Taylor form definition, m = 2):
  *     second-derivative coefficients (halved on the diagonal) and the
  *     combination F(c) + sum_i dF/dx_i(c) W_i + sum_{i<=j} H_ij(B) W_i W_j,
@@ -373,6 +374,20 @@ void orc_centre(double dlo, double dhi, int level, int64_t label, double* r) {
 
 void orc_centre_table(double dlo, double dhi, int level, int64_t n, double* out) {
   for (int64_t i = 0; i < n; i++) orc_centre(dlo, dhi, level, i, out + 2 * i);
+}
+
+/* Enclosure of grid vertex v (0 <= v <= 2^level), the common endpoint of
+ * cells v - 1 and v: the lower end of cell v and the upper end of cell v - 1
+ * (exact on dyadic domains). */
+void orc_vertex(double dlo, double dhi, int level, int64_t v, double* r) {
+  double a[2], b[2];
+  orc_box(dlo, dhi, level, v, a);
+  orc_box(dlo, dhi, level, v - 1, b);
+  r[0] = a[0]; r[1] = b[1];
+}
+
+void orc_vertex_table(double dlo, double dhi, int level, int64_t n, double* out) {
+  for (int64_t i = 0; i < n; i++) orc_vertex(dlo, dhi, level, i, out + 2 * i);
 }
 
 /* Coefficients of dF/dx_axis: entry e is (e_axis + 1) * c_{e + u_axis},

@@ -682,3 +682,103 @@ def test_taylor2_prunes_more_on_the_surface():
         k0 = {tuple(x) for x in r0["kept"]}
         assert all(tuple(x) in k0 for x in r1["kept"])
     assert len(t2[-1]["kept"]) < len(plain[-1]["kept"])
+
+
+# ---------------------------------------------------------------------------
+# Inclusion criterion C1 (Sec. 3.2): sign change over a box's vertices
+# ---------------------------------------------------------------------------
+
+def test_vertex_table_closed_form():
+    for level in (0, 1, 4, 9):
+        t = orc.vertex_table(-1.0, 1.0, level)
+        want = -1.0 + 2.0 * np.arange((1 << level) + 1) / float(1 << level)
+        assert np.array_equal(t[:, 0], want) and np.array_equal(t[:, 1], want)
+    # non-dyadic domain: vertex v is [lower end of cell v, upper end of cell v-1],
+    # a true enclosure of the exact vertex
+    t = orc.vertex_table(-0.3, 0.7, 5)
+    cells = orc.box_table(-0.3, 0.7, 5)
+    for v in range(33):
+        x = ex.F(-0.3) + (ex.F(0.7) - ex.F(-0.3)) * Fraction(v, 32)
+        assert ex.F(t[v, 0]) <= x <= ex.F(t[v, 1])
+        if v < 32:
+            assert t[v, 0] == cells[v, 0]
+        if v > 0:
+            assert t[v, 1] == cells[v - 1, 1]
+
+
+def test_inclusion_of_a_plane():
+    """F = x3 - c: the vertices' x3 are the box's two x3 endpoints, so C1 holds
+    exactly when lo3 < c < hi3 (c strictly inside); c on a grid plane gives
+    zeros on one face and no certified sign change."""
+    k, level = 3, 4
+    rng = np.random.default_rng(200)
+    boxes = rng.integers(0, 16, size=(300, k))
+    S = orc.csf_from_boxes(boxes, level)
+    for c in (0.3125 + 1.0 / 64, -0.5):  # between grid planes; on a grid plane
+        cube = synth.monomial_poly(k, 1, {(0, 0, 1): 1.0, (0, 0, 0): -c})
+        inc = orc.inclusion_level([cube], S, np.array([-1.0, 1.0] * k))[0]
+        lo3 = -1.0 + S["boxes"][:, 2] / 8.0
+        hi3 = lo3 + 1.0 / 8.0
+        assert np.array_equal(inc, (lo3 < c) & (c < hi3)), c
+        assert inc.any() or c == -0.5
+
+
+def test_inclusion_of_the_sphere_closed_form():
+    """F = sum x_i^2 - 1/2 at dyadic vertices is exact: C1 is 'some vertex
+    outside and some inside the sphere'."""
+    k, level = 3, 3
+    boxes = np.array([[a, b, c] for a in range(8) for b in range(8) for c in range(8)])
+    S = orc.csf_from_boxes(boxes, level)
+    inc = orc.inclusion_level([synth.sphere()], S, np.array([-1.0, 1.0] * k))[0]
+    V = orc.box_vertices(S["boxes"])
+    x = -1.0 + V / 4.0
+    f = (x * x).sum(axis=2) - 0.5
+    assert np.array_equal(inc, (f > 0).any(axis=1) & (f < 0).any(axis=1))
+    assert inc.sum() > 0
+
+
+@pytest.mark.parametrize("k,d,level", [(2, 7, 5), (3, 5, 3)])
+def test_inclusion_sound_and_complete_against_exact_signs(k, d, level):
+    """Soundness: a certified box has exact vertex values of both strict
+    signs.  Completeness up to rounding: exact vertex values of both signs,
+    each at least 1e-9 from 0, are certified."""
+    rng = np.random.default_rng(210 + k)
+    poly = synth.small_random(k, d, seed=211 + k)[0]
+    boxes = rng.integers(0, 1 << level, size=(80, k))
+    S = orc.csf_from_boxes(boxes, level)
+    inc = orc.inclusion_level([poly], S, np.array([-1.0, 1.0] * k))[0]
+    V = orc.box_vertices(S["boxes"])
+    h = Fraction(2, 1 << level)
+    nin = 0
+    for q in range(len(S["boxes"])):
+        vals = [ex.exact_point_value(poly, d, [Fraction(-1) + int(v) * h for v in V[q, m]]) for m in range(1 << k)]
+        pos = any(v > 0 for v in vals)
+        neg = any(v < 0 for v in vals)
+        if inc[q]:
+            assert pos and neg, q
+            nin += 1
+        elif any(v > Fraction(1, 10 ** 9) for v in vals) and any(v < -Fraction(1, 10 ** 9) for v in vals):
+            raise AssertionError(f"box {q}: clear sign change not certified")
+    assert nin > 0
+
+
+def test_inclusion_vertex_values_equal_per_vertex_bruteforce():
+    """The amortized vertex evaluation (Algorithm 2 on the vertex grid) gives
+    the per-vertex brute-force Horner bits, so the flags agree."""
+    k, d, level = 3, 6, 3
+    rng = np.random.default_rng(220)
+    poly = synth.small_random(k, d, seed=221)[0]
+    boxes = rng.integers(0, 1 << level, size=(40, k))
+    S = orc.csf_from_boxes(boxes, level)
+    dom = np.array([-0.7, 1.3, -1.0, 1.0, -2.0, 0.5])
+    inc = orc.inclusion_level([poly], S, dom)[0]
+    vt = [orc.vertex_table(float(dom[2 * j]), float(dom[2 * j + 1]), level) for j in range(k)]
+    V = orc.box_vertices(S["boxes"])
+    for q in range(len(S["boxes"])):
+        pos = neg = False
+        for m in range(1 << k):
+            box = np.array([vt[j][V[q, m, j]] for j in range(k)])
+            lo, hi, _ = orc.eval_box(poly, d, box)
+            pos |= lo > 0.0
+            neg |= hi < 0.0
+        assert inc[q] == (pos and neg), q
