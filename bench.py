@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--cpu-depth", type=int, default=9, help="oracle sample: levels 0..cpu-depth of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, mean-value and order-2 Taylor legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, Taylor-test and inclusion legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -181,6 +181,30 @@ def bench_taylor2(vx, polys, dom, depth, plain_stats, plain_ms, mv_stats):
             "mean_value_kept_per_level": mv_stats,
             "plain_kept_per_level": [s["kept"][2] for s in plain_stats],
             "parity": "enclosures bit-identical to the oracle (tests/test_gpu_taylor2.py)"}
+
+
+def bench_inclusion(vx):
+    """The inclusion criterion C1 on the surface's final kept set (levels 0..9
+    of one trivariate degree-40 polynomial): certified boxes and time."""
+    import torch
+    from paper_2406_09857_amd import synth
+    w = synth.surface()
+    dom = w.domain()
+    _, kept = vx.run_subdivision(w.polys, dom, w.depth)
+    K = vx.CSF.from_arrays(3, w.depth, kept["idx"], kept["ptr"])
+    vx.inclusion_test(w.polys, K, dom)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        incl = vx.inclusion_test(w.polys, K, dom)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"workload": "surface_k3_d40: one trivariate polynomial, total degree 40, N(0,1) coefficients, "
+                        "domain [-1,1]^3, kept boxes of level 9",
+            "boxes": K.nboxes, "certified": int(incl.sum()), "ms": ms,
+            "boxes_per_s": K.nboxes / (ms * 1e-3),
+            "parity": "flags equal to the oracle's (tests/test_gpu_inclusion.py)"}
 
 
 COPY_BYTES = 1 << 31  # bytes read (and written) by the calibration copy
@@ -339,6 +363,7 @@ def main():
         out["mean_value"] = bench_mean_value(vx, polys, dom, w.depth, stats, ms_step)
         out["taylor2"] = bench_taylor2(vx, polys, dom, w.depth, stats, ms_step,
                                        out["mean_value"]["kept_per_level"])
+        out["inclusion"] = bench_inclusion(vx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_depth, w.depth))
     print(json.dumps(out))

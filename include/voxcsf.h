@@ -91,7 +91,15 @@ const char* vx_last_error(void);
 
 /* Workspace sizes.  `which` selects the call; arguments not used by that call
  * may be NULL/0.  Returns 0 on invalid arguments. */
-enum { VX_WS_EVAL = 0, VX_WS_FILTER = 1, VX_WS_BUILD = 2, VX_WS_GRAD = 3, VX_WS_MEANVALUE = 4, VX_WS_TAYLOR2 = 5 };
+enum {
+  VX_WS_EVAL = 0,
+  VX_WS_FILTER = 1,
+  VX_WS_BUILD = 2,
+  VX_WS_GRAD = 3,
+  VX_WS_MEANVALUE = 4,
+  VX_WS_TAYLOR2 = 5,
+  VX_WS_INCLUSION = 6
+};
 size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_csf* S, int64_t n);
 
 /*
@@ -168,6 +176,27 @@ int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const do
  */
 int taylor_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, int32_t order, double* lo,
                      double* hi, uint8_t* keep, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * inclusion_test -- the inclusion criterion C1 of Sec. 3.2 ("Inclusion
+ * Criterion") on every box of S and every polynomial: F_p on the 2^k
+ * vertices of the box, the box certified when one vertex enclosure has a
+ * lower bound > 0 and another an upper bound < 0 (then F_p vanishes in the
+ * box, by the intermediate value theorem).  Vertex v of the 2^level grid on
+ * an axis is enclosed by [lower end of cell v, upper end of cell v-1] (exact
+ * on dyadic domains).  The vertices of all boxes form a subset of the vertex
+ * grid: they are evaluated once each by Algorithm 2 on their own CSF
+ * (built on the device with the csf_build sort), as the paper suggests.
+ *   incl : device uint8, np x S->n[k-1], row p = polynomial p, boxes in CSF
+ *          leaf order; 1 = certified, 0 = not certified.  NaN bounds certify
+ *          nothing.
+ * The call waits for the stream once (the vertex count sizes the
+ * evaluation).  Limits: k * (level + 1) <= 62.  Errors as
+ * interval_eval_level, VX_EUNSUPPORTED beyond the limit; workspace
+ * vx_workspace_bytes(VX_WS_INCLUSION, P, np, S, 0).
+ */
+int inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, void* ws,
+                   size_t ws_bytes, void* stream);
 
 /*
  * filter_subdivide -- exclusion filter and bisection (Algorithm 3): prune S

@@ -177,6 +177,9 @@ size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_
       if (check_csf(S, false) || check_poly(P, np, S->k) || np * taylor_tables(S->k, order) > VX_MAXPOLY) return 0;
       return mv_workspace_bytes(P, np, S, order);
     }
+    case VX_WS_INCLUSION:
+      if (check_csf(S, false) || check_poly(P, np, S->k)) return 0;
+      return inclusion_workspace_bytes(P, np, S);
     case VX_WS_GRAD:
       if (!P || np < 1 || np > PMAX_GRAD || check_poly(P, np, P[0].k)) return 0;
       if (S && check_csf(S, false)) return 0;
@@ -214,6 +217,18 @@ int taylor_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double
 int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo, double* hi,
                          uint8_t* keep, void* ws, size_t ws_bytes, void* stream) {
   return taylor_exclusion(P, np, S, dom, 1, lo, hi, keep, ws, ws_bytes, stream);
+}
+
+int inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, void* ws,
+                   size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_csf(S, true))) return rc;
+  if ((rc = check_poly(P, np, S->k))) return rc;
+  if ((rc = check_dom(dom, S->k))) return rc;
+  if (S->n[S->k - 1] > 0 && !incl) VX_FAIL(VX_EINVAL, "null output flags");
+  if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
+  if ((rc = check_ws(ws))) return rc;
+  return inclusion_impl(P, np, S, dom, incl, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int filter_subdivide(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,

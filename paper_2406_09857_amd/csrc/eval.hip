@@ -1336,8 +1336,11 @@ struct EvalPlan {
 
 static int stage1_blocking(int64_t n0) { return n0 <= 4 ? 1 : n0 <= 16 ? 2 : n0 <= 64 ? 4 : 8; }
 
-// Level workspace (measure with A.base == nullptr).
-static void plan_eval(Arena& A, EvalPlan& E, const vx_poly* P, int np, const vx_csf* S) {
+// Level workspace (measure with A.base == nullptr).  With `bound` the plan
+// takes the largest choices at every depth (one node per segment, tail lists
+// planned): its size is then monotone in the node counts, so a plan for upper
+// bounds of the counts covers every smaller level.
+static void plan_eval(Arena& A, EvalPlan& E, const vx_poly* P, int np, const vx_csf* S, bool bound = false) {
   const int k = S->k;
   E.k = k;
   for (int l = 0; l + 1 < k; l++) {
@@ -1357,8 +1360,8 @@ static void plan_eval(Arena& A, EvalPlan& E, const vx_poly* P, int np, const vx_
   for (int l = 0; l < k; l++) nmax = S->n[l] > nmax ? S->n[l] : nmax;
   for (int l = 0; l < k; l++) {
     const int64_t nparent = l == 0 ? 1 : S->n[l - 1];
-    const int Z = l == k - 1 ? (S->n[k - 1] <= LEAF_ONE_NODES ? 1 : LEAF_R) : (l == 0 ? E.R : 64);
-    const int pack = k == 3 && l == 1 && S->n[1] >= PACK_MIN_NODES && nmax > SMALL_LEVEL_NODES;
+    const int Z = bound ? 1 : l == k - 1 ? (S->n[k - 1] <= LEAF_ONE_NODES ? 1 : LEAF_R) : (l == 0 ? E.R : 64);
+    const int pack = k == 3 && l == 1 && (bound || (S->n[1] >= PACK_MIN_NODES && nmax > SMALL_LEVEL_NODES));
     plan_segments(A, E.seg[l], nparent, S->n[l], Z, pack);
   }
 }
@@ -1374,6 +1377,13 @@ size_t eval_level_bytes(const vx_poly* P, int np, const vx_csf* S) {
   Arena A;
   EvalPlan E;
   plan_eval(A, E, P, np, S);
+  return A.off + 256;
+}
+
+size_t eval_level_bytes_bound(const vx_poly* P, int np, const vx_csf* S) {
+  Arena A;
+  EvalPlan E;
+  plan_eval(A, E, P, np, S, true);
   return A.off + 256;
 }
 

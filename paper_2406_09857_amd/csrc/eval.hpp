@@ -23,6 +23,8 @@ struct Prepared {
 size_t prepared_bytes(const vx_poly* P, int np);
 int prepare_polys(const vx_poly* P, int np, void* ws, size_t ws_bytes, Prepared* out, hipStream_t st);
 size_t eval_level_bytes(const vx_poly* P, int np, const vx_csf* S);
+// Covers eval_level_bytes of every CSF whose node counts are <= S->n.
+size_t eval_level_bytes_bound(const vx_poly* P, int np, const vx_csf* S);
 // centre = 1 evaluates at the cell centres (degenerate boxes) instead of the cells.
 int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
                         void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P, int centre = 0);
@@ -55,6 +57,11 @@ void* mv_run_begin(const vx_poly* P, int np, void* ws, size_t bytes, hipStream_t
 int mv_run_level(void* handle, const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi,
                  uint8_t* keep, void* ws, size_t bytes, hipStream_t st);
 void mv_run_end(void* handle);
+
+// Inclusion criterion C1 (meanvalue.hip).
+size_t inclusion_workspace_bytes(const vx_poly* P, int np, const vx_csf* S);
+int inclusion_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, uint8_t* incl, void* ws,
+                   size_t ws_bytes, hipStream_t st);
 
 size_t batch_workspace_bytes(const vx_poly* P, int nsys, int depth, const int64_t* cap);
 int batch_create_impl(const vx_poly* P, int nsys, const double* dom, int depth, const int64_t* cap,

@@ -55,19 +55,25 @@ enum : int { CLS_POS = 0, CLS_NEG = 1, CLS_STRADDLE = 2 };
 // With centre = 1 the "cell" is the degenerate box of the cell's centre, the
 // common endpoint of cells 2*label and 2*label+1 at level+1: its lower bound is
 // the lower end of cell 2*label+1, its upper bound the upper end of cell
-// 2*label (the centre enclosures of the mean-value form).
+// 2*label (the centre enclosures of the Taylor forms).  With centre = 2 it is
+// grid vertex `label` (0 .. 2^level), the common endpoint of cells label-1 and
+// label: the lower end of cell label and the upper end of cell label-1 (the
+// vertex enclosures of the inclusion criterion).
 struct AxisGrid {
   double dlo, ndlo, dhi, ndhi;  // domain endpoints and their negations (host-negated)
   int level;
-  int centre;                   // 0: cells, 1: cell centres
+  int centre;                   // 0: cells, 1: cell centres, 2: grid vertices
 };
 
 __device__ __forceinline__ void cell(const AxisGrid& g, int32_t label, double& nlo, double& hi) {
   const double wu = g.dhi + g.ndlo;   // RU(dhi - dlo)
   const double nw = g.dlo + g.ndhi;   // RU(dlo - dhi) = -RD(dhi - dlo)
-  const int64_t base = (int64_t)label << g.centre;
-  nlo = g.ndlo + ldexp((double)(base + g.centre) * nw, -(g.level + g.centre));
-  hi = g.dlo + ldexp((double)(base + 1) * wu, -(g.level + g.centre));
+  const int sh = g.centre == 1 ? 1 : 0;  // centres are vertices of level + 1
+  const int64_t base = (int64_t)label << sh;
+  const int64_t a = base + (g.centre == 1 ? 1 : 0);  // lower end: of cell a
+  const int64_t b = base + (g.centre == 2 ? 0 : 1);  // upper end: of cell b - 1
+  nlo = g.ndlo + ldexp((double)a * nw, -(g.level + sh));
+  hi = g.dlo + ldexp((double)b * wu, -(g.level + sh));
 }
 
 __device__ __forceinline__ int cell_class(double nlo, double hi) {

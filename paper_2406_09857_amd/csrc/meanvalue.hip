@@ -1,3 +1,5 @@
+// Taylor-form exclusion tests and the inclusion criterion C1.
+//
 // Mean-value exclusion test: the Taylor form of order 1 (Sec. 3.2 of Moroz,
 // arXiv 2406.09857, Taylor form definition with m = 1),
 //   T(F, B) = F(c) + sum_i dF/dx_i(B) * (B_i - c_i),   c the centre of B,
@@ -545,5 +547,163 @@ int mv_run_level(void* handle, const vx_poly* P, int np, const vx_csf* S, const 
 }
 
 void mv_run_end(void* handle) { delete reinterpret_cast<MvRunHandle*>(handle); }
+
+// ---------------------------------------------------------------------------
+// Inclusion criterion C1 (Sec. 3.2): F on the 2^k vertices of every box; the
+// box is certified to meet F = 0 when one vertex enclosure is > 0 and another
+// < 0 (intermediate value theorem along the box's edges).  The vertices of all
+// boxes are grid points: they are listed (2^k per box), turned into a CSF by
+// the radix-sort builder (which merges duplicates), evaluated once each by
+// Algorithm 2 on the degenerate vertex enclosures, and every box looks its
+// vertices up in that CSF.
+// ---------------------------------------------------------------------------
+
+// Vertex m of box b adds bit (k-1-j) of m on axis j (first axis most
+// significant), one thread per (box, vertex).
+__global__ void k_vertex_tuples(int k, int64_t nleaf, const int32_t* __restrict__ labels,
+                                int32_t* __restrict__ tuples) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nv = 1 << k;
+  if (t >= nleaf * nv) return;
+  const int64_t b = t / nv;
+  const int m = (int)(t % nv);
+  for (int j = 0; j < k; j++) tuples[t * k + j] = labels[b * k + j] + ((m >> (k - 1 - j)) & 1);
+}
+
+// Leaf of the vertex CSF holding tuple `tup`: per depth a binary search among
+// the children of the node found so far; -1 if absent (never, for a CSF built
+// from the same tuples; an absent vertex only withholds a certificate).
+__device__ int64_t csf_find(const CsfView& c, int k, const int32_t* tup) {
+  int64_t lo = 0, hi = c.n[0];
+  for (int l = 0; l < k; l++) {
+    int64_t a = lo, b = hi;
+    while (a < b) {
+      const int64_t mid = (a + b) >> 1;
+      if (c.idx[l][mid] < tup[l]) a = mid + 1; else b = mid;
+    }
+    if (a >= hi || c.idx[l][a] != tup[l]) return -1;
+    if (l + 1 == k) return a;
+    lo = c.ptr[l][a];
+    hi = c.ptr[l][a + 1];
+  }
+  return -1;
+}
+
+// incl[p * nleaf + b] = 1 when some vertex of box b has a lower bound > 0 and
+// another an upper bound < 0 for F_p (NaN bounds certify nothing).
+__global__ void k_c1_flags(int k, int np, int64_t nleaf, const int32_t* __restrict__ labels, CsfView V,
+                           const double* __restrict__ vlo, const double* __restrict__ vhi,
+                           uint8_t* __restrict__ incl) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  const int64_t nv = V.n[k - 1];
+  uint64_t pos = 0, neg = 0;
+  for (int m = 0; m < (1 << k); m++) {
+    int32_t tup[VX_KMAX];
+    for (int j = 0; j < k; j++) tup[j] = labels[b * k + j] + ((m >> (k - 1 - j)) & 1);
+    const int64_t q = csf_find(V, k, tup);
+    if (q < 0) continue;
+    for (int p = 0; p < np; p++) {
+      if (vlo[(int64_t)p * nv + q] > 0.0) pos |= 1ull << p;
+      if (vhi[(int64_t)p * nv + q] < 0.0) neg |= 1ull << p;
+    }
+  }
+  for (int p = 0; p < np; p++) incl[(int64_t)p * nleaf + b] = (uint8_t)(((pos & neg) >> p) & 1);
+}
+
+struct InclPlan {
+  int32_t* labels = nullptr;
+  int32_t* tuples = nullptr;
+  vx_csf V;
+  char* build_ws = nullptr;
+  size_t build_bytes = 0;
+  double* vlo = nullptr;
+  double* vhi = nullptr;
+  char* eval_ws = nullptr;
+  size_t eval_bytes = 0;
+};
+
+// Vertex CSF capacities: depth l holds at most min(tuples, (2^level + 1)^(l+1)) nodes.
+static void plan_inclusion(Arena& A, InclPlan& I, const vx_poly* P, int np, const vx_csf* S) {
+  const int k = S->k;
+  const int64_t n = S->n[k - 1], nt = n << k;
+  const int64_t side = ((int64_t)1 << S->level) + 1;
+  memset(&I.V, 0, sizeof I.V);
+  I.V.k = k;
+  I.V.level = S->level;
+  int64_t grid = 1;
+  for (int l = 0; l < k; l++) {
+    grid = grid > nt ? nt : grid * side;
+    I.V.cap[l] = grid < nt ? grid : nt;
+    I.V.n[l] = I.V.cap[l];
+  }
+  I.labels = A.take<int32_t>((size_t)n * k);
+  I.tuples = A.take<int32_t>((size_t)nt * k);
+  for (int l = 0; l < k; l++) {
+    I.V.idx[l] = A.take<int32_t>((size_t)I.V.cap[l]);
+    if (l + 1 < k) I.V.ptr[l] = A.take<int32_t>((size_t)I.V.cap[l] + 1);
+  }
+  I.build_bytes = build_workspace_bytes(k, nt);
+  I.build_ws = A.take<char>(I.build_bytes);
+  I.vlo = A.take<double>((size_t)np * I.V.cap[k - 1]);
+  I.vhi = A.take<double>((size_t)np * I.V.cap[k - 1]);
+  // the vertex counts are known only after the build: plan for their bounds
+  I.eval_bytes = prepared_bytes(P, np) + eval_level_bytes_bound(P, np, &I.V) + 256;
+  I.eval_ws = A.take<char>(I.eval_bytes);
+}
+
+size_t inclusion_workspace_bytes(const vx_poly* P, int np, const vx_csf* S) {
+  Arena A;
+  InclPlan I;
+  plan_inclusion(A, I, P, np, S);
+  return A.off + 256;
+}
+
+int inclusion_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, uint8_t* incl, void* ws,
+                   size_t ws_bytes, hipStream_t st) {
+  const int k = S->k;
+  const int64_t n = S->n[k - 1];
+  if (n == 0) return VX_OK;
+  if ((int64_t)k * (S->level + 1) > 62)
+    VX_FAIL(VX_EUNSUPPORTED, "inclusion test: k * (level + 1) = %d exceeds the 62-bit vertex key",
+            k * (S->level + 1));
+  Arena A;
+  A.base = reinterpret_cast<char*>(ws);
+  A.size = ws_bytes;
+  InclPlan I;
+  plan_inclusion(A, I, P, np, S);
+  if (A.overflow) VX_FAIL(VX_ECAPACITY, "inclusion test: workspace of %zu bytes is too small", ws_bytes);
+  const int pr = prof_start("inclusion", (double)n, st);
+  CsfView cv;
+  memset(&cv, 0, sizeof cv);
+  for (int l = 0; l < k; l++) {
+    cv.idx[l] = S->idx[l];
+    cv.ptr[l] = S->ptr[l];
+    cv.n[l] = S->n[l];
+  }
+  hipLaunchKernelGGL(k_leaf_labels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, cv, I.labels);
+  VX_CHECK_LAUNCH("k_leaf_labels");
+  const int64_t nt = n << k;
+  hipLaunchKernelGGL(k_vertex_tuples, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, k, n,
+                     (const int32_t*)I.labels, I.tuples);
+  VX_CHECK_LAUNCH("k_vertex_tuples");
+  // vertex labels run to 2^level: one more key bit per axis than the cells
+  int rc;
+  if ((rc = build_impl(k, S->level + 1, I.tuples, nt, &I.V, nullptr, I.build_ws, I.build_bytes, st))) return rc;
+  I.V.level = S->level;
+  if ((rc = eval_level_impl(P, np, &I.V, dom, I.vlo, I.vhi, nullptr, I.eval_ws, I.eval_bytes, st, 2))) return rc;
+  CsfView vv;
+  memset(&vv, 0, sizeof vv);
+  for (int l = 0; l < k; l++) {
+    vv.idx[l] = I.V.idx[l];
+    vv.ptr[l] = I.V.ptr[l];
+    vv.n[l] = I.V.n[l];
+  }
+  hipLaunchKernelGGL(k_c1_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, np, n,
+                     (const int32_t*)I.labels, vv, (const double*)I.vlo, (const double*)I.vhi, incl);
+  VX_CHECK_LAUNCH("k_c1_flags");
+  prof_stop(pr, st);
+  return VX_OK;
+}
 
 }  // namespace vx
