@@ -188,36 +188,6 @@ __device__ inline void class_bounds(const int32_t* __restrict__ labels, int64_t 
 
 __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-__global__ void k_seg_count(const int32_t* __restrict__ ptr, int64_t nparent, int64_t nchild,
-                            const int32_t* __restrict__ labels, AxisGrid g, int Z, int64_t* __restrict__ cnt,
-                            int64_t* __restrict__ bounds) {
-  round_up_mode();
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nparent) return;
-  const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : nchild;
-  int64_t ne, pb;
-  class_bounds(labels, b, e, g, ne, pb);
-  bounds[2 * p] = ne;
-  bounds[2 * p + 1] = pb;
-  cnt[p] = cdiv(ne - b, Z) + cdiv(pb - ne, Z) + cdiv(e - pb, Z);
-}
-
-__global__ void k_seg_write(const int32_t* __restrict__ ptr, int64_t nparent, int64_t nchild, int Z,
-                            const int64_t* __restrict__ off, const int64_t* __restrict__ bounds,
-                            int4* __restrict__ seg) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nparent) return;
-  const int64_t b = ptr ? ptr[p] : 0, e = ptr ? ptr[p + 1] : nchild;
-  const int64_t cuts[4] = {b, bounds[2 * p], bounds[2 * p + 1], e};
-  const int cls[3] = {CLS_NEG, CLS_STRADDLE, CLS_POS};
-  int64_t o = off[p];
-  for (int c = 0; c < 3; c++)
-    for (int64_t s = cuts[c]; s < cuts[c + 1]; s += Z) {
-      const int64_t cnt = cuts[c + 1] - s < Z ? cuts[c + 1] - s : Z;
-      seg[o++] = make_int4((int)p, (int)s, (int)cnt, cls[c]);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Stage 1.
 // ---------------------------------------------------------------------------
@@ -969,27 +939,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF == 4 ? 6
 constexpr int64_t LEAF_SPLIT_NODES = 1536 * 1024;
 constexpr int64_t LEAF_ONE_NODES = 16384;
 
-// Parent (depth k-1 node) of every leaf: binary search in ptr.
-__global__ void k_parent_of(const int32_t* __restrict__ ptr, int64_t nparent, int64_t nleaf,
-                            int32_t* __restrict__ parent) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nleaf) return;
-  int64_t lo = 0, hi = nparent;  // find last p with ptr[p] <= b
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (ptr[mid] <= b) lo = mid; else hi = mid;
-  }
-  parent[b] = (int32_t)lo;
-}
-
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-struct I64Loader {
-  const int64_t* a;
-  __device__ int64_t operator()(int64_t i) const { return a[i]; }
-};
-
 static AxisGrid make_grid(const double* dom, int axis, int level, int centre = 0) {
   AxisGrid g;
   g.dlo = dom[2 * axis];
@@ -1056,24 +1008,9 @@ static void plan_segments(Arena& A, SegPlan& sp, int64_t nparent, int64_t nchild
   }
 }
 
-static int build_segments(SegPlan& sp, const int32_t* ptr, const int32_t* labels, const AxisGrid& g,
-                          hipStream_t st) {
-  const int64_t np = sp.nparent;
-  const unsigned blocks = (unsigned)((np + 255) / 256);
-  hipLaunchKernelGGL(k_seg_count, dim3(blocks), dim3(256), 0, st, ptr, np, sp.nchild, labels, g, sp.Z, sp.cnt,
-                     sp.bounds);
-  VX_CHECK_LAUNCH("k_seg_count");
-  scan_exclusive(I64Loader{sp.cnt}, (const int64_t*)nullptr, np, sp.off, sp.nseg, sp.tiles, st);
-  VX_CHECK_LAUNCH("segment scan");
-  hipLaunchKernelGGL(k_seg_write, dim3(blocks), dim3(256), 0, st, ptr, np, sp.nchild, sp.Z,
-                     (const int64_t*)sp.off, (const int64_t*)sp.bounds, sp.seg);
-  VX_CHECK_LAUNCH("k_seg_write");
-  return VX_OK;
-}
-
 // Small levels: one workgroup builds the segments of every depth in a single
-// launch (count, scan, write per depth), instead of five launches per depth.
-// Same segments as build_segments.
+// launch (count, scan, write per depth); the larger levels use the 1-D grid
+// kernels below.  Both write the same segments.
 constexpr int64_t SMALL_LEVEL_NODES = 32768;  // largest depth count for the one-workgroup paths
 
 struct SegJob {
