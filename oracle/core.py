@@ -81,6 +81,9 @@ def lib():
         L.orc_mean_value.restype = C.c_int
         L.orc_vertex_table.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int64, dp]
         L.orc_vertex_table.restype = None
+        L.orc_taylor_inclusion.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp, dp,
+                                           np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
+        L.orc_taylor_inclusion.restype = C.c_int
         L.orc_deriv2.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, C.c_int, dp, dp]
         L.orc_deriv2.restype = C.c_int
         L.orc_taylor2.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp, dp]
@@ -401,27 +404,35 @@ def taylor2_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1, degrees=
     bx = np.stack([btabs[j][boxes[:, j]] for j in range(k)], axis=1) if nb else np.zeros((0, k, 2))
     cx = np.stack([ctabs[j][boxes[:, j]] for j in range(k)], axis=1) if nb else np.zeros((0, k, 2))
     bx = np.ascontiguousarray(bx); cx = np.ascontiguousarray(cx)
-    pairs = taylor_pairs(k)
     los, his = [], []
     for jp, p in enumerate(polys):
         d = poly_degree(p) if degrees is None else degrees[jp]
-        fl, fh, _ = eval_csf(p, d, csf, ctabs, OUTWARD, nthreads)
-        D = np.zeros((k, nb, 2))
-        for i in range(k):
-            if d >= 1:
-                dl, dh, _ = eval_csf(deriv(p, d, i), d - 1, csf, ctabs, OUTWARD, nthreads)
-                D[i, :, 0] = dl; D[i, :, 1] = dh
-        H = np.zeros((len(pairs), nb, 2))
-        for t, (i, j) in enumerate(pairs):
-            if d >= 2:
-                hl, hh, _ = eval_csf(deriv2(p, d, i, j), d - 2, csf, btabs, OUTWARD, nthreads)
-                H[t, :, 0] = hl; H[t, :, 1] = hh
-        fc = np.ascontiguousarray(np.stack([fl, fh], axis=1))
+        fc, D, H = _taylor2_parts(p, d, csf, btabs, ctabs, nthreads)
         out = np.zeros((nb, 2))
         if nb and lib().orc_taylor2(k, nb, _dp(fc), _dp(D), _dp(H), _dp(bx), _dp(cx), _dp(out)):
             raise ValueError("orc_taylor2 failed")
         los.append(out[:, 0]); his.append(out[:, 1])
     return np.array(los).reshape(len(polys), -1), np.array(his).reshape(len(polys), -1)
+
+
+def _taylor2_parts(p, d, csf, btabs, ctabs, nthreads):
+    """F and its first derivatives at the centre enclosures, the H_ij on the
+    boxes: (fc (n, 2), D (k, n, 2), H (pairs, n, 2))."""
+    k = csf["k"]
+    nb = len(csf["boxes"])
+    pairs = taylor_pairs(k)
+    fl, fh, _ = eval_csf(p, d, csf, ctabs, OUTWARD, nthreads)
+    D = np.zeros((k, nb, 2))
+    for i in range(k):
+        if d >= 1:
+            dl, dh, _ = eval_csf(deriv(p, d, i), d - 1, csf, ctabs, OUTWARD, nthreads)
+            D[i, :, 0] = dl; D[i, :, 1] = dh
+    H = np.zeros((len(pairs), nb, 2))
+    for t, (i, j) in enumerate(pairs):
+        if d >= 2:
+            hl, hh, _ = eval_csf(deriv2(p, d, i, j), d - 2, csf, btabs, OUTWARD, nthreads)
+            H[t, :, 0] = hl; H[t, :, 1] = hh
+    return np.ascontiguousarray(np.stack([fl, fh], axis=1)), D, H
 
 
 def subdivide_t2(polys, k: int, depth: int, dom=None, nthreads: int = 1):
@@ -491,4 +502,32 @@ def inclusion_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1, degree
         pos = (vl > 0.0)[where].any(axis=1)
         neg = (vh < 0.0)[where].any(axis=1)
         out[jp] = pos & neg
+    return out
+
+
+def taylor_inclusion_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1, degrees=None):
+    """The Taylor-based C1 (Sec. 3.2, from the order-2 form) for every
+    polynomial and box: (np, n) booleans, true when the order-2 bound of F at
+    the vertex maximizing the linear part is > 0 and at the one minimizing it
+    is < 0 (``orc_taylor_inclusion``)."""
+    k, level = csf["k"], csf["level"]
+    dom = np.asarray(dom, np.float64).reshape(k, 2)
+    btabs = level_tables(dom, k, level)
+    ctabs = [centre_table(float(dom[j, 0]), float(dom[j, 1]), level) for j in range(k)]
+    vtabs = [vertex_table(float(dom[j, 0]), float(dom[j, 1]), level) for j in range(k)]
+    boxes = np.asarray(csf["boxes"], np.int64)
+    nb = boxes.shape[0]
+    out = np.zeros((len(polys), nb), bool)
+    if nb == 0:
+        return out
+    cx = np.ascontiguousarray(np.stack([ctabs[j][boxes[:, j]] for j in range(k)], axis=1))
+    vl = np.ascontiguousarray(np.stack([vtabs[j][boxes[:, j]] for j in range(k)], axis=1))
+    vu = np.ascontiguousarray(np.stack([vtabs[j][boxes[:, j] + 1] for j in range(k)], axis=1))
+    for jp, p in enumerate(polys):
+        d = poly_degree(p) if degrees is None else degrees[jp]
+        fc, D, H = _taylor2_parts(p, d, csf, btabs, ctabs, nthreads)
+        flags = np.zeros(nb, np.uint8)
+        if lib().orc_taylor_inclusion(k, nb, _dp(fc), _dp(D), _dp(H), _dp(vl), _dp(vu), _dp(cx), flags):
+            raise ValueError("orc_taylor_inclusion failed")
+        out[jp] = flags.astype(bool)
     return out

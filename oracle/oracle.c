@@ -26,7 +26,9 @@
  *     comparison), used to pin the amortized routine;
  *   - the mean-value (order-1 Taylor form) enclosure of Sec. 3.2: centre
  *     enclosures, derivative coefficients and the final combination;
- *   - the grid-vertex enclosures of the inclusion criterion C1 (Sec. 3.2);
+ *   - the grid-vertex enclosures of the inclusion criterion C1 (Sec. 3.2) and
+ *     its Taylor-based form (order-2 bounds at the two extreme vertices of
+ *     the linear part);
  *   - the order-2 Taylor form of Sec. 3.2 (Taylor form definition, m = 2):
  *     second-derivative coefficients (halved on the diagonal) and the
  *     combination F(c) + sum_i dF/dx_i(c) W_i + sum_{i<=j} H_ij(B) W_i W_j,
@@ -514,6 +516,58 @@ int orc_taylor2(int k, int64_t nbox, const double* fc, const double* Dc, const d
         acc = iv_add(acc, iv_mul(Ht, X, ORC_OUTWARD), ORC_OUTWARD);
       }
     out[2 * b] = acc.lo; out[2 * b + 1] = acc.hi;
+  }
+  return 0;
+}
+
+/* Taylor-based inclusion criterion (Sec. 3.2, inclusion criterion from a
+ * Taylor form of order m >= 2, here m = 2).  Per box: the linear part
+ * l(x) = F(c) + grad F(c).(x - c) is largest at the vertex V_max that takes,
+ * on axis i, the upper end when the enclosure of dF/dx_i(c) has lo + hi >= 0
+ * (its midpoint is >= 0) and the lower end otherwise, and smallest at the
+ * opposite vertex V_min.  F at a vertex V is bounded by the order-2 form at
+ * the point V: F(c) + sum_i Dc_i (V_i - c_i) + sum_t H_t(B) X_t(V), with
+ * V_i - c_i = [RD(vlo_i - chi_i), RU(vhi_i - clo_i)] from V's enclosure and
+ * X_t the squares and products of those.  out[b] = 1 when the lower bound at
+ * V_max is > 0 and the upper bound at V_min is < 0.  vlo_/vhi_ hold the
+ * enclosures of each box's lower and upper vertex on every axis. */
+static ivl taylor2_at(int k, int64_t nbox, int64_t b, ivl fc, const double* Dc, const double* H, const ivl* W) {
+  ivl acc = fc;
+  for (int i = 0; i < k; i++) {
+    ivl Di = {Dc[((int64_t)i * nbox + b) * 2], Dc[((int64_t)i * nbox + b) * 2 + 1]};
+    acc = iv_add(acc, iv_mul(Di, W[i], ORC_OUTWARD), ORC_OUTWARD);
+  }
+  int t = 0;
+  for (int i = 0; i < k; i++)
+    for (int j = i; j < k; j++, t++) {
+      ivl X = i == j ? iv_sqr(W[i]) : iv_mul(W[i], W[j], ORC_OUTWARD);
+      ivl Ht = {H[((int64_t)t * nbox + b) * 2], H[((int64_t)t * nbox + b) * 2 + 1]};
+      acc = iv_add(acc, iv_mul(Ht, X, ORC_OUTWARD), ORC_OUTWARD);
+    }
+  return acc;
+}
+
+int orc_taylor_inclusion(int k, int64_t nbox, const double* fc, const double* Dc, const double* H,
+                         const double* vlo_, const double* vhi_, const double* centre, uint8_t* out) {
+  if (k < 1 || k > ORC_KMAX) return -1;
+  for (int64_t b = 0; b < nbox; b++) {
+    ivl Wmax[ORC_KMAX], Wmin[ORC_KMAX];
+    for (int i = 0; i < k; i++) {
+      const double* lv = vlo_ + (b * k + i) * 2;  /* lower vertex on axis i */
+      const double* uv = vhi_ + (b * k + i) * 2;  /* upper vertex on axis i */
+      const double* c = centre + (b * k + i) * 2;
+      const double dlo = Dc[((int64_t)i * nbox + b) * 2], dhi = Dc[((int64_t)i * nbox + b) * 2 + 1];
+      const int up = -dlo <= dhi;  /* lo + hi >= 0, exactly */
+      const double* vmax = up ? uv : lv;
+      const double* vmin = up ? lv : uv;
+      round_down(ORC_OUTWARD); Wmax[i].lo = vmax[0] - c[1]; Wmin[i].lo = vmin[0] - c[1];
+      round_up(ORC_OUTWARD);   Wmax[i].hi = vmax[1] - c[0]; Wmin[i].hi = vmin[1] - c[0];
+      round_restore();
+    }
+    ivl f = {fc[2 * b], fc[2 * b + 1]};
+    ivl tmax = taylor2_at(k, nbox, b, f, Dc, H, Wmax);
+    ivl tmin = taylor2_at(k, nbox, b, f, Dc, H, Wmin);
+    out[b] = (tmax.lo > 0.0 && tmin.hi < 0.0) ? 1 : 0;
   }
   return 0;
 }

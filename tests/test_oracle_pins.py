@@ -782,3 +782,44 @@ def test_inclusion_vertex_values_equal_per_vertex_bruteforce():
             pos |= lo > 0.0
             neg |= hi < 0.0
         assert inc[q] == (pos and neg), q
+
+
+def test_taylor_inclusion_of_a_plane_and_the_sphere_closed_forms():
+    """For a polynomial of degree <= 2 the order-2 form at a vertex is F at the
+    vertex exactly (dyadic data): a plane is certified exactly on the boxes it
+    strictly crosses; the sphere exactly when F > 0 at the vertex the
+    gradient at the centre points to (farthest from the origin) and F < 0 at
+    the opposite one."""
+    k, level = 3, 4
+    rng = np.random.default_rng(230)
+    S = orc.csf_from_boxes(rng.integers(0, 16, size=(400, k)), level)
+    dom = np.array([-1.0, 1.0] * k)
+    c = 0.3125 + 1.0 / 64
+    plane = synth.monomial_poly(k, 1, {(0, 0, 1): 1.0, (0, 0, 0): -c})
+    inc = orc.taylor_inclusion_level([plane], S, dom)[0]
+    lo3 = -1.0 + S["boxes"][:, 2] / 8.0
+    assert np.array_equal(inc, (lo3 < c) & (c < lo3 + 1.0 / 8.0)) and inc.any()
+    inc = orc.taylor_inclusion_level([synth.sphere()], S, dom)[0]
+    lo = -1.0 + S["boxes"] / 8.0
+    hi = lo + 1.0 / 8.0
+    cen = (lo + hi) / 2
+    vmax = np.where(cen >= 0, hi, lo)
+    vmin = np.where(cen >= 0, lo, hi)
+    f = lambda v: (v * v).sum(axis=1) - 0.5
+    assert np.array_equal(inc, (f(vmax) > 0) & (f(vmin) < 0)) and inc.any()
+
+
+@pytest.mark.parametrize("k,d,level", [(2, 7, 5), (3, 5, 3)])
+def test_taylor_inclusion_is_sound_against_exact_vertex_values(k, d, level):
+    """Every box certified by the Taylor-based test has exact vertex values of
+    both strict signs (so F vanishes in it)."""
+    rng = np.random.default_rng(240 + k)
+    poly = synth.small_random(k, d, seed=241 + k)[0]
+    S = orc.csf_from_boxes(rng.integers(0, 1 << level, size=(150, k)), level)
+    inc = orc.taylor_inclusion_level([poly], S, np.array([-1.0, 1.0] * k))[0]
+    V = orc.box_vertices(S["boxes"])
+    h = Fraction(2, 1 << level)
+    for q in np.flatnonzero(inc):
+        vals = [ex.exact_point_value(poly, d, [Fraction(-1) + int(v) * h for v in V[q, m]]) for m in range(1 << k)]
+        assert max(vals) > 0 and min(vals) < 0, q
+    assert inc.sum() > 0
