@@ -192,19 +192,21 @@ def bench_inclusion(vx):
     dom = w.domain()
     _, kept = vx.run_subdivision(w.polys, dom, w.depth)
     K = vx.CSF.from_arrays(3, w.depth, kept["idx"], kept["ptr"])
-    vx.inclusion_test(w.polys, K, dom)
-    torch.cuda.synchronize()
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        incl = vx.inclusion_test(w.polys, K, dom)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / reps
-    return {"workload": "surface_k3_d40: one trivariate polynomial, total degree 40, N(0,1) coefficients, "
-                        "domain [-1,1]^3, kept boxes of level 9",
-            "boxes": K.nboxes, "certified": int(incl.sum()), "ms": ms,
-            "boxes_per_s": K.nboxes / (ms * 1e-3),
-            "parity": "flags equal to the oracle's (tests/test_gpu_inclusion.py)"}
+    out = {"workload": "surface_k3_d40: one trivariate polynomial, total degree 40, N(0,1) coefficients, "
+                       "domain [-1,1]^3, kept boxes of level 9",
+           "boxes": K.nboxes,
+           "parity": "flags equal to the oracle's (tests/test_gpu_inclusion.py)"}
+    for name, taylor in (("vertices", False), ("taylor2", True)):
+        vx.inclusion_test(w.polys, K, dom, taylor=taylor)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            incl = vx.inclusion_test(w.polys, K, dom, taylor=taylor)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        out[name] = {"certified": int(incl.sum()), "ms": ms, "boxes_per_s": K.nboxes / (ms * 1e-3)}
+    return out
 
 
 COPY_BYTES = 1 << 31  # bytes read (and written) by the calibration copy

@@ -199,6 +199,24 @@ int inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* 
                    size_t ws_bytes, void* stream);
 
 /*
+ * taylor_inclusion_test -- the inclusion criterion C1 from the order-2 Taylor
+ * form (Sec. 3.2, "Inclusion Criterion", Taylor variant): the linear part
+ * l(x) = F_p(c) + grad F_p(c).(x - c) is largest at the vertex V_max that
+ * takes, on axis i, the box's upper end when the enclosure [a, b] of
+ * dF_p/dx_i(c) has a + b >= 0 and the lower end otherwise, and smallest at
+ * the opposite vertex V_min; F_p at a vertex V is bounded by the order-2 form
+ * at the point V (taylor_exclusion's sum with V_i - c_i in place of B_i - c_i,
+ * from the vertex enclosures of inclusion_test and H_ij still over B).  The
+ * box is certified when the lower bound at V_max is > 0 and the upper bound
+ * at V_min is < 0.
+ *   incl : device uint8, np x S->n[k-1], as inclusion_test.
+ * Limits, errors and workspace as taylor_exclusion with order 2
+ * (vx_workspace_bytes(VX_WS_TAYLOR2, ...)).
+ */
+int taylor_inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/*
  * filter_subdivide -- exclusion filter and bisection (Algorithm 3): prune S
  * to the kept boxes K (keep[b] != 0, internal nodes without kept descendants
  * removed) and build the CSF of their 2^k children at level+1, child c of box

@@ -86,13 +86,14 @@ def lib():
                                        C.c_int32, vp, vp, vp, vp, C.c_size_t, vp]
         L.inclusion_test.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.POINTER(C.c_double), vp, vp,
                                      C.c_size_t, vp]
+        L.taylor_inclusion_test.argtypes = L.inclusion_test.argtypes
         L.csf_build.argtypes = [C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(vx_csf), vp, C.c_size_t, vp]
         L.vx_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
         L.vx_profile_end.argtypes = [C.POINTER(vx_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
         L.vx_profile_select.argtypes = [C.c_char_p]
         for f in ("interval_eval_level", "filter_subdivide", "run_subdivision", "run_subdivision_ex", "csf_build",
                   "vx_copy", "vx_profile_begin", "vx_profile_end", "vx_profile_select", "mean_value_exclusion",
-                  "taylor_exclusion", "inclusion_test"):
+                  "taylor_exclusion", "inclusion_test", "taylor_inclusion_test"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -306,9 +307,11 @@ def root_csf(k: int, device=None) -> CSF:
     return CSF.from_arrays(k, 0, [[0]] * k, [[0, 1]] * (k - 1), device)
 
 
-def inclusion_test(polys, csf: CSF, dom, stream=None) -> torch.Tensor:
+def inclusion_test(polys, csf: CSF, dom, stream=None, taylor: bool = False) -> torch.Tensor:
     """Inclusion criterion C1: (np, nboxes) uint8, 1 where the polynomial
-    certainly vanishes in the box (vertex enclosures of both strict signs)."""
+    certainly vanishes in the box (vertex enclosures of both strict signs);
+    ``taylor=True`` uses the order-2 Taylor variant (bounds at the two
+    extreme vertices of the linear part)."""
     polys = as_polys(polys)
     dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
     nb = csf.nboxes
@@ -316,12 +319,14 @@ def inclusion_test(polys, csf: CSF, dom, stream=None) -> torch.Tensor:
     incl = torch.empty((len(polys), max(nb, 1)), dtype=torch.uint8, device=dev)
     parr = _poly_array(polys)
     s = csf.struct()
-    need = int(lib().vx_workspace_bytes(VX_WS_INCLUSION, parr, len(polys), C.byref(s), 0))
+    need = int(lib().vx_workspace_bytes(VX_WS_TAYLOR2 if taylor else VX_WS_INCLUSION, parr, len(polys),
+                                        C.byref(s), 0))
     if need == 0:
         _check(VX_EINVAL)
     ws = _ws(need, dev)
-    _check(lib().inclusion_test(parr, len(polys), C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)),
-                                incl.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    fn = lib().taylor_inclusion_test if taylor else lib().inclusion_test
+    _check(fn(parr, len(polys), C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)), incl.data_ptr(),
+              ws.data_ptr(), ws.numel(), _stream(stream)))
     return incl[:, :nb]
 
 

@@ -219,6 +219,19 @@ int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const do
   return taylor_exclusion(P, np, S, dom, 1, lo, hi, keep, ws, ws_bytes, stream);
 }
 
+int taylor_inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, void* ws,
+                          size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_csf(S, true))) return rc;
+  if ((rc = check_poly(P, np, S->k))) return rc;
+  if ((rc = check_taylor_polys(np, S->k, 2))) return rc;
+  if ((rc = check_dom(dom, S->k))) return rc;
+  if (S->n[S->k - 1] > 0 && !incl) VX_FAIL(VX_EINVAL, "null output flags");
+  if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
+  if ((rc = check_ws(ws))) return rc;
+  return mv_impl(P, np, S, dom, nullptr, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream, 2, incl);
+}
+
 int inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, void* ws,
                    size_t ws_bytes, void* stream) {
   int rc;

@@ -49,8 +49,9 @@ int build_impl(int k, int level, const int32_t* boxes, int64_t n, vx_csf* out, i
 
 // Taylor-form exclusion tests of order 1 (mean value) and 2 (meanvalue.hip).
 size_t mv_workspace_bytes(const vx_poly* P, int np, const vx_csf* S, int order);
+// With `incl` (order 2) the Taylor-based inclusion flags replace the enclosures.
 int mv_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
-            void* ws, size_t ws_bytes, hipStream_t st, int order);
+            void* ws, size_t ws_bytes, hipStream_t st, int order, uint8_t* incl = nullptr);
 size_t mv_run_workspace(const vx_poly* P, int np, int order);
 size_t mv_level_workspace(const vx_poly* P, int np, const vx_csf* S, int order);
 void* mv_run_begin(const vx_poly* P, int np, void* ws, size_t bytes, hipStream_t st, int* rc, int order);

@@ -163,6 +163,7 @@ __global__ void k_leaf_labels(int k, CsfView c, int32_t* __restrict__ labels) {
 struct GridSet {
   AxisGrid cell[VX_KMAX];
   AxisGrid centre[VX_KMAX];
+  AxisGrid vertex[VX_KMAX];
 };
 
 // T(F_p, B) for every leaf and polynomial; keep (if given) is AND-ed with
@@ -279,6 +280,92 @@ __global__ void k_t2_combine(int k, int np, int64_t nleaf, GridSet gs, const int
     excl = excl || (l > 0.0) || (ah < 0.0);
   }
   if (keep && excl) keep[b] = 0;
+}
+
+// Order-2 bound of F at a point V of the box: F(c) + sum_i Dc_i W_i +
+// sum_t H_t X_t with W_i = V_i - c_i (both held as (nlo, hi)), the same sum
+// as k_t2_combine.
+__device__ __forceinline__ void t2_at(int k, int np_, int p, int64_t nleaf, int64_t b, double fnl, double fh,
+                                      const double* __restrict__ dc_lo, const double* __restrict__ dc_hi,
+                                      const double* __restrict__ h_lo, const double* __restrict__ h_hi,
+                                      const double* wnl, const double* wh, double& rnl, double& rh) {
+  (void)np_;
+  const int npair = k * (k + 1) / 2;
+  double anl = fnl, ah = fh;
+  for (int i = 0; i < k; i++) {
+    const int64_t di = ((int64_t)p * k + i) * nleaf + b;
+    double dnl = -opaque(dc_lo[di]);
+    double dh = dc_hi[di];
+    step_gen(dnl, dh, cell_ops(wnl[i], wh[i], CLS_STRADDLE), anl, ah);
+    anl = dnl;
+    ah = dh;
+  }
+  int t = 0;
+  for (int i = 0; i < k; i++)
+    for (int j = i; j < k; j++, t++) {
+      double xnl, xh;
+      if (i == j) {
+        interval_square(wnl[i], wh[i], xnl, xh);
+      } else {
+        xnl = wnl[i];
+        xh = wh[i];
+        step_gen(xnl, xh, cell_ops(wnl[j], wh[j], CLS_STRADDLE), 0.0, 0.0);
+      }
+      const int64_t hi_ = ((int64_t)p * npair + t) * nleaf + b;
+      double hnl = -opaque(h_lo[hi_]);
+      double hh = h_hi[hi_];
+      step_gen(hnl, hh, cell_ops(xnl, xh, CLS_STRADDLE), anl, ah);
+      anl = hnl;
+      ah = hh;
+    }
+  rnl = anl;
+  rh = ah;
+}
+
+// Taylor-based inclusion criterion (order 2): incl[p * nleaf + b] = 1 when
+// the order-2 bound of F_p at the vertex maximizing the linear part
+// F(c) + grad F(c).(x - c) is > 0 and at the vertex minimizing it is < 0.
+// On axis i the maximizing vertex takes the upper end when the enclosure of
+// dF/dx_i(c) has lo + hi >= 0 (nlo <= hi, exactly), else the lower end.
+__global__ void k_t2_inclusion(int k, int np, int64_t nleaf, GridSet gs, const int32_t* __restrict__ labels,
+                               const double* __restrict__ fc_lo, const double* __restrict__ fc_hi,
+                               const double* __restrict__ dc_lo, const double* __restrict__ dc_hi,
+                               const double* __restrict__ h_lo, const double* __restrict__ h_hi,
+                               uint8_t* __restrict__ incl) {
+  round_up_mode();
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  // per axis: the lower and upper vertex as V - c
+  double lnl[VX_KMAX], lh[VX_KMAX], unl[VX_KMAX], uh[VX_KMAX];
+  for (int i = 0; i < k; i++) {
+    double cnl, ch, vnl, vh;
+    const int32_t lab = labels[b * k + i];
+    cell(gs.centre[i], lab, cnl, ch);
+    cell(gs.vertex[i], lab, vnl, vh);
+    lnl[i] = ch + vnl;  // -RD(v_lo - chi)
+    lh[i] = vh + cnl;   // RU(v_hi - clo)
+    cell(gs.vertex[i], lab + 1, vnl, vh);
+    unl[i] = ch + vnl;
+    uh[i] = vh + cnl;
+  }
+  for (int p = 0; p < np; p++) {
+    double xnl[VX_KMAX], xh[VX_KMAX], nnl[VX_KMAX], nh[VX_KMAX];  // V_max - c, V_min - c
+    for (int i = 0; i < k; i++) {
+      const int64_t di = ((int64_t)p * k + i) * nleaf + b;
+      const bool up = -dc_lo[di] <= dc_hi[di];
+      xnl[i] = up ? unl[i] : lnl[i];
+      xh[i] = up ? uh[i] : lh[i];
+      nnl[i] = up ? lnl[i] : unl[i];
+      nh[i] = up ? lh[i] : uh[i];
+    }
+    const double fnl = -opaque(fc_lo[(int64_t)p * nleaf + b]);
+    const double fh = fc_hi[(int64_t)p * nleaf + b];
+    double mxnl, mxh, mnnl, mnh;
+    t2_at(k, np, p, nleaf, b, fnl, fh, dc_lo, dc_hi, h_lo, h_hi, xnl, xh, mxnl, mxh);
+    t2_at(k, np, p, nleaf, b, fnl, fh, dc_lo, dc_hi, h_lo, h_hi, nnl, nh, mnnl, mnh);
+    // lower bound at V_max > 0 (nlo < 0) and upper bound at V_min < 0
+    incl[(int64_t)p * nleaf + b] = (uint8_t)((-opaque(mxnl) > 0.0) && (mnh < 0.0));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -435,8 +522,10 @@ static size_t mv_level_bytes(const vx_poly* P, int np, const MvPolys& M, const v
 }
 
 // One level: Taylor enclosures lo/hi (np x nleaf) and keep AND-ed.
+// With `incl` (order 2 only) the Taylor-based inclusion flags are written
+// instead of the enclosures.
 static int mv_level(const vx_poly* P, int np, const MvRun& R, const vx_csf* S, const double* dom, double* lo,
-                    double* hi, uint8_t* keep, char* ws, size_t bytes, hipStream_t st) {
+                    double* hi, uint8_t* keep, char* ws, size_t bytes, hipStream_t st, uint8_t* incl = nullptr) {
   const int k = S->k;
   const int64_t nl = S->n[k - 1];
   if (nl == 0) return VX_OK;
@@ -485,8 +574,15 @@ static int mv_level(const vx_poly* P, int np, const MvRun& R, const vx_csf* S, c
     gs.cell[i] = g;
     g.centre = 1;
     gs.centre[i] = g;
+    g.centre = 2;
+    gs.vertex[i] = g;
   }
-  if (t2) {
+  if (incl) {
+    hipLaunchKernelGGL(k_t2_inclusion, dim3(nb), dim3(256), 0, st, k, np, nl, gs, (const int32_t*)labels,
+                       (const double*)fcl, (const double*)fch, (const double*)dl, (const double*)dh,
+                       (const double*)hl, (const double*)hh, incl);
+    VX_CHECK_LAUNCH("k_t2_inclusion");
+  } else if (t2) {
     hipLaunchKernelGGL(k_t2_combine, dim3(nb), dim3(256), 0, st, k, np, nl, gs, (const int32_t*)labels,
                        (const double*)fcl, (const double*)fch, (const double*)dl, (const double*)dh,
                        (const double*)hl, (const double*)hh, lo, hi, keep);
@@ -506,14 +602,14 @@ size_t mv_workspace_bytes(const vx_poly* P, int np, const vx_csf* S, int order) 
 }
 
 int mv_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
-            void* ws, size_t ws_bytes, hipStream_t st, int order) {
+            void* ws, size_t ws_bytes, hipStream_t st, int order, uint8_t* incl) {
   if (S->n[S->k - 1] == 0) return VX_OK;
   const size_t rb = (mv_run_bytes(P, np, order) + 255) / 256 * 256;
   if (rb > ws_bytes) VX_FAIL(VX_ECAPACITY, "Taylor test: workspace too small");
   MvRun R;
   int rc;
   if ((rc = mv_run_prepare(P, np, order, reinterpret_cast<char*>(ws), rb, R, st))) return rc;
-  return mv_level(P, np, R, S, dom, lo, hi, keep, reinterpret_cast<char*>(ws) + rb, ws_bytes - rb, st);
+  return mv_level(P, np, R, S, dom, lo, hi, keep, reinterpret_cast<char*>(ws) + rb, ws_bytes - rb, st, incl);
 }
 
 // Run-level interface for run_subdivision: the tables are built once.

@@ -1,4 +1,6 @@
-"""Inclusion criterion C1 (Sec. 3.2) on the GPU against the oracle.
+"""Inclusion criterion C1 (Sec. 3.2) on the GPU against the oracle, in both
+forms: sign change over the vertices, and the order-2 Taylor variant (bounds
+at the two extreme vertices of the linear part).
 
 Bar: the certification flags (per polynomial and box) equal the oracle's
 exactly.  Cases: every level of `tiny`, the `surface` kept set at level 6
@@ -36,63 +38,76 @@ def vx():
     return binding
 
 
-def _check(vx, polys, S, dom, tag):
-    _say(f"[c1] {tag}: level {S['level']} sizes {orc.csf_sizes(S)}")
-    ref = orc.inclusion_level(polys, S, dom, nthreads=orc.max_threads())
+METHODS = ["vertices", "taylor"]
+
+
+def _ref(polys, S, dom, method):
+    fn = orc.taylor_inclusion_level if method == "taylor" else orc.inclusion_level
+    return fn(polys, S, dom, nthreads=orc.max_threads())
+
+
+def _check(vx, polys, S, dom, tag, method="vertices"):
+    _say(f"[c1] {tag} ({method}): level {S['level']} sizes {orc.csf_sizes(S)}")
+    ref = _ref(polys, S, dom, method)
     csf = vx.CSF.from_arrays(S["k"], S["level"], S["idx"], S["ptr"])
-    got = vx.inclusion_test(polys, csf, dom).cpu().numpy().astype(bool)
+    got = vx.inclusion_test(polys, csf, dom, taylor=method == "taylor").cpu().numpy().astype(bool)
     assert got.shape == ref.shape, tag
     bad = np.argwhere(got != ref)
     assert len(bad) == 0, (tag, bad[:5].tolist(), int(got.sum()), int(ref.sum()))
     return int(ref.sum())
 
 
-def test_tiny_every_level(vx):
+@pytest.mark.parametrize("method", METHODS)
+def test_tiny_every_level(vx, method):
     w = synth.tiny()
     for r in orc.subdivide(w.polys, 2, 8):
-        _check(vx, w.polys, r["S"], w.domain(), "tiny")
+        _check(vx, w.polys, r["S"], w.domain(), "tiny", method)
 
 
-def test_surface_kept_level6(vx):
+@pytest.mark.parametrize("method", METHODS)
+def test_surface_kept_level6(vx, method):
     w = synth.surface()
     r = orc.subdivide(w.polys, 3, 6, nthreads=orc.max_threads())[-1]
     K = orc.csf_from_boxes(r["kept"], 6)
-    assert _check(vx, w.polys, K, w.domain(), "surface kept") > 0
+    assert _check(vx, w.polys, K, w.domain(), "surface kept", method) > 0
 
 
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("k,d,level", [(1, 9, 7), (2, 7, 5), (3, 6, 4), (4, 4, 3)])
-def test_random_k_odd_domain_interval_coefficients(vx, k, d, level):
+def test_random_k_odd_domain_interval_coefficients(vx, k, d, level, method):
     rng = np.random.default_rng(500 + k)
     c = synth.small_random(k, d, seed=510 + k, npolys=2)
     polys = [(c[0] - 1e-3 * np.abs(c[0]), c[0] + 1e-3 * np.abs(c[0])), c[1]]
     dom = np.array([-0.7, 1.3] * k)
     boxes = rng.integers(0, 1 << level, size=(600, k))
     S = orc.csf_from_boxes(boxes, level)
-    _check(vx, polys, S, dom, f"k{k}")
+    _check(vx, polys, S, dom, f"k{k}", method)
 
 
-def test_closed_forms_and_edge_cases(vx):
+@pytest.mark.parametrize("method", METHODS)
+def test_closed_forms_and_edge_cases(vx, method):
     k = 3
     S = orc.csf_from_boxes(np.random.default_rng(7).integers(0, 16, size=(500, k)), 4)
     dom = np.array([-1.0, 1.0] * k)
     on_grid = synth.monomial_poly(k, 1, {(0, 0, 1): 1.0, (0, 0, 0): 0.5})  # x3 = -0.5, a grid plane
     between = synth.monomial_poly(k, 1, {(0, 0, 1): 1.0, (0, 0, 0): -0.34375})
-    _check(vx, [on_grid, between, synth.sphere()], S, dom, "planes+sphere")
+    _check(vx, [on_grid, between, synth.sphere()], S, dom, "planes+sphere", method)
     root = orc.csf_from_boxes(np.zeros((1, k), np.int64), 0)
-    _check(vx, [synth.sphere(), between], root, dom, "level 0")
+    _check(vx, [synth.sphere(), between], root, dom, "level 0", method)
     E = orc.csf_from_boxes(np.zeros((0, k), np.int64), 5)
     csf = vx.CSF.from_arrays(k, 5, E["idx"], E["ptr"])
-    assert vx.inclusion_test([synth.sphere()], csf, dom).shape == (1, 0)
+    assert vx.inclusion_test([synth.sphere()], csf, dom, taylor=method == "taylor").shape == (1, 0)
 
 
 @pytest.mark.timeout(900)
-def test_surface_final_kept_set_sampled(vx):
+@pytest.mark.parametrize("method", METHODS)
+def test_surface_final_kept_set_sampled(vx, method):
     w = synth.surface()
     dom = w.domain()
     t = time.time()
     _, kept = vx.run_subdivision(w.polys, dom, w.depth)
     K = vx.CSF.from_arrays(3, w.depth, kept["idx"], kept["ptr"])
-    got = vx.inclusion_test(w.polys, K, dom).cpu().numpy().astype(bool)[0]
+    got = vx.inclusion_test(w.polys, K, dom, taylor=method == "taylor").cpu().numpy().astype(bool)[0]
     _say(f"[c1] surface level {w.depth}: {K.nboxes} kept boxes, {int(got.sum())} certified, {time.time() - t:.1f} s")
     # leaf labels of the kept CSF
     idx = [np.asarray(a, np.int64) for a in kept["idx"]]
@@ -104,6 +119,6 @@ def test_surface_final_kept_set_sampled(vx):
     pick = np.sort(rng.choice(len(B), size=min(len(B), 4000), replace=False))
     T = orc.csf_from_boxes(B[pick], w.depth)
     assert np.array_equal(T["boxes"], B[pick])
-    ref = orc.inclusion_level(w.polys, T, dom, nthreads=orc.max_threads())[0]
+    ref = _ref(w.polys, T, dom, method)[0]
     assert np.array_equal(got[pick], ref), np.flatnonzero(got[pick] != ref)[:5]
     assert 0 < got.sum() < len(got)
