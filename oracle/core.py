@@ -531,3 +531,30 @@ def taylor_inclusion_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1,
             raise ValueError("orc_taylor_inclusion failed")
         out[jp] = flags.astype(bool)
     return out
+
+
+def subdivide_c1(polys, k: int, depth: int, c1_from: int, dom=None, nthreads: int = 1, taylor: bool = False):
+    """Algorithm 3 with both criteria: at every level the boxes excluded by C0
+    are dropped; from level ``c1_from`` on (boxes smaller than the threshold)
+    the kept boxes that satisfy C1 join the output R and are not bisected;
+    the rest are bisected.  One polynomial (C1 certifies a hypersurface).
+    Per level: S, the C0 flags, the certified boxes and the continuing ones."""
+    assert len(polys) == 1, "C1 certifies one polynomial"
+    dom = np.array([-1.0, 1.0] * k) if dom is None else np.asarray(dom, np.float64)
+    boxes = np.zeros((1, k), np.int64)
+    out = []
+    for level in range(depth + 1):
+        S = csf_from_boxes(boxes, level)
+        lo, hi, _ = eval_level(polys, S, dom, nthreads)
+        keep = keep_mask(lo, hi)
+        incl = np.zeros(len(keep), bool)
+        if level >= c1_from and len(keep):
+            fn = taylor_inclusion_level if taylor else inclusion_level
+            incl = fn(polys, S, dom, nthreads)[0]
+        cert = keep & incl
+        cont = keep & ~incl
+        out.append({"level": level, "S": S, "keep": keep, "certified": S["boxes"][cert],
+                    "kept": S["boxes"][cont]})
+        if level < depth:
+            boxes = children_of(S["boxes"][cont])
+    return out

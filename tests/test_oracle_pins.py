@@ -823,3 +823,45 @@ def test_taylor_inclusion_is_sound_against_exact_vertex_values(k, d, level):
         vals = [ex.exact_point_value(poly, d, [Fraction(-1) + int(v) * h for v in V[q, m]]) for m in range(1 << k)]
         assert max(vals) > 0 and min(vals) < 0, q
     assert inc.sum() > 0
+
+
+def test_subdivision_with_inclusion_covers_the_sphere():
+    """Algorithm 3 with C0 and C1 on the sphere F = sum x_i^2 - 1/2 (dyadic
+    grid, exact vertex values): every certified box has vertices strictly
+    inside and strictly outside; certified and continuing boxes never
+    overlap; and every box of the last level that meets the sphere lies in a
+    certified box of some level or is still continuing (nothing meeting the
+    zero set is lost)."""
+    k, depth, c1_from = 3, 5, 2
+    recs = orc.subdivide_c1([synth.sphere()], k, depth, c1_from)
+    cert_all = []
+    for r in recs:
+        L = r["level"]
+        for b in r["certified"]:
+            v = -1.0 + orc.box_vertices(b[None, :])[0] * (2.0 / (1 << L))
+            f = (v * v).sum(axis=1) - 0.5
+            assert (f > 0).any() and (f < 0).any()
+            cert_all.append((L, tuple(b)))
+        cs = {tuple(b) for b in r["certified"]}
+        assert not cs & {tuple(b) for b in r["kept"]}
+        if L < c1_from:
+            assert len(r["certified"]) == 0
+    assert len(cert_all) > 0
+    # boxes of the finest level meeting the sphere: ancestor certified, or continuing
+    last = recs[-1]
+    cont = {tuple(b) for b in last["kept"]}
+    h = 2.0 / (1 << depth)
+    grid = np.array([[a, b, c] for a in range(1 << depth) for b in range(1 << depth) for c in range(1 << depth)])
+    lo = -1.0 + grid * h
+    hi = lo + h
+    near = np.clip(0.0, lo, hi)
+    far = np.where(np.abs(lo) > np.abs(hi), lo, hi)
+    meets = ((near ** 2).sum(axis=1) <= 0.5) & ((far ** 2).sum(axis=1) >= 0.5)
+    certs = set(cert_all)
+    for b in grid[meets]:
+        t = tuple(int(x) for x in b)
+        ok = t in cont
+        for L in range(c1_from, depth + 1):
+            anc = tuple(x >> (depth - L) for x in t)
+            ok = ok or (L, anc) in certs
+        assert ok, t
