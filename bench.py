@@ -206,6 +206,25 @@ def bench_inclusion(vx):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / reps
         out[name] = {"certified": int(incl.sum()), "ms": ms, "boxes_per_s": K.nboxes / (ms * 1e-3)}
+    # Algorithm 3 with both criteria: C1 from level 7 on (boxes narrower than
+    # 2^-5 on [-1,1]), certified boxes leave the loop
+    plain_ms = None
+    for name in ("plain", "vertices", "taylor"):
+        kw = {} if name == "plain" else {"inclusion": name, "inclusion_from": 7}
+        vx.run_subdivision(w.polys, dom, w.depth, want_kept=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats, _ = vx.run_subdivision(w.polys, dom, w.depth, want_kept=False, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        if name == "plain":
+            plain_ms = ms
+            out["loop_plain"] = {"ms_per_run": ms, "kept_last_level": stats[-1]["kept"][2]}
+        else:
+            out["loop_c1_" + name] = {"ms_per_run": ms, "c1_from_level": 7,
+                                      "certified_per_level": [s["certified"] for s in stats],
+                                      "continuing_last_level": stats[-1]["kept"][2],
+                                      "vs_plain": ms / plain_ms}
     return out
 
 

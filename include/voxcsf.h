@@ -241,6 +241,7 @@ typedef struct vx_level_stat {
   int64_t steps;          /* interval Horner steps, all polynomials (Theorem 1 count) */
   double eval_ms;         /* interval_eval_level time (HIP events) */
   double filter_ms;       /* filter_subdivide time (HIP events) */
+  int64_t certified;      /* boxes certified by C1 at this level (VX_RUN_INCLUSION*) */
 } vx_level_stat;
 
 /* Called after each level with device pointers valid until it returns; a
@@ -269,8 +270,23 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
  * VX_RUN_TAYLOR2 adds the order-2 Taylor test (taylor_exclusion, order 2) in
  * the same way; the two flags are exclusive (VX_EINVAL).  VX_RUN_NO_TIMES
  * records no per-level timing events (stats eval_ms and filter_ms are 0):
- * each event is a packet the stream must pass between the level's kernels. */
-enum { VX_RUN_MEAN_VALUE = 1, VX_RUN_TAYLOR2 = 2, VX_RUN_NO_TIMES = 4 };
+ * each event is a packet the stream must pass between the level's kernels.
+ * VX_RUN_INCLUSION (C1 by vertex signs, inclusion_test) or
+ * VX_RUN_INCLUSION_TAYLOR (its Taylor form, taylor_inclusion_test), with
+ * VX_RUN_INCLUSION_FROM(L), run Algorithm 3 with both criteria: from level L
+ * on (boxes smaller than the threshold) the boxes kept by C0 that C1
+ * certifies join the output and are not bisected; stats certified counts
+ * them, the callback sees keep = 2 for them (1: continue, 0: excluded) and K
+ * holds the continuing boxes.  One polynomial only (C1 certifies a
+ * hypersurface); VX_EINVAL otherwise and for both inclusion flags. */
+enum {
+  VX_RUN_MEAN_VALUE = 1,
+  VX_RUN_TAYLOR2 = 2,
+  VX_RUN_NO_TIMES = 4,
+  VX_RUN_INCLUSION = 8,
+  VX_RUN_INCLUSION_TAYLOR = 16
+};
+#define VX_RUN_INCLUSION_FROM(level) ((int32_t)(level) << 16)
 int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
                        size_t ws_bytes, size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user,
                        void* stream);

@@ -24,7 +24,7 @@ KMAX = 4
 
 VX_OK, VX_EINVAL, VX_ECAPACITY, VX_EHIP, VX_EOVERFLOW, VX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD, VX_WS_MEANVALUE, VX_WS_TAYLOR2, VX_WS_INCLUSION = range(7)
-VX_RUN_MEAN_VALUE, VX_RUN_TAYLOR2, VX_RUN_NO_TIMES = 1, 2, 4
+VX_RUN_MEAN_VALUE, VX_RUN_TAYLOR2, VX_RUN_NO_TIMES, VX_RUN_INCLUSION, VX_RUN_INCLUSION_TAYLOR = 1, 2, 4, 8, 16
 
 
 class VxError(RuntimeError):
@@ -46,7 +46,7 @@ class vx_csf(C.Structure):
 class vx_level_stat(C.Structure):
     _fields_ = [("level", C.c_int32), ("reserved", C.c_int32), ("n", C.c_int64 * KMAX),
                 ("kept", C.c_int64 * KMAX), ("steps", C.c_int64), ("eval_ms", C.c_double),
-                ("filter_ms", C.c_double)]
+                ("filter_ms", C.c_double), ("certified", C.c_int64)]
 
 
 class vx_kernel_stat(C.Structure):
@@ -332,12 +332,15 @@ def inclusion_test(polys, csf: CSF, dom, stream=None, taylor: bool = False) -> t
 
 def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None,
                     ws: torch.Tensor | None = None, want_kept: bool = True, mean_value: bool = False,
-                    taylor2: bool = False, level_times: bool = True):
+                    taylor2: bool = False, level_times: bool = True, inclusion: str | None = None,
+                    inclusion_from: int = 0):
     """Algorithm 3 with C0 to `depth`.  Returns (stats, kept) where stats is a
     list of per-level dicts and kept the final level's kept CSF (host numpy).
     ``mean_value`` / ``taylor2`` add the Taylor test of order 1 / 2 to C0;
     ``level_times=False`` records no per-level timing events (eval_ms and
-    filter_ms are then 0).
+    filter_ms are then 0).  ``inclusion`` ("vertices" or "taylor") runs
+    Algorithm 3 with C1 from level ``inclusion_from`` on: certified boxes
+    leave the loop (keep = 2 in ``record``, counted in "certified").
 
     ``record(level, S, lo, hi, keep, K)`` is called with device-side views
     (numpy copies) when given; it may return True to stop.
@@ -383,13 +386,18 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
             return 1
 
     cb = LEVEL_CB(_cb) if (record is not None or want_kept) else LEVEL_CB()
+    flags = ((VX_RUN_MEAN_VALUE if mean_value else 0) | (VX_RUN_TAYLOR2 if taylor2 else 0)
+             | (0 if level_times else VX_RUN_NO_TIMES))
+    if inclusion is not None:
+        if inclusion not in ("vertices", "taylor"):
+            raise ValueError("inclusion is 'vertices' or 'taylor'")
+        flags |= (VX_RUN_INCLUSION if inclusion == "vertices" else VX_RUN_INCLUSION_TAYLOR) | (inclusion_from << 16)
     size = ws_bytes if ws_bytes is not None else (ws.numel() if ws is not None else 4 << 30)
     for _ in range(8):
         if ws is None or ws.numel() < size:
             ws = _ws(size)
         rc = lib().run_subdivision_ex(parr, len(polys), dom.ctypes.data_as(C.POINTER(C.c_double)), depth,
-                                      (VX_RUN_MEAN_VALUE if mean_value else 0) | (VX_RUN_TAYLOR2 if taylor2 else 0)
-                                      | (0 if level_times else VX_RUN_NO_TIMES),
+                                      flags,
                                       ws.data_ptr(), ws.numel(),
                                       C.byref(need), stats, cb, None, _stream(stream))
         if rc == VX_ECAPACITY and need.value > size:
@@ -403,7 +411,7 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
     out = []
     for r in stats:
         out.append({"level": r.level, "n": list(r.n)[:k], "kept": list(r.kept)[:k], "steps": r.steps,
-                    "eval_ms": r.eval_ms, "filter_ms": r.filter_ms})
+                    "eval_ms": r.eval_ms, "filter_ms": r.filter_ms, "certified": r.certified})
     return out, final.get("kept")
 
 

@@ -108,6 +108,34 @@ static int check_taylor_polys(int np, int k, int order) {
   return VX_OK;
 }
 
+// Algorithm 3 with the inclusion criterion: boxes kept by C0 that C1
+// certifies join the output and are not bisected.  cont = keep && !incl
+// (the boxes that continue); keep becomes 2 for the certified ones (1:
+// continues, 0: excluded); the certified boxes are counted into *count, one
+// atomic per wave.
+__global__ void k_mark_certified(int64_t n, uint8_t* __restrict__ keep, const uint8_t* __restrict__ incl,
+                                 uint8_t* __restrict__ cont, unsigned long long* __restrict__ count) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int c = 0;
+  if (b < n) {
+    const bool kp = keep[b] != 0, ce = kp && incl[b] != 0;
+    cont[b] = (uint8_t)(kp && !ce);
+    if (ce) keep[b] = 2;
+    c = ce;
+  }
+  const uint64_t m = __ballot(c);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (unsigned long long)__popcll(m));
+}
+
+// The count into the host-mapped result slot, visible before anything the
+// stream does afterwards (the filter's flag).
+__global__ void k_put_count(const unsigned long long* __restrict__ count, int64_t* out) {
+  if (threadIdx.x == 0) {
+    *reinterpret_cast<volatile int64_t*>(out) = (int64_t)*count;
+    __threadfence_system();
+  }
+}
+
 // Spin on the mapped flag instead of a stream wait (lower latency per level).
 // The stream is queried now and then so that a failed or idle stream ends the
 // wait with an error instead of spinning forever.
@@ -342,7 +370,16 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   if (depth < 0 || depth > 28) VX_FAIL(VX_EINVAL, "depth %d outside [0, 28]", depth);
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
   if ((rc = check_ws(ws))) return rc;
-  if (flags & ~(VX_RUN_MEAN_VALUE | VX_RUN_TAYLOR2 | VX_RUN_NO_TIMES)) VX_FAIL(VX_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & ~(VX_RUN_MEAN_VALUE | VX_RUN_TAYLOR2 | VX_RUN_NO_TIMES | VX_RUN_INCLUSION | VX_RUN_INCLUSION_TAYLOR |
+                VX_RUN_INCLUSION_FROM(255)))
+    VX_FAIL(VX_EINVAL, "unknown flags 0x%x", flags);
+  const int incl_mode = (flags & VX_RUN_INCLUSION) ? 1 : (flags & VX_RUN_INCLUSION_TAYLOR) ? 2 : 0;
+  const int incl_from = (flags >> 16) & 255;
+  if ((flags & VX_RUN_INCLUSION) && (flags & VX_RUN_INCLUSION_TAYLOR))
+    VX_FAIL(VX_EINVAL, "VX_RUN_INCLUSION and VX_RUN_INCLUSION_TAYLOR are exclusive");
+  if (incl_mode && np != 1) VX_FAIL(VX_EINVAL, "the inclusion criterion certifies one polynomial (np = %d)", np);
+  if (incl_mode == 2 && (rc = check_taylor_polys(np, k, 2))) return rc;
+  if (!incl_mode && incl_from) VX_FAIL(VX_EINVAL, "VX_RUN_INCLUSION_FROM without an inclusion flag");
   const bool times = stats && !(flags & VX_RUN_NO_TIMES);
   if ((flags & VX_RUN_MEAN_VALUE) && (flags & VX_RUN_TAYLOR2))
     VX_FAIL(VX_EINVAL, "VX_RUN_MEAN_VALUE and VX_RUN_TAYLOR2 are exclusive");
@@ -416,8 +453,9 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   // the filter's last kernel: no copy launch, only the stream wait.
   int64_t* counts = nullptr;
   int64_t* counts_dev = nullptr;
-  VX_HIP(hipHostMalloc((void**)&counts, sizeof(int64_t) * (2 * VX_KMAX + 1), hipHostMallocMapped | hipHostMallocCoherent));
-  counts[2 * VX_KMAX] = 0;  // level-done flag
+  VX_HIP(hipHostMalloc((void**)&counts, sizeof(int64_t) * (2 * VX_KMAX + 2), hipHostMallocMapped | hipHostMallocCoherent));
+  counts[2 * VX_KMAX] = 0;      // level-done flag
+  counts[2 * VX_KMAX + 1] = 0;  // boxes certified by C1 at the level
   struct PinGuard {
     int64_t* p;
     ~PinGuard() { (void)hipHostFree(p); }
@@ -447,11 +485,18 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     const size_t o_k = carve(csf_bytes(k, kcap));
     const size_t o_mlo = mv ? carve(sizeof(double) * (size_t)np * nleaf) : 0;
     const size_t o_mhi = mv ? carve(sizeof(double) * (size_t)np * nleaf) : 0;
+    const bool incl_on = incl_mode && level >= incl_from && nleaf > 0;
+    const size_t o_incl = incl_on ? carve((size_t)nleaf) : 0;
+    const size_t o_cont = incl_on ? carve((size_t)nleaf) : 0;
+    const size_t o_ccnt = incl_on ? carve(sizeof(unsigned long long)) : 0;
     const size_t ews = eval_level_bytes(P, np, &S);
     const size_t fws = filter_workspace_bytes(&S);
     const size_t mws = mv ? mv_level_workspace(P, np, &S, order) : 0;
+    const size_t iws = !incl_on ? 0 : incl_mode == 1 ? inclusion_workspace_bytes(P, np, &S)
+                                                     : mv_workspace_bytes(P, np, &S, 2);
     size_t scratch_bytes = ews > fws ? ews : fws;
     scratch_bytes = scratch_bytes > mws ? scratch_bytes : mws;
+    scratch_bytes = scratch_bytes > iws ? scratch_bytes : iws;
     const size_t o_scr = carve(scratch_bytes);
     const size_t mid_bytes = moff;
     const size_t need = s_bytes + n_bytes + mid_bytes;
@@ -489,9 +534,27 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
       double* mhi = reinterpret_cast<double*>(mid_base + o_mhi);
       if ((rc = mv_run_level(mvh, P, np, &S, dom, mlo, mhi, keep, scratch, scratch_bytes, st))) return rc;
     }
+    // C1 on the level's boxes: certified boxes leave, the others continue
+    const uint8_t* cont = keep;
+    if (incl_on) {
+      uint8_t* incl = reinterpret_cast<uint8_t*>(mid_base + o_incl);
+      uint8_t* contw = reinterpret_cast<uint8_t*>(mid_base + o_cont);
+      unsigned long long* ccnt = reinterpret_cast<unsigned long long*>(mid_base + o_ccnt);
+      if (incl_mode == 1) rc = inclusion_impl(P, np, &S, dom, incl, scratch, scratch_bytes, st);
+      else rc = mv_impl(P, np, &S, dom, nullptr, nullptr, nullptr, scratch, scratch_bytes, st, 2, incl);
+      if (rc) return rc;
+      VX_HIP(hipMemsetAsync(ccnt, 0, sizeof *ccnt, st));
+      hipLaunchKernelGGL(k_mark_certified, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st, nleaf, keep,
+                         (const uint8_t*)incl, contw, ccnt);
+      VX_CHECK_LAUNCH("k_mark_certified");
+      hipLaunchKernelGGL(k_put_count, dim3(1), dim3(64), 0, st, (const unsigned long long*)ccnt,
+                         counts_dev + 2 * VX_KMAX + 1);
+      VX_CHECK_LAUNCH("k_put_count");
+      cont = contw;
+    }
     if (times) VX_HIP(hipEventRecord(ev[1], st));
     // the filter publishes its counts (and the flag) as soon as they are known
-    if ((rc = filter_impl(&S, keep, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st,
+    if ((rc = filter_impl(&S, cont, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st,
                           counts_dev + 2 * VX_KMAX, (int64_t)level + 1)))
       return rc;
     if (times) VX_HIP(hipEventRecord(ev[2], st));
@@ -507,6 +570,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
         r.kept[l] = K.n[l];
       }
       r.steps = theorem1_steps(P, np, &S);
+      r.certified = incl_on ? counts[2 * VX_KMAX + 1] : 0;
       pending = level;
     }
     if (cb) {

@@ -122,3 +122,34 @@ def test_surface_final_kept_set_sampled(vx, method):
     ref = _ref(w.polys, T, dom, method)[0]
     assert np.array_equal(got[pick], ref), np.flatnonzero(got[pick] != ref)[:5]
     assert 0 < got.sum() < len(got)
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("name,depth,c1_from", [("tiny", 8, 3), ("surface", 6, 3)])
+def test_run_subdivision_with_inclusion_matches_oracle(vx, method, name, depth, c1_from):
+    """Algorithm 3 with C0 and C1 (from level c1_from on): at every level the
+    evaluated CSF, the certified boxes (keep = 2), their count and the
+    continuing CSF equal the oracle's."""
+    from tests.helpers import csf_equal
+    w = getattr(synth, name)()
+    got = {}
+
+    def rec(level, S, lo, hi, keep, K):
+        got[level] = (S, keep.copy(), K)
+        return False
+
+    stats, _ = vx.run_subdivision(w.polys, w.domain(), depth, record=rec, inclusion=method, inclusion_from=c1_from)
+    ref = orc.subdivide_c1(w.polys, w.k, depth, c1_from, dom=w.domain(), nthreads=orc.max_threads(),
+                           taylor=method == "taylor")
+    total = 0
+    for r in ref:
+        L = r["level"]
+        S, keep, K = got[L]
+        assert csf_equal(S, r["S"]), L
+        cert = r["S"]["boxes"][keep == 2]
+        assert np.array_equal(cert, r["certified"]), L
+        assert stats[L]["certified"] == len(r["certified"]), L
+        assert csf_equal(K, orc.csf_from_boxes(r["kept"], L)), L
+        total += len(cert)
+    _say(f"[c1] {name} ({method}) to level {depth}, C1 from {c1_from}: {total} certified boxes")
+    assert total > 0
