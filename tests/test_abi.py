@@ -91,3 +91,25 @@ def test_taylor_arguments_are_checked_before_any_work():
                               None, None, b.LEVEL_CB(), None, None)
     assert rc == b.VX_EINVAL and b"exclusive" in L.vx_last_error()
     assert b.workspace_bytes(b.VX_WS_TAYLOR2) == 0  # invalid arguments give 0
+
+
+def test_inclusion_run_flags_are_checked_before_any_work():
+    """C1 in the loop needs one polynomial, one inclusion form, and an
+    inclusion flag for a threshold level."""
+    import ctypes as C
+    from paper_2406_09857_amd import binding as b
+    L = b.lib()
+    parr = (b.vx_poly * 2)()
+    for i in range(2):
+        parr[i].k, parr[i].degree, parr[i].side = 1, 1, 2
+        parr[i].c_lo = 4096  # never dereferenced
+    dom = (C.c_double * 2)(-1.0, 1.0)
+
+    def run(np_, flags):
+        return L.run_subdivision_ex(parr, np_, dom, 2, flags, C.c_void_p(4096), 1 << 20, None, None, b.LEVEL_CB(),
+                                    None, None)
+
+    assert run(2, b.VX_RUN_INCLUSION) == b.VX_EINVAL and b"one polynomial" in L.vx_last_error()
+    assert run(1, b.VX_RUN_INCLUSION | b.VX_RUN_INCLUSION_TAYLOR) == b.VX_EINVAL
+    assert b"exclusive" in L.vx_last_error()
+    assert run(1, 3 << 16) == b.VX_EINVAL and b"without an inclusion flag" in L.vx_last_error()
