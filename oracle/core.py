@@ -18,7 +18,9 @@ Paper: G. Moroz, arXiv 2406.09857.
     (``taylor2_level``, ``subdivide_t2``).
   * The inclusion criterion C1 of Sec. 3.2 (sign change over the vertices of
     a box, the vertices evaluated by Algorithm 2 on their grid):
-    ``inclusion_level``.
+    ``inclusion_level``; for square systems the Newton interval test
+    (Krawczyk's form, slopes by Algorithm 2 on mixed box/centre grids):
+    ``newton_level``.
 """
 from __future__ import annotations
 
@@ -84,6 +86,9 @@ def lib():
         L.orc_taylor_inclusion.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp, dp,
                                            np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")]
         L.orc_taylor_inclusion.restype = C.c_int
+        L.orc_krawczyk.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp,
+                                   np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS"), dp]
+        L.orc_krawczyk.restype = C.c_int
         L.orc_deriv2.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, C.c_int, dp, dp]
         L.orc_deriv2.restype = C.c_int
         L.orc_taylor2.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp, dp]
@@ -558,3 +563,49 @@ def subdivide_c1(polys, k: int, depth: int, c1_from: int, dom=None, nthreads: in
         if level < depth:
             boxes = children_of(S["boxes"][cont])
     return out
+
+
+def slope_tables(dom: np.ndarray, k: int, level: int, j: int) -> list:
+    """Axis tables of the slope column j: the cells on axes 0..j, the centre
+    enclosures on axes j+1..k-1."""
+    btabs = level_tables(dom, k, level)
+    ctabs = [centre_table(float(dom[a, 0]), float(dom[a, 1]), level) for a in range(k)]
+    return [btabs[a] if a <= j else ctabs[a] for a in range(k)]
+
+
+def newton_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1, degrees=None, want_k: bool = False):
+    """Newton interval test (Krawczyk's form) of a square system (k
+    polynomials in k variables) on every leaf of the CSF: flags (n,) and,
+    with ``want_k``, the enclosures K (n, k, 2).  F at the centre enclosures
+    and the slopes S_ij = dF_i/dx_j on (B_1..B_j, c_{j+1}..c_k) come from
+    Algorithm 2 on the same CSF; ``orc_krawczyk`` combines them."""
+    k, level = csf["k"], csf["level"]
+    assert len(polys) == k, "a square system"
+    dom = np.asarray(dom, np.float64).reshape(k, 2)
+    btabs = level_tables(dom, k, level)
+    ctabs = [centre_table(float(dom[a, 0]), float(dom[a, 1]), level) for a in range(k)]
+    vtabs = [vertex_table(float(dom[a, 0]), float(dom[a, 1]), level) for a in range(k)]
+    boxes = np.asarray(csf["boxes"], np.int64)
+    nb = boxes.shape[0]
+    flags = np.zeros(nb, np.uint8)
+    K = np.zeros((nb, k, 2))
+    if nb == 0:
+        return (flags.astype(bool), K) if want_k else flags.astype(bool)
+    fc = np.zeros((k, nb, 2))
+    Sm = np.zeros((k * k, nb, 2))
+    for i, p in enumerate(polys):
+        d = poly_degree(p) if degrees is None else degrees[i]
+        fl, fh, _ = eval_csf(p, d, csf, ctabs, OUTWARD, nthreads)
+        fc[i, :, 0] = fl; fc[i, :, 1] = fh
+        for j in range(k):
+            if d >= 1:
+                sl, sh, _ = eval_csf(deriv(p, d, j), d - 1, csf, slope_tables(dom, k, level, j), OUTWARD, nthreads)
+                Sm[i * k + j, :, 0] = sl; Sm[i * k + j, :, 1] = sh
+    bx = np.ascontiguousarray(np.stack([btabs[a][boxes[:, a]] for a in range(k)], axis=1))
+    cx = np.ascontiguousarray(np.stack([ctabs[a][boxes[:, a]] for a in range(k)], axis=1))
+    inner = np.ascontiguousarray(np.stack([np.stack([vtabs[a][boxes[:, a], 1], vtabs[a][boxes[:, a] + 1, 0]], axis=1)
+                                           for a in range(k)], axis=1))
+    if lib().orc_krawczyk(k, nb, _dp(np.ascontiguousarray(fc)), _dp(np.ascontiguousarray(Sm)), _dp(bx), _dp(cx),
+                          _dp(inner), flags, _dp(K)):
+        raise ValueError("orc_krawczyk failed")
+    return (flags.astype(bool), K) if want_k else flags.astype(bool)

@@ -26,6 +26,8 @@
  *     comparison), used to pin the amortized routine;
  *   - the mean-value (order-1 Taylor form) enclosure of Sec. 3.2: centre
  *     enclosures, derivative coefficients and the final combination;
+ *   - the Newton interval inclusion test for square systems (Sec. 3.2) in
+ *     Krawczyk's form, from slope enclosures;
  *   - the grid-vertex enclosures of the inclusion criterion C1 (Sec. 3.2) and
  *     its Taylor-based form (order-2 bounds at the two extreme vertices of
  *     the linear part);
@@ -568,6 +570,103 @@ int orc_taylor_inclusion(int k, int64_t nbox, const double* fc, const double* Dc
     ivl tmax = taylor2_at(k, nbox, b, f, Dc, H, Wmax);
     ivl tmin = taylor2_at(k, nbox, b, f, Dc, H, Wmin);
     out[b] = (tmax.lo > 0.0 && tmin.hi < 0.0) ? 1 : 0;
+  }
+  return 0;
+}
+
+/* Newton interval inclusion test for a square system F = (F_1..F_k)
+ * (Sec. 3.2, inclusion criterion for several polynomials), in Krawczyk's
+ * form: with S the slope matrix of the box (S_ij enclosed by dF_i/dx_j on
+ * the box with the first j variables free and the rest at the centre) and
+ * Y = (mid S)^-1,
+ *   K(B) = c - Y F(c) + (I - Y S)(B - c);
+ * K(B) inside B gives a point where Y F = 0, hence F = 0 (Brouwer).  Per box:
+ *   fc[i][b] (2)      F_i(c) enclosure,
+ *   Sm[(i*k+j)][b] (2) S_ij enclosure,
+ *   box, centre       outer box and centre enclosures (b, axis, 2),
+ *   inner             inner box (b, axis, 2): [upper end of the lower vertex
+ *                     enclosure, lower end of the upper vertex enclosure],
+ *                     inside the true box;
+ * Y in round-to-nearest: mid = (lo + hi) * 0.5, Gauss-Jordan with partial
+ * pivoting (first largest |pivot|, rows swapped in A and Y, the pivot row
+ * divided by the pivot, then r -= f * pivot row for r != col, columns in
+ * ascending order); a zero pivot means no certificate.  K in outward
+ * arithmetic: Yf_i = sum_j Y_ij F_j(c) (j ascending), A_ij = delta_ij -
+ * sum_l Y_il S_lj (l ascending), K_i = (c_i - Yf_i) + sum_j A_ij W_j
+ * (j ascending), W_j = B_j - c_j.  out[b] = 1 when every K_i lies in the
+ * inner box; K (b, axis, 2) is written when not NULL. */
+int orc_krawczyk(int k, int64_t nbox, const double* fc, const double* Sm, const double* box, const double* centre,
+                 const double* inner, uint8_t* out, double* K) {
+  if (k < 1 || k > ORC_KMAX) return -1;
+  for (int64_t b = 0; b < nbox; b++) {
+    double A[ORC_KMAX][ORC_KMAX], Y[ORC_KMAX][ORC_KMAX];
+    round_restore();
+    for (int i = 0; i < k; i++)
+      for (int j = 0; j < k; j++) {
+        const double* e = Sm + (((int64_t)(i * k + j)) * nbox + b) * 2;
+        A[i][j] = (e[0] + e[1]) * 0.5;
+        Y[i][j] = i == j ? 1.0 : 0.0;
+      }
+    int ok = 1;
+    for (int col = 0; col < k && ok; col++) {
+      int piv = col;
+      for (int r = col + 1; r < k; r++)
+        if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+      if (!(A[piv][col] != 0.0)) { ok = 0; break; }  /* zero (or NaN) pivot */
+      if (piv != col)
+        for (int j = 0; j < k; j++) {
+          double t = A[col][j]; A[col][j] = A[piv][j]; A[piv][j] = t;
+          t = Y[col][j]; Y[col][j] = Y[piv][j]; Y[piv][j] = t;
+        }
+      const double p = A[col][col];
+      for (int j = 0; j < k; j++) { A[col][j] = A[col][j] / p; Y[col][j] = Y[col][j] / p; }
+      for (int r = 0; r < k; r++) {
+        if (r == col) continue;
+        const double f = A[r][col];
+        for (int j = 0; j < k; j++) {
+          A[r][j] = A[r][j] - f * A[col][j];
+          Y[r][j] = Y[r][j] - f * Y[col][j];
+        }
+      }
+    }
+    int inside = ok;
+    for (int i = 0; i < k; i++) {
+      ivl Ki = {0.0, 0.0};
+      if (ok) {
+        ivl yf = {0.0, 0.0};
+        for (int j = 0; j < k; j++) {
+          ivl fj = {fc[((int64_t)j * nbox + b) * 2], fc[((int64_t)j * nbox + b) * 2 + 1]};
+          ivl yj = {Y[i][j], Y[i][j]};
+          yf = j == 0 ? iv_mul(yj, fj, ORC_OUTWARD) : iv_add(yf, iv_mul(yj, fj, ORC_OUTWARD), ORC_OUTWARD);
+        }
+        const double* c = centre + (b * k + i) * 2;
+        ivl ci = {c[0], c[1]};
+        ivl nyf = {-yf.hi, -yf.lo};
+        Ki = iv_add(ci, nyf, ORC_OUTWARD);
+        for (int j = 0; j < k; j++) {
+          ivl a = {i == j ? 1.0 : 0.0, i == j ? 1.0 : 0.0};
+          for (int l = 0; l < k; l++) {
+            const double* e = Sm + (((int64_t)(l * k + j)) * nbox + b) * 2;
+            ivl sl = {e[0], e[1]};
+            ivl yl = {Y[i][l], Y[i][l]};
+            ivl t = iv_mul(yl, sl, ORC_OUTWARD);
+            ivl nt = {-t.hi, -t.lo};
+            a = iv_add(a, nt, ORC_OUTWARD);
+          }
+          const double* I = box + (b * k + j) * 2;
+          const double* cj = centre + (b * k + j) * 2;
+          ivl W;
+          round_down(ORC_OUTWARD); W.lo = I[0] - cj[1];
+          round_up(ORC_OUTWARD);   W.hi = I[1] - cj[0];
+          round_restore();
+          Ki = iv_add(Ki, iv_mul(a, W, ORC_OUTWARD), ORC_OUTWARD);
+        }
+        const double* in = inner + (b * k + i) * 2;
+        if (!(Ki.lo >= in[0] && Ki.hi <= in[1])) inside = 0;
+      }
+      if (K) { K[(b * k + i) * 2] = Ki.lo; K[(b * k + i) * 2 + 1] = Ki.hi; }
+    }
+    out[b] = (uint8_t)inside;
   }
   return 0;
 }

@@ -865,3 +865,100 @@ def test_subdivision_with_inclusion_covers_the_sphere():
             anc = tuple(x >> (depth - L) for x in t)
             ok = ok or (L, anc) in certs
         assert ok, t
+
+
+# ---------------------------------------------------------------------------
+# Newton interval inclusion test for square systems (Sec. 3.2, Krawczyk form)
+# ---------------------------------------------------------------------------
+
+def _all_boxes(k, level):
+    n = 1 << level
+    return np.array(np.meshgrid(*[np.arange(n)] * k, indexing="ij")).reshape(k, -1).T
+
+
+@pytest.mark.parametrize("A,b", [([[2.0, 0.0], [0.0, 4.0]], [0.3125, -0.75]),
+                                 ([[1.0, 1.0], [0.0, 1.0]], [0.40625, -0.15625])])
+def test_newton_on_linear_systems_closed_form(A, b):
+    """F = A x - b with an exactly invertible dyadic A: S = A, Y = A^-1
+    exactly, I - Y S = 0, so K(B) is the solution point itself; the boxes
+    certified are exactly those whose interior holds it."""
+    k, level = 2, 4
+    A = np.array(A); b = np.array(b)
+    polys = [synth.monomial_poly(2, 1, {(1, 0): A[i, 0], (0, 1): A[i, 1], (0, 0): -b[i]}) for i in range(k)]
+    S = orc.csf_from_boxes(_all_boxes(k, level), level)
+    flags, K = orc.newton_level(polys, S, np.array([-1.0, 1.0] * k), want_k=True)
+    x = np.linalg.solve(A, b)  # dyadic data: exact
+    lo = -1.0 + S["boxes"] / 8.0
+    hi = lo + 1.0 / 8.0
+    want = ((lo <= x) & (x <= hi)).all(axis=1)
+    assert np.array_equal(flags, want) and want.sum() >= 1
+    assert np.all(K[flags, :, 0] == x) and np.all(K[flags, :, 1] == x)
+
+
+def test_newton_certifies_exactly_the_boxes_holding_the_roots():
+    """x^2 + y^2 = 0.3, x = y: roots +-(r, r) with r^2 = 0.15; at every level
+    the certified boxes are the two holding the roots (exact rational test
+    lo^2 < 0.15 < hi^2), none elsewhere."""
+    k = 2
+    F1 = synth.monomial_poly(2, 2, {(2, 0): 1.0, (0, 2): 1.0, (0, 0): -0.3})
+    F2 = synth.monomial_poly(2, 2, {(1, 0): 1.0, (0, 1): -1.0})
+    dom = np.array([-1.0, 1.0] * k)
+    r2 = ex.F(0.3) / 2
+    for level in (3, 5, 7):
+        S = orc.csf_from_boxes(_all_boxes(k, level), level)
+        flags = orc.newton_level([F1, F2], S, dom)
+        h = Fraction(2, 1 << level)
+        for q in np.flatnonzero(flags):
+            bx = [(Fraction(-1) + int(v) * h, Fraction(-1) + (int(v) + 1) * h) for v in S["boxes"][q]]
+            sgn = 1 if bx[0][0] >= 0 else -1
+            for lo_, hi_ in bx:
+                a, c = (lo_, hi_) if sgn > 0 else (-hi_, -lo_)
+                assert a * a < r2 < c * c
+        assert flags.sum() == 2, level
+
+
+def test_newton_gives_nothing_without_a_regular_root():
+    """Parallel lines (no root, singular slope matrix) and two copies of one
+    curve (no isolated root) certify no box."""
+    k, level = 2, 4
+    S = orc.csf_from_boxes(_all_boxes(k, level), level)
+    dom = np.array([-1.0, 1.0] * k)
+    L1 = synth.monomial_poly(2, 1, {(1, 0): 1.0, (0, 1): 1.0})
+    L2 = synth.monomial_poly(2, 1, {(1, 0): 1.0, (0, 1): 1.0, (0, 0): -0.1})
+    assert not orc.newton_level([L1, L2], S, dom).any()
+    C = synth.monomial_poly(2, 2, {(2, 0): 1.0, (0, 2): 1.0, (0, 0): -0.3})
+    assert not orc.newton_level([C, C], S, dom).any()
+
+
+def test_newton_certified_boxes_hold_a_root_random_system():
+    """A random 2 x 2 system of degree 3: from the centre of every certified
+    box, floating-point Newton converges to a root inside the box."""
+    k, d, level = 2, 3, 6
+    polys = synth.small_random(k, d, seed=260, npolys=2)
+    dom = np.array([-1.0, 1.0] * k)
+    recs = orc.subdivide(polys, k, level)
+    S = recs[-1]["S"]
+    flags = orc.newton_level(polys, S, dom)
+    assert flags.sum() > 0
+    h = 2.0 / (1 << level)
+
+    def F(x):
+        return np.array([sum(p[e] * x[0] ** e[0] * x[1] ** e[1] for e in np.ndindex(*p.shape)) for p in polys])
+
+    def J(x):
+        out = np.zeros((2, 2))
+        for i, p in enumerate(polys):
+            for e in np.ndindex(*p.shape):
+                if e[0]:
+                    out[i, 0] += p[e] * e[0] * x[0] ** (e[0] - 1) * x[1] ** e[1]
+                if e[1]:
+                    out[i, 1] += p[e] * e[1] * x[0] ** e[0] * x[1] ** (e[1] - 1)
+        return out
+
+    for q in np.flatnonzero(flags):
+        lo = -1.0 + S["boxes"][q] * h
+        x = lo + h / 2
+        for _ in range(40):
+            x = x - np.linalg.solve(J(x), F(x))
+        assert np.abs(F(x)).max() < 1e-12
+        assert np.all(x >= lo - 1e-9) and np.all(x <= lo + h + 1e-9), (q, x, lo)
