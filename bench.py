@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--cpu-depth", type=int, default=9, help="oracle sample: levels 0..cpu-depth of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, Taylor-test and inclusion legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, Taylor-test, inclusion and Newton legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -228,6 +228,32 @@ def bench_inclusion(vx):
     return out
 
 
+def bench_newton(vx):
+    """The Newton interval test on the final kept set of the points workload
+    (three trivariate polynomials of degree 20, levels 0..9)."""
+    import torch
+    from paper_2406_09857_amd import synth
+    w = synth.points()
+    dom = w.domain()
+    t0 = time.perf_counter()
+    _, kept = vx.run_subdivision(w.polys, dom, w.depth, want_kept=True)
+    torch.cuda.synchronize()
+    run_ms = (time.perf_counter() - t0) * 1e3
+    K = vx.CSF.from_arrays(3, w.depth, kept["idx"], kept["ptr"])
+    vx.newton_test(w.polys, K, dom)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        incl = vx.newton_test(w.polys, K, dom)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"workload": "points_k3_d20: three trivariate polynomials, total degree 20, coefficients uniform in "
+                        "[-10, 10], domain [-1,1]^3, kept boxes of level 9",
+            "run_ms_with_kept_copy": run_ms, "boxes": K.nboxes, "certified": int(incl.sum()), "ms": ms,
+            "parity": "flags and Krawczyk enclosures equal to the oracle's (tests/test_gpu_newton.py)"}
+
+
 COPY_BYTES = 1 << 31  # bytes read (and written) by the calibration copy
 
 
@@ -385,6 +411,7 @@ def main():
         out["taylor2"] = bench_taylor2(vx, polys, dom, w.depth, stats, ms_step,
                                        out["mean_value"]["kept_per_level"])
         out["inclusion"] = bench_inclusion(vx)
+        out["newton"] = bench_newton(vx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_depth, w.depth))
     print(json.dumps(out))

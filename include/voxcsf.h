@@ -98,7 +98,8 @@ enum {
   VX_WS_GRAD = 3,
   VX_WS_MEANVALUE = 4,
   VX_WS_TAYLOR2 = 5,
-  VX_WS_INCLUSION = 6
+  VX_WS_INCLUSION = 6,
+  VX_WS_NEWTON = 7
 };
 size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_csf* S, int64_t n);
 
@@ -215,6 +216,29 @@ int inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* 
  */
 int taylor_inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, void* ws,
                           size_t ws_bytes, void* stream);
+
+/*
+ * newton_test -- the Newton interval inclusion test for a square system
+ * F = (F_1..F_k) (np == k; Sec. 3.2, inclusion criterion for several
+ * polynomials), on every box of S, in Krawczyk's form:
+ *   K(B) = c - Y F(c) + (I - Y S)(B - c),
+ * c the centre enclosure, S the slope matrix of the box (S_ij enclosed by
+ * dF_i/dx_j on the box with x_1..x_j free and x_{j+1}..x_k at the centre,
+ * each column one Algorithm-2 evaluation with cells on the first j axes and
+ * centres on the others), Y = (mid S)^-1 in round-to-nearest (mid =
+ * (lo + hi) * 0.5, Gauss-Jordan with partial pivoting: first largest
+ * |pivot|, pivot row divided by the pivot, r -= f * pivot row), K in outward
+ * arithmetic with every sum in ascending index order.  The box is certified
+ * (F has a zero in it) when every K_i lies in the inner box [upper end of
+ * the lower vertex enclosure, lower end of the upper one]; a zero pivot
+ * certifies nothing.
+ *   incl : device uint8, S->n[k-1]; 1 = certified.
+ *   kout : device double, S->n[k-1] x k x 2 (box, axis, lo/hi), or NULL: K.
+ * Errors as interval_eval_level, VX_EINVAL when np != k; workspace
+ * vx_workspace_bytes(VX_WS_NEWTON, P, np, S, 0).
+ */
+int newton_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, double* kout,
+                void* ws, size_t ws_bytes, void* stream);
 
 /*
  * filter_subdivide -- exclusion filter and bisection (Algorithm 3): prune S

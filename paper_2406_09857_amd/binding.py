@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libvoxcsf.so")
 KMAX = 4
 
 VX_OK, VX_EINVAL, VX_ECAPACITY, VX_EHIP, VX_EOVERFLOW, VX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD, VX_WS_MEANVALUE, VX_WS_TAYLOR2, VX_WS_INCLUSION = range(7)
+VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD, VX_WS_MEANVALUE, VX_WS_TAYLOR2, VX_WS_INCLUSION, VX_WS_NEWTON = range(8)
 VX_RUN_MEAN_VALUE, VX_RUN_TAYLOR2, VX_RUN_NO_TIMES, VX_RUN_INCLUSION, VX_RUN_INCLUSION_TAYLOR = 1, 2, 4, 8, 16
 
 
@@ -87,13 +87,15 @@ def lib():
         L.inclusion_test.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.POINTER(C.c_double), vp, vp,
                                      C.c_size_t, vp]
         L.taylor_inclusion_test.argtypes = L.inclusion_test.argtypes
+        L.newton_test.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.POINTER(C.c_double), vp, vp, vp,
+                                  C.c_size_t, vp]
         L.csf_build.argtypes = [C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(vx_csf), vp, C.c_size_t, vp]
         L.vx_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
         L.vx_profile_end.argtypes = [C.POINTER(vx_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
         L.vx_profile_select.argtypes = [C.c_char_p]
         for f in ("interval_eval_level", "filter_subdivide", "run_subdivision", "run_subdivision_ex", "csf_build",
                   "vx_copy", "vx_profile_begin", "vx_profile_end", "vx_profile_select", "mean_value_exclusion",
-                  "taylor_exclusion", "inclusion_test", "taylor_inclusion_test"):
+                  "taylor_exclusion", "inclusion_test", "taylor_inclusion_test", "newton_test"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -328,6 +330,28 @@ def inclusion_test(polys, csf: CSF, dom, stream=None, taylor: bool = False) -> t
     _check(fn(parr, len(polys), C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)), incl.data_ptr(),
               ws.data_ptr(), ws.numel(), _stream(stream)))
     return incl[:, :nb]
+
+
+def newton_test(polys, csf: CSF, dom, want_k: bool = False, stream=None):
+    """Newton interval test (Krawczyk's form) of a square system on every box:
+    (nboxes,) uint8, 1 where the system certainly has a zero in the box;
+    with ``want_k`` also the enclosures K (nboxes, k, 2)."""
+    polys = as_polys(polys)
+    dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
+    nb = csf.nboxes
+    dev = csf.idx[0].device
+    incl = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+    kout = torch.empty((max(nb, 1), csf.k, 2), dtype=torch.float64, device=dev) if want_k else None
+    parr = _poly_array(polys)
+    s = csf.struct()
+    need = int(lib().vx_workspace_bytes(VX_WS_NEWTON, parr, len(polys), C.byref(s), 0))
+    if need == 0:
+        _check(VX_EINVAL)
+    ws = _ws(need, dev)
+    _check(lib().newton_test(parr, len(polys), C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)),
+                             incl.data_ptr(), kout.data_ptr() if want_k else None, ws.data_ptr(), ws.numel(),
+                             _stream(stream)))
+    return (incl[:nb], kout[:nb]) if want_k else incl[:nb]
 
 
 def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None,

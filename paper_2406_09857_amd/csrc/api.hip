@@ -208,6 +208,9 @@ size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_
     case VX_WS_INCLUSION:
       if (check_csf(S, false) || check_poly(P, np, S->k)) return 0;
       return inclusion_workspace_bytes(P, np, S);
+    case VX_WS_NEWTON:
+      if (check_csf(S, false) || check_poly(P, np, S->k) || np != S->k) return 0;
+      return newton_workspace_bytes(P, np, S);
     case VX_WS_GRAD:
       if (!P || np < 1 || np > PMAX_GRAD || check_poly(P, np, P[0].k)) return 0;
       if (S && check_csf(S, false)) return 0;
@@ -258,6 +261,19 @@ int taylor_inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const d
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
   if ((rc = check_ws(ws))) return rc;
   return mv_impl(P, np, S, dom, nullptr, nullptr, nullptr, ws, ws_bytes, (hipStream_t)stream, 2, incl);
+}
+
+int newton_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, double* kout,
+                void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_csf(S, true))) return rc;
+  if ((rc = check_poly(P, np, S->k))) return rc;
+  if (np != S->k) VX_FAIL(VX_EINVAL, "the Newton test needs a square system (%d polynomials, k = %d)", np, S->k);
+  if ((rc = check_dom(dom, S->k))) return rc;
+  if (S->n[S->k - 1] > 0 && !incl) VX_FAIL(VX_EINVAL, "null output flags");
+  if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
+  if ((rc = check_ws(ws))) return rc;
+  return newton_impl(P, np, S, dom, incl, kout, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, void* ws,

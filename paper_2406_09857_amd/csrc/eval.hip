@@ -1260,6 +1260,23 @@ int prepare_polys(const vx_poly* P, int np, void* ws, size_t ws_bytes, Prepared*
   return VX_OK;
 }
 
+Prepared prepared_subset(const Prepared& Q, const int* idx, int n) {
+  Prepared R;
+  R.k = Q.k;
+  R.np = n;
+  for (int i = 0; i < n; i++) {
+    const int p = idx[i];
+    R.packed[i] = Q.packed[p];
+    R.ttab[i] = Q.ttab[p];
+    R.lens2[i] = Q.lens2[p];
+    R.lens1[i] = Q.lens1[p];
+    R.padlist[i] = Q.padlist[p];
+    R.d[i] = Q.d[p];
+    R.dmax = R.d[i] > R.dmax ? R.d[i] : R.dmax;
+  }
+  return R;
+}
+
 // Middle-stage node count from which tails are packed into full waves.
 constexpr int64_t PACK_MIN_NODES = 8192;
 
@@ -1268,7 +1285,7 @@ struct EvalPlan {
   double* rows[VX_KMAX][VX_MAXPOLY] = {};  // output rows of stage l for polynomial p
   SegPlan seg[VX_KMAX];
   int R = 8;
-  int centre = 0;  // evaluate at the cell centres (degenerate boxes)
+  int mode[VX_KMAX] = {};  // per axis: 0 cells, 1 cell centres, 2 grid vertices (AxisGrid::centre)
 };
 
 static int stage1_blocking(int64_t n0) { return n0 <= 4 ? 1 : n0 <= 16 ? 2 : n0 <= 64 ? 4 : 8; }
@@ -1355,7 +1372,7 @@ static int launch_stage1(const Prepared& Q, int p0, int pn, const vx_csf* S, con
   const int64_t maxseg = sp.maxseg > 0 ? sp.maxseg : 1;
   const int64_t items = maxseg * ny * pn, chunk = maxseg;
   const dim3 grid((unsigned)xcd_grid(items, chunk));
-  const AxisGrid g = make_grid(dom, 0, S->level, E.centre);
+  const AxisGrid g = make_grid(dom, 0, S->level, E.mode[0]);
   const int4* sg = (const int4*)sp.seg;
   const int64_t* ns = (const int64_t*)sp.nseg;
   const int pr = prof_start("k_stage1", units, st);
@@ -1412,7 +1429,7 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
   const SegPlan& sp = E.seg[l];
   const int64_t items = sp.maxseg * gmax * pn;
   dim3 grid((unsigned)xcd_grid(items, NARROW_XCD_CHUNK));
-  const AxisGrid g = make_grid(dom, l, S->level, E.centre);
+  const AxisGrid g = make_grid(dom, l, S->level, E.mode[l]);
   const int pr = prof_start("k_narrow", units, st);
   if (k == 3 && sp.pack) {
     TailLists tl;
@@ -1456,7 +1473,7 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
     units += (double)d * (double)nleaf;
   }
   const SegPlan& sp = E.seg[k - 1];
-  const AxisGrid g = make_grid(dom, k - 1, S->level, E.centre);
+  const AxisGrid g = make_grid(dom, k - 1, S->level, E.mode[k - 1]);
   double* lo_p = lo + (int64_t)p0 * nleaf;
   double* hi_p = hi + (int64_t)p0 * nleaf;
   const int4* sg = (const int4*)sp.seg;
@@ -1489,7 +1506,8 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
 }
 
 int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
-                        void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P, int centre) {
+                        void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P, int centre,
+                        const int* axis_modes) {
   const int k = S->k;
   const int64_t nleaf = S->n[k - 1];
   if (nleaf == 0) return VX_OK;
@@ -1498,7 +1516,7 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
   A.size = ws_bytes;
   EvalPlan E;
   plan_eval(A, E, P, Q.np, S);
-  E.centre = centre;
+  for (int l = 0; l < k; l++) E.mode[l] = axis_modes ? axis_modes[l] : centre;
   if (A.overflow)
     VX_FAIL(VX_ECAPACITY, "interval_eval_level: workspace of %zu bytes is too small (%zu needed)", ws_bytes,
             A.off + 256);
@@ -1511,7 +1529,7 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
     const SegPlan& sp = E.seg[l];
     J.ptr[l] = l == 0 ? nullptr : S->ptr[l - 1];
     J.labels[l] = S->idx[l];
-    J.g[l] = make_grid(dom, l, S->level, centre);
+    J.g[l] = make_grid(dom, l, S->level, E.mode[l]);
     J.Z[l] = sp.Z;
     J.nparent[l] = sp.nparent;
     J.nchild[l] = sp.nchild;

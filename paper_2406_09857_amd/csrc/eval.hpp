@@ -25,9 +25,14 @@ int prepare_polys(const vx_poly* P, int np, void* ws, size_t ws_bytes, Prepared*
 size_t eval_level_bytes(const vx_poly* P, int np, const vx_csf* S);
 // Covers eval_level_bytes of every CSF whose node counts are <= S->n.
 size_t eval_level_bytes_bound(const vx_poly* P, int np, const vx_csf* S);
-// centre = 1 evaluates at the cell centres (degenerate boxes) instead of the cells.
+// centre = 1 evaluates at the cell centres (degenerate boxes) instead of the
+// cells, 2 at the grid vertices; axis_modes (k entries), if given, sets that
+// choice per axis instead.
 int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
-                        void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P, int centre = 0);
+                        void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P, int centre = 0,
+                        const int* axis_modes = nullptr);
+// The tables of polynomials idx[0..n) of Q, as a system of their own.
+Prepared prepared_subset(const Prepared& Q, const int* idx, int n);
 
 size_t eval_workspace_bytes(const vx_poly* P, int np, const vx_csf* S);
 int eval_level_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi,
@@ -58,6 +63,12 @@ void* mv_run_begin(const vx_poly* P, int np, void* ws, size_t bytes, hipStream_t
 int mv_run_level(void* handle, const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi,
                  uint8_t* keep, void* ws, size_t bytes, hipStream_t st);
 void mv_run_end(void* handle);
+
+// Newton interval inclusion test for square systems (meanvalue.hip); kout
+// (nleaf x k x 2, may be null) receives the Krawczyk enclosures.
+size_t newton_workspace_bytes(const vx_poly* P, int np, const vx_csf* S);
+int newton_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, uint8_t* incl, double* kout, void* ws,
+                size_t ws_bytes, hipStream_t st);
 
 // Inclusion criterion C1 (meanvalue.hip).
 size_t inclusion_workspace_bytes(const vx_poly* P, int np, const vx_csf* S);

@@ -802,4 +802,259 @@ int inclusion_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom,
   return VX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Newton interval inclusion test for a square system (Sec. 3.2, inclusion
+// criterion for several polynomials), in Krawczyk's form:
+//   K(B) = c - Y F(c) + (I - Y S)(B - c),   Y = (mid S)^-1,
+// S the slope matrix: S_ij enclosed by dF_i/dx_j on the box with the
+// variables 1..j free and j+1..k at the centre (Algorithm 2 with cell
+// enclosures on the first j+1 axes and centre enclosures on the others).
+// K(B) inside B means x - Y F(x) maps B into itself, so (Brouwer) F has a
+// zero in B.  Y is computed in round-to-nearest by one kernel, K in outward
+// arithmetic by another (each kernel keeps one rounding mode).
+// ---------------------------------------------------------------------------
+
+// Y = (mid S)^-1 per box: mid = (lo + hi) * 0.5, Gauss-Jordan with partial
+// pivoting (first largest |pivot|), rows swapped in both matrices, the
+// pivot row divided by the pivot, then row r -= f * pivot row for every
+// other row; a zero (or NaN) pivot leaves ok = 0.  S_ij sits at
+// ((j * k + i) * nleaf + b), Y_ij is written at ((i * k + j) * nleaf + b).
+__global__ void k_newton_y(int k, int64_t nleaf, const double* __restrict__ s_lo, const double* __restrict__ s_hi,
+                           double* __restrict__ Y, uint8_t* __restrict__ ok) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  double A[VX_KMAX][VX_KMAX], Z[VX_KMAX][VX_KMAX];
+  for (int i = 0; i < k; i++)
+    for (int j = 0; j < k; j++) {
+      const int64_t e = ((int64_t)j * k + i) * nleaf + b;
+      A[i][j] = (s_lo[e] + s_hi[e]) * 0.5;
+      Z[i][j] = i == j ? 1.0 : 0.0;
+    }
+  int good = 1;
+  for (int col = 0; col < k && good; col++) {
+    int piv = col;
+    for (int r = col + 1; r < k; r++)
+      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    if (!(A[piv][col] != 0.0)) {
+      good = 0;
+      break;
+    }
+    if (piv != col)
+      for (int j = 0; j < k; j++) {
+        double t = A[col][j];
+        A[col][j] = A[piv][j];
+        A[piv][j] = t;
+        t = Z[col][j];
+        Z[col][j] = Z[piv][j];
+        Z[piv][j] = t;
+      }
+    const double p = A[col][col];
+    for (int j = 0; j < k; j++) {
+      A[col][j] = A[col][j] / p;
+      Z[col][j] = Z[col][j] / p;
+    }
+    for (int r = 0; r < k; r++) {
+      if (r == col) continue;
+      const double f = A[r][col];
+      for (int j = 0; j < k; j++) {
+        A[r][j] = A[r][j] - f * A[col][j];
+        Z[r][j] = Z[r][j] - f * Z[col][j];
+      }
+    }
+  }
+  for (int i = 0; i < k; i++)
+    for (int j = 0; j < k; j++) Y[((int64_t)i * k + j) * nleaf + b] = good ? Z[i][j] : 0.0;
+  ok[b] = (uint8_t)good;
+}
+
+// Point y times interval (xnl, xh), in (nlo, hi): the product rule with the
+// degenerate interval [y, y].
+__device__ __forceinline__ void point_times(double y, double xnl, double xh, double& rnl, double& rh) {
+  rnl = xnl;
+  rh = xh;
+  step_gen(rnl, rh, cell_ops(opaque(-y), y, CLS_STRADDLE), 0.0, 0.0);
+}
+
+// K(B) per box in outward arithmetic and the test K inside the inner box
+// [upper end of the lower vertex enclosure, lower end of the upper one]
+// (inside the true box): Yf_i = sum_j Y_ij F_j(c), K_i = (c_i - Yf_i) +
+// sum_j A_ij W_j with A_ij = delta_ij - sum_l Y_il S_lj, sums in ascending
+// index order, W_j = B_j - c_j.
+__global__ void k_newton_k(int k, int64_t nleaf, GridSet gs, const int32_t* __restrict__ labels,
+                           const double* __restrict__ fc_lo, const double* __restrict__ fc_hi,
+                           const double* __restrict__ s_lo, const double* __restrict__ s_hi,
+                           const double* __restrict__ Y, const uint8_t* __restrict__ ok, uint8_t* __restrict__ incl,
+                           double* __restrict__ kout) {
+  round_up_mode();
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  double cnl[VX_KMAX], ch[VX_KMAX], in_lo[VX_KMAX], in_hi[VX_KMAX];
+  CellOps W[VX_KMAX];
+  for (int a = 0; a < k; a++) {
+    double inl, ih, vnl, vh;
+    const int32_t lab = labels[b * k + a];
+    cell(gs.cell[a], lab, inl, ih);
+    cell(gs.centre[a], lab, cnl[a], ch[a]);
+    W[a] = cell_ops(ch[a] + inl, ih + cnl[a], CLS_STRADDLE);
+    cell(gs.vertex[a], lab, vnl, vh);
+    in_lo[a] = vh;  // upper end of the lower vertex
+    cell(gs.vertex[a], lab + 1, vnl, vh);
+    in_hi[a] = -opaque(vnl);  // lower end of the upper vertex
+  }
+  const bool good = ok[b] != 0;
+  bool inside = good;
+  for (int i = 0; i < k; i++) {
+    double knl = 0.0, kh = 0.0;
+    if (good) {
+      double ynl = 0.0, yh = 0.0;
+      for (int j = 0; j < k; j++) {
+        const double y = Y[((int64_t)i * k + j) * nleaf + b];
+        double pnl, ph;
+        point_times(y, -opaque(fc_lo[(int64_t)j * nleaf + b]), fc_hi[(int64_t)j * nleaf + b], pnl, ph);
+        if (j == 0) {
+          ynl = pnl;
+          yh = ph;
+        } else {
+          ynl = ynl + pnl;
+          yh = yh + ph;
+        }
+      }
+      knl = cnl[i] + yh;  // c_i - Yf_i
+      kh = ch[i] + ynl;
+      for (int j = 0; j < k; j++) {
+        double anl = i == j ? -1.0 : opaque(-0.0), ah = i == j ? 1.0 : 0.0;
+        for (int l = 0; l < k; l++) {
+          const int64_t e = ((int64_t)j * k + l) * nleaf + b;  // S_lj
+          double tnl, th;
+          point_times(Y[((int64_t)i * k + l) * nleaf + b], -opaque(s_lo[e]), s_hi[e], tnl, th);
+          anl = anl + th;  // a - t
+          ah = ah + tnl;
+        }
+        step_gen(anl, ah, W[j], knl, kh);  // A_ij W_j + K_i
+        knl = anl;
+        kh = ah;
+      }
+      inside = inside && (-opaque(knl) >= in_lo[i]) && (kh <= in_hi[i]);
+    }
+    if (kout) {
+      kout[(b * k + i) * 2] = -opaque(knl);
+      kout[(b * k + i) * 2 + 1] = kh;
+    }
+  }
+  incl[b] = (uint8_t)inside;
+}
+
+struct NewtonPlan {
+  double *fcl, *fch, *sl, *sh, *Y;
+  uint8_t* ok;
+  int32_t* labels;
+  char* scratch;
+  size_t scratch_bytes;
+};
+
+static size_t newton_scratch_bytes(const vx_poly* P, int np, const MvPolys& M, const vx_csf* S) {
+  const int k = S->k;
+  size_t e = eval_level_bytes(P, np, S);
+  for (int j = 0; j < k; j++) {
+    vx_poly col[VX_KMAX];
+    for (int i = 0; i < k; i++) col[i] = M.dp[(size_t)i * k + j];
+    const size_t ej = eval_level_bytes(col, k, S);
+    e = ej > e ? ej : e;
+  }
+  return e;
+}
+
+static void plan_newton(Arena& A, NewtonPlan& N, const vx_poly* P, int np, const MvPolys& M, const vx_csf* S) {
+  const int k = S->k;
+  const size_t nl = (size_t)S->n[k - 1];
+  N.fcl = A.take<double>(np * nl);
+  N.fch = A.take<double>(np * nl);
+  N.sl = A.take<double>((size_t)k * k * nl);
+  N.sh = A.take<double>((size_t)k * k * nl);
+  N.Y = A.take<double>((size_t)k * k * nl);
+  N.ok = A.take<uint8_t>(nl);
+  N.labels = A.take<int32_t>((size_t)k * nl);
+  N.scratch_bytes = newton_scratch_bytes(P, np, M, S);
+  N.scratch = A.take<char>(N.scratch_bytes);
+}
+
+size_t newton_workspace_bytes(const vx_poly* P, int np, const vx_csf* S) {
+  MvPolys M = mv_polys(P, np, 1, nullptr, nullptr, nullptr, nullptr);
+  Arena A;
+  NewtonPlan N;
+  plan_newton(A, N, P, np, M, S);
+  return (mv_run_bytes(P, np, 1) + 255) / 256 * 256 + A.off + 512;
+}
+
+int newton_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, uint8_t* incl, double* kout, void* ws,
+                size_t ws_bytes, hipStream_t st) {
+  const int k = S->k;
+  const int64_t nl = S->n[k - 1];
+  if (nl == 0) return VX_OK;
+  const size_t rb = (mv_run_bytes(P, np, 1) + 255) / 256 * 256;
+  if (rb > ws_bytes) VX_FAIL(VX_ECAPACITY, "Newton test: workspace too small");
+  MvRun R;
+  int rc;
+  if ((rc = mv_run_prepare(P, np, 1, reinterpret_cast<char*>(ws), rb, R, st))) return rc;
+  Arena A;
+  A.base = reinterpret_cast<char*>(ws) + rb;
+  A.size = ws_bytes - rb;
+  NewtonPlan N;
+  plan_newton(A, N, P, np, R.M, S);
+  if (A.overflow) VX_FAIL(VX_ECAPACITY, "Newton test: workspace of %zu bytes is too small", ws_bytes);
+  const int pr = prof_start("newton", (double)nl, st);
+  // F at the centres; slope column j: dF_i/dx_j with cells on axes 0..j and
+  // centres on the others
+  if ((rc = eval_level_prepared(R.QF, S, dom, N.fcl, N.fch, nullptr, N.scratch, N.scratch_bytes, st, P, 1)))
+    return rc;
+  for (int j = 0; j < k; j++) {
+    int idx[VX_KMAX], modes[VX_KMAX];
+    vx_poly col[VX_KMAX];
+    for (int i = 0; i < k; i++) {
+      idx[i] = i * k + j;
+      col[i] = R.M.dp[(size_t)i * k + j];
+    }
+    for (int a = 0; a < k; a++) modes[a] = a <= j ? 0 : 1;
+    const Prepared Qj = prepared_subset(R.QD, idx, k);
+    if ((rc = eval_level_prepared(Qj, S, dom, N.sl + (size_t)j * k * nl, N.sh + (size_t)j * k * nl, nullptr,
+                                  N.scratch, N.scratch_bytes, st, col, 0, modes)))
+      return rc;
+  }
+  CsfView cv;
+  memset(&cv, 0, sizeof cv);
+  for (int l = 0; l < k; l++) {
+    cv.idx[l] = S->idx[l];
+    cv.ptr[l] = S->ptr[l];
+    cv.n[l] = S->n[l];
+  }
+  const unsigned nb = (unsigned)((nl + 255) / 256);
+  hipLaunchKernelGGL(k_leaf_labels, dim3(nb), dim3(256), 0, st, k, cv, N.labels);
+  VX_CHECK_LAUNCH("k_leaf_labels");
+  hipLaunchKernelGGL(k_newton_y, dim3(nb), dim3(256), 0, st, k, nl, (const double*)N.sl, (const double*)N.sh, N.Y,
+                     N.ok);
+  VX_CHECK_LAUNCH("k_newton_y");
+  GridSet gs;
+  memset(&gs, 0, sizeof gs);
+  for (int a = 0; a < k; a++) {
+    AxisGrid g;
+    g.dlo = dom[2 * a];
+    g.dhi = dom[2 * a + 1];
+    g.ndlo = -g.dlo;
+    g.ndhi = -g.dhi;
+    g.level = S->level;
+    g.centre = 0;
+    gs.cell[a] = g;
+    g.centre = 1;
+    gs.centre[a] = g;
+    g.centre = 2;
+    gs.vertex[a] = g;
+  }
+  hipLaunchKernelGGL(k_newton_k, dim3(nb), dim3(256), 0, st, k, nl, gs, (const int32_t*)N.labels,
+                     (const double*)N.fcl, (const double*)N.fch, (const double*)N.sl, (const double*)N.sh,
+                     (const double*)N.Y, (const uint8_t*)N.ok, incl, kout);
+  VX_CHECK_LAUNCH("k_newton_k");
+  prof_stop(pr, st);
+  return VX_OK;
+}
+
 }  // namespace vx

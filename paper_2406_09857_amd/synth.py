@@ -14,6 +14,7 @@ the ones fixed for this implementation:
 
 * ``tiny``   : k=2, d=20, integer coefficients uniform in [-100, 100], depth 8.
 * ``surface``: k=3, d=40, N(0,1) coefficients, depth 9.
+* ``points`` : three polynomials, k=3, d=20, uniform in [-10, 10], depth 9.
 * ``curve``  : two polynomials, k=3, d=100, N(0,1), depth 10 (the paper's
   headline problem: a curve cut out by two trivariate degree-100 equations,
   Sec. 1.2 and Table 1, 3D curves, d=100).
@@ -98,6 +99,15 @@ def curve(seed: int = 3, degree: int = 100, depth: int = 10) -> Workload:
     kids = np.random.SeedSequence(seed).spawn(2)
     polys = [random_poly(3, degree, _gen(s), "normal") for s in kids]
     return Workload(f"curve_k3_d{degree}", 3, depth, polys)
+
+
+def points(seed: int = 6, k: int = 3, degree: int = 20, depth: int = 9) -> Workload:
+    """k polynomials in k variables (isolated points), coefficients uniform
+    in [-10, 10] as in the random-polynomial experiments (Sec. 4.1), depth 9
+    (boxes of width 2^-8 on [-1, 1])."""
+    kids = np.random.SeedSequence(seed).spawn(k)
+    polys = [random_poly(k, degree, _gen(s), "uniform10") for s in kids]
+    return Workload(f"points_k{k}_d{degree}", k, depth, polys)
 
 
 def batch(seed: int = 5, count: int = 64, dmin: int = 10, dmax: int = 60, depth: int = 8) -> Workload:

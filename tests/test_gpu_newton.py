@@ -1,0 +1,111 @@
+"""Newton interval inclusion test (Krawczyk's form, Sec. 3.2) on the GPU
+against the oracle.
+
+Bar: the certification flags and the Krawczyk enclosures K (every endpoint,
+after -0 -> +0) equal the oracle's.  Cases: the circle-line system at
+several levels (every box), random square systems for k = 1..4 with
+interval coefficients on a non-dyadic domain, linear systems, a singular
+system, an empty set, and the `points` workload (three trivariate degree-20
+polynomials): every level-6..9 set of the oracle's subdivision, and the
+final kept set of a GPU run to level 9 (the benchmark's configuration).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import core as orc
+from paper_2406_09857_amd import synth
+from tests.helpers import bits_equal, first_mismatch
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_09857_amd import binding
+    binding.lib()
+    return binding
+
+
+def _check(vx, polys, S, dom, tag, want_k=True):
+    _say(f"[newton] {tag}: level {S['level']} sizes {orc.csf_sizes(S)}")
+    ref, Kref = orc.newton_level(polys, S, dom, nthreads=orc.max_threads(), want_k=True)
+    csf = vx.CSF.from_arrays(S["k"], S["level"], S["idx"], S["ptr"])
+    got, K = vx.newton_test(polys, csf, dom, want_k=True)
+    got = got.cpu().numpy().astype(bool)
+    K = K.cpu().numpy()
+    assert np.array_equal(got, ref), (tag, np.flatnonzero(got != ref)[:5])
+    if want_k:
+        assert bits_equal(K, Kref), (tag, first_mismatch(K, Kref))
+    return int(ref.sum())
+
+
+def _all_boxes(k, level):
+    n = 1 << level
+    return np.array(np.meshgrid(*[np.arange(n)] * k, indexing="ij")).reshape(k, -1).T
+
+
+def test_circle_and_line_every_box(vx):
+    F1 = synth.monomial_poly(2, 2, {(2, 0): 1.0, (0, 2): 1.0, (0, 0): -0.3})
+    F2 = synth.monomial_poly(2, 2, {(1, 0): 1.0, (0, 1): -1.0})
+    for level in (3, 6, 8):
+        S = orc.csf_from_boxes(_all_boxes(2, level), level)
+        assert _check(vx, [F1, F2], S, np.array([-1.0, 1.0] * 2), "circle-line") == 2
+
+
+@pytest.mark.parametrize("k,d,level", [(1, 9, 8), (2, 6, 6), (3, 4, 4), (4, 3, 3)])
+def test_random_square_systems_odd_domain_interval_coefficients(vx, k, d, level):
+    rng = np.random.default_rng(600 + k)
+    c = synth.small_random(k, d, seed=610 + k, npolys=k)
+    polys = [(c[0] - 1e-6 * np.abs(c[0]), c[0] + 1e-6 * np.abs(c[0]))] + c[1:]
+    dom = np.array([-0.7, 1.3] * k)
+    boxes = rng.integers(0, 1 << level, size=(2000, k))
+    S = orc.csf_from_boxes(boxes, level)
+    _check(vx, polys, S, dom, f"k{k}")
+
+
+def test_linear_singular_and_empty(vx):
+    k, level = 2, 4
+    S = orc.csf_from_boxes(_all_boxes(k, level), level)
+    dom = np.array([-1.0, 1.0] * k)
+    lin = [synth.monomial_poly(2, 1, {(1, 0): 1.0, (0, 1): 1.0, (0, 0): -0.40625}),
+           synth.monomial_poly(2, 1, {(0, 1): 1.0, (0, 0): 0.15625})]
+    assert _check(vx, lin, S, dom, "linear") >= 1
+    par = [synth.monomial_poly(2, 1, {(1, 0): 1.0, (0, 1): 1.0}),
+           synth.monomial_poly(2, 1, {(1, 0): 1.0, (0, 1): 1.0, (0, 0): -0.1})]
+    assert _check(vx, par, S, dom, "parallel") == 0
+    E = orc.csf_from_boxes(np.zeros((0, k), np.int64), 5)
+    csf = vx.CSF.from_arrays(k, 5, E["idx"], E["ptr"])
+    assert vx.newton_test(lin, csf, dom).shape == (0,)
+
+
+def test_points_workload_levels_6_to_9(vx):
+    w = synth.points()
+    recs = orc.subdivide(w.polys, 3, 9, nthreads=orc.max_threads())
+    total = 0
+    for r in recs[6:]:
+        total += _check(vx, w.polys, r["S"], w.domain(), "points")
+    assert total > 0
+
+
+def test_points_final_kept_set_of_a_gpu_run(vx):
+    w = synth.points()
+    dom = w.domain()
+    _, kept = vx.run_subdivision(w.polys, dom, w.depth)
+    T = {"k": 3, "level": w.depth, "idx": kept["idx"], "ptr": kept["ptr"]}
+    idx = [np.asarray(a, np.int64) for a in kept["idx"]]
+    ptr = [np.asarray(a, np.int64) for a in kept["ptr"]]
+    up2 = np.searchsorted(ptr[1], np.arange(len(idx[2])), side="right") - 1
+    up1 = np.searchsorted(ptr[0], up2, side="right") - 1
+    T["boxes"] = np.stack([idx[0][up1], idx[1][up2], idx[2]], axis=1)
+    n = _check(vx, w.polys, T, dom, "points final kept")
+    _say(f"[newton] points level {w.depth}: {len(T['boxes'])} kept boxes, {n} certified")
