@@ -248,10 +248,21 @@ def bench_newton(vx):
         incl = vx.newton_test(w.polys, K, dom)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / reps
-    return {"workload": "points_k3_d20: three trivariate polynomials, total degree 20, coefficients uniform in "
-                        "[-10, 10], domain [-1,1]^3, kept boxes of level 9",
-            "run_ms_with_kept_copy": run_ms, "boxes": K.nboxes, "certified": int(incl.sum()), "ms": ms,
-            "parity": "flags and Krawczyk enclosures equal to the oracle's (tests/test_gpu_newton.py)"}
+    out = {"workload": "points_k3_d20: three trivariate polynomials, total degree 20, coefficients uniform in "
+                       "[-10, 10], domain [-1,1]^3, kept boxes of level 9",
+           "run_ms_with_kept_copy": run_ms, "boxes": K.nboxes, "certified": int(incl.sum()), "ms": ms,
+           "parity": "flags and Krawczyk enclosures equal to the oracle's (tests/test_gpu_newton.py)"}
+    # Algorithm 3 with C1 = the Newton test from level 6 on
+    for name, kw in (("loop_plain", {}), ("loop_newton", {"inclusion": "vertices", "inclusion_from": 6})):
+        vx.run_subdivision(w.polys, dom, w.depth, want_kept=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats, _ = vx.run_subdivision(w.polys, dom, w.depth, want_kept=False, **kw)
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_run": (time.perf_counter() - t0) * 1e3,
+                     "certified_per_level": [s_["certified"] for s_ in stats],
+                     "continuing_last_level": stats[-1]["kept"][2]}
+    return out
 
 
 COPY_BYTES = 1 << 31  # bytes read (and written) by the calibration copy

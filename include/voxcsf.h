@@ -295,14 +295,15 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
  * the same way; the two flags are exclusive (VX_EINVAL).  VX_RUN_NO_TIMES
  * records no per-level timing events (stats eval_ms and filter_ms are 0):
  * each event is a packet the stream must pass between the level's kernels.
- * VX_RUN_INCLUSION (C1 by vertex signs, inclusion_test) or
- * VX_RUN_INCLUSION_TAYLOR (its Taylor form, taylor_inclusion_test), with
- * VX_RUN_INCLUSION_FROM(L), run Algorithm 3 with both criteria: from level L
- * on (boxes smaller than the threshold) the boxes kept by C0 that C1
- * certifies join the output and are not bisected; stats certified counts
- * them, the callback sees keep = 2 for them (1: continue, 0: excluded) and K
- * holds the continuing boxes.  One polynomial only (C1 certifies a
- * hypersurface); VX_EINVAL otherwise and for both inclusion flags. */
+ * VX_RUN_INCLUSION (C1: vertex signs, inclusion_test, for one polynomial;
+ * the Newton test, newton_test, for a square system) or
+ * VX_RUN_INCLUSION_TAYLOR (the Taylor form of the vertex test,
+ * taylor_inclusion_test, one polynomial), with VX_RUN_INCLUSION_FROM(L), run
+ * Algorithm 3 with both criteria: from level L on (boxes smaller than the
+ * threshold) the boxes kept by C0 that C1 certifies join the output and are
+ * not bisected; stats certified counts them, the callback sees keep = 2 for
+ * them (1: continue, 0: excluded) and K holds the continuing boxes.
+ * VX_EINVAL for other systems and for both inclusion flags. */
 enum {
   VX_RUN_MEAN_VALUE = 1,
   VX_RUN_TAYLOR2 = 2,

@@ -542,9 +542,11 @@ def subdivide_c1(polys, k: int, depth: int, c1_from: int, dom=None, nthreads: in
     """Algorithm 3 with both criteria: at every level the boxes excluded by C0
     are dropped; from level ``c1_from`` on (boxes smaller than the threshold)
     the kept boxes that satisfy C1 join the output R and are not bisected;
-    the rest are bisected.  One polynomial (C1 certifies a hypersurface).
-    Per level: S, the C0 flags, the certified boxes and the continuing ones."""
-    assert len(polys) == 1, "C1 certifies one polynomial"
+    the rest are bisected.  C1 is the vertex-sign test (or its Taylor form)
+    for one polynomial and the Newton test for a square system.  Per level:
+    S, the C0 flags, the certified boxes and the continuing ones."""
+    newton = len(polys) == k and k >= 2
+    assert len(polys) == 1 or (newton and not taylor), "one polynomial, or a square system"
     dom = np.array([-1.0, 1.0] * k) if dom is None else np.asarray(dom, np.float64)
     boxes = np.zeros((1, k), np.int64)
     out = []
@@ -554,8 +556,11 @@ def subdivide_c1(polys, k: int, depth: int, c1_from: int, dom=None, nthreads: in
         keep = keep_mask(lo, hi)
         incl = np.zeros(len(keep), bool)
         if level >= c1_from and len(keep):
-            fn = taylor_inclusion_level if taylor else inclusion_level
-            incl = fn(polys, S, dom, nthreads)[0]
+            if newton:
+                incl = newton_level(polys, S, dom, nthreads)
+            else:
+                fn = taylor_inclusion_level if taylor else inclusion_level
+                incl = fn(polys, S, dom, nthreads)[0]
         cert = keep & incl
         cont = keep & ~incl
         out.append({"level": level, "S": S, "keep": keep, "certified": S["boxes"][cert],

@@ -393,7 +393,12 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   const int incl_from = (flags >> 16) & 255;
   if ((flags & VX_RUN_INCLUSION) && (flags & VX_RUN_INCLUSION_TAYLOR))
     VX_FAIL(VX_EINVAL, "VX_RUN_INCLUSION and VX_RUN_INCLUSION_TAYLOR are exclusive");
-  if (incl_mode && np != 1) VX_FAIL(VX_EINVAL, "the inclusion criterion certifies one polynomial (np = %d)", np);
+  // C1 of one polynomial: vertex signs (or their Taylor form); of a square
+  // system: the Newton test
+  const bool newton = incl_mode == 1 && np == k && k >= 2;
+  if (incl_mode && np != 1 && !newton)
+    VX_FAIL(VX_EINVAL, "the inclusion criterion needs one polynomial%s (np = %d, k = %d)",
+            incl_mode == 1 ? " or a square system" : "", np, k);
   if (incl_mode == 2 && (rc = check_taylor_polys(np, k, 2))) return rc;
   if (!incl_mode && incl_from) VX_FAIL(VX_EINVAL, "VX_RUN_INCLUSION_FROM without an inclusion flag");
   const bool times = stats && !(flags & VX_RUN_NO_TIMES);
@@ -508,8 +513,10 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     const size_t ews = eval_level_bytes(P, np, &S);
     const size_t fws = filter_workspace_bytes(&S);
     const size_t mws = mv ? mv_level_workspace(P, np, &S, order) : 0;
-    const size_t iws = !incl_on ? 0 : incl_mode == 1 ? inclusion_workspace_bytes(P, np, &S)
-                                                     : mv_workspace_bytes(P, np, &S, 2);
+    const size_t iws = !incl_on ? 0
+                       : newton         ? newton_workspace_bytes(P, np, &S)
+                       : incl_mode == 1 ? inclusion_workspace_bytes(P, np, &S)
+                                        : mv_workspace_bytes(P, np, &S, 2);
     size_t scratch_bytes = ews > fws ? ews : fws;
     scratch_bytes = scratch_bytes > mws ? scratch_bytes : mws;
     scratch_bytes = scratch_bytes > iws ? scratch_bytes : iws;
@@ -556,7 +563,8 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
       uint8_t* incl = reinterpret_cast<uint8_t*>(mid_base + o_incl);
       uint8_t* contw = reinterpret_cast<uint8_t*>(mid_base + o_cont);
       unsigned long long* ccnt = reinterpret_cast<unsigned long long*>(mid_base + o_ccnt);
-      if (incl_mode == 1) rc = inclusion_impl(P, np, &S, dom, incl, scratch, scratch_bytes, st);
+      if (newton) rc = newton_impl(P, np, &S, dom, incl, nullptr, scratch, scratch_bytes, st);
+      else if (incl_mode == 1) rc = inclusion_impl(P, np, &S, dom, incl, scratch, scratch_bytes, st);
       else rc = mv_impl(P, np, &S, dom, nullptr, nullptr, nullptr, scratch, scratch_bytes, st, 2, incl);
       if (rc) return rc;
       VX_HIP(hipMemsetAsync(ccnt, 0, sizeof *ccnt, st));

@@ -109,3 +109,32 @@ def test_points_final_kept_set_of_a_gpu_run(vx):
     T["boxes"] = np.stack([idx[0][up1], idx[1][up2], idx[2]], axis=1)
     n = _check(vx, w.polys, T, dom, "points final kept")
     _say(f"[newton] points level {w.depth}: {len(T['boxes'])} kept boxes, {n} certified")
+
+
+def test_run_subdivision_with_newton_matches_oracle(vx):
+    """Algorithm 3 on the points workload with C1 = the Newton test from
+    level 6 on: every level's CSF, certified boxes and continuing CSF equal
+    the oracle's."""
+    from tests.helpers import csf_equal
+    w = synth.points()
+    depth, c1_from = 9, 6
+    got = {}
+
+    def rec(level, S, lo, hi, keep, K):
+        got[level] = (S, keep.copy(), K)
+        return False
+
+    stats, _ = vx.run_subdivision(w.polys, w.domain(), depth, record=rec, inclusion="vertices",
+                                  inclusion_from=c1_from)
+    ref = orc.subdivide_c1(w.polys, 3, depth, c1_from, dom=w.domain(), nthreads=orc.max_threads())
+    total = 0
+    for r in ref:
+        L = r["level"]
+        S, keep, K = got[L]
+        assert csf_equal(S, r["S"]), L
+        assert np.array_equal(r["S"]["boxes"][keep == 2], r["certified"]), L
+        assert stats[L]["certified"] == len(r["certified"]), L
+        assert csf_equal(K, orc.csf_from_boxes(r["kept"], L)), L
+        total += len(r["certified"])
+    _say(f"[newton] points loop: {total} boxes certified")
+    assert total > 0
