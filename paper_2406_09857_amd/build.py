@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvoxcsf.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "build.hip", "eval.hip", "filter.hip", "grad.hip", "meanvalue.hip"]
+SOURCES = ["api.hip", "build.hip", "eval.hip", "filter.hip", "grad.hip", "criteria.hip"]
 ARCH = os.environ.get("VOXCSF_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,4 +1,6 @@
-// Taylor-form exclusion tests and the inclusion criterion C1.
+// The criteria of Sec. 3.2 beyond C0: Taylor-form exclusion tests (orders 1
+// and 2), the inclusion criterion C1 (vertex signs and its Taylor form) and
+// the Newton interval test for square systems.
 //
 // Mean-value exclusion test: the Taylor form of order 1 (Sec. 3.2 of Moroz,
 // arXiv 2406.09857, Taylor form definition with m = 1),

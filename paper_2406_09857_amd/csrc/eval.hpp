@@ -52,7 +52,7 @@ size_t build_workspace_bytes(int k, int64_t n);
 int build_impl(int k, int level, const int32_t* boxes, int64_t n, vx_csf* out, int64_t* d_counts, void* ws,
                size_t ws_bytes, hipStream_t st);
 
-// Taylor-form exclusion tests of order 1 (mean value) and 2 (meanvalue.hip).
+// Taylor-form exclusion tests of order 1 (mean value) and 2 (criteria.hip).
 size_t mv_workspace_bytes(const vx_poly* P, int np, const vx_csf* S, int order);
 // With `incl` (order 2) the Taylor-based inclusion flags replace the enclosures.
 int mv_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
@@ -64,13 +64,13 @@ int mv_run_level(void* handle, const vx_poly* P, int np, const vx_csf* S, const 
                  uint8_t* keep, void* ws, size_t bytes, hipStream_t st);
 void mv_run_end(void* handle);
 
-// Newton interval inclusion test for square systems (meanvalue.hip); kout
+// Newton interval inclusion test for square systems (criteria.hip); kout
 // (nleaf x k x 2, may be null) receives the Krawczyk enclosures.
 size_t newton_workspace_bytes(const vx_poly* P, int np, const vx_csf* S);
 int newton_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, uint8_t* incl, double* kout, void* ws,
                 size_t ws_bytes, hipStream_t st);
 
-// Inclusion criterion C1 (meanvalue.hip).
+// Inclusion criterion C1 (criteria.hip).
 size_t inclusion_workspace_bytes(const vx_poly* P, int np, const vx_csf* S);
 int inclusion_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, uint8_t* incl, void* ws,
                    size_t ws_bytes, hipStream_t st);
