@@ -320,10 +320,14 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
         sys.exit(2)
+    w, desc = workload(args.workload)
+    # The CPU baseline runs first, before this process touches the GPU, so
+    # that no runtime thread of the GPU legs shares the host cores with it.
+    cpu = cpu_baseline(w, min(args.cpu_depth, w.depth)) if not args.no_cpu_baseline else None
+
     import torch
     from paper_2406_09857_amd import binding as vx
 
-    w, desc = workload(args.workload)
     polys = vx.as_polys(w.polys)
     dom = w.domain()
     ws = torch.empty(6 << 30, dtype=torch.uint8, device="cuda")
@@ -424,7 +428,7 @@ def main():
         out["inclusion"] = bench_inclusion(vx)
         out["newton"] = bench_newton(vx)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, min(args.cpu_depth, w.depth))
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 
