@@ -113,3 +113,13 @@ def test_inclusion_run_flags_are_checked_before_any_work():
     assert run(1, b.VX_RUN_INCLUSION | b.VX_RUN_INCLUSION_TAYLOR) == b.VX_EINVAL
     assert b"exclusive" in L.vx_last_error()
     assert run(1, 3 << 16) == b.VX_EINVAL and b"without an inclusion flag" in L.vx_last_error()
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
+    """No CPU fallback: with the library missing, loading it (which every
+    entry point of the binding does first) raises."""
+    from paper_2406_09857_amd import binding as b
+    monkeypatch.setattr(b, "_lib", None)
+    monkeypatch.setattr(b, "LIB_PATH", str(tmp_path / "libvoxcsf.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        b.lib()
