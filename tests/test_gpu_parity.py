@@ -150,3 +150,15 @@ def test_more_than_eight_polynomials(vx):
     polys = [synth.small_random(3, 4 + (i % 5), seed=900 + i)[0] for i in range(11)]
     S = orc.csf_from_boxes(rng.integers(0, 16, size=(500, 3)), 4)
     _check_level(vx, polys, S, np.array([-1.0, 1.0] * 3), "eleven polynomials")
+
+
+def test_run_without_level_times_gives_the_same_sets(vx):
+    """VX_RUN_NO_TIMES only drops the timing events: every level's counts and
+    the final kept CSF equal those of a timed run (the surface to level 7)."""
+    w = synth.surface()
+    s1, k1 = vx.run_subdivision(w.polys, w.domain(), 7)
+    s2, k2 = vx.run_subdivision(w.polys, w.domain(), 7, level_times=False)
+    assert [(a["n"], a["kept"], a["steps"]) for a in s1] == [(a["n"], a["kept"], a["steps"]) for a in s2]
+    assert all(a["eval_ms"] == 0.0 and a["filter_ms"] == 0.0 for a in s2)
+    assert all(a["eval_ms"] > 0.0 for a in s1)
+    assert csf_equal(k2, k1)
