@@ -318,7 +318,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(sharding by x1 fibres over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     w, desc = workload(args.workload)
     # The CPU baseline runs first, before this process touches the GPU, so

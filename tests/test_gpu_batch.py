@@ -196,8 +196,8 @@ def test_batch_eager_graph_replays_and_autotune_identical(vx):
 
 
 def test_batch_capacity_overflow_is_reported(vx):
-    """Too small capacities: VX_ECAPACITY with the counts needed; the retrying
-    driver then reproduces the roomy run."""
+    """Too small capacities: VX_ECAPACITY with the counts needed; the binding's
+    retry with those counts then reproduces the roomy run."""
     w = synth.batch(count=8, depth=6)
     small = [8, 8 << 6, 64, 256]
     b = vx.Batch(w.systems, w.domain(), 6, cap=small, graph=False)
