@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--cpu-depth", type=int, default=9, help="oracle sample: levels 0..cpu-depth of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, Taylor-test, inclusion and Newton legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, Taylor-test, early-exit, inclusion and Newton legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -181,6 +181,41 @@ def bench_taylor2(vx, polys, dom, depth, plain_stats, plain_ms, mv_stats):
             "mean_value_kept_per_level": mv_stats,
             "plain_kept_per_level": [s["kept"][2] for s in plain_stats],
             "parity": "enclosures bit-identical to the oracle (tests/test_gpu_taylor2.py)"}
+
+
+def bench_early_exit(vx, polys, dom, depth, plain_stats, plain_ms):
+    """Early exit for systems: each polynomial evaluated only on the boxes the
+    earlier ones kept (same kept sets), on the curve and on the points system
+    (three trivariate degree-20 polynomials, levels 0..9)."""
+    import torch
+    from paper_2406_09857_amd import synth
+
+    def timed(ps, dm, dp, **kw):
+        vx.run_subdivision(ps, dm, dp, want_kept=False, level_times=False, **kw)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st, _ = vx.run_subdivision(ps, dm, dp, want_kept=False, level_times=False, **kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps, st
+
+    out = {}
+    for tag, kw in (("curve", {}), ("curve_from_level_9", {"early_exit_from": 9})):
+        ms, st = timed(polys, dom, depth, early_exit=True, **kw)
+        out[tag] = {"ms_per_run": ms, "plain_ms_per_run": plain_ms, "vs_plain": plain_ms / ms,
+                    "steps": sum(s["steps"] for s in st), "plain_steps": sum(s["steps"] for s in plain_stats),
+                    "same_kept_counts": [s["kept"] for s in st] == [s["kept"] for s in plain_stats]}
+    w = synth.points()
+    pp = vx.as_polys(w.polys)
+    ms_p, st_p = timed(pp, w.domain(), w.depth)
+    ms_e, st_e = timed(pp, w.domain(), w.depth, early_exit=True)
+    out["points"] = {"workload": "points_k3_d20, levels 0..9", "ms_per_run": ms_e, "plain_ms_per_run": ms_p,
+                     "vs_plain": ms_p / ms_e, "steps": sum(s["steps"] for s in st_e),
+                     "plain_steps": sum(s["steps"] for s in st_p),
+                     "same_kept_counts": [s["kept"] for s in st_e] == [s["kept"] for s in st_p]}
+    out["parity"] = "kept sets equal to the oracle's, steps equal to Theorem 1 on the survivors (tests/test_gpu_early_exit.py)"
+    return out
 
 
 def bench_inclusion(vx):
@@ -425,6 +460,7 @@ def main():
         out["mean_value"] = bench_mean_value(vx, polys, dom, w.depth, stats, ms_step)
         out["taylor2"] = bench_taylor2(vx, polys, dom, w.depth, stats, ms_step,
                                        out["mean_value"]["kept_per_level"])
+        out["early_exit"] = bench_early_exit(vx, polys, dom, w.depth, stats, ms_step)
         out["inclusion"] = bench_inclusion(vx)
         out["newton"] = bench_newton(vx)
     if not args.no_cpu_baseline:

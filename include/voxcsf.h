@@ -303,15 +303,27 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
  * threshold) the boxes kept by C0 that C1 certifies join the output and are
  * not bisected; stats certified counts them, the callback sees keep = 2 for
  * them (1: continue, 0: excluded) and K holds the continuing boxes.
- * VX_EINVAL for other systems and for both inclusion flags. */
+ * VX_EINVAL for other systems and for both inclusion flags.
+ * VX_RUN_EARLY_EXIT (systems, np >= 2; Sec. 3.2: a box is excluded as soon
+ * as one polynomial excludes it) evaluates polynomial p only on the boxes
+ * that polynomials 0..p-1 kept, compacting the survivors after each one; the
+ * kept sets, and so the whole run, are those of the plain loop.  stats steps
+ * counts the steps actually spent, eval_ms includes the compactions, and the
+ * callback receives lo = hi = keep = NULL (they cover subsets of S).  Each
+ * compaction costs a filter pass and a wait for its counts, which only large
+ * levels repay: with VX_RUN_EARLY_EXIT_FROM(L) the levels below L are
+ * evaluated as without the flag.  It does not combine with the Taylor or
+ * inclusion flags (VX_EINVAL); with one polynomial it has no effect. */
 enum {
   VX_RUN_MEAN_VALUE = 1,
   VX_RUN_TAYLOR2 = 2,
   VX_RUN_NO_TIMES = 4,
   VX_RUN_INCLUSION = 8,
-  VX_RUN_INCLUSION_TAYLOR = 16
+  VX_RUN_INCLUSION_TAYLOR = 16,
+  VX_RUN_EARLY_EXIT = 32
 };
 #define VX_RUN_INCLUSION_FROM(level) ((int32_t)(level) << 16)
+#define VX_RUN_EARLY_EXIT_FROM(level) ((int32_t)(level) << 24)
 int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
                        size_t ws_bytes, size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user,
                        void* stream);

@@ -25,6 +25,7 @@ KMAX = 4
 VX_OK, VX_EINVAL, VX_ECAPACITY, VX_EHIP, VX_EOVERFLOW, VX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD, VX_WS_MEANVALUE, VX_WS_TAYLOR2, VX_WS_INCLUSION, VX_WS_NEWTON = range(8)
 VX_RUN_MEAN_VALUE, VX_RUN_TAYLOR2, VX_RUN_NO_TIMES, VX_RUN_INCLUSION, VX_RUN_INCLUSION_TAYLOR = 1, 2, 4, 8, 16
+VX_RUN_EARLY_EXIT = 32
 
 
 class VxError(RuntimeError):
@@ -357,7 +358,7 @@ def newton_test(polys, csf: CSF, dom, want_k: bool = False, stream=None):
 def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None,
                     ws: torch.Tensor | None = None, want_kept: bool = True, mean_value: bool = False,
                     taylor2: bool = False, level_times: bool = True, inclusion: str | None = None,
-                    inclusion_from: int = 0):
+                    inclusion_from: int = 0, early_exit: bool = False, early_exit_from: int = 0):
     """Algorithm 3 with C0 to `depth`.  Returns (stats, kept) where stats is a
     list of per-level dicts and kept the final level's kept CSF (host numpy).
     ``mean_value`` / ``taylor2`` add the Taylor test of order 1 / 2 to C0;
@@ -365,6 +366,10 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
     filter_ms are then 0).  ``inclusion`` ("vertices" or "taylor") runs
     Algorithm 3 with C1 from level ``inclusion_from`` on: certified boxes
     leave the loop (keep = 2 in ``record``, counted in "certified").
+    ``early_exit`` (systems) evaluates each polynomial only on the boxes the
+    earlier ones kept: the same kept sets, fewer steps; ``record`` then gets
+    lo = hi = keep = None; ``early_exit_from`` keeps the levels below it plain
+    (the compaction pays only on large levels).
 
     ``record(level, S, lo, hi, keep, K)`` is called with device-side views
     (numpy copies) when given; it may return True to stop.
@@ -398,7 +403,9 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
                 Sd = _copy_csf(S.contents)
                 nb = S.contents.n[k - 1]
                 lo_h = np.empty((len(polys), nb)); hi_h = np.empty((len(polys), nb)); kp = np.empty(nb, np.uint8)
-                if nb:
+                if not lo:
+                    lo_h = hi_h = kp = None
+                elif nb:
                     _check(lib().vx_copy(lo_h.ctypes.data, lo, lo_h.nbytes, 0, _stream(stream)))
                     _check(lib().vx_copy(hi_h.ctypes.data, hi, hi_h.nbytes, 0, _stream(stream)))
                     _check(lib().vx_copy(kp.ctypes.data, keep, kp.nbytes, 0, _stream(stream)))
@@ -411,7 +418,11 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
 
     cb = LEVEL_CB(_cb) if (record is not None or want_kept) else LEVEL_CB()
     flags = ((VX_RUN_MEAN_VALUE if mean_value else 0) | (VX_RUN_TAYLOR2 if taylor2 else 0)
-             | (0 if level_times else VX_RUN_NO_TIMES))
+             | (0 if level_times else VX_RUN_NO_TIMES) | (VX_RUN_EARLY_EXIT if early_exit else 0))
+    if early_exit_from:
+        if not early_exit or not 0 < early_exit_from < 64:
+            raise ValueError("early_exit_from needs early_exit and a level in 1..63")
+        flags |= early_exit_from << 24
     if inclusion is not None:
         if inclusion not in ("vertices", "taylor"):
             raise ValueError("inclusion is 'vertices' or 'taylor'")

@@ -387,7 +387,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
   if ((rc = check_ws(ws))) return rc;
   if (flags & ~(VX_RUN_MEAN_VALUE | VX_RUN_TAYLOR2 | VX_RUN_NO_TIMES | VX_RUN_INCLUSION | VX_RUN_INCLUSION_TAYLOR |
-                VX_RUN_INCLUSION_FROM(255)))
+                VX_RUN_EARLY_EXIT | VX_RUN_INCLUSION_FROM(255) | VX_RUN_EARLY_EXIT_FROM(63)))
     VX_FAIL(VX_EINVAL, "unknown flags 0x%x", flags);
   const int incl_mode = (flags & VX_RUN_INCLUSION) ? 1 : (flags & VX_RUN_INCLUSION_TAYLOR) ? 2 : 0;
   const int incl_from = (flags >> 16) & 255;
@@ -407,6 +407,13 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   const int order = (flags & VX_RUN_TAYLOR2) ? 2 : (flags & VX_RUN_MEAN_VALUE) ? 1 : 0;
   const bool mv = order > 0;
   if ((rc = check_taylor_polys(np, k, order))) return rc;
+  // Early exit (systems): polynomial p is evaluated only on the boxes that
+  // polynomials 0..p-1 kept; the kept sets are those of the plain loop.
+  const bool early_on = (flags & VX_RUN_EARLY_EXIT) && np > 1;
+  const int early_from = (flags >> 24) & 63;
+  if ((flags & VX_RUN_EARLY_EXIT) && (mv || incl_mode))
+    VX_FAIL(VX_EINVAL, "VX_RUN_EARLY_EXIT does not combine with the Taylor or inclusion tests");
+  if (!(flags & VX_RUN_EARLY_EXIT) && early_from) VX_FAIL(VX_EINVAL, "VX_RUN_EARLY_EXIT_FROM without VX_RUN_EARLY_EXIT");
   hipStream_t st = (hipStream_t)stream;
   // coefficient tables once for the whole run, at the start of the workspace
   // (followed by the mean-value test's derivative tables when requested)
@@ -520,6 +527,17 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     size_t scratch_bytes = ews > fws ? ews : fws;
     scratch_bytes = scratch_bytes > mws ? scratch_bytes : mws;
     scratch_bytes = scratch_bytes > iws ? scratch_bytes : iws;
+    // early exit: the survivors of polynomials 0..p-1 as CSFs of their own
+    const bool early = early_on && level >= early_from;
+    size_t o_sub[VX_MAXPOLY] = {};
+    if (early) {
+      for (int p = 0; p + 1 < np; p++) o_sub[p] = carve(csf_bytes(k, kcap));
+      for (int p = 0; p < np; p++) {
+        // node counts of the subsets are only known as bounds here
+        const size_t b = eval_level_bytes_bound(P + p, 1, &S);
+        scratch_bytes = scratch_bytes > b ? scratch_bytes : b;
+      }
+    }
     const size_t o_scr = carve(scratch_bytes);
     const size_t mid_bytes = moff;
     const size_t need = s_bytes + n_bytes + mid_bytes;
@@ -551,7 +569,34 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
 
     hipEvent_t* ev = evs + 3 * (level & 1);
     if (times) VX_HIP(hipEventRecord(ev[0], st));
-    if ((rc = eval_level_prepared(Q, &S, dom, lo, hi, keep, scratch, scratch_bytes, st, P))) return rc;
+    // the set the last evaluated polynomial ran on, keep its flags
+    vx_csf cur = S;
+    int64_t steps = 0;
+    if (!early) {
+      if ((rc = eval_level_prepared(Q, &S, dom, lo, hi, keep, scratch, scratch_bytes, st, P))) return rc;
+      steps = theorem1_steps(P, np, &S);
+    }
+    for (int p = 0; early; p++) {
+      const Prepared Qp = prepared_subset(Q, &p, 1);
+      if ((rc = eval_level_prepared(Qp, &cur, dom, lo + (size_t)p * nleaf, hi + (size_t)p * nleaf, keep, scratch,
+                                    scratch_bytes, st, P + p)))
+        return rc;
+      steps += theorem1_steps(P + p, 1, &cur);
+      if (p + 1 == np) break;
+      // the survivors of polynomial p; its own counts come back through the
+      // mapped slot under a flag value of its own (negative: never a level's)
+      vx_csf Kp;
+      csf_place(&Kp, k, level, kcap, mid_base + o_sub[p]);
+      const int64_t fv = -((int64_t)(level + 1) * VX_MAXPOLY + p + 1);
+      if ((rc = filter_impl(&cur, keep, &Kp, nullptr, d_counts, scratch, scratch_bytes, st, counts_dev + 2 * VX_KMAX,
+                            fv)))
+        return rc;
+      if ((rc = wait_for_flag(counts + 2 * VX_KMAX, fv, st))) return rc;
+      for (int l = 0; l < k; l++) Kp.n[l] = counts[l];
+      // nothing left: the final filter runs on cur with these all-zero flags
+      if (Kp.n[k - 1] == 0) break;
+      cur = Kp;
+    }
     if (mv && nleaf > 0) {
       double* mlo = reinterpret_cast<double*>(mid_base + o_mlo);
       double* mhi = reinterpret_cast<double*>(mid_base + o_mhi);
@@ -578,7 +623,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     }
     if (times) VX_HIP(hipEventRecord(ev[1], st));
     // the filter publishes its counts (and the flag) as soon as they are known
-    if ((rc = filter_impl(&S, cont, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st,
+    if ((rc = filter_impl(&cur, cont, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st,
                           counts_dev + 2 * VX_KMAX, (int64_t)level + 1)))
       return rc;
     if (times) VX_HIP(hipEventRecord(ev[2], st));
@@ -593,7 +638,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
         r.n[l] = S.n[l];
         r.kept[l] = K.n[l];
       }
-      r.steps = theorem1_steps(P, np, &S);
+      r.steps = steps;
       r.certified = incl_on ? counts[2 * VX_KMAX + 1] : 0;
       pending = level;
     }
@@ -601,7 +646,8 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
       // the callback reads this level's buffers: let the filter finish first
       if ((rc = finish_times())) return rc;
       VX_HIP(hipStreamSynchronize(st));
-      if (cb(user, level, &S, lo, hi, keep, &K)) break;
+      // early exit: the enclosures and flags cover subsets of S, none is passed
+      if (cb(user, level, &S, early ? nullptr : lo, early ? nullptr : hi, early ? nullptr : keep, &K)) break;
     }
     if (last) break;
     // next becomes S (at the other end)

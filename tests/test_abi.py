@@ -95,7 +95,7 @@ def test_taylor_arguments_are_checked_before_any_work():
 
 def test_inclusion_run_flags_are_checked_before_any_work():
     """C1 in the loop needs one polynomial, one inclusion form, and an
-    inclusion flag for a threshold level."""
+    inclusion flag for a threshold level; the early exit takes neither."""
     import ctypes as C
     from paper_2406_09857_amd import binding as b
     L = b.lib()
@@ -113,6 +113,9 @@ def test_inclusion_run_flags_are_checked_before_any_work():
     assert run(1, b.VX_RUN_INCLUSION | b.VX_RUN_INCLUSION_TAYLOR) == b.VX_EINVAL
     assert b"exclusive" in L.vx_last_error()
     assert run(1, 3 << 16) == b.VX_EINVAL and b"without an inclusion flag" in L.vx_last_error()
+    assert run(1, b.VX_RUN_EARLY_EXIT | b.VX_RUN_INCLUSION) == b.VX_EINVAL
+    assert b"does not combine" in L.vx_last_error()
+    assert run(1, 64) == b.VX_EINVAL and b"unknown flags" in L.vx_last_error()
 
 
 def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
