@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--cpu-depth", type=int, default=9, help="oracle sample: levels 0..cpu-depth of the workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, Taylor-test, early-exit, inclusion and Newton legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, variable-order, Taylor-test, early-exit, inclusion and Newton legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -216,6 +216,22 @@ def bench_early_exit(vx, polys, dom, depth, plain_stats, plain_ms):
                      "same_kept_counts": [s["kept"] for s in st_e] == [s["kept"] for s in st_p]}
     out["parity"] = "kept sets equal to the oracle's, steps equal to Theorem 1 on the survivors (tests/test_gpu_early_exit.py)"
     return out
+
+
+def bench_order(vx, polys, kept):
+    """Theorem 1's cost of the curve's final kept set (level 10) under each of
+    the six orders of the variables, from CSFs built on the device."""
+    import torch
+    K = vx.CSF.from_arrays(kept["k"], kept["level"], kept["idx"], kept["ptr"])
+    vx.variable_order_costs(polys, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    costs = vx.variable_order_costs(polys, K)
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"boxes": int(K.nboxes), "ms_all_orders": ms,
+            "orders": [{"order": list(o), "N": c, "steps": st} for o, c, st in costs],
+            "cheapest": list(min(costs, key=lambda c: c[2])[0]),
+            "parity": "node counts and steps equal to the oracle's (tests/test_gpu_order.py)"}
 
 
 def bench_inclusion(vx):
@@ -457,6 +473,7 @@ def main():
         out["batched"] = bench_batched(vx, reps=5)
         _, kept = vx.run_subdivision(polys, dom, w.depth, want_kept=True)
         out["adjoint"] = bench_adjoint(vx, polys, dom, w.depth, kept)
+        out["variable_order"] = bench_order(vx, polys, kept)
         out["mean_value"] = bench_mean_value(vx, polys, dom, w.depth, stats, ms_step)
         out["taylor2"] = bench_taylor2(vx, polys, dom, w.depth, stats, ms_step,
                                        out["mean_value"]["kept_per_level"])

@@ -99,7 +99,8 @@ enum {
   VX_WS_MEANVALUE = 4,
   VX_WS_TAYLOR2 = 5,
   VX_WS_INCLUSION = 6,
-  VX_WS_NEWTON = 7
+  VX_WS_NEWTON = 7,
+  VX_WS_ORDER = 8
 };
 size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_csf* S, int64_t n);
 
@@ -239,6 +240,29 @@ int taylor_inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const d
  */
 int newton_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, double* kout,
                 void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * variable_order_costs -- Theorem 1's cost of evaluating S under several
+ * orders of the variables (Theorem 1, Sec. 1 "Main Result": the cost sums
+ * the trailing-tuple counts times the node counts N_l(S), and the node
+ * counts depend on which variable each CSF depth holds).  Order o lists,
+ * for each CSF depth l, the axis a = orders[o*k + l] that depth holds (the
+ * default order is 0, 1, ..., k-1); its node counts are those of the CSF of
+ * S's boxes with their labels listed in that order, built on the device.
+ *   orders : host int32, norders x k, each a permutation of 0..k-1
+ *            (1 <= norders <= 24; VX_EINVAL otherwise).
+ *   counts : host int64, norders x k, the node counts N_1..N_k (or NULL).
+ *   steps  : host int64, norders, the interval Horner steps of Theorem 1 for
+ *            the dense total-degree polynomials P (their degrees only; a
+ *            permuted dense simplex is one of the same degree) (or NULL;
+ *            P may then be NULL).
+ * Runs the evaluation with the chosen order by transposing every
+ * polynomial's coefficients the same way (new variable l = old variable
+ * orders[o*k + l]).  Synchronous; VX_EUNSUPPORTED when k * level > 62;
+ * workspace vx_workspace_bytes(VX_WS_ORDER, NULL, 0, S, 0).
+ */
+int variable_order_costs(const vx_poly* P, int32_t np, const vx_csf* S, int32_t norders, const int32_t* orders,
+                         int64_t* counts, int64_t* steps, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * filter_subdivide -- exclusion filter and bisection (Algorithm 3): prune S

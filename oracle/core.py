@@ -305,6 +305,21 @@ def theorem1_steps(k: int, d: int, sizes: list) -> list:
     return [(nt[k - l] - nt[k - l - 1]) * sizes[l] for l in range(k)]
 
 
+def order_costs(boxes: np.ndarray, level: int, degrees: list, orders: list) -> list:
+    """Theorem 1 (Sec. 1, "Main Result") under each order of the variables:
+    the CSF of the boxes with their labels listed in that order (depth l
+    holds axis order[l]), its node counts, and the steps of evaluating dense
+    total-degree polynomials of the given degrees on it.  Returns a list of
+    (order, sizes, steps)."""
+    boxes = np.asarray(boxes).reshape(-1, len(orders[0]))
+    k = boxes.shape[1]
+    out = []
+    for o in orders:
+        sizes = csf_sizes(csf_from_boxes(boxes[:, list(o)], level)) if len(boxes) else [0] * k
+        out.append((tuple(o), sizes, sum(sum(theorem1_steps(k, d, sizes)) for d in degrees)))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Mean-value exclusion (order-1 Taylor form, Sec. 3.2)
 # ---------------------------------------------------------------------------

@@ -23,7 +23,8 @@ LIB_PATH = os.path.join(HERE, "libvoxcsf.so")
 KMAX = 4
 
 VX_OK, VX_EINVAL, VX_ECAPACITY, VX_EHIP, VX_EOVERFLOW, VX_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD, VX_WS_MEANVALUE, VX_WS_TAYLOR2, VX_WS_INCLUSION, VX_WS_NEWTON = range(8)
+(VX_WS_EVAL, VX_WS_FILTER, VX_WS_BUILD, VX_WS_GRAD, VX_WS_MEANVALUE, VX_WS_TAYLOR2, VX_WS_INCLUSION, VX_WS_NEWTON,
+ VX_WS_ORDER) = range(9)
 VX_RUN_MEAN_VALUE, VX_RUN_TAYLOR2, VX_RUN_NO_TIMES, VX_RUN_INCLUSION, VX_RUN_INCLUSION_TAYLOR = 1, 2, 4, 8, 16
 VX_RUN_EARLY_EXIT = 32
 
@@ -91,6 +92,8 @@ def lib():
         L.newton_test.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.POINTER(C.c_double), vp, vp, vp,
                                   C.c_size_t, vp]
         L.csf_build.argtypes = [C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(vx_csf), vp, C.c_size_t, vp]
+        L.variable_order_costs.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.c_int32, vp, vp, vp,
+                                           vp, C.c_size_t, vp]
         L.vx_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
         L.vx_profile_end.argtypes = [C.POINTER(vx_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
         L.vx_profile_select.argtypes = [C.c_char_p]
@@ -353,6 +356,45 @@ def newton_test(polys, csf: CSF, dom, want_k: bool = False, stream=None):
                              incl.data_ptr(), kout.data_ptr() if want_k else None, ws.data_ptr(), ws.numel(),
                              _stream(stream)))
     return (incl[:nb], kout[:nb]) if want_k else incl[:nb]
+
+
+def variable_order_costs(polys, csf: CSF, orders=None, stream=None):
+    """Theorem 1's cost of evaluating the boxes of ``csf`` under each order
+    of the variables (default: all k! orders, lexicographic).  Returns a
+    list of (order, node counts N_1..N_k, interval Horner steps), computed by
+    the library (one CSF build per order on the device)."""
+    import itertools
+    k = csf.k
+    orders = [tuple(o) for o in (orders if orders is not None else itertools.permutations(range(k)))]
+    parr = _poly_array(as_polys(polys)) if polys is not None else None
+    s = csf.struct()
+    need = int(lib().vx_workspace_bytes(VX_WS_ORDER, None, 0, C.byref(s), 0))
+    if need == 0:
+        _check(VX_EINVAL)
+    ws = _ws(need, csf.idx[0].device)
+    oa = np.ascontiguousarray(np.array(orders, np.int32).reshape(len(orders), k))
+    counts = np.zeros((len(orders), k), np.int64)
+    steps = np.zeros(len(orders), np.int64)
+    _check(lib().variable_order_costs(parr, len(polys) if polys is not None else 0, C.byref(s), len(orders),
+                                      oa.ctypes.data, counts.ctypes.data,
+                                      steps.ctypes.data if polys is not None else None,
+                                      ws.data_ptr(), ws.numel(), _stream(stream)))
+    return [(o, [int(x) for x in counts[i]], int(steps[i]) if polys is not None else None)
+            for i, o in enumerate(orders)]
+
+
+def permute_variables(polys, order):
+    """The polynomials with their variables reordered: new variable l is old
+    variable order[l] (the coefficient cubes transposed on the host; interval
+    pairs keep their pairing).  Boxes found for the result map back by
+    listing their labels in the inverse order."""
+    out = []
+    for p in polys:
+        if isinstance(p, tuple):
+            out.append(tuple(np.ascontiguousarray(np.transpose(np.asarray(c), order)) for c in p))
+        else:
+            out.append(np.ascontiguousarray(np.transpose(np.asarray(p), order)))
+    return out
 
 
 def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None,

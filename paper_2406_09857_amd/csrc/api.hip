@@ -208,6 +208,9 @@ size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_
     case VX_WS_INCLUSION:
       if (check_csf(S, false) || check_poly(P, np, S->k)) return 0;
       return inclusion_workspace_bytes(P, np, S);
+    case VX_WS_ORDER:
+      if (check_csf(S, false) || (int64_t)S->k * S->level > 62) return 0;
+      return order_workspace_bytes(S);
     case VX_WS_NEWTON:
       if (check_csf(S, false) || check_poly(P, np, S->k) || np != S->k) return 0;
       return newton_workspace_bytes(P, np, S);
@@ -286,6 +289,36 @@ int inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* 
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
   if ((rc = check_ws(ws))) return rc;
   return inclusion_impl(P, np, S, dom, incl, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int variable_order_costs(const vx_poly* P, int32_t np, const vx_csf* S, int32_t norders, const int32_t* orders,
+                         int64_t* counts, int64_t* steps, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_csf(S, true))) return rc;
+  const int k = S->k;
+  if (norders < 1 || norders > 24 || !orders) VX_FAIL(VX_EINVAL, "need 1..24 axis orders");
+  for (int o = 0; o < norders; o++) {
+    int seen = 0;
+    for (int l = 0; l < k; l++) {
+      const int a = orders[o * k + l];
+      if (a < 0 || a >= k || (seen >> a) & 1) VX_FAIL(VX_EINVAL, "order %d is not a permutation of 0..%d", o, k - 1);
+      seen |= 1 << a;
+    }
+  }
+  if (steps && (rc = check_poly(P, np, k))) return rc;
+  if ((int64_t)k * S->level > 62) VX_FAIL(VX_EUNSUPPORTED, "k * level = %d exceeds the 62-bit key", k * S->level);
+  if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
+  if ((rc = check_ws(ws))) return rc;
+  std::vector<int64_t> c((size_t)norders * k);
+  if ((rc = order_counts_impl(S, norders, orders, c.data(), ws, ws_bytes, (hipStream_t)stream))) return rc;
+  for (int o = 0; o < norders; o++) {
+    vx_csf T = *S;
+    for (int l = 0; l < k; l++) T.n[l] = c[(size_t)o * k + l];
+    if (counts)
+      for (int l = 0; l < k; l++) counts[o * k + l] = T.n[l];
+    if (steps) steps[o] = theorem1_steps(P, np, &T);
+  }
+  return VX_OK;
 }
 
 int filter_subdivide(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,

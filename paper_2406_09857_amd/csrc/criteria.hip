@@ -1059,4 +1059,91 @@ int newton_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, ui
   return VX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Variable order.  Theorem 1's cost sums, over the CSF depths, the trailing
+// tuple counts times the node counts N_l(S), and the node counts depend on
+// which axis each depth holds.  For an order pi (depth l holds axis pi[l])
+// the node counts are those of the CSF built from the boxes' labels listed
+// in that order.
+// ---------------------------------------------------------------------------
+struct AxisOrder {
+  int a[VX_KMAX];
+};
+
+__global__ void k_order_labels(int k, int64_t n, AxisOrder o, const int32_t* __restrict__ in,
+                               int32_t* __restrict__ out) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= n) return;
+  for (int l = 0; l < k; l++) out[b * k + l] = in[b * k + o.a[l]];
+}
+
+struct OrderPlan {
+  int32_t* labels;
+  int32_t* ordered;
+  vx_csf T;
+  size_t build_bytes;
+  char* build_ws;
+};
+
+static void plan_order(Arena& A, OrderPlan& O, const vx_csf* S) {
+  const int k = S->k;
+  const int64_t n = S->n[k - 1] > 0 ? S->n[k - 1] : 1;
+  O.labels = A.take<int32_t>((size_t)n * k);
+  O.ordered = A.take<int32_t>((size_t)n * k);
+  memset(&O.T, 0, sizeof O.T);
+  O.T.k = k;
+  O.T.level = S->level;
+  for (int l = 0; l < k; l++) {
+    O.T.cap[l] = n;
+    O.T.idx[l] = A.take<int32_t>((size_t)n);
+    if (l + 1 < k) O.T.ptr[l] = A.take<int32_t>((size_t)n + 1);
+  }
+  O.build_bytes = build_workspace_bytes(k, n);
+  O.build_ws = A.take<char>(O.build_bytes);
+}
+
+size_t order_workspace_bytes(const vx_csf* S) {
+  Arena A;
+  OrderPlan O;
+  plan_order(A, O, S);
+  return A.off + 256;
+}
+
+int order_counts_impl(const vx_csf* S, int norders, const int32_t* orders, int64_t* counts, void* ws,
+                      size_t ws_bytes, hipStream_t st) {
+  const int k = S->k;
+  const int64_t n = S->n[k - 1];
+  if (n == 0) {
+    for (int i = 0; i < norders * k; i++) counts[i] = 0;
+    return VX_OK;
+  }
+  Arena A;
+  A.base = reinterpret_cast<char*>(ws);
+  A.size = ws_bytes;
+  OrderPlan O;
+  plan_order(A, O, S);
+  if (A.overflow) VX_FAIL(VX_ECAPACITY, "variable_order_costs: workspace of %zu bytes is too small", ws_bytes);
+  CsfView cv;
+  memset(&cv, 0, sizeof cv);
+  for (int l = 0; l < k; l++) {
+    cv.idx[l] = S->idx[l];
+    cv.ptr[l] = S->ptr[l];
+    cv.n[l] = S->n[l];
+  }
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_leaf_labels, dim3(nb), dim3(256), 0, st, k, cv, O.labels);
+  VX_CHECK_LAUNCH("k_leaf_labels");
+  for (int o = 0; o < norders; o++) {
+    AxisOrder ax;
+    memset(&ax, 0, sizeof ax);
+    for (int l = 0; l < k; l++) ax.a[l] = orders[o * k + l];
+    hipLaunchKernelGGL(k_order_labels, dim3(nb), dim3(256), 0, st, k, n, ax, (const int32_t*)O.labels, O.ordered);
+    VX_CHECK_LAUNCH("k_order_labels");
+    int rc;
+    if ((rc = build_impl(k, S->level, O.ordered, n, &O.T, nullptr, O.build_ws, O.build_bytes, st))) return rc;
+    for (int l = 0; l < k; l++) counts[o * k + l] = O.T.n[l];
+  }
+  return VX_OK;
+}
+
 }  // namespace vx

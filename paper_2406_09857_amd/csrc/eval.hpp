@@ -86,4 +86,10 @@ int batch_autotune_impl(vx_batch* H, const vx_batch_tune* cand, int ncand, int r
                         float* level_ms, hipStream_t st);
 void batch_destroy_impl(vx_batch* H);
 
+// Node counts of S's boxes under each axis order (orders: host, norders x k;
+// counts: host, norders x k); synchronizes the stream.
+size_t order_workspace_bytes(const vx_csf* S);
+int order_counts_impl(const vx_csf* S, int norders, const int32_t* orders, int64_t* counts, void* ws,
+                      size_t ws_bytes, hipStream_t st);
+
 }  // namespace vx

@@ -126,3 +126,28 @@ def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
     monkeypatch.setattr(b, "LIB_PATH", str(tmp_path / "libvoxcsf.so"))
     with pytest.raises(RuntimeError, match="missing"):
         b.lib()
+
+
+def test_variable_order_arguments_are_checked_before_any_work():
+    """Orders that are not permutations of 0..k-1, and a count outside
+    1..24, are VX_EINVAL before anything touches the device."""
+    import ctypes as C
+    from paper_2406_09857_amd import binding as b
+    L = b.lib()
+    s = b.vx_csf()
+    s.k = 2
+    s.level = 1
+    for l in range(2):
+        s.n[l] = 0
+        s.cap[l] = 1
+        s.idx[l] = 256  # never dereferenced
+    s.ptr[0] = 512
+    counts = (C.c_int64 * 8)()
+    for bad in ((0, 0), (0, 2), (-1, 1)):
+        o = (C.c_int32 * 2)(*bad)
+        rc = L.variable_order_costs(None, 0, C.byref(s), 1, o, counts, None, C.c_void_p(4096), 1 << 20, None)
+        assert rc == b.VX_EINVAL and b"permutation" in L.vx_last_error()
+    o = (C.c_int32 * 2)(1, 0)
+    assert L.variable_order_costs(None, 0, C.byref(s), 0, o, counts, None, C.c_void_p(4096), 1 << 20,
+                                  None) == b.VX_EINVAL
+    assert b.workspace_bytes(b.VX_WS_ORDER) == 0  # invalid arguments give 0

@@ -1,0 +1,104 @@
+"""GPU parity of the variable-order costs (Theorem 1 under each order of the
+variables) and of a subdivision run in a chosen order.
+
+The node counts of every order come from CSFs the library builds on the
+device; the oracle lists the same boxes' labels in that order and builds
+its CSF on the host.  Counts and steps must be equal.  A run with the
+variables reordered (coefficients transposed) must keep exactly the boxes
+the oracle keeps for the transposed polynomials.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import core as orc
+from paper_2406_09857_amd import synth
+from tests.helpers import csf_equal
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_09857_amd import binding
+    binding.lib()
+    return binding
+
+
+def _dev_csf(vx, S):
+    return vx.CSF.from_arrays(S["k"], S["level"], S["idx"], S["ptr"])
+
+
+def _cases():
+    rng = np.random.default_rng(77)
+    return {
+        "curve_level6": (synth.curve(), 6, None),
+        "tiny_level8": (synth.tiny(), 8, None),
+        "random_k4_level3": (synth.Workload("r4", 4, 3, synth.small_random(4, 5, seed=45, npolys=2)), 3,
+                             rng.integers(0, 8, size=(900, 4))),
+        "single_box_k3": (synth.surface(), 5, np.array([[3, 17, 30]])),
+    }
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_order_costs_match_oracle(vx, name):
+    w, level, boxes = _cases()[name]
+    if boxes is None:
+        boxes = orc.subdivide(w.polys, w.k, level, w.domain(), nthreads=orc.max_threads())[-1]["S"]["boxes"]
+    S = orc.csf_from_boxes(boxes, level)
+    degrees = [orc.poly_degree(p) for p in w.polys]
+    orders = list(itertools.permutations(range(w.k)))
+    _say(f"[order] {name}: {len(S['boxes'])} boxes, {len(orders)} orders")
+    want = orc.order_costs(S["boxes"], level, degrees, orders)
+    got = vx.variable_order_costs(w.polys, _dev_csf(vx, S), orders)
+    assert [(tuple(o), c, st) for o, c, st in got] == want
+    assert got[0][1] == orc.csf_sizes(S)  # the default order is the CSF itself
+    only_counts = vx.variable_order_costs(None, _dev_csf(vx, S), orders[-2:])
+    assert [c for _, c, _ in only_counts] == [c for _, c, _ in want[-2:]]
+
+
+def test_run_in_the_cheapest_order_matches_oracle(vx):
+    """The points system (three trivariate degree-20 polynomials): choose the
+    order with the fewest steps on the level-5 set, then run levels 0..6 in it;
+    every level's kept set equals the oracle's for the transposed
+    polynomials, and mapped back it encloses the same points as a run in the
+    default order (the kept boxes of level 6 in the two runs overlap)."""
+    w = synth.points()
+    recs = orc.subdivide(w.polys, 3, 5, w.domain(), nthreads=orc.max_threads())
+    S5 = recs[-1]["S"]
+    costs = vx.variable_order_costs(w.polys, _dev_csf(vx, S5))
+    best = min(costs, key=lambda c: c[2])[0]
+    _say(f"[order] points: costs {[(o, s) for o, _, s in costs]}, best {best}")
+    tp = [np.ascontiguousarray(np.transpose(p, best)) for p in w.polys]
+    for a, b in zip(vx.permute_variables(w.polys, best), tp):
+        assert np.array_equal(a, b)
+    want = orc.subdivide(tp, 3, 6, w.domain(), nthreads=orc.max_threads())
+    seen = {}
+    stats, kept = vx.run_subdivision(vx.permute_variables(w.polys, best), w.domain(), 6,
+                                     record=lambda lv, S, lo, hi, keep, K: seen.__setitem__(lv, K))
+    for r in want:
+        assert csf_equal(seen[r["level"]], orc.csf_from_boxes(r["kept"], r["level"])), r["level"]
+        assert stats[r["level"]]["steps"] == int(r["steps"].sum())
+    plain = orc.subdivide(w.polys, 3, 6, w.domain(), nthreads=orc.max_threads())[-1]["kept"]
+    inv = np.argsort(best)
+    back = want[-1]["kept"][:, inv]
+    common = set(map(tuple, back)) & set(map(tuple, plain))
+    assert len(common) > 0.5 * min(len(back), len(plain))
+
+
+def test_order_costs_reject_bad_orders(vx):
+    w = synth.tiny()
+    S = orc.csf_from_boxes(np.array([[1, 2], [3, 0]]), 2)
+    with pytest.raises(vx.VxError) as e:
+        vx.variable_order_costs(w.polys, _dev_csf(vx, S), [(0, 0)])
+    assert e.value.code == vx.VX_EINVAL

@@ -962,3 +962,30 @@ def test_newton_certified_boxes_hold_a_root_random_system():
             x = x - np.linalg.solve(J(x), F(x))
         assert np.abs(F(x)).max() < 1e-12
         assert np.all(x >= lo - 1e-9) and np.all(x <= lo + h + 1e-9), (q, x, lo)
+
+
+def test_order_costs_closed_forms():
+    """Node counts under each variable order for sets whose CSFs are known in
+    closed form: the full grid (2^{(l+1)L} nodes at depth l whatever the
+    order), a slab x1 = const (one node at depth 1 only when x1 comes first),
+    a line along x3 (2^L nodes from the depth that holds x3 on)."""
+    import itertools
+    L = 3
+    n = 1 << L
+    grid = np.array(list(itertools.product(range(n), repeat=3)))
+    orders = list(itertools.permutations(range(3)))
+    for o, sizes, steps in orc.order_costs(grid, L, [5], orders):
+        assert sizes == [n, n * n, n ** 3]
+        assert steps == sum(orc.theorem1_steps(3, 5, sizes))
+    slab = grid[grid[:, 0] == 2]
+    got = {o: sz for o, sz, _ in orc.order_costs(slab, L, [1], orders)}
+    assert got[(0, 1, 2)] == [1, n, n * n] and got[(0, 2, 1)] == [1, n, n * n]
+    assert got[(1, 2, 0)] == [n, n * n, n * n] and got[(2, 0, 1)] == [n, n, n * n]
+    line = grid[(grid[:, 0] == 5) & (grid[:, 1] == 1)]
+    got = {o: sz for o, sz, _ in orc.order_costs(line, L, [1], orders)}
+    assert got[(0, 1, 2)] == [1, 1, n] and got[(2, 0, 1)] == [n, n, n] and got[(0, 2, 1)] == [1, n, n]
+    # steps: degree 1 has Nt_m = m + 1, so one step per node at every depth;
+    # degree 2 has Nt = (1, 3, 6, 10): 4, 3, 2 steps per node at depths 1, 2, 3
+    assert [s for o, _, s in orc.order_costs(line, L, [1], [(0, 1, 2), (2, 0, 1)])] == [1 + 1 + n, n + n + n]
+    assert [s for o, _, s in orc.order_costs(line, L, [2], [(0, 1, 2), (2, 0, 1)])] == [4 + 3 + 2 * n, 4 * n + 3 * n + 2 * n]
+    assert orc.order_costs(np.zeros((0, 3), np.int64), L, [4], orders[:1])[0][1:] == ([0, 0, 0], 0)
