@@ -49,6 +49,12 @@ def _early_steps(polys, k, rec):
     return total
 
 
+def _interval_system():
+    a, b = synth.small_random(3, 6, seed=47, npolys=2)
+    rad = np.abs(synth.small_random(3, 6, seed=48)[0]) * 1e-2
+    return [(a - rad, a + rad), b]
+
+
 def _systems():
     pos = synth.monomial_poly(2, 2, {(2, 0): 1.0, (0, 2): 1.0, (0, 0): 1.0})  # > 0 off level 0
     return {
@@ -56,6 +62,8 @@ def _systems():
         "points_k3_d20": (synth.points(), 6),
         "random_k2_np3": (synth.Workload("r2", 2, 8, synth.small_random(2, 7, seed=41, npolys=3)), 8),
         "random_k4_np2": (synth.Workload("r4", 4, 4, synth.small_random(4, 4, seed=43, npolys=2)), 4),
+        # interval coefficients on a non-dyadic domain
+        "interval_k3_odd_domain": (synth.Workload("iv", 3, 6, _interval_system(), dom=(-0.7, 1.3)), 6),
         # disjoint planes: the second polynomial empties the first one's survivors
         "disjoint_planes": (synth.Workload("pl", 3, 6, [synth.plane_x1(3, 0.3), synth.plane_x1(3, -0.45)]), 6),
         # the first polynomial excludes every box of level 1: the later ones never run
