@@ -102,3 +102,23 @@ def test_order_costs_reject_bad_orders(vx):
     with pytest.raises(vx.VxError) as e:
         vx.variable_order_costs(w.polys, _dev_csf(vx, S), [(0, 0)])
     assert e.value.code == vx.VX_EINVAL
+
+
+def test_run_permuted_interval_system(vx):
+    """Interval coefficients on a non-dyadic domain, variables reordered
+    (x3, x1, x2): every level's kept set equals the oracle's for the
+    transposed pairs."""
+    a, b = synth.small_random(3, 5, seed=51, npolys=2)
+    rad = np.abs(synth.small_random(3, 5, seed=52)[0]) * 1e-2
+    polys = [(a - rad, a + rad), b]
+    order = (2, 0, 1)
+    tp = [(np.ascontiguousarray(np.transpose(a - rad, order)), np.ascontiguousarray(np.transpose(a + rad, order))),
+          np.ascontiguousarray(np.transpose(b, order))]
+    dom = np.array([-0.7, 1.3] * 3)
+    want = orc.subdivide(tp, 3, 5, dom, nthreads=orc.max_threads())
+    seen = {}
+    vx.run_subdivision(vx.permute_variables(polys, order), dom, 5,
+                       record=lambda lv, S, lo, hi, keep, K: seen.__setitem__(lv, K))
+    for r in want:
+        if len(r["S"]["boxes"]):
+            assert csf_equal(seen[r["level"]], orc.csf_from_boxes(r["kept"], r["level"])), r["level"]

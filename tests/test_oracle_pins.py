@@ -989,3 +989,18 @@ def test_order_costs_closed_forms():
     assert [s for o, _, s in orc.order_costs(line, L, [1], [(0, 1, 2), (2, 0, 1)])] == [1 + 1 + n, n + n + n]
     assert [s for o, _, s in orc.order_costs(line, L, [2], [(0, 1, 2), (2, 0, 1)])] == [4 + 3 + 2 * n, 4 * n + 3 * n + 2 * n]
     assert orc.order_costs(np.zeros((0, 3), np.int64), L, [4], orders[:1])[0][1:] == ([0, 0, 0], 0)
+
+
+def test_order_costs_count_distinct_prefixes():
+    """Remark 1: N_l of a box set is the number of distinct l-prefixes of its
+    label tuples; under an axis order the prefixes are taken in that order.
+    Counted here with Python sets on random sets for k = 2..4."""
+    import itertools
+    rng = np.random.default_rng(123)
+    for k, L, n in ((2, 5, 300), (3, 4, 700), (4, 3, 900)):
+        boxes = rng.integers(0, 1 << L, size=(n, k))
+        orders = list(itertools.permutations(range(k)))
+        for o, sizes, steps in orc.order_costs(boxes, L, [3, 7], orders):
+            want = [len({tuple(b[list(o[:l + 1])]) for b in boxes}) for l in range(k)]
+            assert sizes == want, (k, o)
+            assert steps == sum(orc.theorem1_steps(k, 3, want)) + sum(orc.theorem1_steps(k, 7, want))
