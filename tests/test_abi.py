@@ -151,3 +151,13 @@ def test_variable_order_arguments_are_checked_before_any_work():
     assert L.variable_order_costs(None, 0, C.byref(s), 0, o, counts, None, C.c_void_p(4096), 1 << 20,
                                   None) == b.VX_EINVAL
     assert b.workspace_bytes(b.VX_WS_ORDER) == 0  # invalid arguments give 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with status 2 and says why,
+    before it imports torch or touches a device."""
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2", "--no-cpu-baseline"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and not r.stdout.strip()
