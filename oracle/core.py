@@ -14,8 +14,9 @@ Paper: G. Moroz, arXiv 2406.09857.
     fixed depth: ``subdivide``.  C0(F, B) is "0 not in []F(B)" (Sec. 3.2); a
     system is excluded when any of its polynomials excludes 0.
   * The Taylor form of Sec. 3.2 as an exclusion test: order 1 (the mean-value
-    form, ``mean_value_level``, ``subdivide_mv``) and order 2
-    (``taylor2_level``, ``subdivide_t2``).
+    form, ``mean_value_level``, ``subdivide_mv``), order 2
+    (``taylor2_level``, ``subdivide_t2``) and any order m
+    (``taylor_m_level``, ``subdivide_tm``).
   * The inclusion criterion C1 of Sec. 3.2 (sign change over the vertices of
     a box, the vertices evaluated by Algorithm 2 on their grid):
     ``inclusion_level``; for square systems the Newton interval test
@@ -25,6 +26,7 @@ Paper: G. Moroz, arXiv 2406.09857.
 from __future__ import annotations
 
 import ctypes as C
+import itertools
 import math
 import os
 import subprocess
@@ -93,6 +95,11 @@ def lib():
         L.orc_deriv2.restype = C.c_int
         L.orc_taylor2.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp, dp]
         L.orc_taylor2.restype = C.c_int
+        i32p = C.POINTER(C.c_int32)
+        L.orc_taylor_coef.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, i32p, dp, dp]
+        L.orc_taylor_coef.restype = C.c_int
+        L.orc_taylor_m.argtypes = [C.c_int, C.c_int, i32p, C.c_int64, dp, dp, dp, dp]
+        L.orc_taylor_m.restype = C.c_int
         _lib = L
     return _lib
 
@@ -468,6 +475,92 @@ def subdivide_t2(polys, k: int, depth: int, dom=None, nthreads: int = 1):
         keep = keep_mask(lo, hi) & keep_mask(tlo, thi)
         K = S["boxes"][keep]
         out.append({"level": level, "S": S, "lo": lo, "hi": hi, "t2_lo": tlo, "t2_hi": thi, "keep": keep,
+                    "kept": K})
+        if level < depth:
+            boxes = children_of(K)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Taylor form of any order m (Sec. 3.2, Taylor form definition)
+# ---------------------------------------------------------------------------
+
+def taylor_multi_indices(k: int, m: int) -> list:
+    """The terms of the order-m form in the order they are summed: (j, alpha)
+    for j = 0..m, the multi-indices of order j as the non-decreasing index
+    tuples i_1 <= ... <= i_j in lexicographic order (j = 1: the axes; j = 2:
+    the pairs of ``taylor_pairs``)."""
+    out = []
+    for j in range(m + 1):
+        for tup in itertools.combinations_with_replacement(range(k), j):
+            alpha = [0] * k
+            for i in tup:
+                alpha[i] += 1
+            out.append((j, tuple(alpha)))
+    return out
+
+
+def taylor_coef(poly, d: int, alpha):
+    """Outward-rounded coefficient cubes (lo, hi) of D^alpha F / alpha!: entry
+    e is prod_i C(e_i + alpha_i, alpha_i) c_{e + alpha} (same side)."""
+    lo, hi, k, cube = _coef(poly)
+    a = (C.c_int32 * k)(*alpha)
+    olo = np.zeros_like(lo); ohi = np.zeros_like(lo)
+    rc = lib().orc_taylor_coef(k, d, cube, _dp(lo), _dp(hi), a, _dp(olo), _dp(ohi))
+    if rc == -2:
+        raise ValueError("Taylor coefficient multiplier reaches 2^53 (not exact in double)")
+    if rc:
+        raise ValueError("orc_taylor_coef failed")
+    return olo, ohi
+
+
+def taylor_m_level(polys, csf: dict, dom: np.ndarray, m: int, nthreads: int = 1, degrees=None):
+    """Order-m Taylor enclosures (lo, hi: (npolys, n)) on every leaf of the
+    CSF: the terms of orders 0..m-1 at the centre enclosures, those of order
+    m on the boxes, every one by Algorithm 2 on the same CSF (a term whose
+    order exceeds the degree is zero), combined by ``orc_taylor_m``."""
+    k, level = csf["k"], csf["level"]
+    dom = np.asarray(dom, np.float64).reshape(k, 2)
+    btabs = level_tables(dom, k, level)
+    ctabs = [centre_table(float(dom[j, 0]), float(dom[j, 1]), level) for j in range(k)]
+    boxes = np.asarray(csf["boxes"], np.int64)
+    nb = boxes.shape[0]
+    bx = np.stack([btabs[j][boxes[:, j]] for j in range(k)], axis=1) if nb else np.zeros((0, k, 2))
+    cx = np.stack([ctabs[j][boxes[:, j]] for j in range(k)], axis=1) if nb else np.zeros((0, k, 2))
+    bx = np.ascontiguousarray(bx); cx = np.ascontiguousarray(cx)
+    terms = taylor_multi_indices(k, m)
+    alphas = np.ascontiguousarray(np.array([a for _, a in terms], np.int32).reshape(-1))
+    los, his = [], []
+    for jp, p in enumerate(polys):
+        d = poly_degree(p) if degrees is None else degrees[jp]
+        T = np.zeros((len(terms), nb, 2))
+        for t, (j, alpha) in enumerate(terms):
+            if j > d:
+                continue
+            coef = p if j == 0 else taylor_coef(p, d, alpha)
+            tl, th, _ = eval_csf(coef, d - j, csf, btabs if j == m else ctabs, OUTWARD, nthreads)
+            T[t, :, 0] = tl; T[t, :, 1] = th
+        out = np.zeros((nb, 2))
+        if nb and lib().orc_taylor_m(k, len(terms), alphas.ctypes.data_as(C.POINTER(C.c_int32)), nb,
+                                     _dp(np.ascontiguousarray(T)), _dp(bx), _dp(cx), _dp(out)):
+            raise ValueError("orc_taylor_m failed")
+        los.append(out[:, 0]); his.append(out[:, 1])
+    return np.array(los).reshape(len(polys), -1), np.array(his).reshape(len(polys), -1)
+
+
+def subdivide_tm(polys, k: int, depth: int, m: int, dom=None, nthreads: int = 1):
+    """Algorithm 3 with the exclusion C0 and the order-m Taylor test together:
+    a box is dropped when, for some polynomial, either enclosure excludes 0."""
+    dom = np.array([-1.0, 1.0] * k) if dom is None else np.asarray(dom, np.float64)
+    boxes = np.zeros((1, k), np.int64)
+    out = []
+    for level in range(depth + 1):
+        S = csf_from_boxes(boxes, level)
+        lo, hi, steps = eval_level(polys, S, dom, nthreads)
+        tlo, thi = taylor_m_level(polys, S, dom, m, nthreads)
+        keep = keep_mask(lo, hi) & keep_mask(tlo, thi)
+        K = S["boxes"][keep]
+        out.append({"level": level, "S": S, "lo": lo, "hi": hi, "tm_lo": tlo, "tm_hi": thi, "keep": keep,
                     "kept": K})
         if level < depth:
             boxes = children_of(K)

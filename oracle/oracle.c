@@ -34,7 +34,10 @@
  *   - the order-2 Taylor form of Sec. 3.2 (Taylor form definition, m = 2):
  *     second-derivative coefficients (halved on the diagonal) and the
  *     combination F(c) + sum_i dF/dx_i(c) W_i + sum_{i<=j} H_ij(B) W_i W_j,
- *     W_i = B_i - c_i, with the diagonal products taken as interval squares.
+ *     W_i = B_i - c_i, with the diagonal products taken as interval squares;
+ *   - the Taylor form of any order m (the same definition): the coefficient
+ *     polynomials D^alpha F / alpha! of every multi-index, the ranges of the
+ *     powers (x_i - c_i)^a over the box, and the combination.
  *
  * Rounding is set with fesetround() around each batch of endpoint
  * computations; the file is compiled with clang -ffp-model=strict so that the
@@ -517,6 +520,133 @@ int orc_taylor2(int k, int64_t nbox, const double* fc, const double* Dc, const d
         ivl Ht = {H[((int64_t)t * nbox + b) * 2], H[((int64_t)t * nbox + b) * 2 + 1]};
         acc = iv_add(acc, iv_mul(Ht, X, ORC_OUTWARD), ORC_OUTWARD);
       }
+    out[2 * b] = acc.lo; out[2 * b + 1] = acc.hi;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Taylor form of general order m (Sec. 3.2, Taylor form definition).  */
+/* ------------------------------------------------------------------ */
+
+/* In k variables the term of order j of the Taylor expansion at c is
+ * sum_{|alpha| = j} (D^alpha F / alpha!) (x - c)^alpha (the multinomial form
+ * of F^(j)(c) (x - c)^j / j!).  The coefficient polynomial D^alpha F / alpha!
+ * has entry e = prod_i C(e_i + alpha_i, alpha_i) * c_{e + alpha}: an exact
+ * integer times the coefficient, rounded outward once.  The integer must stay
+ * below 2^53 (exact in double); -2 otherwise.  Output cube of the same side;
+ * entries with |e| > d - |alpha| are zero.  |alpha| = 1 gives orc_deriv's
+ * coefficients, |alpha| = 2 orc_deriv2's. */
+static int64_t binom_exact(int n, int r) {
+  int64_t v = 1;
+  for (int i = 1; i <= r; i++) v = v * (n - r + i) / i;
+  return v;
+}
+
+int orc_taylor_coef(int k, int d, int cube, const double* clo, const double* chi, const int* alpha, double* olo,
+                    double* ohi) {
+  if (k < 1 || k > ORC_KMAX || cube < d + 1) return -1;
+  int order = 0;
+  int64_t shift = 0;
+  for (int i = 0; i < k; i++) {
+    if (alpha[i] < 0) return -1;
+    order += alpha[i];
+    shift += alpha[i] * ipow(cube, k - 1 - i);
+  }
+  int64_t total = ipow(cube, k);
+  for (int64_t f = 0; f < total; f++) {
+    int64_t q = f; int deg = 0; int e[ORC_KMAX];
+    for (int a = k - 1; a >= 0; a--) { e[a] = (int)(q % cube); q /= cube; deg += e[a]; }
+    olo[f] = 0.0; ohi[f] = 0.0;
+    if (deg + order > d) continue;
+    /* prod_i C(e_i + alpha_i, alpha_i), checked against 2^53 */
+    double m = 1.0;
+    for (int i = 0; i < k; i++) {
+      const int64_t b = binom_exact(e[i] + alpha[i], alpha[i]);
+      m *= (double)b;
+      if (m >= 9007199254740992.0) return -2;
+    }
+    int64_t src = f + shift;
+    round_down(ORC_OUTWARD); olo[f] = m * clo[src];
+    round_up(ORC_OUTWARD);   ohi[f] = m * (chi ? chi[src] : clo[src]);
+    round_restore();
+  }
+  return 0;
+}
+
+/* Range of x^a over X (a >= 0), rounded outward: the power of one variable,
+ * not the product X*X*...*X.  Powers of nonnegative values are formed left
+ * to right by repeated multiplication (p <- p*v) in the direction of the
+ * bound; odd powers are increasing, even powers have their minimum at the
+ * point of X closest to 0. */
+static double pow_up(double v, int a) { /* RU(v^a), v >= 0 */
+  round_up(ORC_OUTWARD);
+  double p = v;
+  for (int i = 1; i < a; i++) p = p * v;
+  round_restore();
+  return p;
+}
+static double pow_down(double v, int a) { /* RD(v^a), v >= 0 */
+  round_down(ORC_OUTWARD);
+  double p = v;
+  for (int i = 1; i < a; i++) p = p * v;
+  round_restore();
+  return p;
+}
+
+static ivl iv_pow(ivl x, int a) {
+  ivl r;
+  if (a == 0) { r.lo = 1.0; r.hi = 1.0; return r; }
+  if (a == 1) return x;
+  if (a % 2 == 1) {
+    r.lo = x.lo >= 0.0 ? pow_down(x.lo, a) : -pow_up(-x.lo, a);
+    r.hi = x.hi >= 0.0 ? pow_up(x.hi, a) : -pow_down(-x.hi, a);
+  } else if (x.lo >= 0.0) {
+    r.lo = pow_down(x.lo, a); r.hi = pow_up(x.hi, a);
+  } else if (x.hi <= 0.0) {
+    r.lo = pow_down(-x.hi, a); r.hi = pow_up(-x.lo, a);
+  } else {
+    r.lo = 0.0; r.hi = pow_up(fmax(-x.lo, x.hi), a);
+  }
+  return r;
+}
+
+/* The order-m Taylor form per box b from the enclosures of its terms:
+ * terms[t][b] (2) for t = 0..nt-1, the multi-indices alpha[t] (k each) in the
+ * order of the sum: |alpha| = 0 (F(c)) first, then orders 1..m, each order's
+ * multi-indices as the non-decreasing index tuples i_1 <= ... <= i_j in
+ * lexicographic order.  With W_i = B_i - c_i = [RD(lo_i - chi_i),
+ * RU(hi_i - clo_i)] from box[b][i] and centre[b][i] (2 each),
+ *   out[b] = terms_0 + sum_{t >= 1} terms_t X_t,
+ *   X_t = prod_i W_i^alpha_i (ranges of powers, multiplied over ascending i),
+ * summed left to right.  The caller evaluates the terms of orders below m
+ * at the centre and those of order m over the box. */
+int orc_taylor_m(int k, int nt, const int* alpha, int64_t nbox, const double* terms, const double* box,
+                 const double* centre, double* out) {
+  if (k < 1 || k > ORC_KMAX || nt < 1) return -1;
+  for (int64_t b = 0; b < nbox; b++) {
+    ivl W[ORC_KMAX];
+    for (int i = 0; i < k; i++) {
+      const double* I = box + (b * k + i) * 2;
+      const double* c = centre + (b * k + i) * 2;
+      round_down(ORC_OUTWARD); W[i].lo = I[0] - c[1];
+      round_up(ORC_OUTWARD);   W[i].hi = I[1] - c[0];
+      round_restore();
+    }
+    ivl acc = {terms[2 * b], terms[2 * b + 1]};
+    for (int t = 1; t < nt; t++) {
+      ivl X = {1.0, 1.0};
+      int first = 1;
+      for (int i = 0; i < k; i++) {
+        const int a = alpha[t * k + i];
+        if (a == 0) continue;
+        const ivl P = iv_pow(W[i], a);
+        X = first ? P : iv_mul(X, P, ORC_OUTWARD);
+        first = 0;
+      }
+      ivl T = {terms[((int64_t)t * nbox + b) * 2], terms[((int64_t)t * nbox + b) * 2 + 1]};
+      acc = iv_add(acc, iv_mul(T, X, ORC_OUTWARD), ORC_OUTWARD);
+    }
     out[2 * b] = acc.lo; out[2 * b + 1] = acc.hi;
   }
   return 0;

@@ -244,6 +244,51 @@ def test_nearest_mode_degenerate_boxes_equal_numpy_polygrid(k):
     assert not bits_equal(lo3, ref.reshape(-1))
 
 
+@pytest.mark.parametrize("k,d", [(1, 30), (2, 20), (3, 12), (3, 100)])
+def test_point_values_equal_numpy_polyval(k, d):
+    """The oracle's round-to-nearest point Horner (the reference for the
+    point evaluation and its derivatives) is numpy's polyval/polyval2d/3d bit
+    for bit: both nest x1 innermost, descending exponents, a product then a
+    sum per step.  Planted mistakes must fail: a transposed cube, and the
+    same polynomial nested the other way round (x_k innermost), which is
+    mathematically equal but rounds differently."""
+    from numpy.polynomial import polynomial as P
+    rng = np.random.default_rng(70 + k + d)
+    poly = synth.curve().polys[0] if d == 100 else synth.small_random(k, d, seed=80 + k + d)[0]
+    n = 300
+    x = rng.uniform(-1, 1, size=(n, k))
+    f = orc.eval_points(poly, d, x)
+    cols = [x[:, j] for j in range(k)]
+    ref = {1: P.polyval, 2: P.polyval2d, 3: P.polyval3d}[k](*cols, poly)
+    assert bits_equal(f, ref)
+    if k >= 2:
+        swapped = np.ascontiguousarray(np.swapaxes(poly, 0, 1))
+        assert not bits_equal(orc.eval_points(swapped, d, x), ref)
+        rev = {2: P.polyval2d, 3: P.polyval3d}[k](*cols[::-1], np.ascontiguousarray(np.transpose(poly)))
+        assert np.allclose(rev, ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())  # the same polynomial ...
+        assert not bits_equal(rev, ref)                                        # ... rounded in another order
+
+
+def test_point_values_exact_on_short_dyadics():
+    """Integer coefficients at points with few significant bits: every
+    product and sum of the Horner chain is exact, so the value is the exact
+    rational F(x)."""
+    rng = np.random.default_rng(91)
+    for k, d in ((2, 6), (3, 5)):
+        poly = synth.small_random(k, d, seed=92 + k, dist="int100")[0]
+        x = rng.integers(-4, 5, size=(50, k)) / 4.0
+        f = orc.eval_points(poly, d, x)
+        for i in range(len(x)):
+            exact = Fraction(0)
+            for e in np.ndindex(*poly.shape):
+                if sum(e) <= d and poly[e] != 0:
+                    term = Fraction(float(poly[e]))
+                    for j in range(k):
+                        term *= Fraction(float(x[i, j])) ** e[j]
+                    exact += term
+            assert Fraction(float(f[i])) == exact
+
+
 # ---------------------------------------------------------------------------
 # Enclosure property on tiny inputs, in exact rationals
 # ---------------------------------------------------------------------------
@@ -683,6 +728,259 @@ def test_taylor2_prunes_more_on_the_surface():
         assert all(tuple(x) in k0 for x in r1["kept"])
     assert len(t2[-1]["kept"]) < len(plain[-1]["kept"])
 
+
+
+# ---------------------------------------------------------------------------
+# Taylor form of order m (Sec. 3.2, Taylor form definition)
+# ---------------------------------------------------------------------------
+
+def _exact_taylor_cube(cube, d, alpha):
+    """Exact rational coefficients of D^alpha F / alpha!: entry e is
+    prod_i C(e_i + alpha_i, alpha_i) c_{e + alpha}."""
+    out = np.empty(cube.shape, dtype=object)
+    order = sum(alpha)
+    for e in np.ndindex(*cube.shape):
+        out[e] = Fraction(0)
+        if sum(e) > d - order:
+            continue
+        src = tuple(ei + ai for ei, ai in zip(e, alpha))
+        if any(v >= cube.shape[0] for v in src):
+            continue
+        m = 1
+        for ei, ai in zip(e, alpha):
+            m *= math.comb(ei + ai, ai)
+        out[e] = m * ex.F(cube[src])
+    return out
+
+
+def _exact_pow_range(w, a):
+    """Exact range of x^a over the rational interval w."""
+    u, v = w
+    if a == 0:
+        return Fraction(1), Fraction(1)
+    if a % 2 == 1:
+        return u ** a, v ** a
+    if u >= 0:
+        return u ** a, v ** a
+    if v <= 0:
+        return v ** a, u ** a
+    return Fraction(0), max(u ** a, v ** a)
+
+
+def _exact_taylor_m(poly, d, m, B, c, k, power=_exact_pow_range, weight=True):
+    """The order-m form in exact rationals on box B with centre c: the terms
+    of orders < m at c, those of order m by exact interval Horner over B,
+    X_alpha the exact ranges of the powers multiplied over ascending i.
+    ``power`` and ``weight`` plant mistakes for the sensitivity checks."""
+    W = [(u - cj, v - cj) for (u, v), cj in zip(B, c)]
+    fc = ex.exact_point_value(poly, d, c)
+    acc = (fc, fc)
+    for j, alpha in orc.taylor_multi_indices(k, m)[1:]:
+        if j > d:
+            continue
+        cube = _exact_taylor_cube(poly, d, alpha)
+        if not weight:  # planted: the 1/alpha! dropped (D^alpha F itself)
+            f = 1
+            for a in alpha:
+                f *= math.factorial(a)
+            cube = cube * f
+        if j < m:
+            v = _exact_value_q(cube, d - j, c)
+            T = (v, v)
+        else:
+            T = _exact_interval_q(cube, d - j, B)
+        X = None
+        for i in range(k):
+            if alpha[i]:
+                P = power(W[i], alpha[i])
+                X = P if X is None else ex._qmul(X, P)
+        acc = ex._qadd(acc, ex._qmul(T, X))
+    return acc
+
+
+def _exact_value_q(cube, d, x):
+    total = Fraction(0)
+    for e in np.ndindex(*cube.shape):
+        if sum(e) <= d and cube[e] != 0:
+            term = cube[e]
+            for j, xj in enumerate(x):
+                term *= xj ** e[j]
+            total += term
+    return total
+
+
+def _exact_interval_q(cube, d, B):
+    """Exact interval Horner (canonical nesting) of a cube of Fractions."""
+    k = cube.ndim
+    e = [0] * k
+
+    def value(s, rem):
+        acc = None
+        for es in range(rem, -1, -1):
+            e[s - 1] = es
+            coef = (cube[tuple(e)], cube[tuple(e)]) if s == 1 else value(s - 1, rem - es)
+            acc = coef if acc is None else ex._qadd(ex._qmul(acc, B[s - 1]), coef)
+        return acc
+
+    return value(k, d)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_taylor_coefficients_match_numpy_polyder(k):
+    """Integer coefficients: the multiplier times c is exact, so the
+    coefficients of D^alpha F / alpha! equal numpy's polyder taken alpha_i
+    times along each axis (a library routine), divided by alpha!; orders 1
+    and 2 are the first- and second-order cubes of the lower-order forms."""
+    from numpy.polynomial import polynomial as P
+    d = 7
+    rng = np.random.default_rng(230 + k)
+    c = synth.random_poly(k, d, rng, "int100")
+    for j, alpha in orc.taylor_multi_indices(k, 4)[1:]:
+        lo, hi = orc.taylor_coef(c, d, alpha)
+        assert np.array_equal(lo, hi)
+        ref = c.copy()
+        fact = 1
+        for i, a in enumerate(alpha):
+            if a:
+                ref = P.polyder(ref, m=a, axis=i)
+                fact *= math.factorial(a)
+                pad = [(0, 0)] * k
+                pad[i] = (0, a)
+                ref = np.pad(ref, pad)
+        ref = ref / fact
+        ref[np.indices(c.shape).sum(axis=0) > d - j] = 0.0
+        assert np.array_equal(lo, ref), alpha
+        if j == 1:
+            assert np.array_equal(lo, orc.deriv(c, d, alpha.index(1))[0])
+        if j == 2:
+            i1 = [i for i in range(k) for _ in range(alpha[i])]
+            assert np.array_equal(lo, orc.deriv2(c, d, i1[0], i1[1])[0])
+    # non-integer coefficients: [RD(m c), RU(m c)] brackets the exact product tightly
+    c = synth.random_poly(k, 5, rng, "normal")
+    for j, alpha in orc.taylor_multi_indices(k, 3)[1:]:
+        lo, hi = orc.taylor_coef(c, 5, alpha)
+        q = _exact_taylor_cube(c, 5, alpha)
+        for e in np.ndindex(*c.shape):
+            assert ex.is_round_down(lo[e], q[e]) and ex.is_round_up(hi[e], q[e]), (alpha, e)
+
+
+def test_taylor_coefficient_multiplier_beyond_2_53_is_refused():
+    c = np.zeros(401); c[400] = 1.0
+    assert math.comb(400, 8) > 2 ** 53 > math.comb(400, 7)
+    with pytest.raises(ValueError, match="2\\^53"):
+        orc.taylor_coef(c, 400, (8,))
+    lo, hi = orc.taylor_coef(c, 400, (7,))  # C(400, 7) is exact in double
+    assert lo[393] == hi[393] == math.comb(400, 7)
+
+
+def test_taylor_m_of_a_cubic_closed_form():
+    """A cubic with dyadic coefficients on dyadic boxes: every centre value,
+    every W_i, every power and product is exact, so the order-3 form must be
+    the exact rational form bit for bit (orders 0..2 at the centre, the
+    constant third-order coefficients times the ranges of the cubes and
+    mixed products)."""
+    k = 3
+    terms = {(3, 0, 0): 0.5, (0, 3, 0): -1.25, (0, 0, 3): 0.75, (2, 1, 0): -0.5, (1, 0, 2): 1.5, (1, 1, 1): -2.0,
+             (2, 0, 0): 1.5, (0, 1, 1): 1.25, (1, 0, 0): 0.375, (0, 0, 1): 0.125, (0, 0, 0): -0.3125}
+    cube = synth.monomial_poly(k, 3, terms)
+    S = orc.csf_from_boxes(np.array([[0, 3, 5], [2, 2, 2], [7, 0, 6], [4, 5, 1], [3, 4, 4]]), 3)
+    lo, hi = orc.taylor_m_level([cube], S, np.array([-1.0, 1.0] * k), 3)
+    tabs = orc.level_tables(np.array([-1.0, 1.0] * k), k, 3)
+    for q, b in enumerate(S["boxes"]):
+        B = [(ex.F(tabs[j][b[j]][0]), ex.F(tabs[j][b[j]][1])) for j in range(k)]
+        c = [(u + v) / 2 for u, v in B]
+        acc = _exact_taylor_m(cube, 3, 3, B, c, k)
+        assert ex.F(lo[0, q]) == acc[0] and ex.F(hi[0, q]) == acc[1], q
+
+
+def test_taylor_m_low_orders_are_the_mean_value_and_order2_forms():
+    """Orders 1 and 2 of the general form are, bit for bit, the mean-value
+    form and the order-2 form (their sums have the same terms in the same
+    order); on an affine polynomial every order gives the mean-value form."""
+    k = 3
+    rng = np.random.default_rng(240)
+    boxes = rng.integers(0, 32, size=(40, k))
+    S = orc.csf_from_boxes(boxes, 5)
+    dom = np.array([-0.7, 1.3, -1.0, 0.9, -2.0, 2.0])
+    poly = synth.small_random(k, 6, seed=241)[0]
+    assert all(bits_equal(a, b) for a, b in zip(orc.taylor_m_level([poly], S, dom, 1),
+                                                 orc.mean_value_level([poly], S, dom)))
+    assert all(bits_equal(a, b) for a, b in zip(orc.taylor_m_level([poly], S, dom, 2),
+                                                 orc.taylor2_level([poly], S, dom)))
+    affine = synth.random_poly(k, 1, rng, "normal")
+    mv = orc.mean_value_level([affine], S, dom)
+    for m in (2, 3, 5):
+        assert all(bits_equal(a, b) for a, b in zip(orc.taylor_m_level([affine], S, dom, m), mv)), m
+
+
+@pytest.mark.parametrize("k,d,level,m", [(2, 6, 3, 3), (3, 5, 2, 3), (2, 7, 2, 4), (1, 9, 3, 5)])
+def test_taylor_m_within_rounding_of_the_exact_rational_form(k, d, level, m):
+    """The order-m form computed in exact rationals (exact coefficients of
+    D^alpha F / alpha!, exact values at the exact centre, exact interval
+    Horner over the box for order m, exact ranges of the powers) lies inside
+    the oracle's enclosure, each endpoint within a few units in the last
+    place.  Two planted mistakes of the exact form -- products W_i W_i W_i
+    where the range of the power belongs, and D^alpha F without the 1/alpha!
+    -- are caught by the same comparison."""
+    rng = np.random.default_rng(250 + 10 * k + m)
+    poly = synth.small_random(k, d, seed=251 + k + m)[0]
+    boxes = rng.integers(0, 1 << level, size=(10, k))
+    S = orc.csf_from_boxes(boxes, level)
+    lo, hi = orc.taylor_m_level([poly], S, np.array([-1.0, 1.0] * k), m)
+    tabs = orc.level_tables(np.array([-1.0, 1.0] * k), k, level)
+
+    def product_power(w, a):  # planted: the power as a product of intervals
+        x = w
+        for _ in range(a - 1):
+            x = ex._qmul(x, w)
+        return x
+
+    def close(acc, q):
+        L, H = ex.F(lo[0, q]), ex.F(hi[0, q])
+        scale = 1 + abs(acc[0]) + abs(acc[1])
+        return (L <= acc[0] and acc[1] <= H and acc[0] - L <= scale * Fraction(1, 2 ** 45)
+                and H - acc[1] <= scale * Fraction(1, 2 ** 45))
+
+    caught_pow = caught_weight = False
+    for q, b in enumerate(S["boxes"]):
+        B = [(ex.F(tabs[j][b[j]][0]), ex.F(tabs[j][b[j]][1])) for j in range(k)]
+        c = [(u + v) / 2 for u, v in B]
+        assert close(_exact_taylor_m(poly, d, m, B, c, k), q), q
+        caught_pow |= not close(_exact_taylor_m(poly, d, m, B, c, k, power=product_power), q)
+        caught_weight |= not close(_exact_taylor_m(poly, d, m, B, c, k, weight=False), q)
+    assert caught_pow and caught_weight
+
+
+@pytest.mark.parametrize("k,d,level,m", [(2, 6, 4, 3), (3, 5, 3, 3), (3, 6, 2, 4)])
+def test_taylor_m_contains_exact_values(k, d, level, m):
+    """Enclosure property: exact F at the corners, the centre and random
+    dyadic points of each box lies in the order-m enclosure."""
+    rng = np.random.default_rng(260 + k + m)
+    poly = synth.small_random(k, d, seed=261 + k + m)[0]
+    boxes = rng.integers(0, 1 << level, size=(20, k))
+    S = orc.csf_from_boxes(boxes, level)
+    lo, hi = orc.taylor_m_level([poly], S, np.array([-1.0, 1.0] * k), m)
+    tabs = orc.level_tables(np.array([-1.0, 1.0] * k), k, level)
+    for q, b in enumerate(S["boxes"]):
+        box = [tuple(tabs[j][b[j]]) for j in range(k)]
+        corners = [list(c) for c in np.array(np.meshgrid(*box, indexing="ij")).reshape(k, -1).T]
+        centre = [(ex.F(u) + ex.F(v)) / 2 for u, v in box]
+        for x in corners + [centre] + _dyadic_points(rng, box, 4):
+            val = ex.exact_point_value(poly, d, x)
+            assert ex.F(lo[0, q]) <= val <= ex.F(hi[0, q])
+
+
+def test_taylor3_prunes_more_on_the_surface():
+    """With the order-3 test the kept sets are subsets of C0's, and at level
+    5 of the degree-40 surface it keeps fewer boxes than the order-2 test."""
+    w = synth.surface()
+    plain = orc.subdivide(w.polys, 3, 5, nthreads=orc.max_threads())
+    t3 = orc.subdivide_tm(w.polys, 3, 5, 3, nthreads=orc.max_threads())
+    t2 = orc.subdivide_t2(w.polys, 3, 5, nthreads=orc.max_threads())
+    for r0, r1 in zip(plain, t3):
+        k0 = {tuple(x) for x in r0["kept"]}
+        assert all(tuple(x) in k0 for x in r1["kept"])
+    assert len(t3[-1]["kept"]) < len(t2[-1]["kept"]) < len(plain[-1]["kept"])
 
 # ---------------------------------------------------------------------------
 # Inclusion criterion C1 (Sec. 3.2): sign change over a box's vertices
