@@ -155,10 +155,13 @@ int interval_eval_level(const vx_poly* P, int32_t np, const vx_csf* S, const dou
 int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo, double* hi,
                          uint8_t* keep, void* ws, size_t ws_bytes, void* stream);
 
+/* Highest order of the Taylor forms (taylor_exclusion, VX_RUN_TAYLOR_ORDER). */
+#define VX_TAYLOR_MAX_ORDER 6
+
 /*
- * taylor_exclusion -- the Taylor form of order `order` (1 or 2; Sec. 3.2,
- * Taylor form definition) as an exclusion test on every box of S.  Order 1
- * is mean_value_exclusion.  Order 2:
+ * taylor_exclusion -- the Taylor form of order `order` (1..VX_TAYLOR_MAX_ORDER;
+ * Sec. 3.2, Taylor form definition) as an exclusion test on every box of S.
+ * Order 1 is mean_value_exclusion.  Order 2:
  *   T2(F_p, B) = F_p(c) + sum_i dF_p/dx_i(c) W_i + sum_{i<=j} H_ij(B) X_ij,
  * W_i = B_i - c_i = [RD(lo_i - chi_i), RU(hi_i - clo_i)] (c's enclosure as in
  * mean_value_exclusion), H_ii = (1/2) d2F_p/dx_i^2 and H_ij = d2F_p/dx_i dx_j
@@ -172,12 +175,31 @@ int mean_value_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const do
  *   lo, hi : device double, np x S->n[k-1], the order-`order` enclosures.
  *   keep   : device uint8 or NULL; if given, keep[b] is cleared when some
  *            enclosure excludes 0 (AND with the caller's flags).
- * Limits: np * k <= 64 (order 1), np * k(k+1)/2 <= 64 (order 2).  Errors as
- * interval_eval_level, VX_EINVAL for another order; workspace
- * vx_workspace_bytes(VX_WS_MEANVALUE or VX_WS_TAYLOR2, P, np, S, 0).
+ * Order m >= 3, in the multinomial form of the definition:
+ *   T_m(F_p, B) = F_p(c) + sum_{t >= 1} T_t X_t
+ * over the multi-indices alpha_t of orders 1..m: orders in increasing
+ * order, each order's multi-indices as the non-decreasing index tuples
+ * i_1 <= ... <= i_j in lexicographic order (for m = 2 this is the sum
+ * above).  T_t is the coefficient polynomial D^alpha F_p / alpha!, whose
+ * coefficients prod_i C(e_i + alpha_i, alpha_i) c_{e + alpha} (an exact
+ * integer times c) are rounded outward once, evaluated at the centre
+ * enclosures for orders below m and over the box for order m, each by
+ * Algorithm 2 on S; X_t = prod_i W_i^(alpha_i) with W_i = B_i - c_i as above
+ * and each power the range of x^a over W_i ([-RU(|lo|^a), RU(hi^a)] for odd
+ * a, [0, RU(max(|lo|, hi)^a)] for even a, powers formed by repeated
+ * multiplication), the powers multiplied over ascending i; the terms are
+ * added left to right.  {F_p(x) : x in B} is contained in T_m(F_p, B).
+ * Limits: np * k <= 64 (order 1), np * k(k+1)/2 <= 64 (order 2); any np for
+ * m >= 3 (its term systems are cut into groups of 64); C(degree + m, m) <
+ * 2^53 (VX_EUNSUPPORTED otherwise).  Errors as interval_eval_level,
+ * VX_EINVAL for an order outside 1..VX_TAYLOR_MAX_ORDER; workspace
+ * vx_taylor_workspace_bytes(P, np, S, order) (for orders 1 and 2 also
+ * vx_workspace_bytes(VX_WS_MEANVALUE or VX_WS_TAYLOR2, P, np, S, 0)).
  */
 int taylor_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, int32_t order, double* lo,
                      double* hi, uint8_t* keep, void* ws, size_t ws_bytes, void* stream);
+/* Workspace of taylor_exclusion of that order on S (0 on invalid arguments). */
+size_t vx_taylor_workspace_bytes(const vx_poly* P, int32_t np, const vx_csf* S, int32_t order);
 
 /*
  * inclusion_test -- the inclusion criterion C1 of Sec. 3.2 ("Inclusion
@@ -316,7 +338,8 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
  * only when both tests keep it (eval_ms then includes both; the callback
  * still receives the C0 enclosures and the combined keep flags).
  * VX_RUN_TAYLOR2 adds the order-2 Taylor test (taylor_exclusion, order 2) in
- * the same way; the two flags are exclusive (VX_EINVAL).  VX_RUN_NO_TIMES
+ * the same way, VX_RUN_TAYLOR_ORDER(m) the Taylor test of order m
+ * (1..VX_TAYLOR_MAX_ORDER); these flags are exclusive (VX_EINVAL).  VX_RUN_NO_TIMES
  * records no per-level timing events (stats eval_ms and filter_ms are 0):
  * each event is a packet the stream must pass between the level's kernels.
  * VX_RUN_INCLUSION (C1: vertex signs, inclusion_test, for one polynomial;
@@ -346,6 +369,7 @@ enum {
   VX_RUN_INCLUSION_TAYLOR = 16,
   VX_RUN_EARLY_EXIT = 32
 };
+#define VX_RUN_TAYLOR_ORDER(m) ((int32_t)(m) << 8)
 #define VX_RUN_INCLUSION_FROM(level) ((int32_t)(level) << 16)
 #define VX_RUN_EARLY_EXIT_FROM(level) ((int32_t)(level) << 24)
 int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
@@ -374,10 +398,18 @@ int vx_copy(void* dst, const void* src, size_t bytes, int32_t kind, void* stream
  *            gradient of the weighted sum with respect to the points.
  *   dcoef  : device, np dense cubes (side^k each, zeros outside the simplex)
  *            receiving sum_i gbar[p][i] x_i^e; requires `grid`.
- *   grid, dom : when the points are the centres of the leaves of a CSF (as
- *            written by csf_centres), the coefficient gradient is the
- *            transpose of the amortized evaluation, one CSF depth at a time
- *            (Algorithm 2 run backwards); NULL for arbitrary points.
+ *   grid, dom : the points are the centres of the leaves of this CSF on the
+ *            domain dom (host, 2k), in leaf order (n = grid->n[k-1]), or
+ *            grid = NULL for arbitrary points.  With a grid, f and jac come
+ *            from the amortized evaluation of Algorithm 2 with points for
+ *            boxes: each partial evaluation is computed once per CSF node and
+ *            shared by all points below it (Sec. 1.1, Property 1; Theorem 1),
+ *            bit-identical to the per-point evaluation; and the coefficient
+ *            gradient is the transpose of that evaluation, one CSF depth at a
+ *            time.  x may then be NULL; if it is given, it must equal the
+ *            centres as csf_centres writes them, bit for bit (checked on the
+ *            device, the call then waits for the stream once; VX_EINVAL
+ *            otherwise).
  * Errors: VX_EINVAL, VX_EUNSUPPORTED (dcoef without grid; degree > 200 for
  * dcoef), VX_ECAPACITY (workspace: vx_workspace_bytes(VX_WS_GRAD, P, np,
  * grid, n)).
@@ -404,8 +436,10 @@ int newton_project(const vx_poly* P, int32_t np, double* x, int64_t n, int32_t s
 /*
  * Batched subdivision -- many independent systems run through Algorithm 3 in
  * lockstep (all levels 0..depth), for workloads of many small problems where
- * one system cannot fill the GPU.  Sec. 3.2 runs independent subdivisions in
- * parallel on CPU threads; here every kernel covers all systems at once.
+ * one system cannot fill the GPU.  Batching independent systems is this
+ * library's own design, not the paper's (whose only remark on parallelism,
+ * in Sec. 4.1, is that its CPU implementation can spread one computation
+ * over several threads): every kernel covers all systems at once.
  *
  * The box sets of all systems form one CSF with an extra top depth: depth 0
  * holds one node per live system (label = system index), depths 1..k hold the

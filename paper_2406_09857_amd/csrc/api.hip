@@ -4,6 +4,7 @@
 #include <stdarg.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -74,6 +75,22 @@ static int check_ws(const void* ws) {
   return VX_OK;
 }
 
+// Node counts of the CSF of the 2^k children of every box of S (the
+// bisection of Algorithm 3, child c of box B being 2B + c): depth l + 1 holds
+// at most 2^(l+1) n[l] nodes.  Labels and offsets are int32, so a bound that
+// reaches 2^31 - 1 is VX_EOVERFLOW; the level loop and filter_subdivide both
+// size the next level through this check.
+static int next_level_bounds(const vx_csf* S, int64_t* ncap) {
+  if (S->level >= 29) VX_FAIL(VX_EOVERFLOW, "level %d cannot be bisected (labels are int32)", S->level);
+  for (int l = 0; l < S->k; l++) {
+    const int64_t bound = S->n[l] << (l + 1);
+    if (bound >= ((int64_t)1 << 31) - 1)
+      VX_FAIL(VX_EOVERFLOW, "the next level may hold %lld nodes at depth %d (int32 limit)", (long long)bound, l + 1);
+    ncap[l] = bound;
+  }
+  return VX_OK;
+}
+
 static int64_t theorem1_steps(const vx_poly* P, int np, const vx_csf* S) {
   int64_t total = 0;
   for (int p = 0; p < np; p++) {
@@ -101,10 +118,24 @@ static int taylor_tables(int k, int order) { return order == 0 ? 0 : order == 1 
 
 static int check_taylor_polys(int np, int k, int order) {
   if (order == 0) return VX_OK;
+  if (order >= 3) return VX_OK;  // the general path cuts its term systems into groups of VX_MAXPOLY
   const int per = taylor_tables(k, order);
   if (np * per > VX_MAXPOLY)
     VX_FAIL(VX_EINVAL, "Taylor test of order %d: %d polynomials x %d derivative tables exceeds %d", order, np, per,
             VX_MAXPOLY);
+  return VX_OK;
+}
+
+// Orders 1..VX_TAYLOR_MAX_ORDER; the multipliers prod_i C(e_i + alpha_i,
+// alpha_i) of the coefficient polynomials stay below C(d + m, m), which must
+// be exact in double.
+static int check_taylor_order(const vx_poly* P, int np, int order) {
+  if (order < 1 || order > VX_TAYLOR_MAX_ORDER)
+    VX_FAIL(VX_EINVAL, "Taylor order %d is outside 1..%d", order, VX_TAYLOR_MAX_ORDER);
+  for (int p = 0; p < np; p++)
+    if (binom64(P[p].degree + order, order) >= ((int64_t)1 << 53))
+      VX_FAIL(VX_EUNSUPPORTED, "Taylor order %d of degree %d: coefficient multipliers reach 2^53", order,
+              P[p].degree);
   return VX_OK;
 }
 
@@ -188,6 +219,13 @@ extern "C" {
 
 const char* vx_last_error(void) { return get_error(); }
 
+size_t vx_taylor_workspace_bytes(const vx_poly* P, int32_t np, const vx_csf* S, int32_t order) {
+  if (check_csf(S, false) || check_poly(P, np, S->k) || order < 1 || order > VX_TAYLOR_MAX_ORDER ||
+      check_taylor_order(P, np, order) || check_taylor_polys(np, S->k, order))
+    return 0;
+  return mv_workspace_bytes(P, np, S, order);
+}
+
 size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_csf* S, int64_t n) {
   switch (which) {
     case VX_WS_EVAL:
@@ -237,9 +275,11 @@ int interval_eval_level(const vx_poly* P, int32_t np, const vx_csf* S, const dou
 int taylor_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, int32_t order, double* lo,
                      double* hi, uint8_t* keep, void* ws, size_t ws_bytes, void* stream) {
   int rc;
-  if (order != 1 && order != 2) VX_FAIL(VX_EINVAL, "Taylor order %d is not 1 or 2", order);
+  if (order < 1 || order > VX_TAYLOR_MAX_ORDER)
+    VX_FAIL(VX_EINVAL, "Taylor order %d is outside 1..%d", order, VX_TAYLOR_MAX_ORDER);
   if ((rc = check_csf(S, true))) return rc;
   if ((rc = check_poly(P, np, S->k))) return rc;
+  if ((rc = check_taylor_order(P, np, order))) return rc;
   if ((rc = check_taylor_polys(np, S->k, order))) return rc;
   if ((rc = check_dom(dom, S->k))) return rc;
   if (S->n[S->k - 1] > 0 && (!lo || !hi)) VX_FAIL(VX_EINVAL, "null output arrays");
@@ -327,14 +367,13 @@ int filter_subdivide(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf*
   if ((rc = check_csf(S, true))) return rc;
   const int k = S->k;
   if (S->n[k - 1] > 0 && !keep) VX_FAIL(VX_EINVAL, "null keep flags");
-  if (S->level >= 29 && next) VX_FAIL(VX_EOVERFLOW, "level %d cannot be bisected (labels are int32)", S->level);
+  int64_t bound[VX_KMAX] = {0, 0, 0, 0};
+  if (next && (rc = next_level_bounds(S, bound))) return rc;
   for (int l = 0; l < k; l++) {
     if (kept && (kept->k != k || kept->cap[l] < S->n[l] || !kept->idx[l] || (l + 1 < k && !kept->ptr[l])))
       VX_FAIL(VX_ECAPACITY, "kept CSF: depth %d needs capacity %lld", l + 1, (long long)S->n[l]);
-    const int64_t bound = S->n[l] << (l + 1);
-    if (bound >= ((int64_t)1 << 31) - 1) VX_FAIL(VX_EOVERFLOW, "next level may exceed int32 at depth %d", l + 1);
-    if (next && (next->k != k || next->cap[l] < bound || !next->idx[l] || (l + 1 < k && !next->ptr[l])))
-      VX_FAIL(VX_ECAPACITY, "next CSF: depth %d needs capacity %lld", l + 1, (long long)bound);
+    if (next && (next->k != k || next->cap[l] < bound[l] || !next->idx[l] || (l + 1 < k && !next->ptr[l])))
+      VX_FAIL(VX_ECAPACITY, "next CSF: depth %d needs capacity %lld", l + 1, (long long)bound[l]);
   }
   if ((rc = check_ws(ws))) return rc;
   if (kept) kept->level = S->level;
@@ -358,21 +397,21 @@ int eval_grad(const vx_poly* P, int32_t np, const double* x, int64_t n, double* 
   int rc;
   if ((rc = check_point_polys(P, np))) return rc;
   const int k = P[0].k;
-  if (n < 0 || (n > 0 && (f || jac || xbar) && !x)) VX_FAIL(VX_EINVAL, "bad point list");
+  if (n < 0 || (n > 0 && (f || jac || xbar) && !x && !grid)) VX_FAIL(VX_EINVAL, "bad point list");
   if (xbar && !gbar) VX_FAIL(VX_EINVAL, "xbar needs gbar");
-  if (dcoef) {
-    if (!gbar) VX_FAIL(VX_EINVAL, "dcoef needs gbar");
-    if (!grid) VX_FAIL(VX_EUNSUPPORTED, "coefficient gradients need the points as a CSF grid of centres");
+  if (dcoef && !gbar) VX_FAIL(VX_EINVAL, "dcoef needs gbar");
+  if (dcoef && !grid) VX_FAIL(VX_EUNSUPPORTED, "coefficient gradients need the points as a CSF grid of centres");
+  if (grid) {
     if ((rc = check_csf(grid, true))) return rc;
     if (grid->k != k) VX_FAIL(VX_EINVAL, "grid has k=%d, polynomials k=%d", grid->k, k);
     if (grid->n[k - 1] != n) VX_FAIL(VX_EINVAL, "grid has %lld leaves, n=%lld", (long long)grid->n[k - 1], (long long)n);
     if ((rc = check_dom(dom, k))) return rc;
+  }
+  if (dcoef)
     for (int p = 0; p < np; p++)
       if (P[p].degree > MAXDEG_ADJ) VX_FAIL(VX_EUNSUPPORTED, "coefficient gradient limited to degree %d", MAXDEG_ADJ);
-  }
   if ((rc = check_ws(ws))) return rc;
-  return grad_impl(P, np, x, n, f, jac, gbar, xbar, dcoef, dcoef ? grid : nullptr, dom, ws, ws_bytes,
-                   (hipStream_t)stream);
+  return grad_impl(P, np, x, n, f, jac, gbar, xbar, dcoef, grid, dom, ws, ws_bytes, (hipStream_t)stream);
 }
 
 int csf_centres(const vx_csf* S, const double* dom, double* x, void* stream) {
@@ -420,7 +459,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
   if ((rc = check_ws(ws))) return rc;
   if (flags & ~(VX_RUN_MEAN_VALUE | VX_RUN_TAYLOR2 | VX_RUN_NO_TIMES | VX_RUN_INCLUSION | VX_RUN_INCLUSION_TAYLOR |
-                VX_RUN_EARLY_EXIT | VX_RUN_INCLUSION_FROM(255) | VX_RUN_EARLY_EXIT_FROM(63)))
+                VX_RUN_EARLY_EXIT | VX_RUN_TAYLOR_ORDER(15) | VX_RUN_INCLUSION_FROM(255) | VX_RUN_EARLY_EXIT_FROM(63)))
     VX_FAIL(VX_EINVAL, "unknown flags 0x%x", flags);
   const int incl_mode = (flags & VX_RUN_INCLUSION) ? 1 : (flags & VX_RUN_INCLUSION_TAYLOR) ? 2 : 0;
   const int incl_from = (flags >> 16) & 255;
@@ -435,10 +474,12 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   if (incl_mode == 2 && (rc = check_taylor_polys(np, k, 2))) return rc;
   if (!incl_mode && incl_from) VX_FAIL(VX_EINVAL, "VX_RUN_INCLUSION_FROM without an inclusion flag");
   const bool times = stats && !(flags & VX_RUN_NO_TIMES);
-  if ((flags & VX_RUN_MEAN_VALUE) && (flags & VX_RUN_TAYLOR2))
-    VX_FAIL(VX_EINVAL, "VX_RUN_MEAN_VALUE and VX_RUN_TAYLOR2 are exclusive");
-  const int order = (flags & VX_RUN_TAYLOR2) ? 2 : (flags & VX_RUN_MEAN_VALUE) ? 1 : 0;
+  const int order_m = (flags >> 8) & 15;  // VX_RUN_TAYLOR_ORDER(m)
+  if (((flags & VX_RUN_MEAN_VALUE) != 0) + ((flags & VX_RUN_TAYLOR2) != 0) + (order_m != 0) > 1)
+    VX_FAIL(VX_EINVAL, "VX_RUN_MEAN_VALUE, VX_RUN_TAYLOR2 and VX_RUN_TAYLOR_ORDER are exclusive");
+  const int order = order_m ? order_m : (flags & VX_RUN_TAYLOR2) ? 2 : (flags & VX_RUN_MEAN_VALUE) ? 1 : 0;
   const bool mv = order > 0;
+  if (mv && (rc = check_taylor_order(P, np, order))) return rc;
   if ((rc = check_taylor_polys(np, k, order))) return rc;
   // Early exit (systems): polynomial p is evaluated only on the boxes that
   // polynomials 0..p-1 kept; the kept sets are those of the plain loop.
@@ -528,7 +569,10 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
     const bool last = level == depth;
     // next CSF capacity bound
     int64_t ncap[VX_KMAX] = {0, 0, 0, 0};
-    for (int l = 0; l < k; l++) ncap[l] = (S.n[l] << (l + 1)) > 0 ? (S.n[l] << (l + 1)) : 1;
+    if (!last) {
+      if ((rc = next_level_bounds(&S, ncap))) return rc;
+      for (int l = 0; l < k; l++) ncap[l] = ncap[l] > 0 ? ncap[l] : 1;
+    }
     const size_t n_bytes = last ? 0 : csf_bytes(k, ncap);
     // middle region (offsets relative to its start)
     size_t moff = 0;

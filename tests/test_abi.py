@@ -71,7 +71,8 @@ def test_misaligned_workspace_is_rejected_before_any_work():
 
 
 def test_taylor_arguments_are_checked_before_any_work():
-    """Order outside {1, 2} and the two exclusive run flags are VX_EINVAL."""
+    """Orders outside 1..6 and the exclusive Taylor run flags are VX_EINVAL;
+    the workspace query gives 0 for them."""
     import ctypes as C
     from paper_2406_09857_amd import binding as b
     L = b.lib()
@@ -85,11 +86,21 @@ def test_taylor_arguments_are_checked_before_any_work():
     parr[0].k, parr[0].degree, parr[0].side = 1, 1, 2
     parr[0].c_lo = 4096  # never dereferenced
     dom = (C.c_double * 2)(-1.0, 1.0)
-    rc = L.taylor_exclusion(parr, 1, C.byref(s), dom, 3, None, None, None, C.c_void_p(4096), 1 << 20, None)
-    assert rc == b.VX_EINVAL and b"order 3" in L.vx_last_error()
-    rc = L.run_subdivision_ex(parr, 1, dom, 2, b.VX_RUN_MEAN_VALUE | b.VX_RUN_TAYLOR2, C.c_void_p(4096), 1 << 20,
-                              None, None, b.LEVEL_CB(), None, None)
-    assert rc == b.VX_EINVAL and b"exclusive" in L.vx_last_error()
+    for bad in (0, 7, -1):
+        rc = L.taylor_exclusion(parr, 1, C.byref(s), dom, bad, None, None, None, C.c_void_p(4096), 1 << 20, None)
+        assert rc == b.VX_EINVAL and f"order {bad}".encode() in L.vx_last_error()
+        assert L.vx_taylor_workspace_bytes(parr, 1, C.byref(s), bad) == 0
+    for good in range(1, 7):  # an empty level: valid, nothing to do
+        assert L.vx_taylor_workspace_bytes(parr, 1, C.byref(s), good) > 0
+        rc = L.taylor_exclusion(parr, 1, C.byref(s), dom, good, None, None, None, C.c_void_p(4096), 1 << 20, None)
+        assert rc == b.VX_OK
+    for flags in (b.VX_RUN_MEAN_VALUE | b.VX_RUN_TAYLOR2, b.VX_RUN_TAYLOR2 | (3 << 8), b.VX_RUN_MEAN_VALUE | (4 << 8)):
+        rc = L.run_subdivision_ex(parr, 1, dom, 2, flags, C.c_void_p(4096), 1 << 20, None, None, b.LEVEL_CB(),
+                                  None, None)
+        assert rc == b.VX_EINVAL and b"exclusive" in L.vx_last_error()
+    rc = L.run_subdivision_ex(parr, 1, dom, 2, 7 << 8, C.c_void_p(4096), 1 << 20, None, None, b.LEVEL_CB(),
+                              None, None)
+    assert rc == b.VX_EINVAL and b"order 7" in L.vx_last_error()
     assert b.workspace_bytes(b.VX_WS_TAYLOR2) == 0  # invalid arguments give 0
 
 
@@ -161,3 +172,47 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2", "--no-cpu-baseline"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and not r.stdout.strip()
+
+
+def test_next_level_bound_overflow_is_refused_before_any_work():
+    """Bisection gives depth l + 1 up to 2^(l+1) n[l] nodes; labels and
+    offsets are int32, so a level whose children could reach 2^31 - 1 at
+    some depth is VX_EOVERFLOW (the same host check sizes the level loop's
+    next level), and one just below the limit passes that check."""
+    import ctypes as C
+    from paper_2406_09857_amd import binding as b
+    L = b.lib()
+
+    def csf(n, level=20):
+        s = b.vx_csf()
+        s.k = 3
+        s.level = level
+        for l in range(3):
+            s.n[l] = n[l]
+            s.cap[l] = n[l]
+            s.idx[l] = 256 * (l + 1)  # never dereferenced: the call fails first
+        s.ptr[0], s.ptr[1] = 4096, 8192
+        return s
+
+    nxt = b.vx_csf()
+    nxt.k = 3
+    keep = C.c_void_p(1 << 20)
+    S = csf([1 << 10, 1 << 20, 1 << 28])  # depth 3: 2^28 << 3 = 2^31
+    rc = L.filter_subdivide(C.byref(S), keep, None, C.byref(nxt), None, None, 0, None)
+    assert rc == b.VX_EOVERFLOW and b"int32" in L.vx_last_error()
+    S = csf([1 << 29, 1 << 29, 1 << 29])  # depth 1: 2^29 << 1 = 2^30 fits; depth 2: 2^31 does not
+    rc = L.filter_subdivide(C.byref(S), keep, None, C.byref(nxt), None, None, 0, None)
+    assert rc == b.VX_EOVERFLOW and b"depth 2" in L.vx_last_error()
+    # just below the limit: the bound check passes and the (empty) next CSF's capacity is what fails
+    S = csf([1 << 10, 1 << 20, (1 << 28) - 1])
+    rc = L.filter_subdivide(C.byref(S), keep, None, C.byref(nxt), None, None, 0, None)
+    assert rc == b.VX_ECAPACITY and b"next CSF" in L.vx_last_error()
+    # without a next CSF nothing is bisected, so no bound applies
+    kept = b.vx_csf()
+    kept.k = 3
+    rc = L.filter_subdivide(C.byref(S), keep, C.byref(kept), None, None, None, 0, None)
+    assert rc == b.VX_ECAPACITY and b"kept CSF" in L.vx_last_error()
+    # level 29 cannot be bisected at all
+    S = csf([1, 1, 1], level=29)
+    rc = L.filter_subdivide(C.byref(S), keep, None, C.byref(nxt), None, None, 0, None)
+    assert rc == b.VX_EOVERFLOW and b"level 29" in L.vx_last_error()
