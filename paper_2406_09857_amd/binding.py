@@ -94,10 +94,13 @@ def lib():
         L.csf_build.argtypes = [C.c_int32, C.c_int32, vp, C.c_int64, C.POINTER(vx_csf), vp, C.c_size_t, vp]
         L.variable_order_costs.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.c_int32, vp, vp, vp,
                                            vp, C.c_size_t, vp]
+        L.vx_taylor_workspace_bytes.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.c_int32]
+        L.vx_taylor_workspace_bytes.restype = C.c_size_t
         L.vx_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
         L.vx_profile_end.argtypes = [C.POINTER(vx_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
         L.vx_profile_select.argtypes = [C.c_char_p]
-        for f in ("interval_eval_level", "filter_subdivide", "run_subdivision", "run_subdivision_ex", "csf_build",
+        for f in ("interval_eval_level", "filter_subdivide", "run_subdivision",
+                  "run_subdivision_ex", "csf_build",
                   "vx_copy", "vx_profile_begin", "vx_profile_end", "vx_profile_select", "mean_value_exclusion",
                   "taylor_exclusion", "inclusion_test", "taylor_inclusion_test", "newton_test"):
             getattr(L, f).restype = C.c_int
@@ -260,10 +263,13 @@ def mean_value_exclusion(polys, csf: CSF, dom, keep: torch.Tensor | None = None,
     return taylor_exclusion(polys, csf, dom, 1, keep, stream)
 
 
+TAYLOR_MAX_ORDER = 6
+
+
 def taylor_exclusion(polys, csf: CSF, dom, order: int, keep: torch.Tensor | None = None, stream=None):
-    """Taylor-form enclosures of order 1 or 2 (lo, hi: (np, nboxes)) on every
-    box; ``keep`` (uint8, nboxes), if given, is cleared in place where some
-    enclosure excludes 0."""
+    """Taylor-form enclosures of order 1..TAYLOR_MAX_ORDER (lo, hi: (np,
+    nboxes)) on every box; ``keep`` (uint8, nboxes), if given, is cleared in
+    place where some enclosure excludes 0."""
     polys = as_polys(polys)
     dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
     nb = csf.nboxes
@@ -272,10 +278,10 @@ def taylor_exclusion(polys, csf: CSF, dom, order: int, keep: torch.Tensor | None
     hi = torch.empty((len(polys), max(nb, 1)), dtype=torch.float64, device=dev)
     parr = _poly_array(polys)
     s = csf.struct()
-    need = int(lib().vx_workspace_bytes(VX_WS_TAYLOR2 if order == 2 else VX_WS_MEANVALUE, parr, len(polys),
-                                        C.byref(s), 0))
+    need = int(lib().vx_taylor_workspace_bytes(parr, len(polys), C.byref(s), order))
     if need == 0:
-        _check(VX_EINVAL)
+        raise VxError(VX_EINVAL, f"invalid Taylor test of order {order} (order outside 1..{TAYLOR_MAX_ORDER}, "
+                                 "too many polynomials for orders 1 and 2, or inconsistent polynomials and CSF)")
     ws = _ws(need, dev)
     _check(lib().taylor_exclusion(parr, len(polys), C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)), order,
                                   lo.data_ptr(), hi.data_ptr(), keep.data_ptr() if keep is not None else None,
@@ -400,10 +406,12 @@ def permute_variables(polys, order):
 def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = None, stream=None,
                     ws: torch.Tensor | None = None, want_kept: bool = True, mean_value: bool = False,
                     taylor2: bool = False, level_times: bool = True, inclusion: str | None = None,
-                    inclusion_from: int = 0, early_exit: bool = False, early_exit_from: int = 0):
+                    inclusion_from: int = 0, early_exit: bool = False, early_exit_from: int = 0,
+                    taylor_order: int = 0):
     """Algorithm 3 with C0 to `depth`.  Returns (stats, kept) where stats is a
     list of per-level dicts and kept the final level's kept CSF (host numpy).
-    ``mean_value`` / ``taylor2`` add the Taylor test of order 1 / 2 to C0;
+    ``mean_value`` / ``taylor2`` add the Taylor test of order 1 / 2 to C0,
+    ``taylor_order=m`` the one of order m (1..TAYLOR_MAX_ORDER);
     ``level_times=False`` records no per-level timing events (eval_ms and
     filter_ms are then 0).  ``inclusion`` ("vertices" or "taylor") runs
     Algorithm 3 with C1 from level ``inclusion_from`` on: certified boxes
@@ -460,7 +468,8 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
 
     cb = LEVEL_CB(_cb) if (record is not None or want_kept) else LEVEL_CB()
     flags = ((VX_RUN_MEAN_VALUE if mean_value else 0) | (VX_RUN_TAYLOR2 if taylor2 else 0)
-             | (0 if level_times else VX_RUN_NO_TIMES) | (VX_RUN_EARLY_EXIT if early_exit else 0))
+             | (0 if level_times else VX_RUN_NO_TIMES) | (VX_RUN_EARLY_EXIT if early_exit else 0)
+             | (int(taylor_order) << 8))
     if early_exit_from:
         if not early_exit or not 0 < early_exit_from < 64:
             raise ValueError("early_exit_from needs early_exit and a level in 1..63")
@@ -557,15 +566,26 @@ def csf_centres(csf: CSF, dom, stream=None) -> torch.Tensor:
     return x[: csf.nboxes]
 
 
-def eval_grad(polys, x: torch.Tensor, want_jac: bool = True, gbar: torch.Tensor | None = None,
+def eval_grad(polys, x: torch.Tensor | None, want_jac: bool = True, gbar: torch.Tensor | None = None,
               want_xbar: bool = False, want_dcoef: bool = False, grid: CSF | None = None, dom=None, stream=None):
     """Point values f (np, n), Jacobian (n, np, k), and with gbar (np, n) the
-    adjoints xbar (n, k) and dcoef (np, side^k cubes; needs `grid`, the CSF
-    whose leaf centres are x)."""
+    adjoints xbar (n, k) and dcoef (np, side^k cubes; needs `grid`).
+
+    With ``grid`` (and ``dom``) the points are the centres of the grid's
+    leaves: f and the Jacobian come from the amortized evaluation on the
+    grid; ``x`` may then be None, and if given must equal those centres bit
+    for bit (the library checks it and raises otherwise)."""
     polys = as_polys(polys)
-    x = x.to(torch.float64).contiguous()
-    n, k = int(x.shape[0]), polys[0].k
-    dev = x.device
+    k = polys[0].k
+    if x is None:
+        if grid is None:
+            raise ValueError("eval_grad needs points or a grid")
+        n = grid.nboxes
+        dev = grid.idx[0].device
+    else:
+        x = x.to(torch.float64).contiguous()
+        n = int(x.shape[0])
+        dev = x.device
     npl = len(polys)
     f = torch.empty((npl, max(n, 1)), dtype=torch.float64, device=dev)
     jac = torch.empty((max(n, 1), npl, k), dtype=torch.float64, device=dev) if want_jac else None
@@ -582,7 +602,7 @@ def eval_grad(polys, x: torch.Tensor, want_jac: bool = True, gbar: torch.Tensor 
         _check(VX_EINVAL)
     ws = _ws(need, dev)
     domarr = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1)) if dom is not None else None
-    _check(_grad_lib().eval_grad(parr, npl, x.data_ptr() if n else None, n, f.data_ptr(),
+    _check(_grad_lib().eval_grad(parr, npl, x.data_ptr() if (n and x is not None) else None, n, f.data_ptr(),
                                  jac.data_ptr() if jac is not None else None,
                                  gbar.data_ptr() if gbar is not None else None,
                                  xbar.data_ptr() if xbar is not None else None,
@@ -610,34 +630,36 @@ def newton_project(polys, x: torch.Tensor, steps: int = 3, stream=None):
 class PolyEval(torch.autograd.Function):
     """F(x) for a polynomial system as a torch autograd function.
 
-    forward(x, *coefs): x (n, k) float64 points, coefs one dense cube per
-    polynomial (point coefficients); returns (np, n).  The backward is the
-    library's adjoint: dL/dx from the forward-mode Jacobian contracted with the
-    incoming gradient, dL/dcoef from the transposed amortized evaluation when a
-    CSF grid is attached with ``PolyEval.grid = (csf, dom)`` (x must then be
-    that grid's centres); otherwise coefficient gradients are not provided.
+    ``PolyEval.apply(x, grid, *coefs)``: x (n, k) float64 points, ``grid``
+    None or a pair (csf, dom) whose leaf centres the points are, coefs one
+    dense cube per polynomial (point coefficients); returns (np, n).  With a
+    grid the library checks that x equals those centres bit for bit, the
+    forward is the amortized evaluation on the grid, and the backward
+    provides dL/dcoef (the transposed amortized evaluation); dL/dx is the
+    forward-mode Jacobian contracted with the incoming gradient either way.
+    Without a grid no coefficient gradient is provided.
     """
-    grid = None
 
     @staticmethod
-    def forward(ctx, x, *coefs):
+    def forward(ctx, x, grid, *coefs):
         polys = [Poly(c.detach().to(torch.float64)) for c in coefs]
-        f, _, _, _ = eval_grad(polys, x.detach(), want_jac=False)
+        csf, dom = grid if grid is not None else (None, None)
+        f, _, _, _ = eval_grad(polys, x.detach(), want_jac=False, grid=csf, dom=dom)
         ctx.save_for_backward(x, *coefs)
-        ctx.grid = PolyEval.grid
+        ctx.grid = grid
         return f
 
     @staticmethod
     def backward(ctx, gf):
         x, *coefs = ctx.saved_tensors
         polys = [Poly(c.detach().to(torch.float64)) for c in coefs]
-        want_dc = any(ctx.needs_input_grad[1:]) and ctx.grid is not None
+        want_dc = any(ctx.needs_input_grad[2:]) and ctx.grid is not None
         grid, dom = ctx.grid if ctx.grid is not None else (None, None)
         _, _, xbar, dcoef = eval_grad(polys, x.detach(), want_jac=False, gbar=gf.contiguous(),
                                       want_xbar=ctx.needs_input_grad[0], want_dcoef=want_dc, grid=grid, dom=dom)
         gx = xbar if ctx.needs_input_grad[0] else None
-        gcs = [dcoef[i] if (want_dc and ctx.needs_input_grad[1 + i]) else None for i in range(len(coefs))]
-        return (gx, *gcs)
+        gcs = [dcoef[i] if (want_dc and ctx.needs_input_grad[2 + i]) else None for i in range(len(coefs))]
+        return (gx, None, *gcs)
 
 
 # ---------------------------------------------------------------------------

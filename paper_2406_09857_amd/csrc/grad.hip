@@ -403,6 +403,150 @@ __global__ void k_adjoint_scatter(int k, int d, int side, const double* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Amortized point evaluation on a CSF grid of centres (Algorithm 2 with
+// points for boxes, round to nearest).  When the points are the centres of
+// the leaves of a CSF, every partial evaluation of the nested Horner above
+// is shared by all points below one node, exactly as the interval path
+// shares it between boxes: the x1 chains run once per depth-1 node, the x2
+// chains once per depth-2 node, and so on (Theorem 1's count with points).
+// A stage runs, for every node, the very instructions that the per-point
+// evaluation runs for each point below it -- acc <- acc*x + c, the earlier
+// variables' derivatives der_j <- der_j*x + c_j and the stage's own
+// der_s <- der_s*x + acc (old acc), starting from zero -- so values and
+// derivatives are bit-identical to k_point_eval.
+//
+// Rows.  Node q of depth l (l = 1..k-1) holds, for every trailing tuple of
+// dimension k-l in O_{k-l} order, the partial evaluation and (with
+// derivatives) its derivatives with respect to x_1..x_l: l+1 planes of
+// `cstride` doubles.  The root row is the padded coefficient stream (one
+// plane).  Stage l walks chains of its parent's row: output entry j is the
+// chain of clen[j] entries starting at cstart[j].
+// ---------------------------------------------------------------------------
+
+// Chain table of a stage whose output tuples have dimension m_out (input
+// rows in O_{m_out+1} order, unpadded): one thread per output tuple.
+__global__ void k_grid_chains(int m_out, int d, int64_t nch, int64_t* __restrict__ cstart,
+                              int64_t* __restrict__ clen) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nch) return;
+  int t[VX_KMAX + 1] = {0, 0, 0, 0, 0};
+  g_unrank(r, m_out, t + 1);
+  int deg = 0;
+  for (int i = 1; i <= m_out; i++) deg += t[i];
+  t[0] = d - deg;  // first entry of the chain: the largest exponent of the stage's variable
+  const int64_t pos = m_out ? g_opos(t + 1, m_out, d) : 0;
+  cstart[pos] = g_opos(t, m_out + 1, d);
+  clen[pos] = d - deg + 1;
+}
+
+// Parent index of every node of a depth (one thread per parent).
+__global__ void k_grid_parents(const int32_t* __restrict__ ptr, int64_t nparent, int32_t* __restrict__ parent) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nparent) return;
+  for (int64_t q = ptr[p]; q < ptr[p + 1]; q++) parent[q] = (int32_t)p;
+}
+
+// Stage L (1..k) for one polynomial: lane = node of depth L, blockIdx.y =
+// chain group (the groups cut the parent row into runs of about equal
+// length at chain boundaries, found by a binary search on cstart).  The
+// lanes of a wave are consecutive nodes, mostly children of one parent, so
+// their row loads mostly hit one address.  GRAD = false carries the value
+// only.  The last stage (a single chain) writes f and jac.
+template <int L, bool GRAD>
+__global__ __launch_bounds__(256) void k_grid_stage(const double* __restrict__ in, int64_t in_stride,
+                                                    int64_t in_cstride, const int32_t* __restrict__ parent,
+                                                    const int32_t* __restrict__ labels, double dlo, double dhi,
+                                                    int level, const int64_t* __restrict__ cstart,
+                                                    const int64_t* __restrict__ clen, int64_t nch, int ngroup,
+                                                    int64_t nnode, double* __restrict__ out, int64_t out_stride,
+                                                    int64_t out_cstride, double* __restrict__ f,
+                                                    double* __restrict__ jac, int np, int p, int k) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nnode) return;
+  // chain group: [first chain starting at or after total*g/G, same for g+1)
+  const int64_t total = cstart[nch - 1] + clen[nch - 1];
+  auto first_at = [&](int g) -> int64_t {
+    if (g >= ngroup) return nch;
+    const int64_t target = (total * g + ngroup - 1) / ngroup;
+    int64_t lo = 0, hi = nch;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (cstart[mid] >= target) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+  };
+  const int64_t j0 = first_at(blockIdx.y), j1 = first_at(blockIdx.y + 1);
+  const int64_t par = parent ? parent[q] : 0;
+  const double x = centre(dlo, dhi, level, labels[q]);
+  const double* row = in + par * in_stride;
+  constexpr int NIN = GRAD ? L : 1;  // input planes: value, d/dx_1 .. d/dx_{L-1}
+  for (int64_t j = j0; j < j1; j++) {
+    const double* c = row + cstart[j];
+    const int64_t len = clen[j];
+    double acc = 0.0;
+    double der[L] = {};
+#pragma unroll 4
+    for (int64_t e = 0; e < len; e++) {
+      double cin[NIN];
+#pragma unroll
+      for (int i = 0; i < NIN; i++) cin[i] = c[i * in_cstride + e];
+      if (GRAD) {
+#pragma unroll
+        for (int i = 1; i < NIN; i++) der[i - 1] = der[i - 1] * x + cin[i];
+        der[L - 1] = der[L - 1] * x + acc;
+      }
+      acc = acc * x + cin[0];
+    }
+    if (out) {
+      double* o = out + q * out_stride + j;
+      o[0] = acc;
+      if (GRAD) {
+#pragma unroll
+        for (int i = 0; i < L; i++) o[(i + 1) * out_cstride] = der[i];
+      }
+    } else {
+      f[p * nnode + q] = acc;
+      if (GRAD && jac) {
+#pragma unroll
+        for (int i = 0; i < L; i++) jac[(q * np + p) * k + i] = der[i];
+      }
+    }
+  }
+}
+
+// Flag (bit 0) any point that is not, bit for bit, the centre of its leaf
+// as csf_centres writes it.
+__global__ void k_check_centres(int k, int level, const int32_t* i0, const int32_t* i1, const int32_t* i2,
+                                const int32_t* i3, const int32_t* p0, const int32_t* p1, const int32_t* p2,
+                                int64_t n0, int64_t n1, int64_t n2, int64_t nleaf, AxisDom dom,
+                                const double* __restrict__ x, unsigned int* __restrict__ bad) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  const int32_t* idx[4] = {i0, i1, i2, i3};
+  const int32_t* ptr[3] = {p0, p1, p2};
+  const int64_t nn[3] = {n0, n1, n2};
+  int64_t node = b;
+  bool ok = true;
+  for (int l = k - 1; l >= 0; l--) {
+    const double c = centre(dom.lo[l], dom.hi[l], level, idx[l][node]);
+    ok = ok && __double_as_longlong(c) == __double_as_longlong(x[b * k + l]);
+    if (l > 0) {
+      int64_t lo = 0, hi = nn[l - 1];
+      while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ptr[l - 1][mid] <= node) lo = mid; else hi = mid;
+      }
+      node = lo;
+    }
+  }
+  if (!ok) atomicOr(bad, 1u);
+}
+
+__global__ void k_zero_u32(unsigned int* p) {
+  if (threadIdx.x == 0) *p = 0u;
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
 struct GradPlan {
@@ -458,6 +602,37 @@ static int build_streams(GradPlan& G, const vx_poly* P, int np, hipStream_t st) 
   return VX_OK;
 }
 
+// Workspace of the amortized forward on a grid: the rows of depths 1..k-1
+// (sized for the largest degree; reused polynomial after polynomial), the
+// parent index of every node below depth 1, the chain tables of stages
+// 2..k, and the centre-check flag.
+struct GridPlan {
+  double* rows[VX_KMAX] = {};
+  int64_t rstride[VX_KMAX] = {};
+  int64_t cstride[VX_KMAX] = {};
+  int32_t* parent[VX_KMAX] = {};
+  int64_t* cstart[VX_KMAX] = {};
+  int64_t* clen[VX_KMAX] = {};
+  unsigned int* bad = nullptr;
+};
+
+static void plan_grid(Arena& A, GridPlan& Gp, const vx_csf* grid, int dmax) {
+  const int k = grid->k;
+  for (int l = 0; l + 1 < k; l++) {  // depth l+1: tuples of dimension k-l-1, l+2 planes
+    const int64_t ent = gbinom(dmax + k - l - 1, k - l - 1);
+    Gp.cstride[l] = (ent + 31) / 32 * 32;
+    Gp.rstride[l] = Gp.cstride[l] * (l + 2);
+    Gp.rows[l] = A.take<double>((size_t)grid->n[l] * Gp.rstride[l] + 1);
+  }
+  for (int l = 1; l < k; l++) Gp.parent[l] = A.take<int32_t>((size_t)grid->n[l] + 1);
+  for (int l = 1; l < k; l++) {  // stage l+1: output tuples of dimension k-l-1
+    const int64_t nch = gbinom(dmax + k - l - 1, k - l - 1);
+    Gp.cstart[l] = A.take<int64_t>(nch + 1);
+    Gp.clen[l] = A.take<int64_t>(nch + 1);
+  }
+  Gp.bad = A.take<unsigned int>(1);
+}
+
 size_t grad_workspace_bytes(const vx_poly* P, int np, const vx_csf* grid, int64_t n) {
   Arena A;
   GradPlan G;
@@ -471,8 +646,111 @@ size_t grad_workspace_bytes(const vx_poly* P, int np, const vx_csf* grid, int64_
     // adjoint rows: depth l nodes hold rows of dimension k - l
     for (int l = 0; l < k; l++) A.take<double>((size_t)grid->n[l] * gbinom(dmax + k - l - 1, k - l - 1) + 1);
     A.take<double>(gbinom(dmax + k, k) + 1);
+    GridPlan Gp;
+    plan_grid(A, Gp, grid, dmax);
   }
   return A.off + 256;
+}
+
+static AxisDom axis_dom(const double* dom, int k) {
+  AxisDom ad;
+  memset(&ad, 0, sizeof ad);
+  for (int j = 0; j < k; j++) {
+    ad.lo[j] = dom[2 * j];
+    ad.hi[j] = dom[2 * j + 1];
+  }
+  return ad;
+}
+
+// Waves to aim for per stage launch (several per SIMD on 256 CUs).
+constexpr int64_t GRID_TARGET_WAVES = 8192;
+
+static int launch_grid_stage(int L, bool grad, const double* in, int64_t in_stride, int64_t in_cstride,
+                             const int32_t* parent, const int32_t* labels, double dlo, double dhi, int level,
+                             const int64_t* cstart, const int64_t* clen, int64_t nch, int64_t nnode, double* out,
+                             int64_t out_stride, int64_t out_cstride, double* f, double* jac, int np, int p, int k,
+                             hipStream_t st) {
+  const int64_t waves = (nnode + 63) / 64;
+  int64_t ng = (GRID_TARGET_WAVES + waves - 1) / waves;
+  ng = ng < 1 ? 1 : ng > nch ? nch : ng;
+  ng = ng > 1024 ? 1024 : ng;
+  const dim3 g((unsigned)((nnode + 255) / 256), (unsigned)ng);
+#define VX_GS(LL, GG)                                                                                           \
+  hipLaunchKernelGGL((k_grid_stage<LL, GG>), g, dim3(256), 0, st, in, in_stride, in_cstride, parent, labels, dlo, \
+                     dhi, level, cstart, clen, nch, (int)ng, nnode, out, out_stride, out_cstride, f, jac, np, p, k)
+  switch (L * 2 + (grad ? 1 : 0)) {
+    case 2: VX_GS(1, false); break;
+    case 3: VX_GS(1, true); break;
+    case 4: VX_GS(2, false); break;
+    case 5: VX_GS(2, true); break;
+    case 6: VX_GS(3, false); break;
+    case 7: VX_GS(3, true); break;
+    case 8: VX_GS(4, false); break;
+    default: VX_GS(4, true); break;
+  }
+#undef VX_GS
+  VX_CHECK_LAUNCH("k_grid_stage");
+  return VX_OK;
+}
+
+// F (and with `jac` its gradient) at the centres of grid's leaves by the
+// amortized stages; bit-identical to k_point_eval at those points.
+static int grid_forward(const GradPlan& G, GridPlan& Gp, const vx_poly* P, int np, const vx_csf* grid,
+                        const double* dom, double* f, double* jac, hipStream_t st) {
+  const int k = grid->k;
+  const int64_t n = grid->n[k - 1];
+  const bool grad = jac != nullptr;
+  for (int l = 1; l < k; l++) {
+    const int64_t np_ = grid->n[l - 1];
+    hipLaunchKernelGGL(k_grid_parents, dim3((unsigned)((np_ + 255) / 256)), dim3(256), 0, st, grid->ptr[l - 1], np_,
+                       Gp.parent[l]);
+    VX_CHECK_LAUNCH("k_grid_parents");
+  }
+  int rc;
+  for (int p = 0; p < np; p++) {
+    const int d = P[p].degree;
+    for (int L = 1; L <= k; L++) {
+      const bool leaf = L == k;
+      double* out = leaf ? nullptr : Gp.rows[L - 1];
+      const int64_t ostride = leaf ? 0 : Gp.rstride[L - 1], ocstride = leaf ? 0 : Gp.cstride[L - 1];
+      const double dlo = dom[2 * (L - 1)], dhi = dom[2 * (L - 1) + 1];
+      if (L == 1) {  // the root row: the padded coefficient stream, its chains from the stream tables
+        rc = launch_grid_stage(1, grad, G.stream[p], 0, 0, nullptr, grid->idx[0], dlo, dhi, grid->level,
+                               G.start[p], G.plen[p], stream_chains(k, d), grid->n[0], out, ostride, ocstride, f,
+                               jac, np, p, k, st);
+      } else {
+        const int m_out = k - L;
+        const int64_t nch = gbinom(d + m_out, m_out);
+        hipLaunchKernelGGL(k_grid_chains, dim3((unsigned)((nch + 255) / 256)), dim3(256), 0, st, m_out, d, nch,
+                           Gp.cstart[L - 1], Gp.clen[L - 1]);
+        VX_CHECK_LAUNCH("k_grid_chains");
+        rc = launch_grid_stage(L, grad, Gp.rows[L - 2], Gp.rstride[L - 2], Gp.cstride[L - 2], Gp.parent[L - 1],
+                               grid->idx[L - 1], dlo, dhi, grid->level, Gp.cstart[L - 1], Gp.clen[L - 1], nch,
+                               grid->n[L - 1], out, ostride, ocstride, f, jac, np, p, k, st);
+      }
+      if (rc) return rc;
+    }
+  }
+  (void)n;
+  return VX_OK;
+}
+
+// VX_OK when x holds, bit for bit, the centres of grid's leaves (waits for
+// the stream once).
+static int check_centres(GridPlan& Gp, const vx_csf* grid, const double* dom, const double* x, hipStream_t st) {
+  const int k = grid->k;
+  const int64_t n = grid->n[k - 1];
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, Gp.bad);
+  VX_CHECK_LAUNCH("k_zero_u32");
+  hipLaunchKernelGGL(k_check_centres, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, grid->level,
+                     grid->idx[0], grid->idx[1], grid->idx[2], grid->idx[3], grid->ptr[0], grid->ptr[1], grid->ptr[2],
+                     grid->n[0], grid->n[1], grid->n[2], n, axis_dom(dom, k), x, Gp.bad);
+  VX_CHECK_LAUNCH("k_check_centres");
+  unsigned int bad = 0;
+  VX_HIP(hipMemcpyAsync(&bad, Gp.bad, sizeof bad, hipMemcpyDeviceToHost, st));
+  VX_HIP(hipStreamSynchronize(st));
+  if (bad) VX_FAIL(VX_EINVAL, "eval_grad: the points are not the centres of the grid's leaves");
+  return VX_OK;
 }
 
 static StreamSet stream_set(const GradPlan& G, const vx_poly* P, int np) {
@@ -510,24 +788,26 @@ int grad_impl(const vx_poly* P, int np, const double* x, int64_t n, double* f, d
   double* root = nullptr;
   int dmax = 0;
   for (int p = 0; p < np; p++) dmax = P[p].degree > dmax ? P[p].degree : dmax;
-  if (grid && dcoef) {
+  if (grid) {
     for (int l = 0; l < k; l++) rows[l] = A.take<double>((size_t)grid->n[l] * gbinom(dmax + k - l - 1, k - l - 1) + 1);
     root = A.take<double>(gbinom(dmax + k, k) + 1);
   }
   double* jac_tmp = nullptr;
   if (xbar && !jac) jac_tmp = A.take<double>((size_t)n * np * k + 1);
+  GridPlan Gp;
+  if (grid) plan_grid(A, Gp, grid, dmax);
+  double* f_tmp = (n > 0 && !f) ? A.take<double>((size_t)n * np + 1) : nullptr;
   if (A.overflow) VX_FAIL(VX_ECAPACITY, "eval_grad: workspace of %zu bytes is too small (%zu needed)", ws_bytes, A.off + 256);
   int rc;
+  if (grid && x && n > 0 && (rc = check_centres(Gp, grid, dom, x, st))) return rc;
   if ((rc = build_streams(G, P, np, st))) return rc;
   const StreamSet ss = stream_set(G, P, np);
   if (jac_tmp) jac = jac_tmp;
-  double* f_tmp = nullptr;
-  if (n > 0 && (f || jac)) {
-    if (!f) {
-      f_tmp = A.take<double>((size_t)n * np + 1);
-      if (A.overflow) VX_FAIL(VX_ECAPACITY, "eval_grad: workspace too small");
-      f = f_tmp;
-    }
+  if (n > 0 && (f || jac) && grid) {
+    if (!f) f = f_tmp;
+    if ((rc = grid_forward(G, Gp, P, np, grid, dom, f, jac, st))) return rc;
+  } else if (n > 0 && (f || jac)) {
+    if (!f) f = f_tmp;
     dim3 grid3((unsigned)((n + 63) / 64), (unsigned)np);
     const bool gradf = jac != nullptr;
 #define VX_PE(KK)                                                                                       \
@@ -610,12 +890,7 @@ int centres_impl(const vx_csf* S, const double* dom, double* x, hipStream_t st) 
   const int k = S->k;
   const int64_t n = S->n[k - 1];
   if (n == 0) return VX_OK;
-  AxisDom ad;
-  memset(&ad, 0, sizeof ad);
-  for (int j = 0; j < k; j++) {
-    ad.lo[j] = dom[2 * j];
-    ad.hi[j] = dom[2 * j + 1];
-  }
+  const AxisDom ad = axis_dom(dom, k);
   hipLaunchKernelGGL(k_csf_centres, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, S->level, S->idx[0],
                      S->idx[1], S->idx[2], S->idx[3], S->ptr[0], S->ptr[1], S->ptr[2], S->n[0], S->n[1], S->n[2], n,
                      ad, x);

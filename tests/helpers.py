@@ -31,3 +31,20 @@ def csf_equal(gpu: dict, orc: dict) -> bool:
         if l + 1 < k and not np.array_equal(np.asarray(gpu["ptr"][l]), np.asarray(orc["ptr"][l])):
             return False
     return True
+
+
+# Results of expensive oracle runs shared between test modules of one pytest
+# process (filled by whichever test computes them first).
+ORACLE_RESULTS: dict = {}
+
+
+def oracle_curve_kept(orc, synth, level: int = 10):
+    """The oracle's kept boxes of the curve workload at `level` (computed once
+    per process; test_gpu_fullsize stores the ones it computes level by level)."""
+    key = ("curve_kept", level)
+    if key not in ORACLE_RESULTS:
+        w = synth.curve()
+        recs = orc.subdivide(w.polys, w.k, level, dom=w.domain(), nthreads=orc.max_threads())
+        for r in recs:
+            ORACLE_RESULTS[("curve_kept", r["level"])] = r["kept"]
+    return ORACLE_RESULTS[key]

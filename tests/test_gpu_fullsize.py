@@ -22,7 +22,7 @@ import pytest
 
 from oracle import core as orc
 from paper_2406_09857_amd import synth
-from tests.helpers import bits_equal, csf_equal, first_mismatch
+from tests.helpers import ORACLE_RESULTS, bits_equal, csf_equal, first_mismatch
 
 pytestmark = pytest.mark.gpu
 
@@ -91,6 +91,8 @@ def test_full_size_every_level_bit_exact(vx, name):
         assert stats[level]["kept"] == orc.csf_sizes(K_o), tag
         assert stats[level]["steps"] == int(steps.sum()), tag
         _say(f"[full] {tag}: {orc.csf_sizes(S_o)} boxes, {int(keep_o.sum())} kept, oracle {time.time() - t:.1f} s")
+        if name == "curve":
+            ORACLE_RESULTS[("curve_kept", level)] = S_o["boxes"][keep_o]
         boxes = orc.children_of(S_o["boxes"][keep_o])
     assert not got
 

@@ -202,17 +202,62 @@ def test_polyeval_gradcheck(vx):
     c1, c2 = (torch.as_tensor(c, device="cuda") for c in synth.small_random(3, 4, seed=31, npolys=2))
     rng = np.random.default_rng(32)
     x = torch.as_tensor(rng.uniform(-0.9, 0.9, size=(20, 3)), device="cuda").requires_grad_(True)
-    vx.PolyEval.grid = None
-    assert gradcheck(lambda xx: vx.PolyEval.apply(xx, c1, c2), (x,), eps=1e-6, atol=1e-7, rtol=1e-6)
-    # coefficient gradients on a grid of centres
+    assert gradcheck(lambda xx: vx.PolyEval.apply(xx, None, c1, c2), (x,), eps=1e-6, atol=1e-7, rtol=1e-6)
+    # coefficient gradients on a grid of centres (the grid is an argument of the call)
     S = _grid(3, 3, 30, 33)
     csf = vx.CSF.from_arrays(3, 3, S["idx"], S["ptr"])
     dom = np.array([-1.0, 1.0] * 3)
     xg = vx.csf_centres(csf, dom)
-    vx.PolyEval.grid = (csf, dom)
     a = c1.clone().requires_grad_(True)
     b = c2.clone().requires_grad_(True)
-    try:
-        assert gradcheck(lambda p, q: vx.PolyEval.apply(xg, p, q), (a, b), eps=1e-6, atol=1e-7, rtol=1e-6)
-    finally:
-        vx.PolyEval.grid = None
+    assert gradcheck(lambda p, q: vx.PolyEval.apply(xg, (csf, dom), p, q), (a, b), eps=1e-6, atol=1e-7, rtol=1e-6)
+    # the grid forward equals the per-point forward bit for bit
+    assert bits_equal(vx.PolyEval.apply(xg, (csf, dom), c1, c2).cpu().numpy(),
+                      vx.PolyEval.apply(xg, None, c1, c2).cpu().numpy())
+
+
+def test_grid_points_must_be_the_grid_centres(vx):
+    """Points that are not, bit for bit, the centres of the grid's leaves (a
+    stale grid, or points a Newton step moved) are refused, not silently
+    evaluated at the centres."""
+    import torch
+    c = synth.small_random(3, 5, seed=34, npolys=1)
+    S = _grid(3, 3, 40, 35)
+    csf = vx.CSF.from_arrays(3, 3, S["idx"], S["ptr"])
+    dom = np.array([-1.0, 1.0] * 3)
+    xg = vx.csf_centres(csf, dom)
+    vx.eval_grad(c, xg, grid=csf, dom=dom)  # the centres pass
+    moved = xg.clone()
+    moved[17, 1] += 1e-12
+    with pytest.raises(vx.VxError, match="centres"):
+        vx.eval_grad(c, moved, grid=csf, dom=dom)
+    other = vx.CSF.from_arrays(3, 3, S["idx"], S["ptr"])
+    with pytest.raises(vx.VxError, match="centres"):
+        vx.eval_grad(c, vx.csf_centres(other, np.array([-1.0, 1.0, -1.0, 1.0, -1.0, 0.5])), grid=csf, dom=dom)
+    with pytest.raises(vx.VxError, match="centres"):
+        vx.PolyEval.apply(moved, (csf, dom), torch.as_tensor(c[0], device="cuda"))
+
+
+@pytest.mark.parametrize("k,d,level,n", [(1, 40, 9, 300), (2, 20, 6, 900), (3, 12, 4, 700), (4, 6, 3, 500),
+                                         (3, 100, 5, 400)])
+def test_grid_forward_bit_identical_to_per_point(vx, k, d, level, n):
+    """The amortized forward on a CSF grid (f and the Jacobian) equals the
+    per-point evaluation bit for bit, and the values equal the oracle's
+    round-to-nearest Horner, for k = 1..4, two polynomials, on a
+    non-dyadic domain too."""
+    import torch
+    print(f"[grad] grid forward k={k} d={d} level={level}", flush=True)
+    polys = synth.small_random(k, d, seed=1200 + k * 10 + d, npolys=2)
+    for dom in (np.array([-1.0, 1.0] * k), np.array([-0.7, 1.3, -1.1, 0.9, -2.0, 0.25, -0.5, 0.5][: 2 * k])):
+        S = _grid(level, k, n, 1300 + k)
+        csf = vx.CSF.from_arrays(k, level, S["idx"], S["ptr"])
+        x = vx.csf_centres(csf, dom)
+        fg, jg, _, _ = vx.eval_grad(polys, None, grid=csf, dom=dom)
+        fp, jp, _, _ = vx.eval_grad(polys, x)
+        assert bits_equal(fg.cpu().numpy(), fp.cpu().numpy())
+        assert bits_equal(jg.cpu().numpy(), jp.cpu().numpy())
+        f1, _, _, _ = vx.eval_grad(polys, x, want_jac=False, grid=csf, dom=dom)
+        assert bits_equal(f1.cpu().numpy(), fp.cpu().numpy())
+        xs = x.cpu().numpy()
+        for p, c in enumerate(polys):
+            assert bits_equal(fg.cpu().numpy()[p], orc.eval_points(c, d, xs))

@@ -1,0 +1,204 @@
+"""Point evaluation, adjoint and Newton projection at the size the benchmark
+times: the centres of the 2,645,621 boxes the oracle keeps at level 10 of the
+curve workload (two trivariate degree-100 polynomials, domain [-1,1]^3).
+
+* the amortized forward on that grid: values bit-identical to the oracle's
+  round-to-nearest Horner on a seeded sample of 2,000 centres, and values and
+  Jacobian bit-identical to the per-point evaluation on every centre;
+* on 500 seeded centres: the Jacobian against the oracle's derivative
+  polynomials (Horner error bound) and against central differences
+  (h = 1e-6, normwise relative error <= 1e-7 per point);
+* the coefficient adjoint over the whole grid, for 40 sampled coefficients
+  of each polynomial, against long-double sums with a rounding bound;
+* three minimum-norm Newton steps (Sec. 3.2, steps in the span of the
+  gradients) from 500 seeded centres against the same steps on the CPU from
+  the oracle's values and derivative polynomials, and the residuals they
+  reach.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import core as orc
+from paper_2406_09857_amd import synth
+from tests.helpers import bits_equal, first_mismatch, oracle_curve_kept
+
+pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -53
+LEVEL = 10
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_09857_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def grid(vx):
+    """The oracle's kept boxes at level 10 as a device CSF, and their centres
+    computed on the host (exact dyadics -1 + (2i+1)/1024)."""
+    t = time.time()
+    kept = np.asarray(oracle_curve_kept(orc, synth, LEVEL), np.int64)
+    _say(f"[c4] oracle level-{LEVEL} kept set: {len(kept)} boxes ({time.time() - t:.1f} s)")
+    K = orc.csf_from_boxes(kept, LEVEL)
+    csf = vx.CSF.from_arrays(3, LEVEL, K["idx"], K["ptr"])
+    centres = -1.0 + (2 * K["boxes"].astype(np.float64) + 1) / (1 << LEVEL)
+    return csf, centres
+
+
+def deriv_cube(c, j):
+    """Coefficients of dF/dx_j: e_j c_e moved to exponent e - u_j (rounded to nearest)."""
+    e = np.indices(c.shape)[j].astype(np.float64)
+    d = c * e
+    out = np.zeros_like(c)
+    sl = [slice(None)] * c.ndim
+    sl[j] = slice(1, None)
+    osl = [slice(None)] * c.ndim
+    osl[j] = slice(0, c.shape[j] - 1)
+    out[tuple(osl)] = d[tuple(sl)]
+    return out
+
+
+def horner_bound(c, dgr, x):
+    """gamma_{4d} |P|(|x|): error bound of a nested Horner evaluation."""
+    return 4 * (4 * dgr + 8) * EPS * orc.eval_points(np.abs(c), dgr, np.abs(x))
+
+
+@pytest.mark.timeout(900)
+def test_grid_forward_full_size(vx, grid):
+    import torch
+    csf, centres = grid
+    w = synth.curve()
+    dom = w.domain()
+    x = vx.csf_centres(csf, dom)
+    assert np.array_equal(x.cpu().numpy(), centres)
+    t = time.time()
+    fg, jg, _, _ = vx.eval_grad(w.polys, x, grid=csf, dom=dom)
+    torch.cuda.synchronize()
+    _say(f"[c4] grid forward with Jacobian on {len(centres)} centres: {time.time() - t:.2f} s (incl. check)")
+    fp, jp, _, _ = vx.eval_grad(w.polys, x)
+    fg = fg.cpu().numpy(); jg = jg.cpu().numpy()
+    assert bits_equal(fg, fp.cpu().numpy()), first_mismatch(fg, fp.cpu().numpy())
+    assert bits_equal(jg, jp.cpu().numpy()), first_mismatch(jg, jp.cpu().numpy())
+    rng = np.random.default_rng(4001)
+    pick = np.sort(rng.choice(len(centres), 2000, replace=False))
+    for p, c in enumerate(w.polys):
+        ref = orc.eval_points(c, 100, centres[pick])
+        assert bits_equal(fg[p, pick], ref), (p, first_mismatch(fg[p, pick], ref))
+
+
+@pytest.mark.timeout(900)
+def test_jacobian_on_sampled_centres(vx, grid):
+    import torch
+    _, centres = grid
+    w = synth.curve()
+    rng = np.random.default_rng(4002)
+    x = centres[np.sort(rng.choice(len(centres), 500, replace=False))]
+    f, jac, _, _ = vx.eval_grad(w.polys, torch.as_tensor(x, device="cuda"))
+    f = f.cpu().numpy(); jac = jac.cpu().numpy()
+    for p, c in enumerate(w.polys):
+        assert bits_equal(f[p], orc.eval_points(c, 100, x))
+        for j in range(3):
+            dc = deriv_cube(c, j)
+            dref = orc.eval_points(dc, 100, x)
+            tol = horner_bound(dc, 100, x) + horner_bound(c, 100, x) * 100
+            assert np.all(np.abs(jac[:, p, j] - dref) <= tol), (p, j)
+    # central differences, h = 1e-6: normwise relative error per point and polynomial
+    h = 1e-6
+    fd = np.zeros_like(jac)
+    for j in range(3):
+        xp = x.copy(); xp[:, j] += h
+        xm = x.copy(); xm[:, j] -= h
+        fpj = vx.eval_grad(w.polys, torch.as_tensor(xp, device="cuda"), want_jac=False)[0].cpu().numpy()
+        fmj = vx.eval_grad(w.polys, torch.as_tensor(xm, device="cuda"), want_jac=False)[0].cpu().numpy()
+        fd[:, :, j] = ((fpj - fmj) / (2 * h)).T
+    rel = np.linalg.norm(fd - jac, axis=(1, 2)) / np.linalg.norm(jac, axis=(1, 2))
+    _say(f"[c4] central differences: largest normwise relative error {rel.max():.2e}")
+    assert rel.max() <= 1e-7
+
+
+@pytest.mark.timeout(900)
+def test_coefficient_adjoint_full_grid(vx, grid):
+    """dF/dcoef = sum_i gbar_i x_i^e over all 2.6 M centres, for sampled
+    exponents, against long-double sums; |error| <= (n + 3d + 10) eps
+    sum |gbar_i x_i^e| covers the double-precision sums of any order."""
+    import torch
+    csf, centres = grid
+    w = synth.curve()
+    dom = w.domain()
+    n = len(centres)
+    rng = np.random.default_rng(4003)
+    gbar = rng.standard_normal((2, n))
+    t = time.time()
+    _, _, _, dcoef = vx.eval_grad(w.polys, None, want_jac=False, gbar=torch.as_tensor(gbar, device="cuda"),
+                                  want_dcoef=True, grid=csf, dom=dom)
+    dcoef = dcoef.cpu().numpy()
+    _say(f"[c4] coefficient adjoint over {n} centres: {time.time() - t:.2f} s")
+    # every centre coordinate is one of 1024 dyadics: long-double power tables per axis
+    lab = ((centres + 1.0) * (1 << LEVEL) - 1.0) / 2.0
+    lab = np.rint(lab).astype(np.int64)
+    vals = (-1.0 + (2 * np.arange(1 << LEVEL) + 1) / (1 << LEVEL)).astype(np.longdouble)
+    pw = np.ones((101, 1 << LEVEL), np.longdouble)
+    for e in range(1, 101):
+        pw[e] = pw[e - 1] * vals
+    g = gbar.astype(np.longdouble)
+    es = np.argwhere(synth.simplex_mask(3, 100))
+    for e in es[rng.choice(len(es), 40, replace=False)]:
+        mono = pw[e[0]][lab[:, 0]] * pw[e[1]][lab[:, 1]] * pw[e[2]][lab[:, 2]]
+        for p in range(2):
+            ref = np.sum(g[p] * mono)
+            bound = float(np.sum(np.abs(g[p] * mono)))
+            tol = (n + 3 * 100 + 10) * EPS * bound
+            assert abs(float(dcoef[p][tuple(e)]) - float(ref)) <= tol + 1e-300, (p, tuple(e))
+
+
+@pytest.mark.timeout(900)
+def test_newton_three_steps_match_cpu(vx, grid):
+    """Three minimum-norm Newton steps x <- x - J^T (J J^T)^-1 F from 500
+    seeded level-10 centres, on the GPU (newton_project) and on the CPU from
+    the oracle's values and the derivative polynomials (whose coefficients
+    e_j c_e round differently from the forward-mode derivative, so the
+    iterates differ by rounding).  Where J J^T stays well conditioned the two
+    end points agree to 1e-8 of the distance travelled, and the residual |F|
+    falls by a factor of 100 or more at the median (about 350 on the CPU for
+    this sample: 4.35 -> 0.0123; C0 keeps boxes up to a few dozen cell widths
+    from the curve, so only some of the points converge within 3 steps)."""
+    import torch
+    _, centres = grid
+    w = synth.curve()
+    rng = np.random.default_rng(4004)
+    x0 = centres[np.sort(rng.choice(len(centres), 500, replace=False))]
+    x, fend = vx.newton_project(w.polys, torch.as_tensor(x0.copy(), device="cuda"), steps=3)
+    xg = x.cpu().numpy()
+    dcs = [[deriv_cube(c, j) for j in range(3)] for c in w.polys]
+    xc = x0.copy()
+    ok = np.ones(len(x0), bool)
+    travel = np.zeros(len(x0))
+    for _ in range(3):
+        F = np.stack([orc.eval_points(c, 100, xc) for c in w.polys], 1)
+        J = np.stack([np.stack([orc.eval_points(dcs[p][j], 100, xc) for j in range(3)], 1) for p in range(2)], 1)
+        JJt = J @ J.transpose(0, 2, 1)
+        ok &= np.linalg.cond(JJt) < 1e8
+        step = (J.transpose(0, 2, 1) @ np.linalg.solve(JJt, F[:, :, None]))[:, :, 0]
+        travel += np.linalg.norm(step, axis=1)
+        xc = xc - step
+    assert ok.sum() >= 450, ok.sum()
+    err = np.linalg.norm(xg - xc, axis=1)[ok]
+    assert np.all(err <= 1e-8 * travel[ok] + 1e-15), np.max(err / np.maximum(travel[ok], 1e-300))
+    r0 = np.abs(np.stack([orc.eval_points(c, 100, x0) for c in w.polys], 1)).max(axis=1)
+    r3 = np.abs(np.stack([orc.eval_points(c, 100, xg) for c in w.polys], 1)).max(axis=1)
+    assert np.array_equal(np.abs(fend.cpu().numpy()).max(axis=0), r3)
+    _say(f"[c4] Newton: median residual {np.median(r0):.3e} -> {np.median(r3):.3e}")
+    assert np.median(r3) <= 1e-2 * np.median(r0)
