@@ -6,6 +6,7 @@ Bar: for every system, the last level's boxes, enclosures (bitwise, -0 ->
 system run alone.
 """
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -210,3 +211,77 @@ def test_batch_capacity_overflow_is_reported(vx):
     b3, r3 = vx.run_subdivision_batch(w.systems, w.domain(), 6)
     assert _same_result(r2, r3)
     b2.close(); b3.close()
+
+
+@pytest.mark.timeout(900)
+def test_batch64_depth8_vs_oracle_every_level(vx):
+    """The batched workload at its stated size (64 systems, degrees 10..60,
+    depth 8, graph replay with autotuned per-level launch shapes) against the
+    oracle at every level, for 8 seeded systems including the one of highest
+    degree and the one with the most level-8 boxes: the evaluated set, every
+    enclosure bit, the keep flags, the kept set, and Theorem 1's steps of the
+    system's own CSF against the oracle's counted steps.
+
+    The depth-8 run's last level is compared directly.  Level L < 8 is read
+    from a run of the same handle configuration stopped at depth L (same
+    systems, capacities and per-level launch shapes): a level's kernels do not
+    depend on the depth a run stops at, and the per-level counts of those
+    runs must equal the depth-8 run's."""
+    from paper_2406_09857_amd.binding import split_systems
+    w = synth.batch()
+    depth, dom = w.depth, w.domain()
+    _say(f"[batch] {w.name}: sizing run, depth {depth}")
+    b0, r0 = vx.run_subdivision_batch(w.systems, dom, depth, graph=False)
+    cap = [max(int(n), 1) for n in r0["need"]]
+    b0.close()
+    del b0, r0
+    b = vx.Batch(w.systems, dom, depth, cap=cap, graph=True)
+    chosen, _ = b.autotune(reps=1)
+    _say(f"[batch] autotuned launch shapes {chosen}")
+    b.run()
+    r = b.result()
+    assert r["rc"] == 0
+    full = _host(r)
+    b.close()
+    del b, r
+    per = split_systems(full["last"], len(w.systems))
+    degs = [s[0].shape[0] - 1 for s in w.systems]
+    top_deg = int(np.argmax(degs))
+    top_boxes = int(np.argmax([len(p["boxes"]) for p in per]))
+    rng = np.random.default_rng(858)
+    pick = {top_deg, top_boxes}
+    for s in rng.permutation(len(w.systems)):
+        if len(pick) == 8:
+            break
+        pick.add(int(s))
+    pick = sorted(pick)
+    _say(f"[batch] systems checked against the oracle: {pick} (degrees {[degs[s] for s in pick]}, "
+         f"level-8 boxes {[len(per[s]['boxes']) for s in pick]})")
+    recs = {}
+    for s in pick:
+        t = time.time()
+        recs[s] = orc.subdivide(w.systems[s], 3, depth, dom=dom, nthreads=orc.max_threads())
+        _say(f"[batch] oracle system {s} (degree {degs[s]}): {time.time() - t:.1f} s")
+    for L in range(depth + 1):
+        if L == depth:
+            h = full
+        else:
+            bl = vx.Batch(w.systems, dom, L, cap=cap, tune=chosen[: L + 1], graph=True)
+            bl.run()
+            rl = bl.result()
+            assert rl["rc"] == 0, L
+            h = _host(rl)
+            bl.close()
+            del bl, rl
+            assert np.array_equal(h["stats"][L], full["stats"][L]), (L, "per-level counts vs the depth-8 run")
+            assert h["steps"][L] == full["steps"][L], (L, "steps vs the depth-8 run")
+        for s in pick:
+            rec = recs[s][L]
+            S = rec["S"] if len(rec["S"]["boxes"]) else _empty_csf()
+            K = orc.csf_from_boxes(rec["kept"], L) if len(rec["kept"]) else _empty_csf()
+            _check_system(h, s, S, rec["lo"][0], rec["hi"][0], rec["keep"], K, f"batch64 level {L}")
+            sub = _sub(h["last"], s)
+            sizes = [len(a) for a in sub["idx"]] if sub is not None else [0, 0, 0]
+            assert sum(orc.theorem1_steps(3, degs[s], sizes)) == int(rec["steps"].sum()), (L, s, "steps")
+        _say(f"[batch] level {L}: {int(full['stats'][L, 0, 3])} boxes over all systems, "
+             f"{len(pick)} systems bit-exact")
