@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -598,7 +599,375 @@ static int mv_level(const vx_poly* P, int np, const MvRun& R, const vx_csf* S, c
   return VX_OK;
 }
 
+constexpr int TM_MAX_TERMS = 256;  // C(k + m, m) for k <= 4, m <= TAYLOR_MAX_ORDER (6): at most 210
+
+__device__ __forceinline__ int64_t dbinom_i(int n, int r) {
+  int64_t v = 1;
+  for (int i = 1; i <= r; i++) v = v * (n - r + i) / i;
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Taylor form of any order m (the same definition; orders 1 and 2 have the
+// dedicated paths above, which give the same bits).  In k variables the term
+// of order j at c is sum_{|alpha| = j} (D^alpha F / alpha!) (x - c)^alpha.
+// The coefficient polynomial of alpha has entry e = prod_i C(e_i + alpha_i,
+// alpha_i) c_{e + alpha}, an exact integer (< 2^53) times the coefficient,
+// rounded outward once.  The terms of orders 0..m-1 are evaluated at the
+// centre enclosures, those of order m over the boxes, each set as systems of
+// polynomials through Algorithm 2 on the level's CSF; then per box
+//   T_m(F, B) = F(c) + sum_{t >= 1} T_t X_t,  X_t = prod_i W_i^alpha_i,
+// W_i = B_i - c_i, the ranges of the powers multiplied over ascending i, the
+// terms summed left to right: orders 1..m, each order's multi-indices as the
+// non-decreasing index tuples i_1 <= ... <= i_j in lexicographic order.
+// ---------------------------------------------------------------------------
+struct TermTab {
+  int8_t a[TM_MAX_TERMS][VX_KMAX];  // multi-index of term t (t = 0: F itself)
+  int n;                             // terms of orders 0..m
+  int ncentre;                       // terms of orders 0..m-1
+  int order;
+};
+
+static void term_tab_rec(TermTab& T, int k, int j, int from, int8_t* alpha, int left) {
+  if (left == 0) {
+    for (int i = 0; i < VX_KMAX; i++) T.a[T.n][i] = i < k ? alpha[i] : 0;
+    T.n++;
+    return;
+  }
+  for (int i = from; i < k; i++) {
+    alpha[i]++;
+    term_tab_rec(T, k, j, i, alpha, left - 1);
+    alpha[i]--;
+  }
+}
+
+static TermTab term_tab(int k, int m) {
+  TermTab T;
+  memset(&T, 0, sizeof T);
+  T.order = m;
+  for (int j = 0; j <= m; j++) {
+    if (j == m) T.ncentre = T.n;
+    int8_t alpha[VX_KMAX] = {0, 0, 0, 0};
+    term_tab_rec(T, k, j, 0, alpha, j);
+  }
+  return T;
+}
+
+// One thread per (polynomial, term t >= 1, cube entry).
+__global__ void k_taylor_coef(DerivArgs a, int k, TermTab T, int64_t cube_max, double* __restrict__ olo,
+                              double* __restrict__ ohi) {
+  round_up_mode();
+  const int nt = T.n - 1;
+  const int p = blockIdx.y / nt, t = 1 + blockIdx.y % nt;
+  const int side = a.side[p], d = a.d[p];
+  int64_t total = 1;
+  for (int j = 0; j < k; j++) total *= side;
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= total) return;
+  int e[VX_KMAX] = {0, 0, 0, 0};
+  int64_t q = f, stride = 1, shift = 0;
+  int deg = 0, order = 0;
+  bool inside = true;
+  for (int j = k - 1; j >= 0; j--) {
+    e[j] = (int)(q % side);
+    q /= side;
+    deg += e[j];
+    order += T.a[t][j];
+    shift += T.a[t][j] * stride;
+    inside = inside && e[j] + T.a[t][j] < side;
+    stride *= side;
+  }
+  double* lo = olo + (int64_t)blockIdx.y * cube_max;
+  double* hi = ohi + (int64_t)blockIdx.y * cube_max;
+  if (deg + order > d || !inside) {
+    lo[f] = 0.0;
+    hi[f] = 0.0;
+    return;
+  }
+  double m = 1.0;  // prod_i C(e_i + alpha_i, alpha_i): exact (the host keeps C(d + m, m) < 2^53)
+  for (int j = 0; j < k; j++) m *= (double)dbinom_i(e[j] + T.a[t][j], T.a[t][j]);
+  const int64_t src = f + shift;
+  const double cl = a.clo[p][src];
+  const double ch = a.chi[p] ? a.chi[p][src] : cl;
+  lo[f] = -opaque(m * opaque(-cl));  // RD(m * cl) = -RU(m * -cl)
+  hi[f] = m * ch;
+}
+
+// Range of x^a over W = [lo, hi] with lo <= 0 <= hi (W = B_i - c_i always
+// holds 0), held as (nlo, hi), in round-up mode: odd a gives
+// [-RU(nlo^a), RU(hi^a)], even a gives [0, RU(max(nlo, hi)^a)]; the powers
+// of the nonnegative bounds by repeated multiplication, left to right.
+__device__ __forceinline__ double pow_ru(double v, int a) {
+  double p = v;
+  for (int i = 1; i < a; i++) p = p * v;
+  return p;
+}
+
+__device__ __forceinline__ void pow_straddle(double wnl, double wh, int a, double& pnl, double& ph) {
+  if (a == 1) {
+    pnl = wnl;
+    ph = wh;
+  } else if (a & 1) {
+    pnl = pow_ru(wnl, a);
+    ph = pow_ru(wh, a);
+  } else {
+    pnl = 0.0;
+    ph = pow_ru(fmax(wnl, wh), a);
+  }
+}
+
+// T_m for every leaf and polynomial; keep (if given) is AND-ed with "0 in
+// T_m(F_p, B) for every p" (NaN endpoints never exclude).  Layouts: fc
+// (np x nleaf), centre terms ((p, t - 1) x nleaf for t = 1..ncentre-1), box
+// terms ((p, t - ncentre) x nleaf).
+__global__ void k_tm_combine(int k, int np, int64_t nleaf, GridSet gs, const int32_t* __restrict__ labels,
+                             TermTab T, const double* __restrict__ fc_lo, const double* __restrict__ fc_hi,
+                             const double* __restrict__ tc_lo, const double* __restrict__ tc_hi,
+                             const double* __restrict__ tb_lo, const double* __restrict__ tb_hi,
+                             double* __restrict__ lo, double* __restrict__ hi, uint8_t* __restrict__ keep) {
+  round_up_mode();
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  double wnl[VX_KMAX], wh[VX_KMAX];
+  for (int i = 0; i < k; i++) {
+    double inl, ih, cnl, ch;
+    const int32_t lab = labels[b * k + i];
+    cell(gs.cell[i], lab, inl, ih);
+    cell(gs.centre[i], lab, cnl, ch);
+    wnl[i] = ch + inl;  // -RD(lo_i - chi_i) = RU(chi_i - lo_i)
+    wh[i] = ih + cnl;   // RU(hi_i - clo_i)
+  }
+  const int ncm = T.ncentre - 1, nbx = T.n - T.ncentre;
+  bool excl = false;
+  for (int p = 0; p < np; p++) {
+    double anl = -opaque(fc_lo[(int64_t)p * nleaf + b]);
+    double ah = fc_hi[(int64_t)p * nleaf + b];
+    for (int t = 1; t < T.n; t++) {
+      double xnl = 0.0, xh = 0.0;
+      bool first = true;
+      for (int i = 0; i < k; i++) {
+        const int a = T.a[t][i];
+        if (a == 0) continue;
+        double pnl, ph;
+        pow_straddle(wnl[i], wh[i], a, pnl, ph);
+        if (first) {
+          xnl = pnl;
+          xh = ph;
+          first = false;
+        } else {
+          step_gen(xnl, xh, cell_ops(pnl, ph, CLS_STRADDLE), 0.0, 0.0);  // X * P (+ 0: exact)
+        }
+      }
+      const int64_t ti = t < T.ncentre ? ((int64_t)p * ncm + (t - 1)) * nleaf + b
+                                       : ((int64_t)p * nbx + (t - T.ncentre)) * nleaf + b;
+      const double* tl = t < T.ncentre ? tc_lo : tb_lo;
+      const double* th = t < T.ncentre ? tc_hi : tb_hi;
+      double tnl = -opaque(tl[ti]);
+      double tt = th[ti];
+      step_gen(tnl, tt, cell_ops(xnl, xh, CLS_STRADDLE), anl, ah);  // T_t * X_t + acc
+      anl = tnl;
+      ah = tt;
+    }
+    const double l = -opaque(anl);
+    lo[(int64_t)p * nleaf + b] = l;
+    hi[(int64_t)p * nleaf + b] = ah;
+    excl = excl || (l > 0.0) || (ah < 0.0);
+  }
+  if (keep && excl) keep[b] = 0;
+}
+
+// The term polynomials of a run (coefficient cube pointers null when only
+// sizes are wanted): centre terms (p, t = 1..ncentre-1) and box terms
+// (p, t = ncentre..n-1), each list cut into systems of at most VX_MAXPOLY.
+struct TmPolys {
+  TermTab T;
+  std::vector<vx_poly> tc, tb;
+  int64_t cube_max = 1;
+};
+
+static TmPolys tm_polys(const vx_poly* P, int np, int order, double* clo, double* chi) {
+  TmPolys M;
+  const int k = P[0].k;
+  M.T = term_tab(k, order);
+  for (int p = 0; p < np; p++) {
+    int64_t cube = 1;
+    for (int j = 0; j < k; j++) cube *= P[p].side;
+    M.cube_max = cube > M.cube_max ? cube : M.cube_max;
+  }
+  for (int p = 0; p < np; p++)
+    for (int t = 1; t < M.T.n; t++) {
+      int j = 0;
+      for (int i = 0; i < k; i++) j += M.T.a[t][i];
+      vx_poly q;
+      memset(&q, 0, sizeof q);
+      q.k = k;
+      q.degree = P[p].degree > j ? P[p].degree - j : 0;
+      q.side = P[p].side;
+      const int64_t slot = (int64_t)p * (M.T.n - 1) + (t - 1);
+      q.c_lo = clo ? clo + slot * M.cube_max : nullptr;
+      q.c_hi = chi ? chi + slot * M.cube_max : nullptr;
+      (t < M.T.ncentre ? M.tc : M.tb).push_back(q);
+    }
+  return M;
+}
+
+static int nchunks(size_t n) { return (int)((n + VX_MAXPOLY - 1) / VX_MAXPOLY); }
+
+struct TmRun {
+  TmPolys M;
+  Prepared QF;
+  std::vector<Prepared> QC, QB;  // per chunk of the centre and box term systems
+  double* clo = nullptr;
+  double* chi = nullptr;
+};
+
+static size_t chunk_prepared_bytes(const std::vector<vx_poly>& v) {
+  size_t b = 0;
+  for (int c = 0; c < nchunks(v.size()); c++) {
+    const int n = (int)std::min(v.size() - (size_t)c * VX_MAXPOLY, (size_t)VX_MAXPOLY);
+    b += (prepared_bytes(v.data() + (size_t)c * VX_MAXPOLY, n) + 255) / 256 * 256;
+  }
+  return b;
+}
+
+static size_t tm_run_bytes(const vx_poly* P, int np, int order) {
+  TmPolys M = tm_polys(P, np, order, nullptr, nullptr);
+  const size_t cubes = (sizeof(double) * (size_t)M.cube_max * np * (M.T.n - 1) + 255) / 256 * 256;
+  return 2 * cubes + (prepared_bytes(P, np) + 255) / 256 * 256 + chunk_prepared_bytes(M.tc) +
+         chunk_prepared_bytes(M.tb) + 2048;
+}
+
+static int prepare_chunks(const std::vector<vx_poly>& v, char*& at, std::vector<Prepared>& out, hipStream_t st) {
+  int rc;
+  for (int c = 0; c < nchunks(v.size()); c++) {
+    const int n = (int)std::min(v.size() - (size_t)c * VX_MAXPOLY, (size_t)VX_MAXPOLY);
+    const size_t b = (prepared_bytes(v.data() + (size_t)c * VX_MAXPOLY, n) + 255) / 256 * 256;
+    Prepared Q;
+    if ((rc = prepare_polys(v.data() + (size_t)c * VX_MAXPOLY, n, at, b, &Q, st))) return rc;
+    out.push_back(Q);
+    at += b;
+  }
+  return VX_OK;
+}
+
+static int tm_run_prepare(const vx_poly* P, int np, int order, char* ws, size_t bytes, TmRun& R, hipStream_t st) {
+  if (tm_run_bytes(P, np, order) > bytes) VX_FAIL(VX_ECAPACITY, "Taylor test: workspace too small");
+  TmPolys M0 = tm_polys(P, np, order, nullptr, nullptr);
+  const size_t cubes = (sizeof(double) * (size_t)M0.cube_max * np * (M0.T.n - 1) + 255) / 256 * 256;
+  R.clo = reinterpret_cast<double*>(ws);
+  R.chi = reinterpret_cast<double*>(ws + cubes);
+  R.M = tm_polys(P, np, order, R.clo, R.chi);
+  const int k = P[0].k;
+  hipLaunchKernelGGL(k_taylor_coef, dim3((unsigned)((R.M.cube_max + 255) / 256), (unsigned)(np * (R.M.T.n - 1))),
+                     dim3(256), 0, st, deriv_args(P, np), k, R.M.T, R.M.cube_max, R.clo, R.chi);
+  VX_CHECK_LAUNCH("k_taylor_coef");
+  char* at = ws + 2 * cubes;
+  const size_t qf = (prepared_bytes(P, np) + 255) / 256 * 256;
+  int rc;
+  if ((rc = prepare_polys(P, np, at, qf, &R.QF, st))) return rc;
+  at += qf;
+  if ((rc = prepare_chunks(R.M.tc, at, R.QC, st))) return rc;
+  if ((rc = prepare_chunks(R.M.tb, at, R.QB, st))) return rc;
+  return VX_OK;
+}
+
+static size_t tm_scratch_bytes(const vx_poly* P, int np, const TmPolys& M, const vx_csf* S) {
+  size_t e = eval_level_bytes(P, np, S);
+  for (const std::vector<vx_poly>* v : {&M.tc, &M.tb})
+    for (int c = 0; c < nchunks(v->size()); c++) {
+      const int n = (int)std::min(v->size() - (size_t)c * VX_MAXPOLY, (size_t)VX_MAXPOLY);
+      const size_t b = eval_level_bytes(v->data() + (size_t)c * VX_MAXPOLY, n, S);
+      e = b > e ? b : e;
+    }
+  return e;
+}
+
+static size_t tm_level_bytes(const vx_poly* P, int np, const TmPolys& M, const vx_csf* S) {
+  const int k = S->k;
+  const int64_t nl = S->n[k - 1];
+  auto r = [](size_t b) { return (b + 255) / 256 * 256; };
+  return r(sizeof(double) * np * nl) * 2 + r(sizeof(double) * M.tc.size() * nl + 8) * 2 +
+         r(sizeof(double) * M.tb.size() * nl + 8) * 2 + r(sizeof(int32_t) * k * nl) + tm_scratch_bytes(P, np, M, S) +
+         256;
+}
+
+static int eval_chunks(const std::vector<Prepared>& Q, const std::vector<vx_poly>& v, const vx_csf* S,
+                       const double* dom, double* lo, double* hi, char* scratch, size_t sb, hipStream_t st,
+                       int centre) {
+  const int64_t nl = S->n[S->k - 1];
+  int rc;
+  for (size_t c = 0; c < Q.size(); c++) {
+    const size_t off = c * VX_MAXPOLY;
+    if ((rc = eval_level_prepared(Q[c], S, dom, lo + off * nl, hi + off * nl, nullptr, scratch, sb, st,
+                                  v.data() + off, centre)))
+      return rc;
+  }
+  return VX_OK;
+}
+
+static int tm_level(const vx_poly* P, int np, const TmRun& R, const vx_csf* S, const double* dom, double* lo,
+                    double* hi, uint8_t* keep, char* ws, size_t bytes, hipStream_t st) {
+  const int k = S->k;
+  const int64_t nl = S->n[k - 1];
+  if (nl == 0) return VX_OK;
+  Arena A;
+  A.base = ws;
+  A.size = bytes;
+  double* fcl = A.take<double>((size_t)np * nl);
+  double* fch = A.take<double>((size_t)np * nl);
+  double* tcl = A.take<double>(R.M.tc.size() * nl + 1);
+  double* tch = A.take<double>(R.M.tc.size() * nl + 1);
+  double* tbl = A.take<double>(R.M.tb.size() * nl + 1);
+  double* tbh = A.take<double>(R.M.tb.size() * nl + 1);
+  int32_t* labels = A.take<int32_t>((size_t)k * nl);
+  const size_t sb = tm_scratch_bytes(P, np, R.M, S);
+  char* scratch = A.take<char>(sb);
+  if (A.overflow) VX_FAIL(VX_ECAPACITY, "Taylor test: workspace of %zu bytes is too small", bytes);
+  const int pr = prof_start("taylor_m", (double)nl, st);
+  int rc;
+  // F and the terms of orders 1..m-1 at the centres, the order-m terms on the boxes
+  if ((rc = eval_level_prepared(R.QF, S, dom, fcl, fch, nullptr, scratch, sb, st, P, 1))) return rc;
+  if ((rc = eval_chunks(R.QC, R.M.tc, S, dom, tcl, tch, scratch, sb, st, 1))) return rc;
+  if ((rc = eval_chunks(R.QB, R.M.tb, S, dom, tbl, tbh, scratch, sb, st, 0))) return rc;
+  CsfView cv;
+  memset(&cv, 0, sizeof cv);
+  for (int l = 0; l < k; l++) {
+    cv.idx[l] = S->idx[l];
+    cv.ptr[l] = S->ptr[l];
+    cv.n[l] = S->n[l];
+  }
+  const unsigned nb = (unsigned)((nl + 255) / 256);
+  hipLaunchKernelGGL(k_leaf_labels, dim3(nb), dim3(256), 0, st, k, cv, labels);
+  VX_CHECK_LAUNCH("k_leaf_labels");
+  GridSet gs;
+  memset(&gs, 0, sizeof gs);
+  for (int i = 0; i < k; i++) {
+    AxisGrid g;
+    g.dlo = dom[2 * i];
+    g.dhi = dom[2 * i + 1];
+    g.ndlo = -g.dlo;
+    g.ndhi = -g.dhi;
+    g.level = S->level;
+    g.centre = 0;
+    gs.cell[i] = g;
+    g.centre = 1;
+    gs.centre[i] = g;
+    g.centre = 2;
+    gs.vertex[i] = g;
+  }
+  hipLaunchKernelGGL(k_tm_combine, dim3(nb), dim3(256), 0, st, k, np, nl, gs, (const int32_t*)labels, R.M.T,
+                     (const double*)fcl, (const double*)fch, (const double*)tcl, (const double*)tch,
+                     (const double*)tbl, (const double*)tbh, lo, hi, keep);
+  VX_CHECK_LAUNCH("k_tm_combine");
+  prof_stop(pr, st);
+  return VX_OK;
+}
+
 size_t mv_workspace_bytes(const vx_poly* P, int np, const vx_csf* S, int order) {
+  if (order >= 3) {
+    TmPolys M = tm_polys(P, np, order, nullptr, nullptr);
+    return (tm_run_bytes(P, np, order) + 255) / 256 * 256 + tm_level_bytes(P, np, M, S) + 512;
+  }
   MvPolys M = mv_polys(P, np, order, nullptr, nullptr, nullptr, nullptr);
   return mv_run_bytes(P, np, order) + mv_level_bytes(P, np, M, S) + 512;
 }
@@ -606,6 +975,14 @@ size_t mv_workspace_bytes(const vx_poly* P, int np, const vx_csf* S, int order) 
 int mv_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
             void* ws, size_t ws_bytes, hipStream_t st, int order, uint8_t* incl) {
   if (S->n[S->k - 1] == 0) return VX_OK;
+  if (order >= 3) {
+    const size_t rb = (tm_run_bytes(P, np, order) + 255) / 256 * 256;
+    if (rb > ws_bytes) VX_FAIL(VX_ECAPACITY, "Taylor test: workspace too small");
+    TmRun R;
+    int rc;
+    if ((rc = tm_run_prepare(P, np, order, reinterpret_cast<char*>(ws), rb, R, st))) return rc;
+    return tm_level(P, np, R, S, dom, lo, hi, keep, reinterpret_cast<char*>(ws) + rb, ws_bytes - rb, st);
+  }
   const size_t rb = (mv_run_bytes(P, np, order) + 255) / 256 * 256;
   if (rb > ws_bytes) VX_FAIL(VX_ECAPACITY, "Taylor test: workspace too small");
   MvRun R;
@@ -616,21 +993,30 @@ int mv_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, double
 
 // Run-level interface for run_subdivision: the tables are built once.
 size_t mv_run_workspace(const vx_poly* P, int np, int order) {
+  if (order >= 3) return (tm_run_bytes(P, np, order) + 255) / 256 * 256;
   return (mv_run_bytes(P, np, order) + 255) / 256 * 256;
 }
 
 size_t mv_level_workspace(const vx_poly* P, int np, const vx_csf* S, int order) {
+  if (order >= 3) {
+    TmPolys M = tm_polys(P, np, order, nullptr, nullptr);
+    return tm_level_bytes(P, np, M, S);
+  }
   MvPolys M = mv_polys(P, np, order, nullptr, nullptr, nullptr, nullptr);
   return mv_level_bytes(P, np, M, S);
 }
 
 struct MvRunHandle {
+  int order = 1;
   MvRun R;
+  TmRun T;
 };
 
 void* mv_run_begin(const vx_poly* P, int np, void* ws, size_t bytes, hipStream_t st, int* rc, int order) {
   MvRunHandle* h = new MvRunHandle;
-  *rc = mv_run_prepare(P, np, order, reinterpret_cast<char*>(ws), bytes, h->R, st);
+  h->order = order;
+  *rc = order >= 3 ? tm_run_prepare(P, np, order, reinterpret_cast<char*>(ws), bytes, h->T, st)
+                   : mv_run_prepare(P, np, order, reinterpret_cast<char*>(ws), bytes, h->R, st);
   if (*rc) {
     delete h;
     return nullptr;
@@ -641,6 +1027,7 @@ void* mv_run_begin(const vx_poly* P, int np, void* ws, size_t bytes, hipStream_t
 int mv_run_level(void* handle, const vx_poly* P, int np, const vx_csf* S, const double* dom, double* lo, double* hi,
                  uint8_t* keep, void* ws, size_t bytes, hipStream_t st) {
   const MvRunHandle* h = reinterpret_cast<const MvRunHandle*>(handle);
+  if (h->order >= 3) return tm_level(P, np, h->T, S, dom, lo, hi, keep, reinterpret_cast<char*>(ws), bytes, st);
   return mv_level(P, np, h->R, S, dom, lo, hi, keep, reinterpret_cast<char*>(ws), bytes, st);
 }
 
