@@ -137,6 +137,26 @@ int interval_eval_level(const vx_poly* P, int32_t np, const vx_csf* S, const dou
                         uint8_t* keep, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * interval_eval_level_noalloc -- interval_eval_level without a workspace
+ * argument, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * scratch is a static 64 MiB device array of the library, one per GPU, held
+ * until the process ends; the call itself allocates nothing.
+ *   Arguments, outputs, results (bit for bit) and errors as
+ *   interval_eval_level; the caller still passes the inputs and outputs.
+ *   A level whose vx_workspace_bytes(VX_WS_EVAL, ...) exceeds 64 MiB
+ *   (67,108,864 bytes) is refused with VX_ECAPACITY before anything is
+ *   enqueued.
+ *   Every call on one GPU shares that GPU's array, and the array keeps the
+ *   last call's contents (every call rewrites what it reads): calls that
+ *   overlap on one GPU (other host threads, or other streams whose work has
+ *   not finished) race and give undefined results.  The first call on a
+ *   device looks up the array's device address once (hipGetSymbolAddress).
+ */
+int interval_eval_level_noalloc(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo,
+                                double* hi, uint8_t* keep, void* stream);
+
+/*
  * mean_value_exclusion -- the Taylor form of order 1 (Sec. 3.2, Taylor form
  * definition with m = 1) as an exclusion test on every box of S:
  *   T(F_p, B) = F_p(c) + sum_i dF_p/dx_i(B) * (B_i - c_i),  c the centre of B,

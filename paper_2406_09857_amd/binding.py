@@ -75,6 +75,8 @@ def lib():
         L.vx_workspace_bytes.restype = C.c_size_t
         L.interval_eval_level.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf), C.POINTER(C.c_double),
                                           vp, vp, vp, vp, C.c_size_t, vp]
+        L.interval_eval_level_noalloc.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(vx_csf),
+                                                  C.POINTER(C.c_double), vp, vp, vp, vp]
         L.filter_subdivide.argtypes = [C.POINTER(vx_csf), vp, C.POINTER(vx_csf), C.POINTER(vx_csf), vp, vp,
                                        C.c_size_t, vp]
         L.run_subdivision.argtypes = [C.POINTER(vx_poly), C.c_int32, C.POINTER(C.c_double), C.c_int32, vp,
@@ -99,7 +101,7 @@ def lib():
         L.vx_copy.argtypes = [vp, vp, C.c_size_t, C.c_int32, vp]
         L.vx_profile_end.argtypes = [C.POINTER(vx_kernel_stat), C.c_int32, C.POINTER(C.c_int32)]
         L.vx_profile_select.argtypes = [C.c_char_p]
-        for f in ("interval_eval_level", "filter_subdivide", "run_subdivision",
+        for f in ("interval_eval_level", "interval_eval_level_noalloc", "filter_subdivide", "run_subdivision",
                   "run_subdivision_ex", "csf_build",
                   "vx_copy", "vx_profile_begin", "vx_profile_end", "vx_profile_select", "mean_value_exclusion",
                   "taylor_exclusion", "inclusion_test", "taylor_inclusion_test", "newton_test"):
@@ -253,6 +255,32 @@ def interval_eval_level(polys, csf: CSF, dom, out=None, keep: bool = True, ws=No
     _check(lib().interval_eval_level(parr, len(polys), C.byref(s), dom.ctypes.data_as(C.POINTER(C.c_double)),
                                      lo.data_ptr(), hi.data_ptr(), kp.data_ptr() if kp is not None else None,
                                      ws.data_ptr(), ws.numel(), _stream(stream)))
+    return lo, hi, (kp[:nb] if kp is not None else None)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def interval_eval_level_noalloc(polys, csf: CSF, dom, out=None, keep: bool = True, stream=None):
+    """interval_eval_level with the library's static per-GPU scratch instead
+    of a workspace (the C call allocates nothing; levels needing more than
+    64 MiB of scratch raise VxError with VX_ECAPACITY)."""
+    polys = as_polys(polys)
+    dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
+    nb = csf.nboxes
+    dev = csf.idx[0].device
+    if out is None:
+        lo = torch.empty((len(polys), nb), dtype=torch.float64, device=dev)
+        hi = torch.empty((len(polys), nb), dtype=torch.float64, device=dev)
+        kp = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev) if keep else None
+    else:
+        lo, hi, kp = out
+    parr = _poly_array(polys)
+    s = csf.struct()
+    _check(lib().interval_eval_level_noalloc(parr, len(polys), C.byref(s),
+                                             dom.ctypes.data_as(C.POINTER(C.c_double)), lo.data_ptr(),
+                                             hi.data_ptr(), kp.data_ptr() if kp is not None else None,
+                                             _stream(stream)))
     return lo, hi, (kp[:nb] if kp is not None else None)
 
 

@@ -16,6 +16,11 @@ namespace vx {
 
 static thread_local std::string g_error;
 
+// Set while interval_eval_level_noalloc runs on this host thread: its
+// launches record no timing events (creating one is an allocation of the
+// runtime).
+static thread_local bool g_prof_suppressed = false;
+
 void set_error(const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -270,6 +275,66 @@ int interval_eval_level(const vx_poly* P, int32_t np, const vx_csf* S, const dou
   if (S->n[S->k - 1] > 0 && (!lo || !hi)) VX_FAIL(VX_EINVAL, "null output arrays");
   if ((rc = check_ws(ws))) return rc;
   return eval_level_impl(P, np, S, dom, lo, hi, keep, ws, ws_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Scratch of interval_eval_level_noalloc: one array per GPU, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, never the
+// device memory: its device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address is handed to
+// kernels.
+// ---------------------------------------------------------------------------
+namespace vx {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+static int scratch_address(void** out) {
+  int dev = 0;
+  VX_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) VX_FAIL(VX_EUNSUPPORTED, "device %d: no scratch slot", dev);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      VX_FAIL(VX_EHIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return VX_OK;
+}
+
+struct ProfSuppress {
+  ProfSuppress() { g_prof_suppressed = true; }
+  ~ProfSuppress() { g_prof_suppressed = false; }
+};
+
+}  // namespace vx
+
+extern "C" {
+
+int interval_eval_level_noalloc(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, double* lo,
+                                double* hi, uint8_t* keep, void* stream) {
+  int rc;
+  if ((rc = check_csf(S, true))) return rc;
+  if ((rc = check_poly(P, np, S->k))) return rc;
+  if ((rc = check_dom(dom, S->k))) return rc;
+  if (S->n[S->k - 1] > 0 && (!lo || !hi)) VX_FAIL(VX_EINVAL, "null output arrays");
+  const size_t need = eval_workspace_bytes(P, np, S);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    VX_FAIL(VX_ECAPACITY, "interval_eval_level_noalloc: this level needs %zu bytes of scratch, the static scratch "
+            "holds %zu (use interval_eval_level with a workspace)", need, NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  if ((rc = scratch_address(&ws))) return rc;
+  ProfSuppress quiet;
+  return eval_level_impl(P, np, S, dom, lo, hi, keep, ws, NOALLOC_SCRATCH_BYTES, (hipStream_t)stream);
 }
 
 int taylor_exclusion(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, int32_t order, double* lo,
@@ -867,10 +932,10 @@ hipEvent_t pool_event() {
 }
 }  // namespace
 
-bool profiling() { return g_prof_on; }
+bool profiling() { return g_prof_on && !g_prof_suppressed; }
 
 int prof_start(const char* name, double units, hipStream_t st) {
-  if (!g_prof_on) return -1;
+  if (!g_prof_on || g_prof_suppressed) return -1;
   std::lock_guard<std::mutex> g(g_prof_mu);
   if (g_prof_only[0] && strncmp(g_prof_only, name, sizeof g_prof_only) != 0) return -1;
   ProfRec r{name, units, pool_event(), pool_event()};
