@@ -325,7 +325,7 @@ int filter_subdivide(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf*
 /* Per-level record of run_subdivision. */
 typedef struct vx_level_stat {
   int32_t level;
-  int32_t reserved;
+  int32_t axes;           /* variable order of the run: CSF depth l holds axis (axes >> 4l) & 15 */
   int64_t n[VX_KMAX];     /* N_l of the evaluated set S_level */
   int64_t kept[VX_KMAX];  /* N_l of the kept set K_level */
   int64_t steps;          /* interval Horner steps, all polynomials (Theorem 1 count) */
@@ -380,16 +380,32 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
  * compaction costs a filter pass and a wait for its counts, which only large
  * levels repay: with VX_RUN_EARLY_EXIT_FROM(L) the levels below L are
  * evaluated as without the flag.  It does not combine with the Taylor or
- * inclusion flags (VX_EINVAL); with one polynomial it has no effect. */
+ * inclusion flags (VX_EINVAL); with one polynomial it has no effect.
+ * VX_RUN_AUTO_ORDER picks the order of the variables by Theorem 1 (its cost
+ * sums the trailing-tuple counts times the node counts N_l(S), which depend on
+ * which variable each CSF depth holds): a probe run in the given order to
+ * level L (VX_RUN_AUTO_ORDER_AT(L), 1..15, default min(depth, 6); plain C0, no
+ * timing) gives the evaluated set of level L, its node counts are taken under
+ * all k! orders (as variable_order_costs does), and the whole run (levels
+ * 0..depth, with the other flags) is done in the cheapest order, ties going
+ * to the first order in lexicographic order of the permutations (the given
+ * order first).  The run in order sigma is the run of the polynomials with
+ * new variable l = old variable sigma[l] (coefficient cubes transposed, the
+ * domain's axes permuted): every CSF passed to the callback lists its labels
+ * in that order, and stats[].axes records it.  The probe adds the cost of
+ * levels 0..L; workspace as without the flag plus the transposed coefficients
+ * and the order scratch (run_subdivision_ex reports the total in *ws_needed). */
 enum {
   VX_RUN_MEAN_VALUE = 1,
   VX_RUN_TAYLOR2 = 2,
   VX_RUN_NO_TIMES = 4,
   VX_RUN_INCLUSION = 8,
   VX_RUN_INCLUSION_TAYLOR = 16,
-  VX_RUN_EARLY_EXIT = 32
+  VX_RUN_EARLY_EXIT = 32,
+  VX_RUN_AUTO_ORDER = 64
 };
 #define VX_RUN_TAYLOR_ORDER(m) ((int32_t)(m) << 8)
+#define VX_RUN_AUTO_ORDER_AT(level) ((int32_t)(level) << 12)
 #define VX_RUN_INCLUSION_FROM(level) ((int32_t)(level) << 16)
 #define VX_RUN_EARLY_EXIT_FROM(level) ((int32_t)(level) << 24)
 int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,

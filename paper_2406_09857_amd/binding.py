@@ -27,6 +27,7 @@ VX_OK, VX_EINVAL, VX_ECAPACITY, VX_EHIP, VX_EOVERFLOW, VX_EUNSUPPORTED = 0, -1, 
  VX_WS_ORDER) = range(9)
 VX_RUN_MEAN_VALUE, VX_RUN_TAYLOR2, VX_RUN_NO_TIMES, VX_RUN_INCLUSION, VX_RUN_INCLUSION_TAYLOR = 1, 2, 4, 8, 16
 VX_RUN_EARLY_EXIT = 32
+VX_RUN_AUTO_ORDER = 64
 
 
 class VxError(RuntimeError):
@@ -46,7 +47,7 @@ class vx_csf(C.Structure):
 
 
 class vx_level_stat(C.Structure):
-    _fields_ = [("level", C.c_int32), ("reserved", C.c_int32), ("n", C.c_int64 * KMAX),
+    _fields_ = [("level", C.c_int32), ("axes", C.c_int32), ("n", C.c_int64 * KMAX),
                 ("kept", C.c_int64 * KMAX), ("steps", C.c_int64), ("eval_ms", C.c_double),
                 ("filter_ms", C.c_double), ("certified", C.c_int64)]
 
@@ -435,7 +436,7 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
                     ws: torch.Tensor | None = None, want_kept: bool = True, mean_value: bool = False,
                     taylor2: bool = False, level_times: bool = True, inclusion: str | None = None,
                     inclusion_from: int = 0, early_exit: bool = False, early_exit_from: int = 0,
-                    taylor_order: int = 0):
+                    taylor_order: int = 0, auto_order: bool = False, auto_order_at: int = 0):
     """Algorithm 3 with C0 to `depth`.  Returns (stats, kept) where stats is a
     list of per-level dicts and kept the final level's kept CSF (host numpy).
     ``mean_value`` / ``taylor2`` add the Taylor test of order 1 / 2 to C0,
@@ -448,6 +449,11 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
     earlier ones kept: the same kept sets, fewer steps; ``record`` then gets
     lo = hi = keep = None; ``early_exit_from`` keeps the levels below it plain
     (the compaction pays only on large levels).
+
+    ``auto_order`` runs in the order of the variables that Theorem 1 finds
+    cheapest on the kept set of a probe level (``auto_order_at``, default
+    min(depth, 6)); every CSF then lists its labels in that order, given in
+    each stats record as "axes" (CSF depth l holds variable axes[l]).
 
     ``record(level, S, lo, hi, keep, K)`` is called with device-side views
     (numpy copies) when given; it may return True to stop.
@@ -497,7 +503,11 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
     cb = LEVEL_CB(_cb) if (record is not None or want_kept) else LEVEL_CB()
     flags = ((VX_RUN_MEAN_VALUE if mean_value else 0) | (VX_RUN_TAYLOR2 if taylor2 else 0)
              | (0 if level_times else VX_RUN_NO_TIMES) | (VX_RUN_EARLY_EXIT if early_exit else 0)
-             | (int(taylor_order) << 8))
+             | (int(taylor_order) << 8) | (VX_RUN_AUTO_ORDER if auto_order else 0))
+    if auto_order_at:
+        if not auto_order or not 0 < auto_order_at < 16:
+            raise ValueError("auto_order_at needs auto_order and a level in 1..15")
+        flags |= auto_order_at << 12
     if early_exit_from:
         if not early_exit or not 0 < early_exit_from < 64:
             raise ValueError("early_exit_from needs early_exit and a level in 1..63")
@@ -525,7 +535,8 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
     out = []
     for r in stats:
         out.append({"level": r.level, "n": list(r.n)[:k], "kept": list(r.kept)[:k], "steps": r.steps,
-                    "eval_ms": r.eval_ms, "filter_ms": r.filter_ms, "certified": r.certified})
+                    "eval_ms": r.eval_ms, "filter_ms": r.filter_ms, "certified": r.certified,
+                    "axes": [(r.axes >> (4 * l)) & 15 for l in range(k)]})
     return out, final.get("kept")
 
 

@@ -4,6 +4,7 @@
 #include <stdarg.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -511,9 +512,15 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
   return run_subdivision_ex(P, np, dom, depth, 0, ws, ws_bytes, ws_needed, stats, cb, user, stream);
 }
 
-int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
-                       size_t ws_bytes, size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user,
-                       void* stream) {
+}  // extern "C"
+
+namespace vx {
+
+// The level loop of Algorithm 3 in the variable order `axes` of the caller's
+// polynomials (recorded in the stats; the loop itself is order-blind).
+static int run_loop(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
+                    size_t ws_bytes, size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user,
+                    void* stream, int32_t axes) {
   if (!P || np < 1) VX_FAIL(VX_EINVAL, "need at least one polynomial");
   const int k = P[0].k;
   int rc;
@@ -776,6 +783,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
       vx_level_stat& r = stats[level];
       memset(&r, 0, sizeof r);
       r.level = level;
+      r.axes = axes;
       for (int l = 0; l < k; l++) {
         r.n[l] = S.n[l];
         r.kept[l] = K.n[l];
@@ -804,6 +812,7 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
         if (stats) {
           memset(&stats[lv], 0, sizeof stats[lv]);
           stats[lv].level = lv;
+          stats[lv].axes = axes;
         }
       }
       break;
@@ -813,6 +822,186 @@ int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t 
   // the last filter may still be writing after it published its counts
   VX_HIP(hipStreamSynchronize(st));
   return VX_OK;
+}
+
+// Transposed coefficient cube: new variable l = old variable order[l], i.e.
+// out[e'] = in[e] with e[order[l]] = e'[l] (one thread per entry).
+__global__ void k_transpose_cube(int k, int side, const double* __restrict__ in, double* __restrict__ out,
+                                 int4 order) {
+  int64_t total = 1;
+  for (int i = 0; i < k; i++) total *= side;
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= total) return;
+  const int ord[4] = {order.x, order.y, order.z, order.w};
+  int e[VX_KMAX] = {0, 0, 0, 0};
+  int64_t q = f;
+  for (int l = k - 1; l >= 0; l--) {  // e' of this output entry, placed at the old axes
+    e[ord[l]] = (int)(q % side);
+    q /= side;
+  }
+  int64_t src = 0;
+  for (int i = 0; i < k; i++) src = src * side + e[i];
+  out[f] = in[src];
+}
+
+static int32_t pack_axes(const int* a, int k) {
+  int32_t v = 0;
+  for (int l = 0; l < k; l++) v |= a[l] << (4 * l);
+  return v;
+}
+
+constexpr int AUTO_ORDER_DEFAULT_LEVEL = 6;
+
+struct ProbeState {
+  int level;
+  int norders;
+  const int32_t* orders;
+  int64_t* counts;
+  void* scratch;
+  size_t scratch_bytes;
+  hipStream_t st;
+  int rc;
+  bool done;
+};
+
+// At the probe level: node counts of the kept set under every order.
+static int probe_cb(void* user, int32_t level, const vx_csf* S, const double*, const double*, const uint8_t*,
+                    const vx_csf* K) {
+  (void)S;
+  ProbeState* ps = reinterpret_cast<ProbeState*>(user);
+  if (level != ps->level) return 0;
+  ps->rc = order_counts_impl(K, ps->norders, ps->orders, ps->counts, ps->scratch, ps->scratch_bytes, ps->st);
+  ps->done = true;
+  return 1;
+}
+
+// Algorithm 3 in the order of the variables that Theorem 1 finds cheapest on
+// the kept set of a probe level (its children's node counts are 2^(l+1)
+// times the kept set's, in every order).
+static int run_auto_order(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
+                          size_t ws_bytes, size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user,
+                          hipStream_t st) {
+  if (!P || np < 1) VX_FAIL(VX_EINVAL, "need at least one polynomial");
+  const int k = P[0].k;
+  int rc;
+  if (k < 1 || k > VX_KMAX) VX_FAIL(VX_EINVAL, "k=%d outside [1, %d]", k, VX_KMAX);
+  if ((rc = check_poly(P, np, k))) return rc;
+  if ((rc = check_dom(dom, k))) return rc;
+  if (depth < 0 || depth > 28) VX_FAIL(VX_EINVAL, "depth %d outside [0, 28]", depth);
+  if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
+  if ((rc = check_ws(ws))) return rc;
+  int probe = (flags >> 12) & 15;
+  if (probe == 0) probe = AUTO_ORDER_DEFAULT_LEVEL;
+  if (probe > depth) probe = depth;
+  const int32_t rest = flags & ~(VX_RUN_AUTO_ORDER | VX_RUN_AUTO_ORDER_AT(15));
+  // every permutation of the axes, lexicographic (the given order first)
+  std::vector<int32_t> orders;
+  int perm[VX_KMAX] = {0, 1, 2, 3};
+  int norders = 0;
+  do {
+    for (int l = 0; l < k; l++) orders.push_back(perm[l]);
+    norders++;
+  } while (std::next_permutation(perm, perm + k));
+  // workspace: transposed cubes | (probe run | order scratch at the tail) then the main run
+  size_t cubes = 0;
+  for (int p = 0; p < np; p++) {
+    int64_t c = 1;
+    for (int i = 0; i < k; i++) c *= P[p].side;
+    cubes += ((size_t)c * 8 + 255) / 256 * 256 * (P[p].c_hi ? 2 : 1);
+  }
+  vx_csf bound;
+  memset(&bound, 0, sizeof bound);
+  bound.k = k;
+  bound.level = probe;
+  for (int l = 0; l < k; l++) {
+    const int sh = (l + 1) * probe;
+    bound.n[l] = sh >= 26 ? ((int64_t)1 << 26) : ((int64_t)1 << sh);
+  }
+  const size_t oscratch = (order_workspace_bytes(&bound) + 255) / 256 * 256;
+  if (cubes + oscratch + (1 << 20) > ws_bytes) {
+    if (ws_needed) *ws_needed = cubes + oscratch + ((size_t)64 << 20);
+    VX_FAIL(VX_ECAPACITY, "run_subdivision: workspace too small for the variable-order probe");
+  }
+  char* base = reinterpret_cast<char*>(ws);
+  char* run_ws = base + cubes;
+  const size_t run_bytes = (ws_bytes - cubes) / 256 * 256;
+  std::vector<int64_t> counts((size_t)norders * k, 0);
+  ProbeState ps{probe, norders, orders.data(), counts.data(), run_ws + run_bytes - oscratch, oscratch, st, VX_OK,
+                false};
+  size_t need = 0;
+  rc = run_loop(P, np, dom, probe, VX_RUN_NO_TIMES, run_ws, run_bytes - oscratch, &need, nullptr, probe_cb, &ps, st,
+                pack_axes(perm, k));
+  if (rc) {
+    if (rc == VX_ECAPACITY && ws_needed) *ws_needed = need + cubes + oscratch;
+    return rc;
+  }
+  if (ps.rc) return ps.rc;
+  // Theorem 1 on the children of the probe's kept set, order by order
+  int best = 0;
+  int64_t best_steps = -1;
+  if (ps.done) {
+    for (int o = 0; o < norders; o++) {
+      vx_csf T;
+      memset(&T, 0, sizeof T);
+      T.k = k;
+      for (int l = 0; l < k; l++) T.n[l] = counts[(size_t)o * k + l] << (l + 1);
+      const int64_t st1 = theorem1_steps(P, np, &T);
+      if (best_steps < 0 || st1 < best_steps) {
+        best_steps = st1;
+        best = o;
+      }
+    }
+  }
+  const int32_t* ord = orders.data() + (size_t)best * k;
+  std::vector<vx_poly> Q(P, P + np);
+  std::vector<double> domq(2 * k);
+  char* at = base;
+  int4 o4 = make_int4(0, 0, 0, 0);
+  int* o4p = reinterpret_cast<int*>(&o4);
+  for (int l = 0; l < k; l++) o4p[l] = ord[l];
+  for (int l = 0; l < k; l++) {
+    domq[2 * l] = dom[2 * ord[l]];
+    domq[2 * l + 1] = dom[2 * ord[l] + 1];
+  }
+  for (int p = 0; p < np; p++) {
+    int64_t c = 1;
+    for (int i = 0; i < k; i++) c *= P[p].side;
+    const unsigned g = (unsigned)((c + 255) / 256);
+    double* lo = reinterpret_cast<double*>(at);
+    at += ((size_t)c * 8 + 255) / 256 * 256;
+    hipLaunchKernelGGL(k_transpose_cube, dim3(g), dim3(256), 0, st, k, P[p].side, P[p].c_lo, lo, o4);
+    VX_CHECK_LAUNCH("k_transpose_cube");
+    Q[p].c_lo = lo;
+    if (P[p].c_hi) {
+      double* hi = reinterpret_cast<double*>(at);
+      at += ((size_t)c * 8 + 255) / 256 * 256;
+      hipLaunchKernelGGL(k_transpose_cube, dim3(g), dim3(256), 0, st, k, P[p].side, P[p].c_hi, hi, o4);
+      VX_CHECK_LAUNCH("k_transpose_cube");
+      Q[p].c_hi = hi;
+    }
+  }
+  int ordi[VX_KMAX] = {0, 0, 0, 0};
+  for (int l = 0; l < k; l++) ordi[l] = ord[l];
+  need = 0;
+  rc = run_loop(Q.data(), np, domq.data(), depth, rest, run_ws, run_bytes, &need, stats, cb, user, st,
+                pack_axes(ordi, k));
+  if (rc == VX_ECAPACITY && ws_needed) *ws_needed = need + cubes;
+  return rc;
+}
+
+}  // namespace vx
+
+extern "C" {
+
+int run_subdivision_ex(const vx_poly* P, int32_t np, const double* dom, int32_t depth, int32_t flags, void* ws,
+                       size_t ws_bytes, size_t* ws_needed, vx_level_stat* stats, vx_level_cb cb, void* user,
+                       void* stream) {
+  if (flags & VX_RUN_AUTO_ORDER)
+    return run_auto_order(P, np, dom, depth, flags, ws, ws_bytes, ws_needed, stats, cb, user, (hipStream_t)stream);
+  if (flags & VX_RUN_AUTO_ORDER_AT(15)) VX_FAIL(VX_EINVAL, "VX_RUN_AUTO_ORDER_AT without VX_RUN_AUTO_ORDER");
+  const int identity[VX_KMAX] = {0, 1, 2, 3};
+  return run_loop(P, np, dom, depth, flags, ws, ws_bytes, ws_needed, stats, cb, user, stream,
+                  pack_axes(identity, P && np > 0 && P[0].k >= 1 && P[0].k <= VX_KMAX ? P[0].k : 1));
 }
 
 static int check_batch(const vx_poly* P, int32_t nsys, int32_t depth, const int64_t* cap) {

@@ -517,10 +517,21 @@ typedef __attribute__((address_space(1))) const dvec2 vrow_t;
 // ROW = crow_t: the row is wave-uniform (scalar loads, the next group issued
 // once the current one has arrived); ROW = vrow_t: every lane reads its own
 // parent's row with vector loads.
+//
+// Scalar rows are also pulled into L2 ahead of the scalar loads: at every
+// eighth group the wave loads the first dword of each 16-byte entry of the
+// 64-entry block that starts 8 groups later straight into a scratch corner
+// of LDS (global_load_lds: no register waits for it, nothing reads it), so
+// that the scalar loads of those groups find the lines in L2 rather than
+// waiting on HBM.  The wave waits for those loads before it leaves.
+#ifndef VX_NARROW_PREFETCH
+#define VX_NARROW_PREFETCH 1
+#endif
 template <int CLS, class ROW>
 __device__ __forceinline__ void narrow_padded(ROW* __restrict__ C, int j, const int jend, const CellOps& o,
                                               bool valid, double* __restrict__ out, int64_t es, int out_width) {
   constexpr bool SCALAR = __is_same(ROW, crow_t);
+  constexpr bool PREFETCH = SCALAR && VX_NARROW_PREFETCH;
   // vector rows move half groups (chains still end on whole PADG groups), so
   // that the two register buffers cost 32 VGPRs, not 64
   constexpr int G = SCALAR ? PADG : PADG / 2;
@@ -541,6 +552,16 @@ __device__ __forceinline__ void narrow_padded(ROW* __restrict__ C, int j, const 
       else if (CLS == CLS_NEG) step_neg(nl, hh, o.u, o.v, X[e].x, X[e].y);
       else step_gen(nl, hh, o, X[e].x, X[e].y);
     }
+  };
+  typedef __attribute__((address_space(1))) const double gdbl_t;
+  typedef __attribute__((address_space(1))) const void gvoid_t;
+  typedef __attribute__((address_space(3))) void lvoid_t;
+  __shared__ int pf_lds[64];
+  gdbl_t* V = reinterpret_cast<gdbl_t*>(reinterpret_cast<uintptr_t>(C));
+  auto prefetch = [&]() {
+    if (PREFETCH && (g & 7) == 0 && g + 16 <= glast)  // lane l: entry l of the block, every line of it
+      __builtin_amdgcn_global_load_lds((gvoid_t*)(V + 2 * ((int64_t)(g + 8) * G + threadIdx.x)), (lvoid_t*)pf_lds,
+                                       4, 0, 0);
   };
   auto finish = [&]() {
     g++;
@@ -565,6 +586,7 @@ __device__ __forceinline__ void narrow_padded(ROW* __restrict__ C, int j, const 
 #pragma unroll
         for (int e = 0; e < G; e++) B[e] = C[(int64_t)(g + 1) * G + z + e];
       }
+      prefetch();
       steps(A);
       finish();
       if (!more) break;
@@ -576,11 +598,13 @@ __device__ __forceinline__ void narrow_padded(ROW* __restrict__ C, int j, const 
 #pragma unroll
         for (int e = 0; e < G; e++) A[e] = C[(int64_t)(g + 1) * G + z + e];
       }
+      prefetch();
       steps(B);
       finish();
       if (!more) break;
     }
   }
+  if (PREFETCH) __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): no LDS write in flight when the wave ends
 }
 
 // Padded rows (k = 3): split g of n splits the chains 0..d into runs of about

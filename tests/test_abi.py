@@ -126,7 +126,8 @@ def test_inclusion_run_flags_are_checked_before_any_work():
     assert run(1, 3 << 16) == b.VX_EINVAL and b"without an inclusion flag" in L.vx_last_error()
     assert run(1, b.VX_RUN_EARLY_EXIT | b.VX_RUN_INCLUSION) == b.VX_EINVAL
     assert b"does not combine" in L.vx_last_error()
-    assert run(1, 64) == b.VX_EINVAL and b"unknown flags" in L.vx_last_error()
+    assert run(1, 128) == b.VX_EINVAL and b"unknown flags" in L.vx_last_error()
+    assert run(1, 5 << 12) == b.VX_EINVAL and b"AUTO_ORDER_AT without" in L.vx_last_error()
 
 
 def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):

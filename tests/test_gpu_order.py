@@ -122,3 +122,69 @@ def test_run_permuted_interval_system(vx):
     for r in want:
         if len(r["S"]["boxes"]):
             assert csf_equal(seen[r["level"]], orc.csf_from_boxes(r["kept"], r["level"])), r["level"]
+
+
+def _near_plane_x3(seed):
+    """x3 - 1/3 plus a small random degree-4 perturbation: a surface that is a
+    graph over (x1, x2), cheapest with x3 as the first CSF variable."""
+    p = 0.05 * synth.small_random(3, 4, seed=seed)[0]
+    p[0, 0, 1] += 1.0
+    p[0, 0, 0] -= 1.0 / 3.0
+    return p
+
+
+def _auto_cases():
+    r = synth.small_random(3, 5, seed=91, npolys=2)
+    lo = r[1] - 1e-6 * np.abs(r[1])
+    hi = r[1] + 1e-6 * np.abs(r[1])
+    return {
+        "near_plane_x3": ([_near_plane_x3(90)], 3, 7, 4, np.array([-1.0, 1.0] * 3)),
+        "points_system": (synth.points().polys, 3, 7, 5, synth.points().domain()),
+        "interval_system_odd_domain": ([_near_plane_x3(92), (lo, hi)], 3, 6, 3,
+                                       np.array([-0.7, 1.1, -1.0, 0.9, -1.3, 1.0])),
+        "tiny": (synth.tiny().polys, 2, 8, 6, synth.tiny().domain()),
+    }
+
+
+@pytest.mark.parametrize("name", list(_auto_cases()))
+def test_run_with_automatic_variable_order_matches_oracle(vx, name):
+    """VX_RUN_AUTO_ORDER: the order is Theorem 1's argmin over the children of
+    the probe level's kept set (ties to the first permutation in
+    lexicographic order), found here by the oracle; the run then equals, level
+    by level, the oracle's run of the transposed polynomials on the permuted
+    domain (evaluated set and kept set of every level)."""
+    polys, k, depth, probe, dom = _auto_cases()[name]
+    _say(f"[order] automatic order: {name}, probe level {probe}, depth {depth}")
+    pre = orc.subdivide(polys, k, probe, dom=dom, nthreads=orc.max_threads())[-1]
+    degrees = [orc.poly_degree(p) for p in polys]
+    orders = list(itertools.permutations(range(k)))
+    if len(pre["kept"]):
+        costs = orc.order_costs(orc.children_of(pre["kept"]), probe + 1, degrees, orders)
+        best = min(range(len(orders)), key=lambda o: (costs[o][2], o))
+    else:
+        best = 0
+    order = list(orders[best])
+    got = {}
+
+    def rec(level, S, lo, hi, keep, K):
+        got[level] = (S, K)
+        return False
+
+    stats, _ = vx.run_subdivision(polys, dom, depth, record=rec, auto_order=True, auto_order_at=probe)
+    assert all(s["axes"] == order for s in stats), (stats[0]["axes"], order)
+    tp = vx.permute_variables(polys, order)
+    tdom = np.asarray(dom, np.float64).reshape(k, 2)[order].reshape(-1)
+    ref = orc.subdivide(tp, k, depth, dom=tdom, nthreads=orc.max_threads())
+    for r in ref:
+        if r["level"] not in got:
+            assert len(r["S"]["boxes"]) == 0
+            continue
+        S, K = got[r["level"]]
+        assert csf_equal(S, r["S"]), (name, r["level"])
+        assert csf_equal(K, orc.csf_from_boxes(r["kept"], r["level"])), (name, r["level"])
+    if name == "near_plane_x3":
+        assert order[0] == 2
+    plain, _ = vx.run_subdivision(polys, dom, depth)
+    _say(f"[order] {name}: order {order}, steps {sum(s['steps'] for s in stats)} against "
+         f"{sum(s['steps'] for s in plain)} in the given order")
+    assert all(s["axes"] == list(range(k)) for s in plain)
