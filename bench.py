@@ -25,11 +25,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "interval box-evals/sec per level + % FP64-VALU peak; batched & adjoint vs plain"
-# MI355X: 256 CUs x 64 FP64 lanes x 2.4 GHz = 39.3e12 FP64 VALU operations/s
-# without fused multiply-add (the published 78.6 TFLOP/s counts an FMA as two).
-FP64_NOFMA_PEAK = 256 * 64 * 2.4e9
-OPS_PER_STEP = 4      # lower/upper product and lower/upper sum of one interval Horner step
-VALU_PER_STEP = 8     # FP64 instructions per step in the sign-specialized kernels
+# MI355X published FP64 vector peak (an FMA counts as two operations).
+FP64_PEAK = 78.6e12
+# FP64 VALU instruction issue without fused multiply-add: 256 CUs x 64 lanes
+# x 2.4 GHz = 39.3e12 lane-instructions/s (every FP64 instruction, min/max
+# included, occupies the lane for one issue slot).
+FP64_ISSUE_PEAK = 256 * 64 * 2.4e9
+OPS_PER_STEP = 4      # algorithmic: lower/upper product and lower/upper sum of one interval Horner step
+EVAL_KERNELS = ("k_stage1", "k_narrow", "k_leaf")
 
 
 def parse():
@@ -115,7 +118,7 @@ def bench_batched(vx, reps):
     return {"workload": f"{w.name}: {len(w.systems)} single-polynomial trivariate systems, degrees uniform in "
                         f"[10, 60], N(0,1) coefficients, domain [-1,1]^3, levels 0..{w.depth}",
             "ms_per_run": ms, "box_evals_per_s": evals / (ms * 1e-3), "interval_steps": steps,
-            "fp64_valu_frac": VALU_PER_STEP * steps / (ms * 1e-3) / FP64_NOFMA_PEAK,
+            "fp64_flop_frac": OPS_PER_STEP * steps / (ms * 1e-3) / FP64_PEAK,
             "plain_64_runs_ms": plain_ms, "speedup_vs_plain": plain_ms / ms,
             "mode": "hipGraph replay, per-level autotuned launch shapes",
             "tune": chosen, "node_capacity": cap,
@@ -123,30 +126,38 @@ def bench_batched(vx, reps):
 
 
 def bench_adjoint(vx, polys, dom, depth, kept):
-    """Point evaluation on the final kept-box centres: forward only, forward +
-    hand-written backward (dF/dx and dF/dcoef on the CSF grid), 3 Newton steps."""
-    import numpy as np
+    """Point evaluation on the final kept-box centres: the forward on the CSF
+    grid of centres (amortized) and per point, forward + hand-written backward
+    (Jacobian, dF/dx and dF/dcoef on the grid), 3 Newton steps (per point:
+    the steps move the points off the grid)."""
     import torch
     csf = vx.CSF.from_arrays(3, depth, kept["idx"], kept["ptr"])
     x = vx.csf_centres(csf, dom)
     n = int(x.shape[0])
     gbar = torch.ones((len(polys), n), dtype=torch.float64, device="cuda")
-    fwd = lambda: vx.eval_grad(polys, x, want_jac=False)
-    fb = lambda: vx.eval_grad(polys, x, want_jac=True, gbar=gbar, want_xbar=True, want_dcoef=True, grid=csf,
+    fwd = lambda: vx.eval_grad(polys, None, want_jac=False, grid=csf, dom=dom)
+    fwd_jac = lambda: vx.eval_grad(polys, None, want_jac=True, grid=csf, dom=dom)
+    fwd_pt = lambda: vx.eval_grad(polys, x, want_jac=False)
+    fb = lambda: vx.eval_grad(polys, None, want_jac=True, gbar=gbar, want_xbar=True, want_dcoef=True, grid=csf,
                               dom=dom)
-    fwd(); fb()
+    fwd(); fwd_jac(); fwd_pt(); fb()
     torch.cuda.synchronize()
-    f_ms = _evt_ms(fwd)
+    f_ms = min(_evt_ms(fwd) for _ in range(3))
+    fj_ms = min(_evt_ms(fwd_jac) for _ in range(3))
+    fpt_ms = _evt_ms(fwd_pt)
     fb_ms = _evt_ms(fb)
     f0 = fwd()[0].abs().amax(dim=0)
     xn = x.clone()
     newton_ms = _evt_ms(lambda: vx.newton_project(polys, xn, steps=3))
     f3 = vx.eval_grad(polys, xn, want_jac=False)[0].abs().amax(dim=0)
-    return {"points": n, "forward_ms": f_ms, "forward_backward_ms": fb_ms, "backward_over_forward": fb_ms / f_ms,
+    return {"points": n, "forward_ms": f_ms, "forward_with_jacobian_ms": fj_ms,
+            "forward_per_point_ms": fpt_ms, "grid_speedup_vs_per_point": fpt_ms / f_ms,
+            "forward_backward_ms": fb_ms, "backward_over_forward": fb_ms / fj_ms,
             "newton3_ms": newton_ms, "median_residual_before": float(torch.median(f0)),
             "median_residual_after_3_newton": float(torch.median(f3)),
-            "parity": "values bit-identical to the oracle, Jacobian vs derivative polynomials and central "
-                      "differences, dcoef vs exact sums (tests/test_gpu_grad.py)"}
+            "parity": "values bit-identical to the oracle and to the per-point path, Jacobian vs derivative "
+                      "polynomials and central differences, dcoef vs long-double sums over the whole grid, "
+                      "Newton vs CPU steps (tests/test_gpu_grad.py, tests/test_gpu_grad_fullsize.py)"}
 
 
 def bench_mean_value(vx, polys, dom, depth, plain_stats, plain_ms):
@@ -181,6 +192,26 @@ def bench_taylor2(vx, polys, dom, depth, plain_stats, plain_ms, mv_stats):
             "mean_value_kept_per_level": mv_stats,
             "plain_kept_per_level": [s["kept"][2] for s in plain_stats],
             "parity": "enclosures bit-identical to the oracle (tests/test_gpu_taylor2.py)"}
+
+
+def bench_taylor_m(vx, polys, dom, depth, plain_stats, plain_ms, t2_stats, m=3):
+    """The curve run with C0 and the Taylor test of order m >= 3 (the
+    multinomial terms of orders below m at the centres, those of order m on
+    the boxes), against C0 alone and against C0 with the order-2 test."""
+    import torch
+    vx.run_subdivision(polys, dom, depth, want_kept=False, taylor_order=m)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        stats, _ = vx.run_subdivision(polys, dom, depth, want_kept=False, taylor_order=m)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"order": m, "ms_per_run": ms, "plain_ms_per_run": plain_ms,
+            "kept_per_level": [s["kept"][2] for s in stats],
+            "taylor2_kept_per_level": t2_stats,
+            "plain_kept_per_level": [s["kept"][2] for s in plain_stats],
+            "parity": "enclosures bit-identical to the oracle (tests/test_gpu_taylor_m.py)"}
 
 
 def bench_early_exit(vx, polys, dom, depth, plain_stats, plain_ms):
@@ -331,22 +362,26 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": COPY_BYTES, "copy_bytes_written": COPY_BYTES}))
 
 
+# The sources compiled into the evaluation kernels (eval.hip and what it includes).
+EVAL_SOURCES = ("eval.hip", "eval.hpp", "batch.inc", "common.hpp", "fill.hpp", "interval.hpp", "profile.hpp",
+                "scan.hpp", "xcd.hpp")
+
+
 def source_digest() -> str:
-    """Digest of the HIP sources: a traffic figure measured on other sources is stale."""
+    """Digest of the evaluation kernels' sources: a counter or traffic figure
+    measured on other sources is stale."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2406_09857_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in sorted(EVAL_SOURCES):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (profiles/<kernel>_<workload>_traffic.txt), or None when there is none
-    or the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+def _profile_fields(path: str):
+    """key: value lines of a committed counter summary, or None when it is
+    missing or was taken on other kernel sources."""
     if not os.path.exists(path):
         return None
     fields = {}
@@ -355,6 +390,36 @@ def measured_traffic(kernel: str, workload: str):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     if fields.get("source_sha256") != source_digest():
+        return None
+    return fields
+
+
+def measured_inst_per_step(workload: str):
+    """VALU instructions (all of them: the FP64 products, sums and max of the
+    interval steps and everything else the kernels issue) per interval step
+    of each evaluation kernel and over all three, counted by rocprofv3
+    (SQ_INSTS_VALU, one count per wave instruction, times 64 lanes) and
+    divided by Theorem 1's steps of the counted launches; from the committed
+    summary profiles/eval_kernels_<workload>_counters.txt, or None when it is
+    missing or was taken on other sources."""
+    f = _profile_fields(os.path.join(ROOT, "profiles", f"eval_kernels_{workload}_counters.txt"))
+    if f is None:
+        return None
+    out = {}
+    for name in EVAL_KERNELS + ("all",):
+        try:
+            out[name] = float(f[f"{name}.valu_inst_per_step"])
+        except (KeyError, ValueError):
+            return None
+    return out
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_<workload>_traffic.txt), or None when there is none
+    or the kernel sources changed since it was taken."""
+    fields = _profile_fields(os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt"))
+    if fields is None:
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
@@ -416,12 +481,25 @@ def main():
     evals = sum(len(polys) * s["n"][w.k - 1] for s in stats)
     steps_total = sum(s["steps"] for s in stats)
     eval_ms = sum(s["eval_ms"] for s in stats)
-    levels = [{"level": s["level"], "boxes": s["n"][w.k - 1], "N": s["n"], "kept": s["kept"][w.k - 1],
-               "eval_ms": round(s["eval_ms"], 4), "filter_ms": round(s["filter_ms"], 4),
-               "box_evals_per_s": (len(polys) * s["n"][w.k - 1] / (s["eval_ms"] * 1e-3)) if s["eval_ms"] > 0 else None,
-               "fp64_valu_frac": (VALU_PER_STEP * s["steps"] / (s["eval_ms"] * 1e-3) / FP64_NOFMA_PEAK)
-               if s["eval_ms"] > 0 else None}
-              for s in stats]
+    ips = measured_inst_per_step(args.workload)  # counted FP64 instructions per step, or None
+
+    def fracs(steps, ms, inst=None):
+        """Algorithmic FP64 FLOP rate over the published peak, and (with a
+        counted instruction rate) the FP64 VALU issue fraction."""
+        if ms <= 0:
+            return None, None
+        flop = OPS_PER_STEP * steps / (ms * 1e-3) / FP64_PEAK
+        issue = inst * steps / (ms * 1e-3) / FP64_ISSUE_PEAK if inst else None
+        return flop, issue
+
+    levels = []
+    for s in stats:
+        fl, iss = fracs(s["steps"], s["eval_ms"], ips["all"] if ips else None)
+        levels.append({"level": s["level"], "boxes": s["n"][w.k - 1], "N": s["n"], "kept": s["kept"][w.k - 1],
+                       "eval_ms": round(s["eval_ms"], 4), "filter_ms": round(s["filter_ms"], 4),
+                       "box_evals_per_s": (len(polys) * s["n"][w.k - 1] / (s["eval_ms"] * 1e-3))
+                       if s["eval_ms"] > 0 else None,
+                       "fp64_flop_frac": fl, "fp64_issue_frac": iss})
 
     roof = None
     kernels = {}
@@ -433,13 +511,23 @@ def main():
     if dom_name and prof.get(dom_name, {}).get("ms", 0) > 0:
         r = prof[dom_name]
         avg_s = r["ms"] * 1e-3 / r["launches"]
-        ops_per_launch = OPS_PER_STEP * r["units"] / r["launches"]
+        steps_per_launch = r["units"] / r["launches"]
+        ops_per_launch = OPS_PER_STEP * steps_per_launch
         achieved = ops_per_launch / avg_s / 1e12
-        roof = {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": FP64_NOFMA_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / (FP64_NOFMA_PEAK / 1e12),
+        inst = ips.get(dom_name) if ips else None
+        roof = {"bound": "alu", "kernel": dom_name, "achieved": achieved, "peak": FP64_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / (FP64_PEAK / 1e12),
                 "traffic": measured_traffic(dom_name, args.workload),
                 "avg_launch_ms": avg_s * 1e3, "ops_per_launch": ops_per_launch,
-                "valu_inst_frac": VALU_PER_STEP * r["units"] / r["launches"] / avg_s / FP64_NOFMA_PEAK}
+                "steps_per_launch": steps_per_launch,
+                "issue": {"note": "VALU instruction issue (256 CUs x 64 lanes x 2.4 GHz, one FP64 instruction "
+                                  "per lane and clock without FMA); VALU instructions per step counted by rocprofv3 "
+                                  f"(profiles/eval_kernels_{args.workload}_counters.txt), null if that "
+                                  "summary is missing or was taken on other sources",
+                          "peak_lane_inst_per_s": FP64_ISSUE_PEAK,
+                          "algorithmic_ops_frac": ops_per_launch / avg_s / FP64_ISSUE_PEAK,
+                          "valu_inst_per_step": inst,
+                          "valu_inst_frac": inst * steps_per_launch / avg_s / FP64_ISSUE_PEAK if inst else None}}
 
     out = {
         "metric": METRIC,
@@ -457,8 +545,8 @@ def main():
         "config": {"workload": f"{w.name}: {desc}", "polynomials": len(polys), "depth": w.depth,
                    "box_evals_per_step": evals, "interval_steps_per_step": steps_total},
         "eval_only": {"box_evals_per_s": evals / (eval_ms * 1e-3) if eval_ms > 0 else None,
-                      "fp64_valu_frac": VALU_PER_STEP * steps_total / (eval_ms * 1e-3) / FP64_NOFMA_PEAK
-                      if eval_ms > 0 else None,
+                      "fp64_flop_frac": fracs(steps_total, eval_ms)[0],
+                      "fp64_issue_frac": fracs(steps_total, eval_ms, ips["all"] if ips else None)[1],
                       "ms": eval_ms},
         "roofline": roof,
         "kernels_note": "every kernel, HIP-event timed over one untimed step before the timed region",
@@ -477,6 +565,8 @@ def main():
         out["mean_value"] = bench_mean_value(vx, polys, dom, w.depth, stats, ms_step)
         out["taylor2"] = bench_taylor2(vx, polys, dom, w.depth, stats, ms_step,
                                        out["mean_value"]["kept_per_level"])
+        out["taylor3"] = bench_taylor_m(vx, polys, dom, w.depth, stats, ms_step,
+                                        out["taylor2"]["kept_per_level"], m=3)
         out["early_exit"] = bench_early_exit(vx, polys, dom, w.depth, stats, ms_step)
         out["inclusion"] = bench_inclusion(vx)
         out["newton"] = bench_newton(vx)
