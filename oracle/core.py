@@ -67,6 +67,7 @@ def lib():
         i64p = C.POINTER(C.c_int64)
         L.orc_iv_add.argtypes = [dp, dp, C.c_int, dp]
         L.orc_iv_mul.argtypes = [dp, dp, C.c_int, dp]
+        L.orc_iv_muladd.argtypes = [dp, dp, dp, C.c_int, dp]
         L.orc_box.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int64, dp]
         L.orc_box_table.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int64, dp]
         L.orc_eval_box.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, C.c_int, dp, i64p]
@@ -125,6 +126,14 @@ def iv_add(x, y, mode=OUTWARD):
 def iv_mul(x, y, mode=OUTWARD):
     a = np.array(x, np.float64); b = np.array(y, np.float64); r = np.zeros(2)
     lib().orc_iv_mul(_dp(a), _dp(b), mode, _dp(r))
+    return float(r[0]), float(r[1])
+
+
+def iv_muladd(x, y, c, mode=OUTWARD):
+    """The Horner step x*y + c as one interval operation (each endpoint of the
+    exact range rounded outward once); NEAREST: plain x*y, then + c."""
+    a = np.array(x, np.float64); b = np.array(y, np.float64); d = np.array(c, np.float64); r = np.zeros(2)
+    lib().orc_iv_muladd(_dp(a), _dp(b), _dp(d), mode, _dp(r))
     return float(r[0]), float(r[1])
 
 

@@ -59,6 +59,40 @@ def _qadd(x, y):
     return x[0] + y[0], x[1] + y[1]
 
 
+def exact_muladd(x, y, c):
+    """Exact range of the set x*y + c: (min P + c_lo, max P + c_hi)."""
+    lo, hi = exact_mul(x, y)
+    return lo + F(c[0]), hi + F(c[1])
+
+
+def round_down_q(q: Fraction) -> float:
+    """The largest double <= q (zero as +0)."""
+    if q == 0:
+        return 0.0
+    x = float(q)  # correctly rounded to nearest
+    return next_down(x) if F(x) > q else x
+
+
+def round_up_q(q: Fraction) -> float:
+    """The smallest double >= q (zero as +0)."""
+    if q == 0:
+        return 0.0
+    x = float(q)
+    return next_up(x) if F(x) < q else x
+
+
+def stepwise_rounded_horner(coefs, cell) -> tuple:
+    """Univariate interval Horner (descending exponents) in which every step
+    J*I + c_e is computed exactly from the previous rounded J and then rounded
+    outward once per endpoint.  coefs[e] = (lo, hi) of c_e."""
+    J = (F(coefs[-1][0]), F(coefs[-1][1]))
+    J = (round_down_q(J[0]), round_up_q(J[1]))
+    for e in range(len(coefs) - 2, -1, -1):
+        lo, hi = exact_muladd(J, cell, coefs[e])
+        J = (round_down_q(lo), round_up_q(hi))
+    return J
+
+
 def exact_interval_eval(cube: np.ndarray, d: int, box) -> tuple:
     """Interval Horner in exact rationals, nested in the canonical order
     (x1 innermost, descending exponents)."""

@@ -18,6 +18,10 @@
  *     product out), with the min rounded down and the max rounded up;
  *   - Horner's rule on an interval (Algorithm 1): J <- a_l; J <- J*I + a_j for
  *     descending exponents (consecutive exponents, so I^(e_{j+1}-e_j) = I);
+ *     each step J*I + a_j is taken as one interval operation: the exact range
+ *     [min P + lo(a_j), max P + hi(a_j)] of that set, each endpoint rounded
+ *     outward once (fma in the directed mode), the tightest floating-point
+ *     enclosure of the step (the paper asks only for the enclosure property);
  *   - EvaluationCSF (Algorithm 2): for every x1 node i of the box CSF, the
  *     partial evaluation F(I_i, x2, ..., xk) and a recursive call on the
  *     subtree of i; a univariate F is evaluated directly on each child.
@@ -96,6 +100,24 @@ static ivl iv_mul(ivl x, ivl y, int mode) {
   return r;
 }
 
+/* The Horner step J*I + C of polynomial evaluation, as one interval
+ * operation: the exact range [min P + c.lo, max P + c.hi] of the set
+ * J*I + C (P = the four endpoint products), each endpoint rounded outward
+ * once.  fma() rounds a*b + c once in the current mode, and RD/RU are
+ * monotone, so RD(min P + c.lo) = min RD(p + c.lo) over p in P (and the same
+ * for the max).  In NEAREST mode the step is the plain floating-point
+ * J*I, then + C, as an ordinary Horner evaluation computes it. */
+static ivl iv_muladd(ivl x, ivl y, ivl c, int mode) {
+  if (mode == ORC_NEAREST) return iv_add(iv_mul(x, y, mode), c, mode);
+  ivl r;
+  round_down(mode);
+  r.lo = min4(fma(x.lo, y.lo, c.lo), fma(x.lo, y.hi, c.lo), fma(x.hi, y.lo, c.lo), fma(x.hi, y.hi, c.lo));
+  round_up(mode);
+  r.hi = max4(fma(x.lo, y.lo, c.hi), fma(x.lo, y.hi, c.hi), fma(x.hi, y.lo, c.hi), fma(x.hi, y.hi, c.hi));
+  round_restore();
+  return r;
+}
+
 void orc_iv_add(const double* x, const double* y, int mode, double* r) {
   ivl a = {x[0], x[1]}, b = {y[0], y[1]};
   ivl s = iv_add(a, b, mode);
@@ -105,6 +127,12 @@ void orc_iv_add(const double* x, const double* y, int mode, double* r) {
 void orc_iv_mul(const double* x, const double* y, int mode, double* r) {
   ivl a = {x[0], x[1]}, b = {y[0], y[1]};
   ivl p = iv_mul(a, b, mode);
+  r[0] = p.lo; r[1] = p.hi;
+}
+
+void orc_iv_muladd(const double* x, const double* y, const double* c, int mode, double* r) {
+  ivl a = {x[0], x[1]}, b = {y[0], y[1]}, d = {c[0], c[1]};
+  ivl p = iv_muladd(a, b, d, mode);
   r[0] = p.lo; r[1] = p.hi;
 }
 
@@ -177,9 +205,10 @@ static void graded_free(graded* G) { free(G->flat); free(G->first); free(G->deg)
 /* every trailing tuple t with |t| <= d, Horner in e_s from d-|t| down   */
 /* to 0.  All chains sharing I advance together, one exponent at a time, */
 /* so the rounding mode is switched twice per exponent, not per step.    */
-/* Each chain performs exactly the operations of Algorithm 1.            */
+/* Each chain performs exactly the steps of Algorithm 1, every step     */
+/* J*I + c rounded outward once per endpoint (iv_muladd).               */
 /* Out: cube of side S over t (m-1 dims), only |t| <= d written.         */
-/* Returns the number of interval steps (one multiply + one add).        */
+/* Returns the number of interval steps (one multiply-add each).         */
 /* ------------------------------------------------------------------ */
 
 static int64_t partial_eval(const ivl* C, int m, int S, int d, const graded* T, ivl I, int mode,
@@ -193,13 +222,17 @@ static int64_t partial_eval(const ivl* C, int m, int S, int d, const graded* T, 
     for (int64_t j = 0; j < nact; j++) {
       int64_t f = T->flat[j];
       ivl J = out[f], c = C[(int64_t)e * tcube + f];
-      tmp[j] = min4(J.lo * I.lo, J.lo * I.hi, J.hi * I.lo, J.hi * I.hi) + c.lo;
+      tmp[j] = mode == ORC_NEAREST ? min4(J.lo * I.lo, J.lo * I.hi, J.hi * I.lo, J.hi * I.hi) + c.lo
+                                   : min4(fma(J.lo, I.lo, c.lo), fma(J.lo, I.hi, c.lo), fma(J.hi, I.lo, c.lo),
+                                          fma(J.hi, I.hi, c.lo));
     }
     round_up(mode);
     for (int64_t j = 0; j < nact; j++) {
       int64_t f = T->flat[j];
       ivl J = out[f], c = C[(int64_t)e * tcube + f];
-      out[f].hi = max4(J.lo * I.lo, J.lo * I.hi, J.hi * I.lo, J.hi * I.hi) + c.hi;
+      out[f].hi = mode == ORC_NEAREST ? max4(J.lo * I.lo, J.lo * I.hi, J.hi * I.lo, J.hi * I.hi) + c.hi
+                                      : max4(fma(J.lo, I.lo, c.hi), fma(J.lo, I.hi, c.hi), fma(J.hi, I.lo, c.hi),
+                                             fma(J.hi, I.hi, c.hi));
       out[f].lo = tmp[j];
     }
     round_restore();
@@ -324,7 +357,7 @@ static ivl box_value(box_job* J, int s, int rem, int* e) {
     if (es == rem) {
       acc = coef;
     } else {
-      acc = iv_add(iv_mul(acc, J->B[s - 1], J->mode), coef, J->mode);
+      acc = iv_muladd(acc, J->B[s - 1], coef, J->mode);
       J->steps++;
     }
   }

@@ -196,7 +196,7 @@ __global__ void k_mv_combine(int k, int np, int64_t nleaf, GridSet gs, const int
       const int64_t di = ((int64_t)p * k + i) * nleaf + b;
       double dnl = -opaque(d_lo[di]);
       double dh = d_hi[di];
-      step_gen(dnl, dh, W[i], anl, ah);  // D_i * W_i + acc
+      mul_add_sep(dnl, dh, W[i], anl, ah);  // D_i * W_i + acc
       anl = dnl;
       ah = dh;
     }
@@ -254,7 +254,7 @@ __global__ void k_t2_combine(int k, int np, int64_t nleaf, GridSet gs, const int
       const int64_t di = ((int64_t)p * k + i) * nleaf + b;
       double dnl = -opaque(dc_lo[di]);
       double dh = dc_hi[di];
-      step_gen(dnl, dh, W[i], anl, ah);  // Dc_i * W_i + acc
+      mul_add_sep(dnl, dh, W[i], anl, ah);  // Dc_i * W_i + acc
       anl = dnl;
       ah = dh;
     }
@@ -267,13 +267,13 @@ __global__ void k_t2_combine(int k, int np, int64_t nleaf, GridSet gs, const int
         } else {
           xnl = wnl[i];
           xh = wh[i];
-          step_gen(xnl, xh, W[j], 0.0, 0.0);  // W_i * W_j (+ 0: exact)
+          mul_add_sep(xnl, xh, W[j], 0.0, 0.0);  // W_i * W_j (+ 0: exact)
         }
         const CellOps X = cell_ops(xnl, xh, CLS_STRADDLE);
         const int64_t hi_ = ((int64_t)p * npair + t) * nleaf + b;
         double hnl = -opaque(h_lo[hi_]);
         double hh = h_hi[hi_];
-        step_gen(hnl, hh, X, anl, ah);  // H_t * X_t + acc
+        mul_add_sep(hnl, hh, X, anl, ah);  // H_t * X_t + acc
         anl = hnl;
         ah = hh;
       }
@@ -299,7 +299,7 @@ __device__ __forceinline__ void t2_at(int k, int np_, int p, int64_t nleaf, int6
     const int64_t di = ((int64_t)p * k + i) * nleaf + b;
     double dnl = -opaque(dc_lo[di]);
     double dh = dc_hi[di];
-    step_gen(dnl, dh, cell_ops(wnl[i], wh[i], CLS_STRADDLE), anl, ah);
+    mul_add_sep(dnl, dh, cell_ops(wnl[i], wh[i], CLS_STRADDLE), anl, ah);
     anl = dnl;
     ah = dh;
   }
@@ -312,12 +312,12 @@ __device__ __forceinline__ void t2_at(int k, int np_, int p, int64_t nleaf, int6
       } else {
         xnl = wnl[i];
         xh = wh[i];
-        step_gen(xnl, xh, cell_ops(wnl[j], wh[j], CLS_STRADDLE), 0.0, 0.0);
+        mul_add_sep(xnl, xh, cell_ops(wnl[j], wh[j], CLS_STRADDLE), 0.0, 0.0);
       }
       const int64_t hi_ = ((int64_t)p * npair + t) * nleaf + b;
       double hnl = -opaque(h_lo[hi_]);
       double hh = h_hi[hi_];
-      step_gen(hnl, hh, cell_ops(xnl, xh, CLS_STRADDLE), anl, ah);
+      mul_add_sep(hnl, hh, cell_ops(xnl, xh, CLS_STRADDLE), anl, ah);
       anl = hnl;
       ah = hh;
     }
@@ -755,7 +755,7 @@ __global__ void k_tm_combine(int k, int np, int64_t nleaf, GridSet gs, const int
           xh = ph;
           first = false;
         } else {
-          step_gen(xnl, xh, cell_ops(pnl, ph, CLS_STRADDLE), 0.0, 0.0);  // X * P (+ 0: exact)
+          mul_add_sep(xnl, xh, cell_ops(pnl, ph, CLS_STRADDLE), 0.0, 0.0);  // X * P (+ 0: exact)
         }
       }
       const int64_t ti = t < T.ncentre ? ((int64_t)p * ncm + (t - 1)) * nleaf + b
@@ -764,7 +764,7 @@ __global__ void k_tm_combine(int k, int np, int64_t nleaf, GridSet gs, const int
       const double* th = t < T.ncentre ? tc_hi : tb_hi;
       double tnl = -opaque(tl[ti]);
       double tt = th[ti];
-      step_gen(tnl, tt, cell_ops(xnl, xh, CLS_STRADDLE), anl, ah);  // T_t * X_t + acc
+      mul_add_sep(tnl, tt, cell_ops(xnl, xh, CLS_STRADDLE), anl, ah);  // T_t * X_t + acc
       anl = tnl;
       ah = tt;
     }
@@ -1261,7 +1261,7 @@ __global__ void k_newton_y(int k, int64_t nleaf, const double* __restrict__ s_lo
 __device__ __forceinline__ void point_times(double y, double xnl, double xh, double& rnl, double& rh) {
   rnl = xnl;
   rh = xh;
-  step_gen(rnl, rh, cell_ops(opaque(-y), y, CLS_STRADDLE), 0.0, 0.0);
+  mul_add_sep(rnl, rh, cell_ops(opaque(-y), y, CLS_STRADDLE), 0.0, 0.0);
 }
 
 // K(B) per box in outward arithmetic and the test K inside the inner box
@@ -1319,7 +1319,7 @@ __global__ void k_newton_k(int k, int64_t nleaf, GridSet gs, const int32_t* __re
           anl = anl + th;  // a - t
           ah = ah + tnl;
         }
-        step_gen(anl, ah, W[j], knl, kh);  // A_ij W_j + K_i
+        mul_add_sep(anl, ah, W[j], knl, kh);  // A_ij W_j + K_i
         knl = anl;
         kh = ah;
       }

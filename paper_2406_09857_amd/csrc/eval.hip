@@ -621,6 +621,16 @@ __device__ __forceinline__ int padded_split(int d, int g, int n) {
   return __builtin_amdgcn_readfirstlane(lo);
 }
 
+// The chains of split gi of gdim on a wave-uniform padded row.
+__device__ __forceinline__ void narrow_scalar_split(const crow_t* __restrict__ C, int d, int gi, int gdim, int cls,
+                                                    const CellOps& o, bool valid, double* __restrict__ w, int64_t es,
+                                                    int out_width) {
+  const int j0 = padded_split(d, gi, gdim), j1 = padded_split(d, gi + 1, gdim);
+  if (cls == CLS_POS) narrow_padded<CLS_POS, crow_t>(C, j0, j1, o, valid, w, es, out_width);
+  else if (cls == CLS_NEG) narrow_padded<CLS_NEG, crow_t>(C, j0, j1, o, valid, w, es, out_width);
+  else narrow_padded<CLS_STRADDLE, crow_t>(C, j0, j1, o, valid, w, es, out_width);
+}
+
 struct SplitSet {
   ChainSplit s[PMAX];
 };
@@ -657,11 +667,7 @@ __global__ __launch_bounds__(64) void k_narrow(PolySet ps, RowSet in, SplitSet s
   const int64_t es = out.estride[pz];
   const int32_t* lens = ps.p[pz].lens2;
   if (PADDED) {
-    const int d = ps.p[pz].d;
-    const int j0 = padded_split(d, gi, gdim), j1 = padded_split(d, gi + 1, gdim);
-    if (cls == CLS_POS) narrow_padded<CLS_POS, crow_t>(C, j0, j1, o, valid, w, es, out_width);
-    else if (cls == CLS_NEG) narrow_padded<CLS_NEG, crow_t>(C, j0, j1, o, valid, w, es, out_width);
-    else narrow_padded<CLS_STRADDLE, crow_t>(C, j0, j1, o, valid, w, es, out_width);
+    narrow_scalar_split(C, ps.p[pz].d, gi, gdim, cls, o, valid, w, es, out_width);
     return;
   }
   const int j0 = __builtin_amdgcn_readfirstlane(split.j0[gi]);
@@ -805,11 +811,7 @@ __global__ __launch_bounds__(64) void k_narrow_mixed(PolySet ps, RowSet in, cons
   const crow_t* C = (const crow_t*)(in.rows[pz] + (int64_t)parent * in.stride[pz]);
   double* w = out.rows[pz] + node * out.stride[pz];
   const int64_t es = out.estride[pz];
-  const int d = ps.p[pz].d;
-  const int j0 = padded_split(d, gi, gdim), j1 = padded_split(d, gi + 1, gdim);
-  if (cls == CLS_POS) narrow_padded<CLS_POS, crow_t>(C, j0, j1, o, valid, w, es, out_width);
-  else if (cls == CLS_NEG) narrow_padded<CLS_NEG, crow_t>(C, j0, j1, o, valid, w, es, out_width);
-  else narrow_padded<CLS_STRADDLE, crow_t>(C, j0, j1, o, valid, w, es, out_width);
+  narrow_scalar_split(C, ps.p[pz].d, gi, gdim, cls, o, valid, w, es, out_width);
 }
 
 // ---------------------------------------------------------------------------
@@ -1204,7 +1206,10 @@ __global__ void k_seg_write_all(DepthBlocks D, SegJob J) {
   if (p == 0) *J.nseg[l] = *J.nfull + cdiv(tn, Z) + cdiv(tp, Z);
 }
 
-constexpr int64_t NARROW_TARGET_WAVES = 8192;
+#ifndef VX_NARROW_TARGET_WAVES
+#define VX_NARROW_TARGET_WAVES 8192
+#endif
+constexpr int64_t NARROW_TARGET_WAVES = VX_NARROW_TARGET_WAVES;
 
 // Chain lengths of O_m (m = 1 or 2) in order, host side.
 static std::vector<int> o_lengths(int m, int d) {

@@ -18,15 +18,19 @@
 // arithmetic (or behind `opaque`) leaves no fold that depends on the mode.
 // Kernels must therefore (1) call `round_up_mode()` before any FP64 arithmetic,
 // (2) never feed a negated value into a multiply or add without `opaque`,
-// (3) be compiled with -ffp-contract=off (no fused multiply-add anywhere).
+// (3) be compiled with -ffp-contract=off (fused multiply-adds only where they
+// are written out, as in the Horner steps below).
 //
 // Interval rules (Sec. 3.2 of Moroz, arXiv 2406.09857, names interval
 // arithmetic and gives the sum; the product is the textbook min/max rule):
 //   [a,b] + [c,d] = [RD(a+c), RU(b+d)]
 //   [a,b] * [c,d] = [RD(min P), RU(max P)],  P = {ac, ad, bc, bd}.
-// RD/RU are monotone, so RD(min P) = min RD(P): every formula below that picks
-// a subset of P known to contain the extremum gives the same bits (up to the
-// sign of a zero).
+// The Horner step J*I + C of polynomial evaluation is one operation: the
+// exact range [min P + lo(C), max P + hi(C)] of the set J*I + C, each endpoint
+// rounded outward once (an FMA in round-up mode: RU(p + c) exactly).
+// RD/RU are monotone, so RD(min P + c) = min RD(p + c) over P: every formula
+// below that picks a subset of P known to contain the extremum gives the same
+// bits (up to the sign of a zero).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -95,29 +99,42 @@ __device__ __forceinline__ CellOps cell_ops(double nlo, double hi, int cls) {
 }
 
 // One Horner step J <- J*I + C for a cell of class POS: I = [u, v], u >= 0.
-//   lo' = min(lo*u, lo*v)  ->  nlo' = max(RU(nlo*u), RU(nlo*v))
-//   hi' = max(hi*u, hi*v)
+//   lo' = min(lo*u, lo*v) + lo(C)  ->  nlo' = max(RU(nlo*u + cn), RU(nlo*v + cn))
+//   hi' = max(hi*u, hi*v) + hi(C)  ->  hi'  = max(RU(hi*u + ch), RU(hi*v + ch))
+// (cn = -lo(C), ch = hi(C)); 4 FMAs and 2 maxima.
 __device__ __forceinline__ void step_pos(double& nlo, double& hi, double u, double v, double cn, double ch) {
-  const double a = fmax(nlo * u, nlo * v);
-  const double b = fmax(hi * u, hi * v);
-  nlo = a + cn;
-  hi = b + ch;
+  const double a = fmax(__builtin_fma(nlo, u, cn), __builtin_fma(nlo, v, cn));
+  const double b = fmax(__builtin_fma(hi, u, ch), __builtin_fma(hi, v, ch));
+  nlo = a;
+  hi = b;
 }
 
 // Class NEG: I = [a, b] <= 0 with u = -a, v = -b:
-//   lo' = min(hi*a, hi*b)  ->  nlo' = max(RU(hi*u), RU(hi*v))
-//   hi' = max(lo*a, lo*b)  ->  hi'  = max(RU(nlo*u), RU(nlo*v))
+//   lo' = min(hi*a, hi*b) + lo(C)  ->  nlo' = max(RU(hi*u + cn), RU(hi*v + cn))
+//   hi' = max(lo*a, lo*b) + hi(C)  ->  hi'  = max(RU(nlo*u + ch), RU(nlo*v + ch))
 __device__ __forceinline__ void step_neg(double& nlo, double& hi, double u, double v, double cn, double ch) {
-  const double a = fmax(hi * u, hi * v);
-  const double b = fmax(nlo * u, nlo * v);
-  nlo = a + cn;
-  hi = b + ch;
+  const double a = fmax(__builtin_fma(hi, u, cn), __builtin_fma(hi, v, cn));
+  const double b = fmax(__builtin_fma(nlo, u, ch), __builtin_fma(nlo, v, ch));
+  nlo = a;
+  hi = b;
 }
 
 // General product (any signs): I = [a, b], na = -a, nb = -b.
-//   nlo' = max RU(-p) over p in P = max(nlo*a, nlo*b, hi*na, hi*nb)
-//   hi'  = max RU(p)               = max(nlo*na, nlo*nb, hi*a, hi*b)
+//   nlo' = max RU(-p - lo(C)) over p in P = max over {nlo*a, nlo*b, hi*na, hi*nb} of RU(. + cn)
+//   hi'  = max RU(p + hi(C))              = max over {nlo*na, nlo*nb, hi*a, hi*b} of RU(. + ch)
 __device__ __forceinline__ void step_gen(double& nlo, double& hi, const CellOps& o, double cn, double ch) {
+  const double a = fmax(fmax(__builtin_fma(nlo, o.u, cn), __builtin_fma(nlo, o.v, cn)),
+                        fmax(__builtin_fma(hi, o.nu, cn), __builtin_fma(hi, o.nv, cn)));
+  const double b = fmax(fmax(__builtin_fma(nlo, o.nu, ch), __builtin_fma(nlo, o.nv, ch)),
+                        fmax(__builtin_fma(hi, o.u, ch), __builtin_fma(hi, o.v, ch)));
+  nlo = a;
+  hi = b;
+}
+
+// Product, then sum, each rounded outward (not a Horner step): J <- J*X + A
+// for the combination formulas of the exclusion and inclusion tests, whose
+// definitions sum separately rounded products.  Same operands as step_gen.
+__device__ __forceinline__ void mul_add_sep(double& nlo, double& hi, const CellOps& o, double cn, double ch) {
   const double a = fmax(fmax(nlo * o.u, nlo * o.v), fmax(hi * o.nu, hi * o.nv));
   const double b = fmax(fmax(nlo * o.nu, nlo * o.nv), fmax(hi * o.u, hi * o.v));
   nlo = a + cn;

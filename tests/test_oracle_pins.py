@@ -68,6 +68,49 @@ def test_primitives_are_correctly_rounded_outward():
         assert ex.is_round_down(lo, elo) and ex.is_round_up(hi, ehi), (x, y, lo, hi)
 
 
+def test_horner_step_is_the_exact_range_rounded_once():
+    """The Horner step x*y + c: each endpoint of the exact range of the set,
+    rounded outward once (correctly rounded, so never wider than the
+    separately rounded product-then-sum, and contained in it)."""
+    rng = np.random.default_rng(13)
+    vals = edge_doubles(rng, 2400)
+    for i in range(0, 2400, 6):
+        x = sorted(vals[i:i + 2]); y = sorted(vals[i + 2:i + 4]); c = sorted(vals[i + 4:i + 6])
+        lo, hi = orc.iv_muladd(x, y, c)
+        elo, ehi = ex.exact_muladd(x, y, c)
+        assert ex.is_round_down(lo, elo) and ex.is_round_up(hi, ehi), (x, y, c, lo, hi)
+        slo, shi = orc.iv_add(orc.iv_mul(x, y), c)
+        assert slo <= lo and hi <= shi, (x, y, c)
+    # NEAREST: the plain floating-point product, then the sum
+    for _ in range(200):
+        a, b, c = (float(v) for v in rng.standard_normal(3))
+        assert orc.iv_muladd((a, a), (b, b), (c, c), orc.NEAREST) == (a * b + c, a * b + c)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_univariate_evaluation_is_stepwise_rounded_horner(seed):
+    """k = 1: eval_box and eval_csf equal, bit for bit (zeros as +0), an
+    exact-rational Horner in which every step's exact range is rounded
+    outward once (cells of both signs and straddling, interval and point
+    coefficients, a non-dyadic domain)."""
+    rng = np.random.default_rng(900 + seed)
+    d = int(rng.integers(1, 9))
+    c = rng.standard_normal(d + 1) * np.exp2(rng.integers(-3, 4, d + 1))
+    rad = np.abs(c) * 1e-3 * (seed % 2)
+    clo, chi = c - rad, c + rad
+    dom = np.array([-0.7, 1.3])
+    level = 3
+    csf = orc.csf_from_boxes(np.arange(1 << level)[:, None], level)
+    tabs = orc.level_tables(dom, 1, level)
+    lo, hi, _ = orc.eval_csf((clo, chi), d, csf, tabs)
+    for q in range(1 << level):
+        cell = tuple(tabs[0][q])
+        want = ex.stepwise_rounded_horner([(clo[e], chi[e]) for e in range(d + 1)], cell)
+        blo, bhi, _ = orc.eval_box((clo, chi), d, np.array([cell]))
+        assert bits_equal([lo[q], hi[q]], list(want)), (q, cell, lo[q], hi[q], want)
+        assert bits_equal([blo, bhi], list(want)), (q, cell)
+
+
 def test_nearest_mode_is_plain_float_arithmetic():
     rng = np.random.default_rng(12)
     for _ in range(200):
