@@ -962,7 +962,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF == 4 ? 6
 
 // Largest leaf count for the one-polynomial-per-lane leaf launch, and for
 // one box per lane.
-constexpr int64_t LEAF_SPLIT_NODES = 1536 * 1024;
+#ifndef VX_LEAF_SPLIT_NODES
+#define VX_LEAF_SPLIT_NODES (1536 * 1024)
+#endif
+constexpr int64_t LEAF_SPLIT_NODES = VX_LEAF_SPLIT_NODES;
 constexpr int64_t LEAF_ONE_NODES = 16384;
 
 // ---------------------------------------------------------------------------
@@ -1207,7 +1210,7 @@ __global__ void k_seg_write_all(DepthBlocks D, SegJob J) {
 }
 
 #ifndef VX_NARROW_TARGET_WAVES
-#define VX_NARROW_TARGET_WAVES 8192
+#define VX_NARROW_TARGET_WAVES 16384
 #endif
 constexpr int64_t NARROW_TARGET_WAVES = VX_NARROW_TARGET_WAVES;
 
@@ -1317,7 +1320,13 @@ struct EvalPlan {
   int mode[VX_KMAX] = {};  // per axis: 0 cells, 1 cell centres, 2 grid vertices (AxisGrid::centre)
 };
 
-static int stage1_blocking(int64_t n0) { return n0 <= 4 ? 1 : n0 <= 16 ? 2 : n0 <= 64 ? 4 : 8; }
+#ifndef VX_STAGE1_RMAX
+#define VX_STAGE1_RMAX 8
+#endif
+static int stage1_blocking(int64_t n0) {
+  const int r = n0 <= 4 ? 1 : n0 <= 16 ? 2 : n0 <= 64 ? 4 : 8;
+  return r < VX_STAGE1_RMAX ? r : VX_STAGE1_RMAX;
+}
 
 // Level workspace (measure with A.base == nullptr).  With `bound` the plan
 // takes the largest choices at every depth (one node per segment, tail lists
