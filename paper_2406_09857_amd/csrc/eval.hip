@@ -28,9 +28,9 @@
 //     O_m = for t in O_{m-1}: for e = d-|t| down to 0: (e, t).  The position
 //     of t in O_m is sum_{j=1..m} C(d - sigma_j + j - 1, j), sigma_j the sum
 //     of t_j..t_m.
-//   Rows read by the leaf kernel hold each entry as (nlo, hi, nlo), 24 bytes,
-//   so that a lane can read the pair swapped by offsetting its address by 8
-//   bytes (see k_leaf).
+//   Rows read by the leaf kernel hold each entry as the pair (nlo, hi), 16
+//   bytes (LEAF_W doubles); a lane that needs the pair swapped loads the two
+//   doubles from swapped offsets (see leaf_chains).
 #include <hip/hip_runtime.h>
 
 #include <string.h>
@@ -80,6 +80,8 @@ __device__ inline int64_t o_pos(const int* t, int m, int d) {
 // multiple of 8 entries, so it occupies the 8-entry groups [c(j), c(j+1)),
 // c(j) = sum_{i=1..j} ceil(i/8).  Entry (e2, e3) sits at 8 c(j+1) - 1 - e2.
 constexpr int PADG = 8;
+// Doubles per entry of the leaf kernel's input rows: (nlo, hi).
+constexpr int LEAF_W = 2;
 constexpr int SEG_PACKED = 4;  // segment class | this flag: a packed middle-stage segment
 
 __host__ __device__ inline int64_t padded_groups(int64_t j) {
@@ -119,9 +121,8 @@ __device__ inline void tables_entry(int64_t f, int k, int d, int side, const dou
   }
   if (k == 1) {
     const int64_t j = d - e[0];
-    packed[3 * j + 0] = -lo;
-    packed[3 * j + 1] = hi;
-    packed[3 * j + 2] = -lo;
+    packed[LEAF_W * j + 0] = -lo;
+    packed[LEAF_W * j + 1] = hi;
     return;
   }
   const int r = d - e[0];
@@ -290,7 +291,8 @@ struct PolyTab {
 
 // Node q's entry j sits at rows + q * stride + j * estride (doubles).  Rows
 // written by stage 1 are node-major (estride = entry width); the leaf input
-// written by a middle stage is entry-major (stride = 3, estride = 3 * nodes),
+// written by a middle stage is entry-major (stride = LEAF_W, estride = LEAF_W *
+// nodes),
 // so the 64 lanes of a middle-stage wave, which are 64 consecutive nodes,
 // store each entry contiguously, and leaf lanes of neighbouring columns read
 // neighbouring addresses.
@@ -334,14 +336,9 @@ __device__ __forceinline__ void stage1_body(const PolyTab& pt, int m, const int3
 #pragma unroll
   for (int j = 0; j < R; j++) {
     if (j < cnt) {
+      // 16-byte aligned (rows, strides and entries are): one store
       double* o = base + (int64_t)(begin + j) * stride + (int64_t)opos * out_width;
-      if (out_width == 2) {  // 16-byte aligned (rows, strides and entries are): one store
-        *reinterpret_cast<double2*>(o) = make_double2(nl[j], hh[j]);
-      } else {
-        o[0] = nl[j];
-        o[1] = hh[j];
-        o[2] = nl[j];
-      }
+      *reinterpret_cast<double2*>(o) = make_double2(nl[j], hh[j]);
     }
   }
 }
@@ -494,10 +491,8 @@ __device__ __forceinline__ void narrow_run(const crow_t* __restrict__ C, const i
     }
     if (g == ng - 1) {
       if (valid) {
-        double* w = out + (int64_t)j * es;
-        w[0] = nl;
-        w[1] = hh;
-        if (out_width == 3) w[2] = nl;
+        // 16-byte aligned rows, strides and entries: one store
+        *reinterpret_cast<double2*>(out + (int64_t)j * es) = make_double2(nl, hh);
       }
       nl = 0.0;
       hh = 0.0;
@@ -567,10 +562,8 @@ __device__ __forceinline__ void narrow_padded(ROW* __restrict__ C, int j, const 
     g++;
     if (g == gend) {
       if (valid) {
-        double* w = out + (int64_t)j * es;
-        w[0] = nl;
-        w[1] = hh;
-        if (out_width == 3) w[2] = nl;
+        // 16-byte aligned rows, strides and entries: one store
+        *reinterpret_cast<double2*>(out + (int64_t)j * es) = make_double2(nl, hh);
       }
       nl = 0.0;
       hh = 0.0;
@@ -727,10 +720,8 @@ __device__ __forceinline__ void narrow_packed_lds(const double* __restrict__ row
     g++;
     if (g == gend) {
       if (valid) {
-        double* w = out + (int64_t)j * es;
-        w[0] = nl;
-        w[1] = hh;
-        if (out_width == 3) w[2] = nl;
+        // 16-byte aligned rows, strides and entries: one store
+        *reinterpret_cast<double2*>(out + (int64_t)j * es) = make_double2(nl, hh);
       }
       nl = 0.0;
       hh = 0.0;
@@ -821,8 +812,8 @@ __global__ __launch_bounds__(64) void k_narrow_mixed(PolySet ps, RowSet in, cons
 // Ft(y) = F(-y) = sum (-1)^e c_e y^e on the nonnegative cell -I with the POS
 // formula.  Negation is exact and commutes with outward rounding, so every
 // intermediate value is (-1)^e times the direct one and the final value (e=0)
-// is identical.  (-1)^e c_e for odd e is the pair read one double later in
-// the (nlo, hi, nlo) row layout.
+// is identical.  (-1)^e c_e for odd e is the pair (nlo, hi) read swapped,
+// (hi, nlo).
 // ---------------------------------------------------------------------------
 typedef double dpair_a8 __attribute__((ext_vector_type(2), aligned(8)));
 
@@ -836,25 +827,24 @@ __device__ __forceinline__ void leaf_chain_gen(const double* __restrict__ R, int
 }
 
 // Up to LR boxes of one column and one sign class (POS or NEG) share every
-// coefficient load.  Entry j (exponent d - j) is read at R + es * j, one double
-// later when the boxes are mirrored (NEG) and d - j is odd; pe serves even j,
-// po odd j.  PF entries are in flight, so entries up to max(PF, d + PF) are
-// read (the buffers are sized for LEAF_PF_MAX); those past d are never used.
+// coefficient load.  Entry j (exponent d - j) is the pair (nlo, hi) at
+// R + es * j; mirrored (NEG) boxes take it swapped, (hi, nlo), when d - j is
+// odd (a per-lane select after the load, once per entry for all LR boxes).
+// PF entries are in flight, so entries up to max(PF, d + PF) are read (the
+// buffers are sized for LEAF_PF_MAX); those past d are never used.
 constexpr int LEAF_PF_MAX = 8;
 
-template <int LR, int PF>
-__device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int64_t es, int d, int sh,
-                                            const double (&u)[LR], const double (&v)[LR], double (&nl)[LR],
-                                            double (&hh)[LR]) {
+// DODD = d is odd (then the even entries are the odd exponents).
+template <int LR, int PF, bool DODD>
+__device__ __forceinline__ void leaf_chains_p(const double* __restrict__ R, int64_t es, int d, bool sh,
+                                              const double (&u)[LR], const double (&v)[LR], double (&nl)[LR],
+                                              double (&hh)[LR]) {
   static_assert(PF % 2 == 0 && PF <= LEAF_PF_MAX, "even prefetch depth within the row slack");
-  const double* pe = R + ((d & 1) ? sh : 0);
-  const double* po = R + es + (((d - 1) & 1) ? sh : 0);
-  // entry j; every call site has j = 1 + (even) + i with i known, so the parity is static
-  auto at = [&](int j) -> dpair_a8 {
-    return (j & 1) ? *reinterpret_cast<const dpair_a8*>(po + es * (j - 1))
-                   : *reinterpret_cast<const dpair_a8*>(pe + es * j);
-  };
-  const dpair_a8 c = at(0);
+  // swap of even entries (d - j odd iff d odd) and of odd entries (iff d even)
+  const bool swe = DODD && sh, swo = !DODD && sh;
+  auto at = [&](int j) -> dpair_a8 { return *reinterpret_cast<const dpair_a8*>(R + es * j); };
+  auto fix = [](const dpair_a8& x, bool sw) -> dpair_a8 { return sw ? dpair_a8{x.y, x.x} : x; };
+  const dpair_a8 c = fix(at(0), swe);
 #pragma unroll
   for (int i = 0; i < LR; i++) {
     nl[i] = c.x;
@@ -867,19 +857,26 @@ __device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int64_
 #pragma unroll
     for (int i = 0; i < LR; i++) step_pos(nl[i], hh[i], u[i], v[i], x.x, x.y);
   };
+  // every call site has j = 1 + (even) + i with i known, so the parity is static
   int j = 1;
   for (; j + PF - 1 <= d; j += PF) {
 #pragma unroll
     for (int i = 0; i < PF; i++) {
-      steps(q[i]);
-      // entry j + PF + i: odd when i is even (j is odd)
-      q[i] = (i & 1) ? *reinterpret_cast<const dpair_a8*>(pe + es * (j + PF + i))
-                     : *reinterpret_cast<const dpair_a8*>(po + es * (j + PF + i - 1));
+      steps(fix(q[i], (i & 1) ? swe : swo));
+      q[i] = at(j + PF + i);
     }
   }
 #pragma unroll
   for (int i = 0; i < PF - 1; i++)
-    if (j + i <= d) steps(q[i]);
+    if (j + i <= d) steps(fix(q[i], (i & 1) ? swe : swo));
+}
+
+template <int LR, int PF>
+__device__ __forceinline__ void leaf_chains(const double* __restrict__ R, int64_t es, int d, int sh,
+                                            const double (&u)[LR], const double (&v)[LR], double (&nl)[LR],
+                                            double (&hh)[LR]) {
+  if (d & 1) leaf_chains_p<LR, PF, true>(R, es, d, sh != 0, u, v, nl, hh);
+  else leaf_chains_p<LR, PF, false>(R, es, d, sh != 0, u, v, nl, hh);
 }
 
 // One lane per leaf segment (<= LR boxes of one parent and one class; LR =
@@ -1259,7 +1256,7 @@ static void plan_prepared(Arena& A, Prepared& Q, const vx_poly* P, int np) {
     const int d = P[p].degree;
     Q.d[p] = d;
     Q.dmax = d > Q.dmax ? d : Q.dmax;
-    Q.packed[p] = A.take<double>((k == 1 ? 3 * (int64_t)(d + 1) : 2 * ntup(k, d)) + 2 * ROW_PAD * 3);
+    Q.packed[p] = A.take<double>((k == 1 ? LEAF_W * (int64_t)(d + 1) : 2 * ntup(k, d)) + 2 * ROW_PAD * 3);
     Q.ttab[p] = A.take<int2>(k >= 2 ? ntup(k - 1, d) : 1);
     Q.lens2[p] = A.take<int32_t>(k == 4 ? ntup(2, d) : 1);
     Q.lens1[p] = A.take<int32_t>(d + 1);
@@ -1337,7 +1334,7 @@ static void plan_eval(Arena& A, EvalPlan& E, const vx_poly* P, int np, const vx_
   E.k = k;
   for (int l = 0; l + 1 < k; l++) {
     const int m = k - l - 1;  // dimension of the trailing tuples left after depth l+1
-    const int width = (l == k - 2) ? 3 : 2;
+    const int width = (l == k - 2) ? LEAF_W : 2;
     for (int p = 0; p < np; p++) {
       // leaf input written by a middle stage: entry-major, d + 1 + LEAF_PF_MAX
       // entry planes (the leaf reads up to entry d + LEAF_PF_MAX)
@@ -1389,7 +1386,7 @@ static int launch_stage1(const Prepared& Q, int p0, int pn, const vx_csf* S, con
   ps.np = pn;
   int nt_max = 0;
   double units = 0;
-  const int width = (k == 2) ? 3 : 2;
+  const int width = 2;  // also the leaf input's LEAF_W when k = 2
   for (int i = 0; i < pn; i++) {
     const int p = p0 + i, d = Q.d[p];
     ps.p[i].packed = reinterpret_cast<const double2*>(Q.packed[p]);
@@ -1429,7 +1426,7 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
                          hipStream_t st) {
   const int k = S->k;
   const int m_in = k - l, m_out = k - l - 1;
-  const int width = (l == k - 2) ? 3 : 2;
+  const int width = (l == k - 2) ? LEAF_W : 2;
   PolySet ps;
   memset(&ps, 0, sizeof ps);
   RowSet in, out;
@@ -1454,8 +1451,8 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
     in.stride[i] = (k == 3 ? padded_entries(d) : ntup(m_in, d)) * 2;
     out.rows[i] = E.rows[l][p];
     const bool to_leaf = l == k - 2;
-    out.stride[i] = to_leaf ? 3 : ntup(m_out, d) * width;
-    out.estride[i] = to_leaf ? 3 * S->n[l] : width;
+    out.stride[i] = to_leaf ? LEAF_W : ntup(m_out, d) * width;
+    out.estride[i] = to_leaf ? LEAF_W * S->n[l] : width;
     if (k == 3) {
       gmax = groups;
     } else {
@@ -1506,8 +1503,8 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
     const int p = p0 + i, d = Q.d[p];
     ps.p[i].d = d;
     rs.rows[i] = k == 1 ? Q.packed[p] : E.rows[k - 2][p];
-    rs.stride[i] = k == 1 ? 0 : (k == 2 ? 3 * (int64_t)(d + 1) : 3);
-    rs.estride[i] = k >= 3 ? 3 * S->n[k - 2] : 3;
+    rs.stride[i] = k == 1 ? 0 : (k == 2 ? LEAF_W * (int64_t)(d + 1) : LEAF_W);
+    rs.estride[i] = k >= 3 ? LEAF_W * S->n[k - 2] : LEAF_W;
     units += (double)d * (double)nleaf;
   }
   const SegPlan& sp = E.seg[k - 1];
