@@ -27,11 +27,12 @@ sys.path.insert(0, ROOT)
 METRIC = "interval box-evals/sec per level + % FP64-VALU peak; batched & adjoint vs plain"
 # MI355X published FP64 vector peak (an FMA counts as two operations).
 FP64_PEAK = 78.6e12
-# FP64 VALU instruction issue without fused multiply-add: 256 CUs x 64 lanes
-# x 2.4 GHz = 39.3e12 lane-instructions/s (every FP64 instruction, min/max
-# included, occupies the lane for one issue slot).
+# FP64 VALU instruction issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz =
+# 39.3e12 lane-instructions/s (every wave64 FP64 instruction, FMA and max
+# alike, holds its SIMD for 4 clocks); the published 78.6 TFLOP/s is this rate
+# with every instruction an FMA counted as two operations.
 FP64_ISSUE_PEAK = 256 * 64 * 2.4e9
-OPS_PER_STEP = 4      # algorithmic: lower/upper product and lower/upper sum of one interval Horner step
+OPS_PER_STEP = 4      # algorithmic: the lower and upper multiply-add (product and sum) of one interval Horner step
 EVAL_KERNELS = ("k_stage1", "k_narrow", "k_leaf")
 
 
@@ -520,8 +521,9 @@ def main():
                 "traffic": measured_traffic(dom_name, args.workload),
                 "avg_launch_ms": avg_s * 1e3, "ops_per_launch": ops_per_launch,
                 "steps_per_launch": steps_per_launch,
-                "issue": {"note": "VALU instruction issue (256 CUs x 64 lanes x 2.4 GHz, one FP64 instruction "
-                                  "per lane and clock without FMA); VALU instructions per step counted by rocprofv3 "
+                "issue": {"note": "VALU instruction issue (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: a wave64 "
+                                  "FP64 instruction, FMA or max, every 4 clocks per SIMD); VALU instructions per "
+                                  "step counted by rocprofv3 "
                                   f"(profiles/eval_kernels_{args.workload}_counters.txt), null if that "
                                   "summary is missing or was taken on other sources",
                           "peak_lane_inst_per_s": FP64_ISSUE_PEAK,
