@@ -92,6 +92,9 @@ def lib():
         L.orc_krawczyk.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp,
                                    np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS"), dp]
         L.orc_krawczyk.restype = C.c_int
+        L.orc_newton_span.argtypes = [C.c_int, C.c_int, C.c_int64, dp, dp, dp, dp, dp,
+                                      np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS"), dp, dp]
+        L.orc_newton_span.restype = C.c_int
         L.orc_deriv2.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, C.c_int, C.c_int, dp, dp]
         L.orc_deriv2.restype = C.c_int
         L.orc_taylor2.argtypes = [C.c_int, C.c_int64, dp, dp, dp, dp, dp, dp]
@@ -731,3 +734,45 @@ def newton_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1, degrees=N
                           _dp(inner), flags, _dp(K)):
         raise ValueError("orc_krawczyk failed")
     return (flags.astype(bool), K) if want_k else flags.astype(bool)
+
+
+def newton_span_level(polys, csf: dict, dom: np.ndarray, nthreads: int = 1, degrees=None, want_k: bool = False):
+    """Newton test of a system of m < k polynomials on every leaf of the CSF
+    (the square test on the span of the gradients at the box centre):
+    flags (n,) and, with ``want_k``, the enclosures K (n, m, 2) in the
+    plane's coordinates and the cube radii r (n,).  F and its first
+    derivatives at the centre enclosures and the derivatives on the boxes
+    come from Algorithm 2 on the same CSF; ``orc_newton_span`` combines them."""
+    k, level = csf["k"], csf["level"]
+    m = len(polys)
+    assert 1 <= m < k, "fewer polynomials than variables"
+    dom = np.asarray(dom, np.float64).reshape(k, 2)
+    btabs = level_tables(dom, k, level)
+    ctabs = [centre_table(float(dom[a, 0]), float(dom[a, 1]), level) for a in range(k)]
+    boxes = np.asarray(csf["boxes"], np.int64)
+    nb = boxes.shape[0]
+    flags = np.zeros(nb, np.uint8)
+    K = np.zeros((nb, m, 2))
+    r = np.zeros(nb)
+    if nb == 0:
+        return (flags.astype(bool), K, r) if want_k else flags.astype(bool)
+    fc = np.zeros((m, nb, 2))
+    gc = np.zeros((m * k, nb, 2))
+    D = np.zeros((m * k, nb, 2))
+    for i, p in enumerate(polys):
+        d = poly_degree(p) if degrees is None else degrees[i]
+        fl, fh, _ = eval_csf(p, d, csf, ctabs, OUTWARD, nthreads)
+        fc[i, :, 0] = fl; fc[i, :, 1] = fh
+        for j in range(k):
+            if d >= 1:
+                dc = deriv(p, d, j)
+                gl, gh, _ = eval_csf(dc, d - 1, csf, ctabs, OUTWARD, nthreads)
+                gc[i * k + j, :, 0] = gl; gc[i * k + j, :, 1] = gh
+                bl, bh, _ = eval_csf(dc, d - 1, csf, btabs, OUTWARD, nthreads)
+                D[i * k + j, :, 0] = bl; D[i * k + j, :, 1] = bh
+    bx = np.ascontiguousarray(np.stack([btabs[a][boxes[:, a]] for a in range(k)], axis=1))
+    cx = np.ascontiguousarray(np.stack([ctabs[a][boxes[:, a]] for a in range(k)], axis=1))
+    if lib().orc_newton_span(k, m, nb, _dp(np.ascontiguousarray(fc)), _dp(np.ascontiguousarray(gc)),
+                             _dp(np.ascontiguousarray(D)), _dp(bx), _dp(cx), flags, _dp(K), _dp(r)):
+        raise ValueError("orc_newton_span failed")
+    return (flags.astype(bool), K, r) if want_k else flags.astype(bool)

@@ -30,6 +30,9 @@
  *     comparison), used to pin the amortized routine;
  *   - the mean-value (order-1 Taylor form) enclosure of Sec. 3.2: centre
  *     enclosures, derivative coefficients and the final combination;
+ *   - the Newton test for systems with fewer equations than variables
+ *     (Sec. 3.2): the same test on the plane through the box spanned by the
+ *     gradients at its centre;
  *   - the Newton interval inclusion test for square systems (Sec. 3.2) in
  *     Krawczyk's form, from slope enclosures;
  *   - the grid-vertex enclosures of the inclusion criterion C1 (Sec. 3.2) and
@@ -829,6 +832,152 @@ int orc_krawczyk(int k, int64_t nbox, const double* fc, const double* Sm, const 
       }
       if (K) { K[(b * k + i) * 2] = Ki.lo; K[(b * k + i) * 2 + 1] = Ki.hi; }
     }
+    out[b] = (uint8_t)inside;
+  }
+  return 0;
+}
+
+/* Newton test for fewer equations than variables (Sec. 3.2, inclusion
+ * criterion, last paragraph: intersect the box with the span of the
+ * gradients at its centre, then apply the Newton test to the resulting
+ * square system).  m < k polynomials.  Per box: the point c (the lower end
+ * of the centre enclosure on every axis), G (k x m, column l = the midpoint
+ * of F_l's gradient enclosure at the centre), the square system
+ * phi(y) = F(c + G y) on the cube Y = [-r, r]^m, r the largest power of two
+ * with c + G Y inside the box, and Krawczyk's operator
+ *   K(Y) = -M phi(0) + (I - M A) Y,   A = D G (D: the Jacobian enclosed on
+ *   the box, so A encloses phi's Jacobian on Y),   M = (mid(D) G)^-1.
+ * K inside the open cube certifies a zero of phi in Y, that is a zero of F
+ * in c + G Y, inside the box.
+ *   fc   : m x nbox x 2, F_i on the centre enclosures (contains F_i(c));
+ *   gc   : (m k) x nbox x 2, dF_i/dx_j on the centre enclosures, row i k + j;
+ *   D    : (m k) x nbox x 2, dF_i/dx_j on the boxes;
+ *   box, centre : nbox x k x 2.
+ * G, mid(D) G and M are computed in round-to-nearest (any real M is valid);
+ * every enclosure is outward.  out[b] = 1 when certified; K (nbox x m x 2)
+ * and r (nbox) when not NULL (0 when no cube was found). */
+int orc_newton_span(int k, int m, int64_t nbox, const double* fc, const double* gc, const double* D,
+                    const double* box, const double* centre, uint8_t* out, double* K, double* rout) {
+  if (k < 2 || k > ORC_KMAX || m < 1 || m >= k) return -1;
+  for (int64_t b = 0; b < nbox; b++) {
+    double G[ORC_KMAX][ORC_KMAX], P[ORC_KMAX][ORC_KMAX], Mi[ORC_KMAX][ORC_KMAX];
+    round_restore();
+    for (int j = 0; j < k; j++)
+      for (int l = 0; l < m; l++) {
+        const double* e = gc + (((int64_t)(l * k + j)) * nbox + b) * 2;
+        G[j][l] = (e[0] + e[1]) * 0.5;
+      }
+    for (int i = 0; i < m; i++)
+      for (int l = 0; l < m; l++) {
+        double acc = 0.0;
+        for (int j = 0; j < k; j++) {
+          const double* e = D + (((int64_t)(i * k + j)) * nbox + b) * 2;
+          const double t = ((e[0] + e[1]) * 0.5) * G[j][l];
+          acc = j == 0 ? t : acc + t;
+        }
+        P[i][l] = acc;
+        Mi[i][l] = i == l ? 1.0 : 0.0;
+      }
+    int ok = 1;
+    for (int col = 0; col < m && ok; col++) {
+      int piv = col;
+      for (int r = col + 1; r < m; r++)
+        if (fabs(P[r][col]) > fabs(P[piv][col])) piv = r;
+      if (!(P[piv][col] != 0.0)) { ok = 0; break; }  /* zero (or NaN) pivot */
+      if (piv != col)
+        for (int j = 0; j < m; j++) {
+          double t = P[col][j]; P[col][j] = P[piv][j]; P[piv][j] = t;
+          t = Mi[col][j]; Mi[col][j] = Mi[piv][j]; Mi[piv][j] = t;
+        }
+      const double p = P[col][col];
+      for (int j = 0; j < m; j++) { P[col][j] = P[col][j] / p; Mi[col][j] = Mi[col][j] / p; }
+      for (int r = 0; r < m; r++) {
+        if (r == col) continue;
+        const double f = P[r][col];
+        for (int j = 0; j < m; j++) {
+          P[r][j] = P[r][j] - f * P[col][j];
+          Mi[r][j] = Mi[r][j] - f * Mi[col][j];
+        }
+      }
+    }
+    /* the cube: s_j = RU(sum_l |G_jl|) and the room RD(min(c_j - lo_j, hi_j - c_j)) on every axis */
+    int e = 0, have = 0;
+    for (int j = 0; j < k && ok; j++) {
+      const double* I = box + (b * k + j) * 2;
+      const double c = centre[(b * k + j) * 2];
+      round_up(ORC_OUTWARD);
+      double sj = fabs(G[j][0]);
+      for (int l = 1; l < m; l++) sj = sj + fabs(G[j][l]);
+      round_down(ORC_OUTWARD);
+      const double r1 = c - I[0], r2 = I[1] - c;
+      round_restore();
+      const double room = r1 < r2 ? r1 : r2;
+      if (!(sj > 0.0)) continue;
+      if (!(room > 0.0)) { ok = 0; break; }
+      const int ej = ilogb(room) - ilogb(sj);  /* s 2^ej < 2 room */
+      e = have ? (ej < e ? ej : e) : ej;
+      have = 1;
+    }
+    if (!have) ok = 0;
+    if (ok) {  /* s_j 2^e <= room_j on every axis, one step down at most */
+      int fits = 1;
+      for (int j = 0; j < k; j++) {
+        const double* I = box + (b * k + j) * 2;
+        const double c = centre[(b * k + j) * 2];
+        round_up(ORC_OUTWARD);
+        double sj = fabs(G[j][0]);
+        for (int l = 1; l < m; l++) sj = sj + fabs(G[j][l]);
+        round_down(ORC_OUTWARD);
+        const double r1 = c - I[0], r2 = I[1] - c;
+        round_restore();
+        const double room = r1 < r2 ? r1 : r2;
+        if (sj > 0.0 && !(ldexp(sj, e) <= room)) fits = 0;
+      }
+      if (!fits) e -= 1;
+    }
+    const double r = ok ? ldexp(1.0, e) : 0.0;
+    const ivl Y = {-r, r};
+    /* A = D G, enclosing phi's Jacobian on Y */
+    ivl A[ORC_KMAX][ORC_KMAX];
+    for (int q = 0; q < m; q++)
+      for (int l = 0; l < m; l++) {
+        ivl acc = {0.0, 0.0};
+        for (int j = 0; j < k; j++) {
+          const double* d = D + (((int64_t)(q * k + j)) * nbox + b) * 2;
+          ivl dj = {d[0], d[1]}, g = {G[j][l], G[j][l]};
+          ivl t = iv_mul(dj, g, ORC_OUTWARD);
+          acc = j == 0 ? t : iv_add(acc, t, ORC_OUTWARD);
+        }
+        A[q][l] = acc;
+      }
+    int inside = ok;
+    for (int i = 0; i < m; i++) {
+      ivl Ki = {0.0, 0.0};
+      if (ok) {
+        ivl yf = {0.0, 0.0};
+        for (int l = 0; l < m; l++) {
+          ivl fl = {fc[((int64_t)l * nbox + b) * 2], fc[((int64_t)l * nbox + b) * 2 + 1]};
+          ivl ml = {Mi[i][l], Mi[i][l]};
+          ivl t = iv_mul(ml, fl, ORC_OUTWARD);
+          yf = l == 0 ? t : iv_add(yf, t, ORC_OUTWARD);
+        }
+        Ki.lo = -yf.hi;
+        Ki.hi = -yf.lo;
+        for (int l = 0; l < m; l++) {
+          ivl a = {i == l ? 1.0 : 0.0, i == l ? 1.0 : 0.0};
+          for (int q = 0; q < m; q++) {
+            ivl mq = {Mi[i][q], Mi[i][q]};
+            ivl t = iv_mul(mq, A[q][l], ORC_OUTWARD);
+            ivl nt = {-t.hi, -t.lo};
+            a = iv_add(a, nt, ORC_OUTWARD);
+          }
+          Ki = iv_add(Ki, iv_mul(a, Y, ORC_OUTWARD), ORC_OUTWARD);
+        }
+        if (!(Ki.lo > -r && Ki.hi < r)) inside = 0;
+      }
+      if (K) { K[(b * m + i) * 2] = Ki.lo; K[(b * m + i) * 2 + 1] = Ki.hi; }
+    }
+    if (rout) rout[b] = r;
     out[b] = (uint8_t)inside;
   }
   return 0;

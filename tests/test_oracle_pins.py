@@ -1305,6 +1305,109 @@ def test_newton_certified_boxes_hold_a_root_random_system():
         assert np.all(x >= lo - 1e-9) and np.all(x <= lo + h + 1e-9), (q, x, lo)
 
 
+# ---------------------------------------------------------------------------
+# Newton test for fewer equations than variables (Sec. 3.2): the square test
+# on the span of the gradients at the box centre
+# ---------------------------------------------------------------------------
+
+def test_newton_span_line_of_two_planes_closed_form():
+    """x = a, y = b in 3 variables (a line along z): G spans the xy-plane,
+    A = D G = I exactly, M = I, r = the half cell width, and K is the
+    point (a - c_x, b - c_y) up to rounding; certified are exactly the boxes
+    whose xy-cell holds (a, b) in its interior (a, b off the grid lines),
+    on every z cell."""
+    k, level = 3, 4
+    a, b = 0.3, -0.21
+    F1 = synth.monomial_poly(3, 1, {(1, 0, 0): 1.0, (0, 0, 0): -a})
+    F2 = synth.monomial_poly(3, 1, {(0, 1, 0): 1.0, (0, 0, 0): -b})
+    S = orc.csf_from_boxes(_all_boxes(k, level), level)
+    flags, K, r = orc.newton_span_level([F1, F2], S, np.array([-1.0, 1.0] * k), want_k=True)
+    h = 2.0 / (1 << level)
+    lo = -1.0 + S["boxes"] * h
+    want = (lo[:, 0] < a) & (a < lo[:, 0] + h) & (lo[:, 1] < b) & (b < lo[:, 1] + h)
+    assert np.array_equal(flags, want) and want.sum() == 1 << level
+    assert np.all(r == h / 2)
+    c = lo + h / 2
+    assert np.all(np.abs(K[flags, 0, :] - (a - c[flags, 0])[:, None]) < 1e-15)
+
+
+def test_newton_span_one_equation_is_the_slab_rule():
+    """One plane x2 = c in 3 variables (m = 1): certified exactly the boxes
+    whose x2 cell holds c in its interior."""
+    k, level, c0 = 3, 3, 0.1
+    F = synth.monomial_poly(3, 1, {(0, 1, 0): 1.0, (0, 0, 0): -c0})
+    S = orc.csf_from_boxes(_all_boxes(k, level), level)
+    flags = orc.newton_span_level([F], S, np.array([-1.0, 1.0] * k))
+    lo = -1.0 + S["boxes"][:, 1] * (2.0 / (1 << level))
+    assert np.array_equal(flags, (lo < c0) & (c0 < lo + 2.0 / (1 << level)))
+
+
+def test_newton_span_circle_is_sound_and_finds_boxes():
+    """x^2 + y^2 + z^2 = 0.5, z = 0.3 (a circle of radius^2 0.41): every
+    certified box meets the circle (exact rational test: its z cell holds 0.3
+    and its xy-rectangle has points at squared distance below and above
+    0.41), and at level 6 over half of the 164 kept boxes that meet it are
+    certified (the cube on the plane is the largest power-of-two cube whose
+    image fits the box, so a zero far from the centre is missed)."""
+    k, level = 3, 6
+    F1 = synth.monomial_poly(3, 2, {(2, 0, 0): 1.0, (0, 2, 0): 1.0, (0, 0, 2): 1.0, (0, 0, 0): -0.5})
+    F2 = synth.monomial_poly(3, 1, {(0, 0, 1): 1.0, (0, 0, 0): -0.3})
+    dom = np.array([-1.0, 1.0] * k)
+    recs = orc.subdivide([F1, F2], k, level)
+    S = recs[-1]["S"]
+    flags = orc.newton_span_level([F1, F2], S, dom)
+    h = Fraction(2, 1 << level)
+    rho2 = ex.F(0.5) - ex.F(0.3) ** 2
+    meets = np.zeros(len(flags), bool)
+    for q in range(len(flags)):
+        bx = [(Fraction(-1) + int(v) * h, Fraction(-1) + (int(v) + 1) * h) for v in S["boxes"][q]]
+        near = sum(min(abs(lo_), abs(hi_)) ** 2 if lo_ * hi_ > 0 else 0 for lo_, hi_ in bx[:2])
+        far = sum(max(abs(lo_), abs(hi_)) ** 2 for lo_, hi_ in bx[:2])
+        meets[q] = bx[2][0] <= ex.F(0.3) <= bx[2][1] and near <= rho2 <= far
+    assert not (flags & ~meets).any()
+    assert meets.sum() == 164 and flags.sum() > meets.sum() // 2, (flags.sum(), meets.sum())
+
+
+def test_newton_span_nothing_without_a_regular_point():
+    """A vanishing gradient at the centre (the origin of x^2 + y^2 + z^2)
+    and two copies of one equation (a rank-deficient system) certify no box;
+    the square case is refused."""
+    k, level = 3, 1
+    S = orc.csf_from_boxes(_all_boxes(k, level), level)
+    dom = np.array([-1.0, 1.0] * k)
+    P = synth.monomial_poly(3, 2, {(2, 0, 0): 1.0, (0, 2, 0): 1.0, (0, 0, 2): 1.0, (0, 0, 0): -0.1})
+    S0 = orc.csf_from_boxes(np.array([[0, 0, 0]]), 0)
+    assert not orc.newton_span_level([P], S0, dom).any()
+    L = synth.monomial_poly(3, 1, {(1, 0, 0): 1.0, (0, 1, 0): 1.0, (0, 0, 0): -0.1})
+    assert not orc.newton_span_level([L, L], S, dom).any()
+    with pytest.raises(AssertionError):
+        orc.newton_span_level([L, L, L], S, dom)
+
+
+def test_newton_span_certified_boxes_hold_a_zero_random_system():
+    """Two random trivariate polynomials of degree 3: from the centre of every
+    certified box, floating-point minimum-norm Newton steps (in the span of
+    the gradients) converge to a zero of the system inside the box."""
+    k, d, level = 3, 3, 6
+    polys = synth.small_random(k, d, seed=263, npolys=2)
+    dom = np.array([-1.0, 1.0] * k)
+    S = orc.subdivide(polys, k, level)[-1]["S"]
+    flags = orc.newton_span_level(polys, S, dom)
+    assert flags.sum() >= 20
+    h = 2.0 / (1 << level)
+    dcs = [[orc.deriv(p, d, j)[0] for j in range(k)] for p in polys]
+    for q in np.flatnonzero(flags):
+        lo = -1.0 + S["boxes"][q] * h
+        x = (lo + h / 2)[None, :]
+        for _ in range(40):
+            Fx = np.array([orc.eval_points(p, d, x)[0] for p in polys])
+            Jx = np.array([[orc.eval_points(dcs[i][j], d, x)[0] for j in range(k)] for i in range(2)])
+            x = x - (Jx.T @ np.linalg.solve(Jx @ Jx.T, Fx))[None, :]
+        Fx = np.array([orc.eval_points(p, d, x)[0] for p in polys])
+        assert np.abs(Fx).max() < 1e-12
+        assert np.all(x[0] >= lo - 1e-9) and np.all(x[0] <= lo + h + 1e-9), (q, x, lo)
+
+
 def test_order_costs_closed_forms():
     """Node counts under each variable order for sets whose CSFs are known in
     closed form: the full grid (2^{(l+1)L} nodes at depth l whatever the
