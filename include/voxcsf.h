@@ -261,9 +261,11 @@ int taylor_inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const d
                           size_t ws_bytes, void* stream);
 
 /*
- * newton_test -- the Newton interval inclusion test for a square system
- * F = (F_1..F_k) (np == k; Sec. 3.2, inclusion criterion for several
- * polynomials), on every box of S, in Krawczyk's form:
+ * newton_test -- the Newton interval inclusion test for a system of
+ * 1 <= np <= k polynomials (Sec. 3.2, inclusion criterion for several
+ * polynomials), on every box of S.
+ *
+ * Square systems (np == k), in Krawczyk's form:
  *   K(B) = c - Y F(c) + (I - Y S)(B - c),
  * c the centre enclosure, S the slope matrix of the box (S_ij enclosed by
  * dF_i/dx_j on the box with x_1..x_j free and x_{j+1}..x_k at the centre,
@@ -275,9 +277,25 @@ int taylor_inclusion_test(const vx_poly* P, int32_t np, const vx_csf* S, const d
  * (F has a zero in it) when every K_i lies in the inner box [upper end of
  * the lower vertex enclosure, lower end of the upper one]; a zero pivot
  * certifies nothing.
+ *
+ * Fewer polynomials than variables (np = m < k; the same passage: the box
+ * intersected with the span of the gradients at its centre gives a square
+ * system): with c the lower end of the centre enclosure and G (k x m) the
+ * midpoints of the gradient enclosures at the centre (column l for F_l),
+ * phi(y) = F(c + G y) is tested on the cube Y = [-r, r]^m, r the largest
+ * power of two with s_j r <= min(c_j - lo_j, hi_j - c_j) on every axis
+ * (s_j = sum_l |G_jl| rounded up, the room rounded down), so that c + G Y
+ * lies in the box:
+ *   K(Y) = -M phi(0) + (I - M A) Y,   A = D G,   M = (mid(D) G)^-1,
+ * D the gradients enclosed on the box (one Algorithm-2 evaluation of the
+ * derivative polynomials), phi(0) enclosed by F on the centre enclosure;
+ * G, mid(D) G and M in round-to-nearest, K outward, sums in ascending index
+ * order.  K inside the open cube certifies a zero of F in the box.
+ *
  *   incl : device uint8, S->n[k-1]; 1 = certified.
- *   kout : device double, S->n[k-1] x k x 2 (box, axis, lo/hi), or NULL: K.
- * Errors as interval_eval_level, VX_EINVAL when np != k; workspace
+ *   kout : device double, S->n[k-1] x np x 2 (box, component, lo/hi), or
+ *          NULL: K (in the cube's coordinates when np < k).
+ * Errors as interval_eval_level, VX_EINVAL when np > k; workspace
  * vx_workspace_bytes(VX_WS_NEWTON, P, np, S, 0).
  */
 int newton_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom, uint8_t* incl, double* kout,
@@ -363,7 +381,7 @@ int run_subdivision(const vx_poly* P, int32_t np, const double* dom, int32_t dep
  * records no per-level timing events (stats eval_ms and filter_ms are 0):
  * each event is a packet the stream must pass between the level's kernels.
  * VX_RUN_INCLUSION (C1: vertex signs, inclusion_test, for one polynomial;
- * the Newton test, newton_test, for a square system) or
+ * the Newton test, newton_test, for a system of 2..k polynomials) or
  * VX_RUN_INCLUSION_TAYLOR (the Taylor form of the vertex test,
  * taylor_inclusion_test, one polynomial), with VX_RUN_INCLUSION_FROM(L), run
  * Algorithm 3 with both criteria: from level L on (boxes smaller than the

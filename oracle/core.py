@@ -663,10 +663,11 @@ def subdivide_c1(polys, k: int, depth: int, c1_from: int, dom=None, nthreads: in
     are dropped; from level ``c1_from`` on (boxes smaller than the threshold)
     the kept boxes that satisfy C1 join the output R and are not bisected;
     the rest are bisected.  C1 is the vertex-sign test (or its Taylor form)
-    for one polynomial and the Newton test for a square system.  Per level:
+    for one polynomial and the Newton test for a system of 2..k polynomials
+    (on the span of the gradients when there are fewer than k).  Per level:
     S, the C0 flags, the certified boxes and the continuing ones."""
-    newton = len(polys) == k and k >= 2
-    assert len(polys) == 1 or (newton and not taylor), "one polynomial, or a square system"
+    newton = 2 <= len(polys) <= k
+    assert len(polys) == 1 or (newton and not taylor), "one polynomial, or a system of at most k"
     dom = np.array([-1.0, 1.0] * k) if dom is None else np.asarray(dom, np.float64)
     boxes = np.zeros((1, k), np.int64)
     out = []
@@ -677,7 +678,8 @@ def subdivide_c1(polys, k: int, depth: int, c1_from: int, dom=None, nthreads: in
         incl = np.zeros(len(keep), bool)
         if level >= c1_from and len(keep):
             if newton:
-                incl = newton_level(polys, S, dom, nthreads)
+                fn = newton_level if len(polys) == k else newton_span_level
+                incl = fn(polys, S, dom, nthreads)
             else:
                 fn = taylor_inclusion_level if taylor else inclusion_level
                 incl = fn(polys, S, dom, nthreads)[0]

@@ -372,15 +372,16 @@ def inclusion_test(polys, csf: CSF, dom, stream=None, taylor: bool = False) -> t
 
 
 def newton_test(polys, csf: CSF, dom, want_k: bool = False, stream=None):
-    """Newton interval test (Krawczyk's form) of a square system on every box:
-    (nboxes,) uint8, 1 where the system certainly has a zero in the box;
-    with ``want_k`` also the enclosures K (nboxes, k, 2)."""
+    """Newton interval test (Krawczyk's form) of a system of np <= k
+    polynomials on every box (np < k: on the span of the gradients at the box
+    centre): (nboxes,) uint8, 1 where the system certainly has a zero in the
+    box; with ``want_k`` also the enclosures K (nboxes, np, 2)."""
     polys = as_polys(polys)
     dom = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
     nb = csf.nboxes
     dev = csf.idx[0].device
     incl = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
-    kout = torch.empty((max(nb, 1), csf.k, 2), dtype=torch.float64, device=dev) if want_k else None
+    kout = torch.empty((max(nb, 1), len(polys), 2), dtype=torch.float64, device=dev) if want_k else None
     parr = _poly_array(polys)
     s = csf.struct()
     need = int(lib().vx_workspace_bytes(VX_WS_NEWTON, parr, len(polys), C.byref(s), 0))

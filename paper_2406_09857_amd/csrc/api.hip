@@ -256,7 +256,7 @@ size_t vx_workspace_bytes(int32_t which, const vx_poly* P, int32_t np, const vx_
       if (check_csf(S, false) || (int64_t)S->k * S->level > 62) return 0;
       return order_workspace_bytes(S);
     case VX_WS_NEWTON:
-      if (check_csf(S, false) || check_poly(P, np, S->k) || np != S->k) return 0;
+      if (check_csf(S, false) || check_poly(P, np, S->k) || np > S->k) return 0;
       return newton_workspace_bytes(P, np, S);
     case VX_WS_GRAD:
       if (!P || np < 1 || np > PMAX_GRAD || check_poly(P, np, P[0].k)) return 0;
@@ -377,7 +377,9 @@ int newton_test(const vx_poly* P, int32_t np, const vx_csf* S, const double* dom
   int rc;
   if ((rc = check_csf(S, true))) return rc;
   if ((rc = check_poly(P, np, S->k))) return rc;
-  if (np != S->k) VX_FAIL(VX_EINVAL, "the Newton test needs a square system (%d polynomials, k = %d)", np, S->k);
+  if (np > S->k)
+    VX_FAIL(VX_EINVAL, "the Newton test needs at most as many polynomials as variables (%d polynomials, k = %d)", np,
+            S->k);
   if ((rc = check_dom(dom, S->k))) return rc;
   if (S->n[S->k - 1] > 0 && !incl) VX_FAIL(VX_EINVAL, "null output flags");
   if (!ws) VX_FAIL(VX_EINVAL, "null workspace");
@@ -537,12 +539,13 @@ static int run_loop(const vx_poly* P, int32_t np, const double* dom, int32_t dep
   const int incl_from = (flags >> 16) & 255;
   if ((flags & VX_RUN_INCLUSION) && (flags & VX_RUN_INCLUSION_TAYLOR))
     VX_FAIL(VX_EINVAL, "VX_RUN_INCLUSION and VX_RUN_INCLUSION_TAYLOR are exclusive");
-  // C1 of one polynomial: vertex signs (or their Taylor form); of a square
-  // system: the Newton test
-  const bool newton = incl_mode == 1 && np == k && k >= 2;
+  // C1 of one polynomial: vertex signs (or their Taylor form); of a system
+  // of 2..k polynomials: the Newton test (on the span of the gradients when
+  // there are fewer polynomials than variables)
+  const bool newton = incl_mode == 1 && np >= 2 && np <= k;
   if (incl_mode && np != 1 && !newton)
     VX_FAIL(VX_EINVAL, "the inclusion criterion needs one polynomial%s (np = %d, k = %d)",
-            incl_mode == 1 ? " or a square system" : "", np, k);
+            incl_mode == 1 ? " or a system of at most k" : "", np, k);
   if (incl_mode == 2 && (rc = check_taylor_polys(np, k, 2))) return rc;
   if (!incl_mode && incl_from) VX_FAIL(VX_EINVAL, "VX_RUN_INCLUSION_FROM without an inclusion flag");
   const bool times = stats && !(flags & VX_RUN_NO_TIMES);

@@ -1333,6 +1333,196 @@ __global__ void k_newton_k(int k, int64_t nleaf, GridSet gs, const int32_t* __re
   incl[b] = (uint8_t)inside;
 }
 
+// ---------------------------------------------------------------------------
+// Newton test for m < k polynomials (Sec. 3.2, inclusion criterion, last
+// paragraph): the box is intersected with the plane through a point c of it
+// spanned by the gradients at its centre, x = c + G y, and the square system
+// phi(y) = F(c + G y) is tested on a cube Y = [-r, r]^m whose image fits the
+// box.  c = the lower end of the centre enclosure, G (k x m) = the midpoints
+// of the gradient enclosures at the centre, r = the largest power of two
+// with s_j r <= min(c_j - lo_j, hi_j - c_j) for s_j = sum_l |G_jl| (rounded
+// up, the room rounded down), and Krawczyk's operator
+//   K(Y) = -M phi(0) + (I - M A) Y,   A = D G,   M = (mid(D) G)^-1,
+// D the Jacobian enclosed on the box (so A encloses phi's Jacobian on Y),
+// phi(0) enclosed by F on the centre enclosure.  K inside the open cube
+// certifies a zero of phi in Y, hence of F in c + G Y, inside the box.
+// G, mid(D) G and M are computed in round-to-nearest (one kernel), every
+// enclosure outward (another).  Derivative enclosures sit at
+// ((i * k + j) * nleaf + b), F_i at (i * nleaf + b).
+// ---------------------------------------------------------------------------
+
+// G (at ((j * m + l) * nleaf + b)) and M = (mid(D) G)^-1 (at ((i * m + l) *
+// nleaf + b)) per box; Gauss-Jordan as in k_newton_y.
+__global__ void k_span_m(int k, int m, int64_t nleaf, const double* __restrict__ gc_lo,
+                         const double* __restrict__ gc_hi, const double* __restrict__ d_lo,
+                         const double* __restrict__ d_hi, double* __restrict__ Gout, double* __restrict__ Mout,
+                         uint8_t* __restrict__ ok) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  double G[VX_KMAX][VX_KMAX], A[VX_KMAX][VX_KMAX], Z[VX_KMAX][VX_KMAX];
+  for (int j = 0; j < k; j++)
+    for (int l = 0; l < m; l++) {
+      const int64_t e = ((int64_t)l * k + j) * nleaf + b;
+      G[j][l] = (gc_lo[e] + gc_hi[e]) * 0.5;
+    }
+  for (int i = 0; i < m; i++)
+    for (int l = 0; l < m; l++) {
+      double acc = 0.0;
+      for (int j = 0; j < k; j++) {
+        const int64_t e = ((int64_t)i * k + j) * nleaf + b;
+        const double t = ((d_lo[e] + d_hi[e]) * 0.5) * G[j][l];
+        acc = j == 0 ? t : acc + t;
+      }
+      A[i][l] = acc;
+      Z[i][l] = i == l ? 1.0 : 0.0;
+    }
+  int good = 1;
+  for (int col = 0; col < m && good; col++) {
+    int piv = col;
+    for (int r = col + 1; r < m; r++)
+      if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+    if (!(A[piv][col] != 0.0)) {
+      good = 0;
+      break;
+    }
+    if (piv != col)
+      for (int j = 0; j < m; j++) {
+        double t = A[col][j];
+        A[col][j] = A[piv][j];
+        A[piv][j] = t;
+        t = Z[col][j];
+        Z[col][j] = Z[piv][j];
+        Z[piv][j] = t;
+      }
+    const double p = A[col][col];
+    for (int j = 0; j < m; j++) {
+      A[col][j] = A[col][j] / p;
+      Z[col][j] = Z[col][j] / p;
+    }
+    for (int r = 0; r < m; r++) {
+      if (r == col) continue;
+      const double f = A[r][col];
+      for (int j = 0; j < m; j++) {
+        A[r][j] = A[r][j] - f * A[col][j];
+        Z[r][j] = Z[r][j] - f * Z[col][j];
+      }
+    }
+  }
+  for (int j = 0; j < k; j++)
+    for (int l = 0; l < m; l++) Gout[((int64_t)j * m + l) * nleaf + b] = G[j][l];
+  for (int i = 0; i < m; i++)
+    for (int l = 0; l < m; l++) Mout[((int64_t)i * m + l) * nleaf + b] = good ? Z[i][l] : 0.0;
+  ok[b] = (uint8_t)good;
+}
+
+// The cube, A = D G, K and the test, in outward arithmetic.
+__global__ void k_span_k(int k, int m, int64_t nleaf, GridSet gs, const int32_t* __restrict__ labels,
+                         const double* __restrict__ fc_lo, const double* __restrict__ fc_hi,
+                         const double* __restrict__ d_lo, const double* __restrict__ d_hi,
+                         const double* __restrict__ Gm, const double* __restrict__ Mm,
+                         const uint8_t* __restrict__ ok, uint8_t* __restrict__ incl, double* __restrict__ kout) {
+  round_up_mode();
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nleaf) return;
+  double G[VX_KMAX][VX_KMAX];
+  for (int j = 0; j < k; j++)
+    for (int l = 0; l < m; l++) G[j][l] = Gm[((int64_t)j * m + l) * nleaf + b];
+  bool good = ok[b] != 0;
+  // s_j r <= room_j on every axis with s_j > 0; r = 2^e
+  int e = 0;
+  bool have = false;
+  double sj[VX_KMAX], room[VX_KMAX];
+  for (int j = 0; j < k; j++) {
+    double inl, ih, cnl, ch;
+    const int32_t lab = labels[b * k + j];
+    cell(gs.cell[j], lab, inl, ih);
+    cell(gs.centre[j], lab, cnl, ch);
+    const double c = opaque(-cnl);  // the lower end of the centre enclosure
+    double s = fabs(G[j][0]);
+    for (int l = 1; l < m; l++) s = s + fabs(G[j][l]);  // rounded up
+    const double r1 = -opaque(cnl + opaque(-inl));  // RD(c - lo) = -RU(lo - c)
+    const double r2 = -opaque(c + opaque(-ih));     // RD(hi - c) = -RU(c - hi)
+    sj[j] = s;
+    room[j] = r1 < r2 ? r1 : r2;
+    if (!good || !(s > 0.0)) continue;
+    if (!(room[j] > 0.0)) {
+      good = false;
+      continue;
+    }
+    const int ej = ilogb(room[j]) - ilogb(s);
+    e = have ? (ej < e ? ej : e) : ej;
+    have = true;
+  }
+  if (!have) good = false;
+  if (good) {
+    bool fits = true;
+    for (int j = 0; j < k; j++)
+      if (sj[j] > 0.0 && !(ldexp(sj[j], e) <= room[j])) fits = false;
+    if (!fits) e -= 1;
+  }
+  const double r = good ? ldexp(1.0, e) : 0.0;
+  const CellOps Ycube = cell_ops(r, r, CLS_STRADDLE);  // [-r, r]
+  // A = D G (m x m intervals, (nlo, hi))
+  double anl[VX_KMAX][VX_KMAX], ah[VX_KMAX][VX_KMAX];
+  for (int q = 0; q < m; q++)
+    for (int l = 0; l < m; l++) {
+      double accn = 0.0, acch = 0.0;
+      for (int j = 0; j < k; j++) {
+        const int64_t ei = ((int64_t)q * k + j) * nleaf + b;
+        double tnl, th;
+        point_times(G[j][l], -opaque(d_lo[ei]), d_hi[ei], tnl, th);
+        if (j == 0) {
+          accn = tnl;
+          acch = th;
+        } else {
+          accn = accn + tnl;
+          acch = acch + th;
+        }
+      }
+      anl[q][l] = accn;
+      ah[q][l] = acch;
+    }
+  bool inside = good;
+  for (int i = 0; i < m; i++) {
+    double knl = 0.0, kh = 0.0;
+    if (good) {
+      double ynl = 0.0, yh = 0.0;
+      for (int l = 0; l < m; l++) {
+        double pnl, ph;
+        point_times(Mm[((int64_t)i * m + l) * nleaf + b], -opaque(fc_lo[(int64_t)l * nleaf + b]),
+                    fc_hi[(int64_t)l * nleaf + b], pnl, ph);
+        if (l == 0) {
+          ynl = pnl;
+          yh = ph;
+        } else {
+          ynl = ynl + pnl;
+          yh = yh + ph;
+        }
+      }
+      knl = yh;  // -yf
+      kh = ynl;
+      for (int l = 0; l < m; l++) {
+        double cnl = i == l ? -1.0 : opaque(-0.0), chh = i == l ? 1.0 : 0.0;
+        for (int q = 0; q < m; q++) {
+          double tnl, th;
+          point_times(Mm[((int64_t)i * m + q) * nleaf + b], anl[q][l], ah[q][l], tnl, th);
+          cnl = cnl + th;  // a - t
+          chh = chh + tnl;
+        }
+        mul_add_sep(cnl, chh, Ycube, knl, kh);  // a Y + K_i
+        knl = cnl;
+        kh = chh;
+      }
+      inside = inside && (knl < r) && (kh < r);
+    }
+    if (kout) {
+      kout[(b * m + i) * 2] = -opaque(knl);
+      kout[(b * m + i) * 2 + 1] = kh;
+    }
+  }
+  incl[b] = (uint8_t)inside;
+}
+
 struct NewtonPlan {
   double *fcl, *fch, *sl, *sh, *Y;
   uint8_t* ok;
@@ -1367,8 +1557,107 @@ static void plan_newton(Arena& A, NewtonPlan& N, const vx_poly* P, int np, const
   N.scratch = A.take<char>(N.scratch_bytes);
 }
 
+struct SpanPlan {
+  double *fcl, *fch, *gl, *gh, *dl, *dh, *G, *M;
+  uint8_t* ok;
+  int32_t* labels;
+  char* scratch;
+  size_t scratch_bytes;
+};
+
+static void plan_span(Arena& A, SpanPlan& N, const vx_poly* P, int np, const MvPolys& M, const vx_csf* S) {
+  const int k = S->k;
+  const size_t nl = (size_t)S->n[k - 1];
+  N.fcl = A.take<double>(np * nl);
+  N.fch = A.take<double>(np * nl);
+  N.gl = A.take<double>((size_t)np * k * nl);
+  N.gh = A.take<double>((size_t)np * k * nl);
+  N.dl = A.take<double>((size_t)np * k * nl);
+  N.dh = A.take<double>((size_t)np * k * nl);
+  N.G = A.take<double>((size_t)k * np * nl);
+  N.M = A.take<double>((size_t)np * np * nl);
+  N.ok = A.take<uint8_t>(nl);
+  N.labels = A.take<int32_t>((size_t)k * nl);
+  N.scratch_bytes = mv_scratch_bytes(P, np, M, S);
+  N.scratch = A.take<char>(N.scratch_bytes);
+}
+
+static GridSet grid_set(const double* dom, int k, int level) {
+  GridSet gs;
+  memset(&gs, 0, sizeof gs);
+  for (int a = 0; a < k; a++) {
+    AxisGrid g;
+    g.dlo = dom[2 * a];
+    g.dhi = dom[2 * a + 1];
+    g.ndlo = -g.dlo;
+    g.ndhi = -g.dhi;
+    g.level = level;
+    g.centre = 0;
+    gs.cell[a] = g;
+    g.centre = 1;
+    gs.centre[a] = g;
+    g.centre = 2;
+    gs.vertex[a] = g;
+  }
+  return gs;
+}
+
+// The test for np < k polynomials (see k_span_m); K is np per box.
+static int newton_span_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, uint8_t* incl,
+                            double* kout, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int k = S->k;
+  const int64_t nl = S->n[k - 1];
+  if (nl == 0) return VX_OK;
+  const size_t rb = (mv_run_bytes(P, np, 1) + 255) / 256 * 256;
+  if (rb > ws_bytes) VX_FAIL(VX_ECAPACITY, "Newton test: workspace too small");
+  MvRun R;
+  int rc;
+  if ((rc = mv_run_prepare(P, np, 1, reinterpret_cast<char*>(ws), rb, R, st))) return rc;
+  Arena A;
+  A.base = reinterpret_cast<char*>(ws) + rb;
+  A.size = ws_bytes - rb;
+  SpanPlan N;
+  plan_span(A, N, P, np, R.M, S);
+  if (A.overflow) VX_FAIL(VX_ECAPACITY, "Newton test: workspace of %zu bytes is too small", ws_bytes);
+  const int pr = prof_start("newton", (double)nl, st);
+  // F and its gradient at the centres, the gradient on the boxes
+  if ((rc = eval_level_prepared(R.QF, S, dom, N.fcl, N.fch, nullptr, N.scratch, N.scratch_bytes, st, P, 1)))
+    return rc;
+  if ((rc = eval_level_prepared(R.QD, S, dom, N.gl, N.gh, nullptr, N.scratch, N.scratch_bytes, st, R.M.dp.data(),
+                                1)))
+    return rc;
+  if ((rc = eval_level_prepared(R.QD, S, dom, N.dl, N.dh, nullptr, N.scratch, N.scratch_bytes, st, R.M.dp.data(),
+                                0)))
+    return rc;
+  CsfView cv;
+  memset(&cv, 0, sizeof cv);
+  for (int l = 0; l < k; l++) {
+    cv.idx[l] = S->idx[l];
+    cv.ptr[l] = S->ptr[l];
+    cv.n[l] = S->n[l];
+  }
+  const unsigned nb = (unsigned)((nl + 255) / 256);
+  hipLaunchKernelGGL(k_leaf_labels, dim3(nb), dim3(256), 0, st, k, cv, N.labels);
+  VX_CHECK_LAUNCH("k_leaf_labels");
+  hipLaunchKernelGGL(k_span_m, dim3(nb), dim3(256), 0, st, k, np, nl, (const double*)N.gl, (const double*)N.gh,
+                     (const double*)N.dl, (const double*)N.dh, N.G, N.M, N.ok);
+  VX_CHECK_LAUNCH("k_span_m");
+  hipLaunchKernelGGL(k_span_k, dim3(nb), dim3(256), 0, st, k, np, nl, grid_set(dom, k, S->level),
+                     (const int32_t*)N.labels, (const double*)N.fcl, (const double*)N.fch, (const double*)N.dl,
+                     (const double*)N.dh, (const double*)N.G, (const double*)N.M, (const uint8_t*)N.ok, incl, kout);
+  VX_CHECK_LAUNCH("k_span_k");
+  prof_stop(pr, st);
+  return VX_OK;
+}
+
 size_t newton_workspace_bytes(const vx_poly* P, int np, const vx_csf* S) {
   MvPolys M = mv_polys(P, np, 1, nullptr, nullptr, nullptr, nullptr);
+  if (np < S->k) {
+    Arena A;
+    SpanPlan N;
+    plan_span(A, N, P, np, M, S);
+    return (mv_run_bytes(P, np, 1) + 255) / 256 * 256 + A.off + 512;
+  }
   Arena A;
   NewtonPlan N;
   plan_newton(A, N, P, np, M, S);
@@ -1379,6 +1668,7 @@ int newton_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom, ui
                 size_t ws_bytes, hipStream_t st) {
   const int k = S->k;
   const int64_t nl = S->n[k - 1];
+  if (np < k) return newton_span_impl(P, np, S, dom, incl, kout, ws, ws_bytes, st);
   if (nl == 0) return VX_OK;
   const size_t rb = (mv_run_bytes(P, np, 1) + 255) / 256 * 256;
   if (rb > ws_bytes) VX_FAIL(VX_ECAPACITY, "Newton test: workspace too small");
