@@ -345,6 +345,24 @@ def bench_newton(vx):
         out[name] = {"ms_per_run": (time.perf_counter() - t0) * 1e3,
                      "certified_per_level": [s_["certified"] for s_ in stats],
                      "continuing_last_level": stats[-1]["kept"][2]}
+    # fewer equations than variables: the circle of a sphere and a plane,
+    # C1 = the Newton test on the span of the gradients from level 5 on
+    c1 = synth.monomial_poly(3, 2, {(2, 0, 0): 1.0, (0, 2, 0): 1.0, (0, 0, 2): 1.0, (0, 0, 0): -0.5})
+    c2 = synth.monomial_poly(3, 1, {(0, 0, 1): 1.0, (0, 0, 0): -0.3})
+    cdom = [-1.0, 1.0] * 3
+    span = {"workload": "circle_k3: x^2 + y^2 + z^2 = 0.5 and z = 0.3 (two equations, three variables), "
+                        "domain [-1,1]^3, levels 0..9"}
+    for name, kw in (("loop_plain", {}), ("loop_newton_span", {"inclusion": "vertices", "inclusion_from": 5})):
+        vx.run_subdivision([c1, c2], cdom, 9, want_kept=False, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats, _ = vx.run_subdivision([c1, c2], cdom, 9, want_kept=False, **kw)
+        torch.cuda.synchronize()
+        span[name] = {"ms_per_run": (time.perf_counter() - t0) * 1e3,
+                      "certified_per_level": [s_["certified"] for s_ in stats],
+                      "continuing_last_level": stats[-1]["kept"][2]}
+    span["parity"] = "flags, K and the loop's sets equal to the oracle's (tests/test_gpu_newton.py)"
+    out["span"] = span
     return out
 
 
