@@ -312,6 +312,49 @@ static int scratch_address(void** out) {
   return VX_OK;
 }
 
+// Mapped, coherent host slots through which the level loop's filter publishes
+// its counts.  Pinning and mapping host memory costs tens of microseconds per
+// call, so a slot returns to a pool when its run ends and serves later runs on
+// the same device: one slot per call running at the same time, each held
+// until the process ends.
+struct CountSlot {
+  int64_t* host = nullptr;
+  int64_t* dev = nullptr;
+  int device = -1;
+};
+constexpr size_t COUNT_SLOT_BYTES = sizeof(int64_t) * (2 * VX_KMAX + 2);
+static std::mutex g_slot_mu;
+static std::vector<CountSlot> g_free_slots;
+
+static int take_count_slot(CountSlot* out) {
+  int dev = 0;
+  VX_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> g(g_slot_mu);
+    for (size_t i = 0; i < g_free_slots.size(); i++)
+      if (g_free_slots[i].device == dev) {
+        *out = g_free_slots[i];
+        g_free_slots.erase(g_free_slots.begin() + (long)i);
+        return VX_OK;
+      }
+  }
+  CountSlot s;
+  s.device = dev;
+  VX_HIP(hipHostMalloc((void**)&s.host, COUNT_SLOT_BYTES, hipHostMallocMapped | hipHostMallocCoherent));
+  const hipError_t e = hipHostGetDevicePointer((void**)&s.dev, s.host, 0);
+  if (e != hipSuccess) {
+    (void)hipHostFree(s.host);
+    VX_FAIL(VX_EHIP, "hipHostGetDevicePointer: %s", hipGetErrorString(e));
+  }
+  *out = s;
+  return VX_OK;
+}
+
+static void give_count_slot(const CountSlot& s) {
+  std::lock_guard<std::mutex> g(g_slot_mu);
+  g_free_slots.push_back(s);
+}
+
 struct ProfSuppress {
   ProfSuppress() { g_prof_suppressed = true; }
   ~ProfSuppress() { g_prof_suppressed = false; }
@@ -626,18 +669,24 @@ static int run_loop(const vx_poly* P, int32_t np, const double* dom, int32_t dep
   csf_place(&S, k, 0, cap, base);
   if ((rc = init_root_impl(&S, st))) return rc;
 
-  // Per-level counts come back through a mapped pinned host buffer written by
+  // Per-level counts come back through a mapped pinned host slot written by
   // the filter's last kernel: no copy launch, only the stream wait.
-  int64_t* counts = nullptr;
-  int64_t* counts_dev = nullptr;
-  VX_HIP(hipHostMalloc((void**)&counts, sizeof(int64_t) * (2 * VX_KMAX + 2), hipHostMallocMapped | hipHostMallocCoherent));
+  CountSlot slot;
+  if ((rc = take_count_slot(&slot))) return rc;
+  struct SlotGuard {
+    CountSlot s;
+    hipStream_t st;
+    bool drained = false;
+    ~SlotGuard() {
+      // a run that failed may have kernels in flight that still write the slot
+      if (!drained) (void)hipStreamSynchronize(st);
+      give_count_slot(s);
+    }
+  } slot_guard{slot, st};
+  int64_t* counts = slot.host;
+  int64_t* counts_dev = slot.dev;
   counts[2 * VX_KMAX] = 0;      // level-done flag
   counts[2 * VX_KMAX + 1] = 0;  // boxes certified by C1 at the level
-  struct PinGuard {
-    int64_t* p;
-    ~PinGuard() { (void)hipHostFree(p); }
-  } pin_guard{counts};
-  VX_HIP(hipHostGetDevicePointer((void**)&counts_dev, counts, 0));
   for (int level = 0; level <= depth; level++) {
     S.level = level;
     const int64_t nleaf = S.n[k - 1];
@@ -824,6 +873,7 @@ static int run_loop(const vx_poly* P, int32_t np, const double* dom, int32_t dep
   if ((rc = finish_times())) return rc;
   // the last filter may still be writing after it published its counts
   VX_HIP(hipStreamSynchronize(st));
+  slot_guard.drained = true;
   return VX_OK;
 }
 
