@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint, variable-order, Taylor-test, early-exit, inclusion and Newton legs")
+    ap.add_argument("--batched-eager", action="store_true",
+                    help="only the batched workload: autotune, then one eager run with the chosen launch shapes "
+                         "(for counter collection); prints its per-level counts and steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (reference for the HBM byte counters)")
     return ap.parse_args()
@@ -446,10 +449,33 @@ def measured_traffic(kernel: str, workload: str):
         return None
 
 
+def batched_eager():
+    """The batched workload run once eagerly (no graph) with autotuned launch
+    shapes, so that a counter collector sees each level's kernels."""
+    import torch
+    from paper_2406_09857_amd import binding as vx, synth
+    w = synth.batch()
+    dom = w.domain()
+    b, r = vx.run_subdivision_batch(w.systems, dom, w.depth, graph=False)
+    cap = [max(int(n), 1) for n in r["need"]]
+    chosen, level_ms = b.autotune(reps=1)
+    b.close()
+    del b
+    e = vx.Batch(w.systems, dom, w.depth, cap=cap, tune=chosen, graph=False)
+    e.run()
+    r = e.result(want_last=False, want_kept=False)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": w.name, "tune": chosen, "level_ms": level_ms,
+                      "n": r["stats"][:, 0, : w.k + 1].tolist(), "steps_depth": r["steps_depth"].tolist()}))
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batched_eager:
+        batched_eager()
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
