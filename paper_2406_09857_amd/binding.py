@@ -56,6 +56,14 @@ class vx_kernel_stat(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64), ("ms", C.c_double), ("units", C.c_double)]
 
 
+# The same record as a numpy structured type, for converting a whole array
+# of records at once (field access through ctypes costs microseconds each).
+LEVEL_STAT_DTYPE = np.dtype({
+    "names": [f for f, _ in vx_level_stat._fields_],
+    "formats": [np.int32, np.int32, (np.int64, KMAX), (np.int64, KMAX), np.int64, np.float64, np.float64, np.int64],
+    "offsets": [getattr(vx_level_stat, f).offset for f, _ in vx_level_stat._fields_],
+    "itemsize": C.sizeof(vx_level_stat)})
+
 LEVEL_CB = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int32, C.POINTER(vx_csf), C.c_void_p, C.c_void_p, C.c_void_p,
                        C.POINTER(vx_csf))
 
@@ -114,6 +122,9 @@ def lib():
 def _check(rc: int):
     if rc != VX_OK:
         raise VxError(rc, lib().vx_last_error().decode())
+
+
+_PDOUBLE = C.POINTER(C.c_double)
 
 
 def _stream(stream=None):
@@ -521,7 +532,7 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
     for _ in range(8):
         if ws is None or ws.numel() < size:
             ws = _ws(size)
-        rc = lib().run_subdivision_ex(parr, len(polys), dom.ctypes.data_as(C.POINTER(C.c_double)), depth,
+        rc = lib().run_subdivision_ex(parr, len(polys), C.cast(dom.__array_interface__["data"][0], _PDOUBLE), depth,
                                       flags,
                                       ws.data_ptr(), ws.numel(),
                                       C.byref(need), stats, cb, None, _stream(stream))
@@ -533,11 +544,11 @@ def run_subdivision(polys, dom, depth: int, record=None, ws_bytes: int | None = 
         break
     if "error" in final:
         raise final["error"]
-    out = []
-    for r in stats:
-        out.append({"level": r.level, "n": list(r.n)[:k], "kept": list(r.kept)[:k], "steps": r.steps,
-                    "eval_ms": r.eval_ms, "filter_ms": r.filter_ms, "certified": r.certified,
-                    "axes": [(r.axes >> (4 * l)) & 15 for l in range(k)]})
+    a = np.frombuffer(stats, dtype=LEVEL_STAT_DTYPE)
+    lv, ax, n, kp = a["level"].tolist(), a["axes"].tolist(), a["n"][:, :k].tolist(), a["kept"][:, :k].tolist()
+    steps, em, fm, ce = a["steps"].tolist(), a["eval_ms"].tolist(), a["filter_ms"].tolist(), a["certified"].tolist()
+    out = [{"level": lv[i], "n": n[i], "kept": kp[i], "steps": steps[i], "eval_ms": em[i], "filter_ms": fm[i],
+            "certified": ce[i], "axes": [(ax[i] >> (4 * l)) & 15 for l in range(k)]} for i in range(len(lv))]
     return out, final.get("kept")
 
 
