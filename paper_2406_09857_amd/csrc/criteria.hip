@@ -34,6 +34,7 @@
 #include "eval.hpp"
 #include "interval.hpp"
 #include "profile.hpp"
+#include "scan.hpp"
 
 namespace vx {
 
@@ -1037,57 +1038,262 @@ void mv_run_end(void* handle) { delete reinterpret_cast<MvRunHandle*>(handle); }
 // Inclusion criterion C1 (Sec. 3.2): F on the 2^k vertices of every box; the
 // box is certified to meet F = 0 when one vertex enclosure is > 0 and another
 // < 0 (intermediate value theorem along the box's edges).  The vertices of all
-// boxes are grid points: they are listed (2^k per box), turned into a CSF by
-// the radix-sort builder (which merges duplicates), evaluated once each by
-// Algorithm 2 on the degenerate vertex enclosures, and every box looks its
-// vertices up in that CSF.
+// boxes are grid points, evaluated once each by Algorithm 2 on the degenerate
+// vertex enclosures of their own CSF; every box then reads its vertices'
+// values through a corner table.
+//
+// The vertex CSF is built in closed form from the box CSF, depth by depth,
+// without listing or sorting vertex tuples.  A vertex prefix (v_0 .. v_l) is
+// a corner prefix of the box prefixes (v_0 - b_0 .. v_l - b_l), b_i in {0, 1}:
+// its "sources", at most 2^(l+1) box CSF nodes, indexed by beta = the bits
+// b_0 .. b_l (b_0 most significant).  The children of a vertex node are the
+// union over its sources s of {c, c + 1} for the children labels c of s (a
+// counting pass, a scan, a writing pass, one wave per vertex node).  The child w's sources are the children c = w - b of the
+// parent's sources, at beta' = 2 beta + b.  At the last depth beta' is the
+// corner index m of box c (bit k-1-j of m = the offset on axis j), so the
+// writing pass fills corner[m * N + c] (N boxes; corner-major, so that the
+// vertices of neighbouring boxes are stored side by side) with the vertex's
+// index: every corner of every box is written exactly once.  The labels
+// come out sorted and without repeats, so the CSF is the one of the sorted
+// vertex set.
 // ---------------------------------------------------------------------------
 
-// Vertex m of box b adds bit (k-1-j) of m on axis j (first axis most
-// significant), one thread per (box, vertex).
-__global__ void k_vertex_tuples(int k, int64_t nleaf, const int32_t* __restrict__ labels,
-                                int32_t* __restrict__ tuples) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int nv = 1 << k;
-  if (t >= nleaf * nv) return;
-  const int64_t b = t / nv;
-  const int m = (int)(t % nv);
-  for (int j = 0; j < k; j++) tuples[t * k + j] = labels[b * k + j] + ((m >> (k - 1 - j)) & 1);
+struct VtxJob {
+  int k;
+  CsfView S;                 // the boxes
+  int32_t* vidx[VX_KMAX];    // the vertex CSF
+  int32_t* vptr[VX_KMAX];
+  int32_t* src[VX_KMAX];     // src[l][v * 2^(l+1) + beta], l < k - 1 (-1: none)
+  int32_t* corner;           // corner[m * nbox + b]: vertex of corner m of box b
+  int64_t nbox;
+  int64_t* cnt;              // children per vertex node of the depth being built
+  int64_t* vn;               // vertex nodes per depth (device)
+};
+
+// Store vertex o of depth l with its sources (nsrc = 2^(l+1) of them).
+__device__ __forceinline__ void vtx_store(const VtxJob& J, int l, int64_t o, int32_t w, const int32_t* srcs,
+                                          int nsrc) {
+  J.vidx[l][o] = w;
+  if (l == J.k - 1) {
+    for (int b = 0; b < nsrc; b++)
+      if (srcs[b] >= 0) J.corner[(int64_t)b * J.nbox + srcs[b]] = (int32_t)o;
+  } else {
+    for (int b = 0; b < nsrc; b++) J.src[l][o * nsrc + b] = srcs[b];
+  }
 }
 
-// Leaf of the vertex CSF holding tuple `tup`: per depth a binary search among
-// the children of the node found so far; -1 if absent (never, for a CSF built
-// from the same tuples; an absent vertex only withholds a certificate).
-__device__ int64_t csf_find(const CsfView& c, int k, const int32_t* tup) {
-  int64_t lo = 0, hi = c.n[0];
-  for (int l = 0; l < k; l++) {
-    int64_t a = lo, b = hi;
-    while (a < b) {
-      const int64_t mid = (a + b) >> 1;
-      if (c.idx[l][mid] < tup[l]) a = mid + 1; else b = mid;
-    }
-    if (a >= hi || c.idx[l][a] != tup[l]) return -1;
-    if (l + 1 == k) return a;
-    lo = c.ptr[l][a];
-    hi = c.ptr[l][a + 1];
+// Depth 0: box node i (label a) gives vertex a, unless a - 1 is the box
+// label before it (then a is that node's a + 1), and vertex a + 1.
+__global__ void k_vtx0(VtxJob J, int write, const int64_t* __restrict__ off) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = J.S.n[0];
+  if (i >= n) return;
+  const int32_t* idx = J.S.idx[0];
+  const int32_t a = idx[i];
+  const bool lead = i == 0 || idx[i - 1] != a - 1;
+  if (!write) {
+    J.cnt[i] = lead ? 2 : 1;
+    return;
   }
-  return -1;
+  int64_t o = off[i];
+  if (lead) {
+    const int32_t s[2] = {(int32_t)i, -1};
+    vtx_store(J, 0, o++, a, s, 2);
+  }
+  const int32_t s[2] = {(i + 1 < n && idx[i + 1] == a + 1) ? (int32_t)(i + 1) : -1, (int32_t)i};
+  vtx_store(J, 0, o, a + 1, s, 2);
 }
+
+// The children of vertex node v (depth L) by a sequential merge of its
+// 2^(L+1) source runs, each run giving c and c + 1 for its labels c; returns
+// their number and, with `write`, stores them from index o on.
+template <int L>
+__device__ int64_t vtx_merge_node(const VtxJob& J, int64_t v, bool write, int64_t o) {
+  constexpr int NS = 1 << (L + 1);
+  const int32_t* cidx = J.S.idx[L + 1];
+  const int32_t* sptr = J.S.ptr[L];
+  constexpr int32_t NONE = 0x7fffffff;
+  int64_t p[NS], e[NS];
+  int32_t c[NS];
+  int ph[NS];
+#pragma unroll
+  for (int b = 0; b < NS; b++) {
+    const int32_t s = J.src[L][v * NS + b];
+    p[b] = s >= 0 ? sptr[s] : 0;
+    e[b] = s >= 0 ? sptr[s + 1] : 0;
+    c[b] = p[b] < e[b] ? cidx[p[b]] : NONE;
+    ph[b] = 0;
+  }
+  int64_t count = 0;
+  while (true) {
+    int32_t w = NONE;
+#pragma unroll
+    for (int b = 0; b < NS; b++)
+      if (c[b] != NONE && c[b] + ph[b] < w) w = c[b] + ph[b];
+    if (w == NONE) break;
+    int32_t srcs[2 * NS];
+#pragma unroll
+    for (int b = 0; b < 2 * NS; b++) srcs[b] = -1;
+#pragma unroll
+    for (int b = 0; b < NS; b++)
+      while (c[b] != NONE && c[b] + ph[b] == w) {  // at most twice: (c, +1) and (c + 1, +0)
+        srcs[2 * b + ph[b]] = (int32_t)p[b];
+        if (ph[b] == 0) {
+          ph[b] = 1;
+        } else {
+          ph[b] = 0;
+          p[b]++;
+          c[b] = p[b] < e[b] ? cidx[p[b]] : NONE;
+        }
+      }
+    if (write) vtx_store(J, L + 1, o++, w, srcs, 2 * NS);
+    count++;
+  }
+  return count;
+}
+
+// Depth L + 1 under every vertex node of depth L, one wave (one workgroup of
+// 64) per node.  The node's children lie in the label window [lo, hi] (lo the
+// smallest first label of its source runs, hi the largest last label + 1);
+// when the window spans at most VTX_WORDS 64-bit words, each source run is
+// set as a bitmap over the window in LDS (run b: bit x for label lo + x), the
+// children are the set bits of U = OR_b (B_b | B_b << 1), and the source of
+// child w at (b, d) is the run's element of label w - d, whose index is its
+// rank in B_b.  Lane j owns word j.  Wider windows take the sequential merge
+// on lane 0.
+constexpr int VTX_WORDS = 64;
+
+template <int L>
+__global__ __launch_bounds__(64) void k_vtx_merge(VtxJob J, int write, const int64_t* __restrict__ off) {
+  constexpr int NS = 1 << (L + 1);
+  __shared__ uint64_t bits[NS][VTX_WORDS];
+  __shared__ int64_t rank[NS][VTX_WORDS];  // set bits of B_b in the words before word j
+  const int64_t v = blockIdx.x;
+  const int64_t nv = J.vn[L];
+  if (v >= nv) return;  // uniform: one wave per workgroup
+  const int lane = threadIdx.x;
+  const int32_t* cidx = J.S.idx[L + 1];
+  const int32_t* sptr = J.S.ptr[L];
+  int64_t p[NS], e[NS];
+  int32_t lo = 0x7fffffff, hi = -1;
+#pragma unroll
+  for (int b = 0; b < NS; b++) {
+    const int32_t s = J.src[L][v * NS + b];
+    p[b] = s >= 0 ? sptr[s] : 0;
+    e[b] = s >= 0 ? sptr[s + 1] : 0;
+    if (p[b] < e[b]) {
+      lo = min(lo, cidx[p[b]]);
+      hi = max(hi, cidx[e[b] - 1] + 1);
+    }
+  }
+  const int64_t o0 = write ? off[v] : 0;
+  if (write) {
+    if (lane == 0) J.vptr[L][v] = (int32_t)o0;
+    if (lane == 0 && v == nv - 1) J.vptr[L][nv] = (int32_t)off[nv];
+  }
+  const int64_t width = (int64_t)hi - lo + 1;
+  if (width > 64 * VTX_WORDS) {
+    if (lane == 0) {
+      const int64_t n = vtx_merge_node<L>(J, v, write != 0, o0);
+      if (!write) J.cnt[v] = n;
+    }
+    return;
+  }
+  const int nw = (int)((width + 63) / 64);
+#pragma unroll
+  for (int b = 0; b < NS; b++) bits[b][lane] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NS; b++)
+    for (int64_t i = p[b] + lane; i < e[b]; i += 64) {
+      const int x = cidx[i] - lo;
+      atomicOr(reinterpret_cast<unsigned long long*>(&bits[b][x >> 6]), 1ull << (x & 63));
+    }
+  __syncthreads();
+  uint64_t u = 0;
+  if (lane < nw) {
+#pragma unroll
+    for (int b = 0; b < NS; b++) u |= bits[b][lane] | (bits[b][lane] << 1) | (lane > 0 ? bits[b][lane - 1] >> 63 : 0);
+  }
+  const int64_t cnt = __popcll(u);
+  if (!write) {
+    int64_t tot = cnt;
+    for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, 64);
+    if (lane == 0) J.cnt[v] = tot;
+    return;
+  }
+  // exclusive prefix over the lanes: of the children, and of each run's bits
+  auto excl_scan = [&](int64_t x) {
+    int64_t inc = x;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t y = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += y;
+    }
+    return inc - x;
+  };
+  __shared__ uint64_t uw[VTX_WORDS];
+  __shared__ int32_t upre[VTX_WORDS + 1];
+  const int64_t pre = excl_scan(cnt);
+  uw[lane] = u;
+  upre[lane] = (int32_t)pre;
+  if (lane == 63) upre[64] = (int32_t)(pre + cnt);
+#pragma unroll
+  for (int b = 0; b < NS; b++) rank[b][lane] = excl_scan(__popcll(bits[b][lane]));
+  __syncthreads();
+  // child t of the node goes to lane t mod 64 (so that lanes share the
+  // work and neighbouring lanes store neighbouring entries): its word is the
+  // last j with upre[j] <= t, its bit the (t - upre[j])-th set bit of word j
+  const int total = upre[64];
+  for (int t = lane; t < total; t += 64) {
+    int j = 0;
+    for (int step = 32; step >= 1; step >>= 1)
+      if (upre[j + step] <= t) j += step;
+    uint64_t wv = uw[j];
+    int r = t - upre[j], x = 0;
+    for (int sh = 32; sh >= 1; sh >>= 1) {
+      const int c = __popcll(wv & ((1ull << sh) - 1));
+      if (r >= c) {
+        r -= c;
+        wv >>= sh;
+        x += sh;
+      }
+    }
+    const int pos = j * 64 + x;  // window position of the child
+    const int64_t o = o0 + t;
+    int32_t srcs[2 * NS];
+#pragma unroll
+    for (int b = 0; b < NS; b++)
+#pragma unroll
+      for (int d = 0; d < 2; d++) {
+        const int y = pos - d;  // window position of label w - d
+        int32_t sv = -1;
+        if (y >= 0) {
+          const uint64_t wb = bits[b][y >> 6];
+          if ((wb >> (y & 63)) & 1)
+            sv = (int32_t)(p[b] + rank[b][y >> 6] + __popcll(wb & ((1ull << (y & 63)) - 1)));
+        }
+        srcs[2 * b + d] = sv;
+      }
+    vtx_store(J, L + 1, o, lo + pos, srcs, 2 * NS);
+  }
+}
+
+struct VtxCountLoader {
+  const int64_t* c;
+  __device__ int64_t operator()(int64_t i) const { return c[i]; }
+};
 
 // incl[p * nleaf + b] = 1 when some vertex of box b has a lower bound > 0 and
 // another an upper bound < 0 for F_p (NaN bounds certify nothing).
-__global__ void k_c1_flags(int k, int np, int64_t nleaf, const int32_t* __restrict__ labels, CsfView V,
+__global__ void k_c1_flags(int k, int np, int64_t nleaf, const int32_t* __restrict__ corner, int64_t nv,
                            const double* __restrict__ vlo, const double* __restrict__ vhi,
                            uint8_t* __restrict__ incl) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nleaf) return;
-  const int64_t nv = V.n[k - 1];
+  const int nc = 1 << k;
   uint64_t pos = 0, neg = 0;
-  for (int m = 0; m < (1 << k); m++) {
-    int32_t tup[VX_KMAX];
-    for (int j = 0; j < k; j++) tup[j] = labels[b * k + j] + ((m >> (k - 1 - j)) & 1);
-    const int64_t q = csf_find(V, k, tup);
-    if (q < 0) continue;
+  for (int m = 0; m < nc; m++) {
+    const int64_t q = corner[(int64_t)m * nleaf + b];
     for (int p = 0; p < np; p++) {
       if (vlo[(int64_t)p * nv + q] > 0.0) pos |= 1ull << p;
       if (vhi[(int64_t)p * nv + q] < 0.0) neg |= 1ull << p;
@@ -1097,39 +1303,52 @@ __global__ void k_c1_flags(int k, int np, int64_t nleaf, const int32_t* __restri
 }
 
 struct InclPlan {
-  int32_t* labels = nullptr;
-  int32_t* tuples = nullptr;
+  VtxJob J;
   vx_csf V;
-  char* build_ws = nullptr;
-  size_t build_bytes = 0;
+  int64_t* off = nullptr;
+  int64_t* tiles = nullptr;
+  int64_t cmax = 1;
   double* vlo = nullptr;
   double* vhi = nullptr;
   char* eval_ws = nullptr;
   size_t eval_bytes = 0;
 };
 
-// Vertex CSF capacities: depth l holds at most min(tuples, (2^level + 1)^(l+1)) nodes.
+// Vertex CSF capacities: depth l holds at most min((2^level + 1)^(l+1),
+// 2^(l+1) N_l) nodes (each box node is a source of at most 2^(l+1) vertex
+// nodes, each vertex node has a source).
 static void plan_inclusion(Arena& A, InclPlan& I, const vx_poly* P, int np, const vx_csf* S) {
   const int k = S->k;
-  const int64_t n = S->n[k - 1], nt = n << k;
+  const int64_t n = S->n[k - 1];
   const int64_t side = ((int64_t)1 << S->level) + 1;
   memset(&I.V, 0, sizeof I.V);
+  memset(&I.J, 0, sizeof I.J);
   I.V.k = k;
   I.V.level = S->level;
+  I.J.k = k;
   int64_t grid = 1;
+  I.cmax = 1;
   for (int l = 0; l < k; l++) {
-    grid = grid > nt ? nt : grid * side;
-    I.V.cap[l] = grid < nt ? grid : nt;
+    grid = grid > ((int64_t)1 << 40) ? grid : grid * side;
+    const int64_t b = S->n[l] << (l + 1);
+    I.V.cap[l] = grid < b ? grid : b;
     I.V.n[l] = I.V.cap[l];
+    I.cmax = I.V.cap[l] > I.cmax ? I.V.cap[l] : I.cmax;
   }
-  I.labels = A.take<int32_t>((size_t)n * k);
-  I.tuples = A.take<int32_t>((size_t)nt * k);
   for (int l = 0; l < k; l++) {
-    I.V.idx[l] = A.take<int32_t>((size_t)I.V.cap[l]);
-    if (l + 1 < k) I.V.ptr[l] = A.take<int32_t>((size_t)I.V.cap[l] + 1);
+    I.V.idx[l] = A.take<int32_t>((size_t)I.V.cap[l] + 1);
+    if (l + 1 < k) {
+      I.V.ptr[l] = A.take<int32_t>((size_t)I.V.cap[l] + 1);
+      I.J.src[l] = A.take<int32_t>((size_t)I.V.cap[l] << (l + 1));
+    }
+    I.J.vidx[l] = I.V.idx[l];
+    I.J.vptr[l] = I.V.ptr[l];
   }
-  I.build_bytes = build_workspace_bytes(k, nt);
-  I.build_ws = A.take<char>(I.build_bytes);
+  I.J.corner = A.take<int32_t>((size_t)(n > 0 ? n : 1) << k);
+  I.J.cnt = A.take<int64_t>((size_t)I.cmax + 1);
+  I.J.vn = A.take<int64_t>(VX_KMAX);
+  I.off = A.take<int64_t>((size_t)I.cmax + 1);
+  I.tiles = A.take<int64_t>(scan_tiles(I.cmax));
   I.vlo = A.take<double>((size_t)np * I.V.cap[k - 1]);
   I.vhi = A.take<double>((size_t)np * I.V.cap[k - 1]);
   // the vertex counts are known only after the build: plan for their bounds
@@ -1149,9 +1368,7 @@ int inclusion_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom,
   const int k = S->k;
   const int64_t n = S->n[k - 1];
   if (n == 0) return VX_OK;
-  if ((int64_t)k * (S->level + 1) > 62)
-    VX_FAIL(VX_EUNSUPPORTED, "inclusion test: k * (level + 1) = %d exceeds the 62-bit vertex key",
-            k * (S->level + 1));
+  if (S->level > 29) VX_FAIL(VX_EUNSUPPORTED, "inclusion test: level %d exceeds the int32 vertex labels", S->level);
   Arena A;
   A.base = reinterpret_cast<char*>(ws);
   A.size = ws_bytes;
@@ -1159,33 +1376,47 @@ int inclusion_impl(const vx_poly* P, int np, const vx_csf* S, const double* dom,
   plan_inclusion(A, I, P, np, S);
   if (A.overflow) VX_FAIL(VX_ECAPACITY, "inclusion test: workspace of %zu bytes is too small", ws_bytes);
   const int pr = prof_start("inclusion", (double)n, st);
-  CsfView cv;
-  memset(&cv, 0, sizeof cv);
+  VtxJob& J = I.J;
+  J.nbox = n;
   for (int l = 0; l < k; l++) {
-    cv.idx[l] = S->idx[l];
-    cv.ptr[l] = S->ptr[l];
-    cv.n[l] = S->n[l];
+    J.S.idx[l] = S->idx[l];
+    J.S.ptr[l] = S->ptr[l];
+    J.S.n[l] = S->n[l];
   }
-  hipLaunchKernelGGL(k_leaf_labels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, cv, I.labels);
-  VX_CHECK_LAUNCH("k_leaf_labels");
-  const int64_t nt = n << k;
-  hipLaunchKernelGGL(k_vertex_tuples, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, k, n,
-                     (const int32_t*)I.labels, I.tuples);
-  VX_CHECK_LAUNCH("k_vertex_tuples");
-  // vertex labels run to 2^level: one more key bit per axis than the cells
-  int rc;
-  if ((rc = build_impl(k, S->level + 1, I.tuples, nt, &I.V, nullptr, I.build_ws, I.build_bytes, st))) return rc;
+  // depth 0
+  const int64_t n0 = S->n[0];
+  hipLaunchKernelGGL(k_vtx0, dim3((unsigned)((n0 + 255) / 256)), dim3(256), 0, st, J, 0, (const int64_t*)nullptr);
+  scan_exclusive(VtxCountLoader{J.cnt}, (const int64_t*)nullptr, n0, I.off, J.vn, I.tiles, st);
+  hipLaunchKernelGGL(k_vtx0, dim3((unsigned)((n0 + 255) / 256)), dim3(256), 0, st, J, 1, (const int64_t*)I.off);
+  VX_CHECK_LAUNCH("k_vtx0");
+  // depths 1 .. k-1; grids from the capacities, counts read on the device
+  for (int l = 0; l + 1 < k; l++) {
+    const dim3 grid((unsigned)I.V.cap[l]);  // one wave per vertex node
+    auto merge = [&](int write) {
+      switch (l) {
+        case 0: hipLaunchKernelGGL(k_vtx_merge<0>, grid, dim3(64), 0, st, J, write, (const int64_t*)I.off); break;
+        case 1: hipLaunchKernelGGL(k_vtx_merge<1>, grid, dim3(64), 0, st, J, write, (const int64_t*)I.off); break;
+        default: hipLaunchKernelGGL(k_vtx_merge<2>, grid, dim3(64), 0, st, J, write, (const int64_t*)I.off); break;
+      }
+    };
+    merge(0);
+    scan_exclusive(VtxCountLoader{J.cnt}, (const int64_t*)(J.vn + l), I.V.cap[l], I.off, J.vn + l + 1, I.tiles, st);
+    merge(1);
+    VX_CHECK_LAUNCH("k_vtx_merge");
+  }
+  int64_t vn[VX_KMAX] = {0, 0, 0, 0};
+  VX_HIP(hipMemcpyAsync(vn, J.vn, sizeof(int64_t) * k, hipMemcpyDeviceToHost, st));
+  VX_HIP(hipStreamSynchronize(st));
+  for (int l = 0; l < k; l++) {
+    if (vn[l] > I.V.cap[l]) VX_FAIL(VX_EHIP, "inclusion test: vertex depth %d holds %lld nodes, over its bound %lld", l,
+                                    (long long)vn[l], (long long)I.V.cap[l]);
+    I.V.n[l] = vn[l];
+  }
   I.V.level = S->level;
+  int rc;
   if ((rc = eval_level_impl(P, np, &I.V, dom, I.vlo, I.vhi, nullptr, I.eval_ws, I.eval_bytes, st, 2))) return rc;
-  CsfView vv;
-  memset(&vv, 0, sizeof vv);
-  for (int l = 0; l < k; l++) {
-    vv.idx[l] = I.V.idx[l];
-    vv.ptr[l] = I.V.ptr[l];
-    vv.n[l] = I.V.n[l];
-  }
   hipLaunchKernelGGL(k_c1_flags, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k, np, n,
-                     (const int32_t*)I.labels, vv, (const double*)I.vlo, (const double*)I.vhi, incl);
+                     (const int32_t*)J.corner, vn[k - 1], (const double*)I.vlo, (const double*)I.vhi, incl);
   VX_CHECK_LAUNCH("k_c1_flags");
   prof_stop(pr, st);
   return VX_OK;

@@ -5,9 +5,10 @@ at the two extreme vertices of the linear part).
 Bar: the certification flags (per polynomial and box) equal the oracle's
 exactly.  Cases: every level of `tiny`, the `surface` kept set at level 6
 (thousands of boxes, several tiles and ragged tails), random k = 1..4 with
-two polynomials, interval coefficients and non-dyadic domains, a plane on a
-grid plane (zeros at vertices certify nothing), the sphere, level 0 and an
-empty set; at full size, the surface's final kept set (level 9) with a seeded
+two polynomials, interval coefficients and non-dyadic domains, level-14 box
+sets whose vertex nodes have narrow and wide label windows (the two merge
+paths of the vertex CSF), a plane on a grid plane (zeros at vertices certify
+nothing), the sphere, level 0 and an empty set; at full size, the surface's final kept set (level 9) with a seeded
 sample re-checked by the oracle on a CSF of the sample alone (a box's flag
 depends on its own vertices only).
 """
@@ -82,6 +83,26 @@ def test_random_k_odd_domain_interval_coefficients(vx, k, d, level, method):
     boxes = rng.integers(0, 1 << level, size=(600, k))
     S = orc.csf_from_boxes(boxes, level)
     _check(vx, polys, S, dom, f"k{k}", method)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_vertex_csf_wide_label_windows(vx, k):
+    """The vertex CSF is merged per vertex node from bitmaps over the label
+    window of its children when that window spans at most 4096 labels, and
+    by a sequential merge otherwise: at level 14, boxes spread over the whole
+    axis take the second path, a clustered set beside them the first."""
+    rng = np.random.default_rng(900 + k)
+    level = 14
+    spread = rng.integers(0, 1 << level, size=(400, k))
+    cluster = rng.integers(0, 64, size=(400, k)) + (1 << (level - 1))
+    # boxes cut by the plane x1 = 0.5 + 2^-20 (inside cells of x1 label 3 * 2^(level-2))
+    cut = rng.integers(0, 1 << level, size=(300, k))
+    cut[:, 0] = 3 << (level - 2)
+    S = orc.csf_from_boxes(np.concatenate([spread, cluster, cut]), level)
+    dom = np.array([-1.0, 1.0] * k)
+    c = synth.small_random(k, 5, seed=920 + k, npolys=2)
+    plane = synth.monomial_poly(k, 1, {tuple([1] + [0] * (k - 1)): 1.0, tuple([0] * k): -(0.5 + 2.0 ** -20)})
+    assert _check(vx, [c[0], c[1], plane], S, dom, f"wide windows k{k}") > 0
 
 
 @pytest.mark.parametrize("method", METHODS)
