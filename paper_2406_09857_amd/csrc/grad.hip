@@ -133,20 +133,24 @@ __device__ __forceinline__ int64_t after_d(double x) {
   return z;
 }
 
-// Value and gradient of one polynomial at the lane's point.  `grad` may be
-// skipped (GRAD = false) for value-only evaluation.
-template <int K, bool GRAD>
-__device__ void point_eval(const cdbl_t* __restrict__ S, int d, const double (&x)[VX_KMAX], double& val,
-                           double (&grad)[VX_KMAX]) {
-  // acc[s]: Horner accumulator of depth s (s = 0 is the x1 chain);
-  // der[s][j]: its derivative with respect to x_j (j <= s).
-  double acc[K], der[K][K];
+// Value and gradient of one polynomial at the lane's PP points (each
+// coefficient load serves all of them; every point's arithmetic is the same,
+// in the same order, whatever PP).  `grad` may be skipped (GRAD = false) for
+// value-only evaluation.
+template <int K, bool GRAD, int PP>
+__device__ void point_eval(const cdbl_t* __restrict__ S, int d, const double (&x)[PP][VX_KMAX], double (&val)[PP],
+                           double (&grad)[PP][VX_KMAX]) {
+  // acc[q][s]: Horner accumulator of depth s (s = 0 is the x1 chain) of point q;
+  // der[q][s][j]: its derivative with respect to x_j (j <= s).
+  double acc[PP][K], der[PP][K][K];
 #pragma unroll
-  for (int s = 0; s < K; s++) {
-    acc[s] = 0.0;
+  for (int q = 0; q < PP; q++)
 #pragma unroll
-    for (int j = 0; j < K; j++) der[s][j] = 0.0;
-  }
+    for (int s = 0; s < K; s++) {
+      acc[q][s] = 0.0;
+#pragma unroll
+      for (int j = 0; j < K; j++) der[q][s][j] = 0.0;
+    }
   double A[SG];
   int64_t g = 0;
 #pragma unroll
@@ -155,18 +159,23 @@ __device__ void point_eval(const cdbl_t* __restrict__ S, int d, const double (&x
   int t[VX_KMAX] = {0, 0, 0, 0};
   auto chain = [&](int L) {  // one x1 chain of L entries, padded
     const int ng = (L + SG - 1) / SG;
-    acc[0] = 0.0;
-    if (GRAD) der[0][0] = 0.0;
+#pragma unroll
+    for (int q = 0; q < PP; q++) {
+      acc[q][0] = 0.0;
+      if (GRAD) der[q][0][0] = 0.0;
+    }
     for (int gg = 0; gg < ng; gg++) {
       const int64_t z = after_d(A[0]);
       double B[SG];
 #pragma unroll
       for (int e = 0; e < SG; e++) B[e] = S[(g + 1) * SG + z + e];
 #pragma unroll
-      for (int e = 0; e < SG; e++) {
-        if (GRAD) der[0][0] = der[0][0] * x[0] + acc[0];
-        acc[0] = acc[0] * x[0] + A[e];
-      }
+      for (int e = 0; e < SG; e++)
+#pragma unroll
+        for (int q = 0; q < PP; q++) {
+          if (GRAD) der[q][0][0] = der[q][0][0] * x[q][0] + acc[q][0];
+          acc[q][0] = acc[q][0] * x[q][0] + A[e];
+        }
 #pragma unroll
       for (int e = 0; e < SG; e++) A[e] = B[e];
       g++;
@@ -174,20 +183,26 @@ __device__ void point_eval(const cdbl_t* __restrict__ S, int d, const double (&x
   };
   // fold accumulator s-1 into s (Horner step in x_s)
   auto fold = [&](int s) {
-    if (GRAD) {
 #pragma unroll
-      for (int j = 0; j < K; j++) {
-        if (j < s) der[s][j] = der[s][j] * x[s] + der[s - 1][j];
-        else if (j == s) der[s][j] = der[s][j] * x[s] + acc[s];
+    for (int q = 0; q < PP; q++) {
+      if (GRAD) {
+#pragma unroll
+        for (int j = 0; j < K; j++) {
+          if (j < s) der[q][s][j] = der[q][s][j] * x[q][s] + der[q][s - 1][j];
+          else if (j == s) der[q][s][j] = der[q][s][j] * x[q][s] + acc[q][s];
+        }
       }
+      acc[q][s] = acc[q][s] * x[q][s] + acc[q][s - 1];
     }
-    acc[s] = acc[s] * x[s] + acc[s - 1];
   };
   auto reset = [&](int s) {
-    acc[s] = 0.0;
-    if (GRAD) {
 #pragma unroll
-      for (int j = 0; j < K; j++) der[s][j] = 0.0;
+    for (int q = 0; q < PP; q++) {
+      acc[q][s] = 0.0;
+      if (GRAD) {
+#pragma unroll
+        for (int j = 0; j < K; j++) der[q][s][j] = 0.0;
+      }
     }
   };
   if (K == 1) {
@@ -220,10 +235,13 @@ __device__ void point_eval(const cdbl_t* __restrict__ S, int d, const double (&x
       fold(3);
     }
   }
-  val = acc[K - 1];
-  if (GRAD) {
 #pragma unroll
-    for (int j = 0; j < K; j++) grad[j] = der[K - 1][j];
+  for (int q = 0; q < PP; q++) {
+    val[q] = acc[q][K - 1];
+    if (GRAD) {
+#pragma unroll
+      for (int j = 0; j < K; j++) grad[q][j] = der[q][K - 1][j];
+    }
   }
 }
 
@@ -232,92 +250,122 @@ struct StreamSet {
   int d[PMAX_GRAD];
 };
 
+// Points per lane of the per-point kernels (point q of the lane is point
+// blockIdx.x * 64 * PPL + q * 64 + lane).
+constexpr int PPL = 2;
+
 template <int K, bool GRAD>
 __global__ __launch_bounds__(64) void k_point_eval(StreamSet ss, int np, const double* __restrict__ x, int64_t n,
                                                    double* __restrict__ f, double* __restrict__ jac) {
   const int p = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const bool valid = i < n;
-  double xi[VX_KMAX] = {0, 0, 0, 0};
+  const int64_t i0 = (int64_t)blockIdx.x * 64 * PPL + threadIdx.x;
+  double xi[PPL][VX_KMAX] = {};
 #pragma unroll
-  for (int j = 0; j < K; j++) xi[j] = valid ? x[i * K + j] : 0.0;
-  double v, gr[VX_KMAX];
-  point_eval<K, GRAD>((const cdbl_t*)ss.s[p], ss.d[p], xi, v, gr);
-  if (!valid) return;
-  f[p * n + i] = v;
-  if (GRAD && jac) {
+  for (int q = 0; q < PPL; q++) {
+    const int64_t i = i0 + q * 64;
 #pragma unroll
-    for (int j = 0; j < K; j++) jac[(i * np + p) * K + j] = gr[j];
+    for (int j = 0; j < K; j++) xi[q][j] = i < n ? x[i * K + j] : 0.0;
+  }
+  double v[PPL], gr[PPL][VX_KMAX];
+  point_eval<K, GRAD, PPL>((const cdbl_t*)ss.s[p], ss.d[p], xi, v, gr);
+#pragma unroll
+  for (int q = 0; q < PPL; q++) {
+    const int64_t i = i0 + q * 64;
+    if (i >= n) continue;
+    f[p * n + i] = v[q];
+    if (GRAD && jac) {
+#pragma unroll
+      for (int j = 0; j < K; j++) jac[(i * np + p) * K + j] = gr[q][j];
+    }
   }
 }
 
 // Newton projection: x <- x - J^T (J J^T)^{-1} F, J the np x K Jacobian
 // (minimum-norm step in the span of the gradients).
+// Newton step of one point from its values F and Jacobian J (np x K).
+template <int K>
+__device__ __forceinline__ void newton_update(int np, const double (&F)[PMAX_GRAD],
+                                              const double (&J)[PMAX_GRAD][VX_KMAX], double (&xi)[VX_KMAX]) {
+  // M = J J^T (np x np), solve M y = F by elimination with partial pivoting
+  double M[PMAX_GRAD][PMAX_GRAD + 1];
+  for (int a = 0; a < np; a++) {
+    for (int b = 0; b < np; b++) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < K; j++) s += J[a][j] * J[b][j];
+      M[a][b] = s;
+    }
+    M[a][np] = F[a];
+  }
+  bool ok = true;
+  for (int c = 0; c < np && ok; c++) {
+    int piv = c;
+    for (int r = c + 1; r < np; r++)
+      if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+    if (!(fabs(M[piv][c]) > 1e-300)) { ok = false; break; }
+    if (piv != c)
+      for (int q = 0; q <= np; q++) {
+        const double tmp = M[c][q];
+        M[c][q] = M[piv][q];
+        M[piv][q] = tmp;
+      }
+    for (int r = c + 1; r < np; r++) {
+      const double fct = M[r][c] / M[c][c];
+      for (int q = c; q <= np; q++) M[r][q] -= fct * M[c][q];
+    }
+  }
+  if (ok) {
+    double y[PMAX_GRAD];
+    for (int r = np - 1; r >= 0; r--) {
+      double s = M[r][np];
+      for (int q = r + 1; q < np; q++) s -= M[r][q] * y[q];
+      y[r] = s / M[r][r];
+    }
+#pragma unroll
+    for (int j = 0; j < K; j++) {
+      double s = 0.0;
+      for (int p = 0; p < np; p++) s += J[p][j] * y[p];
+      xi[j] -= s;
+    }
+  }
+}
+
 template <int K>
 __global__ __launch_bounds__(64) void k_newton(StreamSet ss, int np, double* __restrict__ x, int64_t n, int steps,
                                                double* __restrict__ f_out) {
-  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const bool valid = i < n;
-  double xi[VX_KMAX] = {0, 0, 0, 0};
+  const int64_t i0 = (int64_t)blockIdx.x * 64 * PPL + threadIdx.x;
+  double xi[PPL][VX_KMAX] = {};
 #pragma unroll
-  for (int j = 0; j < K; j++) xi[j] = valid ? x[i * K + j] : 0.0;
-  double F[PMAX_GRAD], J[PMAX_GRAD][VX_KMAX];
+  for (int q = 0; q < PPL; q++) {
+    const int64_t i = i0 + q * 64;
+#pragma unroll
+    for (int j = 0; j < K; j++) xi[q][j] = i < n ? x[i * K + j] : 0.0;
+  }
+  double F[PPL][PMAX_GRAD], J[PPL][PMAX_GRAD][VX_KMAX];
   for (int it = 0; it <= steps; it++) {
     for (int p = 0; p < np; p++) {
-      double gr[VX_KMAX];
-      point_eval<K, true>((const cdbl_t*)ss.s[p], ss.d[p], xi, F[p], gr);
+      double v[PPL], gr[PPL][VX_KMAX];
+      point_eval<K, true, PPL>((const cdbl_t*)ss.s[p], ss.d[p], xi, v, gr);
 #pragma unroll
-      for (int j = 0; j < K; j++) J[p][j] = gr[j];
+      for (int q = 0; q < PPL; q++) {
+        F[q][p] = v[q];
+#pragma unroll
+        for (int j = 0; j < K; j++) J[q][p][j] = gr[q][j];
+      }
     }
     if (it == steps) break;
-    // M = J J^T (np x np), solve M y = F by elimination with partial pivoting
-    double M[PMAX_GRAD][PMAX_GRAD + 1];
-    for (int a = 0; a < np; a++) {
-      for (int b = 0; b < np; b++) {
-        double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < K; j++) s += J[a][j] * J[b][j];
-        M[a][b] = s;
-      }
-      M[a][np] = F[a];
-    }
-    bool ok = true;
-    for (int c = 0; c < np && ok; c++) {
-      int piv = c;
-      for (int r = c + 1; r < np; r++)
-        if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
-      if (!(fabs(M[piv][c]) > 1e-300)) { ok = false; break; }
-      if (piv != c)
-        for (int q = 0; q <= np; q++) {
-          const double tmp = M[c][q];
-          M[c][q] = M[piv][q];
-          M[piv][q] = tmp;
-        }
-      for (int r = c + 1; r < np; r++) {
-        const double fct = M[r][c] / M[c][c];
-        for (int q = c; q <= np; q++) M[r][q] -= fct * M[c][q];
-      }
-    }
-    if (ok) {
-      double y[PMAX_GRAD];
-      for (int r = np - 1; r >= 0; r--) {
-        double s = M[r][np];
-        for (int q = r + 1; q < np; q++) s -= M[r][q] * y[q];
-        y[r] = s / M[r][r];
-      }
-#pragma unroll
-      for (int j = 0; j < K; j++) {
-        double s = 0.0;
-        for (int p = 0; p < np; p++) s += J[p][j] * y[p];
-        xi[j] -= s;
-      }
-    }
+    for (int q = 0; q < PPL; q++) newton_update<K>(np, F[q], J[q], xi[q]);
   }
-  if (!valid) return;
 #pragma unroll
-  for (int j = 0; j < K; j++) x[i * K + j] = xi[j];
-  if (f_out)
-    for (int p = 0; p < np; p++) f_out[p * n + i] = F[p];
+  for (int q = 0; q < PPL; q++) {
+    const int64_t i = i0 + q * 64;
+    if (i >= n) continue;
+#pragma unroll
+    for (int j = 0; j < K; j++) x[i * K + j] = xi[q][j];
+    if (f_out)
+      for (int p = 0; p < np; p++) f_out[p * n + i] = F[q][p];
+  }
 }
 
 // Centres of the leaves of a CSF (n x k, RN).
@@ -808,7 +856,7 @@ int grad_impl(const vx_poly* P, int np, const double* x, int64_t n, double* f, d
     if ((rc = grid_forward(G, Gp, P, np, grid, dom, f, jac, st))) return rc;
   } else if (n > 0 && (f || jac)) {
     if (!f) f = f_tmp;
-    dim3 grid3((unsigned)((n + 63) / 64), (unsigned)np);
+    dim3 grid3((unsigned)((n + 64 * PPL - 1) / (64 * PPL)), (unsigned)np);
     const bool gradf = jac != nullptr;
 #define VX_PE(KK)                                                                                       \
   if (gradf)                                                                                            \
@@ -875,7 +923,7 @@ int newton_impl(const vx_poly* P, int np, double* x, int64_t n, int steps, doubl
   if ((rc = build_streams(G, P, np, st))) return rc;
   const StreamSet ss = stream_set(G, P, np);
   if (n == 0) return VX_OK;
-  dim3 g1((unsigned)((n + 63) / 64));
+  dim3 g1((unsigned)((n + 64 * PPL - 1) / (64 * PPL)));
   switch (k) {
     case 1: hipLaunchKernelGGL(k_newton<1>, g1, dim3(64), 0, st, ss, np, x, n, steps, f); break;
     case 2: hipLaunchKernelGGL(k_newton<2>, g1, dim3(64), 0, st, ss, np, x, n, steps, f); break;
