@@ -708,6 +708,10 @@ static int run_loop(const vx_poly* P, int32_t np, const double* dom, int32_t dep
     const size_t o_lo = carve(sizeof(double) * (size_t)np * nleaf);
     const size_t o_hi = carve(sizeof(double) * (size_t)np * nleaf);
     const size_t o_keep = carve(nleaf > 0 ? (size_t)nleaf : 1);
+    // survival flags of depth k-2, recorded by the leaf when nothing changes
+    // keep after it (the plain loop)
+    const bool leaf_alive = k >= 2 && !mv && !(incl_mode && level >= incl_from) && !(early_on && level >= early_from);
+    const size_t o_alive = leaf_alive ? carve((size_t)(S.n[k - 2] > 0 ? S.n[k - 2] : 1)) : 0;
     const size_t o_cnt = carve(sizeof(int64_t) * 2 * VX_KMAX);
     int64_t kcap[VX_KMAX] = {1, 1, 1, 1};
     for (int l = 0; l < k; l++) kcap[l] = S.n[l] > 0 ? S.n[l] : 1;
@@ -760,6 +764,7 @@ static int run_loop(const vx_poly* P, int32_t np, const double* dom, int32_t dep
     double* lo = reinterpret_cast<double*>(mid_base + o_lo);
     double* hi = reinterpret_cast<double*>(mid_base + o_hi);
     uint8_t* keep = reinterpret_cast<uint8_t*>(mid_base + o_keep);
+    uint8_t* alive = leaf_alive ? reinterpret_cast<uint8_t*>(mid_base + o_alive) : nullptr;
     int64_t* d_counts = counts_dev;
     (void)o_cnt;
     vx_csf K;
@@ -774,7 +779,8 @@ static int run_loop(const vx_poly* P, int32_t np, const double* dom, int32_t dep
     vx_csf cur = S;
     int64_t steps = 0;
     if (!early) {
-      if ((rc = eval_level_prepared(Q, &S, dom, lo, hi, keep, scratch, scratch_bytes, st, P))) return rc;
+      if ((rc = eval_level_prepared(Q, &S, dom, lo, hi, keep, scratch, scratch_bytes, st, P, 0, nullptr, alive)))
+        return rc;
       steps = theorem1_steps(P, np, &S);
     }
     for (int p = 0; early; p++) {
@@ -825,7 +831,7 @@ static int run_loop(const vx_poly* P, int32_t np, const double* dom, int32_t dep
     if (times) VX_HIP(hipEventRecord(ev[1], st));
     // the filter publishes its counts (and the flag) as soon as they are known
     if ((rc = filter_impl(&cur, cont, &K, last ? nullptr : &N, d_counts, scratch, scratch_bytes, st,
-                          counts_dev + 2 * VX_KMAX, (int64_t)level + 1)))
+                          counts_dev + 2 * VX_KMAX, (int64_t)level + 1, alive)))
       return rc;
     if (times) VX_HIP(hipEventRecord(ev[2], st));
     if ((rc = finish_times())) return rc;  // the previous level's times

@@ -893,12 +893,15 @@ constexpr int LEAF_R = 4;
 
 // The large-level form (PF = 4) is held to 80 VGPRs (6 waves per SIMD
 // instead of 4; it fits without spilling); the others keep their registers.
+// alive (may be null; the last launch over the polynomials only): set to 1
+// for the parent of every box that keeps keep != 0 (cleared beforehand by the
+// segment kernels); lanes of one parent may store concurrently, all the value 1.
 template <bool SPLITP, int PF, int LR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF == 4 ? 6 : 1, 8))) void k_leaf(PolySet ps, RowSet rows, const int4* __restrict__ seg,
                                               const int64_t* __restrict__ nseg, const int32_t* __restrict__ labels,
                                               int64_t nleaf, AxisGrid g, double* __restrict__ lo_out,
                                               double* __restrict__ hi_out, uint8_t* __restrict__ keep, int first,
-                                              int p2) {
+                                              int p2, uint8_t* __restrict__ alive) {
   round_up_mode();
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t sid = SPLITP ? q / p2 : q;
@@ -952,11 +955,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PF == 4 ? 6
     if (pl != 0) return;
   }
   if (keep) {
+    bool any = false;
 #pragma unroll
     for (int i = 0; i < LR; i++) {
       const bool ex = (excl >> i) & 1;
-      if (i < cnt) keep[begin + i] = first ? (ex ? 0 : 1) : (ex ? 0 : keep[begin + i]);
+      if (i < cnt) {
+        const uint8_t kv = first ? (ex ? 0 : 1) : (ex ? 0 : keep[begin + i]);
+        keep[begin + i] = kv;
+        any = any || kv != 0;
+      }
     }
+    if (alive && any) alive[par] = 1;
   }
 }
 
@@ -1060,6 +1069,7 @@ struct SegJob {
   int64_t* ttot[2];
   int32_t* tnode[2];
   int32_t* tpar[2];
+  uint8_t* alive;  // cleared per parent of the leaf depth (may be null)
 };
 
 constexpr int SMALL_THREADS = 1024;
@@ -1089,6 +1099,7 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_segments_small(int k, SegJob 
     J.bounds[l][2 * p] = ne;
     J.bounds[l][2 * p + 1] = pb;
     J.cnt[l][p] = cdiv(ne - b, Z) + cdiv(pb - ne, Z) + cdiv(e - pb, Z);
+    if (J.alive && l == k - 1) J.alive[p] = 0;
   }
   __syncthreads();
   constexpr int64_t TILE = (int64_t)SMALL_THREADS * SCAN_ITEMS;
@@ -1149,6 +1160,7 @@ __global__ void k_seg_count_all(DepthBlocks D, SegJob J) {
   class_bounds(J.labels[l], b, e, J.g[l], ne, pb);
   J.bounds[l][2 * p] = ne;
   J.bounds[l][2 * p + 1] = pb;
+  if (J.alive && l == D.count - 1) J.alive[p] = 0;
   if (l == J.pl) {
     J.cnt[l][p] = (ne - b) / Z + cdiv(pb - ne, Z) + (e - pb) / Z;
     J.tcnt[0][p] = (ne - b) % Z;
@@ -1493,7 +1505,7 @@ static int launch_narrow(const Prepared& Q, int p0, int pn, int l, const vx_csf*
 }
 
 static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const double* dom, EvalPlan& E,
-                       double* lo, double* hi, uint8_t* keep, hipStream_t st) {
+                       double* lo, double* hi, uint8_t* keep, hipStream_t st, uint8_t* alive) {
   const int k = S->k;
   const int64_t nleaf = S->n[k - 1];
   PolySet ps;
@@ -1524,19 +1536,19 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
     while (p2 < pn) p2 <<= 1;
     const dim3 grid((unsigned)((sp.maxseg * p2 + 255) / 256));
     hipLaunchKernelGGL((k_leaf<true, 8, 1>), grid, dim3(256), 0, st, ps, rs, sg, ns, S->idx[k - 1], nleaf, g, lo_p,
-                       hi_p, keep, first, p2);
+                       hi_p, keep, first, p2, alive);
   } else if (nleaf <= LEAF_SPLIT_NODES && pn > 1) {
     int p2 = 1;
     while (p2 < pn) p2 <<= 1;
     const int64_t threads = sp.maxseg * p2;
     hipLaunchKernelGGL((k_leaf<true, 8, LEAF_R>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, ps, rs,
-                       sg, ns, S->idx[k - 1], nleaf, g, lo_p, hi_p, keep, first, p2);
+                       sg, ns, S->idx[k - 1], nleaf, g, lo_p, hi_p, keep, first, p2, alive);
   } else if (nleaf <= LEAF_SPLIT_NODES) {
     hipLaunchKernelGGL((k_leaf<false, 8, LEAF_R>), grid1, dim3(256), 0, st, ps, rs, sg, ns, S->idx[k - 1], nleaf, g,
-                       lo_p, hi_p, keep, first, 1);
+                       lo_p, hi_p, keep, first, 1, alive);
   } else {
     hipLaunchKernelGGL((k_leaf<false, 4, LEAF_R>), grid1, dim3(256), 0, st, ps, rs, sg, ns, S->idx[k - 1], nleaf, g,
-                       lo_p, hi_p, keep, first, 1);
+                       lo_p, hi_p, keep, first, 1, alive);
   }
   VX_CHECK_LAUNCH("k_leaf");
   prof_stop(pr, st);
@@ -1545,7 +1557,7 @@ static int launch_leaf(const Prepared& Q, int p0, int pn, const vx_csf* S, const
 
 int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
                         void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P, int centre,
-                        const int* axis_modes) {
+                        const int* axis_modes, uint8_t* alive) {
   const int k = S->k;
   const int64_t nleaf = S->n[k - 1];
   if (nleaf == 0) return VX_OK;
@@ -1578,6 +1590,8 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
     J.nseg[l] = sp.nseg;
   }
   J.pl = -1;
+  if (!keep || k < 2) alive = nullptr;
+  J.alive = alive;
   for (int l = 0; l < k; l++)
     if (E.seg[l].pack) {
       const SegPlan& sp = E.seg[l];
@@ -1628,7 +1642,7 @@ int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, d
     if (k >= 2 && (rc = launch_stage1(Q, p0, pn, S, dom, E, st))) return rc;
     for (int l = 1; l + 1 < k; l++)
       if ((rc = launch_narrow(Q, p0, pn, l, S, dom, E, st))) return rc;
-    if ((rc = launch_leaf(Q, p0, pn, S, dom, E, lo, hi, keep, st))) return rc;
+    if ((rc = launch_leaf(Q, p0, pn, S, dom, E, lo, hi, keep, st, p0 + pn == Q.np ? alive : nullptr))) return rc;
   }
   return VX_OK;
 }

@@ -28,9 +28,13 @@ size_t eval_level_bytes_bound(const vx_poly* P, int np, const vx_csf* S);
 // centre = 1 evaluates at the cell centres (degenerate boxes) instead of the
 // cells, 2 at the grid vertices; axis_modes (k entries), if given, sets that
 // choice per axis instead.
+// alive (may be null; S->n[k-2] bytes, k >= 2): the leaf also records, for
+// every depth-(k-2) node, whether one of its boxes keeps keep != 0 (the
+// survival flag the filter would derive from keep), as long as nothing
+// changes keep afterwards.
 int eval_level_prepared(const Prepared& Q, const vx_csf* S, const double* dom, double* lo, double* hi, uint8_t* keep,
                         void* ws, size_t ws_bytes, hipStream_t st, const vx_poly* P, int centre = 0,
-                        const int* axis_modes = nullptr);
+                        const int* axis_modes = nullptr, uint8_t* alive = nullptr);
 // The tables of polynomials idx[0..n) of Q, as a system of their own.
 Prepared prepared_subset(const Prepared& Q, const int* idx, int n);
 
@@ -43,8 +47,11 @@ size_t filter_workspace_bytes(const vx_csf* S);
 // counts, written as soon as they are known; then, when flag is not null,
 // *flag = flag_value after a system-scope fence (the host may spin on it
 // while the rest of the filter still runs).
+// alive (may be null): the survival flags of depth k-2 already known (from
+// eval_level_prepared with the same keep); the filter then skips deriving them.
 int filter_impl(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
-                size_t ws_bytes, hipStream_t st, int64_t* flag = nullptr, int64_t flag_value = 0);
+                size_t ws_bytes, hipStream_t st, int64_t* flag = nullptr, int64_t flag_value = 0,
+                const uint8_t* alive = nullptr);
 
 int init_root_impl(vx_csf* S, hipStream_t st);
 

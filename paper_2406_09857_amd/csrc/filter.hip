@@ -392,18 +392,20 @@ size_t filter_workspace_bytes(const vx_csf* S) {
 }
 
 static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts,
-                       void* ws, size_t ws_bytes, hipStream_t st, int64_t* flag, int64_t flag_value);
+                       void* ws, size_t ws_bytes, hipStream_t st, int64_t* flag, int64_t flag_value,
+                       const uint8_t* alive_km2);
 
 int filter_impl(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts, void* ws,
-                size_t ws_bytes, hipStream_t st, int64_t* flag, int64_t flag_value) {
+                size_t ws_bytes, hipStream_t st, int64_t* flag, int64_t flag_value, const uint8_t* alive) {
   const int ps = prof_start("filter_subdivide", (double)S->n[S->k - 1], st);
-  const int rc = filter_body(S, keep, kept, next, d_counts, ws, ws_bytes, st, flag, flag_value);
+  const int rc = filter_body(S, keep, kept, next, d_counts, ws, ws_bytes, st, flag, flag_value, alive);
   prof_stop(ps, st);
   return rc;
 }
 
 static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_csf* next, int64_t* d_counts,
-                       void* ws, size_t ws_bytes, hipStream_t st, int64_t* flag, int64_t flag_value) {
+                       void* ws, size_t ws_bytes, hipStream_t st, int64_t* flag, int64_t flag_value,
+                       const uint8_t* alive_km2) {
   const int k = S->k;
   Arena A;
   A.base = reinterpret_cast<char*>(ws);
@@ -441,8 +443,13 @@ static int filter_body(const vx_csf* S, const uint8_t* keep, vx_csf* kept, vx_cs
     return VX_OK;
   }
 
-  // Survival flags of the inner depths, leaves up; then every depth's scan.
+  // Survival flags of the inner depths, leaves up (depth k-2 possibly given);
+  // then every depth's scan.
   for (int l = k - 2; l >= 0; l--) {
+    if (l == k - 2 && alive_km2) {
+      F.alive[l] = const_cast<uint8_t*>(alive_km2);
+      continue;
+    }
     const int64_t n = S->n[l];
     hipLaunchKernelGGL(k_alive, dim3((unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1)), dim3(256), 0, st, n,
                        (const int32_t*)S->ptr[l], l + 2 < k ? (const uint8_t*)F.alive[l + 1] : keep, S->n[l + 1],
