@@ -133,8 +133,9 @@ def bench_batched(vx, reps):
 def bench_adjoint(vx, polys, dom, depth, kept):
     """Point evaluation on the final kept-box centres: the forward on the CSF
     grid of centres (amortized) and per point, forward + hand-written backward
-    (Jacobian, dF/dx and dF/dcoef on the grid), 3 Newton steps (per point:
-    the steps move the points off the grid)."""
+    (Jacobian, dF/dx and dF/dcoef on the grid), 3 Newton steps from the
+    centres (the first evaluation on the grid, the later ones per point: the
+    steps move the points off the grid), and the same steps all per point."""
     import torch
     csf = vx.CSF.from_arrays(3, depth, kept["idx"], kept["ptr"])
     x = vx.csf_centres(csf, dom)
@@ -152,13 +153,17 @@ def bench_adjoint(vx, polys, dom, depth, kept):
     fpt_ms = _evt_ms(fwd_pt)
     fb_ms = _evt_ms(fb)
     f0 = fwd()[0].abs().amax(dim=0)
+    xp = x.clone()
+    newton_pt_ms = _evt_ms(lambda: vx.newton_project(polys, xp, steps=3))
     xn = x.clone()
-    newton_ms = _evt_ms(lambda: vx.newton_project(polys, xn, steps=3))
+    newton_ms = _evt_ms(lambda: vx.newton_project(polys, xn, steps=3, grid=(csf, dom)))
+    assert torch.equal(xn, xp)
     f3 = vx.eval_grad(polys, xn, want_jac=False)[0].abs().amax(dim=0)
     return {"points": n, "forward_ms": f_ms, "forward_with_jacobian_ms": fj_ms,
             "forward_per_point_ms": fpt_ms, "grid_speedup_vs_per_point": fpt_ms / f_ms,
             "forward_backward_ms": fb_ms, "backward_over_forward": fb_ms / fj_ms,
-            "newton3_ms": newton_ms, "median_residual_before": float(torch.median(f0)),
+            "newton3_ms": newton_ms, "newton3_per_point_ms": newton_pt_ms,
+            "median_residual_before": float(torch.median(f0)),
             "median_residual_after_3_newton": float(torch.median(f3)),
             "parity": "values bit-identical to the oracle and to the per-point path, Jacobian vs derivative "
                       "polynomials and central differences, dcoef vs long-double sums over the whole grid, "

@@ -488,6 +488,20 @@ int newton_project(const vx_poly* P, int32_t np, double* x, int64_t n, int32_t s
                    size_t ws_bytes, void* stream);
 
 /*
+ * newton_project_grid -- newton_project from the centres of a CSF's leaves
+ * (x, n = grid->n[k-1] points in leaf order, as csf_centres writes them, on
+ * the domain dom): the first evaluation of F and J, at those centres, runs
+ * on the CSF grid by Algorithm 2 (Sec. 1.1, Property 1: each coordinate
+ * paid once per fiber) instead of per point; the later steps leave the grid
+ * and evaluate per point.  Results are bit-identical to newton_project.  x
+ * must equal the centres bit for bit (checked on the device; VX_EINVAL
+ * otherwise, x unchanged).  Workspace: vx_workspace_bytes(VX_WS_GRAD, P, np,
+ * grid, n).
+ */
+int newton_project_grid(const vx_poly* P, int32_t np, double* x, int64_t n, int32_t steps, double* f,
+                        const vx_csf* grid, const double* dom, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Batched subdivision -- many independent systems run through Algorithm 3 in
  * lockstep (all levels 0..depth), for workloads of many small problems where
  * one system cannot fill the GPU.  Batching independent systems is this

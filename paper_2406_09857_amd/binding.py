@@ -603,6 +603,9 @@ def _grad_lib():
         L.newton_project.argtypes = [C.POINTER(vx_poly), C.c_int32, vp, C.c_int64, C.c_int32, vp, vp, C.c_size_t,
                                      vp]
         L.newton_project.restype = C.c_int
+        L.newton_project_grid.argtypes = [C.POINTER(vx_poly), C.c_int32, vp, C.c_int64, C.c_int32, vp,
+                                          C.POINTER(vx_csf), C.POINTER(C.c_double), vp, C.c_size_t, vp]
+        L.newton_project_grid.restype = C.c_int
         L._grad_ready = True
     return L
 
@@ -664,17 +667,30 @@ def eval_grad(polys, x: torch.Tensor | None, want_jac: bool = True, gbar: torch.
     return (f[:, :n], jac[:n] if jac is not None else None, xbar[:n] if xbar is not None else None, dcoef)
 
 
-def newton_project(polys, x: torch.Tensor, steps: int = 3, stream=None):
+def newton_project(polys, x: torch.Tensor, steps: int = 3, stream=None, grid=None):
     """`steps` minimum-norm Newton steps on every point (in place); returns
-    (x, F at the final points)."""
+    (x, F at the final points).  ``grid`` = (csf, dom) when x holds the
+    centres of csf's leaves (checked): the first evaluation then runs on the
+    CSF grid (``newton_project_grid``)."""
     polys = as_polys(polys)
     n = int(x.shape[0])
     f = torch.empty((len(polys), max(n, 1)), dtype=torch.float64, device=x.device)
     parr = _poly_array(polys)
-    need = int(_grad_lib().vx_workspace_bytes(VX_WS_GRAD, parr, len(polys), None, n))
+    L = _grad_lib()
+    if grid is None:
+        need = int(L.vx_workspace_bytes(VX_WS_GRAD, parr, len(polys), None, n))
+        ws = _ws(need, x.device)
+        _check(L.newton_project(parr, len(polys), x.data_ptr(), n, steps, f.data_ptr(), ws.data_ptr(), ws.numel(),
+                                _stream(stream)))
+        return x, f[:, :n]
+    csf, dom = grid
+    cs = csf.struct()
+    domv = np.ascontiguousarray(np.asarray(dom, np.float64).reshape(-1))
+    need = int(L.vx_workspace_bytes(VX_WS_GRAD, parr, len(polys), C.byref(cs), n))
     ws = _ws(need, x.device)
-    _check(_grad_lib().newton_project(parr, len(polys), x.data_ptr(), n, steps, f.data_ptr(), ws.data_ptr(),
-                                      ws.numel(), _stream(stream)))
+    _check(L.newton_project_grid(parr, len(polys), x.data_ptr(), n, steps, f.data_ptr(), C.byref(cs),
+                                 domv.ctypes.data_as(C.POINTER(C.c_double)), ws.data_ptr(), ws.numel(),
+                                 _stream(stream)))
     return x, f[:, :n]
 
 

@@ -542,6 +542,21 @@ int newton_project(const vx_poly* P, int32_t np, double* x, int64_t n, int32_t s
   return newton_impl(P, np, x, n, steps, f, ws, ws_bytes, (hipStream_t)stream);
 }
 
+int newton_project_grid(const vx_poly* P, int32_t np, double* x, int64_t n, int32_t steps, double* f,
+                        const vx_csf* grid, const double* dom, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_point_polys(P, np))) return rc;
+  if (n < 0 || (n > 0 && !x) || steps < 0 || steps > 100) VX_FAIL(VX_EINVAL, "bad arguments");
+  if (!grid) VX_FAIL(VX_EINVAL, "newton_project_grid: null grid");
+  const int k = P[0].k;
+  if ((rc = check_csf(grid, true))) return rc;
+  if (grid->k != k) VX_FAIL(VX_EINVAL, "grid has k=%d, polynomials k=%d", grid->k, k);
+  if (grid->n[k - 1] != n) VX_FAIL(VX_EINVAL, "grid has %lld leaves, n=%lld", (long long)grid->n[k - 1], (long long)n);
+  if ((rc = check_dom(dom, k))) return rc;
+  if ((rc = check_ws(ws))) return rc;
+  return newton_impl(P, np, x, n, steps, f, ws, ws_bytes, (hipStream_t)stream, grid, dom);
+}
+
 int vx_copy(void* dst, const void* src, size_t bytes, int32_t kind, void* stream) {
   if (bytes == 0) return VX_OK;
   if (!dst || !src) VX_FAIL(VX_EINVAL, "null pointer");

@@ -330,9 +330,13 @@ __device__ __forceinline__ void newton_update(int np, const double (&F)[PMAX_GRA
   }
 }
 
+// f0, j0 (may be null): F and J at the starting points, already evaluated
+// (f0[p * n + i], j0[(i * np + p) * K + j]); the first evaluation is then
+// taken from them.
 template <int K>
 __global__ __launch_bounds__(64) void k_newton(StreamSet ss, int np, double* __restrict__ x, int64_t n, int steps,
-                                               double* __restrict__ f_out) {
+                                               double* __restrict__ f_out, const double* __restrict__ f0,
+                                               const double* __restrict__ j0) {
   const int64_t i0 = (int64_t)blockIdx.x * 64 * PPL + threadIdx.x;
   double xi[PPL][VX_KMAX] = {};
 #pragma unroll
@@ -345,7 +349,17 @@ __global__ __launch_bounds__(64) void k_newton(StreamSet ss, int np, double* __r
   for (int it = 0; it <= steps; it++) {
     for (int p = 0; p < np; p++) {
       double v[PPL], gr[PPL][VX_KMAX];
-      point_eval<K, true, PPL>((const cdbl_t*)ss.s[p], ss.d[p], xi, v, gr);
+      if (it == 0 && f0) {
+#pragma unroll
+        for (int q = 0; q < PPL; q++) {
+          const int64_t i = i0 + q * 64 < n ? i0 + q * 64 : n - 1;
+          v[q] = f0[p * n + i];
+#pragma unroll
+          for (int j = 0; j < K; j++) gr[q][j] = j0[(i * np + p) * K + j];
+        }
+      } else {
+        point_eval<K, true, PPL>((const cdbl_t*)ss.s[p], ss.d[p], xi, v, gr);
+      }
 #pragma unroll
       for (int q = 0; q < PPL; q++) {
         F[q][p] = v[q];
@@ -797,7 +811,7 @@ static int check_centres(GridPlan& Gp, const vx_csf* grid, const double* dom, co
   unsigned int bad = 0;
   VX_HIP(hipMemcpyAsync(&bad, Gp.bad, sizeof bad, hipMemcpyDeviceToHost, st));
   VX_HIP(hipStreamSynchronize(st));
-  if (bad) VX_FAIL(VX_EINVAL, "eval_grad: the points are not the centres of the grid's leaves");
+  if (bad) VX_FAIL(VX_EINVAL, "the points are not the centres of the grid's leaves");
   return VX_OK;
 }
 
@@ -911,24 +925,39 @@ int grad_impl(const vx_poly* P, int np, const double* x, int64_t n, double* f, d
 }
 
 int newton_impl(const vx_poly* P, int np, double* x, int64_t n, int steps, double* f, void* ws, size_t ws_bytes,
-                hipStream_t st) {
+                hipStream_t st, const vx_csf* grid, const double* dom) {
   const int k = P[0].k;
   Arena A;
   A.base = reinterpret_cast<char*>(ws);
   A.size = ws_bytes;
   GradPlan G;
   plan_grad(A, G, P, np);
+  // the same layout as grad_workspace_bytes(P, np, grid, n)
+  double* j0 = A.take<double>((size_t)n * np * VX_KMAX + 1);
+  double* f0 = A.take<double>((size_t)n * np + 1);
+  GridPlan Gp;
+  if (grid) {
+    int dmax = 0;
+    for (int p = 0; p < np; p++) dmax = P[p].degree > dmax ? P[p].degree : dmax;
+    for (int l = 0; l < k; l++) A.take<double>((size_t)grid->n[l] * gbinom(dmax + k - l - 1, k - l - 1) + 1);
+    A.take<double>(gbinom(dmax + k, k) + 1);
+    plan_grid(A, Gp, grid, dmax);
+  }
   if (A.overflow) VX_FAIL(VX_ECAPACITY, "newton_project: workspace too small (%zu needed)", A.off + 256);
   int rc;
+  if (grid && n > 0 && (rc = check_centres(Gp, grid, dom, x, st))) return rc;
   if ((rc = build_streams(G, P, np, st))) return rc;
   const StreamSet ss = stream_set(G, P, np);
   if (n == 0) return VX_OK;
+  if (grid && (rc = grid_forward(G, Gp, P, np, grid, dom, f0, j0, st))) return rc;
+  const double* F0 = grid ? f0 : nullptr;
+  const double* J0 = grid ? j0 : nullptr;
   dim3 g1((unsigned)((n + 64 * PPL - 1) / (64 * PPL)));
   switch (k) {
-    case 1: hipLaunchKernelGGL(k_newton<1>, g1, dim3(64), 0, st, ss, np, x, n, steps, f); break;
-    case 2: hipLaunchKernelGGL(k_newton<2>, g1, dim3(64), 0, st, ss, np, x, n, steps, f); break;
-    case 3: hipLaunchKernelGGL(k_newton<3>, g1, dim3(64), 0, st, ss, np, x, n, steps, f); break;
-    default: hipLaunchKernelGGL(k_newton<4>, g1, dim3(64), 0, st, ss, np, x, n, steps, f); break;
+    case 1: hipLaunchKernelGGL(k_newton<1>, g1, dim3(64), 0, st, ss, np, x, n, steps, f, F0, J0); break;
+    case 2: hipLaunchKernelGGL(k_newton<2>, g1, dim3(64), 0, st, ss, np, x, n, steps, f, F0, J0); break;
+    case 3: hipLaunchKernelGGL(k_newton<3>, g1, dim3(64), 0, st, ss, np, x, n, steps, f, F0, J0); break;
+    default: hipLaunchKernelGGL(k_newton<4>, g1, dim3(64), 0, st, ss, np, x, n, steps, f, F0, J0); break;
   }
   VX_CHECK_LAUNCH("k_newton");
   return VX_OK;

@@ -261,3 +261,27 @@ def test_grid_forward_bit_identical_to_per_point(vx, k, d, level, n):
         xs = x.cpu().numpy()
         for p, c in enumerate(polys):
             assert bits_equal(fg.cpu().numpy()[p], orc.eval_points(c, d, xs))
+
+
+@pytest.mark.parametrize("k,d,level,n", [(2, 20, 6, 900), (3, 12, 4, 700), (3, 100, 5, 400)])
+def test_newton_from_grid_bit_identical(vx, k, d, level, n):
+    """newton_project_grid (first evaluation on the CSF grid of centres)
+    gives the points and values of newton_project bit for bit, and refuses
+    points that are not the grid's centres, leaving them unchanged."""
+    import torch
+    print(f"[newton-grid] k={k} d={d} level={level}", flush=True)
+    polys = synth.small_random(k, d, seed=1300 + d, npolys=min(k, 2))
+    S = _grid(level, k, n, 1310 + k)
+    csf = vx.CSF.from_arrays(k, level, S["idx"], S["ptr"])
+    dom = np.array([-0.7, 1.3] * k)
+    x0 = vx.csf_centres(csf, dom)
+    xa, fa = vx.newton_project(polys, x0.clone(), steps=3)
+    xb, fb = vx.newton_project(polys, x0.clone(), steps=3, grid=(csf, dom))
+    assert bits_equal(xa.cpu().numpy(), xb.cpu().numpy())
+    assert bits_equal(fa.cpu().numpy(), fb.cpu().numpy())
+    moved = x0.clone()
+    moved[n // 2, 0] += 1e-12
+    keep = moved.clone()
+    with pytest.raises(vx.VxError, match="centres"):
+        vx.newton_project(polys, moved, steps=3, grid=(csf, dom))
+    assert torch.equal(moved, keep)
