@@ -330,13 +330,14 @@ __device__ __forceinline__ void newton_update(int np, const double (&F)[PMAX_GRA
   }
 }
 
-// f0, j0 (may be null): F and J at the starting points, already evaluated
-// (f0[p * n + i], j0[(i * np + p) * K + j]); the first evaluation is then
-// taken from them.
+// `steps` Newton steps on the lane's points.  f0, j0 (may be null): F and J
+// at the starting points, already evaluated (f0[p * n + i],
+// j0[(i * np + p) * K + j]); the first evaluation is then taken from them.
+// F at the final points needs no derivatives: the host evaluates it with
+// k_point_eval<K, false> after this kernel.
 template <int K>
 __global__ __launch_bounds__(64) void k_newton(StreamSet ss, int np, double* __restrict__ x, int64_t n, int steps,
-                                               double* __restrict__ f_out, const double* __restrict__ f0,
-                                               const double* __restrict__ j0) {
+                                               const double* __restrict__ f0, const double* __restrict__ j0) {
   const int64_t i0 = (int64_t)blockIdx.x * 64 * PPL + threadIdx.x;
   double xi[PPL][VX_KMAX] = {};
 #pragma unroll
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(64) void k_newton(StreamSet ss, int np, double* __r
     for (int j = 0; j < K; j++) xi[q][j] = i < n ? x[i * K + j] : 0.0;
   }
   double F[PPL][PMAX_GRAD], J[PPL][PMAX_GRAD][VX_KMAX];
-  for (int it = 0; it <= steps; it++) {
+  for (int it = 0; it < steps; it++) {
     for (int p = 0; p < np; p++) {
       double v[PPL], gr[PPL][VX_KMAX];
       if (it == 0 && f0) {
@@ -367,7 +368,6 @@ __global__ __launch_bounds__(64) void k_newton(StreamSet ss, int np, double* __r
         for (int j = 0; j < K; j++) J[q][p][j] = gr[q][j];
       }
     }
-    if (it == steps) break;
 #pragma unroll
     for (int q = 0; q < PPL; q++) newton_update<K>(np, F[q], J[q], xi[q]);
   }
@@ -377,8 +377,6 @@ __global__ __launch_bounds__(64) void k_newton(StreamSet ss, int np, double* __r
     if (i >= n) continue;
 #pragma unroll
     for (int j = 0; j < K; j++) x[i * K + j] = xi[q][j];
-    if (f_out)
-      for (int p = 0; p < np; p++) f_out[p * n + i] = F[q][p];
   }
 }
 
@@ -953,13 +951,29 @@ int newton_impl(const vx_poly* P, int np, double* x, int64_t n, int steps, doubl
   const double* F0 = grid ? f0 : nullptr;
   const double* J0 = grid ? j0 : nullptr;
   dim3 g1((unsigned)((n + 64 * PPL - 1) / (64 * PPL)));
-  switch (k) {
-    case 1: hipLaunchKernelGGL(k_newton<1>, g1, dim3(64), 0, st, ss, np, x, n, steps, f, F0, J0); break;
-    case 2: hipLaunchKernelGGL(k_newton<2>, g1, dim3(64), 0, st, ss, np, x, n, steps, f, F0, J0); break;
-    case 3: hipLaunchKernelGGL(k_newton<3>, g1, dim3(64), 0, st, ss, np, x, n, steps, f, F0, J0); break;
-    default: hipLaunchKernelGGL(k_newton<4>, g1, dim3(64), 0, st, ss, np, x, n, steps, f, F0, J0); break;
+  if (steps > 0) {
+    switch (k) {
+      case 1: hipLaunchKernelGGL(k_newton<1>, g1, dim3(64), 0, st, ss, np, x, n, steps, F0, J0); break;
+      case 2: hipLaunchKernelGGL(k_newton<2>, g1, dim3(64), 0, st, ss, np, x, n, steps, F0, J0); break;
+      case 3: hipLaunchKernelGGL(k_newton<3>, g1, dim3(64), 0, st, ss, np, x, n, steps, F0, J0); break;
+      default: hipLaunchKernelGGL(k_newton<4>, g1, dim3(64), 0, st, ss, np, x, n, steps, F0, J0); break;
+    }
+    VX_CHECK_LAUNCH("k_newton");
   }
-  VX_CHECK_LAUNCH("k_newton");
+  if (!f) return VX_OK;
+  if (steps == 0 && F0) {  // the points have not moved: F is the grid's
+    VX_HIP(hipMemcpyAsync(f, F0, sizeof(double) * (size_t)n * np, hipMemcpyDeviceToDevice, st));
+    return VX_OK;
+  }
+  // values at the final points, without the derivative chains
+  const dim3 g2((unsigned)((n + 64 * PPL - 1) / (64 * PPL)), (unsigned)np);
+  switch (k) {
+    case 1: hipLaunchKernelGGL((k_point_eval<1, false>), g2, dim3(64), 0, st, ss, np, x, n, f, nullptr); break;
+    case 2: hipLaunchKernelGGL((k_point_eval<2, false>), g2, dim3(64), 0, st, ss, np, x, n, f, nullptr); break;
+    case 3: hipLaunchKernelGGL((k_point_eval<3, false>), g2, dim3(64), 0, st, ss, np, x, n, f, nullptr); break;
+    default: hipLaunchKernelGGL((k_point_eval<4, false>), g2, dim3(64), 0, st, ss, np, x, n, f, nullptr); break;
+  }
+  VX_CHECK_LAUNCH("k_point_eval");
   return VX_OK;
 }
 
