@@ -3,11 +3,13 @@
 // Newton steps in the span of the gradients when a system has fewer equations
 // than unknowns; the Taylor/mean-value form uses the gradient on a box).
 //
-// Arithmetic is ordinary round-to-nearest FP64 with no fused multiply-add.
-// Values follow the same nested Horner order as the interval path (x1
-// innermost, descending exponents), so F(x) is bit-identical to a plain
+// Arithmetic is ordinary round-to-nearest FP64.  Values use no fused
+// multiply-add and follow the same nested Horner order as the interval path
+// (x1 innermost, descending exponents), so F(x) is bit-identical to a plain
 // nested Horner evaluation; derivatives are carried forward-mode along the
-// same chains (d(v*x + c)/dx = (dv/dx)*x + v).
+// same chains (d(v*x + c)/dx = (dv/dx)*x + v), each step one fused
+// multiply-add (one rounding instead of two), the same in the per-point and
+// the grid evaluation, so their Jacobians agree bit for bit.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -173,7 +175,7 @@ __device__ void point_eval(const cdbl_t* __restrict__ S, int d, const double (&x
       for (int e = 0; e < SG; e++)
 #pragma unroll
         for (int q = 0; q < PP; q++) {
-          if (GRAD) der[q][0][0] = der[q][0][0] * x[q][0] + acc[q][0];
+          if (GRAD) der[q][0][0] = fma(der[q][0][0], x[q][0], acc[q][0]);
           acc[q][0] = acc[q][0] * x[q][0] + A[e];
         }
 #pragma unroll
@@ -188,8 +190,8 @@ __device__ void point_eval(const cdbl_t* __restrict__ S, int d, const double (&x
       if (GRAD) {
 #pragma unroll
         for (int j = 0; j < K; j++) {
-          if (j < s) der[q][s][j] = der[q][s][j] * x[q][s] + der[q][s - 1][j];
-          else if (j == s) der[q][s][j] = der[q][s][j] * x[q][s] + acc[q][s];
+          if (j < s) der[q][s][j] = fma(der[q][s][j], x[q][s], der[q][s - 1][j]);
+          else if (j == s) der[q][s][j] = fma(der[q][s][j], x[q][s], acc[q][s]);
         }
       }
       acc[q][s] = acc[q][s] * x[q][s] + acc[q][s - 1];
@@ -471,8 +473,8 @@ __global__ void k_adjoint_scatter(int k, int d, int side, const double* __restri
 // chains once per depth-2 node, and so on (Theorem 1's count with points).
 // A stage runs, for every node, the very instructions that the per-point
 // evaluation runs for each point below it -- acc <- acc*x + c, the earlier
-// variables' derivatives der_j <- der_j*x + c_j and the stage's own
-// der_s <- der_s*x + acc (old acc), starting from zero -- so values and
+// variables' derivatives der_j <- fma(der_j, x, c_j) and the stage's own
+// der_s <- fma(der_s, x, acc) (old acc), starting from zero -- so values and
 // derivatives are bit-identical to k_point_eval.
 //
 // Rows.  Node q of depth l (l = 1..k-1) holds, for every trailing tuple of
@@ -552,8 +554,8 @@ __global__ __launch_bounds__(256) void k_grid_stage(const double* __restrict__ i
       for (int i = 0; i < NIN; i++) cin[i] = c[i * in_cstride + e];
       if (GRAD) {
 #pragma unroll
-        for (int i = 1; i < NIN; i++) der[i - 1] = der[i - 1] * x + cin[i];
-        der[L - 1] = der[L - 1] * x + acc;
+        for (int i = 1; i < NIN; i++) der[i - 1] = fma(der[i - 1], x, cin[i]);
+        der[L - 1] = fma(der[L - 1], x, acc);
       }
       acc = acc * x + cin[0];
     }

@@ -169,7 +169,7 @@ def test_newton_three_steps_match_cpu(vx, grid):
     """Three minimum-norm Newton steps x <- x - J^T (J J^T)^-1 F from 500
     seeded level-10 centres, on the GPU (newton_project) and on the CPU from
     the oracle's values and the derivative polynomials (whose coefficients
-    e_j c_e round differently from the forward-mode derivative, so the
+    e_j c_e round differently from the fused forward-mode derivative, so the
     iterates differ by rounding).  Where J J^T stays well conditioned the two
     end points agree to 1e-8 of the distance travelled, and the residual |F|
     falls by a factor of 100 or more at the median (about 350 on the CPU for
