@@ -413,43 +413,77 @@ __global__ void k_csf_centres(int k, int level, const int32_t* i0, const int32_t
 // amortized evaluation.  Depth by depth from the leaves, every parent row is
 //   out[(e, t)] = sum_{children q} x(q)^e * in_q[t]
 // (graded order of tuples); the leaf input is gbar.  Each output entry is one
-// lane summing over the children in order (deterministic).
+// lane summing over the children in order (deterministic).  Children come in
+// chunks of ADJ_CHUNK: their powers x^0..x^d (repeated multiplication) and,
+// where the input rows are short (stage_w entries each: 1 at the leaf depth,
+// d + 1 one depth up), the rows themselves are staged in LDS with one
+// coalesced load, so the sums read LDS only.  Dynamic LDS:
+// ADJ_CHUNK (d + 1 + 1 + stage_w) doubles.
 // ---------------------------------------------------------------------------
 constexpr int ADJ_CHUNK = 32;
+constexpr size_t ADJ_LDS_MAX = 64 * 1024;
+
+__host__ __device__ inline size_t adjoint_lds_bytes(int d, int stage_w) {
+  return sizeof(double) * (size_t)ADJ_CHUNK * (size_t)(d + 2 + stage_w);
+}
 
 __global__ __launch_bounds__(256) void k_adjoint_level(int d, int m_in, const int32_t* __restrict__ ptr,
                                                        int64_t nroot_children, const int32_t* __restrict__ labels,
                                                        double dlo, double dhi, int level,
                                                        const double* __restrict__ in, int64_t in_stride,
                                                        double* __restrict__ out, int64_t out_stride,
-                                                       int64_t nout) {
-  __shared__ double pw[ADJ_CHUNK][MAXDEG_ADJ + 1];
-  __shared__ double xs[ADJ_CHUNK];
+                                                       int64_t nout, int stage_w) {
+  extern __shared__ double adj_lds[];
+  const int W = d + 1;
+  double* pw = adj_lds;                 // [ADJ_CHUNK][W]
+  double* xs = pw + ADJ_CHUNK * W;      // [ADJ_CHUNK]
+  double* ins = xs + ADJ_CHUNK;         // [ADJ_CHUNK][stage_w]
   const int64_t parent = blockIdx.x;
   const int64_t o = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
   const bool act = o < nout;
-  int tt[VX_KMAX] = {0, 0, 0, 0};
-  if (act) g_unrank(o, m_in + 1, tt);
-  const int e = tt[0];
-  const int64_t tin = act ? g_rank(tt + 1, m_in) : 0;
+  // (e, t) of output rank o: closed forms for output tuples of dimension 1
+  // (rank e) and 2 (rank g (g + 1) / 2 + e, g = e + t1), the generic walk
+  // above that
+  int e = 0;
+  int64_t tin = 0;
+  if (act && m_in == 0) {
+    e = (int)o;
+  } else if (act && m_in == 1) {
+    int64_t g = (int64_t)((sqrt(8.0 * (double)o + 1.0) - 1.0) * 0.5);
+    while ((g + 1) * (g + 2) / 2 <= o) g++;
+    while (g * (g + 1) / 2 > o) g--;
+    e = (int)(o - g * (g + 1) / 2);
+    tin = g - e;
+  } else if (act) {
+    int tt[VX_KMAX] = {0, 0, 0, 0};
+    g_unrank(o, m_in + 1, tt);
+    e = tt[0];
+    tin = g_rank(tt + 1, m_in);
+  }
   const int64_t b = ptr ? ptr[parent] : 0, en = ptr ? ptr[parent + 1] : nroot_children;
   double acc = 0.0;
   for (int64_t c0 = b; c0 < en; c0 += ADJ_CHUNK) {
     const int cn = (int)(en - c0 < ADJ_CHUNK ? en - c0 : ADJ_CHUNK);
     __syncthreads();
     if (threadIdx.x < cn) xs[threadIdx.x] = centre(dlo, dhi, level, labels[c0 + threadIdx.x]);
+    // rows of consecutive children are consecutive (in_stride == stage_w)
+    for (int i = threadIdx.x; i < cn * stage_w; i += blockDim.x) ins[i] = in[c0 * in_stride + i];
     __syncthreads();
     // powers x^0..x^d of every child in the chunk, by repeated multiplication
     for (int q = threadIdx.x; q < cn; q += blockDim.x) {
       double p = 1.0;
       for (int j = 0; j <= d; j++) {
-        pw[q][j] = p;
+        pw[q * W + j] = p;
         p = p * xs[q];
       }
     }
     __syncthreads();
-    if (act)
-      for (int q = 0; q < cn; q++) acc += pw[q][e] * in[(c0 + q) * in_stride + tin];
+    if (act) {
+      if (stage_w)
+        for (int q = 0; q < cn; q++) acc += pw[q * W + e] * ins[q * stage_w + tin];
+      else
+        for (int q = 0; q < cn; q++) acc += pw[q * W + e] * in[(c0 + q) * in_stride + tin];
+    }
   }
   if (act) out[parent * out_stride + o] = acc;
 }
@@ -905,10 +939,15 @@ int grad_impl(const vx_poly* P, int np, const double* x, int64_t n, double* f, d
         const int64_t nout = gbinom(d + m_in + 1, m_in + 1);
         const int64_t nparent = l == 0 ? 1 : grid->n[l - 1];
         double* out = l == 0 ? root : rows[l - 1];
-        dim3 g2((unsigned)nparent, (unsigned)((nout + 255) / 256));
-        hipLaunchKernelGGL(k_adjoint_level, g2, dim3(256), 0, st, d, m_in, l == 0 ? nullptr : grid->ptr[l - 1],
-                           grid->n[0], grid->idx[l], dom[2 * l], dom[2 * l + 1], grid->level, in, in_stride, out,
-                           nout, nout);
+        // input rows staged in LDS where they are short: 1 entry (gbar) at the
+        // leaf depth, d + 1 one depth up
+        int stage_w = m_in == 0 ? 1 : (m_in == 1 ? (int)in_stride : 0);
+        if (adjoint_lds_bytes(d, stage_w) > ADJ_LDS_MAX) stage_w = 0;
+        const int threads = nout <= 128 ? 128 : 256;
+        dim3 g2((unsigned)nparent, (unsigned)((nout + threads - 1) / threads));
+        hipLaunchKernelGGL(k_adjoint_level, g2, dim3(threads), adjoint_lds_bytes(d, stage_w), st, d, m_in,
+                           l == 0 ? nullptr : grid->ptr[l - 1], grid->n[0], grid->idx[l], dom[2 * l], dom[2 * l + 1],
+                           grid->level, in, in_stride, out, nout, nout, stage_w);
         VX_CHECK_LAUNCH("k_adjoint_level");
         in = out;
         in_stride = nout;
