@@ -442,8 +442,10 @@ __global__ __launch_bounds__(256) void k_adjoint_level(int d, int m_in, const in
   const int64_t o = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
   const bool act = o < nout;
   // (e, t) of output rank o: closed forms for output tuples of dimension 1
-  // (rank e) and 2 (rank g (g + 1) / 2 + e, g = e + t1), the generic walk
-  // above that
+  // (rank e), 2 (rank g (g + 1) / 2 + e, g = e + t1) and 3 (C(g + 2, 3)
+  // tuples of lower degree, then e (g + 1) - e (e - 1) / 2 with a smaller
+  // first coordinate, then t1), each estimate corrected in integers; the
+  // generic walk above that
   int e = 0;
   int64_t tin = 0;
   if (act && m_in == 0) {
@@ -454,6 +456,20 @@ __global__ __launch_bounds__(256) void k_adjoint_level(int d, int m_in, const in
     while (g * (g + 1) / 2 > o) g--;
     e = (int)(o - g * (g + 1) / 2);
     tin = g - e;
+  } else if (act && m_in == 2) {
+    int64_t g = (int64_t)cbrt(6.0 * (double)o);
+    while ((g + 1) * (g + 2) * (g + 3) / 6 <= o) g++;
+    while (g > 0 && g * (g + 1) * (g + 2) / 6 > o) g--;
+    const int64_t r = o - g * (g + 1) * (g + 2) / 6;
+    const double a = 2.0 * (double)g + 3.0;
+    const double disc = a * a - 8.0 * (double)r;
+    int64_t v = (int64_t)((a - sqrt(disc > 0.0 ? disc : 0.0)) * 0.5);
+    auto before = [&](int64_t x) { return x * (g + 1) - x * (x - 1) / 2; };
+    while (v < g && before(v + 1) <= r) v++;
+    while (v > 0 && before(v) > r) v--;
+    const int64_t t1 = r - before(v), t2 = g - v - t1, gt = t1 + t2;
+    e = (int)v;
+    tin = gt * (gt + 1) / 2 + t1;
   } else if (act) {
     int tt[VX_KMAX] = {0, 0, 0, 0};
     g_unrank(o, m_in + 1, tt);
