@@ -26,9 +26,12 @@
  *     describes the failure (per host thread).  Argument errors are detected
  *     before anything is enqueued.
  *   - Arithmetic: FP64 intervals, every endpoint rounded outward (lower
- *     endpoints toward -inf, upper toward +inf), no fused multiply-add, so
- *     {F(x) : x in B} is contained in [lo, hi] for every box B.  Results are
- *     bit-for-bit reproducible (up to the sign of zero endpoints).
+ *     endpoints toward -inf, upper toward +inf): a Horner step J*I + C is the
+ *     exact range of that set rounded outward once per endpoint (one fused
+ *     multiply-add per candidate product), every other operation is rounded
+ *     on its own, so {F(x) : x in B} is contained in [lo, hi] for every box
+ *     B.  Results are bit-for-bit reproducible (up to the sign of zero
+ *     endpoints).
  *   - The domain is a box [dom[2j], dom[2j+1]] per axis j (host array of 2k
  *     finite doubles, dom[2j] < dom[2j+1]).  At level L, axis j is cut into
  *     2^L cells; cell i is enclosed by
@@ -438,10 +441,11 @@ int vx_copy(void* dst, const void* src, size_t bytes, int32_t kind, void* stream
 /*
  * eval_grad -- point values and gradients of a polynomial system, and the
  * gradient of sum_{p,i} gbar[p][i] F_p(x_i) with respect to the coefficients
- * (the adjoint of the evaluation).  Round-to-nearest FP64, no fused
- * multiply-add, nested Horner in the order of the interval path (x1
- * innermost), so f is bit-identical to that plain evaluation; derivatives are
- * carried forward along the same chains.  Sec. 3.2 uses the gradients for
+ * (the adjoint of the evaluation).  Round-to-nearest FP64: values by nested
+ * Horner in the order of the interval path (x1 innermost) with no fused
+ * multiply-add, so f is bit-identical to that plain evaluation; derivatives
+ * are carried forward along the same chains, each step one fused
+ * multiply-add (the same with and without a grid).  Sec. 3.2 uses the gradients for
  * Newton steps in the span of the gradients and for Taylor forms.
  *   P, np  : point coefficients (c_hi must be NULL), np <= 4, same k.
  *   x      : device, n x k points (row-major).
