@@ -2,8 +2,9 @@
 
     python -m paper_2406_09857_amd.build
 
-Every HIP source is compiled with -ffp-contract=off (no fused multiply-add:
-interval endpoints must see two roundings per Horner step) and with packed
+Every HIP source is compiled with -ffp-contract=off (the compiler fuses
+nothing by itself: the only fused multiply-adds are the explicit ones of the
+interval Horner step and of the forward-mode derivative steps) and with packed
 FP32 instructions disabled.
 """
 from __future__ import annotations
