@@ -486,11 +486,13 @@ __global__ __launch_bounds__(256) void k_adjoint_level(int d, int m_in, const in
     for (int i = threadIdx.x; i < cn * stage_w; i += blockDim.x) ins[i] = in[c0 * in_stride + i];
     __syncthreads();
     // powers x^0..x^d of every child in the chunk, by repeated multiplication
+    // (x held in a register: the table's stores could alias xs)
     for (int q = threadIdx.x; q < cn; q += blockDim.x) {
+      const double xq = xs[q];
       double p = 1.0;
       for (int j = 0; j <= d; j++) {
         pw[q * W + j] = p;
-        p = p * xs[q];
+        p = p * xq;
       }
     }
     __syncthreads();
